@@ -1,0 +1,148 @@
+"""Pins for the oracle's ghost-fluid projection.
+
+Independent references: the Stefan outflow closed form after one projection
+(liquid pushed out at mdot (1/rho_v - 1/rho_l), Sec. 3.1), the DST-II
+diagonalisation of the uniform-density Dirichlet problem, exact
+reproduction of a piecewise-linear pressure with continuous flux across a
+planar interface at any theta, the discrete divergence constraint, the total
+outflow of the constant-mdot bubble (Sec. 3.3) and reflection symmetry.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft as fft
+
+import ebit_inputs as ei
+from oracle import flux, geometry, pipeline, project, solve
+
+
+def test_stefan_projection_closed_form():
+    c = ei.config(0)
+    r = pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+    pr = c.props
+    mdot = pr.lam_v / (0.3 * pr.h_lg)
+    U = mdot * (1.0 / pr.rho_v - 1.0 / pr.rho_l)
+    ul = r["u_l"][0][0]                 # [ny][nx+1]
+    uv = r["u_v"][0][0]
+    # exact up to the direct solve (p ~ 2e3 carries ~1e-12 relative error)
+    assert np.allclose(ul[:, 19:], U, rtol=1e-11, atol=0)
+    # the vapour field is meaningful on faces touching a vapour cell (0..19);
+    # beta_v = 1000 beta_l amplifies the solve's rounding there
+    assert np.max(np.abs(uv[:, :20])) < 1e-10 * U
+    assert np.max(np.abs(r["u_l"][1])) < 1e-10 * U
+    x = (np.arange(64) + 0.5) / 64
+    slope = pr.rho_l * U / c.dt
+    pex = np.where(np.arange(64) >= 19, slope * (1 - x), slope * (1 - 19.5 / 64))
+    p = r["p"].reshape(64, 64)
+    assert np.max(np.abs(p - pex[None, :])) < 1e-10 * slope
+
+
+@pytest.mark.parametrize("dim,n", [(2, 20), (2, 33), (3, 9)])
+def test_uniform_dirichlet_is_dst_diagonal(dim, n):
+    """No interface, p = 0 on every wall: the cell-centred Dirichlet
+    Laplacian (ghost -p) is diagonal in the DST-II basis with eigenvalues
+    -(2 - 2 cos(pi (k+1)/n)) / h^2 per axis."""
+    rng = np.random.default_rng(n)
+    nn = (n, n, n if dim == 3 else 1)
+    h = 1.0 / n
+    shp = ei.cell_shape(dim, nn)
+    props = ei.Props(rho_l=3.0)
+    case = ei.Case("flat", dim, nn, h, props, 2e-3, [(0, 0.0)] * (2 * dim), [(1, 0.0)] * (2 * dim),
+                   [np.full(ei.edge_shape(dim, nn, a), np.nan) for a in range(dim)],
+                   np.ones(ei.vertex_shape(dim, nn), np.uint8), np.ones(shp, np.uint8),
+                   np.zeros(shp), [], [])
+    g = geometry.build(case)
+    L, bc = project.assemble(case, g)
+    assert not np.any(bc)
+    b = rng.normal(size=shp)
+    p = solve.direct(L, b.ravel())
+    sq = b if dim == 3 else b[0]
+    bh = fft.dstn(sq, type=2, norm="ortho")
+    lam = np.zeros(bh.shape)
+    for ax in range(bh.ndim):
+        k = np.arange(bh.shape[ax])
+        ev = (2 - 2 * np.cos(np.pi * (k + 1) / n)) / h ** 2
+        shape = [1] * bh.ndim
+        shape[ax] = -1
+        lam = lam + ev.reshape(shape)
+    beta = case.dt / props.rho_l
+    ref = fft.idstn(-bh / (beta * lam), type=2, norm="ortho")
+    assert np.max(np.abs(p - ref.ravel())) < 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("xg_cells,rho_ratio", [(9.5, 1000.0), (9.03, 1000.0), (9.97, 50.0), (9.31, 7.0)])
+def test_piecewise_linear_pressure_exact(xg_cells, rho_ratio):
+    """Planar interface, Dirichlet p at both x walls, no sources: the exact
+    solution is linear in each phase, continuous, with continuous dt/rho dp/dx.
+    The link property average reproduces it exactly at any theta."""
+    n = 24
+    props = ei.Props(rho_l=1.0, rho_v=1.0 / rho_ratio)
+    c = ei.stefan_2d(n, x_gamma_cells=xg_cells, props=props)
+    p0, p1 = 2.0, -1.0
+    c.p_bc = [(1, p0), (1, p1), (0, 0.0), (0, 0.0)]
+    g = geometry.build(c)
+    L, bc = project.assemble(c, g)
+    p = solve.direct(L, -bc)
+    xg = xg_cells / n
+    # slopes: vapour s_v on [0, xg], liquid s_l on [xg, 1]; rho_l s_v... flux
+    # continuity s_v / rho_v = s_l / rho_l; continuity p0 + s_v xg = p1 - s_l (1 - xg)
+    rv, rl = props.rho_v, props.rho_l
+    s_v = (p1 - p0) / (xg + (1 - xg) * rl / rv)
+    s_l = s_v * rl / rv
+    x = (np.arange(n) + 0.5) / n
+    pex = np.where(x < xg, p0 + s_v * x, p1 - s_l * (1 - x))
+    assert np.max(np.abs(p.reshape(n, n) - pex[None, :])) < 1e-11 * max(abs(p0), abs(p1))
+
+
+@pytest.mark.parametrize("dim,n,seed", [(2, 24, 3), (2, 31, 5), (3, 10, 1)])
+def test_divergence_free_after_projection(dim, n, seed):
+    """Eq. Poisson_equation imposes div_c u^{n+1} = 0 per phase."""
+    c = ei.random_case(dim, n, seed)
+    r = pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+    bnorm = np.linalg.norm(r["b"])
+    assert np.max(np.abs(r["div"])) < 1e-11 * bnorm
+    # both fields are updated with the same gradient on every face
+    for a in range(dim):
+        du_l = r["u_l"][a] - r["u_l_ghost"][a]
+        du_v = r["u_v"][a] - r["u_v_ghost"][a]
+        assert np.max(np.abs(du_l - du_v)) <= 1e-14 * np.max(np.abs(du_l))
+
+
+def _bubble_outflow(n, mdot=0.1):
+    R = 0.2
+    rho_ratio = 1000.0
+    c = ei.bubble(2, n, R, 1.0, 0.02, rho_ratio, 0.1)
+    g = geometry.build(c)
+    m = np.where(g["is_if"], mdot, 0.0)
+    r = project.project(c, g, m, c.u_l, c.u_v, solve.direct)
+    ul = r["u_l"]
+    h = c.h
+    out = (ul[0][0, :, -1].sum() - ul[0][0, :, 0].sum() + ul[1][0, -1, :].sum() - ul[1][0, 0, :].sum()) * h
+    pr = c.props
+    exact = mdot * (1.0 / pr.rho_v - 1.0 / pr.rho_l) * 2 * math.pi * R
+    return abs(out - exact) / exact
+
+
+def test_constant_mdot_bubble_outflow_converges():
+    """Sec. 3.3 bubble with an imposed mdot: the liquid leaving the box per
+    unit time equals mdot (1/rho_v - 1/rho_l) times the perimeter."""
+    errs = [_bubble_outflow(n) for n in (64, 128, 256)]
+    assert errs[-1] < 0.02, errs
+    assert errs[2] < errs[0], errs
+
+
+def test_reflection_symmetry_of_centred_bubble():
+    c = ei.bubble(2, 48, 0.17, 1.0, 0.05, 100.0, 0.2)
+    r = pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+    n = 48
+    T = r["T"].reshape(n, n)
+    assert np.max(np.abs(T - T[:, ::-1])) < 1e-11
+    assert np.max(np.abs(T - T.T)) < 1e-11
+    m = r["mdot"].reshape(n, n)
+    assert np.max(np.abs(m - m[::-1, :])) < 1e-11 * np.max(np.abs(m))
+    p = r["p"].reshape(n, n)
+    assert np.max(np.abs(p - p.T)) < 1e-9 * np.max(np.abs(p))
+    assert np.max(np.abs(p - p[:, ::-1])) < 1e-9 * np.max(np.abs(p))
+    ux = r["u_l"][0][0]          # [ny][nx+1]; x-reflection flips the sign
+    assert np.max(np.abs(ux + ux[:, ::-1])) < 1e-9 * np.max(np.abs(ux))
