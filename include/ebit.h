@@ -1,0 +1,215 @@
+/*
+ * ebit.h -- C ABI of the MI355X (gfx950) library for the interface-aware
+ * elliptic steps of the EBIT phase-change method (Long, Pan & Zaleski,
+ * "A Front-Tracking approach for phase change: the EBIT method").
+ *
+ * The library implements, on a uniform Cartesian grid (2D or 3D):
+ *   ebit_build_coeffs  EBIT edge markers + colour vertices -> interface facets,
+ *                      cut fractions theta on grid links, cell flags and the
+ *                      multigrid hierarchies of both elliptic operators
+ *                      (Sec. 2.1; theta of Eq. ghost_T)
+ *   ebit_heat_solve    implicit per-phase diffusion with T = T_sat imposed
+ *                      sharply at theta (Eqs. energy_diffusion, ghost_T,
+ *                      Txx_ghost), solved by geometric multigrid
+ *   ebit_mass_flux     mass flux from one-sided normal temperature gradients
+ *                      (Eqs. mass_flux_computation, normal_gradient)
+ *   ebit_project       ghost velocities from the mass-flux jump (Eq.
+ *                      ghost_velocity), the variable-density Poisson problem
+ *                      (Eqs. Poisson_equation, poisson_ghost_fluid) solved by
+ *                      geometric multigrid, and the face-velocity update
+ *
+ * Conventions (all calls):
+ *   - Every array argument is a DEVICE pointer owned by the caller, contiguous,
+ *     x fastest: cell (i,j,k) is at i + nx*(j + ny*k).  A 2D grid has n[2] = 1.
+ *       cells             nx*ny*nz
+ *       vertices          (nx+1)*(ny+1)*nvz          nvz = nz+1 (3D), 1 (2D)
+ *       axis-a edges      vertex layout with one fewer entry along a
+ *                         (edge from vertex v to v + e_a)
+ *       axis-a faces      cell layout with one more entry along a
+ *                         (face index i_a separates cells i_a - 1 and i_a)
+ *   - Colours: 1 = liquid, 0 = vapour.  Markers: fractional position
+ *     s in [0, 1] along the edge from its lower vertex; NaN = no marker.
+ *   - Domain sides are ordered (-x, +x, -y, +y, -z, +z).
+ *   - Work is enqueued on the stream given to ebit_create (a hipStream_t
+ *     passed as void*).  Calls that fill an ebit_stats (or return a solver
+ *     status) synchronise that stream before returning; ebit_build_coeffs
+ *     synchronises to report geometry errors.
+ *   - The library never allocates device memory: the caller passes one
+ *     workspace of ebit_workspace_bytes() bytes to ebit_create and keeps it
+ *     alive until ebit_destroy.  The library never frees caller memory.
+ *   - No exception crosses the ABI.  Every call returns an ebit_status;
+ *     ebit_status_string() gives a static text; ebit_last_error() gives the
+ *     text of the last failure on a context (HIP error strings included).
+ *   - Calls on one context must not overlap (one stream, one workspace).
+ */
+#ifndef EBIT_H
+#define EBIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBIT_MAX_LEVELS 24
+
+typedef enum {
+  EBIT_OK = 0,
+  EBIT_EINVAL = -1,   /* bad argument; nothing was launched                    */
+  EBIT_ENOMEM = -2,   /* workspace smaller than ebit_workspace_bytes()         */
+  EBIT_EGEOM = -3,    /* markers inconsistent with colours, or a cut link with
+                         no interface cell on either side                      */
+  EBIT_ENOCONV = -4,  /* max_iters reached; the best iterate is returned       */
+  EBIT_ENAN = -5,     /* NaN/Inf met in a residual norm                        */
+  EBIT_EHIP = -6,     /* a HIP call failed (sticky on the context)             */
+  EBIT_ESTATE = -7    /* call order violated (e.g. solve before build_coeffs)  */
+} ebit_status;
+
+typedef enum { EBIT_BC_NEUMANN = 0, EBIT_BC_DIRICHLET = 1, EBIT_BC_PERIODIC = 2 } ebit_bc;
+typedef enum { EBIT_FP64 = 0, EBIT_MIXED = 1 } ebit_precision;
+typedef enum { EBIT_OUTER_PCG = 0, EBIT_OUTER_DC = 1 } ebit_outer;
+typedef enum { EBIT_SYS_HEAT = 0, EBIT_SYS_PRESSURE = 1 } ebit_system;
+
+/* Grid and boundary conditions.  Periodic sides come in pairs and apply to
+ * both T and p; a periodic axis needs n_a = 2^m (the red-black multigrid
+ * keeps an even size on every level).  Heat: Dirichlet sides impose T_val
+ * through the face ghost 2 T_w - T_c; Neumann sides are insulated.
+ * Pressure: Dirichlet (outflow) sides impose p = p_val on the face; Neumann
+ * sides are walls (no flux, face velocity left as given). */
+typedef struct {
+  int dim;          /* 2 or 3                                                */
+  int n[3];         /* cells per axis, each >= 3 (n[2] = 1 in 2D)             */
+  double h;         /* uniform spacing                                       */
+  int T_bc[6];      /* ebit_bc per side                                      */
+  double T_val[6];
+  int p_bc[6];
+  double p_val[6];
+} ebit_grid;
+
+/* Phase properties (index l = liquid, v = vapour) and saturation data. */
+typedef struct {
+  double rho_l, rho_v, lam_l, lam_v, cp_l, cp_v, h_lg, T_sat;
+} ebit_props;
+
+/* Solver options; ebit_default_opts() fills the defaults in brackets. */
+typedef struct {
+  int precision;      /* EBIT_FP64 [default] or EBIT_MIXED (FP32 V-cycles
+                         inside the FP64 outer loop)                          */
+  int outer;          /* EBIT_OUTER_PCG [default]: flexible CG preconditioned
+                         by one V-cycle; EBIT_OUTER_DC: defect correction
+                         x += V(b - A x)                                      */
+  double rtol;        /* relative L2 residual ||b - A x|| / ||b|| [1e-9]; a
+                         target below the residual's rounding floor stops
+                         at the floor (ebit_stats.res_floor)                  */
+  int max_iters;      /* outer iterations [200]                               */
+  int nu1, nu2;       /* red-black Gauss-Seidel sweeps before / after the
+                         coarse correction [2, 2]                             */
+  double theta_min;   /* lower clamp of theta in the 1/theta terms [1e-3]     */
+  int check_every;    /* outer iterations between host residual checks [1]    */
+  int tail_cells;     /* levels with at most this many cells are smoothed by
+                         one work-group [4096]; 0 disables                    */
+} ebit_opts;
+
+typedef struct {
+  int iters;            /* outer iterations                                  */
+  int vcycles;          /* V-cycles applied                                   */
+  double rel_res;       /* final relative residual (recomputed, not recursive)*/
+  double bnorm;         /* ||b||_2                                            */
+  double res_floor;     /* rounding floor of rel_res: 4 (dim+1) eps
+                           || |b| + |A||x| || / ||b||; a solve also counts as
+                           converged once rel_res <= res_floor                */
+  double seconds;       /* device time of the call (hipEvent)                 */
+  double div_max;       /* ebit_project: max_c |div_c u_{k(c)}| after update  */
+  int fallbacks;        /* ebit_mass_flux: first-order gradient fallbacks     */
+  int status;           /* ebit_status of the call                            */
+} ebit_stats;
+
+typedef struct ebit_ctx ebit_ctx;
+
+void ebit_default_opts(ebit_opts* opts);
+const char* ebit_status_string(ebit_status s);
+
+/* Bytes of device workspace a context on this grid needs.  Returns 0 for an
+ * invalid grid. */
+size_t ebit_workspace_bytes(const ebit_grid* grid, const ebit_opts* opts);
+
+/* Create a context.  workspace: device memory of at least
+ * ebit_workspace_bytes(grid, opts) bytes, 256-byte aligned, owned by the
+ * caller.  hip_stream: the hipStream_t all work is enqueued on (NULL = the
+ * null stream).  Returns EBIT_EINVAL for a bad grid / props / opts and
+ * EBIT_ENOMEM if bytes is too small. */
+ebit_status ebit_create(ebit_ctx** ctx, const ebit_grid* grid, const ebit_props* props,
+                        const ebit_opts* opts, void* workspace, size_t bytes, void* hip_stream);
+ebit_status ebit_destroy(ebit_ctx* ctx);
+const char* ebit_last_error(const ebit_ctx* ctx);
+
+/* Sec. 2.1 and Eq. ghost_T.  marker[a] (a < dim): axis-a edge array of s or
+ * NaN; vertex_colour, cell_colour: uint8 colours.  Computes each interface
+ * cell's facet (centroid = mean of its markers, unit normal from vapour into
+ * liquid), theta on every cut link (fraction of the link from its lower cell
+ * to the interface), the cell flags, and both multigrid hierarchies for the
+ * time step dt.  Returns EBIT_EGEOM if a marker sits on an edge whose end
+ * colours agree (or is missing where they differ), a marker is outside
+ * [0, 1], periodic seams disagree, or a cut link has no interface cell on
+ * either side. */
+ebit_status ebit_build_coeffs(ebit_ctx* ctx, const double* const marker[3],
+                              const uint8_t* vertex_colour, const uint8_t* cell_colour, double dt);
+
+/* Eqs. energy_diffusion, ghost_T, Txx_ghost: one backward-Euler diffusion
+ * step for both phases at once (the cut links decouple them).  T_star: the
+ * advected field (cells).  T: output (cells); if use_guess != 0 it also holds
+ * the initial guess.  T may alias T_star.  stats may be NULL.  Returns
+ * EBIT_ENOCONV / EBIT_ENAN on solver failure (T then holds the last iterate). */
+ebit_status ebit_heat_solve(ebit_ctx* ctx, const double* T_star, double* T, int use_guess,
+                            ebit_stats* stats);
+
+/* Eqs. mass_flux_computation and normal_gradient.  T: cells, each holding
+ * its own phase's temperature.  mdot_cell: output, mdot per cell (0 off the
+ * interface), positive for evaporation.  mdot_face[a]: optional outputs
+ * (NULL to skip, else all dim non-NULL): mdot on cut faces of axis a (the
+ * value of the cell holding the crossing), NaN elsewhere.  The stencil takes
+ * two points at h and 2h from the facet centroid along the normal into each
+ * phase, tri-/bi-quadratic Lagrange values on the 3^d block around the point
+ * (phase cells or one-layer ghost values from Eq. ghost_T). */
+ebit_status ebit_mass_flux(ebit_ctx* ctx, const double* T, double* mdot_cell,
+                           double* const mdot_face[3], ebit_stats* stats);
+
+/* Eqs. ghost_velocity, Poisson_equation, poisson_ghost_fluid and the
+ * face-velocity update.  u_l[a], u_v[a] (a < dim): axis-a face arrays of
+ * the liquid and vapour fields; in: u*, out: u^{n+1} (both fields updated on
+ * every face; a cut face's non-owning field first receives its ghost value).
+ * mdot_cell: from ebit_mass_flux.  p: output pressure (cells); if use_guess
+ * != 0 it also holds the initial guess.  stats->div_max reports the discrete
+ * divergence after the update. */
+ebit_status ebit_project(ebit_ctx* ctx, double* const u_l[3], double* const u_v[3],
+                         const double* mdot_cell, double* p, int use_guess, ebit_stats* stats);
+
+/* ---- inspection entry points (same conventions) --------------------------- */
+
+/* Copy the geometry of the last ebit_build_coeffs: theta[a] (axis-a faces,
+ * NaN where the link is not cut), flags (uint8 per cell: bits 0..5 cut link
+ * on side -x,+x,-y,+y,-z,+z; bit 6 liquid; bit 7 interface cell) and facet
+ * (6 arrays of cells back to back: centroid x,y,z then normal x,y,z; only
+ * interface cells are defined).  Any output may be NULL. */
+ebit_status ebit_get_geometry(ebit_ctx* ctx, double* const theta[3], uint8_t* flags, double* facet);
+
+/* y = A x for system EBIT_SYS_HEAT (the heat matrix) or EBIT_SYS_PRESSURE
+ * (the negated Poisson matrix -L, symmetric positive definite), FP64. */
+ebit_status ebit_apply(ebit_ctx* ctx, int system, const double* x, double* y);
+
+/* Right-hand side of the heat system for T_star (cells -> cells). */
+ebit_status ebit_heat_rhs(ebit_ctx* ctx, const double* T_star, double* b);
+
+/* First half of ebit_project: writes the ghost values into u_l / u_v and the
+ * right-hand side b of the SPD pressure system (-L p = b). */
+ebit_status ebit_project_rhs(ebit_ctx* ctx, double* const u_l[3], double* const u_v[3],
+                             const double* mdot_cell, double* b);
+
+/* Levels of the multigrid hierarchy and their sizes (host outputs). */
+ebit_status ebit_levels(const ebit_ctx* ctx, int* nlevels, int* sizes /* [3*nlevels] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBIT_H */

@@ -1,0 +1,569 @@
+// C ABI of the EBIT elliptic-path library: context, workspace carving,
+// argument checks and the entry points declared in include/ebit.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "ebit_internal.h"
+
+using namespace ebit;
+
+struct ebit_ctx {
+  ebit_grid grid;
+  ebit_props props;
+  ebit_opts opts;
+  hipStream_t st;
+  char* ws;
+  size_t ws_bytes;
+  Dims fd;
+  int nlev;
+  EbitLevelHost lv[EBIT_MAX_LEVELS];
+  uint8_t* flags;
+  double* th[3];
+  double* cF;
+  double* nF;
+  double* bvec;
+  EbitSolveBufs B;
+  double dt;
+  int built;
+  FineOp op[2];
+  hipEvent_t ev0, ev1;
+  hipError_t herr;
+  char msg[512];
+};
+
+namespace {
+
+const size_t ALIGN = 256;
+
+struct Carver {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+bool valid_grid(const ebit_grid* g, char* msg, size_t ml) {
+  if (!g) {
+    snprintf(msg, ml, "grid is NULL");
+    return false;
+  }
+  if (g->dim != 2 && g->dim != 3) {
+    snprintf(msg, ml, "dim must be 2 or 3");
+    return false;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (a < g->dim && g->n[a] < 3) {
+      snprintf(msg, ml, "n[%d] must be >= 3", a);
+      return false;
+    }
+    if (a >= g->dim && g->n[a] != 1) {
+      snprintf(msg, ml, "n[2] must be 1 in 2D");
+      return false;
+    }
+    if (g->n[a] > (1 << 20)) {
+      snprintf(msg, ml, "n[%d] too large", a);
+      return false;
+    }
+  }
+  const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
+  if (N >= (1LL << 31)) {
+    snprintf(msg, ml, "grid has too many cells");
+    return false;
+  }
+  if (!(g->h > 0) || !isfinite(g->h)) {
+    snprintf(msg, ml, "h must be positive");
+    return false;
+  }
+  for (int s = 0; s < 2 * g->dim; ++s) {
+    for (int w = 0; w < 2; ++w) {
+      const int b = w ? g->p_bc[s] : g->T_bc[s];
+      if (b < 0 || b > 2) {
+        snprintf(msg, ml, "bad boundary kind on side %d", s);
+        return false;
+      }
+    }
+    if (!isfinite(g->T_val[s]) || !isfinite(g->p_val[s])) {
+      snprintf(msg, ml, "boundary value on side %d not finite", s);
+      return false;
+    }
+  }
+  for (int a = 0; a < g->dim; ++a) {
+    const int kinds[4] = {g->T_bc[2 * a], g->T_bc[2 * a + 1], g->p_bc[2 * a], g->p_bc[2 * a + 1]};
+    int nper = 0;
+    for (int q = 0; q < 4; ++q) nper += kinds[q] == EBIT_BC_PERIODIC;
+    if (nper != 0 && nper != 4) {
+      snprintf(msg, ml, "axis %d: periodic must be set on both sides for T and p", a);
+      return false;
+    }
+    if (nper == 4 && !is_pow2(g->n[a])) {
+      snprintf(msg, ml, "axis %d: a periodic axis needs a power-of-two size", a);
+      return false;
+    }
+  }
+  return true;
+}
+
+bool valid_props(const ebit_props* p, char* msg, size_t ml) {
+  if (!p) {
+    snprintf(msg, ml, "props is NULL");
+    return false;
+  }
+  const double v[7] = {p->rho_l, p->rho_v, p->lam_l, p->lam_v, p->cp_l, p->cp_v, p->h_lg};
+  for (int q = 0; q < 7; ++q)
+    if (!(v[q] > 0) || !isfinite(v[q])) {
+      snprintf(msg, ml, "properties must be positive and finite");
+      return false;
+    }
+  if (!isfinite(p->T_sat)) {
+    snprintf(msg, ml, "T_sat not finite");
+    return false;
+  }
+  return true;
+}
+
+bool valid_opts(const ebit_opts* o, char* msg, size_t ml) {
+  if (!o) return true;
+  if (o->precision != EBIT_FP64 && o->precision != EBIT_MIXED) {
+    snprintf(msg, ml, "bad precision");
+    return false;
+  }
+  if (o->outer != EBIT_OUTER_PCG && o->outer != EBIT_OUTER_DC) {
+    snprintf(msg, ml, "bad outer loop");
+    return false;
+  }
+  if (!(o->rtol > 0) || o->max_iters < 1 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
+      !(o->theta_min > 0 && o->theta_min <= 0.5)) {
+    snprintf(msg, ml, "bad solver options");
+    return false;
+  }
+  return true;
+}
+
+Dims dims_of(const ebit_grid* g) {
+  Dims d;
+  d.dim = g->dim;
+  long long N = 1;
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = g->n[a];
+    d.per[a] = (a < g->dim) && g->T_bc[2 * a] == EBIT_BC_PERIODIC;
+    N *= g->n[a];
+  }
+  d.N = N;
+  return d;
+}
+
+long long faces(const Dims& d, int a) {
+  long long f = 1;
+  for (int b = 0; b < 3; ++b) f *= d.n[b] + (b == a ? 1 : 0);
+  return f;
+}
+
+// Carve the workspace; base == nullptr only measures.  Fills ctx pointers
+// when ctx != nullptr.
+size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx) {
+  Carver cv{base, 0};
+  const Dims fd = dims_of(g);
+  const long long N = fd.N;
+  uint8_t* flags = cv.take<uint8_t>(N);
+  double* th[3] = {nullptr, nullptr, nullptr};
+  for (int a = 0; a < fd.dim; ++a) th[a] = cv.take<double>(faces(fd, a));
+  double* cF = cv.take<double>(3 * N);
+  double* nF = cv.take<double>(3 * N);
+  double* bvec = cv.take<double>(N);
+  EbitSolveBufs B;
+  B.r = cv.take<double>(N);
+  B.z64 = cv.take<double>(N);
+  B.z32 = cv.take<float>(N);
+  B.p[0] = cv.take<double>(N);
+  B.p[1] = cv.take<double>(N);
+  B.q = cv.take<double>(N);
+  B.partial = cv.take<double>(4 * EBIT_RED_BLOCKS);
+  B.scal = cv.take<Scal>(1);
+  // levels
+  EbitLevelHost lv[EBIT_MAX_LEVELS];
+  memset(lv, 0, sizeof(lv));
+  lv[0].d = fd;
+  int nlev = 1;
+  while (lv[nlev - 1].d.N > 1 && nlev < EBIT_MAX_LEVELS) {
+    Dims c = lv[nlev - 1].d;
+    long long NN = 1;
+    for (int a = 0; a < 3; ++a) {
+      c.n[a] = (c.n[a] + 1) / 2;
+      NN *= c.n[a];
+    }
+    c.N = NN;
+    lv[nlev].d = c;
+    ++nlev;
+  }
+  for (int l = 1; l < nlev; ++l) {
+    const long long n = lv[l].d.N;
+    for (int s = 0; s < 2; ++s) {
+      lv[l].diag64[s] = cv.take<double>(n);
+      lv[l].mass64[s] = cv.take<double>(n);
+      for (int a = 0; a < fd.dim; ++a) lv[l].off64[s][a] = cv.take<double>(n);
+      lv[l].diag32[s] = cv.take<float>(n);
+      for (int a = 0; a < fd.dim; ++a) lv[l].off32[s][a] = cv.take<float>(n);
+    }
+    lv[l].x64 = cv.take<double>(n);
+    lv[l].b64 = cv.take<double>(n);
+    lv[l].x32 = cv.take<float>(n);
+    lv[l].b32 = cv.take<float>(n);
+  }
+  const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;
+  if (ctx) {
+    ctx->fd = fd;
+    ctx->flags = flags;
+    for (int a = 0; a < 3; ++a) ctx->th[a] = th[a];
+    ctx->cF = cF;
+    ctx->nF = nF;
+    ctx->bvec = bvec;
+    ctx->B = B;
+    ctx->nlev = nlev;
+    memcpy(ctx->lv, lv, sizeof(lv));
+  }
+  (void)o;
+  return total;
+}
+
+ebit_status fail(ebit_ctx* c, ebit_status s, const char* what) {
+  if (c) snprintf(c->msg, sizeof(c->msg), "%s", what);
+  return s;
+}
+
+ebit_status hip_fail(ebit_ctx* c, hipError_t e, const char* where) {
+  c->herr = e;
+  snprintf(c->msg, sizeof(c->msg), "%s: %s", where, hipGetErrorString(e));
+  return EBIT_EHIP;
+}
+
+#define HIPCK(ctx, expr, where)                          \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+void set_ops(ebit_ctx* c) {
+  const ebit_props& p = c->props;
+  const double dt = c->dt;
+  for (int sys = 0; sys < 2; ++sys) {
+    FineOp& op = c->op[sys];
+    op.d = c->fd;
+    op.h = c->grid.h;
+    op.ih2 = 1.0 / (c->grid.h * c->grid.h);
+    op.sys = sys;
+    op.rho[0] = p.rho_v;
+    op.rho[1] = p.rho_l;
+    op.dt = dt;
+    op.Tsat = p.T_sat;
+    op.theta_min = c->opts.theta_min;
+    op.flags = c->flags;
+    for (int a = 0; a < 3; ++a) op.th[a] = c->th[a];
+    if (sys == EBIT_SYS_HEAT) {
+      op.mass[0] = p.rho_v * p.cp_v / dt;
+      op.mass[1] = p.rho_l * p.cp_l / dt;
+      op.coef[0] = p.lam_v;
+      op.coef[1] = p.lam_l;
+      for (int s = 0; s < 6; ++s) {
+        op.bc[s] = c->grid.T_bc[s];
+        op.bcval[s] = c->grid.T_val[s];
+      }
+    } else {
+      op.mass[0] = op.mass[1] = 0.0;
+      op.coef[0] = dt / p.rho_v;
+      op.coef[1] = dt / p.rho_l;
+      for (int s = 0; s < 6; ++s) {
+        op.bc[s] = c->grid.p_bc[s];
+        op.bcval[s] = c->grid.p_val[s];
+      }
+    }
+  }
+}
+
+ebit_status check_ready(ebit_ctx* c) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  if (!c->built) return fail(c, EBIT_ESTATE, "ebit_build_coeffs has not been called");
+  return EBIT_OK;
+}
+
+ebit_status run_solve(ebit_ctx* c, int sys, double* x, int use_guess, ebit_stats* st) {
+  int iters = 0, vcyc = 0;
+  double relres = 0, bnorm = 0, floor = 0;
+  hipError_t herr = hipSuccess;
+  const int rc = ebit_solve_stream(&c->op[sys], c->lv, c->nlev, &c->B, c->bvec, x, use_guess, &c->opts, c->st,
+                                   &iters, &vcyc, &relres, &bnorm, &floor, &herr);
+  if (rc < 0) return hip_fail(c, herr, "solve");
+  if (st) {
+    st->iters = iters;
+    st->vcycles = vcyc;
+    st->rel_res = relres;
+    st->bnorm = bnorm;
+    st->res_floor = floor;
+  }
+  if (rc == 1) return fail(c, EBIT_ENOCONV, "no convergence within max_iters");
+  if (rc == 2) return fail(c, EBIT_ENAN, "NaN or Inf in a residual norm");
+  return EBIT_OK;
+}
+
+void stats_init(ebit_stats* s) {
+  if (!s) return;
+  memset(s, 0, sizeof(*s));
+}
+
+}  // namespace
+
+extern "C" {
+
+void ebit_default_opts(ebit_opts* o) {
+  if (!o) return;
+  o->precision = EBIT_FP64;
+  o->outer = EBIT_OUTER_PCG;
+  o->rtol = 1e-9;
+  o->max_iters = 200;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->theta_min = 1e-3;
+  o->check_every = 1;
+  o->tail_cells = 4096;
+}
+
+const char* ebit_status_string(ebit_status s) {
+  switch (s) {
+    case EBIT_OK: return "ok";
+    case EBIT_EINVAL: return "invalid argument";
+    case EBIT_ENOMEM: return "workspace too small";
+    case EBIT_EGEOM: return "inconsistent interface geometry";
+    case EBIT_ENOCONV: return "solver did not converge";
+    case EBIT_ENAN: return "NaN or Inf in the solver";
+    case EBIT_EHIP: return "HIP runtime error";
+    case EBIT_ESTATE: return "call order violated";
+  }
+  return "unknown status";
+}
+
+size_t ebit_workspace_bytes(const ebit_grid* g, const ebit_opts* o) {
+  char msg[256];
+  if (!valid_grid(g, msg, sizeof msg)) return 0;
+  return layout(g, o, nullptr, nullptr);
+}
+
+ebit_status ebit_create(ebit_ctx** out, const ebit_grid* g, const ebit_props* p, const ebit_opts* o, void* ws,
+                        size_t bytes, void* stream) {
+  if (!out) return EBIT_EINVAL;
+  *out = nullptr;
+  char msg[256];
+  if (!valid_grid(g, msg, sizeof msg) || !valid_props(p, msg, sizeof msg) || !valid_opts(o, msg, sizeof msg))
+    return EBIT_EINVAL;
+  if (!ws || ((uintptr_t)ws % ALIGN) != 0) return EBIT_EINVAL;
+  const size_t need = layout(g, o, nullptr, nullptr);
+  if (bytes < need) return EBIT_ENOMEM;
+  ebit_ctx* c = new (std::nothrow) ebit_ctx;
+  if (!c) return EBIT_ENOMEM;
+  memset(c, 0, sizeof(*c));
+  c->grid = *g;
+  c->props = *p;
+  if (o)
+    c->opts = *o;
+  else
+    ebit_default_opts(&c->opts);
+  if (c->opts.check_every < 1) c->opts.check_every = 1;
+  c->st = (hipStream_t)stream;
+  c->ws = (char*)ws;
+  c->ws_bytes = bytes;
+  layout(g, o, c->ws, c);
+  c->herr = hipSuccess;
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return EBIT_EHIP;
+  }
+  *out = c;
+  return EBIT_OK;
+}
+
+ebit_status ebit_destroy(ebit_ctx* c) {
+  if (!c) return EBIT_EINVAL;
+  (void)hipEventDestroy(c->ev0);
+  (void)hipEventDestroy(c->ev1);
+  delete c;
+  return EBIT_OK;
+}
+
+const char* ebit_last_error(const ebit_ctx* c) { return c ? c->msg : "null context"; }
+
+ebit_status ebit_build_coeffs(ebit_ctx* c, const double* const marker[3], const uint8_t* vcol, const uint8_t* ccol,
+                              double dt) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  if (!marker || !vcol || !ccol) return fail(c, EBIT_EINVAL, "NULL marker or colour array");
+  for (int a = 0; a < c->grid.dim; ++a)
+    if (!marker[a]) return fail(c, EBIT_EINVAL, "NULL marker array");
+  if (!(dt > 0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be positive");
+  c->built = 0;
+  c->dt = dt;
+  HIPCK(c, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)c->B.scal, 0.0, c->st),
+        "reset");
+  HIPCK(c,
+        ebit_launch_geometry(&c->fd, c->grid.h, marker, vcol, ccol, c->flags, c->cF, c->nF, c->th, c->B.scal, c->st),
+        "geometry");
+  Scal hs;
+  HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "geometry status");
+  HIPCK(c, hipStreamSynchronize(c->st), "geometry sync");
+  if (hs.err & ERR_GEOM_MARKER) return fail(c, EBIT_EGEOM, "a marker is inconsistent with the vertex colours");
+  if (hs.err & ERR_GEOM_SEAM) return fail(c, EBIT_EGEOM, "periodic seam markers or colours disagree");
+  if (hs.err & ERR_GEOM_NOFACET) return fail(c, EBIT_EGEOM, "a cut link has no interface cell on either side");
+  set_ops(c);
+  const int want32 = c->opts.precision == EBIT_MIXED;
+  for (int sys = 0; sys < 2; ++sys)
+    HIPCK(c, ebit_build_hierarchy(&c->op[sys], c->lv, c->nlev, sys, want32, c->st), "hierarchy");
+  c->built = 1;
+  return EBIT_OK;
+}
+
+ebit_status ebit_heat_solve(ebit_ctx* c, const double* Ts, double* T, int use_guess, ebit_stats* st) {
+  stats_init(st);
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!Ts || !T) return fail(c, EBIT_EINVAL, "NULL field");
+  HIPCK(c, hipEventRecord(c->ev0, c->st), "event");
+  HIPCK(c, ebit_launch_heat_rhs(&c->op[EBIT_SYS_HEAT], Ts, c->bvec, c->st), "heat rhs");
+  s = run_solve(c, EBIT_SYS_HEAT, T, use_guess, st);
+  if (s == EBIT_EHIP) return s;
+  HIPCK(c, hipEventRecord(c->ev1, c->st), "event");
+  HIPCK(c, hipEventSynchronize(c->ev1), "event sync");
+  if (st) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    st->seconds = ms * 1e-3;
+    st->status = s;
+  }
+  return s;
+}
+
+ebit_status ebit_mass_flux(ebit_ctx* c, const double* T, double* mdot, double* const mface[3], ebit_stats* st) {
+  stats_init(st);
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!T || !mdot) return fail(c, EBIT_EINVAL, "NULL field");
+  if (mface)
+    for (int a = 0; a < c->grid.dim; ++a)
+      if (!mface[a]) return fail(c, EBIT_EINVAL, "mdot_face must be NULL or hold dim arrays");
+  HIPCK(c, hipEventRecord(c->ev0, c->st), "event");
+  HIPCK(c, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)c->B.scal, 0.0, c->st),
+        "reset");
+  const double lam[2] = {c->props.lam_v, c->props.lam_l};
+  HIPCK(c,
+        ebit_launch_mass_flux(&c->fd, c->grid.h, lam, c->props.h_lg, c->props.T_sat, c->opts.theta_min, c->flags,
+                              c->th, c->cF, c->nF, T, mdot, mface, c->B.scal, c->st),
+        "mass flux");
+  HIPCK(c, hipEventRecord(c->ev1, c->st), "event");
+  Scal hs;
+  HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "status");
+  HIPCK(c, hipStreamSynchronize(c->st), "sync");
+  if (st) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    st->seconds = ms * 1e-3;
+    st->fallbacks = hs.fallbacks;
+    st->status = EBIT_OK;
+  }
+  return EBIT_OK;
+}
+
+ebit_status ebit_project_rhs(ebit_ctx* c, double* const ul[3], double* const uv[3], const double* mdot, double* b) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!ul || !uv || !mdot || !b) return fail(c, EBIT_EINVAL, "NULL field");
+  for (int a = 0; a < c->grid.dim; ++a)
+    if (!ul[a] || !uv[a]) return fail(c, EBIT_EINVAL, "NULL velocity array");
+  const double rho[2] = {c->props.rho_v, c->props.rho_l};
+  HIPCK(c,
+        ebit_launch_proj_rhs(&c->fd, c->grid.h, rho, c->dt, c->grid.p_bc, c->grid.p_val, c->flags, c->th, c->nF,
+                             mdot, ul, uv, b, c->st),
+        "projection rhs");
+  return EBIT_OK;
+}
+
+ebit_status ebit_project(ebit_ctx* c, double* const ul[3], double* const uv[3], const double* mdot, double* p,
+                         int use_guess, ebit_stats* st) {
+  stats_init(st);
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!p) return fail(c, EBIT_EINVAL, "NULL pressure");
+  HIPCK(c, hipEventRecord(c->ev0, c->st), "event");
+  s = ebit_project_rhs(c, ul, uv, mdot, c->bvec);
+  if (s != EBIT_OK) return s;
+  s = run_solve(c, EBIT_SYS_PRESSURE, p, use_guess, st);
+  if (s == EBIT_EHIP) return s;
+  const double rho[2] = {c->props.rho_v, c->props.rho_l};
+  HIPCK(c,
+        ebit_launch_face_update(&c->fd, c->grid.h, rho, c->dt, c->grid.p_bc, c->grid.p_val, c->flags, c->th, ul, uv,
+                                p, c->B.partial, c->B.scal, c->st),
+        "face update");
+  HIPCK(c, hipEventRecord(c->ev1, c->st), "event");
+  Scal hs;
+  HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "status");
+  HIPCK(c, hipStreamSynchronize(c->st), "sync");
+  if (st) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    st->seconds = ms * 1e-3;
+    st->div_max = hs.divmax;
+    st->status = s;
+  }
+  return s;
+}
+
+ebit_status ebit_get_geometry(ebit_ctx* c, double* const theta[3], uint8_t* flags, double* facet) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  const Dims& d = c->fd;
+  if (theta)
+    for (int a = 0; a < d.dim; ++a)
+      if (theta[a])
+        HIPCK(c, hipMemcpyAsync(theta[a], c->th[a], faces(d, a) * sizeof(double), hipMemcpyDeviceToDevice, c->st),
+              "copy theta");
+  if (flags) HIPCK(c, hipMemcpyAsync(flags, c->flags, d.N, hipMemcpyDeviceToDevice, c->st), "copy flags");
+  if (facet) {
+    HIPCK(c, hipMemcpyAsync(facet, c->cF, 3 * d.N * sizeof(double), hipMemcpyDeviceToDevice, c->st), "copy facet");
+    HIPCK(c, hipMemcpyAsync(facet + 3 * d.N, c->nF, 3 * d.N * sizeof(double), hipMemcpyDeviceToDevice, c->st),
+          "copy facet");
+  }
+  HIPCK(c, hipStreamSynchronize(c->st), "sync");
+  return EBIT_OK;
+}
+
+ebit_status ebit_apply(ebit_ctx* c, int sys, const double* x, double* y) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (sys != EBIT_SYS_HEAT && sys != EBIT_SYS_PRESSURE) return fail(c, EBIT_EINVAL, "bad system");
+  if (!x || !y) return fail(c, EBIT_EINVAL, "NULL vector");
+  HIPCK(c, ebit_launch_apply(&c->op[sys], x, y, c->st), "apply");
+  return EBIT_OK;
+}
+
+ebit_status ebit_heat_rhs(ebit_ctx* c, const double* Ts, double* b) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!Ts || !b) return fail(c, EBIT_EINVAL, "NULL vector");
+  HIPCK(c, ebit_launch_heat_rhs(&c->op[EBIT_SYS_HEAT], Ts, b, c->st), "heat rhs");
+  return EBIT_OK;
+}
+
+ebit_status ebit_levels(const ebit_ctx* c, int* nlevels, int* sizes) {
+  if (!c || !nlevels) return EBIT_EINVAL;
+  *nlevels = c->nlev;
+  if (sizes)
+    for (int l = 0; l < c->nlev; ++l)
+      for (int a = 0; a < 3; ++a) sizes[3 * l + a] = c->lv[l].d.n[a];
+  return EBIT_OK;
+}
+
+}  // extern "C"

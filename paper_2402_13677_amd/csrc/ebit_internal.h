@@ -1,0 +1,256 @@
+// Internal definitions of the EBIT elliptic-path library (gfx950).
+//
+// Layout reminders (see include/ebit.h): cells x-fastest, c = i + nx*(j + ny*k);
+// axis-a face arrays carry n_a + 1 entries along a; cell flags are one byte:
+// bits 0..5 = cut link on side (-x,+x,-y,+y,-z,+z), bit 6 = liquid,
+// bit 7 = interface cell.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ebit.h"
+
+#define EBIT_BLOCK 256
+#define EBIT_RED_BLOCKS 2048
+
+namespace ebit {
+
+enum : uint8_t { F_LIQ = 1u << 6, F_IF = 1u << 7, F_CUT = 0x3f };
+
+// device-side error bits (Scal::err)
+enum : int { ERR_GEOM_MARKER = 1, ERR_GEOM_NOFACET = 2, ERR_GEOM_SEAM = 4, ERR_NAN = 8 };
+
+// Per-solve scalars kept on the device (no host round trip per iteration).
+struct Scal {
+  double bb, rr, gamma, delta, alpha, beta, zq, divmax;
+  double aa;      // || |b| + |A| |x| ||^2: sets the rounding floor of the residual
+  double red[7];
+  int err;
+  int fallbacks;
+  int pad[2];
+};
+
+// Geometry of one grid level.
+struct Dims {
+  int dim;
+  int n[3];
+  int per[3];  // periodic axis flags
+  long long N;
+};
+
+__host__ __device__ inline long long cell_index(const Dims& d, int i, int j, int k) {
+  return (long long)i + (long long)d.n[0] * ((long long)j + (long long)d.n[1] * k);
+}
+
+// Face index of the face on side s of cell (i,j,k) in the axis-(s/2) face array.
+__host__ __device__ inline long long face_of_side(const Dims& d, int i, int j, int k, int s) {
+  const int a = s >> 1, up = s & 1;
+  if (a == 0) return (long long)(i + up) + (long long)(d.n[0] + 1) * ((long long)j + (long long)d.n[1] * k);
+  if (a == 1) return (long long)i + (long long)d.n[0] * ((long long)(j + up) + (long long)(d.n[1] + 1) * k);
+  return (long long)i + (long long)d.n[0] * ((long long)j + (long long)d.n[1] * (k + up));
+}
+
+// Neighbour across side s; returns false at a non-periodic wall.
+__host__ __device__ inline bool neighbour(const Dims& d, int i, int j, int k, int s, int& ni, int& nj,
+                                          int& nk) {
+  const int a = s >> 1;
+  const int step = (s & 1) ? 1 : -1;
+  int q[3] = {i, j, k};
+  q[a] += step;
+  if (q[a] < 0 || q[a] >= d.n[a]) {
+    if (!d.per[a]) return false;
+    q[a] = (q[a] + d.n[a]) % d.n[a];
+  }
+  ni = q[0];
+  nj = q[1];
+  nk = q[2];
+  return true;
+}
+
+// Matrix-free description of a fine-level operator (heat or pressure).
+struct FineOp {
+  Dims d;
+  double h, ih2;
+  int sys;            // EBIT_SYS_HEAT / EBIT_SYS_PRESSURE
+  double mass[2];     // heat: rho_k cp_k / dt per phase (index 0 vapour, 1 liquid); pressure: 0
+  double coef[2];     // heat: lam_k; pressure: dt / rho_k
+  double rho[2];
+  double dt;
+  double Tsat;
+  int bc[6];
+  double bcval[6];
+  double theta_min;
+  const uint8_t* flags;
+  const double* th[3];
+};
+
+// One row of the fine operator at cell (i,j,k):  A x = diag x_c + sum_s off[s] x_nb(s).
+// Heat (Eqs. energy_diffusion, Txx_ghost): diag = mass + sum of lam/h^2 weights with
+// 1/theta' on cut links and 2 on Dirichlet walls; off = -lam/h^2 on same-phase links.
+// Pressure (SPD form -L of Eq. Poisson_equation): off = -beta_f/h^2 with
+// beta_f = dt/rho_f, rho_f the link property average on cut links; Dirichlet
+// (outflow) walls add 2 beta/h^2 to the diagonal.  The boundary and interface
+// terms of the right-hand side are added, side by side, to rhs_bc (heat:
+// + lam T_sat/(theta' h^2) and + 2 lam T_w/h^2; pressure: + 2 beta p_w/h^2);
+// the caller initialises rhs_bc.  mexc = diag + sum_s off[s] accumulated
+// without cancellation (mass, interface and wall terms only): the row in
+// difference form is  A x = mexc x_c + sum_s (-off[s]) (x_c - x_nb(s)).
+template <typename T>
+__device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f, T& diag, T off[6],
+                                T& mass, T& rhs_bc, T* mexc = nullptr) {
+  const int ph = (f & F_LIQ) ? 1 : 0;
+  const T ih2 = (T)op.ih2;
+  mass = (T)op.mass[ph];
+  diag = mass;
+  T mx = mass;
+  const int ns = 2 * op.d.dim;
+  for (int s = 0; s < ns; ++s) {
+    off[s] = (T)0;
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    const bool wall = !op.d.per[a] && (up ? (ia == op.d.n[a] - 1) : (ia == 0));
+    if (op.sys == EBIT_SYS_HEAT) {
+      const T lam = (T)op.coef[ph];
+      if (wall) {
+        if (op.bc[s] == EBIT_BC_DIRICHLET) {
+          diag += (T)2 * lam * ih2;
+          mx += (T)2 * lam * ih2;
+          rhs_bc += (T)2 * lam * (T)op.bcval[s] * ih2;
+        }
+      } else if ((f >> s) & 1) {
+        const double tf = op.th[a][face_of_side(op.d, i, j, k, s)];
+        double tc = up ? tf : 1.0 - tf;
+        if (tc < op.theta_min) tc = op.theta_min;
+        diag += lam * ih2 / (T)tc;
+        mx += lam * ih2 / (T)tc;
+        rhs_bc += lam * (T)op.Tsat * ih2 / (T)tc;
+      } else {
+        diag += lam * ih2;
+        off[s] = -lam * ih2;
+      }
+    } else {
+      if (wall) {
+        if (op.bc[s] == EBIT_BC_DIRICHLET) {
+          const T beta = (T)op.coef[ph];
+          diag += (T)2 * beta * ih2;
+          mx += (T)2 * beta * ih2;
+          rhs_bc += (T)2 * beta * (T)op.bcval[s] * ih2;
+        }
+      } else {
+        T beta;
+        if ((f >> s) & 1) {
+          const double tf = op.th[a][face_of_side(op.d, i, j, k, s)];
+          // lower cell of the link: this cell on a + side, the neighbour on a - side
+          const double rlo = up ? op.rho[ph] : op.rho[1 - ph];
+          const double rup = up ? op.rho[1 - ph] : op.rho[ph];
+          const double rf = tf * rlo + (1.0 - tf) * rup;
+          beta = (T)(op.dt / rf);
+        } else {
+          beta = (T)op.coef[ph];
+        }
+        diag += beta * ih2;
+        off[s] = -beta * ih2;
+      }
+    }
+  }
+  if (mexc) *mexc = mx;
+}
+
+// Explicit coarse level: symmetric 5/7-point operator, off[a][c] couples c and c + e_a.
+template <typename T>
+struct CoarseOp {
+  Dims d;
+  const T* diag;
+  const T* off[3];
+  const double* mass;  // used by the hierarchy builder only
+};
+
+__device__ inline void cell_ijk(const Dims& d, long long c, int& i, int& j, int& k) {
+  i = (int)(c % d.n[0]);
+  j = (int)((c / d.n[0]) % d.n[1]);
+  k = (int)(c / ((long long)d.n[0] * d.n[1]));
+}
+
+// ---------------------------------------------------------------------------
+// reductions (deterministic: fixed grid, fixed order)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// Block-wide sum of up to NV values per thread; result valid in thread 0.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* sh /* [NV * 4] */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) sh[q * 4 + w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = sh[q * 4 + 0] + sh[q * 4 + 1] + sh[q * 4 + 2] + sh[q * 4 + 3];
+  }
+}
+
+}  // namespace ebit
+
+// Host view of one multigrid level (level 0 = the matrix-free fine grid).
+struct EbitLevelHost {
+  ebit::Dims d;
+  double* diag64[2];   // [system]
+  double* mass64[2];
+  double* off64[2][3];
+  float* diag32[2];
+  float* off32[2][3];
+  double* x64;
+  double* b64;
+  float* x32;
+  float* b32;
+};
+
+// Work vectors of the outer loop (fine level).
+struct EbitSolveBufs {
+  double* r;
+  double* z64;
+  float* z32;
+  double* p[2];
+  double* q;
+  double* partial;     // [2][EBIT_RED_BLOCKS]
+  ebit::Scal* scal;
+};
+
+extern "C" {
+hipError_t ebit_launch_geometry(const ebit::Dims* d, double h, const double* const mk[3], const uint8_t* vcol,
+                                const uint8_t* ccol, uint8_t* flags, double* cF, double* nF, double* const th[3],
+                                ebit::Scal* scal, hipStream_t st);
+hipError_t ebit_launch_fill_f64(long long n, double* x, double v, hipStream_t st);
+hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
+hipError_t ebit_build_hierarchy(const ebit::FineOp* op, EbitLevelHost* lv, int nlev, int sys, int want32,
+                                hipStream_t st);
+hipError_t ebit_launch_apply(const ebit::FineOp* op, const double* x, double* y, hipStream_t st);
+hipError_t ebit_launch_heat_rhs(const ebit::FineOp* op, const double* Ts, double* b, hipStream_t st);
+hipError_t ebit_launch_finalize_max(const double* partial, int nb, ebit::Scal* sc, hipStream_t st);
+hipError_t ebit_launch_mass_flux(const ebit::Dims* d, double h, const double lam[2], double h_lg, double Tsat,
+                                 double theta_min, const uint8_t* flags, const double* const th[3], const double* cF,
+                                 const double* nF, const double* T, double* mdot, double* const mface[3],
+                                 ebit::Scal* scal, hipStream_t st);
+hipError_t ebit_launch_proj_rhs(const ebit::Dims* d, double h, const double rho[2], double dt, const int pbc[6],
+                                const double pval[6], const uint8_t* flags, const double* const th[3],
+                                const double* nF, const double* mdot, double* const ul[3], double* const uv[3],
+                                double* b, hipStream_t st);
+hipError_t ebit_launch_face_update(const ebit::Dims* d, double h, const double rho[2], double dt, const int pbc[6],
+                                   const double pval[6], const uint8_t* flags, const double* const th[3],
+                                   double* const ul[3], double* const uv[3], const double* p, double* partial,
+                                   ebit::Scal* scal, hipStream_t st);
+int ebit_solve_stream(const ebit::FineOp* op, const EbitLevelHost* lv, int nlev, const EbitSolveBufs* B,
+                      const double* b, double* x, int use_guess, const ebit_opts* o, hipStream_t st, int* iters,
+                      int* vcyc, double* relres, double* bnorm, double* floor, hipError_t* herr);
+}

@@ -1,0 +1,370 @@
+// EBIT markers -> interface facets -> cut fractions and cell flags (Sec. 2.1;
+// theta of Eq. ghost_T; centroid and normal of Eq. normal_gradient).
+//
+// One thread per edge / vertex / cell; every pass reads its inputs once,
+// coalesced along x.  The facet of an interface cell is its marker centroid
+// and the unit normal from vapour into liquid (two-marker perpendicular in 2D,
+// least-squares plane otherwise, via cyclic Jacobi on the 3x3 covariance).
+#pragma clang fp contract(off)
+
+#include "ebit_internal.h"
+
+namespace ebit {
+
+struct GeoArgs {
+  Dims d;
+  double h;
+  const double* mk[3];
+  const uint8_t* vcol;
+  const uint8_t* ccol;
+  uint8_t* flags;
+  double* cF;  // [3][N]
+  double* nF;  // [3][N]
+  double* th[3];
+  Scal* scal;
+};
+
+__host__ __device__ inline int nvz_of(const Dims& d) { return d.dim == 3 ? d.n[2] + 1 : 1; }
+
+__device__ inline long long vidx(const Dims& d, int i, int j, int k) {
+  return (long long)i + (long long)(d.n[0] + 1) * ((long long)j + (long long)(d.n[1] + 1) * k);
+}
+
+// edge (i,j,k) along axis a: vertex layout with one fewer entry along a
+__device__ inline long long eidx(const Dims& d, int a, int i, int j, int k) {
+  const int ex = d.n[0] + (a == 0 ? 0 : 1);
+  const int ey = d.n[1] + (a == 1 ? 0 : 1);
+  return (long long)i + (long long)ex * ((long long)j + (long long)ey * k);
+}
+
+// Marker present <=> end colours differ; s in [0, 1]; periodic seams agree.
+__global__ void k_check_markers(GeoArgs g, int a) {
+  const Dims& d = g.d;
+  const int ex = d.n[0] + (a == 0 ? 0 : 1);
+  const int ey = d.n[1] + (a == 1 ? 0 : 1);
+  const int ez = (d.dim == 3) ? d.n[2] + (a == 2 ? 0 : 1) : 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)ex * ey * ez) return;
+  const int i = (int)(t % ex);
+  const int j = (int)((t / ex) % ey);
+  const int k = (int)(t / ((long long)ex * ey));
+  int q[3] = {i, j, k};
+  const uint8_t c0 = g.vcol[vidx(d, i, j, k)];
+  q[a] += 1;
+  const uint8_t c1 = g.vcol[vidx(d, q[0], q[1], q[2])];
+  const double s = g.mk[a][t];
+  const bool has = !isnan(s);
+  int bad = 0;
+  if (has != (c0 != c1)) bad |= ERR_GEOM_MARKER;
+  if (has && !(s >= 0.0 && s <= 1.0)) bad |= ERR_GEOM_MARKER;
+  // periodic seam: an edge on the layer 0 of a periodic axis b != a equals its copy on layer n_b
+  for (int b = 0; b < d.dim; ++b) {
+    if (b == a || !d.per[b]) continue;
+    int r[3] = {i, j, k};
+    if (r[b] != 0) continue;
+    r[b] = d.n[b];
+    const double s2 = g.mk[a][eidx(d, a, r[0], r[1], r[2])];
+    const bool same = (isnan(s) && isnan(s2)) || (s == s2);
+    if (!same) bad |= ERR_GEOM_SEAM;
+  }
+  if (bad) atomicOr(&g.scal->err, bad);
+}
+
+__global__ void k_check_seam_vertices(GeoArgs g) {
+  const Dims& d = g.d;
+  const int vx = d.n[0] + 1, vy = d.n[1] + 1, vz = nvz_of(d);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)vx * vy * vz) return;
+  const int i = (int)(t % vx);
+  const int j = (int)((t / vx) % vy);
+  const int k = (int)(t / ((long long)vx * vy));
+  int q[3] = {i, j, k};
+  for (int b = 0; b < d.dim; ++b) {
+    if (!d.per[b] || q[b] != 0) continue;
+    int r[3] = {i, j, k};
+    r[b] = d.n[b];
+    if (g.vcol[t] != g.vcol[vidx(d, r[0], r[1], r[2])]) atomicOr(&g.scal->err, (int)ERR_GEOM_SEAM);
+  }
+}
+
+// Smallest-eigenvalue eigenvector of a symmetric m x m matrix (m = 2 or 3) by
+// cyclic Jacobi rotations.
+__device__ inline void min_eigvec(double A[3][3], int m, double v[3]) {
+  double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    double offn = 0.0, tot = 0.0;
+    for (int p = 0; p < m; ++p)
+      for (int q = 0; q < m; ++q) {
+        tot += A[p][q] * A[p][q];
+        if (p != q) offn += A[p][q] * A[p][q];
+      }
+    if (offn <= 1e-36 * tot) break;
+    for (int p = 0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
+        for (int r = 0; r < m; ++r) {
+          const double arp = A[r][p], arq = A[r][q];
+          A[r][p] = c * arp - s * arq;
+          A[r][q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < m; ++r) {
+          const double apr = A[p][r], aqr = A[q][r];
+          A[p][r] = c * apr - s * aqr;
+          A[q][r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < m; ++r) {
+          const double vrp = V[r][p], vrq = V[r][q];
+          V[r][p] = c * vrp - s * vrq;
+          V[r][q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  int best = 0;
+  for (int p = 1; p < m; ++p)
+    if (A[p][p] < A[best][best]) best = p;
+  for (int r = 0; r < 3; ++r) v[r] = (r < m) ? V[r][best] : 0.0;
+}
+
+// Facet of every interface cell; writes flags = liquid bit | interface bit.
+__global__ void k_facets(GeoArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  const int i = (int)(c % d.n[0]);
+  const int j = (int)((c / d.n[0]) % d.n[1]);
+  const int k = (int)(c / ((long long)d.n[0] * d.n[1]));
+  const double h = g.h;
+  double P[12][3];
+  int cnt = 0;
+  const int noff = (d.dim == 3) ? 4 : 2;
+  for (int a = 0; a < d.dim; ++a) {
+    int oth[2];
+    int no = 0;
+    for (int b = 0; b < d.dim; ++b)
+      if (b != a) oth[no++] = b;
+    for (int o = 0; o < noff; ++o) {
+      const int ob = o & 1, oc = o >> 1;
+      int q[3] = {i, j, k};
+      q[oth[0]] += ob;
+      if (d.dim == 3) q[oth[1]] += oc;
+      const double s = g.mk[a][eidx(d, a, q[0], q[1], q[2])];
+      if (isnan(s)) continue;
+      double pos[3] = {q[0] * h, q[1] * h, (d.dim == 3) ? q[2] * h : 0.0};
+      pos[a] = pos[a] + s * h;
+      P[cnt][0] = pos[0];
+      P[cnt][1] = pos[1];
+      P[cnt][2] = pos[2];
+      ++cnt;
+    }
+  }
+  const int need = (d.dim == 2) ? 2 : 3;
+  const uint8_t liq = g.ccol[c] ? F_LIQ : 0;
+  if (cnt < need) {
+    g.flags[c] = liq;
+    return;
+  }
+  double cen[3] = {0, 0, 0};
+  for (int q = 0; q < cnt; ++q)
+    for (int r = 0; r < 3; ++r) cen[r] += P[q][r];
+  for (int r = 0; r < 3; ++r) cen[r] = cen[r] / (double)cnt;
+  double n[3] = {0, 0, 0};
+  bool ok = false;
+  if (d.dim == 2 && cnt == 2) {
+    const double dx = P[1][0] - P[0][0], dy = P[1][1] - P[0][1];
+    const double L = hypot(dx, dy);
+    if (L > 0) {
+      n[0] = -dy / L;
+      n[1] = dx / L;
+      ok = true;
+    }
+  } else {
+    double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < cnt; ++q) {
+      double x[3];
+      for (int r = 0; r < 3; ++r) x[r] = P[q][r] - cen[r];
+      for (int r = 0; r < 3; ++r)
+        for (int s2 = 0; s2 < 3; ++s2) C[r][s2] += x[r] * x[s2];
+    }
+    double mx = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int s2 = 0; s2 < 3; ++s2) mx = fmax(mx, fabs(C[r][s2]));
+    if (mx > 0) {
+      min_eigvec(C, d.dim, n);
+      const double L = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int r = 0; r < 3; ++r) n[r] /= L;
+      ok = true;
+    }
+  }
+  // corners, in the order (dk, dj, di)
+  double gsum[3] = {0, 0, 0};
+  double corner_pos[8][3];
+  double corner_w[8];
+  int ncorner = 0;
+  for (int dk = 0; dk < (d.dim == 3 ? 2 : 1); ++dk)
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) {
+        const double col = (double)g.vcol[vidx(d, i + di, j + dj, k + dk)];
+        corner_pos[ncorner][0] = (i + di) * h;
+        corner_pos[ncorner][1] = (j + dj) * h;
+        corner_pos[ncorner][2] = (d.dim == 3) ? (k + dk) * h : 0.0;
+        corner_w[ncorner] = 2.0 * col - 1.0;
+        ++ncorner;
+      }
+  if (!ok) {
+    for (int q = 0; q < ncorner; ++q)
+      for (int r = 0; r < 3; ++r) gsum[r] += corner_w[q] * (corner_pos[q][r] - cen[r]);
+    const double L = sqrt(gsum[0] * gsum[0] + gsum[1] * gsum[1] + gsum[2] * gsum[2]);
+    for (int r = 0; r < 3; ++r) n[r] = gsum[r] / L;
+  }
+  double s = 0.0;
+  for (int q = 0; q < ncorner; ++q) {
+    const double dot = n[0] * (corner_pos[q][0] - cen[0]) + n[1] * (corner_pos[q][1] - cen[1]) +
+                       n[2] * (corner_pos[q][2] - cen[2]);
+    s += corner_w[q] * dot;
+  }
+  if (s == 0.0) {
+    const double xc[3] = {(i + 0.5) * h, (j + 0.5) * h, (d.dim == 3) ? (k + 0.5) * h : 0.0};
+    const double fc = (double)g.ccol[c];
+    s = (2.0 * fc - 1.0) *
+        (n[0] * (xc[0] - cen[0]) + n[1] * (xc[1] - cen[1]) + n[2] * (xc[2] - cen[2]));
+  }
+  if (s < 0.0)
+    for (int r = 0; r < 3; ++r) n[r] = -n[r];
+  for (int r = 0; r < 3; ++r) {
+    g.cF[r * d.N + c] = cen[r];
+    g.nF[r * d.N + c] = n[r];
+  }
+  g.flags[c] = liq | F_IF;
+}
+
+// theta of the link from lower cell (li,lj,lk) to upper cell (ui,uj,uk) along
+// axis a, measured from the lower cell; wrap = the upper cell is across the
+// periodic seam.  Returns false if neither cell carries a facet.
+__device__ inline bool link_theta(const GeoArgs& g, int a, int li, int lj, int lk, int ui, int uj,
+                                  int uk, bool wrap, double& theta) {
+  const Dims& d = g.d;
+  const double h = g.h;
+  const long long lo = cell_index(d, li, lj, lk), hi = cell_index(d, ui, uj, uk);
+  const double xc[3] = {(li + 0.5) * h, (lj + 0.5) * h, (d.dim == 3) ? (lk + 0.5) * h : 0.0};
+  double tv[2];
+  bool valid[2], exist[2];
+  int nfacet = 0;
+  for (int side = 0; side < 2; ++side) {
+    const long long X = side ? hi : lo;
+    valid[side] = exist[side] = false;
+    if (!(g.flags[X] & F_IF)) continue;
+    ++nfacet;
+    double n[3], cen[3];
+    for (int r = 0; r < 3; ++r) {
+      n[r] = g.nF[r * d.N + X];
+      cen[r] = g.cF[r * d.N + X];
+    }
+    if (fabs(n[a]) < 1e-12) continue;
+    if (side == 1 && wrap) cen[a] += d.n[a] * h;
+    const double dot = (cen[0] - xc[0]) * n[0] + (cen[1] - xc[1]) * n[1] + (cen[2] - xc[2]) * n[2];
+    const double t = dot / (h * n[a]);
+    tv[side] = t;
+    exist[side] = true;
+    valid[side] = side ? (t >= 0.5 && t <= 1.0) : (t >= 0.0 && t <= 0.5);
+  }
+  if (nfacet == 0) {
+    theta = 0.5;
+    return false;
+  }
+  if (valid[0] && valid[1])
+    theta = 0.5 * (tv[0] + tv[1]);
+  else if (valid[0])
+    theta = tv[0];
+  else if (valid[1])
+    theta = tv[1];
+  else if (exist[0] || exist[1]) {
+    double sum = 0.0;
+    int m = 0;
+    for (int side = 0; side < 2; ++side)
+      if (exist[side]) {
+        sum += tv[side];
+        ++m;
+      }
+    double t = sum / m;
+    theta = fmin(fmax(t, 0.0), 1.0);
+  } else {
+    theta = 0.5;
+  }
+  return true;
+}
+
+// Cut bits of every side, and theta on the + faces (and face 0 of each axis).
+__global__ void k_theta_flags(GeoArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  const int i = (int)(c % d.n[0]);
+  const int j = (int)((c / d.n[0]) % d.n[1]);
+  const int k = (int)(c / ((long long)d.n[0] * d.n[1]));
+  uint8_t f = g.flags[c];
+  const uint8_t myc = g.ccol[c];
+  const double qnan = __builtin_nan("");
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    int ni, nj, nk;
+    const bool has = neighbour(d, i, j, k, s, ni, nj, nk);
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    const bool cut = has && (g.ccol[cell_index(d, ni, nj, nk)] != myc);
+    if (cut) f |= (uint8_t)(1u << s);
+    // faces this cell writes: its + face, and face 0 when it is the first cell
+    if (up || ia == 0) {
+      double th = qnan;
+      if (cut) {
+        bool ok;
+        if (up)
+          ok = link_theta(g, a, i, j, k, ni, nj, nk, ia == d.n[a] - 1, th);
+        else
+          ok = link_theta(g, a, ni, nj, nk, i, j, k, true, th);
+        if (!ok) atomicOr(&g.scal->err, (int)ERR_GEOM_NOFACET);
+      }
+      g.th[a][face_of_side(d, i, j, k, s)] = th;
+    }
+  }
+  g.flags[c] = f;
+}
+
+}  // namespace ebit
+
+using namespace ebit;
+
+// host launcher used by the API layer
+extern "C" hipError_t ebit_launch_geometry(const Dims* d, double h, const double* const mk[3],
+                                           const uint8_t* vcol, const uint8_t* ccol, uint8_t* flags,
+                                           double* cF, double* nF, double* const th[3], Scal* scal,
+                                           hipStream_t st) {
+  GeoArgs g;
+  g.d = *d;
+  g.h = h;
+  for (int a = 0; a < 3; ++a) {
+    g.mk[a] = (a < d->dim) ? mk[a] : nullptr;
+    g.th[a] = (a < d->dim) ? th[a] : nullptr;
+  }
+  g.vcol = vcol;
+  g.ccol = ccol;
+  g.flags = flags;
+  g.cF = cF;
+  g.nF = nF;
+  g.scal = scal;
+  for (int a = 0; a < d->dim; ++a) {
+    const long long ne = (long long)(d->n[0] + (a == 0 ? 0 : 1)) * (d->n[1] + (a == 1 ? 0 : 1)) *
+                         ((d->dim == 3) ? d->n[2] + (a == 2 ? 0 : 1) : 1);
+    hipLaunchKernelGGL(k_check_markers, dim3((unsigned)((ne + EBIT_BLOCK - 1) / EBIT_BLOCK)),
+                       dim3(EBIT_BLOCK), 0, st, g, a);
+  }
+  const long long nv = (long long)(d->n[0] + 1) * (d->n[1] + 1) * nvz_of(*d);
+  hipLaunchKernelGGL(k_check_seam_vertices, dim3((unsigned)((nv + EBIT_BLOCK - 1) / EBIT_BLOCK)),
+                     dim3(EBIT_BLOCK), 0, st, g);
+  const unsigned nb = (unsigned)((d->N + EBIT_BLOCK - 1) / EBIT_BLOCK);
+  hipLaunchKernelGGL(k_facets, dim3(nb), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_theta_flags, dim3(nb), dim3(EBIT_BLOCK), 0, st, g);
+  return hipGetLastError();
+}

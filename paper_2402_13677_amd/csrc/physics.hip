@@ -1,0 +1,474 @@
+// Mass flux from one-sided gradients (Eqs. mass_flux_computation,
+// normal_gradient) with the one-layer FP64 ghost values of Eq. ghost_T, and
+// the ghost-fluid projection around the Poisson solve (Eqs. ghost_velocity,
+// poisson_ghost_fluid, face update).
+//
+// Sign reading: the facet normal points from vapour into liquid; the
+// gradient into each phase is taken along +n (liquid) and -n (vapour), so
+// mdot > 0 is evaporation, and the ghosts are u_liq^g = u_vap - mdot [1/rho] n,
+// u_vap^g = u_liq + mdot [1/rho] n with [1/rho] = 1/rho_liq - 1/rho_vap.
+//
+// Everything here is FP64: the ghost extrapolation amplifies T by
+// (1 - theta)/theta, which exceeds 19 for theta < 0.05.
+#pragma clang fp contract(off)
+
+#include "ebit_internal.h"
+
+namespace ebit {
+
+struct FluxArgs {
+  Dims d;
+  double h;
+  double lam[2];  // [vapour, liquid]
+  double h_lg, Tsat, theta_min;
+  const uint8_t* flags;
+  const double* th[3];
+  const double* cF;  // [3][N]
+  const double* nF;
+  const double* T;
+  double* mdot;
+  double* mface[3];
+  Scal* scal;
+};
+
+// T of phase k at cell (i,j,k) (periodic wrap), from the cell itself or its
+// ghost value (mean of Eq. ghost_T over its cut links); false if unavailable.
+__device__ inline bool value_k(const FluxArgs& g, int kph, int i, int j, int k, double& v) {
+  const Dims& d = g.d;
+  int q[3] = {i, j, k};
+  for (int a = 0; a < d.dim; ++a) {
+    if (q[a] < 0 || q[a] >= d.n[a]) {
+      if (!d.per[a]) return false;
+      q[a] = ((q[a] % d.n[a]) + d.n[a]) % d.n[a];
+    }
+  }
+  const long long c = cell_index(d, q[0], q[1], q[2]);
+  const uint8_t f = g.flags[c];
+  const int ph = (f & F_LIQ) ? 1 : 0;
+  if (ph == kph) {
+    v = g.T[c];
+    return true;
+  }
+  double acc = 0.0;
+  int cnt = 0;
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    if (!((f >> s) & 1)) continue;
+    int ni, nj, nk;
+    neighbour(d, q[0], q[1], q[2], s, ni, nj, nk);
+    const double tf = g.th[s >> 1][face_of_side(d, q[0], q[1], q[2], s)];
+    const double th_g = (s & 1) ? tf : 1.0 - tf;  // from the ghost cell's centre
+    double th_c = 1.0 - th_g;                     // from the phase-k cell's centre
+    if (th_c < g.theta_min) th_c = g.theta_min;
+    const double Tc = g.T[cell_index(d, ni, nj, nk)];
+    acc += g.Tsat + (g.Tsat - Tc) * (1.0 - th_c) / th_c;
+    ++cnt;
+  }
+  if (cnt == 0) return false;
+  v = acc / (double)cnt;
+  return true;
+}
+
+__device__ inline void lagrange3(double t, double w[3]) {
+  w[0] = 0.5 * t * (t - 1.0);
+  w[1] = (1.0 - t) * (1.0 + t);
+  w[2] = 0.5 * t * (t + 1.0);
+}
+
+__device__ inline void clamp_block(const FluxArgs& g, int ctr[3]) {
+  for (int a = 0; a < g.d.dim; ++a)
+    if (!g.d.per[a]) ctr[a] = min(max(ctr[a], 1), g.d.n[a] - 2);
+}
+
+__device__ inline bool interp_block(const FluxArgs& g, int kph, const double P[3], const int ctr[3], double& out) {
+  const double h = g.h;
+  double w[3][3];
+  for (int a = 0; a < 3; ++a) {
+    if (a < g.d.dim) {
+      const double t = (P[a] - (ctr[a] + 0.5) * h) / h;
+      lagrange3(t, w[a]);
+    } else {
+      w[a][0] = 0.0;
+      w[a][1] = 1.0;
+      w[a][2] = 0.0;
+    }
+  }
+  double tot = 0.0;
+  const int kr = (g.d.dim == 3) ? 1 : 0;
+  for (int dk = -kr; dk <= kr; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        double v;
+        if (!value_k(g, kph, ctr[0] + di, ctr[1] + dj, ctr[2] + dk, v)) return false;
+        tot += w[0][di + 1] * w[1][dj + 1] * w[2][dk + 1] * v;
+      }
+  out = tot;
+  return true;
+}
+
+__device__ inline bool point_value(const FluxArgs& g, int kph, const double P[3], const double sd[3], double& v) {
+  int ctr[3] = {0, 0, 0};
+  for (int a = 0; a < g.d.dim; ++a) ctr[a] = (int)floor(P[a] / g.h);
+  clamp_block(g, ctr);
+  if (interp_block(g, kph, P, ctr, v)) return true;
+  int am = 0;
+  for (int a = 1; a < g.d.dim; ++a)
+    if (fabs(sd[a]) > fabs(sd[am])) am = a;
+  ctr[am] += (sd[am] > 0) ? 1 : -1;
+  clamp_block(g, ctr);
+  return interp_block(g, kph, P, ctr, v);
+}
+
+// first-order fallback from the nearest phase-k centre around P1
+__device__ inline double fallback_grad(const FluxArgs& g, int kph, const double cF[3], const double sd[3],
+                                       const double P1[3]) {
+  const Dims& d = g.d;
+  const double h = g.h;
+  int ctr[3] = {0, 0, 0};
+  for (int a = 0; a < d.dim; ++a) ctr[a] = (int)floor(P1[a] / h);
+  double best_d = 0.0, best_p = 0.0, best_T = 0.0;
+  long long best_c = -1;
+  const int kr = (d.dim == 3) ? 1 : 0;
+  for (int dk = -kr; dk <= kr; ++dk)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int di = -1; di <= 1; ++di) {
+        int q[3] = {ctr[0] + di, ctr[1] + dj, ctr[2] + dk};
+        bool ok = true;
+        for (int a = 0; a < d.dim; ++a)
+          if (q[a] < 0 || q[a] >= d.n[a]) {
+            if (d.per[a])
+              q[a] = ((q[a] % d.n[a]) + d.n[a]) % d.n[a];
+            else
+              ok = false;
+          }
+        if (!ok) continue;
+        const long long c = cell_index(d, q[0], q[1], q[2]);
+        if (((g.flags[c] & F_LIQ) ? 1 : 0) != kph) continue;
+        const double x[3] = {(ctr[0] + di + 0.5) * h, (ctr[1] + dj + 0.5) * h,
+                             (d.dim == 3) ? (ctr[2] + dk + 0.5) * h : 0.0};
+        const double proj = (x[0] - cF[0]) * sd[0] + (x[1] - cF[1]) * sd[1] + (x[2] - cF[2]) * sd[2];
+        if (proj <= 0) continue;
+        const double dist = (x[0] - P1[0]) * (x[0] - P1[0]) + (x[1] - P1[1]) * (x[1] - P1[1]) +
+                            (x[2] - P1[2]) * (x[2] - P1[2]);
+        if (best_c < 0 || dist < best_d || (dist == best_d && c < best_c)) {
+          best_c = c;
+          best_d = dist;
+          best_p = proj;
+          best_T = g.T[c];
+        }
+      }
+  if (best_c < 0) return 0.0;
+  return (best_T - g.Tsat) / best_p;
+}
+
+__global__ void k_mass_flux(FluxArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  const uint8_t f = g.flags[c];
+  if (!(f & F_IF)) {
+    g.mdot[c] = 0.0;
+    return;
+  }
+  const double h = g.h;
+  double cF[3], nF[3];
+  for (int r = 0; r < 3; ++r) {
+    cF[r] = g.cF[r * d.N + c];
+    nF[r] = g.nF[r * d.N + c];
+  }
+  const double d1 = h, d2 = 2.0 * h;
+  double D[2];
+  int fb = 0;
+  for (int kk = 0; kk < 2; ++kk) {
+    const int kph = kk == 0 ? 1 : 0;  // liquid first, as the oracle does
+    const double sg = kph ? 1.0 : -1.0;
+    double sd[3], P1[3], P2[3];
+    for (int r = 0; r < 3; ++r) {
+      sd[r] = sg * nF[r];
+      P1[r] = cF[r] + d1 * sd[r];
+      P2[r] = cF[r] + d2 * sd[r];
+    }
+    double T1, T2;
+    const bool ok1 = point_value(g, kph, P1, sd, T1);
+    const bool ok2 = ok1 && point_value(g, kph, P2, sd, T2);
+    if (ok1 && ok2) {
+      D[kph] = (d2 / d1 * (T1 - g.Tsat) - d1 / d2 * (T2 - g.Tsat)) / (d2 - d1);
+    } else {
+      ++fb;
+      D[kph] = fallback_grad(g, kph, cF, sd, P1);
+    }
+  }
+  g.mdot[c] = (g.lam[1] * D[1] + g.lam[0] * D[0]) / g.h_lg;
+  if (fb) atomicAdd(&g.scal->fallbacks, fb);
+}
+
+// mdot on cut faces: value of the cell holding the crossing (theta <= 1/2 ->
+// lower cell), the other one if that cell has no facet.  NaN elsewhere.
+__global__ void k_mass_flux_faces(FluxArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  const uint8_t f = g.flags[c];
+  const double qnan = __builtin_nan("");
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    if (!(up || ia == 0)) continue;
+    const long long fi = face_of_side(d, i, j, k, s);
+    double v = qnan;
+    if ((f >> s) & 1) {
+      int ni, nj, nk;
+      neighbour(d, i, j, k, s, ni, nj, nk);
+      const long long nb = cell_index(d, ni, nj, nk);
+      const long long lo = up ? c : nb, hi = up ? nb : c;
+      const double t = g.th[a][fi];
+      long long hold = (t <= 0.5) ? lo : hi;
+      if (!(g.flags[hold] & F_IF)) hold = (hold == lo) ? hi : lo;
+      v = g.mdot[hold];
+    }
+    g.mface[a][fi] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection
+// ---------------------------------------------------------------------------
+struct ProjArgs {
+  Dims d;
+  double h;
+  double jump;  // [1/rho] = 1/rho_l - 1/rho_v
+  double rho[2];
+  double dt;
+  int pbc[6];
+  double pval[6];
+  const uint8_t* flags;
+  const double* th[3];
+  const double* nF;
+  const double* mdot;
+  double* ul[3];
+  double* uv[3];
+  const double* p;
+  double* b;
+  double* partial;
+};
+
+// Ghost value on every cut face (Eq. ghost_velocity).  Each cell handles its
+// + faces and, on the first layer, face 0 (the periodic copy of face n).
+__global__ void k_ghost_vel(ProjArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  const uint8_t f = g.flags[c];
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    if (!((f >> s) & 1)) continue;
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    if (!(up || ia == 0)) continue;
+    int ni, nj, nk;
+    neighbour(d, i, j, k, s, ni, nj, nk);
+    const long long nb = cell_index(d, ni, nj, nk);
+    const long long lo = up ? c : nb, hi = up ? nb : c;
+    const long long fi = face_of_side(d, i, j, k, s);
+    const double t = g.th[a][fi];
+    const int col_lo = (g.flags[lo] & F_LIQ) ? 1 : 0, col_hi = (g.flags[hi] & F_LIQ) ? 1 : 0;
+    const int kf = (t > 0.5) ? col_lo : ((t < 0.5) ? col_hi : 1);
+    long long hold = (t <= 0.5) ? lo : hi;
+    if (!(g.flags[hold] & F_IF)) hold = (hold == lo) ? hi : lo;
+    const double jmp = g.mdot[hold] * g.jump * g.nF[a * d.N + hold];
+    if (kf == 1)
+      g.uv[a][fi] = g.ul[a][fi] + jmp;
+    else
+      g.ul[a][fi] = g.uv[a][fi] - jmp;
+  }
+}
+
+// b = bc - div_c u_{k(c)}  (right-hand side of the SPD system -L p = b)
+__global__ void k_proj_rhs(ProjArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  const uint8_t f = g.flags[c];
+  const int ph = (f & F_LIQ) ? 1 : 0;
+  double div = 0.0;
+  for (int a = 0; a < d.dim; ++a) {
+    const double* u = ph ? g.ul[a] : g.uv[a];
+    div += u[face_of_side(d, i, j, k, 2 * a + 1)] - u[face_of_side(d, i, j, k, 2 * a)];
+  }
+  div = div / g.h;
+  double bc = 0.0;
+  const double ih2 = 1.0 / (g.h * g.h);
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    const bool wall = !d.per[a] && (up ? (ia == d.n[a] - 1) : (ia == 0));
+    if (wall && g.pbc[s] == EBIT_BC_DIRICHLET) bc += 2.0 * (g.dt / g.rho[ph]) * g.pval[s] * ih2;
+  }
+  g.b[c] = bc - div;
+}
+
+// beta_f and the gradient across side s of cell (i,j,k); false if no update
+__device__ inline bool face_grad(const ProjArgs& g, int i, int j, int k, long long c, int s, double& beta,
+                                 double& grad) {
+  const Dims& d = g.d;
+  const int a = s >> 1, up = s & 1;
+  const int ia = (a == 0) ? i : (a == 1) ? j : k;
+  const uint8_t f = g.flags[c];
+  const int ph = (f & F_LIQ) ? 1 : 0;
+  const bool wall = !d.per[a] && (up ? (ia == d.n[a] - 1) : (ia == 0));
+  const double pc = g.p[c];
+  if (wall) {
+    if (g.pbc[s] != EBIT_BC_DIRICHLET) return false;
+    beta = g.dt / g.rho[ph];
+    grad = up ? 2.0 * (g.pval[s] - pc) / g.h : 2.0 * (pc - g.pval[s]) / g.h;
+    return true;
+  }
+  int ni, nj, nk;
+  neighbour(d, i, j, k, s, ni, nj, nk);
+  const long long nb = cell_index(d, ni, nj, nk);
+  if ((f >> s) & 1) {
+    const double tf = g.th[a][face_of_side(d, i, j, k, s)];
+    const double rlo = up ? g.rho[ph] : g.rho[1 - ph];
+    const double rup = up ? g.rho[1 - ph] : g.rho[ph];
+    beta = g.dt / (tf * rlo + (1.0 - tf) * rup);
+  } else {
+    beta = g.dt / g.rho[ph];
+  }
+  grad = up ? (g.p[nb] - pc) / g.h : (pc - g.p[nb]) / g.h;
+  return true;
+}
+
+// u <- u - beta_f grad p on both fields; each cell writes its + faces and, on
+// the first layer, face 0 (so every face is written exactly once).
+__global__ void k_face_update(ProjArgs g) {
+  const Dims& d = g.d;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    if (!(up || ia == 0)) continue;
+    double beta, grad;
+    if (!face_grad(g, i, j, k, c, s, beta, grad)) continue;
+    const long long fi = face_of_side(d, i, j, k, s);
+    const double dl = beta * grad;
+    g.ul[a][fi] = g.ul[a][fi] - dl;
+    g.uv[a][fi] = g.uv[a][fi] - dl;
+  }
+}
+
+// max_c |div_c u_{k(c)}| of the updated fields (a separate pass: every face
+// is final when it is read)
+__global__ void k_divmax(ProjArgs g) {
+  const Dims& d = g.d;
+  double vmax = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < d.N;
+       c += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
+    const int ph = (g.flags[c] & F_LIQ) ? 1 : 0;
+    double div = 0.0;
+    for (int a = 0; a < d.dim; ++a) {
+      const double* u = ph ? g.ul[a] : g.uv[a];
+      div += u[face_of_side(d, i, j, k, 2 * a + 1)] - u[face_of_side(d, i, j, k, 2 * a)];
+    }
+    div = div / g.h;
+    vmax = fmax(vmax, fabs(div));
+  }
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double m = wave_max(vmax);
+  if (lane == 0) sh[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) g.partial[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+static inline unsigned nblk(long long n) { return (unsigned)((n + EBIT_BLOCK - 1) / EBIT_BLOCK); }
+
+}  // namespace ebit
+
+using namespace ebit;
+
+extern "C" hipError_t ebit_launch_mass_flux(const Dims* d, double h, const double lam[2], double h_lg, double Tsat,
+                                            double theta_min, const uint8_t* flags, const double* const th[3],
+                                            const double* cF, const double* nF, const double* T, double* mdot,
+                                            double* const mface[3], Scal* scal, hipStream_t st) {
+  FluxArgs g;
+  g.d = *d;
+  g.h = h;
+  g.lam[0] = lam[0];
+  g.lam[1] = lam[1];
+  g.h_lg = h_lg;
+  g.Tsat = Tsat;
+  g.theta_min = theta_min;
+  g.flags = flags;
+  for (int a = 0; a < 3; ++a) {
+    g.th[a] = (a < d->dim) ? th[a] : nullptr;
+    g.mface[a] = (mface && a < d->dim) ? mface[a] : nullptr;
+  }
+  g.cF = cF;
+  g.nF = nF;
+  g.T = T;
+  g.mdot = mdot;
+  g.scal = scal;
+  hipLaunchKernelGGL(k_mass_flux, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  if (mface) hipLaunchKernelGGL(k_mass_flux_faces, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  return hipGetLastError();
+}
+
+static ProjArgs make_proj(const Dims* d, double h, const double rho[2], double dt, const int pbc[6],
+                          const double pval[6], const uint8_t* flags, const double* const th[3], const double* nF,
+                          const double* mdot, double* const ul[3], double* const uv[3], const double* p, double* b,
+                          double* partial) {
+  ProjArgs g;
+  g.d = *d;
+  g.h = h;
+  g.rho[0] = rho[0];
+  g.rho[1] = rho[1];
+  g.jump = 1.0 / rho[1] - 1.0 / rho[0];
+  g.dt = dt;
+  for (int s = 0; s < 6; ++s) {
+    g.pbc[s] = pbc[s];
+    g.pval[s] = pval[s];
+  }
+  g.flags = flags;
+  for (int a = 0; a < 3; ++a) {
+    g.th[a] = (a < d->dim) ? th[a] : nullptr;
+    g.ul[a] = (a < d->dim) ? ul[a] : nullptr;
+    g.uv[a] = (a < d->dim) ? uv[a] : nullptr;
+  }
+  g.nF = nF;
+  g.mdot = mdot;
+  g.p = p;
+  g.b = b;
+  g.partial = partial;
+  return g;
+}
+
+extern "C" hipError_t ebit_launch_proj_rhs(const Dims* d, double h, const double rho[2], double dt, const int pbc[6],
+                                           const double pval[6], const uint8_t* flags, const double* const th[3],
+                                           const double* nF, const double* mdot, double* const ul[3],
+                                           double* const uv[3], double* b, hipStream_t st) {
+  ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nF, mdot, ul, uv, nullptr, b, nullptr);
+  hipLaunchKernelGGL(k_ghost_vel, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_proj_rhs, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t ebit_launch_face_update(const Dims* d, double h, const double rho[2], double dt,
+                                              const int pbc[6], const double pval[6], const uint8_t* flags,
+                                              const double* const th[3], double* const ul[3], double* const uv[3],
+                                              const double* p, double* partial, Scal* scal, hipStream_t st) {
+  ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nullptr, nullptr, ul, uv, p, nullptr, partial);
+  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_divmax, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
+}

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every entry point include/ebit.h
+declares; host-only calls behave without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2402_13677_amd import ebit
+import ebit_inputs as ei
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ebit.h")).read()
+    decl = re.compile(r"^(?:const\s+)?[a-z_]+\s*\*?\s*(ebit_[a-z_0-9]+)\s*\(", re.M)
+    return sorted(set(decl.findall(txt)))
+
+
+def test_header_symbols_exported():
+    lib = ebit.load()
+    names = declared_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(ebit.EXPORTED) == names
+
+
+def test_default_opts_and_status_strings():
+    o = ebit.default_opts()
+    assert o.precision == ebit.FP64 and o.outer == ebit.OUTER_PCG
+    assert o.rtol == 1e-9 and o.nu1 == 2 and o.nu2 == 2 and o.theta_min == 1e-3
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert ebit.status_string(s) != "unknown status"
+
+
+def _bytes(grid):
+    o = ebit.default_opts()
+    return ebit.load().ebit_workspace_bytes(ctypes.byref(grid), ctypes.byref(o))
+
+
+def test_workspace_bytes_valid_and_invalid_grids():
+    c = ei.config(0)
+    g = ebit.make_grid(c.dim, c.n, c.h, c.T_bc, c.p_bc)
+    n = _bytes(g)
+    assert n > 64 * 64 * 100
+    bad = ebit.make_grid(2, (2, 64, 1), 1 / 64, c.T_bc, c.p_bc)     # n < 3
+    assert _bytes(bad) == 0
+    bad = ebit.make_grid(2, (64, 64, 4), 1 / 64, c.T_bc, c.p_bc)    # n[2] != 1 in 2D
+    assert _bytes(bad) == 0
+    per = [(2, 0.0), (2, 0.0), (0, 0.0), (0, 0.0)]
+    bad = ebit.make_grid(2, (48, 64, 1), 1 / 64, per, per)           # periodic, not a power of two
+    assert _bytes(bad) == 0
+    onlyT = [(2, 0.0), (2, 0.0), (0, 0.0), (0, 0.0)]
+    bad = ebit.make_grid(2, (64, 64, 1), 1 / 64, onlyT, c.p_bc)      # periodic for T only
+    assert _bytes(bad) == 0
+    ok = ebit.make_grid(2, (64, 64, 1), 1 / 64, per, per)
+    assert _bytes(ok) > 0
+
+
+def test_workspace_scales_with_cells():
+    f = ei.config(4, 32)
+    g = ebit.make_grid(f.dim, f.n, f.h, f.T_bc, f.p_bc)
+    n32 = _bytes(g)
+    g64 = ebit.make_grid(3, (64, 64, 64), 1 / 64, f.T_bc, f.p_bc)
+    n64 = _bytes(g64)
+    assert 7.0 < n64 / n32 < 9.0
