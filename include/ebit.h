@@ -98,7 +98,8 @@ typedef struct {
                          inside the FP64 outer loop)                          */
   int outer;          /* EBIT_OUTER_PCG [default]: flexible CG preconditioned
                          by one V-cycle; EBIT_OUTER_DC: defect correction
-                         x += V(b - A x)                                      */
+                         x += alpha V(b - A x) with the energy-optimal step
+                         alpha = (r.z)/(z.Az)                                 */
   double rtol;        /* relative L2 residual ||b - A x|| / ||b|| [1e-9]; a
                          target below the residual's rounding floor stops
                          at the floor (ebit_stats.res_floor)                  */

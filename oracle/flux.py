@@ -116,15 +116,17 @@ def _point_value(case, k, T, ghost, P, s_dir):
     return _interp(case, k, T, ghost, P, centre)
 
 
-def mass_flux(case, geo, T, theta_min=1e-3):
-    """Per-cell mdot (0 off the interface) and the number of fallbacks."""
+def mass_flux(case, geo, T, theta_min=1e-3, cells=None):
+    """Per-cell mdot (0 off the interface) and the number of fallbacks;
+    ``cells`` restricts the evaluation to a sample of interface cells."""
     pr, h, dim = case.props, case.h, case.dim
     ghost = ghost_fill(case, geo, T, theta_min)
     N = case.ccol.size
     mdot = np.zeros(N)
     fallbacks = 0
     d1, d2 = h, 2.0 * h
-    for c in np.nonzero(geo["is_if"])[0]:
+    todo = np.nonzero(geo["is_if"])[0] if cells is None else np.asarray(cells)
+    for c in todo:
         cF, nF = geo["cF"][c], geo["nF"][c]
         D = {}
         for k, sgn in ((1, 1.0), (0, -1.0)):

@@ -32,22 +32,19 @@ class GeometryError(ValueError):
     pass
 
 
-def _edge_marker_positions(case):
-    """List of (positions [ncell, 3], present [ncell]) per cell edge slot."""
+def _edge_marker_positions(case, cells):
+    """For the given cells: list over the cell's edge slots (axis-major, then
+    transverse offsets) of (positions [n, 3], present [n])."""
     dim, h = case.dim, case.h
-    nx, ny, nz = case.n
-    nzc = nz if dim == 3 else 1
-    k, j, i = np.meshgrid(np.arange(nzc), np.arange(ny), np.arange(nx), indexing="ij")
-    k, j, i = k.ravel(), j.ravel(), i.ravel()
+    nx, ny, _ = case.n
+    i, j, k = cells % nx, (cells // nx) % ny, cells // (nx * ny)
     slots = []
     offs = [(0, 0), (1, 0), (0, 1), (1, 1)] if dim == 3 else [(0, 0), (1, 0)]
     for a in range(dim):
         m = case.markers[a]
+        others = [x for x in range(dim) if x != a]
         for (b, c) in offs:
-            # transverse offsets: the two other axes (in increasing order)
-            ii, jj, kk = i.copy(), j.copy(), k.copy()
-            others = [x for x in range(dim) if x != a]
-            idx = [ii, jj, kk]
+            idx = [i.copy(), j.copy(), k.copy()]
             idx[others[0]] = idx[others[0]] + b
             if dim == 3:
                 idx[others[1]] = idx[others[1]] + c
@@ -59,6 +56,26 @@ def _edge_marker_positions(case):
             pos[:, a] = pos[:, a] + np.where(np.isnan(s), 0.0, s) * h
             slots.append((pos, ~np.isnan(s)))
     return slots
+
+
+def _marker_count(case):
+    """Number of markers on the edges of every cell (uint8, cell layout)."""
+    dim = case.dim
+    nz = case.n[2] if dim == 3 else 1
+    cnt = np.zeros((nz, case.n[1], case.n[0]), np.uint8)
+    for a in range(dim):
+        has = (~np.isnan(case.markers[a])).astype(np.uint8)
+        others = [x for x in range(dim) if x != a]
+        offs = [(0, 0), (1, 0), (0, 1), (1, 1)] if dim == 3 else [(0, 0), (1, 0)]
+        for (b, c) in offs:
+            sl = [slice(0, nz), slice(0, case.n[1]), slice(0, case.n[0])]
+            o = [0, 0, 0]
+            o[others[0]] = b
+            if dim == 3:
+                o[others[1]] = c
+            sl = [slice(o[2], o[2] + nz), slice(o[1], o[1] + case.n[1]), slice(o[0], o[0] + case.n[0])]
+            cnt += has[tuple(sl)]
+    return cnt.ravel()
 
 
 def check_markers(case):
@@ -106,20 +123,20 @@ def facets(case):
     nx, ny, nz = case.n
     nzc = nz if dim == 3 else 1
     N = nx * ny * nzc
-    slots = _edge_marker_positions(case)
-    P = np.stack([p for p, _ in slots], axis=1)          # [N, S, 3]
-    M = np.stack([m for _, m in slots], axis=1)          # [N, S]
-    cnt = M.sum(axis=1)
     need = 2 if dim == 2 else 3
-    is_if = cnt >= need
+    is_if = _marker_count(case) >= need
+    cells = np.nonzero(is_if)[0]
     cF = np.zeros((N, 3))
     nF = np.zeros((N, 3))
+    slots = _edge_marker_positions(case, cells)
+    P = np.stack([p for p, _ in slots], axis=1)          # [n, S, 3]
+    M = np.stack([m for _, m in slots], axis=1)          # [n, S]
+    cnt = M.sum(axis=1)
     Pm = np.where(M[:, :, None], P, 0.0)
-    cF[is_if] = Pm[is_if].sum(axis=1) / cnt[is_if][:, None]
-
-    # corner positions and colours of every cell
-    k, j, i = np.meshgrid(np.arange(nzc), np.arange(ny), np.arange(nx), indexing="ij")
-    k, j, i = k.ravel(), j.ravel(), i.ravel()
+    cen = Pm.sum(axis=1) / cnt[:, None]
+    cF[cells] = cen
+    # corners of each interface cell, in the order (dk, dj, di), and colours
+    i, j, k = cells % nx, (cells // nx) % ny, cells // (nx * ny)
     corners = []
     for dk in ((0, 1) if dim == 3 else (0,)):
         for dj in (0, 1):
@@ -128,37 +145,57 @@ def facets(case):
                 pos = np.stack([(i + di) * h, (j + dj) * h, (k + dk) * h if dim == 3 else 0.0 * k], axis=1)
                 corners.append((pos, col))
     xc = np.stack([(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h if dim == 3 else 0.0 * k], axis=1)
-    fc = case.ccol.ravel().astype(float)
+    fc = case.ccol.ravel().astype(float)[cells]
 
-    for c in np.nonzero(is_if)[0]:
-        pts = P[c][M[c]]
-        cen = cF[c]
-        n = None
-        if dim == 2 and len(pts) == 2:
-            d = pts[1] - pts[0]
-            L = np.hypot(d[0], d[1])
-            if L > 0:
-                n = np.array([-d[1], d[0], 0.0]) / L
-        else:
-            X = pts - cen
-            C = X.T @ X
+    idx = np.arange(cells.size)
+    n_all = np.full((idx.size, 3), np.nan)
+    # 2D cells with two markers: unit perpendicular of the segment P1 -> P2
+    if dim == 2:
+        two = cnt == 2
+        sel = idx[two]
+        # the two present slots, in slot order
+        order = np.argsort(~M[sel], axis=1, kind="stable")[:, :2]
+        p1 = P[sel, order[:, 0]]
+        p2 = P[sel, order[:, 1]]
+        d = p2 - p1
+        L = np.hypot(d[:, 0], d[:, 1])
+        ok = L > 0
+        nn = np.full((sel.size, 3), np.nan)
+        nn[ok, 0] = -d[ok, 1] / L[ok]
+        nn[ok, 1] = d[ok, 0] / L[ok]
+        nn[ok, 2] = 0.0
+        n_all[two] = nn
+        rest = ~two
+    else:
+        rest = np.ones(idx.size, bool)
+    # otherwise: least-squares plane, eigenvector of the smallest eigenvalue
+    sel = idx[rest]
+    if sel.size:
+        X = np.where(M[sel][:, :, None], P[sel] - cen[sel][:, None, :], 0.0)
+        C = np.einsum("nsi,nsj->nij", X, X)
+        if dim == 2:
+            C = C[:, :2, :2]
+        good = np.max(np.abs(C.reshape(sel.size, -1)), axis=1) > 0
+        nn = np.full((sel.size, 3), np.nan)
+        if good.any():
+            w, V = np.linalg.eigh(C[good])
+            v = V[:, :, 0]
             if dim == 2:
-                C = C[:2, :2]
-            if np.max(np.abs(C)) > 0:
-                w, V = np.linalg.eigh(C)
-                v = V[:, 0]
-                n = np.array([v[0], v[1], 0.0]) if dim == 2 else v.copy()
-                n /= np.linalg.norm(n)
-        if n is None:
-            # all markers coincide: direction of the corner-colour contrast
-            g = sum((2 * col[c] - 1) * (pos[c] - cen) for pos, col in corners)
-            n = g / np.linalg.norm(g)
-        s = sum((2 * col[c] - 1) * np.dot(n, pos[c] - cen) for pos, col in corners)
-        if s == 0:
-            s = (2 * fc[c] - 1) * np.dot(n, xc[c] - cen)
-        if s < 0:
-            n = -n
-        nF[c] = n
+                v = np.concatenate([v, np.zeros((v.shape[0], 1))], axis=1)
+            nn[good] = v / np.linalg.norm(v, axis=1)[:, None]
+        n_all[rest] = nn
+    # coinciding markers: direction of the corner-colour contrast
+    for q in np.nonzero(np.isnan(n_all[:, 0]))[0]:
+        g = sum((2 * col[q] - 1) * (pos[q] - cen[q]) for pos, col in corners)
+        n_all[q] = g / np.linalg.norm(g)
+    # orientation from vapour into liquid: corner colours, then the centre colour
+    s = np.zeros(idx.size)
+    for pos, col in corners:
+        s = s + (2 * col - 1) * np.einsum("ni,ni->n", n_all, pos - cen)
+    tie = s == 0
+    s[tie] = (2 * fc[tie] - 1) * np.einsum("ni,ni->n", n_all[tie], xc[tie] - cen[tie])
+    n_all[s < 0] *= -1
+    nF[cells] = n_all
     return is_if, cF, nF
 
 
@@ -176,75 +213,95 @@ def link_theta(case, fac=None):
     if fac is None:
         fac = facets(case)
     is_if, cF, nF = fac
-    dim, h = case.dim, case.h
     ids = _cell_index(case)
     col = case.ccol
     out = []
-    for a in range(dim):
+    for a in range(case.dim):
         ax = 2 - a
         n_a = ids.shape[ax]
         fshape = list(ids.shape)
         fshape[ax] += 1
         th = np.full(fshape, np.nan)
         periodic = case.T_bc[2 * a][0] == 2
-        # links (lower cell at index t, upper at t+1) ; wrap link when periodic
-        lo_list = list(range(n_a - 1)) + ([n_a - 1] if periodic else [])
-        for t in lo_list:
-            up = (t + 1) % n_a
-            c = np.take(ids, t, axis=ax).ravel()
-            nb = np.take(ids, up, axis=ax).ravel()
-            cc = np.take(col, t, axis=ax).ravel()
-            cn = np.take(col, up, axis=ax).ravel()
-            vals = np.full(c.shape, np.nan)
-            for q in np.nonzero(cc != cn)[0]:
-                vals[q] = _theta_one(case, a, c[q], nb[q], is_if, cF, nF, wrap=(up == 0))
-            sl = [slice(None)] * 3
-            sl[ax] = t + 1
-            th[tuple(sl)] = vals.reshape(np.take(th, t + 1, axis=ax).shape)
-            if periodic and up == 0:
-                sl[ax] = 0
-                th[tuple(sl)] = vals.reshape(np.take(th, 0, axis=ax).shape)
+        if periodic:
+            lo = ids.ravel()
+            up = np.roll(ids, -1, axis=ax).ravel()
+        else:
+            lo = np.take(ids, np.arange(n_a - 1), axis=ax).ravel()
+            up = np.take(ids, np.arange(1, n_a), axis=ax).ravel()
+        cut = col.ravel()[lo] != col.ravel()[up]
+        lo, up = lo[cut], up[cut]
+        t_lo = (lo // _stride(case, a)) % n_a
+        wrap = t_lo == n_a - 1            # the upper cell sits across the seam
+        theta = _theta_links(case, a, lo, up, wrap, is_if, cF, nF)
+        # the face between lower index t and t + 1; the seam also fills face 0
+        th.ravel()[_face_index(case, a, lo, t_lo + 1)] = theta
+        if wrap.any():
+            th.ravel()[_face_index(case, a, lo[wrap], np.zeros(int(wrap.sum()), int))] = theta[wrap]
         out.append(th)
     return out
 
 
-def _centre(case, c):
+def _stride(case, a):
+    nx, ny, _ = case.n
+    return (1, nx, nx * ny)[a]
+
+
+def _face_index(case, a, cells, t_face):
+    """Flat index, in the axis-a face array, of the face at position t_face
+    along a in the row of each given cell."""
     nx, ny, nz = case.n
-    i = c % nx
-    j = (c // nx) % ny
-    k = c // (nx * ny)
-    h = case.h
-    return np.array([(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h if case.dim == 3 else 0.0])
+    nzc = nz if case.dim == 3 else 1
+    q = [cells % nx, (cells // nx) % ny, cells // (nx * ny)]
+    q[a] = t_face
+    dims = [nx, ny, nzc]
+    dims[a] += 1
+    return q[0] + dims[0] * (q[1] + dims[1] * q[2])
 
 
-def _theta_one(case, a, c, nb, is_if, cF, nF, wrap=False):
+def _centres(case, cells):
+    nx, ny, _ = case.n
     h = case.h
-    xc = _centre(case, c)
-    cands = []    # (value, valid)
-    for cell, lo_hi in ((c, 0), (nb, 1)):
-        if not is_if[cell]:
-            continue
-        n = nF[cell]
-        if abs(n[a]) < NORMAL_EPS:
-            cands.append((None, False, True))
-            continue
-        cen = cF[cell].copy()
-        if lo_hi == 1 and wrap:
-            cen[a] += case.n[a] * h
-        t = np.dot(cen - xc, n) / (h * n[a])
-        ok = (0.0 <= t <= 0.5) if lo_hi == 0 else (0.5 <= t <= 1.0)
-        cands.append((t, ok, True))
-    if not cands:
+    i = cells % nx
+    j = (cells // nx) % ny
+    k = cells // (nx * ny)
+    return np.stack([(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h if case.dim == 3 else 0.0 * k], axis=1)
+
+
+def _theta_links(case, a, lo, up, wrap, is_if, cF, nF):
+    """theta of each cut link from the two cells' facets: candidate t from
+    the lower cell's facet valid in [0, 1/2], from the upper cell's in
+    [1/2, 1]; the mean of the valid ones, else the clamped mean of the
+    computable ones, else 1/2.  No facet on either side: geometry error."""
+    h = case.h
+    if np.any(~is_if[lo] & ~is_if[up]):
         raise GeometryError("cut link with no interface cell on either side")
-    valid = [t for t, ok, _ in cands if ok]
-    if len(valid) == 1:
-        return valid[0]
-    if len(valid) == 2:
-        return 0.5 * (valid[0] + valid[1])
-    exist = [t for t, _, _ in cands if t is not None]
-    if exist:
-        return min(max(sum(exist) / len(exist), 0.0), 1.0)
-    return 0.5
+    xc = _centres(case, lo)
+    t = np.full((lo.size, 2), np.nan)
+    for side, cell in ((0, lo), (1, up)):
+        n = nF[cell]
+        cen = cF[cell].copy()
+        if side == 1:
+            cen[wrap, a] += case.n[a] * h
+        ok = is_if[cell] & (np.abs(n[:, a]) >= NORMAL_EPS)
+        dot = (cen[:, 0] - xc[:, 0]) * n[:, 0] + (cen[:, 1] - xc[:, 1]) * n[:, 1] + (cen[:, 2] - xc[:, 2]) * n[:, 2]
+        t[ok, side] = dot[ok] / (h * n[ok, a])
+    v0 = (t[:, 0] >= 0.0) & (t[:, 0] <= 0.5)
+    v1 = (t[:, 1] >= 0.5) & (t[:, 1] <= 1.0)
+    theta = np.full(lo.size, 0.5)
+    both = v0 & v1
+    theta[both] = 0.5 * (t[both, 0] + t[both, 1])
+    only0 = v0 & ~v1
+    theta[only0] = t[only0, 0]
+    only1 = v1 & ~v0
+    theta[only1] = t[only1, 1]
+    none = ~v0 & ~v1
+    ex = ~np.isnan(t)
+    cnt = ex.sum(axis=1)
+    some = none & (cnt > 0)
+    mean = np.where(ex, t, 0.0).sum(axis=1)[some] / cnt[some]
+    theta[some] = np.minimum(np.maximum(mean, 0.0), 1.0)
+    return theta
 
 
 def flags(case, theta, is_if):

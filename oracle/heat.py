@@ -55,42 +55,67 @@ def theta_from_cell(theta, case, a, sgn):
     return t if sgn > 0 else 1.0 - t
 
 
-def assemble(case, geo, T_star, theta_min=1e-3):
-    """Return (A csr, b) of the heat system (Eqs. energy_diffusion, Txx_ghost)."""
+def operator(case, geo, theta_min=1e-3):
+    """The heat operator as link fluxes (solve.FluxOp): m_c = rho cp/dt plus
+    the wall (2 lam/h^2) and cut-link (lam/(theta' h^2)) terms; w = lam/h^2
+    on every same-phase link."""
+    from .solve import FluxOp
     pr = case.props
     dim, h, dt = case.dim, case.h, case.dt
     col = case.ccol.ravel().astype(int)
-    N = col.size
     rho = np.where(col == 1, pr.rho_l, pr.rho_v)
     cp = np.where(col == 1, pr.cp_l, pr.cp_v)
     lam = np.where(col == 1, pr.lam_l, pr.lam_v)
-    diag = rho * cp / dt
+    mexc = rho * cp / dt
+    rows, cols, w = [], [], []
+    for a in range(dim):
+        for sgn, side in ((-1, 2 * a), (+1, 2 * a + 1)):
+            ids, nb = side_neighbours(case, a, sgn)
+            kind, _ = case.T_bc[side]
+            wall = nb < 0
+            if kind == DIRICHLET:
+                mexc[wall] += 2 * lam[wall] / h ** 2
+            inner = ~wall
+            same = inner.copy()
+            same[inner] = col[nb[inner]] == col[inner]
+            cut = inner & ~same
+            rows.append(ids[same])
+            cols.append(nb[same])
+            w.append(lam[same] / h ** 2)
+            th = theta_from_cell(geo["theta"], case, a, sgn)
+            if np.any(np.isnan(th[cut])):
+                raise ValueError("cut link without theta")
+            tc = np.maximum(th[cut], theta_min)
+            mexc[cut] += lam[cut] / (tc * h ** 2)
+    return FluxOp(mexc, np.concatenate(rows), np.concatenate(cols), np.concatenate(w))
+
+
+def rhs(case, geo, T_star, theta_min=1e-3):
+    """Right-hand side of the heat system: rho cp/dt T* plus the interface
+    (lam T_sat/(theta' h^2)) and wall (2 lam T_w/h^2) terms."""
+    pr = case.props
+    dim, h, dt = case.dim, case.h, case.dt
+    col = case.ccol.ravel().astype(int)
+    rho = np.where(col == 1, pr.rho_l, pr.rho_v)
+    cp = np.where(col == 1, pr.cp_l, pr.cp_v)
+    lam = np.where(col == 1, pr.lam_l, pr.lam_v)
     b = rho * cp / dt * T_star.ravel()
-    rows, cols, vals = [], [], []
     for a in range(dim):
         for sgn, side in ((-1, 2 * a), (+1, 2 * a + 1)):
             ids, nb = side_neighbours(case, a, sgn)
             kind, val = case.T_bc[side]
             wall = nb < 0
             if kind == DIRICHLET:
-                diag[wall] += 2 * lam[wall] / h ** 2
                 b[wall] += 2 * lam[wall] * val / h ** 2
             inner = ~wall
-            same = inner.copy()
-            same[inner] = col[nb[inner]] == col[inner]
-            cut = inner & ~same
-            diag[same] += lam[same] / h ** 2
-            rows.append(ids[same])
-            cols.append(nb[same])
-            vals.append(-lam[same] / h ** 2)
+            cut = inner.copy()
+            cut[inner] = col[nb[inner]] != col[inner]
             th = theta_from_cell(geo["theta"], case, a, sgn)
-            if np.any(np.isnan(th[cut])):
-                raise ValueError("cut link without theta")
             tc = np.maximum(th[cut], theta_min)
-            diag[cut] += lam[cut] / (tc * h ** 2)
             b[cut] += lam[cut] * pr.T_sat / (tc * h ** 2)
-    rows.append(np.arange(N))
-    cols.append(np.arange(N))
-    vals.append(diag)
-    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
-    return A, b
+    return b
+
+
+def assemble(case, geo, T_star, theta_min=1e-3):
+    """Return (A csr, b) of the heat system (Eqs. energy_diffusion, Txx_ghost)."""
+    return operator(case, geo, theta_min).to_csr(), rhs(case, geo, T_star, theta_min)

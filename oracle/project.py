@@ -95,15 +95,36 @@ def divergence(case, u_l, u_v):
     return (div / case.h).ravel()
 
 
-def assemble(case, geo):
-    """(L csr, bc_rhs): L p = div - bc_rhs is the discrete Eq. Poisson_equation,
-    L p = sum_a [beta_+ (p_+ - p_c) - beta_- (p_c - p_-)] / h^2."""
+def operator(case, geo):
+    """The SPD form A = -L as link fluxes (solve.FluxOp): w = beta_f/h^2 on
+    every interior or periodic link, m_c = 2 beta/h^2 per outflow face."""
+    from .solve import FluxOp
     dim, h = case.dim, case.h
     N = case.ccol.size
-    diag = np.zeros(N)
-    bc_rhs = np.zeros(N)
-    rows, cols, vals = [], [], []
+    mexc = np.zeros(N)
+    rows, cols, w = [], [], []
     for a in range(dim):
+        beta = face_beta(case, geo, a)
+        for sgn, side in ((-1, 2 * a), (+1, 2 * a + 1)):
+            ids, nb = side_neighbours(case, a, sgn)
+            bf = face_of_side(beta, case, a, sgn)
+            wall = nb < 0
+            kind, _ = case.p_bc[side]
+            if kind == DIRICHLET:
+                mexc[wall] += 2 * bf[wall] / h ** 2
+            inner = ~wall
+            rows.append(ids[inner])
+            cols.append(nb[inner])
+            w.append(bf[inner] / h ** 2)
+    return FluxOp(mexc, np.concatenate(rows), np.concatenate(cols), np.concatenate(w))
+
+
+def bc_rhs(case, geo):
+    """Boundary part of the Poisson right-hand side: 2 beta p_w/h^2 on every
+    outflow face (L p = div - bc_rhs)."""
+    h = case.h
+    out = np.zeros(case.ccol.size)
+    for a in range(case.dim):
         beta = face_beta(case, geo, a)
         for sgn, side in ((-1, 2 * a), (+1, 2 * a + 1)):
             ids, nb = side_neighbours(case, a, sgn)
@@ -111,18 +132,14 @@ def assemble(case, geo):
             wall = nb < 0
             kind, val = case.p_bc[side]
             if kind == DIRICHLET:
-                diag[wall] -= 2 * bf[wall] / h ** 2
-                bc_rhs[wall] += 2 * bf[wall] * val / h ** 2
-            inner = ~wall
-            diag[inner] -= bf[inner] / h ** 2
-            rows.append(ids[inner])
-            cols.append(nb[inner])
-            vals.append(bf[inner] / h ** 2)
-    rows.append(np.arange(N))
-    cols.append(np.arange(N))
-    vals.append(diag)
-    L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
-    return L, bc_rhs
+                out[wall] += 2 * bf[wall] * val / h ** 2
+    return out
+
+
+def assemble(case, geo):
+    """(L csr, bc_rhs): L p = div - bc_rhs is the discrete Eq. Poisson_equation,
+    L p = sum_a [beta_+ (p_+ - p_c) - beta_- (p_c - p_-)] / h^2."""
+    return -operator(case, geo).to_csr(), bc_rhs(case, geo)
 
 
 def face_update(case, geo, p, u_l, u_v):
@@ -164,7 +181,7 @@ def project(case, geo, mdot, u_l, u_v, solver):
     div0 = divergence(case, ulg, uvg)
     L, bc = assemble(case, geo)
     rhs = div0 - bc
-    p = solver(L, rhs)
+    p = solver(-L, -rhs, operator(case, geo))
     ul1, uv1 = face_update(case, geo, p, ulg, uvg)
     div1 = divergence(case, ul1, uv1)
     return dict(p=p, u_l=ul1, u_v=uv1, b=rhs, div=div1, L=L, u_l_ghost=ulg, u_v_ghost=uvg)

@@ -289,8 +289,27 @@ __device__ inline void write_partials(double (&v)[NV], double* partial) {
     for (int q = 0; q < NV; ++q) partial[q * gridDim.x + blockIdx.x] = v[q];
 }
 
-// r = b - A x (x may be null: r = b); partials: b.b, r.r and the squared norm
-// of |b| + |A||x| (the magnitude the residual is computed from)
+// Error-free transformations (Knuth TwoSum, FMA-based TwoProd) for a
+// residual evaluated in double-double arithmetic.
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ inline void dd_add(double& hi, double& lo, double p, double pe) {
+  double s, e;
+  two_sum(hi, p, s, e);
+  e += lo + pe;
+  hi = s + e;
+  lo = e - (hi - s);
+}
+
+// r = b - A x in flux form, accumulated in double-double and rounded once
+// (x may be null: r = b); partials: b.b, r.r and the squared norm of
+// |b| + |A||x| (a residual cannot be certified below ~eps of that, since the
+// rounding of x itself, eps |x| per entry and not smooth, leaves a residual
+// of that size).  With the compensated residual the outer loop's restarts
+// steer x to the correctly rounded discrete solution.
 __global__ void k_resid_init(FineOp op, const double* __restrict__ b, const double* __restrict__ x,
                              double* __restrict__ r, double* partial) {
   double v[3] = {0, 0, 0};
@@ -303,17 +322,25 @@ __global__ void k_resid_init(FineOp op, const double* __restrict__ b, const doub
       double diag, off[6], mass, rb = 0, mx;
       fine_row<double>(op, i, j, k, op.flags[c], diag, off, mass, rb, &mx);
       const double xc = x[c];
-      const double t0 = mx * xc;
-      rc = bc - t0;
-      ac += fabs(t0);
+      double hi = bc, lo = 0.0;
+      {
+        const double p = mx * xc;
+        dd_add(hi, lo, -p, -fma(mx, xc, -p));
+      }
+      ac += fabs(diag * xc);
       for (int q = 0; q < 2 * op.d.dim; ++q) {
         if (off[q] == 0.0) continue;
         int ni, nj, nk;
         neighbour(op.d, i, j, k, q, ni, nj, nk);
-        const double tq = -off[q] * (xc - x[cell_index(op.d, ni, nj, nk)]);
-        rc -= tq;
-        ac += fabs(tq);
+        const double xn = x[cell_index(op.d, ni, nj, nk)];
+        double dh, dl;
+        two_sum(xc, -xn, dh, dl);         // x_c - x_n exactly as dh + dl
+        // r += off (x_c - x_n)  (off = -w, so this subtracts w (x_c - x_n))
+        const double p = off[q] * dh;
+        dd_add(hi, lo, p, fma(off[q], dh, -p) + off[q] * dl);
+        ac += fabs(off[q] * xn);
       }
+      rc = hi + lo;
     }
     if (r) r[c] = rc;
     v[0] += bc * bc;
@@ -410,12 +437,6 @@ __global__ void k_update_xr(long long N, double* __restrict__ x, double* __restr
     v[0] += rc * rc;
   }
   write_partials<1>(v, partial);
-}
-
-// defect correction: x += z
-template <typename TZ>
-__global__ void k_add(long long N, double* __restrict__ x, const TZ* __restrict__ z) {
-  GRID_STRIDE(c, N) { x[c] += (double)z[c]; }
 }
 
 // finalize kinds
@@ -694,12 +715,11 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
     return 0;
   }
   const double tol2 = o->rtol * o->rtol * bb;
-  // rounding floor of the residual itself: |r_i| cannot be resolved below a
-  // few ulps of |b_i| + |m_i x_i| + sum_j |w_ij (x_i - x_j)| (difference form)
-  const double fc = 4.0 * (op.d.dim + 1) * 2.220446049250313e-16;
+  // representability floor of the residual: eps || |b| + |A||x| ||
+  const double fc = 2.220446049250313e-16;
   double floor2 = fc * fc * hs.aa;
   double rr = hs.rr;
-  if (rr <= (tol2 > floor2 ? tol2 : floor2)) {
+  if (rr <= tol2) {
     *relres = sqrt(rr / bb);
     *floor = sqrt(floor2 / bb);
     return 0;
@@ -710,31 +730,28 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
   int first = 1;
   int pi = 0;
   bool conv = false;
+  double last_true = rr;  // last recomputed residual (squared)
+  int at_floor = 0;
   while (it < o->max_iters) {
     CK(vcycle<T>(op, lv, nlev, B->r, z, o->nu1, o->nu2, st));
     ++*vcyc;
-    if (o->outer == EBIT_OUTER_DC) {
-      hipLaunchKernelGGL(k_add<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, x, (const T*)z);
-      hipLaunchKernelGGL(k_resid_init, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, b, (const double*)x, B->r,
-                         B->partial);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 3, B->scal,
-                         (int)FIN_INIT, 0);
-    } else {
-      hipLaunchKernelGGL(k_dots_zr_zq<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, (const T*)z,
-                         (const double*)B->r, first ? nullptr : (const double*)B->q, B->partial);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 2, B->scal,
-                         (int)FIN_GAMMA, first);
-      hipLaunchKernelGGL(k_p_update_apply<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, (const T*)z,
-                         (const double*)B->p[pi], B->p[1 - pi], B->q, (const Scal*)B->scal, first, B->partial);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
-                         (int)FIN_DELTA, 0);
-      pi = 1 - pi;
-      hipLaunchKernelGGL(k_update_xr, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, x, B->r, (const double*)B->p[pi],
-                         (const double*)B->q, (const Scal*)B->scal, B->partial);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
-                         (int)FIN_RR, 0);
-      first = 0;
-    }
+    // defect correction = the same loop with beta = 0: x += alpha V(r) with the
+    // energy-optimal step alpha = (r.z)/(z.Az), so it contracts for any SPD A
+    const int fresh = (o->outer == EBIT_OUTER_DC) ? 1 : first;
+    hipLaunchKernelGGL(k_dots_zr_zq<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, (const T*)z,
+                       (const double*)B->r, fresh ? nullptr : (const double*)B->q, B->partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 2, B->scal,
+                       (int)FIN_GAMMA, fresh);
+    hipLaunchKernelGGL(k_p_update_apply<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, (const T*)z,
+                       (const double*)B->p[pi], B->p[1 - pi], B->q, (const Scal*)B->scal, fresh, B->partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
+                       (int)FIN_DELTA, 0);
+    pi = 1 - pi;
+    hipLaunchKernelGGL(k_update_xr, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, x, B->r, (const double*)B->p[pi],
+                       (const double*)B->q, (const Scal*)B->scal, B->partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
+                       (int)FIN_RR, 0);
+    first = 0;
     CK(hipGetLastError());
     ++it;
     if (it % check == 0 || it == o->max_iters) {
@@ -744,14 +761,8 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
         return 2;
       }
       rr = hs.rr;
-      if (o->outer == EBIT_OUTER_DC) {
-        floor2 = fc * fc * hs.aa;
-        if (rr <= (tol2 > floor2 ? tol2 : floor2)) {
-          conv = true;
-          break;
-        }
-      } else if (rr <= (tol2 > floor2 ? tol2 : floor2)) {
-        // confirm with the true residual (the CG recurrence drifts from it)
+      if (rr <= tol2 || (restarts > 0 && rr <= 1e-12 * last_true)) {
+        // recompute the true residual (the CG recurrence drifts from it)
         hipLaunchKernelGGL(k_resid_init, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, b, (const double*)x, B->r,
                            B->partial);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 3, B->scal,
@@ -760,13 +771,19 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
         CK(read_scal(B->scal, &hs, st));
         rr = hs.rr;
         floor2 = fc * fc * hs.aa;
-        if (rr <= (tol2 > floor2 ? tol2 : floor2)) {
+        // At the representability floor the residual no longer tracks the
+        // error, but the compensated residual still carries it: take two more
+        // restart cycles there before stopping.
+        const bool stagnant = restarts > 0 && rr > 0.25 * last_true;
+        if (stagnant && rr <= floor2) ++at_floor;
+        if (rr <= tol2 || at_floor >= 2) {
           conv = true;
           break;
         }
-        if (restarts >= 3) break;
+        if (restarts >= 8 || (stagnant && rr > floor2)) break;
         ++restarts;
-        first = 1;  // restart the recurrence from the true residual
+        last_true = rr;
+        first = 1;  // restart the recurrence from the recomputed residual
       }
     }
   }

@@ -1,0 +1,175 @@
+"""Edge cases and error paths of the HIP path, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import ebit_inputs as ei
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _ebit():
+    from paper_2402_13677_amd import ebit
+    return ebit
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=float).ravel()
+    b = np.asarray(b, dtype=float).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def test_inconsistent_markers_give_egeom():
+    say("[gpu] edge egeom")
+    ebit = _ebit()
+    c = ei.config(0, 16)
+    c.markers[0][0, 3, 2] = 0.5       # marker on an edge whose end colours agree
+    ctx, dc = ebit.context_for(c)
+    with pytest.raises(ebit.EbitError) as e:
+        ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    assert e.value.status == ebit.EGEOM
+    # a solve before a successful build is a call-order error
+    T = torch.zeros_like(dc.T0)
+    with pytest.raises(ebit.EbitError) as e2:
+        ctx.heat_solve(dc.T0, T)
+    assert e2.value.status == ebit.ESTATE
+    # a consistent rebuild recovers
+    ok = ei.config(0, 16)
+    dok = ebit.DeviceCase(ok)
+    ctx.build_coeffs(dok.markers, dok.vcol, dok.ccol, ok.dt)
+    ctx.heat_solve(dok.T0, T)
+    ctx.close()
+
+
+def test_marker_out_of_range_gives_egeom():
+    say("[gpu] edge marker range")
+    ebit = _ebit()
+    c = ei.config(0, 16)
+    cut = np.argwhere(~np.isnan(c.markers[0]))[0]
+    c.markers[0][tuple(cut)] = 1.5
+    ctx, dc = ebit.context_for(c)
+    with pytest.raises(ebit.EbitError) as e:
+        ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    assert e.value.status == ebit.EGEOM
+    ctx.close()
+
+
+def test_bad_arguments_give_einval():
+    say("[gpu] edge einval")
+    ebit = _ebit()
+    c = ei.config(0, 16)
+    ctx, dc = ebit.context_for(c)
+    with pytest.raises(ebit.EbitError) as e:
+        ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, -1.0)
+    assert e.value.status == ebit.EINVAL
+    st = ctx.lib.ebit_heat_solve(ctx.h, None, None, 0, None)
+    assert st in (ebit.EINVAL, ebit.ESTATE)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    st = ctx.lib.ebit_heat_solve(ctx.h, None, None, 0, None)
+    assert st == ebit.EINVAL
+    st = ctx.lib.ebit_apply(ctx.h, 7, None, None)
+    assert st == ebit.EINVAL
+    ctx.close()
+
+
+def test_max_iters_gives_enoconv_with_last_iterate():
+    say("[gpu] edge enoconv")
+    ebit = _ebit()
+    c = ei.config(1, 64)
+    ctx, dc = ebit.context_for(c, ebit.default_opts(rtol=1e-12, max_iters=1))
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    T = torch.zeros_like(dc.T0)
+    s = ctx.heat_solve(dc.T0, T, check=False)
+    assert s["status"] == ebit.ENOCONV and s["iters"] == 1
+    assert s["rel_res"] > 1e-12 and np.isfinite(s["rel_res"])
+    assert torch.isfinite(T).all()
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_no_interface(dim):
+    """All liquid: no cut link, no facet; mdot = 0; the projection of a
+    random field is divergence-free and matches the oracle."""
+    say(f"[gpu] edge no-interface {dim}d")
+    ebit = _ebit()
+    n = 20 if dim == 2 else 9
+    nn = (n, n, n if dim == 3 else 1)
+    rng = np.random.default_rng(3)
+    shp = ei.cell_shape(dim, nn)
+    u = [rng.normal(0, 1e-2, ei.face_shape(dim, nn, a)) for a in range(dim)]
+    c = ei.Case("flat", dim, nn, 1.0 / n, ei.Props(), 1e-3, [(0, 0.0)] * (2 * dim), [(1, 0.0)] * (2 * dim),
+                [np.full(ei.edge_shape(dim, nn, a), np.nan) for a in range(dim)],
+                np.ones(ei.vertex_shape(dim, nn), np.uint8), np.ones(shp, np.uint8),
+                rng.normal(size=shp), u, [x.copy() for x in u])
+    ref = oracle.pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+    ctx, dc = ebit.context_for(c, ebit.default_opts(rtol=1e-15))
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    T = torch.zeros_like(dc.T0)
+    ctx.heat_solve(dc.T0, T)
+    m = torch.zeros_like(dc.T0)
+    ctx.mass_flux(T, m)
+    p = torch.zeros_like(dc.T0)
+    ctx.project(dc.u_l, dc.u_v, m, p)
+    assert torch.count_nonzero(m).item() == 0
+    assert rel(T.cpu().numpy(), ref["T"]) < 1e-12
+    assert rel(p.cpu().numpy(), ref["p"]) < 1e-12
+    ctx.close()
+
+
+def test_minimum_grid_three_cells():
+    say("[gpu] edge n=3")
+    ebit = _ebit()
+    dim, n = 2, 3
+    nn = (n, n, 1)
+    ls = ei.Plane((1.0, 0.3, 0.0), (0.45, 0.5, 0.0))
+    vcol, ccol, mk = ei.colours_and_markers(dim, nn, 1.0 / n, ls)
+    rng = np.random.default_rng(0)
+    u = [rng.normal(0, 1e-2, ei.face_shape(dim, nn, a)) for a in range(dim)]
+    c = ei.Case("tiny", dim, nn, 1.0 / n, ei.Props(rho_v=0.1), 1e-3, [(1, 1.0)] + [(0, 0.0)] * 3,
+                [(0, 0.0), (1, 0.0), (0, 0.0), (0, 0.0)], mk, vcol, ccol,
+                rng.uniform(0, 1, ei.cell_shape(dim, nn)), u, [x.copy() for x in u])
+    ref = oracle.pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+    ctx, dc = ebit.context_for(c, ebit.default_opts(rtol=1e-15))
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    assert len(ctx.levels()) == 3           # 3x3 -> 2x2 -> 1x1
+    T = torch.zeros_like(dc.T0)
+    ctx.heat_solve(dc.T0, T)
+    m = torch.zeros_like(dc.T0)
+    ctx.mass_flux(T, m)
+    p = torch.zeros_like(dc.T0)
+    ctx.project(dc.u_l, dc.u_v, m, p)
+    assert rel(T.cpu().numpy(), ref["T"]) < 1e-12
+    assert rel(m.cpu().numpy(), ref["mdot"]) < 1e-12
+    assert rel(p.cpu().numpy(), ref["p"]) < 1e-12
+    ctx.close()
+
+
+def test_theta_min_clamp_small_cut_fractions():
+    """Interface 1e-6 h from a cell centre: theta' < theta_min is clamped on
+    both sides identically (heat operator and ghost extrapolation)."""
+    say("[gpu] edge theta_min")
+    ebit = _ebit()
+    n = 32
+    xg = 10.5 + 1e-6          # a hair past the centre of cell 10
+    c = ei.stefan_2d(n, x_gamma_cells=xg)
+    ref = oracle.pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+    th = ref["geo"]["theta"][0]
+    assert np.nanmin(th) < 1e-3 or np.nanmin(1 - th) < 1e-3
+    ctx, dc = ebit.context_for(c, ebit.default_opts(rtol=1e-15))
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+    T = torch.zeros_like(dc.T0)
+    ctx.heat_solve(dc.T0, T)
+    m = torch.zeros_like(dc.T0)
+    ctx.mass_flux(T, m)
+    assert rel(T.cpu().numpy(), ref["T"]) < 1e-12
+    assert rel(m.cpu().numpy(), ref["mdot"]) < 1e-11
+    ctx.close()
