@@ -32,11 +32,48 @@ WORKLOADS = {
     "film3d_256": (4, None),
 }
 
-# algorithmic bytes per fine cell of one red-black half sweep of the fine
-# level (one colour updated): read b and flags of the updated half, the other
-# half's x (neighbours), write the updated half's x -> (8 + 1 + 8 + 8) / 2
-HALF_SWEEP_BYTES = {"f64": 12.5, "f32": 6.5}
 HBM_PEAK_GBS = 8000.0
+KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "fine_prolong", "outer_apply", "outer_update"]
+# the HIP kernels of each class (names as rocprofv3 reports them)
+KERNEL_NAMES = {
+    "fine_smooth": "k_fine_smooth",
+    "fine_restrict": "k_fine_resid_restrict",
+    "fine_prolong": "k_prolong",
+    "outer_apply": "k_p_update_apply",
+    "outer_update": "k_update_xr",
+}
+
+
+def algorithmic_bytes_per_cell(kclass, precision, dim):
+    """Bytes one launch of a kernel class must move per fine cell (sparse
+    theta reads on cut links, O(interface), are not counted).  sx: size of
+    the inner iterate (4 in mixed precision, 8 in FP64); the residual r the
+    V-cycle smooths against is FP64."""
+    sx = 4 if precision == "mixed" else 8
+    agg = 2 ** dim
+    if kclass == "fine_smooth":      # one colour: read r, flags of the updated half, x of the other half; write x
+        return (8 + 1 + sx + sx) / 2
+    if kclass == "fine_restrict":    # read x, r, flags; write coarse b and clear coarse x
+        return sx + 8 + 1 + 2 * sx / agg
+    if kclass == "fine_prolong":     # read coarse x, read and write x
+        return sx / agg + 2 * sx
+    if kclass == "outer_apply":      # read z, p_old, flags; write p_new and q (FP64)
+        return sx + 8 + 1 + 8 + 8
+    if kclass == "outer_update":     # read x, p, r, q; write x, r (FP64)
+        return 48.0
+    raise KeyError(kclass)
+
+
+def kernel_source_digest():
+    """Digest of the HIP sources: the committed counter traffic is reported
+    only while the kernels are unchanged since it was measured."""
+    import hashlib
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_2402_13677_amd", "csrc")
+    for name in sorted(os.listdir(cdir)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(cdir, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def make_case(name):
@@ -46,6 +83,9 @@ def make_case(name):
 
 
 def run_gpu(case, precision, steps, warmup, profile=False):
+    """Time `steps` full steps after `warmup` untimed ones.  With profile,
+    the library also times every launch of each kernel class with hipEvents
+    on its stream; returns (elapsed, records, per-class (launches, ms))."""
     import torch
     from paper_2402_13677_amd import ebit
 
@@ -76,14 +116,21 @@ def run_gpu(case, precision, steps, warmup, profile=False):
 
     for _ in range(warmup):
         step(False)
+    if profile:
+        ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    kern = {}
+    if profile:
+        for kc, name in enumerate(KERNEL_CLASSES):
+            kern[name] = ctx.profile_read(kc)
+        ctx.profile(False)
     ctx.close()
-    return elapsed, rec
+    return elapsed, rec, kern
 
 
 def cpu_baseline(case, budget_s=15.0, max_steps=30):
@@ -113,6 +160,49 @@ def cpu_baseline(case, budget_s=15.0, max_steps=30):
             "sample": f"{steps} full steps of the same workload ({el:.1f} s, SciPy SuperLU direct solves, 1 thread)"}
 
 
+def roofline(case, precision, steps):
+    """Profiled timed pass: average launch duration of each kernel class,
+    measured with hipEvents on the library's stream; the class with the most
+    device time is the dominant kernel."""
+    _, _, kern = run_gpu(case, precision, steps, 1, profile=True)
+    rows = {}
+    for name, (n, ms) in kern.items():
+        if n == 0:
+            continue
+        bpc = algorithmic_bytes_per_cell(name, precision, case.dim)
+        avg_s = ms * 1e-3 / n
+        bytes_launch = bpc * case.ncells
+        rows[name] = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6,
+                      "algorithmic_bytes_per_launch": bytes_launch,
+                      "achieved_GBps": bytes_launch / avg_s / 1e9}
+    dom = max(rows, key=lambda k: rows[k]["total_ms"])
+    r = rows[dom]
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        key = f"{case.name}:{precision}:{KERNEL_NAMES[dom]}"
+        ent = t.get("kernels", {}).get(key)
+        if ent and t.get("source_digest") == kernel_source_digest():
+            traffic = ent["hbm_bytes_per_launch"]
+    ro = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS,
+          "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+          "avg_launch_us": r["avg_us"], "algorithmic_bytes_per_launch": r["algorithmic_bytes_per_launch"]}
+    return ro, rows
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,13 +214,19 @@ def main():
                     help="also time the plain FP64 solve (reported beside the value)")
     ap.add_argument("--no-compare", dest="compare", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a design note only",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     case = make_case(args.workload)
-    elapsed, rec = run_gpu(case, args.precision, args.steps, args.warmup)
+    elapsed, rec, _ = run_gpu(case, args.precision, args.steps, args.warmup)
     ms_per_step = elapsed / args.steps * 1e3
     med = lambda v: statistics.median(v) if v else None
     extra = {
@@ -142,7 +238,7 @@ def main():
     }
     if args.compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
-        el2, rec2 = run_gpu(case, other, max(5, args.steps // 5), 1)
+        el2, rec2, _ = run_gpu(case, other, max(5, args.steps // 5), 1)
         extra[f"{other}_time_to_1e9_ms"] = {"heat": med(rec2["heat_ms"]), "projection": med(rec2["proj_ms"])}
         extra[f"{other}_ms_per_step"] = el2 / max(5, args.steps // 5) * 1e3
     out = {
@@ -163,6 +259,8 @@ def main():
         "extra": extra,
         "roofline": None,
     }
+    if not args.no_roofline:
+        out["roofline"], extra["kernels"] = roofline(case, args.precision, max(5, args.steps // 5))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))

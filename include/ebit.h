@@ -207,6 +207,24 @@ ebit_status ebit_heat_rhs(ebit_ctx* ctx, const double* T_star, double* b);
 ebit_status ebit_project_rhs(ebit_ctx* ctx, double* const u_l[3], double* const u_v[3],
                              const double* mdot_cell, double* b);
 
+/* Kernel classes the profiler times (ebit_profile_read). */
+typedef enum {
+  EBIT_KC_FINE_SMOOTH = 0,    /* fine-level red-black smoothing launches       */
+  EBIT_KC_FINE_RESTRICT = 1,  /* fine-level residual + restriction             */
+  EBIT_KC_FINE_PROLONG = 2,   /* fine-level prolongation + correction          */
+  EBIT_KC_OUTER_APPLY = 3,    /* outer loop: search direction update + A p     */
+  EBIT_KC_OUTER_UPDATE = 4    /* outer loop: x and r update                    */
+} ebit_kernel_class;
+
+/* Profiling of individual launches with hipEvents recorded on the context's
+ * stream around each launch of the classes above (enable != 0 turns it on
+ * and clears the totals; the events are created by this call, once).
+ * ebit_profile_read returns, for one class, the number of launches timed
+ * and their summed device time in milliseconds, after synchronising the
+ * stream.  Meant for measurement runs: the events add a little host work. */
+ebit_status ebit_profile(ebit_ctx* ctx, int enable);
+ebit_status ebit_profile_read(ebit_ctx* ctx, int kernel_class, long long* launches, double* ms);
+
 /* Levels of the multigrid hierarchy and their sizes (host outputs). */
 ebit_status ebit_levels(const ebit_ctx* ctx, int* nlevels, int* sizes /* [3*nlevels] */);
 

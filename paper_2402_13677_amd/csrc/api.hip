@@ -28,6 +28,7 @@ struct ebit_ctx {
   int built;
   FineOp op[2];
   hipEvent_t ev0, ev1;
+  EbitProfiler* prof;
   hipError_t herr;
   char msg[512];
 };
@@ -379,6 +380,7 @@ ebit_status ebit_create(ebit_ctx** out, const ebit_grid* g, const ebit_props* p,
   c->ws = (char*)ws;
   c->ws_bytes = bytes;
   layout(g, o, c->ws, c);
+  c->B.prof = nullptr;
   c->herr = hipSuccess;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
@@ -392,6 +394,13 @@ ebit_status ebit_destroy(ebit_ctx* c) {
   if (!c) return EBIT_EINVAL;
   (void)hipEventDestroy(c->ev0);
   (void)hipEventDestroy(c->ev1);
+  if (c->prof) {
+    for (int i = 0; i < EBIT_PROF_CAP; ++i) {
+      (void)hipEventDestroy(c->prof->ev0[i]);
+      (void)hipEventDestroy(c->prof->ev1[i]);
+    }
+    delete c->prof;
+  }
   delete c;
   return EBIT_OK;
 }
@@ -554,6 +563,47 @@ ebit_status ebit_heat_rhs(ebit_ctx* c, const double* Ts, double* b) {
   if (s != EBIT_OK) return s;
   if (!Ts || !b) return fail(c, EBIT_EINVAL, "NULL vector");
   HIPCK(c, ebit_launch_heat_rhs(&c->op[EBIT_SYS_HEAT], Ts, b, c->st), "heat rhs");
+  return EBIT_OK;
+}
+
+ebit_status ebit_profile(ebit_ctx* c, int enable) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  if (enable && !c->prof) {
+    EbitProfiler* pr = new (std::nothrow) EbitProfiler;
+    if (!pr) return EBIT_ENOMEM;
+    memset(pr, 0, sizeof(*pr));
+    for (int i = 0; i < EBIT_PROF_CAP; ++i) {
+      if (hipEventCreate(&pr->ev0[i]) != hipSuccess || hipEventCreate(&pr->ev1[i]) != hipSuccess) {
+        delete pr;
+        return fail(c, EBIT_EHIP, "hipEventCreate failed");
+      }
+    }
+    c->prof = pr;
+  }
+  if (c->prof) {
+    HIPCK(c, ebit_prof_flush(c->prof), "profile flush");
+    c->prof->on = enable ? 1 : 0;
+    if (enable)
+      for (int k = 0; k < EBIT_PROF_CLASSES; ++k) {
+        c->prof->launches[k] = 0;
+        c->prof->ms[k] = 0.0;
+      }
+  }
+  c->B.prof = c->prof;
+  return EBIT_OK;
+}
+
+ebit_status ebit_profile_read(ebit_ctx* c, int kc, long long* launches, double* ms) {
+  if (!c || kc < 0 || kc >= EBIT_PROF_CLASSES || !launches || !ms) return EBIT_EINVAL;
+  if (!c->prof) {
+    *launches = 0;
+    *ms = 0.0;
+    return EBIT_OK;
+  }
+  HIPCK(c, ebit_prof_flush(c->prof), "profile flush");
+  *launches = c->prof->launches[kc];
+  *ms = c->prof->ms[kc];
   return EBIT_OK;
 }
 

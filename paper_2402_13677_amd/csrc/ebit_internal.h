@@ -216,6 +216,20 @@ struct EbitLevelHost {
   float* b32;
 };
 
+// Optional per-kernel timing with hipEvents recorded around individual
+// launches on the context's stream (kernel classes: ebit_kernel_class).
+#define EBIT_PROF_CAP 1024
+#define EBIT_PROF_CLASSES 8
+struct EbitProfiler {
+  int on;
+  int npend;
+  hipEvent_t ev0[EBIT_PROF_CAP];
+  hipEvent_t ev1[EBIT_PROF_CAP];
+  int kid[EBIT_PROF_CAP];
+  long long launches[EBIT_PROF_CLASSES];
+  double ms[EBIT_PROF_CLASSES];
+};
+
 // Work vectors of the outer loop (fine level).
 struct EbitSolveBufs {
   double* r;
@@ -225,6 +239,7 @@ struct EbitSolveBufs {
   double* q;
   double* partial;     // [2][EBIT_RED_BLOCKS]
   ebit::Scal* scal;
+  EbitProfiler* prof;  // may be null
 };
 
 extern "C" {
@@ -250,6 +265,7 @@ hipError_t ebit_launch_face_update(const ebit::Dims* d, double h, const double r
                                    const double pval[6], const uint8_t* flags, const double* const th[3],
                                    double* const ul[3], double* const uv[3], const double* p, double* partial,
                                    ebit::Scal* scal, hipStream_t st);
+hipError_t ebit_prof_flush(EbitProfiler* pr);
 int ebit_solve_stream(const ebit::FineOp* op, const EbitLevelHost* lv, int nlev, const EbitSolveBufs* B,
                       const double* b, double* x, int use_guess, const ebit_opts* o, hipStream_t st, int* iters,
                       int* vcyc, double* relres, double* bnorm, double* floor, hipError_t* herr);

@@ -551,6 +551,39 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
 
 }  // extern "C"
 
+// ---- profiling ----
+hipError_t ebit_prof_flush(EbitProfiler* pr) {
+  if (!pr || pr->npend == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(pr->ev1[pr->npend - 1]);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < pr->npend; ++i) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, pr->ev0[i], pr->ev1[i]);
+    if (e != hipSuccess) return e;
+    pr->ms[pr->kid[i]] += ms;
+    pr->launches[pr->kid[i]] += 1;
+  }
+  pr->npend = 0;
+  return hipSuccess;
+}
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+  EbitProfiler* pr;
+  hipStream_t st;
+  int slot;
+  ProfScope(EbitProfiler* p, int kid, hipStream_t s) : pr(p), st(s), slot(-1) {
+    if (!pr || !pr->on) return;
+    if (pr->npend == EBIT_PROF_CAP) (void)ebit_prof_flush(pr);
+    slot = pr->npend++;
+    pr->kid[slot] = kid;
+    (void)hipEventRecord(pr->ev0[slot], st);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(pr->ev1[slot], st);
+  }
+};
+
 // ---- V-cycle driver (templated on the inner precision) ----
 template <typename T>
 static CoarseOp<T> coarse_op(const EbitLevelHost& L, int sys);
@@ -588,7 +621,7 @@ float* lvb<float>(const EbitLevelHost& L) { return L.b32; }
 // One V(nu1, nu2) cycle on A z = r with z = 0 initially; fine level matrix-free.
 template <typename T>
 static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, const double* r, T* z,
-                         int nu1, int nu2, hipStream_t st) {
+                         int nu1, int nu2, hipStream_t st, EbitProfiler* pf) {
   const Dims& fd = op.d;
   const int sys = op.sys;
   hipLaunchKernelGGL(k_fill<T>, dim3(nblk(fd.N)), dim3(EBIT_BLOCK), 0, st, fd.N, z, (T)0);
@@ -602,11 +635,16 @@ static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, co
   }
   // descend
   for (int s = 0; s < nu1; ++s)
-    for (int col = 0; col < 2; ++col)
+    for (int col = 0; col < 2; ++col) {
+      ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
       hipLaunchKernelGGL((k_fine_smooth<T, double>), dim3(nblk(half_count(fd))), dim3(EBIT_BLOCK), 0, st, op, r,
                          z, col);
-  hipLaunchKernelGGL((k_fine_resid_restrict<T, double>), dim3(nblk(lv[1].d.N)), dim3(EBIT_BLOCK), 0, st, op, r,
-                     (const T*)z, lv[1].d, lvb<T>(lv[1]), lvx<T>(lv[1]));
+    }
+  {
+    ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
+    hipLaunchKernelGGL((k_fine_resid_restrict<T, double>), dim3(nblk(lv[1].d.N)), dim3(EBIT_BLOCK), 0, st, op, r,
+                       (const T*)z, lv[1].d, lvb<T>(lv[1]), lvx<T>(lv[1]));
+  }
   for (int l = 1; l < nlev - 1; ++l) {
     CoarseOp<T> c = coarse_op<T>(lv[l], sys);
     for (int s = 0; s < nu1; ++s)
@@ -632,12 +670,17 @@ static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, co
         hipLaunchKernelGGL(k_coarse_smooth<T>, dim3(nblk(half_count(c.d))), dim3(EBIT_BLOCK), 0, st, c,
                            (const T*)lvb<T>(lv[l]), lvx<T>(lv[l]), col);
   }
-  hipLaunchKernelGGL(k_prolong<T>, dim3(nblk(fd.N)), dim3(EBIT_BLOCK), 0, st, fd, lv[1].d, z,
-                     (const T*)lvx<T>(lv[1]));
+  {
+    ProfScope ps(pf, EBIT_KC_FINE_PROLONG, st);
+    hipLaunchKernelGGL(k_prolong<T>, dim3(nblk(fd.N)), dim3(EBIT_BLOCK), 0, st, fd, lv[1].d, z,
+                       (const T*)lvx<T>(lv[1]));
+  }
   for (int s = 0; s < nu2; ++s)
-    for (int col = 1; col >= 0; --col)
+    for (int col = 1; col >= 0; --col) {
+      ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
       hipLaunchKernelGGL((k_fine_smooth<T, double>), dim3(nblk(half_count(fd))), dim3(EBIT_BLOCK), 0, st, op, r,
                          z, col);
+    }
   return hipGetLastError();
 }
 
@@ -733,7 +776,7 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
   double last_true = rr;  // last recomputed residual (squared)
   int at_floor = 0;
   while (it < o->max_iters) {
-    CK(vcycle<T>(op, lv, nlev, B->r, z, o->nu1, o->nu2, st));
+    CK(vcycle<T>(op, lv, nlev, B->r, z, o->nu1, o->nu2, st, B->prof));
     ++*vcyc;
     // defect correction = the same loop with beta = 0: x += alpha V(r) with the
     // energy-optimal step alpha = (r.z)/(z.Az), so it contracts for any SPD A
@@ -742,13 +785,19 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
                        (const double*)B->r, fresh ? nullptr : (const double*)B->q, B->partial);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 2, B->scal,
                        (int)FIN_GAMMA, fresh);
-    hipLaunchKernelGGL(k_p_update_apply<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, (const T*)z,
-                       (const double*)B->p[pi], B->p[1 - pi], B->q, (const Scal*)B->scal, fresh, B->partial);
+    {
+      ProfScope ps(B->prof, EBIT_KC_OUTER_APPLY, st);
+      hipLaunchKernelGGL(k_p_update_apply<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, (const T*)z,
+                         (const double*)B->p[pi], B->p[1 - pi], B->q, (const Scal*)B->scal, fresh, B->partial);
+    }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
                        (int)FIN_DELTA, 0);
     pi = 1 - pi;
-    hipLaunchKernelGGL(k_update_xr, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, x, B->r, (const double*)B->p[pi],
-                       (const double*)B->q, (const Scal*)B->scal, B->partial);
+    {
+      ProfScope ps(B->prof, EBIT_KC_OUTER_UPDATE, st);
+      hipLaunchKernelGGL(k_update_xr, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, x, B->r, (const double*)B->p[pi],
+                         (const double*)B->q, (const Scal*)B->scal, B->partial);
+    }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
                        (int)FIN_RR, 0);
     first = 0;

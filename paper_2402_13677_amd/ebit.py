@@ -79,6 +79,8 @@ def load():
         "ebit_heat_rhs": (i, [vp, vp, vp]),
         "ebit_project_rhs": (i, [vp, _P3, _P3, vp, vp]),
         "ebit_levels": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "ebit_profile": (i, [vp, i]),
+        "ebit_profile_read": (i, [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -90,7 +92,9 @@ def load():
 
 EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "ebit_create", "ebit_destroy",
             "ebit_last_error", "ebit_build_coeffs", "ebit_heat_solve", "ebit_mass_flux", "ebit_project",
-            "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_project_rhs", "ebit_levels"]
+            "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_project_rhs", "ebit_levels",
+            "ebit_profile", "ebit_profile_read"]
+KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_FINE_PROLONG, KC_OUTER_APPLY, KC_OUTER_UPDATE = range(5)
 
 
 class EbitError(RuntimeError):
@@ -234,6 +238,16 @@ class Context:
     def project_rhs(self, u_l, u_v, mdot, b):
         self._check(self.lib.ebit_project_rhs(self.h, _p3(u_l), _p3(u_v), _ptr(mdot, torch.float64),
                                               _ptr(b, torch.float64)), "ebit_project_rhs")
+
+    def profile(self, enable=True):
+        self._check(self.lib.ebit_profile(self.h, int(enable)), "ebit_profile")
+
+    def profile_read(self, kernel_class):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        self._check(self.lib.ebit_profile_read(self.h, int(kernel_class), ctypes.byref(n), ctypes.byref(ms)),
+                    "ebit_profile_read")
+        return n.value, ms.value
 
     def levels(self):
         n = ctypes.c_int()
