@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "fine_prolong", "outer_apply", "outer_update"]
 # the HIP kernels of each class (names as rocprofv3 reports them)
 KERNEL_NAMES = {
-    "fine_smooth": "k_fine_smooth",
+    "fine_smooth": "k_rb_fused",
     "fine_restrict": "k_fine_resid_restrict",
     "fine_prolong": "k_prolong",
     "outer_apply": "k_p_update_apply",
@@ -51,8 +51,8 @@ def algorithmic_bytes_per_cell(kclass, precision, dim):
     V-cycle smooths against is FP64."""
     sx = 4 if precision == "mixed" else 8
     agg = 2 ** dim
-    if kclass == "fine_smooth":      # one colour: read r, flags of the updated half, x of the other half; write x
-        return (8 + 1 + sx + sx) / 2
+    if kclass == "fine_smooth":      # one full red-black sweep: read x, r (FP64), flags; write x
+        return sx + 8 + 1 + sx
     if kclass == "fine_restrict":    # read x, r, flags; write coarse b and clear coarse x
         return sx + 8 + 1 + 2 * sx / agg
     if kclass == "fine_prolong":     # read coarse x, read and write x

@@ -105,7 +105,7 @@ typedef struct {
                          at the floor (ebit_stats.res_floor)                  */
   int max_iters;      /* outer iterations [200]                               */
   int nu1, nu2;       /* red-black Gauss-Seidel sweeps before / after the
-                         coarse correction [2, 2]                             */
+                         coarse correction, 1..8 each [2, 2]                  */
   double theta_min;   /* lower clamp of theta in the 1/theta terms [1e-3]     */
   int check_every;    /* outer iterations between host residual checks [1]    */
   int tail_cells;     /* levels with at most this many cells are smoothed by

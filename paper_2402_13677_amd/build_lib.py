@@ -40,6 +40,11 @@ def build(verbose: bool = True, jobs: int = 4) -> str:
     if out.returncode != 0:
         sys.stderr.write(out.stdout)
         raise RuntimeError("link of libebit.so failed")
+    # every internal launcher must resolve inside the library itself
+    nm = subprocess.run(["nm", "-D", "--undefined-only", tmp], stdout=subprocess.PIPE, text=True)
+    missing = [ln.split()[-1] for ln in nm.stdout.splitlines() if ln.split() and ln.split()[-1].startswith("ebit_")]
+    if missing:
+        raise RuntimeError(f"libebit.so leaves library symbols undefined: {missing}")
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

@@ -140,7 +140,7 @@ bool valid_opts(const ebit_opts* o, char* msg, size_t ml) {
     snprintf(msg, ml, "bad outer loop");
     return false;
   }
-  if (!(o->rtol > 0) || o->max_iters < 1 || o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 ||
+  if (!(o->rtol > 0) || o->max_iters < 1 || o->nu1 < 1 || o->nu2 < 1 || o->nu1 > 8 || o->nu2 > 8 ||
       !(o->theta_min > 0 && o->theta_min <= 0.5)) {
     snprintf(msg, ml, "bad solver options");
     return false;
@@ -182,7 +182,9 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
   EbitSolveBufs B;
   B.r = cv.take<double>(N);
   B.z64 = cv.take<double>(N);
+  B.z64b = cv.take<double>(N);
   B.z32 = cv.take<float>(N);
+  B.z32b = cv.take<float>(N);
   B.p[0] = cv.take<double>(N);
   B.p[1] = cv.take<double>(N);
   B.q = cv.take<double>(N);
@@ -214,8 +216,10 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
       for (int a = 0; a < fd.dim; ++a) lv[l].off32[s][a] = cv.take<float>(n);
     }
     lv[l].x64 = cv.take<double>(n);
+    lv[l].x64b = cv.take<double>(n);
     lv[l].b64 = cv.take<double>(n);
     lv[l].x32 = cv.take<float>(n);
+    lv[l].x32b = cv.take<float>(n);
     lv[l].b32 = cv.take<float>(n);
   }
   const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;

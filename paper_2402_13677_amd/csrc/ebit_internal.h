@@ -211,8 +211,10 @@ struct EbitLevelHost {
   float* diag32[2];
   float* off32[2][3];
   double* x64;
+  double* x64b;        // second iterate buffer (out-of-place fused sweeps)
   double* b64;
   float* x32;
+  float* x32b;
   float* b32;
 };
 
@@ -234,7 +236,9 @@ struct EbitProfiler {
 struct EbitSolveBufs {
   double* r;
   double* z64;
+  double* z64b;
   float* z32;
+  float* z32b;
   double* p[2];
   double* q;
   double* partial;     // [2][EBIT_RED_BLOCKS]

@@ -53,24 +53,6 @@ __device__ inline T fine_residual_at(const FineOp& op, int i, int j, int k, long
   return s;
 }
 
-template <typename T, typename TB>
-__global__ void k_fine_smooth(FineOp op, const TB* __restrict__ b, T* __restrict__ x, int color) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!red_black_cell(op.d, t, color, i, j, k)) return;
-  const long long c = cell_index(op.d, i, j, k);
-  T diag, off[6], mass, rb = 0;
-  fine_row<T>(op, i, j, k, op.flags[c], diag, off, mass, rb);
-  T s = (T)b[c];
-  for (int q = 0; q < 2 * op.d.dim; ++q) {
-    if (off[q] == (T)0) continue;
-    int ni, nj, nk;
-    neighbour(op.d, i, j, k, q, ni, nj, nk);
-    s -= off[q] * x[cell_index(op.d, ni, nj, nk)];
-  }
-  x[c] = s / diag;
-}
-
 // Residual of the 2^d children of every coarse cell, summed (= P^T r); also
 // clears the coarse iterate.
 template <typename T, typename TB>
@@ -98,15 +80,6 @@ __global__ void k_fine_resid_restrict(FineOp op, const TB* __restrict__ b, const
   xc[I] = (T)0;
 }
 
-template <typename T>
-__global__ void k_prolong(Dims fd, Dims cd, T* __restrict__ x, const T* __restrict__ xc) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= fd.N) return;
-  int i, j, k;
-  cell_ijk(fd, c, i, j, k);
-  x[c] += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
-}
-
 // ---------------------------------------------------------------------------
 // coarse levels (explicit symmetric coefficients)
 // ---------------------------------------------------------------------------
@@ -122,15 +95,6 @@ __device__ inline T coarse_offsum(const CoarseOp<T>& op, int i, int j, int k, lo
     }
   }
   return s;
-}
-
-template <typename T>
-__global__ void k_coarse_smooth(CoarseOp<T> op, const T* __restrict__ b, T* __restrict__ x, int color) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!red_black_cell(op.d, t, color, i, j, k)) return;
-  const long long c = cell_index(op.d, i, j, k);
-  x[c] = (b[c] - coarse_offsum<T>(op, i, j, k, c, x)) / op.diag[c];
 }
 
 template <typename T>
@@ -173,6 +137,310 @@ __global__ void k_coarsest(CoarseOp<T> op, const T* __restrict__ b, T* __restric
         cell_ijk(op.d, c, i, j, k);
         x[c] = (b[c] - coarse_offsum<T>(op, i, j, k, c, x)) / op.diag[c];
       }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep: one HBM pass per full sweep.
+//
+// A work-group owns a TX x TY tile of an x-y plane and marches along z over
+// a chunk of planes, holding four planes (tile + 2-cell ring) in LDS.  For
+// each plane k it first updates the red cells of plane k+1 on the tile + 1
+// ring (from the old black values), then the black cells of plane k on the
+// tile (from the new red values of planes k-1, k, k+1), and writes plane k.
+// Red cells on the ring are recomputed by every tile that needs them from
+// the same old values, so the result equals a red half-sweep over the whole
+// grid followed by a black one.  Reads x_in, writes x_out (a different
+// buffer: neighbouring tiles read x_in while this one writes).  x_in may be
+// null (zero initial guess) and a coarse correction xc may be added on load
+// (fused prolongation).
+// ---------------------------------------------------------------------------
+#define RB_TX 64
+#define RB_TY 8
+#define RB_PX (RB_TX + 4)
+#define RB_PY (RB_TY + 4)
+#define RB_PLANE (RB_PX * RB_PY)
+#define RB_THREADS 256
+
+// row of the fine (matrix-free) operator
+template <typename T, typename TB>
+struct FineRows {
+  FineOp op;
+  const TB* b;
+  __device__ const Dims& dims() const { return op.d; }
+  __device__ inline void row(int i, int j, int k, long long c, T& diag, T off[6], T& rhs) const {
+    T mass, rb = 0;
+    fine_row<T>(op, i, j, k, op.flags[c], diag, off, mass, rb);
+    rhs = (T)b[c];
+  }
+};
+
+// row of an explicit coarse level
+template <typename T>
+struct CoarseRows {
+  CoarseOp<T> op;
+  const T* b;
+  __device__ const Dims& dims() const { return op.d; }
+  __device__ inline void row(int i, int j, int k, long long c, T& diag, T off[6], T& rhs) const {
+    diag = op.diag[c];
+    rhs = b[c];
+    for (int a = 0; a < 3; ++a) {
+      off[2 * a] = off[2 * a + 1] = (T)0;
+      if (a >= op.d.dim) continue;
+      int ni, nj, nk;
+      if (neighbour(op.d, i, j, k, 2 * a + 1, ni, nj, nk) && op.d.n[a] > 1) off[2 * a + 1] = op.off[a][c];
+      if (neighbour(op.d, i, j, k, 2 * a, ni, nj, nk) && op.d.n[a] > 1)
+        off[2 * a] = op.off[a][cell_index(op.d, ni, nj, nk)];
+    }
+  }
+};
+
+template <typename T, typename R>
+__device__ inline void rb_load_plane(const R& rows, int kk, int tx0, int ty0, const T* __restrict__ xin,
+                                     const T* __restrict__ xc, const Dims& cd, T* plane) {
+  const Dims& d = rows.dims();
+  int k = kk;
+  bool present = true;
+  if (k < 0 || k >= d.n[2]) {
+    if (d.per[2] && d.dim == 3)
+      k = (k % d.n[2] + d.n[2]) % d.n[2];
+    else
+      present = false;
+  }
+  for (int t = threadIdx.x; t < RB_PLANE; t += RB_THREADS) {
+    const int ly = t / RB_PX - 2, lx = t % RB_PX - 2;
+    int i = tx0 + lx, j = ty0 + ly;
+    T v = (T)0;
+    bool ok = present;
+    if (ok && (i < 0 || i >= d.n[0])) {
+      if (d.per[0]) i = (i % d.n[0] + d.n[0]) % d.n[0];
+      else ok = false;
+    }
+    if (ok && (j < 0 || j >= d.n[1])) {
+      if (d.per[1]) j = (j % d.n[1] + d.n[1]) % d.n[1];
+      else ok = false;
+    }
+    if (ok) {
+      const long long c = cell_index(d, i, j, k);
+      if (xin) v = xin[c];
+      if (xc) v += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
+    }
+    plane[t] = v;
+  }
+}
+
+// update the cells of one colour in plane k over the local window [lo, hi)
+template <typename T, typename R>
+__device__ inline void rb_update_plane(const R& rows, int k, int tx0, int ty0, int color, int lo_x, int hi_x,
+                                       int lo_y, int hi_y, T* pm, T* p0, T* pp) {
+  const Dims& d = rows.dims();
+  if (k < 0 || k >= d.n[2]) {
+    if (!(d.per[2] && d.dim == 3)) return;
+  }
+  const int kw = (k % d.n[2] + d.n[2]) % d.n[2];
+  const int wx = hi_x - lo_x, wy = hi_y - lo_y;
+  for (int t = threadIdx.x; t < wx * wy; t += RB_THREADS) {
+    const int lx = lo_x + t % wx, ly = lo_y + t / wx;
+    const int i = tx0 + lx, j = ty0 + ly;
+    if (((i + j + k) & 1) != color) continue;
+    // cells outside the domain along a non-periodic axis are not updated
+    int iw = i, jw = j;
+    if (iw < 0 || iw >= d.n[0]) {
+      if (!d.per[0]) continue;
+      iw = (iw % d.n[0] + d.n[0]) % d.n[0];
+    }
+    if (jw < 0 || jw >= d.n[1]) {
+      if (!d.per[1]) continue;
+      jw = (jw % d.n[1] + d.n[1]) % d.n[1];
+    }
+    const long long c = cell_index(d, iw, jw, kw);
+    T diag, off[6], rhs;
+    rows.row(iw, jw, kw, c, diag, off, rhs);
+    const int q = (ly + 2) * RB_PX + (lx + 2);
+    T sum = rhs - off[0] * p0[q - 1] - off[1] * p0[q + 1];
+    if (d.dim >= 2) sum -= off[2] * p0[q - RB_PX] + off[3] * p0[q + RB_PX];
+    if (d.dim == 3) sum -= off[4] * pm[q] + off[5] * pp[q];
+    p0[q] = sum / diag;
+  }
+}
+
+template <typename T, typename R>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_fused(R rows, const T* __restrict__ xin,
+                                                         const T* __restrict__ xc, Dims cd, T* __restrict__ xout,
+                                                         int zchunk) {
+  __shared__ T buf[4][RB_PLANE];
+  const Dims& d = rows.dims();
+  const int tx0 = blockIdx.x * RB_TX, ty0 = blockIdx.y * RB_TY;
+  const int z0 = blockIdx.z * zchunk;
+  const int z1 = min(z0 + zchunk, d.n[2]);
+  const bool zdim = d.dim == 3;
+  auto slot = [&](int k) { return buf[((k % 4) + 4) % 4]; };
+  if (zdim) {
+    for (int k = z0 - 2; k <= z0 + 1; ++k) rb_load_plane<T>(rows, k, tx0, ty0, xin, xc, cd, slot(k));
+    __syncthreads();
+    // red on the tile + 1 ring of the two planes before the first black one
+    rb_update_plane<T>(rows, z0 - 1, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, slot(z0 - 2), slot(z0 - 1),
+                       slot(z0));
+    __syncthreads();
+    rb_update_plane<T>(rows, z0, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, slot(z0 - 1), slot(z0), slot(z0 + 1));
+    __syncthreads();
+  } else {
+    rb_load_plane<T>(rows, 0, tx0, ty0, xin, xc, cd, buf[0]);
+    __syncthreads();
+    rb_update_plane<T>(rows, 0, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, buf[1], buf[0], buf[2]);
+    __syncthreads();
+  }
+  for (int k = z0; k < z1; ++k) {
+    T* p0 = zdim ? slot(k) : buf[0];
+    if (zdim) {
+      rb_load_plane<T>(rows, k + 2, tx0, ty0, xin, xc, cd, slot(k + 2));
+      __syncthreads();
+      rb_update_plane<T>(rows, k + 1, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, slot(k), slot(k + 1), slot(k + 2));
+      __syncthreads();
+    }
+    rb_update_plane<T>(rows, k, tx0, ty0, 1, 0, RB_TX, 0, RB_TY, zdim ? slot(k - 1) : buf[1], p0,
+                       zdim ? slot(k + 1) : buf[2]);
+    __syncthreads();
+    for (int t = threadIdx.x; t < RB_TX * RB_TY; t += RB_THREADS) {
+      const int lx = t % RB_TX, ly = t / RB_TX;
+      const int i = tx0 + lx, j = ty0 + ly;
+      if (i < d.n[0] && j < d.n[1]) xout[cell_index(d, i, j, k)] = p0[(ly + 2) * RB_PX + (lx + 2)];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tail of the V-cycle: every level small enough to sit in LDS, in one
+// work-group (no launch per smoothing sweep on the coarse levels)
+// ---------------------------------------------------------------------------
+#define EBIT_TAIL_MAX 16
+#define EBIT_TAIL_THREADS 1024
+
+template <typename T>
+struct TailArgs {
+  int nl;  // levels in the tail; the last one is the coarsest
+  int nu1, nu2;
+  Dims d[EBIT_TAIL_MAX];
+  const T* diag[EBIT_TAIL_MAX];
+  const T* off[EBIT_TAIL_MAX][3];
+  int base[EBIT_TAIL_MAX];  // LDS element offset of the level's x (b follows)
+  const T* bg;              // right-hand side of the top tail level
+  T* xg;                    // its correction (output)
+};
+
+template <typename T>
+__device__ inline CoarseOp<T> tail_op(const TailArgs<T>& a, int l) {
+  CoarseOp<T> c;
+  c.d = a.d[l];
+  c.diag = a.diag[l];
+  for (int q = 0; q < 3; ++q) c.off[q] = a.off[l][q];
+  c.mass = nullptr;
+  return c;
+}
+
+template <typename T>
+__device__ inline void tail_sweep(const CoarseOp<T>& c, const T* b, T* x, int color) {
+  const long long nh = (long long)((c.d.n[0] + 1) >> 1) * c.d.n[1] * c.d.n[2];
+  for (long long t = threadIdx.x; t < nh; t += blockDim.x) {
+    int i, j, k;
+    if (!red_black_cell(c.d, t, color, i, j, k)) continue;
+    const long long q = cell_index(c.d, i, j, k);
+    x[q] = (b[q] - coarse_offsum<T>(c, i, j, k, q, x)) / c.diag[q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(EBIT_TAIL_THREADS) void k_tail(TailArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char tail_smem[];
+  T* sm = reinterpret_cast<T*>(tail_smem);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  {
+    const long long N = a.d[0].N;
+    T* x = sm + a.base[0];
+    T* b = x + N;
+    for (long long q = tid; q < N; q += nth) {
+      b[q] = a.bg[q];
+      x[q] = (T)0;
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < a.nl - 1; ++l) {
+    const CoarseOp<T> c = tail_op(a, l);
+    T* x = sm + a.base[l];
+    T* b = x + c.d.N;
+    for (int s = 0; s < a.nu1; ++s)
+      for (int col = 0; col < 2; ++col) {
+        tail_sweep(c, b, x, col);
+        __syncthreads();
+      }
+    const Dims cd = a.d[l + 1];
+    T* xc = sm + a.base[l + 1];
+    T* bc = xc + cd.N;
+    for (long long I = tid; I < cd.N; I += nth) {
+      int ci, cj, ck;
+      cell_ijk(cd, I, ci, cj, ck);
+      T sum = 0;
+      for (int dk = 0; dk < 2; ++dk) {
+        const int k = 2 * ck + dk;
+        if (k >= c.d.n[2]) break;
+        for (int dj = 0; dj < 2; ++dj) {
+          const int j = 2 * cj + dj;
+          if (j >= c.d.n[1]) break;
+          for (int di = 0; di < 2; ++di) {
+            const int i = 2 * ci + di;
+            if (i >= c.d.n[0]) break;
+            const long long q = cell_index(c.d, i, j, k);
+            sum += b[q] - c.diag[q] * x[q] - coarse_offsum<T>(c, i, j, k, q, x);
+          }
+        }
+      }
+      bc[I] = sum;
+      xc[I] = (T)0;
+    }
+    __syncthreads();
+  }
+  {
+    // coarsest level: symmetric Gauss-Seidel by one thread (exact for one cell)
+    const int l = a.nl - 1;
+    const CoarseOp<T> c = tail_op(a, l);
+    T* x = sm + a.base[l];
+    T* b = x + c.d.N;
+    if (tid == 0) {
+      const int sweeps = c.d.N == 1 ? 1 : 50;
+      for (int s = 0; s < sweeps; ++s)
+        for (int dir = 0; dir < 2; ++dir)
+          for (long long qq = 0; qq < c.d.N; ++qq) {
+            const long long q = dir ? (c.d.N - 1 - qq) : qq;
+            int i, j, k;
+            cell_ijk(c.d, q, i, j, k);
+            x[q] = (b[q] - coarse_offsum<T>(c, i, j, k, q, x)) / c.diag[q];
+          }
+    }
+    __syncthreads();
+  }
+  for (int l = a.nl - 2; l >= 0; --l) {
+    const CoarseOp<T> c = tail_op(a, l);
+    T* x = sm + a.base[l];
+    T* b = x + c.d.N;
+    const Dims cd = a.d[l + 1];
+    const T* xc = sm + a.base[l + 1];
+    for (long long q = tid; q < c.d.N; q += nth) {
+      int i, j, k;
+      cell_ijk(c.d, q, i, j, k);
+      x[q] += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
+    }
+    __syncthreads();
+    for (int s = 0; s < a.nu2; ++s)
+      for (int col = 1; col >= 0; --col) {
+        tail_sweep(c, b, x, col);
+        __syncthreads();
+      }
+  }
+  {
+    const long long N = a.d[0].N;
+    const T* x = sm + a.base[0];
+    for (long long q = tid; q < N; q += nth) a.xg[q] = x[q];
   }
 }
 
@@ -619,68 +887,137 @@ template <>
 float* lvb<float>(const EbitLevelHost& L) { return L.b32; }
 
 // One V(nu1, nu2) cycle on A z = r with z = 0 initially; fine level matrix-free.
+// LDS the tail kernel may use (bytes); the hierarchy from level l down fits
+// if sum_m 2 N_m sizeof(T) stays below it.
+#define EBIT_TAIL_LDS (64 * 1024)
+
+// First coarse level (>= 1) from which the tail kernel takes over: the
+// remaining levels must fit its LDS and hold at most tail_cells cells on top.
 template <typename T>
-static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, const double* r, T* z,
-                         int nu1, int nu2, hipStream_t st, EbitProfiler* pf) {
-  const Dims& fd = op.d;
+static int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells) {
+  if (tail_cells <= 0) return nlev;
+  long long tot = 0;
+  int lt = nlev;
+  for (int l = nlev - 1; l >= 1; --l) {
+    tot += 2 * lv[l].d.N;
+    if (tot * (long long)sizeof(T) > EBIT_TAIL_LDS || lv[l].d.N > tail_cells || nlev - l > EBIT_TAIL_MAX) break;
+    lt = l;
+  }
+  return lt;
+}
+
+template <typename T>
+static T* lvxb(const EbitLevelHost& L);
+template <>
+double* lvxb<double>(const EbitLevelHost& L) { return L.x64b; }
+template <>
+float* lvxb<float>(const EbitLevelHost& L) { return L.x32b; }
+
+static inline dim3 rb_grid(const Dims& d, int zchunk) {
+  return dim3((unsigned)((d.n[0] + RB_TX - 1) / RB_TX), (unsigned)((d.n[1] + RB_TY - 1) / RB_TY),
+              (unsigned)((d.n[2] + zchunk - 1) / zchunk));
+}
+
+// z-chunk: enough work-groups to fill the chip, at most 32 planes each
+static inline int rb_zchunk(const Dims& d) {
+  if (d.dim < 3) return 1;
+  const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
+  int zc = 32;
+  while (zc > 4 && tiles * ((d.n[2] + zc - 1) / zc) < 1024) zc >>= 1;
+  return zc;
+}
+
+// S = nu1 + nu2 fused sweeps on one level; sweep s (1-based) writes X when
+// S - s is even and Xb otherwise, so the last one lands in X.  The first
+// pre-smoothing sweep starts from zero; the first post-smoothing sweep adds
+// the coarse correction xc on load.
+template <typename T, typename R>
+static void smooth_pre(const R& rows, int nu1, int S, T* X, T* Xb, hipStream_t st, EbitProfiler* pf, int kc) {
+  const Dims& d = rows.op.d;
+  const int zc = rb_zchunk(d);
+  const T* in = nullptr;
+  for (int s = 1; s <= nu1; ++s) {
+    T* out = ((S - s) % 2 == 0) ? X : Xb;
+    ProfScope ps(pf, kc, st);
+    hipLaunchKernelGGL((k_rb_fused<T, R>), rb_grid(d, zc), dim3(RB_THREADS), 0, st, rows, in, (const T*)nullptr, d,
+                       out, zc);
+    in = out;
+  }
+}
+template <typename T, typename R>
+static void smooth_post(const R& rows, int nu1, int S, T* X, T* Xb, const T* xc, const Dims& cd, hipStream_t st,
+                        EbitProfiler* pf, int kc) {
+  const Dims& d = rows.op.d;
+  const int zc = rb_zchunk(d);
+  const T* in = ((S - nu1) % 2 == 0) ? X : Xb;
+  for (int s = nu1 + 1; s <= S; ++s) {
+    T* out = ((S - s) % 2 == 0) ? X : Xb;
+    ProfScope ps(pf, kc, st);
+    hipLaunchKernelGGL((k_rb_fused<T, R>), rb_grid(d, zc), dim3(RB_THREADS), 0, st, rows, in,
+                       s == nu1 + 1 ? xc : (const T*)nullptr, cd, out, zc);
+    in = out;
+  }
+}
+
+// One V(nu1, nu2) cycle on A z = r (zero initial guess); the fine level is
+// matrix-free, levels 1 .. lt-1 explicit, levels lt .. in the tail kernel.
+template <typename T>
+static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, const double* r, T* z, T* zb,
+                         int nu1, int nu2, int tail_cells, hipStream_t st, EbitProfiler* pf) {
   const int sys = op.sys;
-  hipLaunchKernelGGL(k_fill<T>, dim3(nblk(fd.N)), dim3(EBIT_BLOCK), 0, st, fd.N, z, (T)0);
+  const int S = nu1 + nu2;
+  FineRows<T, double> fine{op, r};
   if (nlev == 1) {
-    // no coarse level: smoothing only
-    for (int s = 0; s < nu1 + nu2; ++s)
-      for (int col = 0; col < 2; ++col)
-        hipLaunchKernelGGL((k_fine_smooth<T, double>), dim3(nblk(half_count(fd))), dim3(EBIT_BLOCK), 0, st, op,
-                           r, z, col);
+    smooth_pre<T>(fine, S, S, z, zb, st, pf, EBIT_KC_FINE_SMOOTH);
     return hipGetLastError();
   }
   // descend
-  for (int s = 0; s < nu1; ++s)
-    for (int col = 0; col < 2; ++col) {
-      ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
-      hipLaunchKernelGGL((k_fine_smooth<T, double>), dim3(nblk(half_count(fd))), dim3(EBIT_BLOCK), 0, st, op, r,
-                         z, col);
-    }
+  smooth_pre<T>(fine, nu1, S, z, zb, st, pf, EBIT_KC_FINE_SMOOTH);
+  const T* zpre = ((S - nu1) % 2 == 0) ? z : zb;
   {
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
     hipLaunchKernelGGL((k_fine_resid_restrict<T, double>), dim3(nblk(lv[1].d.N)), dim3(EBIT_BLOCK), 0, st, op, r,
-                       (const T*)z, lv[1].d, lvb<T>(lv[1]), lvx<T>(lv[1]));
+                       zpre, lv[1].d, lvb<T>(lv[1]), lvx<T>(lv[1]));
   }
-  for (int l = 1; l < nlev - 1; ++l) {
-    CoarseOp<T> c = coarse_op<T>(lv[l], sys);
-    for (int s = 0; s < nu1; ++s)
-      for (int col = 0; col < 2; ++col)
-        hipLaunchKernelGGL(k_coarse_smooth<T>, dim3(nblk(half_count(c.d))), dim3(EBIT_BLOCK), 0, st, c,
-                           (const T*)lvb<T>(lv[l]), lvx<T>(lv[l]), col);
-    hipLaunchKernelGGL(k_coarse_resid_restrict<T>, dim3(nblk(lv[l + 1].d.N)), dim3(EBIT_BLOCK), 0, st, c,
-                       (const T*)lvb<T>(lv[l]), (const T*)lvx<T>(lv[l]), lv[l + 1].d, lvb<T>(lv[l + 1]),
-                       lvx<T>(lv[l + 1]));
+  // first level whose whole remaining hierarchy fits the tail kernel's LDS
+  const int lt = tail_start<T>(lv, nlev, tail_cells);
+  for (int l = 1; l < lt; ++l) {
+    CoarseRows<T> rows{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])};
+    smooth_pre<T>(rows, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), st, nullptr, 0);
+    const T* xpre = ((S - nu1) % 2 == 0) ? lvx<T>(lv[l]) : lvxb<T>(lv[l]);
+    hipLaunchKernelGGL(k_coarse_resid_restrict<T>, dim3(nblk(lv[l + 1].d.N)), dim3(EBIT_BLOCK), 0, st, rows.op,
+                       (const T*)lvb<T>(lv[l]), xpre, lv[l + 1].d, lvb<T>(lv[l + 1]), lvx<T>(lv[l + 1]));
   }
-  {
+  if (lt < nlev) {
+    TailArgs<T> ta;
+    ta.nl = nlev - lt;
+    ta.nu1 = nu1;
+    ta.nu2 = nu2;
+    int off = 0;
+    for (int m = 0; m < ta.nl; ++m) {
+      const EbitLevelHost& L = lv[lt + m];
+      ta.d[m] = L.d;
+      CoarseOp<T> c = coarse_op<T>(L, sys);
+      ta.diag[m] = c.diag;
+      for (int q = 0; q < 3; ++q) ta.off[m][q] = c.off[q];
+      ta.base[m] = off;
+      off += (int)(2 * L.d.N);
+    }
+    ta.bg = lvb<T>(lv[lt]);
+    ta.xg = lvx<T>(lv[lt]);
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(EBIT_TAIL_THREADS), (size_t)off * sizeof(T), st, ta);
+  } else {
     CoarseOp<T> c = coarse_op<T>(lv[nlev - 1], sys);
     hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(64), 0, st, c, (const T*)lvb<T>(lv[nlev - 1]),
                        lvx<T>(lv[nlev - 1]), c.d.N == 1 ? 1 : 50);
   }
-  // ascend
-  for (int l = nlev - 2; l >= 1; --l) {
-    CoarseOp<T> c = coarse_op<T>(lv[l], sys);
-    hipLaunchKernelGGL(k_prolong<T>, dim3(nblk(c.d.N)), dim3(EBIT_BLOCK), 0, st, c.d, lv[l + 1].d, lvx<T>(lv[l]),
-                       (const T*)lvx<T>(lv[l + 1]));
-    for (int s = 0; s < nu2; ++s)
-      for (int col = 1; col >= 0; --col)
-        hipLaunchKernelGGL(k_coarse_smooth<T>, dim3(nblk(half_count(c.d))), dim3(EBIT_BLOCK), 0, st, c,
-                           (const T*)lvb<T>(lv[l]), lvx<T>(lv[l]), col);
+  // ascend: the first post-smoothing sweep of each level adds the correction
+  for (int l = lt - 1; l >= 1; --l) {
+    CoarseRows<T> rows{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])};
+    smooth_post<T>(rows, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), (const T*)lvx<T>(lv[l + 1]), lv[l + 1].d, st,
+                   nullptr, 0);
   }
-  {
-    ProfScope ps(pf, EBIT_KC_FINE_PROLONG, st);
-    hipLaunchKernelGGL(k_prolong<T>, dim3(nblk(fd.N)), dim3(EBIT_BLOCK), 0, st, fd, lv[1].d, z,
-                       (const T*)lvx<T>(lv[1]));
-  }
-  for (int s = 0; s < nu2; ++s)
-    for (int col = 1; col >= 0; --col) {
-      ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
-      hipLaunchKernelGGL((k_fine_smooth<T, double>), dim3(nblk(half_count(fd))), dim3(EBIT_BLOCK), 0, st, op, r,
-                         z, col);
-    }
+  smooth_post<T>(fine, nu1, S, z, zb, (const T*)lvx<T>(lv[1]), lv[1].d, st, pf, EBIT_KC_FINE_SMOOTH);
   return hipGetLastError();
 }
 
@@ -711,6 +1048,12 @@ static hipError_t read_scal(Scal* d, Scal* h, hipStream_t st) {
   return hipStreamSynchronize(st);
 }
 
+template <typename T>
+static T* zbuf2(const EbitSolveBufs* B);
+template <>
+double* zbuf2<double>(const EbitSolveBufs* B) { return B->z64b; }
+template <>
+float* zbuf2<float>(const EbitSolveBufs* B) { return B->z32b; }
 template <typename T>
 static T* zbuf(const EbitSolveBufs* B);
 template <>
@@ -776,7 +1119,7 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
   double last_true = rr;  // last recomputed residual (squared)
   int at_floor = 0;
   while (it < o->max_iters) {
-    CK(vcycle<T>(op, lv, nlev, B->r, z, o->nu1, o->nu2, st, B->prof));
+    CK(vcycle<T>(op, lv, nlev, B->r, z, zbuf2<T>(B), o->nu1, o->nu2, o->tail_cells, st, B->prof));
     ++*vcyc;
     // defect correction = the same loop with beta = 0: x += alpha V(r) with the
     // energy-optimal step alpha = (r.z)/(z.Az), so it contracts for any SPD A
