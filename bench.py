@@ -33,12 +33,13 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "fine_prolong", "outer_apply", "outer_update"]
+KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "coarse", "outer_apply", "outer_update", "tail"]
 # the HIP kernels of each class (names as rocprofv3 reports them)
 KERNEL_NAMES = {
-    "fine_smooth": "k_rb_fused",
+    "fine_smooth": "k_rb_fine",
     "fine_restrict": "k_fine_resid_restrict",
-    "fine_prolong": "k_prolong",
+    "coarse": "k_rb_fused",
+    "tail": "k_tail",
     "outer_apply": "k_p_update_apply",
     "outer_update": "k_update_xr",
 }
@@ -48,20 +49,19 @@ def algorithmic_bytes_per_cell(kclass, precision, dim):
     """Bytes one launch of a kernel class must move per fine cell (sparse
     theta reads on cut links, O(interface), are not counted).  sx: size of
     the inner iterate (4 in mixed precision, 8 in FP64); the residual r the
-    V-cycle smooths against is FP64."""
+    V-cycle smooths against is FP64.  The coarse-level and tail classes work
+    on levels of varying size and have no per-fine-cell model (None)."""
     sx = 4 if precision == "mixed" else 8
     agg = 2 ** dim
     if kclass == "fine_smooth":      # one full red-black sweep: read x, r (FP64), flags; write x
         return sx + 8 + 1 + sx
     if kclass == "fine_restrict":    # read x, r, flags; write coarse b and clear coarse x
         return sx + 8 + 1 + 2 * sx / agg
-    if kclass == "fine_prolong":     # read coarse x, read and write x
-        return sx / agg + 2 * sx
     if kclass == "outer_apply":      # read z, p_old, flags; write p_new and q (FP64)
         return sx + 8 + 1 + 8 + 8
     if kclass == "outer_update":     # read x, p, r, q; write x, r (FP64)
         return 48.0
-    raise KeyError(kclass)
+    return None
 
 
 def kernel_source_digest():
@@ -171,11 +171,13 @@ def roofline(case, precision, steps):
             continue
         bpc = algorithmic_bytes_per_cell(name, precision, case.dim)
         avg_s = ms * 1e-3 / n
-        bytes_launch = bpc * case.ncells
-        rows[name] = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6,
-                      "algorithmic_bytes_per_launch": bytes_launch,
-                      "achieved_GBps": bytes_launch / avg_s / 1e9}
-    dom = max(rows, key=lambda k: rows[k]["total_ms"])
+        rows[name] = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6}
+        if bpc is not None:
+            bytes_launch = bpc * case.ncells
+            rows[name]["algorithmic_bytes_per_launch"] = bytes_launch
+            rows[name]["achieved_GBps"] = bytes_launch / avg_s / 1e9
+    modelled = [k for k in rows if "achieved_GBps" in rows[k]]
+    dom = max(modelled, key=lambda k: rows[k]["total_ms"])
     r = rows[dom]
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")

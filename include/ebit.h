@@ -209,11 +209,14 @@ ebit_status ebit_project_rhs(ebit_ctx* ctx, double* const u_l[3], double* const 
 
 /* Kernel classes the profiler times (ebit_profile_read). */
 typedef enum {
-  EBIT_KC_FINE_SMOOTH = 0,    /* fine-level red-black smoothing launches       */
+  EBIT_KC_FINE_SMOOTH = 0,    /* fine-level red-black sweeps (the first       */
+                              /* post-smoothing sweep adds the prolongation)  */
   EBIT_KC_FINE_RESTRICT = 1,  /* fine-level residual + restriction             */
-  EBIT_KC_FINE_PROLONG = 2,   /* fine-level prolongation + correction          */
+  EBIT_KC_COARSE = 2,         /* sweeps + restrictions of the explicit coarse  */
+                              /* levels above the tail                        */
   EBIT_KC_OUTER_APPLY = 3,    /* outer loop: search direction update + A p     */
-  EBIT_KC_OUTER_UPDATE = 4    /* outer loop: x and r update                    */
+  EBIT_KC_OUTER_UPDATE = 4,   /* outer loop: x and r update                    */
+  EBIT_KC_TAIL = 5            /* single-work-group solve of the coarsest levels */
 } ebit_kernel_class;
 
 /* Profiling of individual launches with hipEvents recorded on the context's

@@ -385,6 +385,7 @@ ebit_status ebit_create(ebit_ctx** out, const ebit_grid* g, const ebit_props* p,
   c->ws_bytes = bytes;
   layout(g, o, c->ws, c);
   c->B.prof = nullptr;
+  c->B.tail_lds = ebit_tail_lds_setup();
   c->herr = hipSuccess;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;

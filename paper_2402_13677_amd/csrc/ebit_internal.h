@@ -105,8 +105,10 @@ __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f
   diag = mass;
   T mx = mass;
   const int ns = 2 * op.d.dim;
-  for (int s = 0; s < ns; ++s) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
     off[s] = (T)0;
+    if (s >= ns) continue;
     const int a = s >> 1, up = s & 1;
     const int ia = (a == 0) ? i : (a == 1) ? j : k;
     const bool wall = !op.d.per[a] && (up ? (ia == op.d.n[a] - 1) : (ia == 0));
@@ -244,6 +246,7 @@ struct EbitSolveBufs {
   double* partial;     // [2][EBIT_RED_BLOCKS]
   ebit::Scal* scal;
   EbitProfiler* prof;  // may be null
+  int tail_lds;        // LDS bytes the coarse-tail kernel may take
 };
 
 extern "C" {
@@ -270,6 +273,7 @@ hipError_t ebit_launch_face_update(const ebit::Dims* d, double h, const double r
                                    double* const ul[3], double* const uv[3], const double* p, double* partial,
                                    ebit::Scal* scal, hipStream_t st);
 hipError_t ebit_prof_flush(EbitProfiler* pr);
+int ebit_tail_lds_setup(void);
 int ebit_solve_stream(const ebit::FineOp* op, const EbitLevelHost* lv, int nlev, const EbitSolveBufs* B,
                       const double* b, double* x, int use_guess, const ebit_opts* o, hipStream_t st, int* iters,
                       int* vcyc, double* relres, double* bnorm, double* floor, hipError_t* herr);

@@ -162,19 +162,6 @@ __global__ void k_coarsest(CoarseOp<T> op, const T* __restrict__ b, T* __restric
 #define RB_PLANE (RB_PX * RB_PY)
 #define RB_THREADS 256
 
-// row of the fine (matrix-free) operator
-template <typename T, typename TB>
-struct FineRows {
-  FineOp op;
-  const TB* b;
-  __device__ const Dims& dims() const { return op.d; }
-  __device__ inline void row(int i, int j, int k, long long c, T& diag, T off[6], T& rhs) const {
-    T mass, rb = 0;
-    fine_row<T>(op, i, j, k, op.flags[c], diag, off, mass, rb);
-    rhs = (T)b[c];
-  }
-};
-
 // row of an explicit coarse level
 template <typename T>
 struct CoarseRows {
@@ -229,20 +216,21 @@ __device__ inline void rb_load_plane(const R& rows, int kk, int tx0, int ty0, co
   }
 }
 
-// update the cells of one colour in plane k over the local window [lo, hi)
-template <typename T, typename R>
-__device__ inline void rb_update_plane(const R& rows, int k, int tx0, int ty0, int color, int lo_x, int hi_x,
-                                       int lo_y, int hi_y, T* pm, T* p0, T* pp) {
+// update the cells of one colour of plane k on the tile (RING = 0) or on the
+// tile + 1 ring (RING = 1); threads walk only the cells of the colour
+template <typename T, int RING, typename R>
+__device__ inline void rb_update_plane(const R& rows, int k, int tx0, int ty0, int color, T* pm, T* p0, T* pp) {
+  constexpr int WX = RB_TX + 2 * RING, WY = RB_TY + 2 * RING, HX = WX / 2;
   const Dims& d = rows.dims();
   if (k < 0 || k >= d.n[2]) {
     if (!(d.per[2] && d.dim == 3)) return;
   }
   const int kw = (k % d.n[2] + d.n[2]) % d.n[2];
-  const int wx = hi_x - lo_x, wy = hi_y - lo_y;
-  for (int t = threadIdx.x; t < wx * wy; t += RB_THREADS) {
-    const int lx = lo_x + t % wx, ly = lo_y + t / wx;
-    const int i = tx0 + lx, j = ty0 + ly;
-    if (((i + j + k) & 1) != color) continue;
+  for (int t = threadIdx.x; t < HX * WY; t += RB_THREADS) {
+    const int ly = t / HX - RING;
+    const int j = ty0 + ly;
+    const int lx = 2 * (t % HX) - RING + ((color + tx0 - RING + j + k) & 1);
+    const int i = tx0 + lx;
     // cells outside the domain along a non-periodic axis are not updated
     int iw = i, jw = j;
     if (iw < 0 || iw >= d.n[0]) {
@@ -279,15 +267,15 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_fused(R rows, const T* __rest
     for (int k = z0 - 2; k <= z0 + 1; ++k) rb_load_plane<T>(rows, k, tx0, ty0, xin, xc, cd, slot(k));
     __syncthreads();
     // red on the tile + 1 ring of the two planes before the first black one
-    rb_update_plane<T>(rows, z0 - 1, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, slot(z0 - 2), slot(z0 - 1),
+    rb_update_plane<T, 1>(rows, z0 - 1, tx0, ty0, 0, slot(z0 - 2), slot(z0 - 1),
                        slot(z0));
     __syncthreads();
-    rb_update_plane<T>(rows, z0, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, slot(z0 - 1), slot(z0), slot(z0 + 1));
+    rb_update_plane<T, 1>(rows, z0, tx0, ty0, 0, slot(z0 - 1), slot(z0), slot(z0 + 1));
     __syncthreads();
   } else {
     rb_load_plane<T>(rows, 0, tx0, ty0, xin, xc, cd, buf[0]);
     __syncthreads();
-    rb_update_plane<T>(rows, 0, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, buf[1], buf[0], buf[2]);
+    rb_update_plane<T, 1>(rows, 0, tx0, ty0, 0, buf[1], buf[0], buf[2]);
     __syncthreads();
   }
   for (int k = z0; k < z1; ++k) {
@@ -295,10 +283,10 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_fused(R rows, const T* __rest
     if (zdim) {
       rb_load_plane<T>(rows, k + 2, tx0, ty0, xin, xc, cd, slot(k + 2));
       __syncthreads();
-      rb_update_plane<T>(rows, k + 1, tx0, ty0, 0, -1, RB_TX + 1, -1, RB_TY + 1, slot(k), slot(k + 1), slot(k + 2));
+      rb_update_plane<T, 1>(rows, k + 1, tx0, ty0, 0, slot(k), slot(k + 1), slot(k + 2));
       __syncthreads();
     }
-    rb_update_plane<T>(rows, k, tx0, ty0, 1, 0, RB_TX, 0, RB_TY, zdim ? slot(k - 1) : buf[1], p0,
+    rb_update_plane<T, 0>(rows, k, tx0, ty0, 1, zdim ? slot(k - 1) : buf[1], p0,
                        zdim ? slot(k + 1) : buf[2]);
     __syncthreads();
     for (int t = threadIdx.x; t < RB_TX * RB_TY; t += RB_THREADS) {
@@ -311,42 +299,336 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_fused(R rows, const T* __rest
 }
 
 // ---------------------------------------------------------------------------
+// Fine-level red-black sweep, software pipelined along z.
+//
+// Same ordering as k_rb_fused (red on the tile + 1 ring of plane k+1, then
+// black on the tile of plane k), but the right-hand side and the flag byte
+// are staged in LDS with the iterate, and the global loads of plane k+3 (x)
+// and k+2 (r, flags) are issued into registers before the two updates of
+// plane k, so their latency is hidden behind LDS work.  2D grids are one
+// plane: x, r and flags of the tile are loaded in a single phase.
+// ---------------------------------------------------------------------------
+template <int TX, int TY>
+struct FineTile {
+  static constexpr int PX = TX + 4, PY = TY + 4, PL = PX * PY;  // iterate: tile + 2-cell ring
+  static constexpr int QX = TX + 2, QY = TY + 2, QL = QX * QY;  // r, flags: tile + 1-cell ring
+  static constexpr int NX = (PL + RB_THREADS - 1) / RB_THREADS;
+  static constexpr int NQ = (QL + RB_THREADS - 1) / RB_THREADS;
+};
+
+// wrap index v along axis a; false if it lies outside a non-periodic domain
+__device__ inline bool wrap_axis(const Dims& d, int a, int& v) {
+  if (v >= 0 && v < d.n[a]) return true;
+  if (!d.per[a]) return false;
+  v = (v % d.n[a] + d.n[a]) % d.n[a];
+  return true;
+}
+
+template <typename T, int TX, int TY>
+__device__ inline void fine_load_x(const Dims& d, int kk, int tx0, int ty0, const T* __restrict__ xin,
+                                   const T* __restrict__ xc, const Dims& cd, T (&v)[FineTile<TX, TY>::NX]) {
+  using FT = FineTile<TX, TY>;
+  int k = kk;
+  const bool pz = wrap_axis(d, 2, k);
+#pragma unroll
+  for (int e = 0; e < FT::NX; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    T s = (T)0;
+    if (pz && t < FT::PL && (xin || xc)) {
+      int i = tx0 + t % FT::PX - 2, j = ty0 + t / FT::PX - 2;
+      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+        if (xin) s = xin[cell_index(d, i, j, k)];
+        if (xc) s += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
+      }
+    }
+    v[e] = s;
+  }
+}
+
+template <int TX, int TY>
+__device__ inline void fine_load_rf(const Dims& d, int kk, int tx0, int ty0, const double* __restrict__ rhs,
+                                    const uint8_t* __restrict__ flags, double (&r)[FineTile<TX, TY>::NQ],
+                                    uint8_t (&f)[FineTile<TX, TY>::NQ]) {
+  using FT = FineTile<TX, TY>;
+  int k = kk;
+  const bool pz = wrap_axis(d, 2, k);
+#pragma unroll
+  for (int e = 0; e < FT::NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    r[e] = 0.0;
+    f[e] = 0;
+    if (pz && t < FT::QL) {
+      int i = tx0 + t % FT::QX - 1, j = ty0 + t / FT::QX - 1;
+      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+        const long long c = cell_index(d, i, j, k);
+        r[e] = rhs[c];
+        f[e] = flags[c];
+      }
+    }
+  }
+}
+
+template <typename T, int TX, int TY>
+__device__ inline void fine_store(const T (&v)[FineTile<TX, TY>::NX], T* xs) {
+  using FT = FineTile<TX, TY>;
+#pragma unroll
+  for (int e = 0; e < FT::NX; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < FT::PL) xs[t] = v[e];
+  }
+}
+
+template <int TX, int TY>
+__device__ inline void fine_store_rf(const double (&r)[FineTile<TX, TY>::NQ], const uint8_t (&f)[FineTile<TX, TY>::NQ],
+                                     double* rs, uint8_t* fs) {
+  using FT = FineTile<TX, TY>;
+#pragma unroll
+  for (int e = 0; e < FT::NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < FT::QL) {
+      rs[t] = r[e];
+      fs[t] = f[e];
+    }
+  }
+}
+
+// Coefficients of a regular fine cell (no cut link, no wall face) of each
+// phase: A x = dg x_c - w sum_nb x_nb.
+template <typename T>
+struct RegularRow {
+  T w0, w1, inv0, inv1;  // per phase (0 vapour, 1 liquid)
+};
+
+template <typename T>
+__device__ inline RegularRow<T> regular_row(const FineOp& op) {
+  const T ih2 = (T)op.ih2;
+  T w[2], inv[2];
+  for (int ph = 0; ph < 2; ++ph) {
+    w[ph] = (T)op.coef[ph] * ih2;
+    T dg = (op.sys == EBIT_SYS_HEAT) ? (T)op.mass[ph] : (T)0;
+    for (int s = 0; s < 2 * op.d.dim; ++s) dg += w[ph];
+    inv[ph] = (T)1 / dg;
+  }
+  return RegularRow<T>{w[0], w[1], inv[0], inv[1]};
+}
+
+// Update the cells of one colour of plane k on the tile (RING = 0) or on the
+// tile + 1 ring (RING = 1) from LDS.  Threads walk only the cells of the
+// colour; regular cells take the per-phase constant row, cells with a cut
+// link or a wall face the full row of fine_row.
+template <typename T, int TX, int TY, int RING>
+__device__ inline void fine_update(const FineOp& op, const RegularRow<T>& rr, int k, int tx0, int ty0, int color,
+                                   const T* pm, T* p0, const T* pp, const double* rq, const uint8_t* fq) {
+  using FT = FineTile<TX, TY>;
+  constexpr int WX = TX + 2 * RING, WY = TY + 2 * RING, HX = WX / 2;
+  static_assert(WX % 2 == 0, "tile width must be even");
+  const Dims& d = op.d;
+  int kw = k;
+  if (!wrap_axis(d, 2, kw)) return;
+  const bool zwall = d.dim == 3 && !d.per[2] && (kw == 0 || kw == d.n[2] - 1);
+  for (int t = threadIdx.x; t < HX * WY; t += RB_THREADS) {
+    const int ly = t / HX - RING;
+    const int j = ty0 + ly;
+    const int lx = 2 * (t % HX) - RING + ((color + tx0 - RING + j + k) & 1);
+    const int i = tx0 + lx;
+    int iw = i, jw = j;
+    if (!wrap_axis(d, 0, iw) || !wrap_axis(d, 1, jw)) continue;
+    const int qq = (ly + 1) * FT::QX + (lx + 1);
+    const int q = (ly + 2) * FT::PX + (lx + 2);
+    const uint8_t f = fq[qq];
+    const bool wall = zwall || (!d.per[0] && (iw == 0 || iw == d.n[0] - 1)) ||
+                      (!d.per[1] && (jw == 0 || jw == d.n[1] - 1));
+    if (!(f & F_CUT) && !wall) {
+      const bool liq = (f & F_LIQ) != 0;
+      T xn = (p0[q - 1] + p0[q + 1]) + (p0[q - FT::PX] + p0[q + FT::PX]);
+      if (d.dim == 3) xn += pm[q] + pp[q];
+      p0[q] = ((T)rq[qq] + (liq ? rr.w1 : rr.w0) * xn) * (liq ? rr.inv1 : rr.inv0);
+    } else {
+      T diag, off[6], mass, rb = 0;
+      fine_row<T>(op, iw, jw, kw, f, diag, off, mass, rb);
+      T sum = (T)rq[qq] - off[0] * p0[q - 1] - off[1] * p0[q + 1];
+      sum -= off[2] * p0[q - FT::PX] + off[3] * p0[q + FT::PX];
+      if (d.dim == 3) sum -= off[4] * pm[q] + off[5] * pp[q];
+      p0[q] = sum / diag;
+    }
+  }
+}
+
+template <typename T, int TX, int TY>
+__device__ inline void fine_write(const Dims& d, int k, int tx0, int ty0, const T* p0, T* __restrict__ xout) {
+  using FT = FineTile<TX, TY>;
+  for (int t = threadIdx.x; t < TX * TY; t += RB_THREADS) {
+    const int lx = t % TX, ly = t / TX;
+    const int i = tx0 + lx, j = ty0 + ly;
+    if (i < d.n[0] && j < d.n[1]) xout[cell_index(d, i, j, k)] = p0[(ly + 2) * FT::PX + (lx + 2)];
+  }
+}
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_fine(FineOp op, const double* __restrict__ rhs,
+                                                        const T* __restrict__ xin, const T* __restrict__ xc, Dims cd,
+                                                        T* __restrict__ xout, int zchunk) {
+  using FT = FineTile<TX, TY>;
+  __shared__ T xs[4][FT::PL];
+  __shared__ double rs[2][FT::QL];
+  __shared__ uint8_t fs[2][FT::QL];
+  const Dims& d = op.d;
+  const RegularRow<T> rr = regular_row<T>(op);
+  const int tx0 = blockIdx.x * TX, ty0 = blockIdx.y * TY;
+  T xv[FT::NX];
+  double rv[FT::NQ];
+  uint8_t fv[FT::NQ];
+  if (d.dim < 3) {
+    fine_load_x<T, TX, TY>(d, 0, tx0, ty0, xin, xc, cd, xv);
+    fine_load_rf<TX, TY>(d, 0, tx0, ty0, rhs, op.flags, rv, fv);
+    fine_store<T, TX, TY>(xv, xs[0]);
+    fine_store_rf<TX, TY>(rv, fv, rs[0], fs[0]);
+    __syncthreads();
+    fine_update<T, TX, TY, 1>(op, rr, 0, tx0, ty0, 0, xs[0], xs[0], xs[0], rs[0], fs[0]);
+    __syncthreads();
+    fine_update<T, TX, TY, 0>(op, rr, 0, tx0, ty0, 1, xs[0], xs[0], xs[0], rs[0], fs[0]);
+    __syncthreads();
+    fine_write<T, TX, TY>(d, 0, tx0, ty0, xs[0], xout);
+    return;
+  }
+  // slots: x plane p in xs[p & 3], r / flags of plane p in rs[p & 1] (p may be negative)
+  const int z0 = blockIdx.z * zchunk;
+  const int z1 = min(z0 + zchunk, d.n[2]);
+  {
+    T xa[FT::NX], xb[FT::NX];
+    double ra[FT::NQ];
+    uint8_t fa[FT::NQ];
+    fine_load_x<T, TX, TY>(d, z0 - 2, tx0, ty0, xin, xc, cd, xv);
+    fine_load_x<T, TX, TY>(d, z0 - 1, tx0, ty0, xin, xc, cd, xa);
+    fine_load_x<T, TX, TY>(d, z0, tx0, ty0, xin, xc, cd, xb);
+    fine_load_rf<TX, TY>(d, z0 - 1, tx0, ty0, rhs, op.flags, rv, fv);
+    fine_load_rf<TX, TY>(d, z0, tx0, ty0, rhs, op.flags, ra, fa);
+    fine_store<T, TX, TY>(xv, xs[(z0 - 2) & 3]);
+    fine_store<T, TX, TY>(xa, xs[(z0 - 1) & 3]);
+    fine_store<T, TX, TY>(xb, xs[z0 & 3]);
+    fine_store_rf<TX, TY>(rv, fv, rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
+    fine_store_rf<TX, TY>(ra, fa, rs[z0 & 1], fs[z0 & 1]);
+    fine_load_x<T, TX, TY>(d, z0 + 1, tx0, ty0, xin, xc, cd, xv);
+    fine_store<T, TX, TY>(xv, xs[(z0 + 1) & 3]);
+  }
+  __syncthreads();
+  fine_update<T, TX, TY, 1>(op, rr, z0 - 1, tx0, ty0, 0, xs[(z0 - 2) & 3], xs[(z0 - 1) & 3], xs[z0 & 3],
+                         rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
+  __syncthreads();
+  fine_update<T, TX, TY, 1>(op, rr, z0, tx0, ty0, 0, xs[(z0 - 1) & 3], xs[z0 & 3], xs[(z0 + 1) & 3], rs[z0 & 1],
+                         fs[z0 & 1]);
+  fine_load_x<T, TX, TY>(d, z0 + 2, tx0, ty0, xin, xc, cd, xv);
+  fine_load_rf<TX, TY>(d, z0 + 1, tx0, ty0, rhs, op.flags, rv, fv);
+  __syncthreads();
+  for (int k = z0; k < z1; ++k) {
+    // plane k+2's iterate replaces plane k-2's, plane k+1's r / flags replace plane k-1's
+    fine_store<T, TX, TY>(xv, xs[(k + 2) & 3]);
+    fine_store_rf<TX, TY>(rv, fv, rs[(k + 1) & 1], fs[(k + 1) & 1]);
+    __syncthreads();
+    if (k + 1 < z1) {
+      fine_load_x<T, TX, TY>(d, k + 3, tx0, ty0, xin, xc, cd, xv);
+      fine_load_rf<TX, TY>(d, k + 2, tx0, ty0, rhs, op.flags, rv, fv);
+    }
+    fine_update<T, TX, TY, 1>(op, rr, k + 1, tx0, ty0, 0, xs[k & 3], xs[(k + 1) & 3], xs[(k + 2) & 3], rs[(k + 1) & 1],
+                           fs[(k + 1) & 1]);
+    __syncthreads();
+    fine_update<T, TX, TY, 0>(op, rr, k, tx0, ty0, 1, xs[(k - 1) & 3], xs[k & 3], xs[(k + 1) & 3], rs[k & 1],
+                           fs[k & 1]);
+    __syncthreads();
+    fine_write<T, TX, TY>(d, k, tx0, ty0, xs[k & 3], xout);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // tail of the V-cycle: every level small enough to sit in LDS, in one
-// work-group (no launch per smoothing sweep on the coarse levels)
+// work-group (no launch per smoothing sweep on the coarse levels).  The
+// coefficients of all tail levels are staged into LDS once, at the start.
 // ---------------------------------------------------------------------------
 #define EBIT_TAIL_MAX 16
 #define EBIT_TAIL_THREADS 1024
+
+// LDS block of one tail level: x, b, diag, off[0 .. dim-1], N elements each.
+struct TailLevel {
+  Dims d;
+  int base;  // element offset of x
+};
+
+__host__ __device__ inline long long tail_level_elems(const Dims& d) { return (3 + d.dim) * d.N; }
 
 template <typename T>
 struct TailArgs {
   int nl;  // levels in the tail; the last one is the coarsest
   int nu1, nu2;
-  Dims d[EBIT_TAIL_MAX];
+  TailLevel L[EBIT_TAIL_MAX];
   const T* diag[EBIT_TAIL_MAX];
   const T* off[EBIT_TAIL_MAX][3];
-  int base[EBIT_TAIL_MAX];  // LDS element offset of the level's x (b follows)
-  const T* bg;              // right-hand side of the top tail level
-  T* xg;                    // its correction (output)
+  const T* bg;  // right-hand side of the top tail level
+  T* xg;        // its correction (output)
 };
 
+// The 1024 threads of the tail form 32 rows of 32: thread row ty takes grid
+// rows (j, k) = ty, ty + 32, ... and lane tx the cells i = 2 tx + parity,
+// + 64, ... of one colour (or every cell for the grid transfers).
+struct TailRow {
+  int j, k;
+  __device__ TailRow(const Dims& d, int r) : j(r % d.n[1]), k(r / d.n[1]) {}
+  __device__ void next(const Dims& d) {
+    j += 32;
+    while (j >= d.n[1]) {
+      j -= d.n[1];
+      ++k;
+    }
+  }
+};
+
+// sum over the neighbours of cell q = (i, j, k) of coupling x neighbour; the
+// same neighbour set as neighbour() (periodic wrap, none across a wall)
 template <typename T>
-__device__ inline CoarseOp<T> tail_op(const TailArgs<T>& a, int l) {
-  CoarseOp<T> c;
-  c.d = a.d[l];
-  c.diag = a.diag[l];
-  for (int q = 0; q < 3; ++q) c.off[q] = a.off[l][q];
-  c.mass = nullptr;
-  return c;
+__device__ inline T tail_offsum(const T* x, const Dims& d, int i, int j, int k, int q) {
+  const int N = (int)d.N;
+  T s = 0;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const int s1 = n0, s2 = n0 * n1;
+  {
+    const T* o = x + 3 * N;
+    if (i + 1 < n0) s += o[q] * x[q + 1];
+    else if (d.per[0]) s += o[q] * x[q + 1 - n0];
+    if (i > 0) s += o[q - 1] * x[q - 1];
+    else if (d.per[0]) s += o[q + n0 - 1] * x[q + n0 - 1];
+  }
+  if (d.dim >= 2) {
+    const T* o = x + 4 * N;
+    if (j + 1 < n1) s += o[q] * x[q + s1];
+    else if (d.per[1]) s += o[q] * x[q + s1 - s2];
+    if (j > 0) s += o[q - s1] * x[q - s1];
+    else if (d.per[1]) s += o[q + s2 - s1] * x[q + s2 - s1];
+  }
+  if (d.dim == 3) {
+    const T* o = x + 5 * N;
+    if (k + 1 < n2) s += o[q] * x[q + s2];
+    else if (d.per[2]) s += o[q] * x[q + s2 - N];
+    if (k > 0) s += o[q - s2] * x[q - s2];
+    else if (d.per[2]) s += o[q + N - s2] * x[q + N - s2];
+  }
+  return s;
 }
 
 template <typename T>
-__device__ inline void tail_sweep(const CoarseOp<T>& c, const T* b, T* x, int color) {
-  const long long nh = (long long)((c.d.n[0] + 1) >> 1) * c.d.n[1] * c.d.n[2];
-  for (long long t = threadIdx.x; t < nh; t += blockDim.x) {
-    int i, j, k;
-    if (!red_black_cell(c.d, t, color, i, j, k)) continue;
-    const long long q = cell_index(c.d, i, j, k);
-    x[q] = (b[q] - coarse_offsum<T>(c, i, j, k, q, x)) / c.diag[q];
+__device__ inline void tail_sweep(T* sm, const TailLevel& L, int color) {
+  const Dims& d = L.d;
+  const int N = (int)d.N;
+  T* x = sm + L.base;
+  const T* b = x + N;
+  const T* dg = x + 2 * N;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int rows = d.n[1] * d.n[2];
+  TailRow r(d, ty);
+  for (int row = ty; row < rows; row += 32, r.next(d)) {
+    const int base = row * d.n[0];
+    for (int i = 2 * tx + ((r.j + r.k + color) & 1); i < d.n[0]; i += 64) {
+      const int q = base + i;
+      x[q] = (b[q] - tail_offsum<T>(x, d, i, r.j, r.k, q)) / dg[q];
+    }
   }
 }
 
@@ -355,92 +637,113 @@ __global__ __launch_bounds__(EBIT_TAIL_THREADS) void k_tail(TailArgs<T> a) {
   extern __shared__ __align__(16) unsigned char tail_smem[];
   T* sm = reinterpret_cast<T*>(tail_smem);
   const int tid = threadIdx.x, nth = blockDim.x;
-  {
-    const long long N = a.d[0].N;
-    T* x = sm + a.base[0];
-    T* b = x + N;
-    for (long long q = tid; q < N; q += nth) {
-      b[q] = a.bg[q];
-      x[q] = (T)0;
+  const int tx = tid & 31, ty = tid >> 5;
+  for (int l = 0; l < a.nl; ++l) {
+    const TailLevel& L = a.L[l];
+    const int N = (int)L.d.N;
+    T* x = sm + L.base;
+    const T* dg = a.diag[l];
+    const T* o0 = a.off[l][0];
+    const T* o1 = a.off[l][1];
+    const T* o2 = a.off[l][2];
+    for (int q = tid; q < N; q += nth) {
+      x[2 * N + q] = dg[q];
+      x[3 * N + q] = o0[q];
+      if (L.d.dim >= 2) x[4 * N + q] = o1[q];
+      if (L.d.dim == 3) x[5 * N + q] = o2[q];
+      if (l == 0) {
+        x[N + q] = a.bg[q];
+        x[q] = (T)0;
+      }
     }
   }
   __syncthreads();
   for (int l = 0; l < a.nl - 1; ++l) {
-    const CoarseOp<T> c = tail_op(a, l);
-    T* x = sm + a.base[l];
-    T* b = x + c.d.N;
+    const TailLevel& L = a.L[l];
+    const Dims& d = L.d;
+    const int N = (int)d.N;
+    T* x = sm + L.base;
+    const T* b = x + N;
+    const T* dg = x + 2 * N;
     for (int s = 0; s < a.nu1; ++s)
       for (int col = 0; col < 2; ++col) {
-        tail_sweep(c, b, x, col);
+        tail_sweep(sm, L, col);
         __syncthreads();
       }
-    const Dims cd = a.d[l + 1];
-    T* xc = sm + a.base[l + 1];
+    // residual of the 2^d children, summed into the coarse right-hand side
+    const TailLevel& C = a.L[l + 1];
+    const Dims& cd = C.d;
+    T* xc = sm + C.base;
     T* bc = xc + cd.N;
-    for (long long I = tid; I < cd.N; I += nth) {
-      int ci, cj, ck;
-      cell_ijk(cd, I, ci, cj, ck);
-      T sum = 0;
-      for (int dk = 0; dk < 2; ++dk) {
-        const int k = 2 * ck + dk;
-        if (k >= c.d.n[2]) break;
-        for (int dj = 0; dj < 2; ++dj) {
-          const int j = 2 * cj + dj;
-          if (j >= c.d.n[1]) break;
-          for (int di = 0; di < 2; ++di) {
-            const int i = 2 * ci + di;
-            if (i >= c.d.n[0]) break;
-            const long long q = cell_index(c.d, i, j, k);
-            sum += b[q] - c.diag[q] * x[q] - coarse_offsum<T>(c, i, j, k, q, x);
+    const int crows = cd.n[1] * cd.n[2];
+    TailRow r(cd, ty);
+    for (int row = ty; row < crows; row += 32, r.next(cd)) {
+      for (int ci = tx; ci < cd.n[0]; ci += 32) {
+        T sum = 0;
+        for (int dk = 0; dk < 2; ++dk) {
+          const int k = 2 * r.k + dk;
+          if (k >= d.n[2]) break;
+          for (int dj = 0; dj < 2; ++dj) {
+            const int j = 2 * r.j + dj;
+            if (j >= d.n[1]) break;
+            for (int di = 0; di < 2; ++di) {
+              const int i = 2 * ci + di;
+              if (i >= d.n[0]) break;
+              const int q = i + d.n[0] * (j + d.n[1] * k);
+              sum += b[q] - dg[q] * x[q] - tail_offsum<T>(x, d, i, j, k, q);
+            }
           }
         }
+        const int I = row * cd.n[0] + ci;
+        bc[I] = sum;
+        xc[I] = (T)0;
       }
-      bc[I] = sum;
-      xc[I] = (T)0;
     }
     __syncthreads();
   }
   {
     // coarsest level: symmetric Gauss-Seidel by one thread (exact for one cell)
-    const int l = a.nl - 1;
-    const CoarseOp<T> c = tail_op(a, l);
-    T* x = sm + a.base[l];
-    T* b = x + c.d.N;
+    const TailLevel& L = a.L[a.nl - 1];
+    const Dims& d = L.d;
+    const int N = (int)d.N;
+    T* x = sm + L.base;
+    const T* b = x + N;
+    const T* dg = x + 2 * N;
     if (tid == 0) {
-      const int sweeps = c.d.N == 1 ? 1 : 50;
+      const int sweeps = N == 1 ? 1 : 50;
       for (int s = 0; s < sweeps; ++s)
         for (int dir = 0; dir < 2; ++dir)
-          for (long long qq = 0; qq < c.d.N; ++qq) {
-            const long long q = dir ? (c.d.N - 1 - qq) : qq;
-            int i, j, k;
-            cell_ijk(c.d, q, i, j, k);
-            x[q] = (b[q] - coarse_offsum<T>(c, i, j, k, q, x)) / c.diag[q];
+          for (int qq = 0; qq < N; ++qq) {
+            const int q = dir ? (N - 1 - qq) : qq;
+            const int i = q % d.n[0], j = (q / d.n[0]) % d.n[1], k = q / (d.n[0] * d.n[1]);
+            x[q] = (b[q] - tail_offsum<T>(x, d, i, j, k, q)) / dg[q];
           }
     }
     __syncthreads();
   }
   for (int l = a.nl - 2; l >= 0; --l) {
-    const CoarseOp<T> c = tail_op(a, l);
-    T* x = sm + a.base[l];
-    T* b = x + c.d.N;
-    const Dims cd = a.d[l + 1];
-    const T* xc = sm + a.base[l + 1];
-    for (long long q = tid; q < c.d.N; q += nth) {
-      int i, j, k;
-      cell_ijk(c.d, q, i, j, k);
-      x[q] += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
+    const TailLevel& L = a.L[l];
+    const Dims& d = L.d;
+    T* x = sm + L.base;
+    const TailLevel& C = a.L[l + 1];
+    const T* xc = sm + C.base;
+    const int rows = d.n[1] * d.n[2];
+    TailRow r(d, ty);
+    for (int row = ty; row < rows; row += 32, r.next(d)) {
+      const int cb = C.d.n[0] * ((r.j >> 1) + C.d.n[1] * (r.k >> 1));
+      for (int i = tx; i < d.n[0]; i += 32) x[row * d.n[0] + i] += xc[cb + (i >> 1)];
     }
     __syncthreads();
     for (int s = 0; s < a.nu2; ++s)
       for (int col = 1; col >= 0; --col) {
-        tail_sweep(c, b, x, col);
+        tail_sweep(sm, L, col);
         __syncthreads();
       }
   }
   {
-    const long long N = a.d[0].N;
-    const T* x = sm + a.base[0];
-    for (long long q = tid; q < N; q += nth) a.xg[q] = x[q];
+    const int N = (int)a.L[0].d.N;
+    const T* x = sm + a.L[0].base;
+    for (int q = tid; q < N; q += nth) a.xg[q] = x[q];
   }
 }
 
@@ -886,21 +1189,17 @@ double* lvb<double>(const EbitLevelHost& L) { return L.b64; }
 template <>
 float* lvb<float>(const EbitLevelHost& L) { return L.b32; }
 
-// One V(nu1, nu2) cycle on A z = r with z = 0 initially; fine level matrix-free.
-// LDS the tail kernel may use (bytes); the hierarchy from level l down fits
-// if sum_m 2 N_m sizeof(T) stays below it.
-#define EBIT_TAIL_LDS (64 * 1024)
-
 // First coarse level (>= 1) from which the tail kernel takes over: the
-// remaining levels must fit its LDS and hold at most tail_cells cells on top.
+// remaining levels (x, b and coefficients) must fit lds_bytes of LDS and the
+// top one hold at most tail_cells cells.
 template <typename T>
-static int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells) {
+static int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells, int lds_bytes) {
   if (tail_cells <= 0) return nlev;
   long long tot = 0;
   int lt = nlev;
   for (int l = nlev - 1; l >= 1; --l) {
-    tot += 2 * lv[l].d.N;
-    if (tot * (long long)sizeof(T) > EBIT_TAIL_LDS || lv[l].d.N > tail_cells || nlev - l > EBIT_TAIL_MAX) break;
+    tot += tail_level_elems(lv[l].d);
+    if (tot * (long long)sizeof(T) > lds_bytes || lv[l].d.N > tail_cells || nlev - l > EBIT_TAIL_MAX) break;
     lt = l;
   }
   return lt;
@@ -930,43 +1229,72 @@ static inline int rb_zchunk(const Dims& d) {
 // S = nu1 + nu2 fused sweeps on one level; sweep s (1-based) writes X when
 // S - s is even and Xb otherwise, so the last one lands in X.  The first
 // pre-smoothing sweep starts from zero; the first post-smoothing sweep adds
-// the coarse correction xc on load.
-template <typename T, typename R>
-static void smooth_pre(const R& rows, int nu1, int S, T* X, T* Xb, hipStream_t st, EbitProfiler* pf, int kc) {
-  const Dims& d = rows.op.d;
-  const int zc = rb_zchunk(d);
+// the coarse correction xc on load.  launch(in, xc, out) issues one sweep.
+template <typename T, typename L>
+static void smooth_pre(const L& launch, int nu1, int S, T* X, T* Xb, hipStream_t st, EbitProfiler* pf, int kc) {
   const T* in = nullptr;
   for (int s = 1; s <= nu1; ++s) {
     T* out = ((S - s) % 2 == 0) ? X : Xb;
     ProfScope ps(pf, kc, st);
-    hipLaunchKernelGGL((k_rb_fused<T, R>), rb_grid(d, zc), dim3(RB_THREADS), 0, st, rows, in, (const T*)nullptr, d,
-                       out, zc);
+    launch(in, (const T*)nullptr, out);
     in = out;
   }
 }
-template <typename T, typename R>
-static void smooth_post(const R& rows, int nu1, int S, T* X, T* Xb, const T* xc, const Dims& cd, hipStream_t st,
-                        EbitProfiler* pf, int kc) {
-  const Dims& d = rows.op.d;
-  const int zc = rb_zchunk(d);
+template <typename T, typename L>
+static void smooth_post(const L& launch, int nu1, int S, T* X, T* Xb, const T* xc, hipStream_t st, EbitProfiler* pf,
+                        int kc) {
   const T* in = ((S - nu1) % 2 == 0) ? X : Xb;
   for (int s = nu1 + 1; s <= S; ++s) {
     T* out = ((S - s) % 2 == 0) ? X : Xb;
     ProfScope ps(pf, kc, st);
-    hipLaunchKernelGGL((k_rb_fused<T, R>), rb_grid(d, zc), dim3(RB_THREADS), 0, st, rows, in,
-                       s == nu1 + 1 ? xc : (const T*)nullptr, cd, out, zc);
+    launch(in, s == nu1 + 1 ? xc : (const T*)nullptr, out);
     in = out;
   }
 }
+
+// fine-level sweep launcher: 64 x 8 tiles marching along z in 3D, 64 x 4
+// tiles in 2D (twice the work-groups for the single plane)
+template <typename T>
+struct FineSweep {
+  FineOp op;
+  const double* r;
+  Dims cd;
+  hipStream_t st;
+  void operator()(const T* in, const T* xc, T* out) const {
+    const Dims& d = op.d;
+    if (d.dim == 3) {
+      const int zc = rb_zchunk(d);
+      const dim3 g((unsigned)((d.n[0] + 63) / 64), (unsigned)((d.n[1] + 7) / 8), (unsigned)((d.n[2] + zc - 1) / zc));
+      hipLaunchKernelGGL((k_rb_fine<T, 64, 8>), g, dim3(RB_THREADS), 0, st, op, r, in, xc, cd, out, zc);
+    } else {
+      const dim3 g((unsigned)((d.n[0] + 63) / 64), (unsigned)((d.n[1] + 3) / 4), 1);
+      hipLaunchKernelGGL((k_rb_fine<T, 64, 4>), g, dim3(RB_THREADS), 0, st, op, r, in, xc, cd, out, 1);
+    }
+  }
+};
+
+// explicit coarse-level sweep launcher
+template <typename T>
+struct CoarseSweep {
+  CoarseRows<T> rows;
+  Dims cd;
+  hipStream_t st;
+  void operator()(const T* in, const T* xc, T* out) const {
+    const Dims& d = rows.op.d;
+    const int zc = rb_zchunk(d);
+    hipLaunchKernelGGL((k_rb_fused<T, CoarseRows<T>>), rb_grid(d, zc), dim3(RB_THREADS), 0, st, rows, in, xc, cd,
+                       out, zc);
+  }
+};
 
 // One V(nu1, nu2) cycle on A z = r (zero initial guess); the fine level is
 // matrix-free, levels 1 .. lt-1 explicit, levels lt .. in the tail kernel.
 template <typename T>
 static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, const double* r, T* z, T* zb,
-                         int nu1, int nu2, int tail_cells, hipStream_t st, EbitProfiler* pf) {
+                         int nu1, int nu2, int tail_cells, int tail_lds, hipStream_t st, EbitProfiler* pf) {
   const int sys = op.sys;
   const int S = nu1 + nu2;
-  FineRows<T, double> fine{op, r};
+  const FineSweep<T> fine{op, r, nlev > 1 ? lv[1].d : op.d, st};
   if (nlev == 1) {
     smooth_pre<T>(fine, S, S, z, zb, st, pf, EBIT_KC_FINE_SMOOTH);
     return hipGetLastError();
@@ -980,11 +1308,13 @@ static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, co
                        zpre, lv[1].d, lvb<T>(lv[1]), lvx<T>(lv[1]));
   }
   // first level whose whole remaining hierarchy fits the tail kernel's LDS
-  const int lt = tail_start<T>(lv, nlev, tail_cells);
+  const int lt = tail_start<T>(lv, nlev, tail_cells, tail_lds);
   for (int l = 1; l < lt; ++l) {
-    CoarseRows<T> rows{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])};
-    smooth_pre<T>(rows, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), st, nullptr, 0);
+    const CoarseRows<T> rows{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])};
+    const CoarseSweep<T> sw{rows, lv[l + 1].d, st};
+    smooth_pre<T>(sw, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), st, pf, EBIT_KC_COARSE);
     const T* xpre = ((S - nu1) % 2 == 0) ? lvx<T>(lv[l]) : lvxb<T>(lv[l]);
+    ProfScope ps(pf, EBIT_KC_COARSE, st);
     hipLaunchKernelGGL(k_coarse_resid_restrict<T>, dim3(nblk(lv[l + 1].d.N)), dim3(EBIT_BLOCK), 0, st, rows.op,
                        (const T*)lvb<T>(lv[l]), xpre, lv[l + 1].d, lvb<T>(lv[l + 1]), lvx<T>(lv[l + 1]));
   }
@@ -993,18 +1323,19 @@ static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, co
     ta.nl = nlev - lt;
     ta.nu1 = nu1;
     ta.nu2 = nu2;
-    int off = 0;
+    long long off = 0;
     for (int m = 0; m < ta.nl; ++m) {
       const EbitLevelHost& L = lv[lt + m];
-      ta.d[m] = L.d;
-      CoarseOp<T> c = coarse_op<T>(L, sys);
+      ta.L[m].d = L.d;
+      ta.L[m].base = (int)off;
+      const CoarseOp<T> c = coarse_op<T>(L, sys);
       ta.diag[m] = c.diag;
       for (int q = 0; q < 3; ++q) ta.off[m][q] = c.off[q];
-      ta.base[m] = off;
-      off += (int)(2 * L.d.N);
+      off += tail_level_elems(L.d);
     }
     ta.bg = lvb<T>(lv[lt]);
     ta.xg = lvx<T>(lv[lt]);
+    ProfScope ps(pf, EBIT_KC_TAIL, st);
     hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(EBIT_TAIL_THREADS), (size_t)off * sizeof(T), st, ta);
   } else {
     CoarseOp<T> c = coarse_op<T>(lv[nlev - 1], sys);
@@ -1013,11 +1344,10 @@ static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, co
   }
   // ascend: the first post-smoothing sweep of each level adds the correction
   for (int l = lt - 1; l >= 1; --l) {
-    CoarseRows<T> rows{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])};
-    smooth_post<T>(rows, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), (const T*)lvx<T>(lv[l + 1]), lv[l + 1].d, st,
-                   nullptr, 0);
+    const CoarseSweep<T> sw{CoarseRows<T>{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])}, lv[l + 1].d, st};
+    smooth_post<T>(sw, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), (const T*)lvx<T>(lv[l + 1]), st, pf, EBIT_KC_COARSE);
   }
-  smooth_post<T>(fine, nu1, S, z, zb, (const T*)lvx<T>(lv[1]), lv[1].d, st, pf, EBIT_KC_FINE_SMOOTH);
+  smooth_post<T>(fine, nu1, S, z, zb, (const T*)lvx<T>(lv[1]), st, pf, EBIT_KC_FINE_SMOOTH);
   return hipGetLastError();
 }
 
@@ -1031,6 +1361,25 @@ hipError_t ebit_launch_apply(const FineOp* op, const double* x, double* y, hipSt
 hipError_t ebit_launch_heat_rhs(const FineOp* op, const double* Ts, double* b, hipStream_t st) {
   hipLaunchKernelGGL(k_heat_rhs, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, *op, Ts, b);
   return hipGetLastError();
+}
+
+// LDS the tail kernel may use: the device's per-work-group maximum (raising
+// the kernel's dynamic-LDS limit above 64 KiB where the device allows it).
+int ebit_tail_lds_setup(void) {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 64 * 1024;
+  if (v > 64 * 1024) {
+    if (hipFuncSetAttribute((const void*)ebit::k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)ebit::k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      return 64 * 1024;
+    }
+  }
+  return v;
 }
 
 hipError_t ebit_launch_finalize_max(const double* partial, int nb, Scal* sc, hipStream_t st) {
@@ -1119,7 +1468,7 @@ static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const Eb
   double last_true = rr;  // last recomputed residual (squared)
   int at_floor = 0;
   while (it < o->max_iters) {
-    CK(vcycle<T>(op, lv, nlev, B->r, z, zbuf2<T>(B), o->nu1, o->nu2, o->tail_cells, st, B->prof));
+    CK(vcycle<T>(op, lv, nlev, B->r, z, zbuf2<T>(B), o->nu1, o->nu2, o->tail_cells, B->tail_lds, st, B->prof));
     ++*vcyc;
     // defect correction = the same loop with beta = 0: x += alpha V(r) with the
     // energy-optimal step alpha = (r.z)/(z.Az), so it contracts for any SPD A

@@ -94,7 +94,7 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_last_error", "ebit_build_coeffs", "ebit_heat_solve", "ebit_mass_flux", "ebit_project",
             "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_project_rhs", "ebit_levels",
             "ebit_profile", "ebit_profile_read"]
-KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_FINE_PROLONG, KC_OUTER_APPLY, KC_OUTER_UPDATE = range(5)
+KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 
 
 class EbitError(RuntimeError):
