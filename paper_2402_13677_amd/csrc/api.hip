@@ -29,6 +29,9 @@ struct ebit_ctx {
   FineOp op[2];
   hipEvent_t ev0, ev1;
   EbitProfiler* prof;
+  EbitPlan* plan;      // solve plan of this one case
+  char* plan_mem;
+  size_t plan_bytes;
   hipError_t herr;
   char msg[512];
 };
@@ -222,8 +225,12 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
     lv[l].x32b = cv.take<float>(n);
     lv[l].b32 = cv.take<float>(n);
   }
+  const size_t plan_bytes = ebit_plan_device_bytes(1, o ? o->precision : EBIT_FP64);
+  char* plan_mem = cv.take<char>(plan_bytes);
   const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;
   if (ctx) {
+    ctx->plan_mem = plan_mem;
+    ctx->plan_bytes = plan_bytes;
     ctx->fd = fd;
     ctx->flags = flags;
     for (int a = 0; a < 3; ++a) ctx->th[a] = th[a];
@@ -299,23 +306,28 @@ ebit_status check_ready(ebit_ctx* c) {
   return EBIT_OK;
 }
 
-ebit_status run_solve(ebit_ctx* c, int sys, double* x, int use_guess, ebit_stats* st) {
-  int iters = 0, vcyc = 0;
-  double relres = 0, bnorm = 0, floor = 0;
-  hipError_t herr = hipSuccess;
-  const int rc = ebit_solve_stream(&c->op[sys], c->lv, c->nlev, &c->B, c->bvec, x, use_guess, &c->opts, c->st,
-                                   &iters, &vcyc, &relres, &bnorm, &floor, &herr);
-  if (rc < 0) return hip_fail(c, herr, "solve");
+ebit_status solve_status(const EbitSolveOut& r, ebit_stats* st) {
   if (st) {
-    st->iters = iters;
-    st->vcycles = vcyc;
-    st->rel_res = relres;
-    st->bnorm = bnorm;
-    st->res_floor = floor;
+    st->iters = r.iters;
+    st->vcycles = r.iters;
+    st->rel_res = r.rel_res;
+    st->bnorm = r.bnorm;
+    st->res_floor = r.res_floor;
   }
-  if (rc == 1) return fail(c, EBIT_ENOCONV, "no convergence within max_iters");
-  if (rc == 2) return fail(c, EBIT_ENAN, "NaN or Inf in a residual norm");
+  if (r.status == 1) return EBIT_ENOCONV;
+  if (r.status == 2) return EBIT_ENAN;
   return EBIT_OK;
+}
+
+ebit_status run_solve(ebit_ctx* c, int sys, double* x, int use_guess, ebit_stats* st) {
+  EbitSolveOut r;
+  double* xs[1] = {x};
+  const hipError_t e = ebit_plan_solve(c->plan, sys, xs, use_guess, c->st, c->prof, &r);
+  if (e != hipSuccess) return hip_fail(c, e, "solve");
+  const ebit_status s = solve_status(r, st);
+  if (s == EBIT_ENOCONV) return fail(c, s, "no convergence within max_iters");
+  if (s == EBIT_ENAN) return fail(c, s, "NaN or Inf in a residual norm");
+  return s;
 }
 
 void stats_init(ebit_stats* s) {
@@ -391,12 +403,21 @@ ebit_status ebit_create(ebit_ctx** out, const ebit_grid* g, const ebit_props* p,
     delete c;
     return EBIT_EHIP;
   }
+  const EbitPlanCase pc{c->lv, c->nlev, c->op, c->B, c->bvec};
+  if (ebit_plan_create(&c->plan, 1, &pc, &c->opts, c->B.tail_lds, c->plan_mem, c->plan_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(c->ev0);
+    (void)hipEventDestroy(c->ev1);
+    delete c;
+    return EBIT_EHIP;
+  }
   *out = c;
   return EBIT_OK;
 }
 
 ebit_status ebit_destroy(ebit_ctx* c) {
   if (!c) return EBIT_EINVAL;
+  ebit_plan_destroy(c->plan);
   (void)hipEventDestroy(c->ev0);
   (void)hipEventDestroy(c->ev1);
   if (c->prof) {

@@ -28,7 +28,8 @@ struct Scal {
   double red[7];
   int err;
   int fallbacks;
-  int pad[2];
+  int iters;      // outer iterations taken (solves)
+  int pad;
 };
 
 // Geometry of one grid level.
@@ -274,7 +275,36 @@ hipError_t ebit_launch_face_update(const ebit::Dims* d, double h, const double r
                                    ebit::Scal* scal, hipStream_t st);
 hipError_t ebit_prof_flush(EbitProfiler* pr);
 int ebit_tail_lds_setup(void);
-int ebit_solve_stream(const ebit::FineOp* op, const EbitLevelHost* lv, int nlev, const EbitSolveBufs* B,
-                      const double* b, double* x, int use_guess, const ebit_opts* o, hipStream_t st, int* iters,
-                      int* vcyc, double* relres, double* bnorm, double* floor, hipError_t* herr);
+}
+
+// One case as a solve plan sees it: its hierarchy, both fine operators
+// (read at every solve, so rebuilt coefficients are picked up), its work
+// vectors and the right-hand-side buffer the solves read.
+struct EbitPlanCase {
+  const EbitLevelHost* lv;
+  int nlev;
+  const ebit::FineOp* op;  // [2]: EBIT_SYS_HEAT, EBIT_SYS_PRESSURE
+  EbitSolveBufs B;
+  const double* b;
+};
+
+// Result of one case's solve: status 0 converged, 1 not converged
+// (max_iters, or stagnation above the rounding floor), 2 NaN/Inf.
+struct EbitSolveOut {
+  int status;
+  int iters;
+  double rel_res, bnorm, res_floor;
+};
+
+// A solve plan: device tables and work lists of a batch of cases (carved
+// from caller memory of ebit_plan_device_bytes()), the graphs of its
+// iteration blocks and its own stream.
+struct EbitPlan;
+extern "C" {
+size_t ebit_plan_device_bytes(int ncases, int precision);
+hipError_t ebit_plan_create(EbitPlan** out, int ncases, const EbitPlanCase* cases, const ebit_opts* o, int tail_lds,
+                            void* mem, size_t bytes);
+void ebit_plan_destroy(EbitPlan* p);
+hipError_t ebit_plan_solve(EbitPlan* p, int sys, double* const* x, int use_guess, hipStream_t ust, EbitProfiler* pf,
+                           EbitSolveOut* out);
 }

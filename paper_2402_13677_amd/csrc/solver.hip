@@ -8,6 +8,13 @@
 // symmetric and scales like a re-discretisation on the coarse grid.
 // Smoother: red-black Gauss-Seidel (red then black before the correction,
 // black then red after, so the V-cycle is a symmetric preconditioner).
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <utility>
+#include <vector>
+
 #include "ebit_internal.h"
 
 namespace ebit {
@@ -53,33 +60,6 @@ __device__ inline T fine_residual_at(const FineOp& op, int i, int j, int k, long
   return s;
 }
 
-// Residual of the 2^d children of every coarse cell, summed (= P^T r); also
-// clears the coarse iterate.
-template <typename T, typename TB>
-__global__ void k_fine_resid_restrict(FineOp op, const TB* __restrict__ b, const T* __restrict__ x,
-                                      Dims cd, T* __restrict__ bc, T* __restrict__ xc) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= cd.N) return;
-  int ci, cj, ck;
-  cell_ijk(cd, I, ci, cj, ck);
-  T sum = 0;
-  for (int dk = 0; dk < 2; ++dk) {
-    const int k = 2 * ck + dk;
-    if (k >= op.d.n[2]) break;
-    for (int dj = 0; dj < 2; ++dj) {
-      const int j = 2 * cj + dj;
-      if (j >= op.d.n[1]) break;
-      for (int di = 0; di < 2; ++di) {
-        const int i = 2 * ci + di;
-        if (i >= op.d.n[0]) break;
-        sum += fine_residual_at<T, TB>(op, i, j, k, cell_index(op.d, i, j, k), b, x);
-      }
-    }
-  }
-  bc[I] = sum;
-  xc[I] = (T)0;
-}
-
 // ---------------------------------------------------------------------------
 // coarse levels (explicit symmetric coefficients)
 // ---------------------------------------------------------------------------
@@ -95,49 +75,6 @@ __device__ inline T coarse_offsum(const CoarseOp<T>& op, int i, int j, int k, lo
     }
   }
   return s;
-}
-
-template <typename T>
-__global__ void k_coarse_resid_restrict(CoarseOp<T> op, const T* __restrict__ b, const T* __restrict__ x,
-                                        Dims cd, T* __restrict__ bc, T* __restrict__ xc) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= cd.N) return;
-  int ci, cj, ck;
-  cell_ijk(cd, I, ci, cj, ck);
-  T sum = 0;
-  for (int dk = 0; dk < 2; ++dk) {
-    const int k = 2 * ck + dk;
-    if (k >= op.d.n[2]) break;
-    for (int dj = 0; dj < 2; ++dj) {
-      const int j = 2 * cj + dj;
-      if (j >= op.d.n[1]) break;
-      for (int di = 0; di < 2; ++di) {
-        const int i = 2 * ci + di;
-        if (i >= op.d.n[0]) break;
-        const long long c = cell_index(op.d, i, j, k);
-        sum += b[c] - op.diag[c] * x[c] - coarse_offsum<T>(op, i, j, k, c, x);
-      }
-    }
-  }
-  bc[I] = sum;
-  xc[I] = (T)0;
-}
-
-// Coarsest level: at most a few cells; a fixed number of symmetric
-// Gauss-Seidel sweeps by one thread (exact for one cell).
-template <typename T>
-__global__ void k_coarsest(CoarseOp<T> op, const T* __restrict__ b, T* __restrict__ x, int sweeps) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (long long c = 0; c < op.d.N; ++c) x[c] = (T)0;
-  for (int s = 0; s < sweeps; ++s) {
-    for (int dir = 0; dir < 2; ++dir)
-      for (long long q = 0; q < op.d.N; ++q) {
-        const long long c = dir ? (op.d.N - 1 - q) : q;
-        int i, j, k;
-        cell_ijk(op.d, c, i, j, k);
-        x[c] = (b[c] - coarse_offsum<T>(op, i, j, k, c, x)) / op.diag[c];
-      }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -253,13 +190,12 @@ __device__ inline void rb_update_plane(const R& rows, int k, int tx0, int ty0, i
 }
 
 template <typename T, typename R>
-__global__ __launch_bounds__(RB_THREADS) void k_rb_fused(R rows, const T* __restrict__ xin,
-                                                         const T* __restrict__ xc, Dims cd, T* __restrict__ xout,
-                                                         int zchunk) {
-  __shared__ T buf[4][RB_PLANE];
+__device__ inline void rb_fused_body(const R& rows, const T* __restrict__ xin, const T* __restrict__ xc,
+                                     const Dims& cd, T* __restrict__ xout, int zchunk, int bx, int by, int bz,
+                                     T (*buf)[RB_PLANE]) {
   const Dims& d = rows.dims();
-  const int tx0 = blockIdx.x * RB_TX, ty0 = blockIdx.y * RB_TY;
-  const int z0 = blockIdx.z * zchunk;
+  const int tx0 = bx * RB_TX, ty0 = by * RB_TY;
+  const int z0 = bz * zchunk;
   const int z1 = min(z0 + zchunk, d.n[2]);
   const bool zdim = d.dim == 3;
   auto slot = [&](int k) { return buf[((k % 4) + 4) % 4]; };
@@ -465,16 +401,14 @@ __device__ inline void fine_write(const Dims& d, int k, int tx0, int ty0, const 
 }
 
 template <typename T, int TX, int TY>
-__global__ __launch_bounds__(RB_THREADS) void k_rb_fine(FineOp op, const double* __restrict__ rhs,
-                                                        const T* __restrict__ xin, const T* __restrict__ xc, Dims cd,
-                                                        T* __restrict__ xout, int zchunk) {
+__device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
+                                    const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int zchunk,
+                                    int bx, int by, int bz, T (*xs)[FineTile<TX, TY>::PL],
+                                    double (*rs)[FineTile<TX, TY>::QL], uint8_t (*fs)[FineTile<TX, TY>::QL]) {
   using FT = FineTile<TX, TY>;
-  __shared__ T xs[4][FT::PL];
-  __shared__ double rs[2][FT::QL];
-  __shared__ uint8_t fs[2][FT::QL];
   const Dims& d = op.d;
   const RegularRow<T> rr = regular_row<T>(op);
-  const int tx0 = blockIdx.x * TX, ty0 = blockIdx.y * TY;
+  const int tx0 = bx * TX, ty0 = by * TY;
   T xv[FT::NX];
   double rv[FT::NQ];
   uint8_t fv[FT::NQ];
@@ -492,7 +426,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_fine(FineOp op, const double*
     return;
   }
   // slots: x plane p in xs[p & 3], r / flags of plane p in rs[p & 1] (p may be negative)
-  const int z0 = blockIdx.z * zchunk;
+  const int z0 = bz * zchunk;
   const int z1 = min(z0 + zchunk, d.n[2]);
   {
     T xa[FT::NX], xb[FT::NX];
@@ -633,9 +567,7 @@ __device__ inline void tail_sweep(T* sm, const TailLevel& L, int color) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(EBIT_TAIL_THREADS) void k_tail(TailArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char tail_smem[];
-  T* sm = reinterpret_cast<T*>(tail_smem);
+__device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int tx = tid & 31, ty = tid >> 5;
   for (int l = 0; l < a.nl; ++l) {
@@ -847,17 +779,21 @@ __global__ void k_cast_level(long long n, int dim, const double* d64, const doub
 }
 
 // ---------------------------------------------------------------------------
-// outer loop kernels (FP64) with deterministic two-stage reductions
+// outer loop (FP64) with deterministic two-stage reductions
 // ---------------------------------------------------------------------------
 #define GRID_STRIDE(c, N) \
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < (N); c += (long long)gridDim.x * blockDim.x)
+// the same over the nb blocks one case owns in a batched launch (this block
+// is its lb-th)
+#define CASE_STRIDE(c, N) \
+  for (long long c = (long long)lb * blockDim.x + threadIdx.x; c < (N); c += (long long)nb * blockDim.x)
 
 template <int NV>
-__device__ inline void write_partials(double (&v)[NV], double* partial) {
+__device__ inline void write_partials(double (&v)[NV], double* partial, int lb, int nb) {
   __shared__ double sh[NV * 4];
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0)
-    for (int q = 0; q < NV; ++q) partial[q * gridDim.x + blockIdx.x] = v[q];
+    for (int q = 0; q < NV; ++q) partial[q * nb + lb] = v[q];
 }
 
 // Error-free transformations (Knuth TwoSum, FMA-based TwoProd) for a
@@ -881,10 +817,10 @@ __device__ inline void dd_add(double& hi, double& lo, double p, double pe) {
 // rounding of x itself, eps |x| per entry and not smooth, leaves a residual
 // of that size).  With the compensated residual the outer loop's restarts
 // steer x to the correctly rounded discrete solution.
-__global__ void k_resid_init(FineOp op, const double* __restrict__ b, const double* __restrict__ x,
-                             double* __restrict__ r, double* partial) {
+__device__ inline void resid_init_body(const FineOp& op, const double* __restrict__ b, const double* __restrict__ x,
+                                       double* __restrict__ r, double* partial, int lb, int nb) {
   double v[3] = {0, 0, 0};
-  GRID_STRIDE(c, op.d.N) {
+  CASE_STRIDE(c, op.d.N) {
     const double bc = b[c];
     double rc = bc, ac = fabs(bc);
     if (x) {
@@ -899,8 +835,10 @@ __global__ void k_resid_init(FineOp op, const double* __restrict__ b, const doub
         dd_add(hi, lo, -p, -fma(mx, xc, -p));
       }
       ac += fabs(diag * xc);
-      for (int q = 0; q < 2 * op.d.dim; ++q) {
-        if (off[q] == 0.0) continue;
+      const int ns = 2 * op.d.dim;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        if (q >= ns || off[q] == 0.0) continue;
         int ni, nj, nk;
         neighbour(op.d, i, j, k, q, ni, nj, nk);
         const double xn = x[cell_index(op.d, ni, nj, nk)];
@@ -918,7 +856,7 @@ __global__ void k_resid_init(FineOp op, const double* __restrict__ b, const doub
     v[1] += rc * rc;
     v[2] += ac * ac;
   }
-  write_partials<3>(v, partial);
+  write_partials<3>(v, partial, lb, nb);
 }
 
 // y = A x (difference form: no cancellation between diagonal and couplings)
@@ -953,32 +891,297 @@ __global__ void k_heat_rhs(FineOp op, const double* __restrict__ Ts, double* __r
   }
 }
 
-// z.r and z.q (q = A p of the previous iteration)
-template <typename TZ>
-__global__ void k_dots_zr_zq(long long N, const TZ* __restrict__ z, const double* __restrict__ r,
-                             const double* __restrict__ q, double* partial) {
-  double v[2] = {0, 0};
-  GRID_STRIDE(c, N) {
-    const double zc = (double)z[c];
-    v[0] += zc * r[c];
-    if (q) v[1] += zc * q[c];
+// finalize kinds
+enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5 };
+
+// Sum (or max) of nv rows of nb partials, in a fixed order; result in thread 0.
+__device__ inline void reduce_partials(const double* __restrict__ partial, int nb, int nv, bool mx,
+                                       double (&v)[3]) {
+  __shared__ double sh[4 * 4];
+  for (int q = 0; q < 3; ++q) {
+    double s = 0;
+    if (q < nv) {
+      if (mx) {
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) s = fmax(s, partial[q * nb + t]);
+      } else {
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) s += partial[q * nb + t];
+      }
+    }
+    v[q] = s;
   }
-  write_partials<2>(v, partial);
+  if (mx) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double m = wave_max(v[0]);
+    if (lane == 0) sh[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) v[0] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  } else {
+    block_sum<3>(v, sh);
+  }
+}
+
+// single-system reductions outside the solves (divergence maximum)
+__global__ void k_finalize(const double* __restrict__ partial, int nb, int nv, Scal* sc, int kind) {
+  double v[3];
+  reduce_partials(partial, nb, nv, kind == FIN_MAX, v);
+  if (threadIdx.x != 0) return;
+  if (kind == FIN_MAX) sc->divmax = v[0];
+  if (kind == FIN_SUM1) sc->red[0] = v[0];
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves.  Every kernel of the solve takes the table of cases and a
+// work list that maps its 1D grid onto (case, block of that case), so one
+// launch serves every case of a batch; the single-context entry points run
+// a batch of one.  Per-case control words carry the active mask, the CG
+// restart flag and the search-direction slot: a fixed block of outer
+// iterations can be replayed as a graph while converged cases drop out on
+// the device.
+// ---------------------------------------------------------------------------
+struct WorkList {
+  const int* start;  // [n + 1]: first block of entry e; start[n] = blocks in the launch
+  const int* cid;    // [n]: case of entry e
+  int n;
+};
+
+__device__ inline int wl_find(const WorkList& w, int& lb, int& nb) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = w.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w.start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  lb = b - w.start[lo];
+  nb = w.start[lo + 1] - w.start[lo];
+  return w.cid[lo];
+}
+
+// control word of one case (host writes between iteration blocks, the
+// finalize kernels on the device)
+struct CaseCtl {
+  int active;   // iterating
+  int fresh;    // next iteration restarts the CG recurrence (beta = 0)
+  int pi;       // p[pi] holds the current search direction
+  int recheck;  // selected for a recomputation of the true residual
+};
+
+enum { MASK_ACTIVE = 0, MASK_ALL = 1, MASK_RECHECK = 2 };
+__device__ inline bool selected(const CaseCtl& c, int mask) {
+  return mask == MASK_ALL || (mask == MASK_ACTIVE ? c.active : c.recheck) != 0;
+}
+
+// Device view of one solve of one case: operator, vectors, hierarchy.
+template <typename T>
+struct SolveCase {
+  FineOp op;
+  const double* b;
+  double* x;
+  double* r;
+  T* z[2];           // V-cycle result (z[0]) and the second sweep buffer
+  double* p[2];
+  double* q;
+  double* partial;   // [3][nred]
+  Scal* sc;
+  int nred;          // reduction blocks of this case
+  int nlev, lt;      // levels; levels lt .. nlev-1 are solved by the tail kernel
+  int fzc, fgx, fgy; // fine sweep: z-chunk and tile grid
+  CoarseOp<T> lev[EBIT_MAX_LEVELS];  // explicit levels 1 .. lt-1 (and lt: its size)
+  T* lb[EBIT_MAX_LEVELS];
+  T* lx[EBIT_MAX_LEVELS][2];
+  int lzc[EBIT_MAX_LEVELS], lgx[EBIT_MAX_LEVELS], lgy[EBIT_MAX_LEVELS];
+  TailArgs<T> tail;
+};
+
+template <typename T>
+__global__ void kb_scal_reset(const SolveCase<T>* __restrict__ cs) {
+  Scal* sc = cs[blockIdx.x].sc;
+  int* w = reinterpret_cast<int*>(sc);
+  for (int t = threadIdx.x; t < (int)(sizeof(Scal) / sizeof(int)); t += blockDim.x) w[t] = 0;
+}
+
+template <typename T>
+__global__ void kb_zero_x(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
+                          int mask) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!selected(ctl[c], mask)) return;
+  const SolveCase<T>& C = cs[c];
+  CASE_STRIDE(i, C.op.d.N) C.x[i] = 0.0;
+}
+
+template <typename T>
+__global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
+                              int mask, int use_x) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!selected(ctl[c], mask)) return;
+  const SolveCase<T>& C = cs[c];
+  resid_init_body(C.op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb);
+}
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __restrict__ cs,
+                                                         const CaseCtl* __restrict__ ctl, WorkList wl, int in_sel,
+                                                         int out_sel, int add_xc) {
+  using FT = FineTile<TX, TY>;
+  __shared__ T xs[4][FT::PL];
+  __shared__ double rs[2][FT::QL];
+  __shared__ uint8_t fs[2][FT::QL];
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const int bx = lb % C.fgx, by = (lb / C.fgx) % C.fgy, bz = lb / (C.fgx * C.fgy);
+  rb_fine_body<T, TX, TY>(C.op, C.r, in_sel < 0 ? nullptr : (const T*)C.z[in_sel],
+                          add_xc ? (const T*)C.lx[1][0] : nullptr, C.lev[1].d, C.z[out_sel], C.fzc, bx, by, bz, xs,
+                          rs, fs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* __restrict__ cs,
+                                                           const CaseCtl* __restrict__ ctl, WorkList wl, int l,
+                                                           int in_sel, int out_sel, int add_xc) {
+  __shared__ T buf[4][RB_PLANE];
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const CoarseRows<T> rows{C.lev[l], C.lb[l]};
+  const int gx = C.lgx[l], gy = C.lgy[l];
+  rb_fused_body<T, CoarseRows<T>>(rows, in_sel < 0 ? nullptr : (const T*)C.lx[l][in_sel],
+                                  add_xc ? (const T*)C.lx[l + 1][0] : nullptr, C.lev[l + 1].d, C.lx[l][out_sel],
+                                  C.lzc[l], lb % gx, (lb / gx) % gy, lb / (gx * gy), buf);
+}
+
+// Residual of the 2^d children of every coarse cell of level 1, summed
+// (= P^T r); also clears the level-1 iterate.
+template <typename T>
+__global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
+                                 int src_sel) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const FineOp& op = C.op;
+  const Dims cd = C.lev[1].d;
+  const T* x = C.z[src_sel];
+  T* bc = C.lb[1];
+  T* xc = C.lx[1][0];
+  CASE_STRIDE(I, cd.N) {
+    int ci, cj, ck;
+    cell_ijk(cd, I, ci, cj, ck);
+    T sum = 0;
+    for (int dk = 0; dk < 2; ++dk) {
+      const int k = 2 * ck + dk;
+      if (k >= op.d.n[2]) break;
+      for (int dj = 0; dj < 2; ++dj) {
+        const int j = 2 * cj + dj;
+        if (j >= op.d.n[1]) break;
+        for (int di = 0; di < 2; ++di) {
+          const int i = 2 * ci + di;
+          if (i >= op.d.n[0]) break;
+          sum += fine_residual_at<T, double>(op, i, j, k, cell_index(op.d, i, j, k), C.r, x);
+        }
+      }
+    }
+    bc[I] = sum;
+    xc[I] = (T)0;
+  }
+}
+
+// the same from explicit level l to level l + 1
+template <typename T>
+__global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
+                                   int l, int src_sel) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const CoarseOp<T>& op = C.lev[l];
+  const Dims cd = C.lev[l + 1].d;
+  const T* b = C.lb[l];
+  const T* x = C.lx[l][src_sel];
+  T* bc = C.lb[l + 1];
+  T* xc = C.lx[l + 1][0];
+  CASE_STRIDE(I, cd.N) {
+    int ci, cj, ck;
+    cell_ijk(cd, I, ci, cj, ck);
+    T sum = 0;
+    for (int dk = 0; dk < 2; ++dk) {
+      const int k = 2 * ck + dk;
+      if (k >= op.d.n[2]) break;
+      for (int dj = 0; dj < 2; ++dj) {
+        const int j = 2 * cj + dj;
+        if (j >= op.d.n[1]) break;
+        for (int di = 0; di < 2; ++di) {
+          const int i = 2 * ci + di;
+          if (i >= op.d.n[0]) break;
+          const long long q = cell_index(op.d, i, j, k);
+          sum += b[q] - op.diag[q] * x[q] - coarse_offsum<T>(op, i, j, k, q, x);
+        }
+      }
+    }
+    bc[I] = sum;
+    xc[I] = (T)0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(EBIT_TAIL_THREADS) void kb_tail(const SolveCase<T>* __restrict__ cs,
+                                                             const CaseCtl* __restrict__ ctl) {
+  extern __shared__ __align__(16) unsigned char tail_smem[];
+  const int c = blockIdx.x;
+  if (!ctl[c].active) return;
+  tail_body<T>(cs[c].tail, reinterpret_cast<T*>(tail_smem));
+}
+
+// z.r and, unless the recurrence restarts, z.q (q = A p of the previous iteration)
+template <typename T>
+__global__ void kb_dots(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl, int dc) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  const CaseCtl cc = ctl[c];
+  if (!cc.active) return;
+  const SolveCase<T>& C = cs[c];
+  const bool first = dc || cc.fresh;
+  const T* z = C.z[0];
+  const double* r = C.r;
+  const double* q = C.q;
+  double v[2] = {0, 0};
+  CASE_STRIDE(i, C.op.d.N) {
+    const double zc = (double)z[i];
+    v[0] += zc * r[i];
+    if (!first) v[1] += zc * q[i];
+  }
+  write_partials<2>(v, C.partial, lb, nb);
 }
 
 // p_new = z + beta p_old; q = A p_new; partial p.q
-template <typename TZ>
-__global__ void k_p_update_apply(FineOp op, const TZ* __restrict__ z, const double* __restrict__ p_old,
-                                 double* __restrict__ p_new, double* __restrict__ q, const Scal* sc,
-                                 int first, double* partial) {
-  const double beta = first ? 0.0 : sc->beta;
+template <typename T>
+__global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
+                                  int dc) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  const CaseCtl cc = ctl[c];
+  if (!cc.active) return;
+  const SolveCase<T>& C = cs[c];
+  const FineOp& op = C.op;
+  const bool first = dc || cc.fresh;
+  const double beta = first ? 0.0 : C.sc->beta;
+  const T* z = C.z[0];
+  const double* p_old = C.p[cc.pi];
+  double* p_new = C.p[cc.pi ^ 1];
+  double* q = C.q;
   double v[1] = {0};
-  GRID_STRIDE(c, op.d.N) {
+  CASE_STRIDE(i0, op.d.N) {
     int i, j, k;
-    cell_ijk(op.d, c, i, j, k);
+    cell_ijk(op.d, i0, i, j, k);
     double diag, off[6], mass, rb = 0, mx;
-    fine_row<double>(op, i, j, k, op.flags[c], diag, off, mass, rb, &mx);
-    const double pc = first ? (double)z[c] : (double)z[c] + beta * p_old[c];
+    fine_row<double>(op, i, j, k, op.flags[i0], diag, off, mass, rb, &mx);
+    const double pc = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
     double s = mx * pc;
     for (int qq = 0; qq < 2 * op.d.dim; ++qq) {
       if (off[qq] == 0.0) continue;
@@ -988,53 +1191,50 @@ __global__ void k_p_update_apply(FineOp op, const TZ* __restrict__ z, const doub
       const double pm = first ? (double)z[m] : (double)z[m] + beta * p_old[m];
       s -= off[qq] * (pc - pm);
     }
-    p_new[c] = pc;
-    q[c] = s;
+    p_new[i0] = pc;
+    q[i0] = s;
     v[0] += pc * s;
   }
-  write_partials<1>(v, partial);
+  write_partials<1>(v, C.partial, lb, nb);
 }
 
 // x += alpha p; r -= alpha q; partial r.r
-__global__ void k_update_xr(long long N, double* __restrict__ x, double* __restrict__ r,
-                            const double* __restrict__ p, const double* __restrict__ q, const Scal* sc,
-                            double* partial) {
-  const double alpha = sc->alpha;
+template <typename T>
+__global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  const CaseCtl cc = ctl[c];
+  if (!cc.active) return;
+  const SolveCase<T>& C = cs[c];
+  const double alpha = C.sc->alpha;
+  const double* p = C.p[cc.pi ^ 1];
+  const double* q = C.q;
+  double* x = C.x;
+  double* r = C.r;
   double v[1] = {0};
-  GRID_STRIDE(c, N) {
-    x[c] += alpha * p[c];
-    const double rc = r[c] - alpha * q[c];
-    r[c] = rc;
+  CASE_STRIDE(i, C.op.d.N) {
+    x[i] += alpha * p[i];
+    const double rc = r[i] - alpha * q[i];
+    r[i] = rc;
     v[0] += rc * rc;
   }
-  write_partials<1>(v, partial);
+  write_partials<1>(v, C.partial, lb, nb);
 }
 
-// finalize kinds
-enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5 };
-
-__global__ void k_finalize(const double* __restrict__ partial, int nb, int nv, Scal* sc, int kind, int first) {
-  __shared__ double sh[4 * 4];
-  double v[3] = {0, 0, 0};
-  for (int q = 0; q < nv; ++q) {
-    double s = 0;
-    if (kind == FIN_MAX) {
-      for (int t = threadIdx.x; t < nb; t += blockDim.x) s = fmax(s, partial[q * nb + t]);
-    } else {
-      for (int t = threadIdx.x; t < nb; t += blockDim.x) s += partial[q * nb + t];
-    }
-    v[q] = s;
-  }
-  if (kind == FIN_MAX) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double m = wave_max(v[0]);
-    if (lane == 0) sh[w] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) v[0] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-  } else {
-    block_sum<3>(v, sh);
-  }
+// One block per case: reduce its partials and advance its scalars.  FIN_RR
+// also ends the iteration: the direction slot flips, the restart flag
+// clears, and the case stops (active = 0) once r.r <= stop2 or on NaN/Inf.
+template <typename T>
+__global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl,
+                            const double* __restrict__ stop2, int kind, int nv, int mask, int dc) {
+  const int c = blockIdx.x;
+  const CaseCtl cc = ctl[c];
+  if (!selected(cc, mask)) return;
+  const SolveCase<T>& C = cs[c];
+  double v[3];
+  reduce_partials(C.partial, C.nred, nv, false, v);
   if (threadIdx.x != 0) return;
+  Scal* sc = C.sc;
   bool bad = false;
   switch (kind) {
     case FIN_INIT:
@@ -1044,6 +1244,7 @@ __global__ void k_finalize(const double* __restrict__ partial, int nb, int nv, S
       bad = !isfinite(v[0]) || !isfinite(v[1]);
       break;
     case FIN_GAMMA: {
+      const bool first = dc || cc.fresh;
       const double gnew = v[0];
       sc->beta = first ? 0.0 : -sc->alpha * v[1] / sc->gamma;
       sc->gamma = gnew;
@@ -1056,18 +1257,22 @@ __global__ void k_finalize(const double* __restrict__ partial, int nb, int nv, S
       sc->alpha = sc->gamma / v[0];
       bad = !isfinite(sc->alpha);
       break;
-    case FIN_RR:
+    case FIN_RR: {
       sc->rr = v[0];
+      sc->iters += 1;
       bad = !isfinite(v[0]);
+      CaseCtl n = cc;
+      n.fresh = 0;
+      n.pi = cc.pi ^ 1;
+      if (v[0] <= stop2[c]) n.active = 0;
+      ctl[c] = n;
       break;
-    case FIN_MAX:
-      sc->divmax = v[0];
-      break;
-    case FIN_SUM1:
-      sc->red[0] = v[0];
-      break;
+    }
   }
-  if (bad) sc->err |= ERR_NAN;
+  if (bad) {
+    sc->err |= ERR_NAN;
+    ctl[c].active = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1120,7 +1325,39 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
   return hipGetLastError();
 }
 
-}  // extern "C"
+hipError_t ebit_launch_apply(const FineOp* op, const double* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_apply, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, *op, x, y);
+  return hipGetLastError();
+}
+
+hipError_t ebit_launch_heat_rhs(const FineOp* op, const double* Ts, double* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_heat_rhs, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, *op, Ts, b);
+  return hipGetLastError();
+}
+
+hipError_t ebit_launch_finalize_max(const double* partial, int nb, Scal* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partial, nb, 1, sc, (int)FIN_MAX);
+  return hipGetLastError();
+}
+
+// LDS the tail kernel may use: the device's per-work-group maximum (raising
+// the kernel's dynamic-LDS limit above 64 KiB where the device allows it).
+int ebit_tail_lds_setup(void) {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 64 * 1024;
+  if (v > 64 * 1024) {
+    if (hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      return 64 * 1024;
+    }
+  }
+  return v;
+}
 
 // ---- profiling ----
 hipError_t ebit_prof_flush(EbitProfiler* pr) {
@@ -1137,6 +1374,14 @@ hipError_t ebit_prof_flush(EbitProfiler* pr) {
   pr->npend = 0;
   return hipSuccess;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Solve plans: device tables and work lists of a batch of cases, and the
+// host side of the outer iteration.
+// ---------------------------------------------------------------------------
+namespace {
 
 // Bracket one launch with events when profiling is on.
 struct ProfScope {
@@ -1155,70 +1400,48 @@ struct ProfScope {
   }
 };
 
-// ---- V-cycle driver (templated on the inner precision) ----
 template <typename T>
-static CoarseOp<T> coarse_op(const EbitLevelHost& L, int sys);
+CoarseOp<T> coarse_op_of(const EbitLevelHost& L, int sys);
 template <>
-CoarseOp<double> coarse_op<double>(const EbitLevelHost& L, int sys) {
+CoarseOp<double> coarse_op_of<double>(const EbitLevelHost& L, int sys) {
   CoarseOp<double> c;
   c.d = L.d;
   c.diag = L.diag64[sys];
-  for (int a = 0; a < 3; ++a) c.off[a] = (a < L.d.dim) ? L.off64[sys][a] : nullptr;
+  for (int a = 0; a < 3; ++a) c.off[a] = L.off64[sys][a];
   c.mass = L.mass64[sys];
   return c;
 }
 template <>
-CoarseOp<float> coarse_op<float>(const EbitLevelHost& L, int sys) {
+CoarseOp<float> coarse_op_of<float>(const EbitLevelHost& L, int sys) {
   CoarseOp<float> c;
   c.d = L.d;
   c.diag = L.diag32[sys];
-  for (int a = 0; a < 3; ++a) c.off[a] = (a < L.d.dim) ? L.off32[sys][a] : nullptr;
+  for (int a = 0; a < 3; ++a) c.off[a] = L.off32[sys][a];
   c.mass = L.mass64[sys];
   return c;
 }
 template <typename T>
-static T* lvx(const EbitLevelHost& L);
+T* lvx(const EbitLevelHost& L, int s);
 template <>
-double* lvx<double>(const EbitLevelHost& L) { return L.x64; }
+double* lvx<double>(const EbitLevelHost& L, int s) { return s ? L.x64b : L.x64; }
 template <>
-float* lvx<float>(const EbitLevelHost& L) { return L.x32; }
+float* lvx<float>(const EbitLevelHost& L, int s) { return s ? L.x32b : L.x32; }
 template <typename T>
-static T* lvb(const EbitLevelHost& L);
+T* lvb(const EbitLevelHost& L);
 template <>
 double* lvb<double>(const EbitLevelHost& L) { return L.b64; }
 template <>
 float* lvb<float>(const EbitLevelHost& L) { return L.b32; }
-
-// First coarse level (>= 1) from which the tail kernel takes over: the
-// remaining levels (x, b and coefficients) must fit lds_bytes of LDS and the
-// top one hold at most tail_cells cells.
 template <typename T>
-static int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells, int lds_bytes) {
-  if (tail_cells <= 0) return nlev;
-  long long tot = 0;
-  int lt = nlev;
-  for (int l = nlev - 1; l >= 1; --l) {
-    tot += tail_level_elems(lv[l].d);
-    if (tot * (long long)sizeof(T) > lds_bytes || lv[l].d.N > tail_cells || nlev - l > EBIT_TAIL_MAX) break;
-    lt = l;
-  }
-  return lt;
-}
-
-template <typename T>
-static T* lvxb(const EbitLevelHost& L);
+T* zb(const EbitSolveBufs& B, int s);
 template <>
-double* lvxb<double>(const EbitLevelHost& L) { return L.x64b; }
+double* zb<double>(const EbitSolveBufs& B, int s) { return s ? B.z64b : B.z64; }
 template <>
-float* lvxb<float>(const EbitLevelHost& L) { return L.x32b; }
+float* zb<float>(const EbitSolveBufs& B, int s) { return s ? B.z32b : B.z32; }
 
-static inline dim3 rb_grid(const Dims& d, int zchunk) {
-  return dim3((unsigned)((d.n[0] + RB_TX - 1) / RB_TX), (unsigned)((d.n[1] + RB_TY - 1) / RB_TY),
-              (unsigned)((d.n[2] + zchunk - 1) / zchunk));
-}
-
-// z-chunk: enough work-groups to fill the chip, at most 32 planes each
-static inline int rb_zchunk(const Dims& d) {
+// z-chunk of a 64 x 8-tiled sweep: enough work-groups to fill the chip, at
+// most 32 planes each
+int rb_zchunk(const Dims& d) {
   if (d.dim < 3) return 1;
   const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
   int zc = 32;
@@ -1226,322 +1449,566 @@ static inline int rb_zchunk(const Dims& d) {
   return zc;
 }
 
-// S = nu1 + nu2 fused sweeps on one level; sweep s (1-based) writes X when
-// S - s is even and Xb otherwise, so the last one lands in X.  The first
-// pre-smoothing sweep starts from zero; the first post-smoothing sweep adds
-// the coarse correction xc on load.  launch(in, xc, out) issues one sweep.
-template <typename T, typename L>
-static void smooth_pre(const L& launch, int nu1, int S, T* X, T* Xb, hipStream_t st, EbitProfiler* pf, int kc) {
-  const T* in = nullptr;
-  for (int s = 1; s <= nu1; ++s) {
-    T* out = ((S - s) % 2 == 0) ? X : Xb;
-    ProfScope ps(pf, kc, st);
-    launch(in, (const T*)nullptr, out);
-    in = out;
+// First level (>= 1) of the tail: the levels from there down (x, b and
+// coefficients) fit lds_bytes of LDS and the top one has at most tail_cells
+// cells; the coarsest level is always in the tail.
+template <typename T>
+int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells, int lds_bytes) {
+  long long tot = tail_level_elems(lv[nlev - 1].d);
+  int lt = nlev - 1;
+  for (int l = nlev - 2; l >= 1; --l) {
+    tot += tail_level_elems(lv[l].d);
+    if (tot * (long long)sizeof(T) > lds_bytes || lv[l].d.N > tail_cells || nlev - l > EBIT_TAIL_MAX) break;
+    lt = l;
   }
-}
-template <typename T, typename L>
-static void smooth_post(const L& launch, int nu1, int S, T* X, T* Xb, const T* xc, hipStream_t st, EbitProfiler* pf,
-                        int kc) {
-  const T* in = ((S - nu1) % 2 == 0) ? X : Xb;
-  for (int s = nu1 + 1; s <= S; ++s) {
-    T* out = ((S - s) % 2 == 0) ? X : Xb;
-    ProfScope ps(pf, kc, st);
-    launch(in, s == nu1 + 1 ? xc : (const T*)nullptr, out);
-    in = out;
-  }
+  return lt;
 }
 
-// fine-level sweep launcher: 64 x 8 tiles marching along z in 3D, 64 x 4
-// tiles in 2D (twice the work-groups for the single plane)
+// reduction blocks of a case: one cell per thread up to EBIT_RED_BLOCKS blocks
+int red_blocks(long long N) {
+  const long long b = (N + EBIT_BLOCK - 1) / EBIT_BLOCK;
+  return (int)(b < 1 ? 1 : (b > EBIT_RED_BLOCKS ? EBIT_RED_BLOCKS : b));
+}
+
+const size_t PALIGN = 256;
+struct PCarver {
+  char* base;
+  size_t off;
+  template <typename X>
+  X* take(size_t n) {
+    off = (off + PALIGN - 1) / PALIGN * PALIGN;
+    X* p = base ? (X*)(base + off) : nullptr;
+    off += n * sizeof(X);
+    return p;
+  }
+};
+
+constexpr int PLAN_MAX_K = 16;                     // outer iterations per graph block
+constexpr int PLAN_LISTS = 3 + 2 * EBIT_MAX_LEVELS;  // work lists of a plan
+
+struct HostList {
+  WorkList w;
+  int blocks;
+};
+
 template <typename T>
-struct FineSweep {
-  FineOp op;
-  const double* r;
-  Dims cd;
-  hipStream_t st;
-  void operator()(const T* in, const T* xc, T* out) const {
-    const Dims& d = op.d;
-    if (d.dim == 3) {
-      const int zc = rb_zchunk(d);
-      const dim3 g((unsigned)((d.n[0] + 63) / 64), (unsigned)((d.n[1] + 7) / 8), (unsigned)((d.n[2] + zc - 1) / zc));
-      hipLaunchKernelGGL((k_rb_fine<T, 64, 8>), g, dim3(RB_THREADS), 0, st, op, r, in, xc, cd, out, zc);
-    } else {
-      const dim3 g((unsigned)((d.n[0] + 63) / 64), (unsigned)((d.n[1] + 3) / 4), 1);
-      hipLaunchKernelGGL((k_rb_fine<T, 64, 4>), g, dim3(RB_THREADS), 0, st, op, r, in, xc, cd, out, 1);
+struct PlanT {
+  int n = 0, dim = 0, Lmax = 0;
+  ebit_opts o;
+  std::vector<EbitPlanCase> cases;
+  SolveCase<T>* d_cs[2] = {nullptr, nullptr};
+  SolveCase<T>* h_cs[2] = {nullptr, nullptr};
+  CaseCtl* d_ctl = nullptr;
+  CaseCtl* h_ctl = nullptr;
+  double* d_stop2 = nullptr;
+  double* h_stop2 = nullptr;
+  Scal* d_sc = nullptr;
+  Scal* h_sc = nullptr;
+  HostList fine, frestrict, red;
+  HostList coarse[EBIT_MAX_LEVELS], crestrict[EBIT_MAX_LEVELS];
+  size_t tail_bytes = 0;
+  hipStream_t ist = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t graph[2][PLAN_MAX_K + 1] = {};
+  bool no_graph = false;
+};
+
+template <typename T>
+size_t plan_carve(int n, PCarver& cv, PlanT<T>* P, int** wl) {
+  SolveCase<T>* cs0 = cv.take<SolveCase<T>>(n);
+  SolveCase<T>* cs1 = cv.take<SolveCase<T>>(n);
+  CaseCtl* ctl = cv.take<CaseCtl>(n);
+  double* stop2 = cv.take<double>(n);
+  Scal* sc = cv.take<Scal>(n);
+  int* w = cv.take<int>((size_t)PLAN_LISTS * (2 * n + 1));
+  if (P) {
+    P->d_cs[0] = cs0;
+    P->d_cs[1] = cs1;
+    P->d_ctl = ctl;
+    P->d_stop2 = stop2;
+    P->d_sc = sc;
+    *wl = w;
+  }
+  return (cv.off + PALIGN - 1) / PALIGN * PALIGN;
+}
+
+// append a work list of (case, blocks) entries with at least one block
+HostList make_list(const std::vector<std::pair<int, int>>& ent, std::vector<int>& host, const int* dev) {
+  HostList L;
+  const size_t o = host.size();
+  int tot = 0;
+  int m = 0;
+  for (const auto& e : ent)
+    if (e.second > 0) ++m;
+  for (const auto& e : ent)
+    if (e.second > 0) {
+      host.push_back(tot);
+      tot += e.second;
     }
-  }
-};
+  host.push_back(tot);
+  for (const auto& e : ent)
+    if (e.second > 0) host.push_back(e.first);
+  L.w.start = dev + o;
+  L.w.cid = dev + o + m + 1;
+  L.w.n = m;
+  L.blocks = tot;
+  return L;
+}
 
-// explicit coarse-level sweep launcher
 template <typename T>
-struct CoarseSweep {
-  CoarseRows<T> rows;
-  Dims cd;
-  hipStream_t st;
-  void operator()(const T* in, const T* xc, T* out) const {
-    const Dims& d = rows.op.d;
-    const int zc = rb_zchunk(d);
-    hipLaunchKernelGGL((k_rb_fused<T, CoarseRows<T>>), rb_grid(d, zc), dim3(RB_THREADS), 0, st, rows, in, xc, cd,
-                       out, zc);
-  }
-};
+void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, hipStream_t st) {
+  if (P.dim == 3)
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs,
+                       (const CaseCtl*)P.d_ctl, P.fine.w, in, out, add);
+  else
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs,
+                       (const CaseCtl*)P.d_ctl, P.fine.w, in, out, add);
+}
 
-// One V(nu1, nu2) cycle on A z = r (zero initial guess); the fine level is
-// matrix-free, levels 1 .. lt-1 explicit, levels lt .. in the tail kernel.
+// One V(nu1, nu2) cycle on A z = r (zero initial guess) for every active
+// case.  Sweep s of S = nu1 + nu2 on a level writes buffer 0 when S - s is
+// even, else buffer 1, so the last one lands in buffer 0.
 template <typename T>
-static hipError_t vcycle(const FineOp& op, const EbitLevelHost* lv, int nlev, const double* r, T* z, T* zb,
-                         int nu1, int nu2, int tail_cells, int tail_lds, hipStream_t st, EbitProfiler* pf) {
-  const int sys = op.sys;
-  const int S = nu1 + nu2;
-  const FineSweep<T> fine{op, r, nlev > 1 ? lv[1].d : op.d, st};
-  if (nlev == 1) {
-    smooth_pre<T>(fine, S, S, z, zb, st, pf, EBIT_KC_FINE_SMOOTH);
-    return hipGetLastError();
+void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitProfiler* pf) {
+  const int nu1 = P.o.nu1, S = P.o.nu1 + P.o.nu2;
+  const CaseCtl* ctl = P.d_ctl;
+  auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
+  int in = -1;
+  for (int s = 1; s <= nu1; ++s) {
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
+    launch_fine(P, cs, in, slot(s), 0, st);
+    in = slot(s);
   }
-  // descend
-  smooth_pre<T>(fine, nu1, S, z, zb, st, pf, EBIT_KC_FINE_SMOOTH);
-  const T* zpre = ((S - nu1) % 2 == 0) ? z : zb;
   {
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
-    hipLaunchKernelGGL((k_fine_resid_restrict<T, double>), dim3(nblk(lv[1].d.N)), dim3(EBIT_BLOCK), 0, st, op, r,
-                       zpre, lv[1].d, lvb<T>(lv[1]), lvx<T>(lv[1]));
+    hipLaunchKernelGGL(kb_fine_restrict<T>, dim3(P.frestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                       P.frestrict.w, in);
   }
-  // first level whose whole remaining hierarchy fits the tail kernel's LDS
-  const int lt = tail_start<T>(lv, nlev, tail_cells, tail_lds);
-  for (int l = 1; l < lt; ++l) {
-    const CoarseRows<T> rows{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])};
-    const CoarseSweep<T> sw{rows, lv[l + 1].d, st};
-    smooth_pre<T>(sw, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), st, pf, EBIT_KC_COARSE);
-    const T* xpre = ((S - nu1) % 2 == 0) ? lvx<T>(lv[l]) : lvxb<T>(lv[l]);
+  for (int l = 1; l < P.Lmax; ++l) {
+    in = -1;
+    for (int s = 1; s <= nu1; ++s) {
+      ProfScope ps(pf, EBIT_KC_COARSE, st);
+      hipLaunchKernelGGL(kb_rb_coarse<T>, dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.coarse[l].w,
+                         l, in, slot(s), 0);
+      in = slot(s);
+    }
     ProfScope ps(pf, EBIT_KC_COARSE, st);
-    hipLaunchKernelGGL(k_coarse_resid_restrict<T>, dim3(nblk(lv[l + 1].d.N)), dim3(EBIT_BLOCK), 0, st, rows.op,
-                       (const T*)lvb<T>(lv[l]), xpre, lv[l + 1].d, lvb<T>(lv[l + 1]), lvx<T>(lv[l + 1]));
+    hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                       P.crestrict[l].w, l, in);
   }
-  if (lt < nlev) {
-    TailArgs<T> ta;
-    ta.nl = nlev - lt;
-    ta.nu1 = nu1;
-    ta.nu2 = nu2;
-    long long off = 0;
-    for (int m = 0; m < ta.nl; ++m) {
-      const EbitLevelHost& L = lv[lt + m];
-      ta.L[m].d = L.d;
-      ta.L[m].base = (int)off;
-      const CoarseOp<T> c = coarse_op<T>(L, sys);
-      ta.diag[m] = c.diag;
-      for (int q = 0; q < 3; ++q) ta.off[m][q] = c.off[q];
-      off += tail_level_elems(L.d);
-    }
-    ta.bg = lvb<T>(lv[lt]);
-    ta.xg = lvx<T>(lv[lt]);
+  {
     ProfScope ps(pf, EBIT_KC_TAIL, st);
-    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(EBIT_TAIL_THREADS), (size_t)off * sizeof(T), st, ta);
-  } else {
-    CoarseOp<T> c = coarse_op<T>(lv[nlev - 1], sys);
-    hipLaunchKernelGGL(k_coarsest<T>, dim3(1), dim3(64), 0, st, c, (const T*)lvb<T>(lv[nlev - 1]),
-                       lvx<T>(lv[nlev - 1]), c.d.N == 1 ? 1 : 50);
+    hipLaunchKernelGGL(kb_tail<T>, dim3(P.n), dim3(EBIT_TAIL_THREADS), P.tail_bytes, st, cs, ctl);
   }
-  // ascend: the first post-smoothing sweep of each level adds the correction
-  for (int l = lt - 1; l >= 1; --l) {
-    const CoarseSweep<T> sw{CoarseRows<T>{coarse_op<T>(lv[l], sys), lvb<T>(lv[l])}, lv[l + 1].d, st};
-    smooth_post<T>(sw, nu1, S, lvx<T>(lv[l]), lvxb<T>(lv[l]), (const T*)lvx<T>(lv[l + 1]), st, pf, EBIT_KC_COARSE);
+  for (int l = P.Lmax - 1; l >= 1; --l) {
+    in = slot(nu1);
+    for (int s = nu1 + 1; s <= S; ++s) {
+      ProfScope ps(pf, EBIT_KC_COARSE, st);
+      hipLaunchKernelGGL(kb_rb_coarse<T>, dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.coarse[l].w,
+                         l, in, slot(s), s == nu1 + 1 ? 1 : 0);
+      in = slot(s);
+    }
   }
-  smooth_post<T>(fine, nu1, S, z, zb, (const T*)lvx<T>(lv[1]), st, pf, EBIT_KC_FINE_SMOOTH);
-  return hipGetLastError();
+  in = slot(nu1);
+  for (int s = nu1 + 1; s <= S; ++s) {
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
+    launch_fine(P, cs, in, slot(s), s == nu1 + 1 ? 1 : 0, st);
+    in = slot(s);
+  }
 }
 
-extern "C" {
-
-hipError_t ebit_launch_apply(const FineOp* op, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, *op, x, y);
-  return hipGetLastError();
+// K outer iterations: flexible CG preconditioned by one V-cycle; defect
+// correction is the same loop with beta = 0 (x += alpha V(r) with the
+// energy-optimal step alpha = (r.z)/(z.Az), which contracts for any SPD A).
+template <typename T>
+void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st, EbitProfiler* pf) {
+  const int dc = P.o.outer == EBIT_OUTER_DC;
+  for (int k = 0; k < K; ++k) {
+    vcycle_b(P, cs, st, pf);
+    hipLaunchKernelGGL(kb_dots<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl, P.red.w,
+                       dc);
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
+                       (int)FIN_GAMMA, 2, (int)MASK_ACTIVE, dc);
+    {
+      ProfScope ps(pf, EBIT_KC_OUTER_APPLY, st);
+      hipLaunchKernelGGL(kb_p_update_apply<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs,
+                         (const CaseCtl*)P.d_ctl, P.red.w, dc);
+    }
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
+                       (int)FIN_DELTA, 1, (int)MASK_ACTIVE, dc);
+    {
+      ProfScope ps(pf, EBIT_KC_OUTER_UPDATE, st);
+      hipLaunchKernelGGL(kb_update_xr<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                         P.red.w);
+    }
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
+                       (int)FIN_RR, 1, (int)MASK_ACTIVE, dc);
+  }
 }
 
-hipError_t ebit_launch_heat_rhs(const FineOp* op, const double* Ts, double* b, hipStream_t st) {
-  hipLaunchKernelGGL(k_heat_rhs, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, *op, Ts, b);
-  return hipGetLastError();
-}
-
-// LDS the tail kernel may use: the device's per-work-group maximum (raising
-// the kernel's dynamic-LDS limit above 64 KiB where the device allows it).
-int ebit_tail_lds_setup(void) {
-  int dev = 0, v = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-    return 64 * 1024;
-  if (v > 64 * 1024) {
-    if (hipFuncSetAttribute((const void*)ebit::k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void*)ebit::k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
-            hipSuccess) {
+// Run K iterations: replay the captured graph of the block (captured on
+// first use), or launch eagerly while per-launch profiling is on.
+template <typename T>
+hipError_t run_block(PlanT<T>& P, int sys, int K, EbitProfiler* pf) {
+  const SolveCase<T>* cs = P.d_cs[sys];
+  if ((pf && pf->on) || P.no_graph || K > PLAN_MAX_K) {
+    iterations(P, cs, K, P.ist, pf);
+    return hipGetLastError();
+  }
+  hipGraphExec_t& ge = P.graph[sys][K];
+  if (!ge) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(P.ist, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      iterations(P, cs, K, P.ist, nullptr);
+      e = hipStreamEndCapture(P.ist, &g);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      // no graph on this stream or runtime: launch eagerly from now on
       (void)hipGetLastError();
-      return 64 * 1024;
+      ge = nullptr;
+      P.no_graph = true;
+      iterations(P, cs, K, P.ist, nullptr);
+      return hipGetLastError();
     }
   }
-  return v;
-}
-
-hipError_t ebit_launch_finalize_max(const double* partial, int nb, Scal* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partial, nb, 1, sc, (int)FIN_MAX, 0);
-  return hipGetLastError();
-}
-
-}  // extern "C"
-
-namespace ebit {
-
-static hipError_t read_scal(Scal* d, Scal* h, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(h, d, sizeof(Scal), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(st);
+  return hipGraphLaunch(ge, P.ist);
 }
 
 template <typename T>
-static T* zbuf2(const EbitSolveBufs* B);
-template <>
-double* zbuf2<double>(const EbitSolveBufs* B) { return B->z64b; }
-template <>
-float* zbuf2<float>(const EbitSolveBufs* B) { return B->z32b; }
-template <typename T>
-static T* zbuf(const EbitSolveBufs* B);
-template <>
-double* zbuf<double>(const EbitSolveBufs* B) { return B->z64; }
-template <>
-float* zbuf<float>(const EbitSolveBufs* B) { return B->z32; }
-
-template <typename T>
-static int solve_t(const FineOp& op, const EbitLevelHost* lv, int nlev, const EbitSolveBufs* B, const double* b,
-                   double* x, int use_guess, const ebit_opts* o, hipStream_t st, int* iters, int* vcyc,
-                   double* relres, double* bnorm, double* floor, hipError_t* herr) {
-  const long long N = op.d.N;
-  const int RB = EBIT_RED_BLOCKS;
-  Scal hs;
-  T* z = zbuf<T>(B);
-  *iters = 0;
-  *vcyc = 0;
-  *herr = hipSuccess;
-#define CK(e)                 \
-  do {                        \
-    hipError_t _e = (e);      \
-    if (_e != hipSuccess) {   \
-      *herr = _e;             \
-      return -1;              \
-    }                         \
-  } while (0)
-  // reset device scalars (a fill kernel, so the sequence stays graph-capturable)
-  hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, st, (long long)(sizeof(Scal) / sizeof(double)),
-                     (double*)B->scal, 0.0);
-  if (!use_guess) hipLaunchKernelGGL(k_fill<double>, dim3(nblk(N)), dim3(EBIT_BLOCK), 0, st, N, x, 0.0);
-  hipLaunchKernelGGL(k_resid_init, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, b, use_guess ? (const double*)x : nullptr,
-                     B->r, B->partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 3, B->scal,
-                     (int)FIN_INIT, 1);
-  CK(hipGetLastError());
-  CK(read_scal(B->scal, &hs, st));
-  if (hs.err & ERR_NAN) return 2;
-  const double bb = hs.bb;
-  *bnorm = sqrt(bb);
-  if (bb == 0.0) {
-    hipLaunchKernelGGL(k_fill<double>, dim3(nblk(N)), dim3(EBIT_BLOCK), 0, st, N, x, 0.0);
-    *relres = 0.0;
-    *floor = 0.0;
-    CK(hipGetLastError());
-    return 0;
+hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const ebit_opts* o, int tail_lds, void* mem,
+                         size_t bytes) {
+  P->n = n;
+  P->o = *o;
+  P->cases.assign(cases, cases + n);
+  P->dim = cases[0].lv[0].d.dim;
+  PCarver cv{(char*)mem, 0};
+  int* d_wl = nullptr;
+  if (plan_carve<T>(n, cv, P, &d_wl) > bytes) return hipErrorInvalidValue;
+  hipError_t e;
+  for (int s = 0; s < 2; ++s)
+    if ((e = hipHostMalloc((void**)&P->h_cs[s], n * sizeof(SolveCase<T>), 0)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&P->h_ctl, n * sizeof(CaseCtl), 0)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&P->h_stop2, n * sizeof(double), 0)) != hipSuccess) return e;
+  if ((e = hipHostMalloc((void**)&P->h_sc, n * sizeof(Scal), 0)) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&P->ist, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming)) != hipSuccess) return e;
+  std::vector<int> lt(n);
+  size_t tail_elems = 0;
+  P->Lmax = 1;
+  for (int c = 0; c < n; ++c) {
+    const EbitPlanCase& pc = cases[c];
+    lt[c] = tail_start<T>(pc.lv, pc.nlev, o->tail_cells, tail_lds);
+    size_t el = 0;
+    for (int l = lt[c]; l < pc.nlev; ++l) el += tail_level_elems(pc.lv[l].d);
+    if (el > tail_elems) tail_elems = el;
+    if (lt[c] > P->Lmax) P->Lmax = lt[c];
   }
-  const double tol2 = o->rtol * o->rtol * bb;
-  // representability floor of the residual: eps || |b| + |A||x| ||
-  const double fc = 2.220446049250313e-16;
-  double floor2 = fc * fc * hs.aa;
-  double rr = hs.rr;
-  if (rr <= tol2) {
-    *relres = sqrt(rr / bb);
-    *floor = sqrt(floor2 / bb);
-    return 0;
-  }
-  const int check = o->check_every > 0 ? o->check_every : 1;
-  int it = 0;
-  int restarts = 0;
-  int first = 1;
-  int pi = 0;
-  bool conv = false;
-  double last_true = rr;  // last recomputed residual (squared)
-  int at_floor = 0;
-  while (it < o->max_iters) {
-    CK(vcycle<T>(op, lv, nlev, B->r, z, zbuf2<T>(B), o->nu1, o->nu2, o->tail_cells, B->tail_lds, st, B->prof));
-    ++*vcyc;
-    // defect correction = the same loop with beta = 0: x += alpha V(r) with the
-    // energy-optimal step alpha = (r.z)/(z.Az), so it contracts for any SPD A
-    const int fresh = (o->outer == EBIT_OUTER_DC) ? 1 : first;
-    hipLaunchKernelGGL(k_dots_zr_zq<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, (const T*)z,
-                       (const double*)B->r, fresh ? nullptr : (const double*)B->q, B->partial);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 2, B->scal,
-                       (int)FIN_GAMMA, fresh);
-    {
-      ProfScope ps(B->prof, EBIT_KC_OUTER_APPLY, st);
-      hipLaunchKernelGGL(k_p_update_apply<T>, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, (const T*)z,
-                         (const double*)B->p[pi], B->p[1 - pi], B->q, (const Scal*)B->scal, fresh, B->partial);
-    }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
-                       (int)FIN_DELTA, 0);
-    pi = 1 - pi;
-    {
-      ProfScope ps(B->prof, EBIT_KC_OUTER_UPDATE, st);
-      hipLaunchKernelGGL(k_update_xr, dim3(RB), dim3(EBIT_BLOCK), 0, st, N, x, B->r, (const double*)B->p[pi],
-                         (const double*)B->q, (const Scal*)B->scal, B->partial);
-    }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 1, B->scal,
-                       (int)FIN_RR, 0);
-    first = 0;
-    CK(hipGetLastError());
-    ++it;
-    if (it % check == 0 || it == o->max_iters) {
-      CK(read_scal(B->scal, &hs, st));
-      if (hs.err & ERR_NAN) {
-        *iters = it;
-        return 2;
+  P->tail_bytes = tail_elems * sizeof(T);
+  std::vector<std::pair<int, int>> efine, efr, ered;
+  std::vector<std::pair<int, int>> ecs[EBIT_MAX_LEVELS], ecr[EBIT_MAX_LEVELS];
+  for (int sys = 0; sys < 2; ++sys)
+    for (int c = 0; c < n; ++c) {
+      const EbitPlanCase& pc = cases[c];
+      SolveCase<T>& C = P->h_cs[sys][c];
+      memset(&C, 0, sizeof(C));
+      C.op = pc.op[sys];
+      C.b = pc.b;
+      C.x = nullptr;
+      C.r = pc.B.r;
+      C.z[0] = zb<T>(pc.B, 0);
+      C.z[1] = zb<T>(pc.B, 1);
+      C.p[0] = pc.B.p[0];
+      C.p[1] = pc.B.p[1];
+      C.q = pc.B.q;
+      C.partial = pc.B.partial;
+      C.sc = P->d_sc + c;
+      const Dims& fd = pc.lv[0].d;
+      C.nred = red_blocks(fd.N);
+      C.nlev = pc.nlev;
+      C.lt = lt[c];
+      const int fty = P->dim == 3 ? 8 : 4;
+      C.fzc = rb_zchunk(fd);
+      C.fgx = (fd.n[0] + 63) / 64;
+      C.fgy = (fd.n[1] + fty - 1) / fty;
+      for (int l = 1; l < pc.nlev; ++l) {
+        const EbitLevelHost& L = pc.lv[l];
+        C.lev[l] = coarse_op_of<T>(L, sys);
+        C.lb[l] = lvb<T>(L);
+        C.lx[l][0] = lvx<T>(L, 0);
+        C.lx[l][1] = lvx<T>(L, 1);
+        C.lzc[l] = rb_zchunk(L.d);
+        C.lgx[l] = (L.d.n[0] + RB_TX - 1) / RB_TX;
+        C.lgy[l] = (L.d.n[1] + RB_TY - 1) / RB_TY;
       }
-      rr = hs.rr;
-      if (rr <= tol2 || (restarts > 0 && rr <= 1e-12 * last_true)) {
-        // recompute the true residual (the CG recurrence drifts from it)
-        hipLaunchKernelGGL(k_resid_init, dim3(RB), dim3(EBIT_BLOCK), 0, st, op, b, (const double*)x, B->r,
-                           B->partial);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, (const double*)B->partial, RB, 3, B->scal,
-                           (int)FIN_INIT, 0);
-        CK(hipGetLastError());
-        CK(read_scal(B->scal, &hs, st));
-        rr = hs.rr;
-        floor2 = fc * fc * hs.aa;
+      TailArgs<T>& ta = C.tail;
+      ta.nl = pc.nlev - lt[c];
+      ta.nu1 = o->nu1;
+      ta.nu2 = o->nu2;
+      long long off = 0;
+      for (int m = 0; m < ta.nl; ++m) {
+        const EbitLevelHost& L = pc.lv[lt[c] + m];
+        ta.L[m].d = L.d;
+        ta.L[m].base = (int)off;
+        const CoarseOp<T> co = coarse_op_of<T>(L, sys);
+        ta.diag[m] = co.diag;
+        for (int q = 0; q < 3; ++q) ta.off[m][q] = co.off[q];
+        off += tail_level_elems(L.d);
+      }
+      ta.bg = lvb<T>(pc.lv[lt[c]]);
+      ta.xg = lvx<T>(pc.lv[lt[c]], 0);
+      if (sys == 0) {
+        const int fgz = (fd.n[2] + C.fzc - 1) / C.fzc;
+        efine.push_back({c, C.fgx * C.fgy * fgz});
+        efr.push_back({c, (int)nblk(pc.lv[1].d.N)});
+        ered.push_back({c, C.nred});
+        for (int l = 1; l < lt[c]; ++l) {
+          const Dims& d = pc.lv[l].d;
+          ecs[l].push_back({c, C.lgx[l] * C.lgy[l] * ((d.n[2] + C.lzc[l] - 1) / C.lzc[l])});
+          ecr[l].push_back({c, (int)nblk(pc.lv[l + 1].d.N)});
+        }
+      }
+    }
+  std::vector<int> host;
+  P->fine = make_list(efine, host, d_wl);
+  P->frestrict = make_list(efr, host, d_wl);
+  P->red = make_list(ered, host, d_wl);
+  for (int l = 1; l < P->Lmax; ++l) {
+    P->coarse[l] = make_list(ecs[l], host, d_wl);
+    P->crestrict[l] = make_list(ecr[l], host, d_wl);
+  }
+  if ((e = hipMemcpyAsync(d_wl, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, P->ist)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(P->ist);
+}
+
+template <typename T>
+void plan_destroy_t(PlanT<T>* P) {
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k <= PLAN_MAX_K; ++k)
+      if (P->graph[s][k]) (void)hipGraphExecDestroy(P->graph[s][k]);
+  if (P->ist) {
+    (void)hipStreamSynchronize(P->ist);
+    (void)hipStreamDestroy(P->ist);
+  }
+  if (P->ev_in) (void)hipEventDestroy(P->ev_in);
+  if (P->ev_out) (void)hipEventDestroy(P->ev_out);
+  for (int s = 0; s < 2; ++s)
+    if (P->h_cs[s]) (void)hipHostFree(P->h_cs[s]);
+  if (P->h_ctl) (void)hipHostFree(P->h_ctl);
+  if (P->h_stop2) (void)hipHostFree(P->h_stop2);
+  if (P->h_sc) (void)hipHostFree(P->h_sc);
+  delete P;
+}
+
+// The outer loop of every case of the plan, to rel. residual rtol.  Status
+// per case: 0 converged, 1 max_iters or stagnation above the rounding floor,
+// 2 NaN/Inf.  Returns a HIP error, if any.
+template <typename T>
+hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, hipStream_t ust, EbitProfiler* pf,
+                        EbitSolveOut* out) {
+  const int n = P.n;
+  const ebit_opts& o = P.o;
+  const int dc = o.outer == EBIT_OUTER_DC;
+  hipStream_t st = P.ist;
+  hipError_t e;
+#define PK(expr)                          \
+  do {                                    \
+    if ((e = (expr)) != hipSuccess) return e; \
+  } while (0)
+  for (int c = 0; c < n; ++c) {
+    P.h_cs[sys][c].op = P.cases[c].op[sys];
+    P.h_cs[sys][c].x = x[c];
+    P.h_ctl[c] = CaseCtl{1, 1, 0, 0};
+    P.h_stop2[c] = 0.0;
+  }
+  const SolveCase<T>* cs = P.d_cs[sys];
+  PK(hipEventRecord(P.ev_in, ust));
+  PK(hipStreamWaitEvent(st, P.ev_in, 0));
+  PK(hipMemcpyAsync(P.d_cs[sys], P.h_cs[sys], n * sizeof(SolveCase<T>), hipMemcpyHostToDevice, st));
+  PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
+  PK(hipMemcpyAsync(P.d_stop2, P.h_stop2, n * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(kb_scal_reset<T>, dim3(n), dim3(64), 0, st, cs);
+  if (!use_guess)
+    hipLaunchKernelGGL(kb_zero_x<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                       P.red.w, (int)MASK_ALL);
+  hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                     P.red.w, (int)MASK_ALL, use_guess ? 1 : 0);
+  hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2, (int)FIN_INIT,
+                     3, (int)MASK_ALL, dc);
+  PK(hipGetLastError());
+  PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
+  PK(hipStreamSynchronize(st));
+  const double fc = 2.220446049250313e-16;
+  std::vector<int> status(n, -1), restarts(n, 0), at_floor(n, 0);
+  std::vector<double> tol2(n), floor2(n), last_true(n), bb(n);
+  bool zero_fill = false;
+  for (int c = 0; c < n; ++c) {
+    const Scal& S = P.h_sc[c];
+    bb[c] = S.bb;
+    tol2[c] = o.rtol * o.rtol * S.bb;
+    floor2[c] = fc * fc * S.aa;
+    last_true[c] = S.rr;
+    P.h_ctl[c] = CaseCtl{0, 1, 0, 0};
+    if (S.err & ERR_NAN) {
+      status[c] = 2;
+    } else if (S.bb == 0.0) {
+      status[c] = 0;  // b = 0: x = 0
+      P.h_ctl[c].recheck = 1;
+      zero_fill = true;
+    } else if (S.rr <= tol2[c]) {
+      status[c] = 0;
+    } else {
+      P.h_ctl[c].active = 1;
+      P.h_stop2[c] = tol2[c];
+    }
+  }
+  PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
+  PK(hipMemcpyAsync(P.d_stop2, P.h_stop2, n * sizeof(double), hipMemcpyHostToDevice, st));
+  if (zero_fill) {
+    hipLaunchKernelGGL(kb_zero_x<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                       P.red.w, (int)MASK_RECHECK);
+    for (int c = 0; c < n; ++c) P.h_ctl[c].recheck = 0;
+    PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
+  }
+  const int check = o.check_every > 0 ? o.check_every : 1;
+  for (;;) {
+    int K = check;
+    int running = 0;
+    for (int c = 0; c < n; ++c)
+      if (status[c] < 0) {
+        ++running;
+        const int left = o.max_iters - P.h_sc[c].iters;
+        if (left < K) K = left;
+      }
+    if (running == 0) break;
+    if (K < 1) K = 1;
+    PK(run_block(P, sys, K, pf));
+    PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
+    PK(hipMemcpyAsync(P.h_ctl, P.d_ctl, n * sizeof(CaseCtl), hipMemcpyDeviceToHost, st));
+    PK(hipStreamSynchronize(st));
+    int nre = 0;
+    for (int c = 0; c < n; ++c) {
+      if (status[c] >= 0) continue;
+      const Scal& S = P.h_sc[c];
+      if (S.err & ERR_NAN) {
+        status[c] = 2;
+        P.h_ctl[c].active = 0;
+      } else if (!P.h_ctl[c].active) {
+        P.h_ctl[c].recheck = 1;  // r.r reached its stop level: recompute the true residual
+        ++nre;
+      } else if (S.iters >= o.max_iters) {
+        status[c] = 1;
+        P.h_ctl[c].active = 0;
+      }
+    }
+    if (nre) {
+      PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                         P.red.w, (int)MASK_RECHECK, 1);
+      hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
+                         (int)FIN_INIT, 3, (int)MASK_RECHECK, dc);
+      PK(hipGetLastError());
+      PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
+      PK(hipStreamSynchronize(st));
+      for (int c = 0; c < n; ++c) {
+        if (!P.h_ctl[c].recheck) continue;
+        P.h_ctl[c].recheck = 0;
+        const Scal& S = P.h_sc[c];
+        if (S.err & ERR_NAN) {
+          status[c] = 2;
+          continue;
+        }
+        const double rr = S.rr;
+        floor2[c] = fc * fc * S.aa;
         // At the representability floor the residual no longer tracks the
         // error, but the compensated residual still carries it: take two more
         // restart cycles there before stopping.
-        const bool stagnant = restarts > 0 && rr > 0.25 * last_true;
-        if (stagnant && rr <= floor2) ++at_floor;
-        if (rr <= tol2 || at_floor >= 2) {
-          conv = true;
-          break;
+        const bool stagnant = restarts[c] > 0 && rr > 0.25 * last_true[c];
+        if (stagnant && rr <= floor2[c]) ++at_floor[c];
+        if (rr <= tol2[c] || at_floor[c] >= 2) {
+          status[c] = 0;
+        } else if (restarts[c] >= 8 || (stagnant && rr > floor2[c]) || S.iters >= o.max_iters) {
+          status[c] = 1;
+        } else {
+          // restart the recurrence from the recomputed residual
+          ++restarts[c];
+          last_true[c] = rr;
+          P.h_ctl[c].active = 1;
+          P.h_ctl[c].fresh = 1;
+          P.h_stop2[c] = fmax(tol2[c], 1e-12 * rr);
         }
-        if (restarts >= 8 || (stagnant && rr > floor2)) break;
-        ++restarts;
-        last_true = rr;
-        first = 1;  // restart the recurrence from the recomputed residual
       }
     }
+    PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
+    PK(hipMemcpyAsync(P.d_stop2, P.h_stop2, n * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  *floor = sqrt(floor2 / bb);
-  *iters = it;
-  *relres = sqrt(rr / bb);
-  return conv ? 0 : 1;
-#undef CK
+  PK(hipEventRecord(P.ev_out, st));
+  PK(hipStreamWaitEvent(ust, P.ev_out, 0));
+  for (int c = 0; c < n; ++c) {
+    const Scal& S = P.h_sc[c];
+    EbitSolveOut& r = out[c];
+    r.status = status[c] < 0 ? 1 : status[c];
+    r.iters = S.iters;
+    r.bnorm = sqrt(bb[c]);
+    r.rel_res = bb[c] > 0 ? sqrt(S.rr / bb[c]) : 0.0;
+    r.res_floor = bb[c] > 0 ? sqrt(floor2[c] / bb[c]) : 0.0;
+  }
+  return hipSuccess;
+#undef PK
 }
 
-}  // namespace ebit
+}  // namespace
 
-extern "C" int ebit_solve_stream(const FineOp* op, const EbitLevelHost* lv, int nlev, const EbitSolveBufs* B,
-                                 const double* b, double* x, int use_guess, const ebit_opts* o, hipStream_t st,
-                                 int* iters, int* vcyc, double* relres, double* bnorm, double* floor,
-                                 hipError_t* herr) {
-  if (o->precision == EBIT_MIXED)
-    return ebit::solve_t<float>(*op, lv, nlev, B, b, x, use_guess, o, st, iters, vcyc, relres, bnorm, floor, herr);
-  return ebit::solve_t<double>(*op, lv, nlev, B, b, x, use_guess, o, st, iters, vcyc, relres, bnorm, floor, herr);
+struct EbitPlan {
+  int precision;
+  PlanT<float>* f;
+  PlanT<double>* d;
+};
+
+extern "C" {
+
+size_t ebit_plan_device_bytes(int ncases, int precision) {
+  PCarver cv{nullptr, 0};
+  if (precision == EBIT_MIXED) return plan_carve<float>(ncases, cv, nullptr, nullptr);
+  return plan_carve<double>(ncases, cv, nullptr, nullptr);
 }
+
+hipError_t ebit_plan_create(EbitPlan** out, int ncases, const EbitPlanCase* cases, const ebit_opts* o, int tail_lds,
+                            void* mem, size_t bytes) {
+  *out = nullptr;
+  EbitPlan* p = new (std::nothrow) EbitPlan{o->precision, nullptr, nullptr};
+  if (!p) return hipErrorOutOfMemory;
+  hipError_t e;
+  if (o->precision == EBIT_MIXED) {
+    p->f = new (std::nothrow) PlanT<float>;
+    e = p->f ? plan_create_t<float>(p->f, ncases, cases, o, tail_lds, mem, bytes) : hipErrorOutOfMemory;
+  } else {
+    p->d = new (std::nothrow) PlanT<double>;
+    e = p->d ? plan_create_t<double>(p->d, ncases, cases, o, tail_lds, mem, bytes) : hipErrorOutOfMemory;
+  }
+  if (e != hipSuccess) {
+    ebit_plan_destroy(p);
+    return e;
+  }
+  *out = p;
+  return hipSuccess;
+}
+
+void ebit_plan_destroy(EbitPlan* p) {
+  if (!p) return;
+  if (p->f) plan_destroy_t(p->f);
+  if (p->d) plan_destroy_t(p->d);
+  delete p;
+}
+
+hipError_t ebit_plan_solve(EbitPlan* p, int sys, double* const* x, int use_guess, hipStream_t ust, EbitProfiler* pf,
+                           EbitSolveOut* out) {
+  if (p->f) return plan_solve_t<float>(*p->f, sys, x, use_guess, ust, pf, out);
+  return plan_solve_t<double>(*p->d, sys, x, use_guess, ust, pf, out);
+}
+
+}  // extern "C"
