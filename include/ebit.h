@@ -107,9 +107,14 @@ typedef struct {
   int nu1, nu2;       /* red-black Gauss-Seidel sweeps before / after the
                          coarse correction, 1..8 each [2, 2]                  */
   double theta_min;   /* lower clamp of theta in the 1/theta terms [1e-3]     */
-  int check_every;    /* outer iterations between host residual checks [1]    */
-  int tail_cells;     /* levels with at most this many cells are smoothed by
-                         one work-group [4096]; 0 disables                    */
+  int check_every;    /* outer iterations per block between host checks [1]:
+                         a block is captured once as a hipGraph and replayed;
+                         a case that meets its stop level inside a block
+                         skips the rest of it on the device, so results do
+                         not depend on this value, only the host round trips */
+  int tail_cells;     /* levels with at most this many cells (and that fit
+                         the work-group's LDS) are solved by one work-group
+                         kernel; the coarsest level always is [4096]          */
 } ebit_opts;
 
 typedef struct {
@@ -230,6 +235,41 @@ ebit_status ebit_profile_read(ebit_ctx* ctx, int kernel_class, long long* launch
 
 /* Levels of the multigrid hierarchy and their sizes (host outputs). */
 ebit_status ebit_levels(const ebit_ctx* ctx, int* nlevels, int* sizes /* [3*nlevels] */);
+
+/* ---- batches of independent cases --------------------------------------
+ * A batch groups existing contexts (any grid sizes, one dim, equal solver
+ * options except theta_min) so that every kernel of a solve is ONE launch
+ * over all cases: a work list maps each launch's blocks onto (case, block),
+ * and a per-case active mask lets converged cases drop out while the others
+ * iterate.  The other steps (geometry, right-hand sides, mass flux, face
+ * update) are launched case by case on the batch stream.  Results per case
+ * equal those of the same calls on each context.  While a batch call runs,
+ * its contexts must not be used on their own; the batch never frees them.
+ * Arrays of per-case pointers are HOST arrays of DEVICE pointers; marker,
+ * u_l and u_v hold 3 entries per case (entry 3 c + a). */
+typedef struct ebit_batch ebit_batch;
+
+/* Device workspace of a batch of ncases (plan tables and work lists). */
+size_t ebit_batch_workspace_bytes(int ncases, const ebit_opts* opts);
+/* ws: >= ebit_batch_workspace_bytes(ncases, &opts of ctx[0]) bytes, 256-byte
+ * aligned, caller-owned.  EBIT_EINVAL if the contexts differ in dim or in
+ * the solver options above, or a context appears twice. */
+ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[], void* workspace, size_t bytes,
+                              void* hip_stream);
+ebit_status ebit_batch_destroy(ebit_batch* batch);
+const char* ebit_batch_last_error(const ebit_batch* batch);
+/* ebit_build_coeffs of every case (one synchronisation for all geometry
+ * checks); dt[] per case. */
+ebit_status ebit_batch_build_coeffs(ebit_batch* batch, const double* const marker[], const uint8_t* const vcol[],
+                                    const uint8_t* const ccol[], const double dt[]);
+/* ebit_heat_solve / ebit_mass_flux / ebit_project of every case; stats[]
+ * (may be NULL) gets each case's figures and status, seconds = the whole
+ * batch call; the return value is the first failing case's status. */
+ebit_status ebit_batch_heat_solve(ebit_batch* batch, const double* const T_star[], double* const T[], int use_guess,
+                                  ebit_stats stats[]);
+ebit_status ebit_batch_mass_flux(ebit_batch* batch, const double* const T[], double* const mdot[], ebit_stats stats[]);
+ebit_status ebit_batch_project(ebit_batch* batch, double* const u_l[], double* const u_v[], const double* const mdot[],
+                               double* const p[], int use_guess, ebit_stats stats[]);
 
 #ifdef __cplusplus
 }

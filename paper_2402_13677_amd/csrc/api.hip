@@ -36,6 +36,20 @@ struct ebit_ctx {
   char msg[512];
 };
 
+// A batch of contexts whose solves share one plan: every kernel of a solve
+// is one launch over all cases.
+struct ebit_batch {
+  int n;
+  ebit_ctx** ctx;
+  ebit_opts opts;
+  hipStream_t st;
+  EbitPlan* plan;
+  hipEvent_t ev0, ev1;
+  Scal* hsc;  // host copies of the contexts' status scalars
+  hipError_t herr;
+  char msg[512];
+};
+
 namespace {
 
 const size_t ALIGN = 256;
@@ -330,6 +344,37 @@ ebit_status run_solve(ebit_ctx* c, int sys, double* x, int use_guess, ebit_stats
   return s;
 }
 
+// First half of a coefficient build: argument checks and the geometry pass
+// (cut fractions, flags, facets); its error bits land in the context's Scal.
+ebit_status build_launch(ebit_ctx* c, const double* const marker[3], const uint8_t* vcol, const uint8_t* ccol,
+                         double dt, hipStream_t st) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  if (!marker || !vcol || !ccol) return fail(c, EBIT_EINVAL, "NULL marker or colour array");
+  for (int a = 0; a < c->grid.dim; ++a)
+    if (!marker[a]) return fail(c, EBIT_EINVAL, "NULL marker array");
+  if (!(dt > 0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be positive");
+  c->built = 0;
+  c->dt = dt;
+  HIPCK(c, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)c->B.scal, 0.0, st), "reset");
+  HIPCK(c, ebit_launch_geometry(&c->fd, c->grid.h, marker, vcol, ccol, c->flags, c->cF, c->nF, c->th, c->B.scal, st),
+        "geometry");
+  return EBIT_OK;
+}
+
+// Second half: report geometry errors, then the operators and hierarchies.
+ebit_status build_finish(ebit_ctx* c, const Scal& hs, hipStream_t st) {
+  if (hs.err & ERR_GEOM_MARKER) return fail(c, EBIT_EGEOM, "a marker is inconsistent with the vertex colours");
+  if (hs.err & ERR_GEOM_SEAM) return fail(c, EBIT_EGEOM, "periodic seam markers or colours disagree");
+  if (hs.err & ERR_GEOM_NOFACET) return fail(c, EBIT_EGEOM, "a cut link has no interface cell on either side");
+  set_ops(c);
+  const int want32 = c->opts.precision == EBIT_MIXED;
+  for (int sys = 0; sys < 2; ++sys)
+    HIPCK(c, ebit_build_hierarchy(&c->op[sys], c->lv, c->nlev, sys, want32, st), "hierarchy");
+  c->built = 1;
+  return EBIT_OK;
+}
+
 void stats_init(ebit_stats* s) {
   if (!s) return;
   memset(s, 0, sizeof(*s));
@@ -435,31 +480,12 @@ const char* ebit_last_error(const ebit_ctx* c) { return c ? c->msg : "null conte
 
 ebit_status ebit_build_coeffs(ebit_ctx* c, const double* const marker[3], const uint8_t* vcol, const uint8_t* ccol,
                               double dt) {
-  if (!c) return EBIT_EINVAL;
-  if (c->herr != hipSuccess) return EBIT_EHIP;
-  if (!marker || !vcol || !ccol) return fail(c, EBIT_EINVAL, "NULL marker or colour array");
-  for (int a = 0; a < c->grid.dim; ++a)
-    if (!marker[a]) return fail(c, EBIT_EINVAL, "NULL marker array");
-  if (!(dt > 0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be positive");
-  c->built = 0;
-  c->dt = dt;
-  HIPCK(c, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)c->B.scal, 0.0, c->st),
-        "reset");
-  HIPCK(c,
-        ebit_launch_geometry(&c->fd, c->grid.h, marker, vcol, ccol, c->flags, c->cF, c->nF, c->th, c->B.scal, c->st),
-        "geometry");
+  ebit_status s = build_launch(c, marker, vcol, ccol, dt, c ? c->st : nullptr);
+  if (s != EBIT_OK) return s;
   Scal hs;
   HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "geometry status");
   HIPCK(c, hipStreamSynchronize(c->st), "geometry sync");
-  if (hs.err & ERR_GEOM_MARKER) return fail(c, EBIT_EGEOM, "a marker is inconsistent with the vertex colours");
-  if (hs.err & ERR_GEOM_SEAM) return fail(c, EBIT_EGEOM, "periodic seam markers or colours disagree");
-  if (hs.err & ERR_GEOM_NOFACET) return fail(c, EBIT_EGEOM, "a cut link has no interface cell on either side");
-  set_ops(c);
-  const int want32 = c->opts.precision == EBIT_MIXED;
-  for (int sys = 0; sys < 2; ++sys)
-    HIPCK(c, ebit_build_hierarchy(&c->op[sys], c->lv, c->nlev, sys, want32, c->st), "hierarchy");
-  c->built = 1;
-  return EBIT_OK;
+  return build_finish(c, hs, c->st);
 }
 
 ebit_status ebit_heat_solve(ebit_ctx* c, const double* Ts, double* T, int use_guess, ebit_stats* st) {
@@ -640,6 +666,262 @@ ebit_status ebit_levels(const ebit_ctx* c, int* nlevels, int* sizes) {
     for (int l = 0; l < c->nlev; ++l)
       for (int a = 0; a < 3; ++a) sizes[3 * l + a] = c->lv[l].d.n[a];
   return EBIT_OK;
+}
+
+/* ---- batches ---------------------------------------------------------- */
+
+size_t ebit_batch_workspace_bytes(int ncases, const ebit_opts* o) {
+  if (ncases < 1) return 0;
+  const size_t b = ebit_plan_device_bytes(ncases, o ? o->precision : EBIT_FP64);
+  return (b + ALIGN - 1) / ALIGN * ALIGN;
+}
+
+ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[], void* ws, size_t bytes,
+                              void* stream) {
+  if (!out) return EBIT_EINVAL;
+  *out = nullptr;
+  if (ncases < 1 || !ctx || !ws || ((uintptr_t)ws % ALIGN) != 0) return EBIT_EINVAL;
+  for (int c = 0; c < ncases; ++c) {
+    if (!ctx[c] || ctx[c]->herr != hipSuccess) return EBIT_EINVAL;
+    const ebit_opts& a = ctx[0]->opts;
+    const ebit_opts& b = ctx[c]->opts;
+    if (ctx[c]->grid.dim != ctx[0]->grid.dim || a.precision != b.precision || a.outer != b.outer ||
+        a.rtol != b.rtol || a.max_iters != b.max_iters || a.nu1 != b.nu1 || a.nu2 != b.nu2 ||
+        a.check_every != b.check_every || a.tail_cells != b.tail_cells)
+      return EBIT_EINVAL;
+    for (int q = 0; q < c; ++q)
+      if (ctx[q] == ctx[c]) return EBIT_EINVAL;
+  }
+  if (bytes < ebit_batch_workspace_bytes(ncases, &ctx[0]->opts)) return EBIT_ENOMEM;
+  ebit_batch* b = new (std::nothrow) ebit_batch;
+  if (!b) return EBIT_ENOMEM;
+  memset(b, 0, sizeof(*b));
+  b->n = ncases;
+  b->opts = ctx[0]->opts;
+  b->st = (hipStream_t)stream;
+  b->ctx = new (std::nothrow) ebit_ctx*[ncases];
+  b->hsc = new (std::nothrow) Scal[ncases];
+  EbitPlanCase* pc = new (std::nothrow) EbitPlanCase[ncases];
+  if (!b->ctx || !b->hsc || !pc) {
+    delete[] b->ctx;
+    delete[] b->hsc;
+    delete[] pc;
+    delete b;
+    return EBIT_ENOMEM;
+  }
+  for (int c = 0; c < ncases; ++c) {
+    b->ctx[c] = ctx[c];
+    pc[c] = EbitPlanCase{ctx[c]->lv, ctx[c]->nlev, ctx[c]->op, ctx[c]->B, ctx[c]->bvec};
+  }
+  hipError_t e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess) e = ebit_plan_create(&b->plan, ncases, pc, &b->opts, ctx[0]->B.tail_lds, ws, bytes);
+  delete[] pc;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ebit_batch_destroy(b);
+    return EBIT_EHIP;
+  }
+  *out = b;
+  return EBIT_OK;
+}
+
+ebit_status ebit_batch_destroy(ebit_batch* b) {
+  if (!b) return EBIT_EINVAL;
+  ebit_plan_destroy(b->plan);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete[] b->ctx;
+  delete[] b->hsc;
+  delete b;
+  return EBIT_OK;
+}
+
+const char* ebit_batch_last_error(const ebit_batch* b) { return b ? b->msg : "null batch"; }
+
+}  // extern "C"
+
+namespace {
+
+ebit_status bfail(ebit_batch* b, ebit_status s, int c, const char* what) {
+  snprintf(b->msg, sizeof(b->msg), "case %d: %s", c, what);
+  return s;
+}
+
+ebit_status bhip(ebit_batch* b, hipError_t e, const char* where) {
+  b->herr = e;
+  snprintf(b->msg, sizeof(b->msg), "%s: %s", where, hipGetErrorString(e));
+  return EBIT_EHIP;
+}
+
+#define BHIPCK(b, expr, where)                          \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return bhip(b, _e, where);    \
+  } while (0)
+
+// copy every context's status scalars to b->hsc (one synchronisation)
+ebit_status batch_read_scal(ebit_batch* b) {
+  for (int c = 0; c < b->n; ++c)
+    BHIPCK(b, hipMemcpyAsync(&b->hsc[c], b->ctx[c]->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, b->st), "status");
+  BHIPCK(b, hipStreamSynchronize(b->st), "sync");
+  return EBIT_OK;
+}
+
+ebit_status batch_ready(ebit_batch* b) {
+  if (!b) return EBIT_EINVAL;
+  if (b->herr != hipSuccess) return EBIT_EHIP;
+  for (int c = 0; c < b->n; ++c) {
+    ebit_status s = check_ready(b->ctx[c]);
+    if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
+  }
+  return EBIT_OK;
+}
+
+// per-case solve results into stats; the first failing status is returned
+ebit_status batch_results(ebit_batch* b, const EbitSolveOut* r, ebit_stats* stats, double seconds) {
+  ebit_status first = EBIT_OK;
+  for (int c = 0; c < b->n; ++c) {
+    ebit_stats* st = stats ? &stats[c] : nullptr;
+    if (st) memset(st, 0, sizeof(*st));
+    const ebit_status s = solve_status(r[c], st);
+    if (st) {
+      st->seconds = seconds;
+      st->status = s;
+    }
+    if (s != EBIT_OK && first == EBIT_OK) {
+      first = s;
+      bfail(b, s, c, s == EBIT_ENAN ? "NaN or Inf in a residual norm" : "no convergence within max_iters");
+    }
+  }
+  return first;
+}
+
+}  // namespace
+
+extern "C" {
+
+ebit_status ebit_batch_build_coeffs(ebit_batch* b, const double* const marker[], const uint8_t* const vcol[],
+                                    const uint8_t* const ccol[], const double dt[]) {
+  if (!b) return EBIT_EINVAL;
+  if (b->herr != hipSuccess) return EBIT_EHIP;
+  if (!marker || !vcol || !ccol || !dt) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  for (int c = 0; c < b->n; ++c) {
+    const ebit_status s = build_launch(b->ctx[c], marker + 3 * c, vcol[c], ccol[c], dt[c], b->st);
+    if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
+  }
+  ebit_status s = batch_read_scal(b);
+  if (s != EBIT_OK) return s;
+  for (int c = 0; c < b->n; ++c) {
+    s = build_finish(b->ctx[c], b->hsc[c], b->st);
+    if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
+  }
+  return EBIT_OK;
+}
+
+ebit_status ebit_batch_heat_solve(ebit_batch* b, const double* const T_star[], double* const T[], int use_guess,
+                                  ebit_stats stats[]) {
+  ebit_status s = batch_ready(b);
+  if (s != EBIT_OK) return s;
+  if (!T_star || !T) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  for (int c = 0; c < b->n; ++c)
+    if (!T_star[c] || !T[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
+  BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
+  for (int c = 0; c < b->n; ++c)
+    BHIPCK(b, ebit_launch_heat_rhs(&b->ctx[c]->op[EBIT_SYS_HEAT], T_star[c], b->ctx[c]->bvec, b->st), "heat rhs");
+  EbitSolveOut* r = new (std::nothrow) EbitSolveOut[b->n];
+  if (!r) return EBIT_ENOMEM;
+  const hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_HEAT, T, use_guess, b->st, nullptr, r);
+  if (e != hipSuccess) {
+    delete[] r;
+    return bhip(b, e, "solve");
+  }
+  float ms = 0;
+  if (hipEventRecord(b->ev1, b->st) == hipSuccess && hipEventSynchronize(b->ev1) == hipSuccess)
+    (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+  s = batch_results(b, r, stats, ms * 1e-3);
+  delete[] r;
+  return s;
+}
+
+ebit_status ebit_batch_mass_flux(ebit_batch* b, const double* const T[], double* const mdot[], ebit_stats stats[]) {
+  ebit_status s = batch_ready(b);
+  if (s != EBIT_OK) return s;
+  if (!T || !mdot) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
+  for (int c = 0; c < b->n; ++c) {
+    ebit_ctx* x = b->ctx[c];
+    if (!T[c] || !mdot[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
+    BHIPCK(b, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)x->B.scal, 0.0, b->st),
+           "reset");
+    const double lam[2] = {x->props.lam_v, x->props.lam_l};
+    BHIPCK(b,
+           ebit_launch_mass_flux(&x->fd, x->grid.h, lam, x->props.h_lg, x->props.T_sat, x->opts.theta_min, x->flags,
+                                 x->th, x->cF, x->nF, T[c], mdot[c], nullptr, x->B.scal, b->st),
+           "mass flux");
+  }
+  BHIPCK(b, hipEventRecord(b->ev1, b->st), "event");
+  s = batch_read_scal(b);
+  if (s != EBIT_OK) return s;
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+  if (stats)
+    for (int c = 0; c < b->n; ++c) {
+      memset(&stats[c], 0, sizeof(stats[c]));
+      stats[c].seconds = ms * 1e-3;
+      stats[c].fallbacks = b->hsc[c].fallbacks;
+    }
+  return EBIT_OK;
+}
+
+ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const u_v[], const double* const mdot[],
+                               double* const p[], int use_guess, ebit_stats stats[]) {
+  ebit_status s = batch_ready(b);
+  if (s != EBIT_OK) return s;
+  if (!u_l || !u_v || !mdot || !p) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
+  for (int c = 0; c < b->n; ++c) {
+    ebit_ctx* x = b->ctx[c];
+    if (!mdot[c] || !p[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
+    for (int a = 0; a < x->grid.dim; ++a)
+      if (!u_l[3 * c + a] || !u_v[3 * c + a]) return bfail(b, EBIT_EINVAL, c, "NULL velocity array");
+    const double rho[2] = {x->props.rho_v, x->props.rho_l};
+    BHIPCK(b,
+           ebit_launch_proj_rhs(&x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val, x->flags, x->th, x->nF,
+                                mdot[c], u_l + 3 * c, u_v + 3 * c, x->bvec, b->st),
+           "projection rhs");
+  }
+  EbitSolveOut* r = new (std::nothrow) EbitSolveOut[b->n];
+  if (!r) return EBIT_ENOMEM;
+  const hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_PRESSURE, p, use_guess, b->st, nullptr, r);
+  if (e != hipSuccess) {
+    delete[] r;
+    return bhip(b, e, "solve");
+  }
+  for (int c = 0; c < b->n; ++c) {
+    ebit_ctx* x = b->ctx[c];
+    const double rho[2] = {x->props.rho_v, x->props.rho_l};
+    const hipError_t e2 = ebit_launch_face_update(&x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val,
+                                                  x->flags, x->th, u_l + 3 * c, u_v + 3 * c, p[c], x->B.partial,
+                                                  x->B.scal, b->st);
+    if (e2 != hipSuccess) {
+      delete[] r;
+      return bhip(b, e2, "face update");
+    }
+  }
+  BHIPCK(b, hipEventRecord(b->ev1, b->st), "event");
+  s = batch_read_scal(b);
+  if (s != EBIT_OK) {
+    delete[] r;
+    return s;
+  }
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+  s = batch_results(b, r, stats, ms * 1e-3);
+  if (stats)
+    for (int c = 0; c < b->n; ++c) stats[c].div_max = b->hsc[c].divmax;
+  delete[] r;
+  return s;
 }
 
 }  // extern "C"

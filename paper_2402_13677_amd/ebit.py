@@ -81,6 +81,16 @@ def load():
         "ebit_levels": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "ebit_profile": (i, [vp, i]),
         "ebit_profile_read": (i, [vp, i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]),
+        "ebit_batch_workspace_bytes": (ctypes.c_size_t, [i, ctypes.POINTER(Opts)]),
+        "ebit_batch_create": (i, [ctypes.POINTER(vp), i, ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]),
+        "ebit_batch_destroy": (i, [vp]),
+        "ebit_batch_last_error": (ctypes.c_char_p, [vp]),
+        "ebit_batch_build_coeffs": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(d)]),
+        "ebit_batch_heat_solve": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i, ctypes.POINTER(Stats)]),
+        "ebit_batch_mass_flux": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Stats)]),
+        "ebit_batch_project": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), i, ctypes.POINTER(Stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -93,7 +103,9 @@ def load():
 EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "ebit_create", "ebit_destroy",
             "ebit_last_error", "ebit_build_coeffs", "ebit_heat_solve", "ebit_mass_flux", "ebit_project",
             "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_project_rhs", "ebit_levels",
-            "ebit_profile", "ebit_profile_read"]
+            "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
+            "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
+            "ebit_batch_mass_flux", "ebit_batch_project"]
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 
 
@@ -254,6 +266,84 @@ class Context:
         sizes = (ctypes.c_int * (3 * 32))()
         self._check(self.lib.ebit_levels(self.h, ctypes.byref(n), sizes), "ebit_levels")
         return [tuple(sizes[3 * l: 3 * l + 3]) for l in range(n.value)]
+
+
+def _ptrs(ts, dtype=torch.float64, per=1):
+    """Host array of device pointers; per = 3 pads each case's list to 3."""
+    vals = []
+    for t in ts:
+        if per == 1:
+            vals.append(_ptr(t, dtype).value)
+        else:
+            for a in range(per):
+                vals.append(_ptr(t[a], dtype).value if a < len(t) and t[a] is not None else None)
+    return (ctypes.c_void_p * len(vals))(*vals)
+
+
+class Batch:
+    """Contexts whose solves run as one launch per kernel over all cases."""
+
+    def __init__(self, contexts: Sequence[Context], device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        lib = load()
+        self.lib = lib
+        self.contexts = list(contexts)
+        n = len(self.contexts)
+        opts = self.contexts[0].opts
+        nbytes = lib.ebit_batch_workspace_bytes(n, ctypes.byref(opts))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        hs = (ctypes.c_void_p * n)(*[c.h.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        st = lib.ebit_batch_create(ctypes.byref(h), n, hs, ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes),
+                                   ctypes.c_void_p(self.stream.cuda_stream))
+        if st != OK:
+            raise EbitError(st, "ebit_batch_create")
+        self.h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ebit_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, where):
+        if st != OK:
+            raise EbitError(st, where, self.lib.ebit_batch_last_error(self.h).decode())
+
+    def _stats(self):
+        return (Stats * self.n)()
+
+    def build_coeffs(self, markers, vcols, ccols, dts):
+        self._check(self.lib.ebit_batch_build_coeffs(self.h, _ptrs(markers, per=3), _ptrs(vcols, torch.uint8),
+                                                     _ptrs(ccols, torch.uint8), (ctypes.c_double * self.n)(*dts)),
+                    "ebit_batch_build_coeffs")
+
+    def heat_solve(self, T_star, T, use_guess=False, check=True):
+        s = self._stats()
+        st = self.lib.ebit_batch_heat_solve(self.h, _ptrs(T_star), _ptrs(T), int(use_guess), s)
+        if check:
+            self._check(st, "ebit_batch_heat_solve")
+        return [x.as_dict() for x in s]
+
+    def mass_flux(self, T, mdot):
+        s = self._stats()
+        self._check(self.lib.ebit_batch_mass_flux(self.h, _ptrs(T), _ptrs(mdot), s), "ebit_batch_mass_flux")
+        return [x.as_dict() for x in s]
+
+    def project(self, u_l, u_v, mdot, p, use_guess=False, check=True):
+        s = self._stats()
+        st = self.lib.ebit_batch_project(self.h, _ptrs(u_l, per=3), _ptrs(u_v, per=3), _ptrs(mdot), _ptrs(p),
+                                         int(use_guess), s)
+        if check:
+            self._check(st, "ebit_batch_project")
+        return [x.as_dict() for x in s]
 
 
 # ---------------------------------------------------------------------------

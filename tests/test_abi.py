@@ -66,3 +66,14 @@ def test_workspace_scales_with_cells():
     g64 = ebit.make_grid(3, (64, 64, 64), 1 / 64, f.T_bc, f.p_bc)
     n64 = _bytes(g64)
     assert 7.0 < n64 / n32 < 9.0
+
+
+def test_batch_workspace_bytes():
+    lib = ebit.load()
+    o = ebit.default_opts()
+    assert lib.ebit_batch_workspace_bytes(0, ctypes.byref(o)) == 0
+    b1 = lib.ebit_batch_workspace_bytes(1, ctypes.byref(o))
+    b64 = lib.ebit_batch_workspace_bytes(64, ctypes.byref(o))
+    assert b1 > 0 and b64 > 32 * b1
+    om = ebit.default_opts(precision=ebit.MIXED)
+    assert lib.ebit_batch_workspace_bytes(64, ctypes.byref(om)) > 0
