@@ -271,6 +271,23 @@ ebit_status ebit_batch_mass_flux(ebit_batch* batch, const double* const T[], dou
 ebit_status ebit_batch_project(ebit_batch* batch, double* const u_l[], double* const u_v[], const double* const mdot[],
                                double* const p[], int use_guess, ebit_stats stats[]);
 
+/* ---- autotuning ----------------------------------------------------------
+ * Pick the solve schedule -- sweeps nu1 = nu2 in {1, 2, 3}, the top size of
+ * the single-work-group tail in {256, 1024, 4096, 16384} cells (capped by
+ * the LDS), and the iteration-block length check_every in {1, 2, 4} -- by
+ * timing cold-start solves to rtol of the caller's right-hand sides of the
+ * current coefficients (after ebit_build_coeffs): b_heat and b_press are
+ * device arrays of a heat and a pressure right-hand side (either may be
+ * NULL), x a device array the solves write.  The fastest candidate whose
+ * solves all converge becomes the context's (batch's) schedule and is
+ * returned in *chosen with its summed solve time (ms) in *best_ms.
+ * Clobbers the contexts' internal right-hand-side buffers.  A batch's
+ * contexts keep their own options. */
+ebit_status ebit_autotune(ebit_ctx* ctx, const double* b_heat, const double* b_press, double* x, ebit_opts* chosen,
+                          double* best_ms);
+ebit_status ebit_batch_autotune(ebit_batch* batch, const double* const b_heat[], const double* const b_press[],
+                                double* const x[], ebit_opts* chosen, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

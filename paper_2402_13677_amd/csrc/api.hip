@@ -44,6 +44,8 @@ struct ebit_batch {
   ebit_opts opts;
   hipStream_t st;
   EbitPlan* plan;
+  void* ws;
+  size_t ws_bytes;
   hipEvent_t ev0, ev1;
   Scal* hsc;  // host copies of the contexts' status scalars
   hipError_t herr;
@@ -699,6 +701,8 @@ ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[
   b->n = ncases;
   b->opts = ctx[0]->opts;
   b->st = (hipStream_t)stream;
+  b->ws = ws;
+  b->ws_bytes = bytes;
   b->ctx = new (std::nothrow) ebit_ctx*[ncases];
   b->hsc = new (std::nothrow) Scal[ncases];
   EbitPlanCase* pc = new (std::nothrow) EbitPlanCase[ncases];
@@ -922,6 +926,128 @@ ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const
     for (int c = 0; c < b->n; ++c) stats[c].div_max = b->hsc[c].divmax;
   delete[] r;
   return s;
+}
+
+
+/* ---- autotuning ------------------------------------------------------- */
+
+}  // extern "C"
+
+namespace {
+
+// Candidate schedules: (nu1 = nu2) x tail_cells x check_every.
+const int TUNE_NU[] = {1, 2, 3};
+const int TUNE_TAIL[] = {256, 1024, 4096, 16384};
+const int TUNE_K[] = {1, 2, 4};
+
+// Re-plan a set of cases with new options (same plan memory).
+hipError_t replan(EbitPlan** plan, ebit_ctx* const* ctx, int n, const ebit_opts* o, void* mem, size_t bytes) {
+  ebit_plan_destroy(*plan);
+  *plan = nullptr;
+  EbitPlanCase* pc = new (std::nothrow) EbitPlanCase[n];
+  if (!pc) return hipErrorOutOfMemory;
+  for (int c = 0; c < n; ++c) pc[c] = EbitPlanCase{ctx[c]->lv, ctx[c]->nlev, ctx[c]->op, ctx[c]->B, ctx[c]->bvec};
+  const hipError_t e = ebit_plan_create(plan, n, pc, o, ctx[0]->B.tail_lds, mem, bytes);
+  delete[] pc;
+  return e;
+}
+
+// Time every candidate on cold-start solves of the given right-hand sides
+// (per case, per system; a null system is skipped) and keep the fastest one
+// whose solves all converge.  The right-hand sides are copied into the
+// contexts' own right-hand-side buffers.
+hipError_t tune(EbitPlan** plan, ebit_ctx* const* ctx, int n, const ebit_opts& base, const double* const* bh,
+                const double* const* bp, double* const* x, void* mem, size_t bytes, hipStream_t st, hipEvent_t ev0,
+                hipEvent_t ev1, ebit_opts* best, double* best_ms) {
+  hipError_t e;
+  *best = base;
+  *best_ms = INFINITY;
+  EbitSolveOut* r = new (std::nothrow) EbitSolveOut[n];
+  if (!r) return hipErrorOutOfMemory;
+  for (int nu : TUNE_NU)
+    for (int tail : TUNE_TAIL)
+      for (int k : TUNE_K) {
+        ebit_opts o = base;
+        o.nu1 = o.nu2 = nu;
+        o.tail_cells = tail;
+        o.check_every = k;
+        if ((e = replan(plan, ctx, n, &o, mem, bytes)) != hipSuccess) {
+          delete[] r;
+          return e;
+        }
+        double ms_tot = 0.0;
+        bool ok = true;
+        for (int sys = 0; sys < 2 && ok; ++sys) {
+          const double* const* bs = sys == EBIT_SYS_HEAT ? bh : bp;
+          if (!bs) continue;
+          for (int rep = 0; rep < 2 && ok; ++rep) {
+            for (int c = 0; c < n; ++c)
+              if ((e = hipMemcpyAsync(ctx[c]->bvec, bs[c], ctx[c]->fd.N * sizeof(double), hipMemcpyDeviceToDevice,
+                                      st)) != hipSuccess)
+                break;
+            if (e == hipSuccess) e = hipEventRecord(ev0, st);
+            if (e == hipSuccess) e = ebit_plan_solve(*plan, sys, x, 0, st, nullptr, r);
+            if (e == hipSuccess) e = hipEventRecord(ev1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (e != hipSuccess) {
+              delete[] r;
+              return e;
+            }
+            for (int c = 0; c < n; ++c) ok = ok && r[c].status == 0;
+            if (rep == 1) ms_tot += ms;  // the first run captures the graphs
+          }
+        }
+        if (ok && ms_tot < *best_ms) {
+          *best_ms = ms_tot;
+          *best = o;
+        }
+      }
+  delete[] r;
+  return replan(plan, ctx, n, best, mem, bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+ebit_status ebit_autotune(ebit_ctx* c, const double* b_heat, const double* b_press, double* x, ebit_opts* chosen,
+                          double* best_ms) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!x || (!b_heat && !b_press)) return fail(c, EBIT_EINVAL, "need x and at least one right-hand side");
+  ebit_opts best;
+  double ms = 0;
+  ebit_ctx* const cs[1] = {c};
+  double* const xs[1] = {x};
+  const double* const bh[1] = {b_heat};
+  const double* const bp[1] = {b_press};
+  const hipError_t e = tune(&c->plan, cs, 1, c->opts, b_heat ? bh : nullptr, b_press ? bp : nullptr, xs, c->plan_mem,
+                            c->plan_bytes, c->st, c->ev0, c->ev1, &best, &ms);
+  if (e != hipSuccess) return hip_fail(c, e, "autotune");
+  c->opts = best;
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = ms;
+  if (!isfinite(ms)) return fail(c, EBIT_ENOCONV, "no candidate schedule converged");
+  return EBIT_OK;
+}
+
+ebit_status ebit_batch_autotune(ebit_batch* b, const double* const b_heat[], const double* const b_press[],
+                                double* const x[], ebit_opts* chosen, double* best_ms) {
+  ebit_status s = batch_ready(b);
+  if (s != EBIT_OK) return s;
+  if (!x || (!b_heat && !b_press)) return bfail(b, EBIT_EINVAL, -1, "need x and at least one right-hand side");
+  ebit_opts best;
+  double ms = 0;
+  const hipError_t e =
+      tune(&b->plan, b->ctx, b->n, b->opts, b_heat, b_press, x, b->ws, b->ws_bytes, b->st, b->ev0, b->ev1, &best, &ms);
+  if (e != hipSuccess) return bhip(b, e, "autotune");
+  b->opts = best;
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = ms;
+  if (!isfinite(ms)) return bfail(b, EBIT_ENOCONV, -1, "no candidate schedule converged");
+  return EBIT_OK;
 }
 
 }  // extern "C"

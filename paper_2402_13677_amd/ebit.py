@@ -91,6 +91,9 @@ def load():
         "ebit_batch_mass_flux": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Stats)]),
         "ebit_batch_project": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), i, ctypes.POINTER(Stats)]),
+        "ebit_autotune": (i, [vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(d)]),
+        "ebit_batch_autotune": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(Opts), ctypes.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -105,7 +108,7 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_project_rhs", "ebit_levels",
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
-            "ebit_batch_mass_flux", "ebit_batch_project"]
+            "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune"]
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 
 
@@ -261,6 +264,19 @@ class Context:
                     "ebit_profile_read")
         return n.value, ms.value
 
+    def autotune(self, b_heat=None, b_press=None, x=None):
+        """Choose nu1 = nu2, tail_cells and check_every by timing solves of
+        the given right-hand sides; returns (chosen options dict, ms)."""
+        o = Opts()
+        ms = ctypes.c_double()
+        if x is None:
+            x = torch.empty_like(b_heat if b_heat is not None else b_press)
+        self._check(self.lib.ebit_autotune(self.h, _ptr(b_heat, torch.float64), _ptr(b_press, torch.float64),
+                                           _ptr(x, torch.float64), ctypes.byref(o), ctypes.byref(ms)),
+                    "ebit_autotune")
+        self.opts = o
+        return {k: getattr(o, k) for k, _ in Opts._fields_}, ms.value
+
     def levels(self):
         n = ctypes.c_int()
         sizes = (ctypes.c_int * (3 * 32))()
@@ -336,6 +352,18 @@ class Batch:
         s = self._stats()
         self._check(self.lib.ebit_batch_mass_flux(self.h, _ptrs(T), _ptrs(mdot), s), "ebit_batch_mass_flux")
         return [x.as_dict() for x in s]
+
+    def autotune(self, b_heat=None, b_press=None, x=None):
+        """Batch counterpart of Context.autotune (per-case lists)."""
+        o = Opts()
+        ms = ctypes.c_double()
+        ref = b_heat if b_heat is not None else b_press
+        if x is None:
+            x = [torch.empty_like(t) for t in ref]
+        self._check(self.lib.ebit_batch_autotune(self.h, _ptrs(b_heat) if b_heat is not None else None,
+                                                 _ptrs(b_press) if b_press is not None else None, _ptrs(x),
+                                                 ctypes.byref(o), ctypes.byref(ms)), "ebit_batch_autotune")
+        return {k: getattr(o, k) for k, _ in Opts._fields_}, ms.value
 
     def project(self, u_l, u_v, mdot, p, use_guess=False, check=True):
         s = self._stats()
