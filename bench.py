@@ -83,15 +83,38 @@ def make_case(name):
     return ei.config(idx, n)
 
 
-def run_gpu(case, precision, steps, warmup, profile=False):
-    """Time `steps` full steps after `warmup` untimed ones.  With profile,
-    the library also times every launch of each kernel class with hipEvents
-    on its stream; returns (elapsed, records, per-class (launches, ms))."""
+def autotune(ctx, dc, case):
+    """Untimed set-up: let the library pick the solve schedule on the first
+    step's heat and pressure right-hand sides."""
+    import torch
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    bh = torch.empty_like(dc.T0)
+    ctx.heat_rhs(dc.T0, bh)
+    m = torch.zeros_like(dc.T0)
+    ctx.mass_flux(dc.T0, m)
+    bp = torch.empty_like(dc.T0)
+    ctx.project_rhs([u.clone() for u in dc.u_l], [u.clone() for u in dc.u_v], m, bp)
+    chosen, _ = ctx.autotune(bh, bp)
+    return {k: chosen[k] for k in ("nu1", "nu2", "tail_cells", "check_every")}
+
+
+def parse_schedule(text):
+    nu, tail, k = (int(v) for v in text.split(","))
+    return {"nu1": nu, "nu2": nu, "tail_cells": tail, "check_every": k}
+
+
+def run_gpu(case, precision, steps, warmup, profile=False, tune=True):
+    """Time `steps` full steps after `warmup` untimed ones (and, with tune,
+    the untimed schedule autotuning).  With profile, the library also times
+    every launch of each kernel class with hipEvents on its stream; returns
+    (elapsed, records, per-class (launches, ms), schedule)."""
     import torch
     from paper_2402_13677_amd import ebit
 
-    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64)
+    fixed = tune if isinstance(tune, dict) else {}
+    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64, **fixed)
     ctx, dc = ebit.context_for(case, opts)
+    schedule = autotune(ctx, dc, case) if tune is True else (fixed or None)
     T = dc.T0.clone()
     mdot = torch.zeros_like(T)
     p = torch.zeros_like(T)
@@ -131,17 +154,20 @@ def run_gpu(case, precision, steps, warmup, profile=False):
             kern[name] = ctx.profile_read(kc)
         ctx.profile(False)
     ctx.close()
-    return elapsed, rec, kern
+    return elapsed, rec, kern, schedule
 
 
-def run_gpu_batch(cases, precision, steps, warmup, batched=True):
+def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
     """The uneven batch: one step = build + heat + mass flux + projection
-    of every case; batched (one launch per solve kernel over all cases) or
-    one context after another."""
+    of every case; batched (one launch per solve kernel over all cases, the
+    schedule autotuned untimed on the first step's right-hand sides) or one
+    context after another with a given schedule.  Returns (elapsed,
+    iterations, schedule)."""
     import torch
     from paper_2402_13677_amd import ebit
 
-    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64)
+    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
+                             **(schedule or {}))
     ctxs, dcs = [], []
     for c in cases:
         ctx, dc = ebit.context_for(c, opts)
@@ -154,6 +180,21 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True):
     u_v = [[u.clone() for u in d.u_v] for d in dcs]
     b = ebit.Batch(ctxs) if batched else None
     its = []
+    if batched and schedule is None:
+        b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs],
+                       [c.dt for c in cases])
+        bh, bp = [], []
+        for ctx, d in zip(ctxs, dcs):
+            x = torch.empty_like(d.T0)
+            ctx.heat_rhs(d.T0, x)
+            bh.append(x)
+            mm = torch.zeros_like(d.T0)
+            ctx.mass_flux(d.T0, mm)
+            y = torch.empty_like(d.T0)
+            ctx.project_rhs([u.clone() for u in d.u_l], [u.clone() for u in d.u_v], mm, y)
+            bp.append(y)
+        chosen, _ = b.autotune(bh, bp)
+        schedule = {k: chosen[k] for k in ("nu1", "nu2", "tail_cells", "check_every")}
 
     def step():
         if batched:
@@ -182,7 +223,7 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True):
         b.close()
     for c in ctxs:
         c.close()
-    return el, its
+    return el, its, schedule
 
 
 def cpu_baseline(case, budget_s=15.0, max_steps=30):
@@ -212,11 +253,11 @@ def cpu_baseline(case, budget_s=15.0, max_steps=30):
             "sample": f"{steps} full steps of the same workload ({el:.1f} s, SciPy SuperLU direct solves, 1 thread)"}
 
 
-def roofline(case, precision, steps):
+def roofline(case, precision, steps, tune=True):
     """Profiled timed pass: average launch duration of each kernel class,
     measured with hipEvents on the library's stream; the class with the most
     device time is the dominant kernel."""
-    _, _, kern = run_gpu(case, precision, steps, 1, profile=True)
+    _, _, kern, _ = run_gpu(case, precision, steps, 1, profile=True, tune=tune)
     rows = {}
     for name, (n, ms) in kern.items():
         if n == 0:
@@ -269,6 +310,9 @@ def main():
     ap.add_argument("--no-compare", dest="compare", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default solve schedule")
+    ap.add_argument("--schedule", default=None,
+                    help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -282,7 +326,8 @@ def main():
     case = make_case(args.workload)
     if isinstance(case, list):
         return main_batch(args, case)
-    elapsed, rec, _ = run_gpu(case, args.precision, args.steps, args.warmup)
+    tune = parse_schedule(args.schedule) if args.schedule else (not args.no_autotune)
+    elapsed, rec, _, schedule = run_gpu(case, args.precision, args.steps, args.warmup, tune=tune)
     ms_per_step = elapsed / args.steps * 1e3
     med = lambda v: statistics.median(v) if v else None
     extra = {
@@ -294,7 +339,7 @@ def main():
     }
     if args.compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
-        el2, rec2, _ = run_gpu(case, other, max(5, args.steps // 5), 1)
+        el2, rec2, _, _ = run_gpu(case, other, max(5, args.steps // 5), 1, tune=tune)
         extra[f"{other}_time_to_1e9_ms"] = {"heat": med(rec2["heat_ms"]), "projection": med(rec2["proj_ms"])}
         extra[f"{other}_ms_per_step"] = el2 / max(5, args.steps // 5) * 1e3
     out = {
@@ -311,12 +356,13 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": case.name, "cells": case.ncells, "precision": args.precision,
-                   "rtol": 1e-9, "parallelism": "single GPU"},
+                   "rtol": 1e-9, "parallelism": "single GPU", "schedule": schedule},
         "extra": extra,
         "roofline": None,
     }
     if not args.no_roofline:
-        out["roofline"], extra["kernels"] = roofline(case, args.precision, max(5, args.steps // 5))
+        out["roofline"], extra["kernels"] = roofline(case, args.precision, max(5, args.steps // 5),
+                                                     tune=schedule if schedule else False)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))
@@ -326,9 +372,9 @@ def main_batch(args, cases):
     """The 64-case uneven 2D batch (sides 64..256): batched solves, with the
     same cases one context after another beside it."""
     ncells = sum(c.ncells for c in cases)
-    el, its = run_gpu_batch(cases, args.precision, args.steps, args.warmup, batched=True)
+    el, its, schedule = run_gpu_batch(cases, args.precision, args.steps, args.warmup, batched=True)
     seq_steps = max(2, args.steps // 5)
-    el_seq, _ = run_gpu_batch(cases, args.precision, seq_steps, 1, batched=False)
+    el_seq, _, _ = run_gpu_batch(cases, args.precision, seq_steps, 1, batched=False, schedule=schedule)
     out = {
         "metric": "time-to-1e-9 residual per solve (mixed vs FP64) + cell-updates/s, % HBM peak",
         "value": ncells * args.steps / el,
@@ -343,7 +389,7 @@ def main_batch(args, cases):
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "batch64_2d", "cases": len(cases), "cells": ncells, "precision": args.precision,
-                   "rtol": 1e-9, "parallelism": "single GPU"},
+                   "rtol": 1e-9, "parallelism": "single GPU", "schedule": schedule},
         "extra": {"sequential_ms_per_step": el_seq / seq_steps * 1e3,
                   "batched_speedup": (el_seq / seq_steps) / (el / args.steps),
                   "max_outer_iters": {"heat": max(i[0] for i in its), "projection": max(i[1] for i in its)}},

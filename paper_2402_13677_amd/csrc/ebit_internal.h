@@ -100,9 +100,14 @@ struct FineOp {
 template <typename T>
 __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f, T& diag, T off[6],
                                 T& mass, T& rhs_bc, T* mexc = nullptr) {
-  const int ph = (f & F_LIQ) ? 1 : 0;
+  // per-phase values by selection, not by a run-time index, so a register
+  // copy of the operator never needs a memory home
+  const bool liq = (f & F_LIQ) != 0;
   const T ih2 = (T)op.ih2;
-  mass = (T)op.mass[ph];
+  const double coef = liq ? op.coef[1] : op.coef[0];
+  const double rho_k = liq ? op.rho[1] : op.rho[0];
+  const double rho_o = liq ? op.rho[0] : op.rho[1];
+  mass = (T)(liq ? op.mass[1] : op.mass[0]);
   diag = mass;
   T mx = mass;
   const int ns = 2 * op.d.dim;
@@ -114,7 +119,7 @@ __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f
     const int ia = (a == 0) ? i : (a == 1) ? j : k;
     const bool wall = !op.d.per[a] && (up ? (ia == op.d.n[a] - 1) : (ia == 0));
     if (op.sys == EBIT_SYS_HEAT) {
-      const T lam = (T)op.coef[ph];
+      const T lam = (T)coef;
       if (wall) {
         if (op.bc[s] == EBIT_BC_DIRICHLET) {
           diag += (T)2 * lam * ih2;
@@ -135,7 +140,7 @@ __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f
     } else {
       if (wall) {
         if (op.bc[s] == EBIT_BC_DIRICHLET) {
-          const T beta = (T)op.coef[ph];
+          const T beta = (T)coef;
           diag += (T)2 * beta * ih2;
           mx += (T)2 * beta * ih2;
           rhs_bc += (T)2 * beta * (T)op.bcval[s] * ih2;
@@ -145,12 +150,12 @@ __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f
         if ((f >> s) & 1) {
           const double tf = op.th[a][face_of_side(op.d, i, j, k, s)];
           // lower cell of the link: this cell on a + side, the neighbour on a - side
-          const double rlo = up ? op.rho[ph] : op.rho[1 - ph];
-          const double rup = up ? op.rho[1 - ph] : op.rho[ph];
+          const double rlo = up ? rho_k : rho_o;
+          const double rup = up ? rho_o : rho_k;
           const double rf = tf * rlo + (1.0 - tf) * rup;
           beta = (T)(op.dt / rf);
         } else {
-          beta = (T)op.coef[ph];
+          beta = (T)coef;
         }
         diag += beta * ih2;
         off[s] = -beta * ih2;

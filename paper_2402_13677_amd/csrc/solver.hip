@@ -51,8 +51,9 @@ __device__ inline T fine_residual_at(const FineOp& op, int i, int j, int k, long
   T diag, off[6], mass, rb = 0;
   fine_row<T>(op, i, j, k, op.flags[c], diag, off, mass, rb);
   T s = (T)b[c] - diag * x[c];
-  for (int q = 0; q < 2 * op.d.dim; ++q) {
-    if (off[q] == (T)0) continue;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q >= 2 * op.d.dim || off[q] == (T)0) continue;
     int ni, nj, nk;
     neighbour(op.d, i, j, k, q, ni, nj, nk);
     s -= off[q] * x[cell_index(op.d, ni, nj, nk)];
@@ -500,68 +501,99 @@ struct TailArgs {
   T* xg;        // its correction (output)
 };
 
+// Register copy of one tail level's shape (read once per level, so the
+// loops below do not go back to the case table).
+struct TLev {
+  int n0, n1, n2, N, base, dim, p0, p1, p2;
+};
+
+__device__ inline TLev tlev(const TailLevel& L) {
+  TLev t;
+  t.n0 = L.d.n[0];
+  t.n1 = L.d.n[1];
+  t.n2 = L.d.n[2];
+  t.N = (int)L.d.N;
+  t.base = L.base;
+  t.dim = L.d.dim;
+  t.p0 = L.d.per[0];
+  t.p1 = L.d.per[1];
+  t.p2 = L.d.per[2];
+  return t;
+}
+
 // The 1024 threads of the tail form 32 rows of 32: thread row ty takes grid
 // rows (j, k) = ty, ty + 32, ... and lane tx the cells i = 2 tx + parity,
 // + 64, ... of one colour (or every cell for the grid transfers).
 struct TailRow {
   int j, k;
-  __device__ TailRow(const Dims& d, int r) : j(r % d.n[1]), k(r / d.n[1]) {}
-  __device__ void next(const Dims& d) {
+  __device__ TailRow(const TLev& d, int r) : j(r % d.n1), k(r / d.n1) {}
+  __device__ void next(const TLev& d) {
     j += 32;
-    while (j >= d.n[1]) {
-      j -= d.n[1];
+    while (j >= d.n1) {
+      j -= d.n1;
       ++k;
     }
   }
 };
 
-// sum over the neighbours of cell q = (i, j, k) of coupling x neighbour; the
-// same neighbour set as neighbour() (periodic wrap, none across a wall)
+// Sum over the neighbours of cell q = (i, j, k) of coupling x neighbour;
+// the same neighbour set as neighbour() (periodic wrap, none across a
+// wall).  With xc non-null, neighbour values are read as x + xc[parent]
+// (the prolongated coarse correction, C the coarse level).
 template <typename T>
-__device__ inline T tail_offsum(const T* x, const Dims& d, int i, int j, int k, int q) {
-  const int N = (int)d.N;
-  T s = 0;
-  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+__device__ inline T tail_offsum(const T* x, const TLev& d, int i, int j, int k, int q, const T* xc = nullptr,
+                                const TLev* C = nullptr) {
+  const int N = d.N;
+  const int n0 = d.n0, n1 = d.n1, n2 = d.n2;
   const int s1 = n0, s2 = n0 * n1;
+  auto xv = [&](int m, int mi, int mj, int mk) {
+    T v = x[m];
+    if (xc) v += xc[(mi >> 1) + C->n0 * ((mj >> 1) + C->n1 * (mk >> 1))];
+    return v;
+  };
+  T s = 0;
   {
     const T* o = x + 3 * N;
-    if (i + 1 < n0) s += o[q] * x[q + 1];
-    else if (d.per[0]) s += o[q] * x[q + 1 - n0];
-    if (i > 0) s += o[q - 1] * x[q - 1];
-    else if (d.per[0]) s += o[q + n0 - 1] * x[q + n0 - 1];
+    if (i + 1 < n0) s += o[q] * xv(q + 1, i + 1, j, k);
+    else if (d.p0) s += o[q] * xv(q + 1 - n0, 0, j, k);
+    if (i > 0) s += o[q - 1] * xv(q - 1, i - 1, j, k);
+    else if (d.p0) s += o[q + n0 - 1] * xv(q + n0 - 1, n0 - 1, j, k);
   }
   if (d.dim >= 2) {
     const T* o = x + 4 * N;
-    if (j + 1 < n1) s += o[q] * x[q + s1];
-    else if (d.per[1]) s += o[q] * x[q + s1 - s2];
-    if (j > 0) s += o[q - s1] * x[q - s1];
-    else if (d.per[1]) s += o[q + s2 - s1] * x[q + s2 - s1];
+    if (j + 1 < n1) s += o[q] * xv(q + s1, i, j + 1, k);
+    else if (d.p1) s += o[q] * xv(q + s1 - s2, i, 0, k);
+    if (j > 0) s += o[q - s1] * xv(q - s1, i, j - 1, k);
+    else if (d.p1) s += o[q + s2 - s1] * xv(q + s2 - s1, i, n1 - 1, k);
   }
   if (d.dim == 3) {
     const T* o = x + 5 * N;
-    if (k + 1 < n2) s += o[q] * x[q + s2];
-    else if (d.per[2]) s += o[q] * x[q + s2 - N];
-    if (k > 0) s += o[q - s2] * x[q - s2];
-    else if (d.per[2]) s += o[q + N - s2] * x[q + N - s2];
+    if (k + 1 < n2) s += o[q] * xv(q + s2, i, j, k + 1);
+    else if (d.p2) s += o[q] * xv(q + s2 - N, i, j, 0);
+    if (k > 0) s += o[q - s2] * xv(q - s2, i, j, k - 1);
+    else if (d.p2) s += o[q + N - s2] * xv(q + N - s2, i, j, n2 - 1);
   }
   return s;
 }
 
+// One colour of a Gauss-Seidel sweep on a tail level.  With xc, the
+// neighbours (all of the other colour) are read with the coarse correction
+// added: the first post-smoothing sweep, which makes a separate
+// prolongation pass unnecessary (a Gauss-Seidel update does not read the
+// cell's own old value, and the next sweep overwrites the other colour).
 template <typename T>
-__device__ inline void tail_sweep(T* sm, const TailLevel& L, int color) {
-  const Dims& d = L.d;
-  const int N = (int)d.N;
-  T* x = sm + L.base;
-  const T* b = x + N;
-  const T* dg = x + 2 * N;
+__device__ inline void tail_sweep(T* sm, const TLev& d, int color, const T* xc = nullptr, const TLev* C = nullptr) {
+  T* x = sm + d.base;
+  const T* b = x + d.N;
+  const T* dg = x + 2 * d.N;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int rows = d.n[1] * d.n[2];
+  const int rows = d.n1 * d.n2;
   TailRow r(d, ty);
   for (int row = ty; row < rows; row += 32, r.next(d)) {
-    const int base = row * d.n[0];
-    for (int i = 2 * tx + ((r.j + r.k + color) & 1); i < d.n[0]; i += 64) {
+    const int base = row * d.n0;
+    for (int i = 2 * tx + ((r.j + r.k + color) & 1); i < d.n0; i += 64) {
       const int q = base + i;
-      x[q] = (b[q] - tail_offsum<T>(x, d, i, r.j, r.k, q)) / dg[q];
+      x[q] = (b[q] - tail_offsum<T>(x, d, i, r.j, r.k, q, xc, C)) / dg[q];
     }
   }
 }
@@ -570,63 +602,62 @@ template <typename T>
 __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int tx = tid & 31, ty = tid >> 5;
-  for (int l = 0; l < a.nl; ++l) {
-    const TailLevel& L = a.L[l];
-    const int N = (int)L.d.N;
+  const int nl = a.nl, nu1 = a.nu1, nu2 = a.nu2;
+  for (int l = 0; l < nl; ++l) {
+    const TLev L = tlev(a.L[l]);
+    const int N = L.N;
     T* x = sm + L.base;
     const T* dg = a.diag[l];
     const T* o0 = a.off[l][0];
     const T* o1 = a.off[l][1];
     const T* o2 = a.off[l][2];
+    const T* bg = a.bg;
     for (int q = tid; q < N; q += nth) {
       x[2 * N + q] = dg[q];
       x[3 * N + q] = o0[q];
-      if (L.d.dim >= 2) x[4 * N + q] = o1[q];
-      if (L.d.dim == 3) x[5 * N + q] = o2[q];
+      if (L.dim >= 2) x[4 * N + q] = o1[q];
+      if (L.dim == 3) x[5 * N + q] = o2[q];
       if (l == 0) {
-        x[N + q] = a.bg[q];
+        x[N + q] = bg[q];
         x[q] = (T)0;
       }
     }
   }
   __syncthreads();
-  for (int l = 0; l < a.nl - 1; ++l) {
-    const TailLevel& L = a.L[l];
-    const Dims& d = L.d;
-    const int N = (int)d.N;
+  for (int l = 0; l < nl - 1; ++l) {
+    const TLev L = tlev(a.L[l]);
+    const TLev C = tlev(a.L[l + 1]);
     T* x = sm + L.base;
-    const T* b = x + N;
-    const T* dg = x + 2 * N;
-    for (int s = 0; s < a.nu1; ++s)
+    const T* b = x + L.N;
+    const T* dg = x + 2 * L.N;
+    for (int s = 0; s < nu1; ++s)
       for (int col = 0; col < 2; ++col) {
         tail_sweep(sm, L, col);
         __syncthreads();
       }
     // residual of the 2^d children, summed into the coarse right-hand side
-    const TailLevel& C = a.L[l + 1];
-    const Dims& cd = C.d;
     T* xc = sm + C.base;
-    T* bc = xc + cd.N;
-    const int crows = cd.n[1] * cd.n[2];
-    TailRow r(cd, ty);
-    for (int row = ty; row < crows; row += 32, r.next(cd)) {
-      for (int ci = tx; ci < cd.n[0]; ci += 32) {
+    T* bc = xc + C.N;
+    const int crows = C.n1 * C.n2;
+    TailRow r(C, ty);
+    for (int row = ty; row < crows; row += 32, r.next(C)) {
+      for (int ci = tx; ci < C.n0; ci += 32) {
         T sum = 0;
         for (int dk = 0; dk < 2; ++dk) {
           const int k = 2 * r.k + dk;
-          if (k >= d.n[2]) break;
+          if (k >= L.n2) break;
           for (int dj = 0; dj < 2; ++dj) {
             const int j = 2 * r.j + dj;
-            if (j >= d.n[1]) break;
+            if (j >= L.n1) break;
             for (int di = 0; di < 2; ++di) {
               const int i = 2 * ci + di;
-              if (i >= d.n[0]) break;
-              const int q = i + d.n[0] * (j + d.n[1] * k);
-              sum += b[q] - dg[q] * x[q] - tail_offsum<T>(x, d, i, j, k, q);
+              if (i >= L.n0) break;
+              const int q = i + L.n0 * (j + L.n1 * k);
+              sum += b[q] - dg[q] * x[q] - tail_offsum<T>(x, L, i, j, k, q);
             }
           }
         }
-        const int I = row * cd.n[0] + ci;
+        const int I = row * C.n0 + ci;
         bc[I] = sum;
         xc[I] = (T)0;
       }
@@ -635,9 +666,8 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   }
   {
     // coarsest level: symmetric Gauss-Seidel by one thread (exact for one cell)
-    const TailLevel& L = a.L[a.nl - 1];
-    const Dims& d = L.d;
-    const int N = (int)d.N;
+    const TLev L = tlev(a.L[nl - 1]);
+    const int N = L.N;
     T* x = sm + L.base;
     const T* b = x + N;
     const T* dg = x + 2 * N;
@@ -647,35 +677,32 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
         for (int dir = 0; dir < 2; ++dir)
           for (int qq = 0; qq < N; ++qq) {
             const int q = dir ? (N - 1 - qq) : qq;
-            const int i = q % d.n[0], j = (q / d.n[0]) % d.n[1], k = q / (d.n[0] * d.n[1]);
-            x[q] = (b[q] - tail_offsum<T>(x, d, i, j, k, q)) / dg[q];
+            const int i = q % L.n0, j = (q / L.n0) % L.n1, k = q / (L.n0 * L.n1);
+            x[q] = (b[q] - tail_offsum<T>(x, L, i, j, k, q)) / dg[q];
           }
     }
     __syncthreads();
   }
-  for (int l = a.nl - 2; l >= 0; --l) {
-    const TailLevel& L = a.L[l];
-    const Dims& d = L.d;
-    T* x = sm + L.base;
-    const TailLevel& C = a.L[l + 1];
+  for (int l = nl - 2; l >= 0; --l) {
+    const TLev L = tlev(a.L[l]);
+    const TLev C = tlev(a.L[l + 1]);
     const T* xc = sm + C.base;
-    const int rows = d.n[1] * d.n[2];
-    TailRow r(d, ty);
-    for (int row = ty; row < rows; row += 32, r.next(d)) {
-      const int cb = C.d.n[0] * ((r.j >> 1) + C.d.n[1] * (r.k >> 1));
-      for (int i = tx; i < d.n[0]; i += 32) x[row * d.n[0] + i] += xc[cb + (i >> 1)];
-    }
+    // black sweep with the correction added to its (red) neighbours, then red
+    tail_sweep(sm, L, 1, xc, &C);
     __syncthreads();
-    for (int s = 0; s < a.nu2; ++s)
+    tail_sweep(sm, L, 0);
+    __syncthreads();
+    for (int s = 1; s < nu2; ++s)
       for (int col = 1; col >= 0; --col) {
         tail_sweep(sm, L, col);
         __syncthreads();
       }
   }
   {
-    const int N = (int)a.L[0].d.N;
-    const T* x = sm + a.L[0].base;
-    for (int q = tid; q < N; q += nth) a.xg[q] = x[q];
+    const TLev L = tlev(a.L[0]);
+    const T* x = sm + L.base;
+    T* xg = a.xg;
+    for (int q = tid; q < L.N; q += nth) xg[q] = x[q];
   }
 }
 
@@ -868,8 +895,9 @@ __global__ void k_apply(FineOp op, const double* __restrict__ x, double* __restr
     fine_row<double>(op, i, j, k, op.flags[c], diag, off, mass, rb, &mx);
     const double xc = x[c];
     double s = mx * xc;
-    for (int q = 0; q < 2 * op.d.dim; ++q) {
-      if (off[q] == 0.0) continue;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (q >= 2 * op.d.dim || off[q] == 0.0) continue;
       int ni, nj, nk;
       neighbour(op.d, i, j, k, q, ni, nj, nk);
       s -= off[q] * (xc - x[cell_index(op.d, ni, nj, nk)]);
@@ -1019,7 +1047,8 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
   const int c = wl_find(wl, lb, nb);
   if (!selected(ctl[c], mask)) return;
   const SolveCase<T>& C = cs[c];
-  resid_init_body(C.op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb);
+  const FineOp op = C.op;
+  resid_init_body(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb);
 }
 
 template <typename T, int TX, int TY>
@@ -1034,8 +1063,9 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   const int c = wl_find(wl, lb, nb);
   if (!ctl[c].active) return;
   const SolveCase<T>& C = cs[c];
+  const FineOp op = C.op;  // a register copy: the sweep never goes back to the table
   const int bx = lb % C.fgx, by = (lb / C.fgx) % C.fgy, bz = lb / (C.fgx * C.fgy);
-  rb_fine_body<T, TX, TY>(C.op, C.r, in_sel < 0 ? nullptr : (const T*)C.z[in_sel],
+  rb_fine_body<T, TX, TY>(op, C.r, in_sel < 0 ? nullptr : (const T*)C.z[in_sel],
                           add_xc ? (const T*)C.lx[1][0] : nullptr, C.lev[1].d, C.z[out_sel], C.fzc, bx, by, bz, xs,
                           rs, fs);
 }
@@ -1065,7 +1095,7 @@ __global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const Case
   const int c = wl_find(wl, lb, nb);
   if (!ctl[c].active) return;
   const SolveCase<T>& C = cs[c];
-  const FineOp& op = C.op;
+  const FineOp op = C.op;
   const Dims cd = C.lev[1].d;
   const T* x = C.z[src_sel];
   T* bc = C.lb[1];
@@ -1100,7 +1130,7 @@ __global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const Ca
   const int c = wl_find(wl, lb, nb);
   if (!ctl[c].active) return;
   const SolveCase<T>& C = cs[c];
-  const CoarseOp<T>& op = C.lev[l];
+  const CoarseOp<T> op = C.lev[l];
   const Dims cd = C.lev[l + 1].d;
   const T* b = C.lb[l];
   const T* x = C.lx[l][src_sel];
@@ -1168,7 +1198,7 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   const CaseCtl cc = ctl[c];
   if (!cc.active) return;
   const SolveCase<T>& C = cs[c];
-  const FineOp& op = C.op;
+  const FineOp op = C.op;
   const bool first = dc || cc.fresh;
   const double beta = first ? 0.0 : C.sc->beta;
   const T* z = C.z[0];
@@ -1183,8 +1213,9 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
     fine_row<double>(op, i, j, k, op.flags[i0], diag, off, mass, rb, &mx);
     const double pc = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
     double s = mx * pc;
-    for (int qq = 0; qq < 2 * op.d.dim; ++qq) {
-      if (off[qq] == 0.0) continue;
+#pragma unroll
+    for (int qq = 0; qq < 6; ++qq) {
+      if (qq >= 2 * op.d.dim || off[qq] == 0.0) continue;
       int ni, nj, nk;
       neighbour(op.d, i, j, k, qq, ni, nj, nk);
       const long long m = cell_index(op.d, ni, nj, nk);
