@@ -482,13 +482,14 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
 #define EBIT_TAIL_MAX 16
 #define EBIT_TAIL_THREADS 1024
 
-// LDS block of one tail level: x, b, diag, off[0 .. dim-1], N elements each.
+// LDS block of one tail level: x, b, diag, 1/diag, off[0 .. dim-1], N
+// elements each.
 struct TailLevel {
   Dims d;
   int base;  // element offset of x
 };
 
-__host__ __device__ inline long long tail_level_elems(const Dims& d) { return (3 + d.dim) * d.N; }
+__host__ __device__ inline long long tail_level_elems(const Dims& d) { return (4 + d.dim) * d.N; }
 
 template <typename T>
 struct TailArgs {
@@ -502,9 +503,11 @@ struct TailArgs {
 };
 
 // Register copy of one tail level's shape (read once per level, so the
-// loops below do not go back to the case table).
+// loops below do not go back to the case table), with float reciprocals of
+// the row and plane sizes for division-free index decoding.
 struct TLev {
   int n0, n1, n2, N, base, dim, p0, p1, p2;
+  float r0, r1, r01;  // 1/n0, 1/n1, 1/(n0 n1)
 };
 
 __device__ inline TLev tlev(const TailLevel& L) {
@@ -518,31 +521,44 @@ __device__ inline TLev tlev(const TailLevel& L) {
   t.p0 = L.d.per[0];
   t.p1 = L.d.per[1];
   t.p2 = L.d.per[2];
+  t.r0 = 1.0f / (float)t.n0;
+  t.r1 = 1.0f / (float)t.n1;
+  t.r01 = 1.0f / (float)(t.n0 * t.n1);
   return t;
 }
 
-// The 1024 threads of the tail form 32 rows of 32: thread row ty takes grid
-// rows (j, k) = ty, ty + 32, ... and lane tx the cells i = 2 tx + parity,
-// + 64, ... of one colour (or every cell for the grid transfers).
-struct TailRow {
-  int j, k;
-  __device__ TailRow(const TLev& d, int r) : j(r % d.n1), k(r / d.n1) {}
-  __device__ void next(const TLev& d) {
-    j += 32;
-    while (j >= d.n1) {
-      j -= d.n1;
-      ++k;
-    }
-  }
-};
+// c / n for 0 <= c < 2^22 given r = 1/n in float: the float quotient is off
+// by at most one, which the remainder test corrects.
+__device__ inline int qdiv(int c, int n, float r) {
+  int q = (int)((float)c * r);
+  const int m = c - q * n;
+  q += (m >= n) - (m < 0);
+  return q;
+}
+
+__device__ inline void cell_of(const TLev& d, int c, int& i, int& j, int& k) {
+  const int s2 = d.n0 * d.n1;
+  k = qdiv(c, s2, d.r01);
+  const int r = c - k * s2;
+  j = qdiv(r, d.n0, d.r0);
+  i = r - j * d.n0;
+}
+
+// LDS block of a tail level: x, b, diag, 1/diag, couplings off[0 .. dim-1]
+#define TAIL_X(L, sm) ((sm) + (L).base)
+#define TAIL_B(L, sm) ((sm) + (L).base + (L).N)
+#define TAIL_D(L, sm) ((sm) + (L).base + 2 * (L).N)
+#define TAIL_DI(L, sm) ((sm) + (L).base + 3 * (L).N)
+#define TAIL_O(L, sm, a) ((sm) + (L).base + (4 + (a)) * (L).N)
 
 // Sum over the neighbours of cell q = (i, j, k) of coupling x neighbour;
 // the same neighbour set as neighbour() (periodic wrap, none across a
 // wall).  With xc non-null, neighbour values are read as x + xc[parent]
 // (the prolongated coarse correction, C the coarse level).
 template <typename T>
-__device__ inline T tail_offsum(const T* x, const TLev& d, int i, int j, int k, int q, const T* xc = nullptr,
+__device__ inline T tail_offsum(const T* sm, const TLev& d, int i, int j, int k, int q, const T* xc = nullptr,
                                 const TLev* C = nullptr) {
+  const T* x = TAIL_X(d, sm);
   const int N = d.N;
   const int n0 = d.n0, n1 = d.n1, n2 = d.n2;
   const int s1 = n0, s2 = n0 * n1;
@@ -553,21 +569,21 @@ __device__ inline T tail_offsum(const T* x, const TLev& d, int i, int j, int k, 
   };
   T s = 0;
   {
-    const T* o = x + 3 * N;
+    const T* o = TAIL_O(d, sm, 0);
     if (i + 1 < n0) s += o[q] * xv(q + 1, i + 1, j, k);
     else if (d.p0) s += o[q] * xv(q + 1 - n0, 0, j, k);
     if (i > 0) s += o[q - 1] * xv(q - 1, i - 1, j, k);
     else if (d.p0) s += o[q + n0 - 1] * xv(q + n0 - 1, n0 - 1, j, k);
   }
   if (d.dim >= 2) {
-    const T* o = x + 4 * N;
+    const T* o = TAIL_O(d, sm, 1);
     if (j + 1 < n1) s += o[q] * xv(q + s1, i, j + 1, k);
     else if (d.p1) s += o[q] * xv(q + s1 - s2, i, 0, k);
     if (j > 0) s += o[q - s1] * xv(q - s1, i, j - 1, k);
     else if (d.p1) s += o[q + s2 - s1] * xv(q + s2 - s1, i, n1 - 1, k);
   }
   if (d.dim == 3) {
-    const T* o = x + 5 * N;
+    const T* o = TAIL_O(d, sm, 2);
     if (k + 1 < n2) s += o[q] * xv(q + s2, i, j, k + 1);
     else if (d.p2) s += o[q] * xv(q + s2 - N, i, j, 0);
     if (k > 0) s += o[q - s2] * xv(q - s2, i, j, k - 1);
@@ -576,24 +592,165 @@ __device__ inline T tail_offsum(const T* x, const TLev& d, int i, int j, int k, 
   return s;
 }
 
-// One colour of a Gauss-Seidel sweep on a tail level.  With xc, the
-// neighbours (all of the other colour) are read with the coarse correction
-// added: the first post-smoothing sweep, which makes a separate
+// One colour of a Gauss-Seidel sweep on a tail level by the work-group.
+// Only as many waves as half the level needs take part (the others go
+// straight to the caller's barrier); threads form rows of 32, the lane
+// taking cells i = 2 lane + parity, + 64, ... of its grid rows.  With xc,
+// the neighbours (all of the other colour) are read with the coarse
+// correction added: the first post-smoothing sweep, which makes a separate
 // prolongation pass unnecessary (a Gauss-Seidel update does not read the
 // cell's own old value, and the next sweep overwrites the other colour).
 template <typename T>
 __device__ inline void tail_sweep(T* sm, const TLev& d, int color, const T* xc = nullptr, const TLev* C = nullptr) {
-  T* x = sm + d.base;
-  const T* b = x + d.N;
-  const T* dg = x + 2 * d.N;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  int act = ((d.N + 1) / 2 + 63) / 64 * 64;
+  if (act > EBIT_TAIL_THREADS) act = EBIT_TAIL_THREADS;
+  if ((int)threadIdx.x >= act) return;
+  T* x = TAIL_X(d, sm);
+  const T* b = TAIL_B(d, sm);
+  const T* di = TAIL_DI(d, sm);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5, rs = act >> 5;
   const int rows = d.n1 * d.n2;
-  TailRow r(d, ty);
-  for (int row = ty; row < rows; row += 32, r.next(d)) {
+  int j = 0, k = 0;
+  if (ty < rows) {
+    k = qdiv(ty, d.n1, d.r1);
+    j = ty - k * d.n1;
+  }
+  for (int row = ty; row < rows; row += rs) {
     const int base = row * d.n0;
-    for (int i = 2 * tx + ((r.j + r.k + color) & 1); i < d.n0; i += 64) {
+    for (int i = 2 * tx + ((j + k + color) & 1); i < d.n0; i += 64) {
       const int q = base + i;
-      x[q] = (b[q] - tail_offsum<T>(x, d, i, r.j, r.k, q, xc, C)) / dg[q];
+      x[q] = (b[q] - tail_offsum<T>(sm, d, i, j, k, q, xc, C)) * di[q];
+    }
+    j += rs;
+    while (j >= d.n1) {
+      j -= d.n1;
+      ++k;
+    }
+  }
+}
+
+// Residual of the 2^d children of each cell of C, summed into C's
+// right-hand side; C's iterate cleared.  Thread t (of nth) takes coarse
+// cells t, t + nth, ...
+template <typename T>
+__device__ inline void tail_restrict(T* sm, const TLev& L, const TLev& C, int t, int nth) {
+  const T* x = TAIL_X(L, sm);
+  const T* b = TAIL_B(L, sm);
+  const T* dg = TAIL_D(L, sm);
+  T* xc = TAIL_X(C, sm);
+  T* bc = TAIL_B(C, sm);
+  for (int I = t; I < C.N; I += nth) {
+    int ci, cj, ck;
+    cell_of(C, I, ci, cj, ck);
+    T sum = 0;
+    for (int dk = 0; dk < 2; ++dk) {
+      const int k = 2 * ck + dk;
+      if (k >= L.n2) break;
+      for (int dj = 0; dj < 2; ++dj) {
+        const int j = 2 * cj + dj;
+        if (j >= L.n1) break;
+        for (int di = 0; di < 2; ++di) {
+          const int i = 2 * ci + di;
+          if (i >= L.n0) break;
+          const int q = i + L.n0 * (j + L.n1 * k);
+          sum += b[q] - dg[q] * x[q] - tail_offsum<T>(sm, L, i, j, k, q);
+        }
+      }
+    }
+    bc[I] = sum;
+    xc[I] = (T)0;
+  }
+}
+
+// ---- the smallest tail levels by one wavefront ----------------------------
+// Levels of at most EBIT_TAIL_WAVE_CELLS cells are processed by wave 0 alone:
+// its lanes synchronise through wave-scope fences instead of work-group
+// barriers (LDS operations of one wave complete in order).
+#define EBIT_TAIL_WAVE_CELLS 512
+#define EBIT_TAIL_WAVE_SLOTS (EBIT_TAIL_WAVE_CELLS / 64)
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cells of one level owned by this lane: lane + 64 m, with (i, j, k).
+struct LaneCells {
+  int n;
+  int i[EBIT_TAIL_WAVE_SLOTS], j[EBIT_TAIL_WAVE_SLOTS], k[EBIT_TAIL_WAVE_SLOTS];
+  __device__ LaneCells(const TLev& d, int lane) : n(0) {
+#pragma unroll
+    for (int m = 0; m < EBIT_TAIL_WAVE_SLOTS; ++m) {
+      const int c = lane + 64 * m;
+      cell_of(d, c < d.N ? c : 0, i[m], j[m], k[m]);
+      if (c < d.N) n = m + 1;
+    }
+  }
+};
+
+template <typename T>
+__device__ inline void wave_sweep(T* sm, const TLev& d, const LaneCells& lc, int lane, int color,
+                                  const T* xc = nullptr, const TLev* C = nullptr) {
+  T* x = TAIL_X(d, sm);
+  const T* b = TAIL_B(d, sm);
+  const T* di = TAIL_DI(d, sm);
+#pragma unroll
+  for (int m = 0; m < EBIT_TAIL_WAVE_SLOTS; ++m) {
+    if (m >= lc.n || ((lc.i[m] + lc.j[m] + lc.k[m]) & 1) != color) continue;
+    const int q = lane + 64 * m;
+    x[q] = (b[q] - tail_offsum<T>(sm, d, lc.i[m], lc.j[m], lc.k[m], q, xc, C)) * di[q];
+  }
+  wave_sync();
+}
+
+// V-cycle over tail levels l0 .. nl-1 by wave 0 (the rest of the work-group
+// waits at the caller's barrier); level l0's right-hand side is in place and
+// its iterate zero.
+template <typename T>
+__device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0) {
+  const int lane = threadIdx.x;
+  const int nl = a.nl, nu1 = a.nu1, nu2 = a.nu2;
+  for (int l = l0; l < nl - 1; ++l) {
+    const TLev L = tlev(a.L[l]);
+    const TLev C = tlev(a.L[l + 1]);
+    const LaneCells lc(L, lane);
+    for (int s = 0; s < nu1; ++s) {
+      wave_sweep(sm, L, lc, lane, 0);
+      wave_sweep(sm, L, lc, lane, 1);
+    }
+    tail_restrict(sm, L, C, lane, 64);
+    wave_sync();
+  }
+  {
+    // coarsest level: symmetric Gauss-Seidel by one lane (exact for one cell)
+    const TLev L = tlev(a.L[nl - 1]);
+    if (lane == 0) {
+      T* x = TAIL_X(L, sm);
+      const T* b = TAIL_B(L, sm);
+      const T* di = TAIL_DI(L, sm);
+      const int sweeps = L.N == 1 ? 1 : 50;
+      for (int s = 0; s < sweeps; ++s)
+        for (int dir = 0; dir < 2; ++dir)
+          for (int qq = 0; qq < L.N; ++qq) {
+            const int q = dir ? (L.N - 1 - qq) : qq;
+            int i, j, k;
+            cell_of(L, q, i, j, k);
+            x[q] = (b[q] - tail_offsum<T>(sm, L, i, j, k, q)) * di[q];
+          }
+    }
+    wave_sync();
+  }
+  for (int l = nl - 2; l >= l0; --l) {
+    const TLev L = tlev(a.L[l]);
+    const TLev C = tlev(a.L[l + 1]);
+    const LaneCells lc(L, lane);
+    const T* xcs = TAIL_X(C, sm);
+    wave_sweep(sm, L, lc, lane, 1, xcs, &C);
+    wave_sweep(sm, L, lc, lane, 0);
+    for (int s = 1; s < nu2; ++s) {
+      wave_sweep(sm, L, lc, lane, 1);
+      wave_sweep(sm, L, lc, lane, 0);
     }
   }
 }
@@ -601,22 +758,23 @@ __device__ inline void tail_sweep(T* sm, const TLev& d, int color, const T* xc =
 template <typename T>
 __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int tx = tid & 31, ty = tid >> 5;
-  const int nl = a.nl, nu1 = a.nu1, nu2 = a.nu2;
+  const int nl = a.nl, nu2 = a.nu2, nu1 = a.nu1;
   for (int l = 0; l < nl; ++l) {
     const TLev L = tlev(a.L[l]);
     const int N = L.N;
-    T* x = sm + L.base;
     const T* dg = a.diag[l];
     const T* o0 = a.off[l][0];
     const T* o1 = a.off[l][1];
     const T* o2 = a.off[l][2];
     const T* bg = a.bg;
+    T* x = TAIL_X(L, sm);
     for (int q = tid; q < N; q += nth) {
-      x[2 * N + q] = dg[q];
-      x[3 * N + q] = o0[q];
-      if (L.dim >= 2) x[4 * N + q] = o1[q];
-      if (L.dim == 3) x[5 * N + q] = o2[q];
+      const T d = dg[q];
+      x[2 * N + q] = d;
+      x[3 * N + q] = (T)1 / d;
+      x[4 * N + q] = o0[q];
+      if (L.dim >= 2) x[5 * N + q] = o1[q];
+      if (L.dim == 3) x[6 * N + q] = o2[q];
       if (l == 0) {
         x[N + q] = bg[q];
         x[q] = (T)0;
@@ -624,71 +782,27 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
     }
   }
   __syncthreads();
-  for (int l = 0; l < nl - 1; ++l) {
+  // levels l0 .. nl-1 are small enough for one wavefront
+  int l0 = nl - 1;
+  while (l0 > 0 && a.L[l0 - 1].d.N <= EBIT_TAIL_WAVE_CELLS) --l0;
+  for (int l = 0; l < l0; ++l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
-    T* x = sm + L.base;
-    const T* b = x + L.N;
-    const T* dg = x + 2 * L.N;
     for (int s = 0; s < nu1; ++s)
       for (int col = 0; col < 2; ++col) {
         tail_sweep(sm, L, col);
         __syncthreads();
       }
-    // residual of the 2^d children, summed into the coarse right-hand side
-    T* xc = sm + C.base;
-    T* bc = xc + C.N;
-    const int crows = C.n1 * C.n2;
-    TailRow r(C, ty);
-    for (int row = ty; row < crows; row += 32, r.next(C)) {
-      for (int ci = tx; ci < C.n0; ci += 32) {
-        T sum = 0;
-        for (int dk = 0; dk < 2; ++dk) {
-          const int k = 2 * r.k + dk;
-          if (k >= L.n2) break;
-          for (int dj = 0; dj < 2; ++dj) {
-            const int j = 2 * r.j + dj;
-            if (j >= L.n1) break;
-            for (int di = 0; di < 2; ++di) {
-              const int i = 2 * ci + di;
-              if (i >= L.n0) break;
-              const int q = i + L.n0 * (j + L.n1 * k);
-              sum += b[q] - dg[q] * x[q] - tail_offsum<T>(x, L, i, j, k, q);
-            }
-          }
-        }
-        const int I = row * C.n0 + ci;
-        bc[I] = sum;
-        xc[I] = (T)0;
-      }
-    }
+    tail_restrict(sm, L, C, tid, nth);
     __syncthreads();
   }
-  {
-    // coarsest level: symmetric Gauss-Seidel by one thread (exact for one cell)
-    const TLev L = tlev(a.L[nl - 1]);
-    const int N = L.N;
-    T* x = sm + L.base;
-    const T* b = x + N;
-    const T* dg = x + 2 * N;
-    if (tid == 0) {
-      const int sweeps = N == 1 ? 1 : 50;
-      for (int s = 0; s < sweeps; ++s)
-        for (int dir = 0; dir < 2; ++dir)
-          for (int qq = 0; qq < N; ++qq) {
-            const int q = dir ? (N - 1 - qq) : qq;
-            const int i = q % L.n0, j = (q / L.n0) % L.n1, k = q / (L.n0 * L.n1);
-            x[q] = (b[q] - tail_offsum<T>(x, L, i, j, k, q)) / dg[q];
-          }
-    }
-    __syncthreads();
-  }
-  for (int l = nl - 2; l >= 0; --l) {
+  if (tid < 64) tail_wave<T>(a, sm, l0);
+  __syncthreads();
+  for (int l = l0 - 1; l >= 0; --l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
-    const T* xc = sm + C.base;
     // black sweep with the correction added to its (red) neighbours, then red
-    tail_sweep(sm, L, 1, xc, &C);
+    tail_sweep(sm, L, 1, TAIL_X(C, sm), &C);
     __syncthreads();
     tail_sweep(sm, L, 0);
     __syncthreads();
@@ -700,7 +814,7 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   }
   {
     const TLev L = tlev(a.L[0]);
-    const T* x = sm + L.base;
+    const T* x = TAIL_X(L, sm);
     T* xg = a.xg;
     for (int q = tid; q < L.N; q += nth) xg[q] = x[q];
   }
