@@ -37,12 +37,12 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "coarse", "outer_apply", "outer_update", "tail"]
 # the HIP kernels of each class (names as rocprofv3 reports them)
 KERNEL_NAMES = {
-    "fine_smooth": "k_rb_fine",
-    "fine_restrict": "k_fine_resid_restrict",
-    "coarse": "k_rb_fused",
-    "tail": "k_tail",
-    "outer_apply": "k_p_update_apply",
-    "outer_update": "k_update_xr",
+    "fine_smooth": "kb_rb_fine",
+    "fine_restrict": "kb_fine_restrict",
+    "coarse": "kb_rb_coarse",
+    "tail": "kb_tail",
+    "outer_apply": "kb_p_update_apply",
+    "outer_update": "kb_update_xr",
 }
 
 

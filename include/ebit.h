@@ -224,12 +224,14 @@ typedef enum {
   EBIT_KC_TAIL = 5            /* single-work-group solve of the coarsest levels */
 } ebit_kernel_class;
 
-/* Profiling of individual launches with hipEvents recorded on the context's
- * stream around each launch of the classes above (enable != 0 turns it on
- * and clears the totals; the events are created by this call, once).
- * ebit_profile_read returns, for one class, the number of launches timed
- * and their summed device time in milliseconds, after synchronising the
- * stream.  Meant for measurement runs: the events add a little host work. */
+/* Profiling of launches with hipEvents recorded on the solve stream around
+ * each launch of the classes above -- around each run of consecutive fine
+ * sweeps as one bracket (enable != 0 turns it on and clears the totals; the
+ * events are created by this call, once).  ebit_profile_read returns, for
+ * one class, the number of launches timed and their summed device time in
+ * milliseconds, after synchronising.  While profiling is on, the iteration
+ * blocks are launched one kernel at a time instead of replayed as graphs.
+ * Meant for measurement runs: the events add a little host work. */
 ebit_status ebit_profile(ebit_ctx* ctx, int enable);
 ebit_status ebit_profile_read(ebit_ctx* ctx, int kernel_class, long long* launches, double* ms);
 

@@ -236,6 +236,7 @@ struct EbitProfiler {
   hipEvent_t ev0[EBIT_PROF_CAP];
   hipEvent_t ev1[EBIT_PROF_CAP];
   int kid[EBIT_PROF_CAP];
+  int count[EBIT_PROF_CAP];  // launches inside each bracket
   long long launches[EBIT_PROF_CLASSES];
   double ms[EBIT_PROF_CLASSES];
 };

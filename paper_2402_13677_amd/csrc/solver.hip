@@ -1514,7 +1514,7 @@ hipError_t ebit_prof_flush(EbitProfiler* pr) {
     e = hipEventElapsedTime(&ms, pr->ev0[i], pr->ev1[i]);
     if (e != hipSuccess) return e;
     pr->ms[pr->kid[i]] += ms;
-    pr->launches[pr->kid[i]] += 1;
+    pr->launches[pr->kid[i]] += pr->count[i];
   }
   pr->npend = 0;
   return hipSuccess;
@@ -1528,16 +1528,19 @@ hipError_t ebit_prof_flush(EbitProfiler* pr) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// Bracket one launch with events when profiling is on.
+// Bracket one launch, or a run of n consecutive launches of one class, with
+// events when profiling is on (a run shares one pair of events, so the
+// events' own dispatch is paid once per run).
 struct ProfScope {
   EbitProfiler* pr;
   hipStream_t st;
   int slot;
-  ProfScope(EbitProfiler* p, int kid, hipStream_t s) : pr(p), st(s), slot(-1) {
+  ProfScope(EbitProfiler* p, int kid, hipStream_t s, int n = 1) : pr(p), st(s), slot(-1) {
     if (!pr || !pr->on) return;
     if (pr->npend == EBIT_PROF_CAP) (void)ebit_prof_flush(pr);
     slot = pr->npend++;
     pr->kid[slot] = kid;
+    pr->count[slot] = n;
     (void)hipEventRecord(pr->ev0[slot], st);
   }
   ~ProfScope() {
@@ -1719,10 +1722,12 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   const CaseCtl* ctl = P.d_ctl;
   auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
   int in = -1;
-  for (int s = 1; s <= nu1; ++s) {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
-    launch_fine(P, cs, in, slot(s), 0, st);
-    in = slot(s);
+  {
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, nu1);
+    for (int s = 1; s <= nu1; ++s) {
+      launch_fine(P, cs, in, slot(s), 0, st);
+      in = slot(s);
+    }
   }
   {
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
@@ -1755,10 +1760,12 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
     }
   }
   in = slot(nu1);
-  for (int s = nu1 + 1; s <= S; ++s) {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st);
-    launch_fine(P, cs, in, slot(s), s == nu1 + 1 ? 1 : 0, st);
-    in = slot(s);
+  {
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, S - nu1);
+    for (int s = nu1 + 1; s <= S; ++s) {
+      launch_fine(P, cs, in, slot(s), s == nu1 + 1 ? 1 : 0, st);
+      in = slot(s);
+    }
   }
 }
 
