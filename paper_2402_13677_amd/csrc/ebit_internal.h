@@ -24,6 +24,7 @@ enum : int { ERR_GEOM_MARKER = 1, ERR_GEOM_NOFACET = 2, ERR_GEOM_SEAM = 4, ERR_N
 // Per-solve scalars kept on the device (no host round trip per iteration).
 struct Scal {
   double bb, rr, gamma, delta, alpha, beta, zq, divmax;
+  double sa[2], sg[2];  // alpha and gamma by iteration parity (read by one kernel while the next is written)
   double aa;      // || |b| + |A| |x| ||^2: sets the rounding floor of the residual
   double red[7];
   int err;

@@ -262,45 +262,132 @@ __device__ inline bool wrap_axis(const Dims& d, int a, int& v) {
 }
 
 template <typename T, int TX, int TY>
-__device__ inline void fine_load_x(const Dims& d, int kk, int tx0, int ty0, const T* __restrict__ xin,
-                                   const T* __restrict__ xc, const Dims& cd, T (&v)[FineTile<TX, TY>::NX]) {
+struct FineGeom;
+
+// Plane-invariant part of one thread's work in a fine sweep: which cells of
+// the staged windows it loads (their in-plane offsets, -1 outside the domain
+// or the window) and which cells it updates in each phase, for both colour
+// parities of a plane (the parity alternates with k).  Computed once per
+// work-group; the z-march then only adds plane offsets.
+template <int TX, int TY>
+struct FineSlots {
   using FT = FineTile<TX, TY>;
-  int k = kk;
-  const bool pz = wrap_axis(d, 2, k);
+  static constexpr int HR = (TX + 2) / 2, NR = (HR * (TY + 2) + RB_THREADS - 1) / RB_THREADS;  // red, tile + ring
+  static constexpr int HB = TX / 2, NB = (HB * TY + RB_THREADS - 1) / RB_THREADS;              // black, tile
+  static constexpr int NW = (TX * TY + RB_THREADS - 1) / RB_THREADS;                           // write-back
+  int xo[FT::NX], xco[FT::NX];  // iterate window: cell offset i + n0 j, parent offset on the coarse level
+  int qo[FT::NQ];               // r / flags window
+  // update slots: q (P = 0; P = 1 is q + 1), qq = q - dq, wrapped i for
+  // both parities, wrapped j, parity base, bits: 1 ok(P=0), 2 ok(P=1),
+  // 4 x-wall(P=0), 8 x-wall(P=1), 16 y-wall
+  int rq[NR], rdq[NR], ri0[NR], ri1[NR], rj[NR], rp[NR], rbits[NR];
+  int bq[NB], bdq[NB], bi0[NB], bi1[NB], bj[NB], bp[NB], bbits[NB];
+  int wo[NW], wq[NW];
+};
+
+template <int TX, int TY, int RING, int NS>
+__device__ inline void slot_setup(const Dims& d, int tx0, int ty0, int color, int (&q)[NS], int (&dq)[NS],
+                                  int (&i0)[NS], int (&i1)[NS], int (&jj)[NS], int (&pb)[NS], int (&bits)[NS]) {
+  using FT = FineTile<TX, TY>;
+  constexpr int HX = (TX + 2 * RING) / 2, WY = TY + 2 * RING;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int t = threadIdx.x + s * RB_THREADS;
+    bits[s] = 0;
+    q[s] = dq[s] = i0[s] = i1[s] = jj[s] = pb[s] = 0;
+    if (t >= HX * WY) continue;
+    const int ly = t / HX - RING, m = t % HX;
+    int j = ty0 + ly;
+    pb[s] = (color + tx0 - RING + j) & 1;
+    const int lx0 = 2 * m - RING;
+    q[s] = (ly + 2) * FT::PX + (lx0 + 2);
+    dq[s] = FT::PX + 3 + 2 * ly;
+    const bool okj = wrap_axis(d, 1, j);
+    jj[s] = j;
+    int a = tx0 + lx0, b = tx0 + lx0 + 1;
+    const bool oka = okj && wrap_axis(d, 0, a);
+    const bool okb = okj && wrap_axis(d, 0, b);
+    i0[s] = a;
+    i1[s] = b;
+    int bt = (oka ? 1 : 0) | (okb ? 2 : 0);
+    if (!d.per[0] && (a == 0 || a == d.n[0] - 1)) bt |= 4;
+    if (!d.per[0] && (b == 0 || b == d.n[0] - 1)) bt |= 8;
+    if (!d.per[1] && (j == 0 || j == d.n[1] - 1)) bt |= 16;
+    bits[s] = bt;
+  }
+}
+
+template <int TX, int TY>
+__device__ inline void fine_slots(const Dims& d, const Dims& cd, int tx0, int ty0, FineSlots<TX, TY>& S) {
+  using FT = FineTile<TX, TY>;
+  using FS = FineSlots<TX, TY>;
 #pragma unroll
   for (int e = 0; e < FT::NX; ++e) {
     const int t = threadIdx.x + e * RB_THREADS;
+    S.xo[e] = -1;
+    S.xco[e] = 0;
+    if (t >= FT::PL) continue;
+    int i = tx0 + t % FT::PX - 2, j = ty0 + t / FT::PX - 2;
+    if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      S.xo[e] = i + d.n[0] * j;
+      S.xco[e] = (i >> 1) + cd.n[0] * (j >> 1);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < FT::NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    S.qo[e] = -1;
+    if (t >= FT::QL) continue;
+    int i = tx0 + t % FT::QX - 1, j = ty0 + t / FT::QX - 1;
+    if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) S.qo[e] = i + d.n[0] * j;
+  }
+  slot_setup<TX, TY, 1, FS::NR>(d, tx0, ty0, 0, S.rq, S.rdq, S.ri0, S.ri1, S.rj, S.rp, S.rbits);
+  slot_setup<TX, TY, 0, FS::NB>(d, tx0, ty0, 1, S.bq, S.bdq, S.bi0, S.bi1, S.bj, S.bp, S.bbits);
+#pragma unroll
+  for (int e = 0; e < FS::NW; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    const int lx = t % TX, ly = t / TX;
+    const int i = tx0 + lx, j = ty0 + ly;
+    S.wo[e] = (t < TX * TY && i < d.n[0] && j < d.n[1]) ? i + d.n[0] * j : -1;
+    S.wq[e] = (ly + 2) * FT::PX + (lx + 2);
+  }
+}
+
+// iterate window of plane kk into registers (x_in + coarse correction)
+template <typename T, int TX, int TY>
+__device__ inline void fine_load_x(const Dims& d, const Dims& cd, const FineSlots<TX, TY>& S, int kk,
+                                   const T* __restrict__ xin, const T* __restrict__ xc, T (&v)[FineTile<TX, TY>::NX]) {
+  using FT = FineTile<TX, TY>;
+  int k = kk;
+  const bool pz = wrap_axis(d, 2, k) && (xin || xc);
+  const long long base = (long long)k * d.n[0] * d.n[1];
+  const long long cbase = (long long)(k >> 1) * cd.n[0] * cd.n[1];
+#pragma unroll
+  for (int e = 0; e < FT::NX; ++e) {
     T s = (T)0;
-    if (pz && t < FT::PL && (xin || xc)) {
-      int i = tx0 + t % FT::PX - 2, j = ty0 + t / FT::PX - 2;
-      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
-        if (xin) s = xin[cell_index(d, i, j, k)];
-        if (xc) s += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
-      }
+    if (pz && S.xo[e] >= 0) {
+      if (xin) s = xin[base + S.xo[e]];
+      if (xc) s += xc[cbase + S.xco[e]];
     }
     v[e] = s;
   }
 }
 
 template <int TX, int TY>
-__device__ inline void fine_load_rf(const Dims& d, int kk, int tx0, int ty0, const double* __restrict__ rhs,
+__device__ inline void fine_load_rf(const Dims& d, const FineSlots<TX, TY>& S, int kk, const double* __restrict__ rhs,
                                     const uint8_t* __restrict__ flags, double (&r)[FineTile<TX, TY>::NQ],
                                     uint8_t (&f)[FineTile<TX, TY>::NQ]) {
   using FT = FineTile<TX, TY>;
   int k = kk;
   const bool pz = wrap_axis(d, 2, k);
+  const long long base = (long long)k * d.n[0] * d.n[1];
 #pragma unroll
   for (int e = 0; e < FT::NQ; ++e) {
-    const int t = threadIdx.x + e * RB_THREADS;
     r[e] = 0.0;
     f[e] = 0;
-    if (pz && t < FT::QL) {
-      int i = tx0 + t % FT::QX - 1, j = ty0 + t / FT::QX - 1;
-      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
-        const long long c = cell_index(d, i, j, k);
-        r[e] = rhs[c];
-        f[e] = flags[c];
-      }
+    if (pz && S.qo[e] >= 0) {
+      r[e] = rhs[base + S.qo[e]];
+      f[e] = flags[base + S.qo[e]];
     }
   }
 }
@@ -349,32 +436,29 @@ __device__ inline RegularRow<T> regular_row(const FineOp& op) {
   return RegularRow<T>{w[0], w[1], inv[0], inv[1]};
 }
 
-// Update the cells of one colour of plane k on the tile (RING = 0) or on the
-// tile + 1 ring (RING = 1) from LDS.  Threads walk only the cells of the
-// colour; regular cells take the per-phase constant row, cells with a cut
-// link or a wall face the full row of fine_row.
-template <typename T, int TX, int TY, int RING>
-__device__ inline void fine_update(const FineOp& op, const RegularRow<T>& rr, int k, int tx0, int ty0, int color,
-                                   const T* pm, T* p0, const T* pp, const double* rq, const uint8_t* fq) {
+// Update this thread's cells of one colour of plane k (slots from
+// FineSlots) from LDS.  Regular cells take the per-phase constant row,
+// cells with a cut link or a wall face the full row of fine_row.
+template <typename T, int TX, int TY, int NS>
+__device__ inline void fine_update(const FineOp& op, const RegularRow<T>& rr, int k, const int (&q0)[NS],
+                                   const int (&dq)[NS], const int (&i0)[NS], const int (&i1)[NS], const int (&jj)[NS],
+                                   const int (&pb)[NS], const int (&bits)[NS], const T* pm, T* p0, const T* pp,
+                                   const double* rq, const uint8_t* fq) {
   using FT = FineTile<TX, TY>;
-  constexpr int WX = TX + 2 * RING, WY = TY + 2 * RING, HX = WX / 2;
-  static_assert(WX % 2 == 0, "tile width must be even");
   const Dims& d = op.d;
   int kw = k;
   if (!wrap_axis(d, 2, kw)) return;
   const bool zwall = d.dim == 3 && !d.per[2] && (kw == 0 || kw == d.n[2] - 1);
-  for (int t = threadIdx.x; t < HX * WY; t += RB_THREADS) {
-    const int ly = t / HX - RING;
-    const int j = ty0 + ly;
-    const int lx = 2 * (t % HX) - RING + ((color + tx0 - RING + j + k) & 1);
-    const int i = tx0 + lx;
-    int iw = i, jw = j;
-    if (!wrap_axis(d, 0, iw) || !wrap_axis(d, 1, jw)) continue;
-    const int qq = (ly + 1) * FT::QX + (lx + 1);
-    const int q = (ly + 2) * FT::PX + (lx + 2);
+  const int kp = k & 1;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int P = pb[s] ^ kp;
+    const int bt = bits[s];
+    if (!(bt & (P ? 2 : 1))) continue;
+    const int q = q0[s] + P;
+    const int qq = q - dq[s];
     const uint8_t f = fq[qq];
-    const bool wall = zwall || (!d.per[0] && (iw == 0 || iw == d.n[0] - 1)) ||
-                      (!d.per[1] && (jw == 0 || jw == d.n[1] - 1));
+    const bool wall = zwall || (bt & (P ? 8 : 4)) || (bt & 16);
     if (!(f & F_CUT) && !wall) {
       const bool liq = (f & F_LIQ) != 0;
       T xn = (p0[q - 1] + p0[q + 1]) + (p0[q - FT::PX] + p0[q + FT::PX]);
@@ -382,7 +466,7 @@ __device__ inline void fine_update(const FineOp& op, const RegularRow<T>& rr, in
       p0[q] = ((T)rq[qq] + (liq ? rr.w1 : rr.w0) * xn) * (liq ? rr.inv1 : rr.inv0);
     } else {
       T diag, off[6], mass, rb = 0;
-      fine_row<T>(op, iw, jw, kw, f, diag, off, mass, rb);
+      fine_row<T>(op, P ? i1[s] : i0[s], jj[s], kw, f, diag, off, mass, rb);
       T sum = (T)rq[qq] - off[0] * p0[q - 1] - off[1] * p0[q + 1];
       sum -= off[2] * p0[q - FT::PX] + off[3] * p0[q + FT::PX];
       if (d.dim == 3) sum -= off[4] * pm[q] + off[5] * pp[q];
@@ -392,14 +476,20 @@ __device__ inline void fine_update(const FineOp& op, const RegularRow<T>& rr, in
 }
 
 template <typename T, int TX, int TY>
-__device__ inline void fine_write(const Dims& d, int k, int tx0, int ty0, const T* p0, T* __restrict__ xout) {
-  using FT = FineTile<TX, TY>;
-  for (int t = threadIdx.x; t < TX * TY; t += RB_THREADS) {
-    const int lx = t % TX, ly = t / TX;
-    const int i = tx0 + lx, j = ty0 + ly;
-    if (i < d.n[0] && j < d.n[1]) xout[cell_index(d, i, j, k)] = p0[(ly + 2) * FT::PX + (lx + 2)];
-  }
+__device__ inline void fine_write(const Dims& d, const FineSlots<TX, TY>& S, int k, const T* p0, T* __restrict__ xout) {
+  using FS = FineSlots<TX, TY>;
+  const long long base = (long long)k * d.n[0] * d.n[1];
+#pragma unroll
+  for (int e = 0; e < FS::NW; ++e)
+    if (S.wo[e] >= 0) xout[base + S.wo[e]] = p0[S.wq[e]];
 }
+
+#define FINE_RED(K, PM, P0, PP, RS, FS_)                                                                          \
+  fine_update<T, TX, TY, FS::NR>(op, rr, (K), S.rq, S.rdq, S.ri0, S.ri1, S.rj, S.rp, S.rbits, (PM), (P0), (PP), \
+                                 (RS), (FS_))
+#define FINE_BLACK(K, PM, P0, PP, RS, FS_)                                                                        \
+  fine_update<T, TX, TY, FS::NB>(op, rr, (K), S.bq, S.bdq, S.bi0, S.bi1, S.bj, S.bp, S.bbits, (PM), (P0), (PP), \
+                                 (RS), (FS_))
 
 template <typename T, int TX, int TY>
 __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
@@ -407,23 +497,26 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
                                     int bx, int by, int bz, T (*xs)[FineTile<TX, TY>::PL],
                                     double (*rs)[FineTile<TX, TY>::QL], uint8_t (*fs)[FineTile<TX, TY>::QL]) {
   using FT = FineTile<TX, TY>;
+  using FS = FineSlots<TX, TY>;
   const Dims& d = op.d;
   const RegularRow<T> rr = regular_row<T>(op);
   const int tx0 = bx * TX, ty0 = by * TY;
+  FS S;
+  fine_slots<TX, TY>(d, cd, tx0, ty0, S);
   T xv[FT::NX];
   double rv[FT::NQ];
   uint8_t fv[FT::NQ];
   if (d.dim < 3) {
-    fine_load_x<T, TX, TY>(d, 0, tx0, ty0, xin, xc, cd, xv);
-    fine_load_rf<TX, TY>(d, 0, tx0, ty0, rhs, op.flags, rv, fv);
+    fine_load_x<T, TX, TY>(d, cd, S, 0, xin, xc, xv);
+    fine_load_rf<TX, TY>(d, S, 0, rhs, op.flags, rv, fv);
     fine_store<T, TX, TY>(xv, xs[0]);
     fine_store_rf<TX, TY>(rv, fv, rs[0], fs[0]);
     __syncthreads();
-    fine_update<T, TX, TY, 1>(op, rr, 0, tx0, ty0, 0, xs[0], xs[0], xs[0], rs[0], fs[0]);
+    FINE_RED(0, xs[0], xs[0], xs[0], rs[0], fs[0]);
     __syncthreads();
-    fine_update<T, TX, TY, 0>(op, rr, 0, tx0, ty0, 1, xs[0], xs[0], xs[0], rs[0], fs[0]);
+    FINE_BLACK(0, xs[0], xs[0], xs[0], rs[0], fs[0]);
     __syncthreads();
-    fine_write<T, TX, TY>(d, 0, tx0, ty0, xs[0], xout);
+    fine_write<T, TX, TY>(d, S, 0, xs[0], xout);
     return;
   }
   // slots: x plane p in xs[p & 3], r / flags of plane p in rs[p & 1] (p may be negative)
@@ -433,27 +526,25 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
     T xa[FT::NX], xb[FT::NX];
     double ra[FT::NQ];
     uint8_t fa[FT::NQ];
-    fine_load_x<T, TX, TY>(d, z0 - 2, tx0, ty0, xin, xc, cd, xv);
-    fine_load_x<T, TX, TY>(d, z0 - 1, tx0, ty0, xin, xc, cd, xa);
-    fine_load_x<T, TX, TY>(d, z0, tx0, ty0, xin, xc, cd, xb);
-    fine_load_rf<TX, TY>(d, z0 - 1, tx0, ty0, rhs, op.flags, rv, fv);
-    fine_load_rf<TX, TY>(d, z0, tx0, ty0, rhs, op.flags, ra, fa);
+    fine_load_x<T, TX, TY>(d, cd, S, z0 - 2, xin, xc, xv);
+    fine_load_x<T, TX, TY>(d, cd, S, z0 - 1, xin, xc, xa);
+    fine_load_x<T, TX, TY>(d, cd, S, z0, xin, xc, xb);
+    fine_load_rf<TX, TY>(d, S, z0 - 1, rhs, op.flags, rv, fv);
+    fine_load_rf<TX, TY>(d, S, z0, rhs, op.flags, ra, fa);
     fine_store<T, TX, TY>(xv, xs[(z0 - 2) & 3]);
     fine_store<T, TX, TY>(xa, xs[(z0 - 1) & 3]);
     fine_store<T, TX, TY>(xb, xs[z0 & 3]);
     fine_store_rf<TX, TY>(rv, fv, rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
     fine_store_rf<TX, TY>(ra, fa, rs[z0 & 1], fs[z0 & 1]);
-    fine_load_x<T, TX, TY>(d, z0 + 1, tx0, ty0, xin, xc, cd, xv);
+    fine_load_x<T, TX, TY>(d, cd, S, z0 + 1, xin, xc, xv);
     fine_store<T, TX, TY>(xv, xs[(z0 + 1) & 3]);
   }
   __syncthreads();
-  fine_update<T, TX, TY, 1>(op, rr, z0 - 1, tx0, ty0, 0, xs[(z0 - 2) & 3], xs[(z0 - 1) & 3], xs[z0 & 3],
-                         rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
+  FINE_RED(z0 - 1, xs[(z0 - 2) & 3], xs[(z0 - 1) & 3], xs[z0 & 3], rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
   __syncthreads();
-  fine_update<T, TX, TY, 1>(op, rr, z0, tx0, ty0, 0, xs[(z0 - 1) & 3], xs[z0 & 3], xs[(z0 + 1) & 3], rs[z0 & 1],
-                         fs[z0 & 1]);
-  fine_load_x<T, TX, TY>(d, z0 + 2, tx0, ty0, xin, xc, cd, xv);
-  fine_load_rf<TX, TY>(d, z0 + 1, tx0, ty0, rhs, op.flags, rv, fv);
+  FINE_RED(z0, xs[(z0 - 1) & 3], xs[z0 & 3], xs[(z0 + 1) & 3], rs[z0 & 1], fs[z0 & 1]);
+  fine_load_x<T, TX, TY>(d, cd, S, z0 + 2, xin, xc, xv);
+  fine_load_rf<TX, TY>(d, S, z0 + 1, rhs, op.flags, rv, fv);
   __syncthreads();
   for (int k = z0; k < z1; ++k) {
     // plane k+2's iterate replaces plane k-2's, plane k+1's r / flags replace plane k-1's
@@ -461,18 +552,18 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
     fine_store_rf<TX, TY>(rv, fv, rs[(k + 1) & 1], fs[(k + 1) & 1]);
     __syncthreads();
     if (k + 1 < z1) {
-      fine_load_x<T, TX, TY>(d, k + 3, tx0, ty0, xin, xc, cd, xv);
-      fine_load_rf<TX, TY>(d, k + 2, tx0, ty0, rhs, op.flags, rv, fv);
+      fine_load_x<T, TX, TY>(d, cd, S, k + 3, xin, xc, xv);
+      fine_load_rf<TX, TY>(d, S, k + 2, rhs, op.flags, rv, fv);
     }
-    fine_update<T, TX, TY, 1>(op, rr, k + 1, tx0, ty0, 0, xs[k & 3], xs[(k + 1) & 3], xs[(k + 2) & 3], rs[(k + 1) & 1],
-                           fs[(k + 1) & 1]);
+    FINE_RED(k + 1, xs[k & 3], xs[(k + 1) & 3], xs[(k + 2) & 3], rs[(k + 1) & 1], fs[(k + 1) & 1]);
     __syncthreads();
-    fine_update<T, TX, TY, 0>(op, rr, k, tx0, ty0, 1, xs[(k - 1) & 3], xs[k & 3], xs[(k + 1) & 3], rs[k & 1],
-                           fs[k & 1]);
+    FINE_BLACK(k, xs[(k - 1) & 3], xs[k & 3], xs[(k + 1) & 3], rs[k & 1], fs[k & 1]);
     __syncthreads();
-    fine_write<T, TX, TY>(d, k, tx0, ty0, xs[k & 3], xout);
+    fine_write<T, TX, TY>(d, S, k, xs[k & 3], xout);
   }
 }
+#undef FINE_RED
+#undef FINE_BLACK
 
 // ---------------------------------------------------------------------------
 // tail of the V-cycle: every level small enough to sit in LDS, in one
@@ -1084,10 +1175,16 @@ struct WorkList {
   const int* start;  // [n + 1]: first block of entry e; start[n] = blocks in the launch
   const int* cid;    // [n]: case of entry e
   int n;
+  int c0, total;     // the case and block count when n == 1 (no table lookup)
 };
 
 __device__ inline int wl_find(const WorkList& w, int& lb, int& nb) {
   const int b = blockIdx.x;
+  if (w.n == 1) {
+    lb = b;
+    nb = w.total;
+    return w.c0;
+  }
   int lo = 0, hi = w.n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1125,7 +1222,7 @@ struct SolveCase {
   T* z[2];           // V-cycle result (z[0]) and the second sweep buffer
   double* p[2];
   double* q;
-  double* partial;   // [3][nred]
+  double* partial;   // [4][nred]: rows 0-1 z.r, z.q (0-2 at a residual recomputation), 2 p.q, 3 r.r
   Scal* sc;
   int nred;          // reduction blocks of this case
   int nlev, lt;      // levels; levels lt .. nlev-1 are solved by the tail kernel
@@ -1175,13 +1272,19 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   __shared__ uint8_t fs[2][FT::QL];
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
-  if (!ctl[c].active) return;
+  // register copies, read together with the control word: the sweep never
+  // goes back to the table
   const SolveCase<T>& C = cs[c];
-  const FineOp op = C.op;  // a register copy: the sweep never goes back to the table
-  const int bx = lb % C.fgx, by = (lb / C.fgx) % C.fgy, bz = lb / (C.fgx * C.fgy);
-  rb_fine_body<T, TX, TY>(op, C.r, in_sel < 0 ? nullptr : (const T*)C.z[in_sel],
-                          add_xc ? (const T*)C.lx[1][0] : nullptr, C.lev[1].d, C.z[out_sel], C.fzc, bx, by, bz, xs,
-                          rs, fs);
+  const FineOp op = C.op;
+  const double* r = C.r;
+  const T* zin = in_sel < 0 ? nullptr : (const T*)C.z[in_sel];
+  T* zout = C.z[out_sel];
+  const T* xc = add_xc ? (const T*)C.lx[1][0] : nullptr;
+  const Dims cd = C.lev[1].d;
+  const int fgx = C.fgx, fgy = C.fgy, fzc = C.fzc;
+  if (!ctl[c].active) return;
+  const int bx = lb % fgx, by = (lb / fgx) % fgy, bz = lb / (fgx * fgy);
+  rb_fine_body<T, TX, TY>(op, r, zin, xc, cd, zout, fzc, bx, by, bz, xs, rs, fs);
 }
 
 template <typename T>
@@ -1191,13 +1294,15 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
   __shared__ T buf[4][RB_PLANE];
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
-  if (!ctl[c].active) return;
   const SolveCase<T>& C = cs[c];
   const CoarseRows<T> rows{C.lev[l], C.lb[l]};
-  const int gx = C.lgx[l], gy = C.lgy[l];
-  rb_fused_body<T, CoarseRows<T>>(rows, in_sel < 0 ? nullptr : (const T*)C.lx[l][in_sel],
-                                  add_xc ? (const T*)C.lx[l + 1][0] : nullptr, C.lev[l + 1].d, C.lx[l][out_sel],
-                                  C.lzc[l], lb % gx, (lb / gx) % gy, lb / (gx * gy), buf);
+  const int gx = C.lgx[l], gy = C.lgy[l], zc = C.lzc[l];
+  const T* xin = in_sel < 0 ? nullptr : (const T*)C.lx[l][in_sel];
+  const T* xc = add_xc ? (const T*)C.lx[l + 1][0] : nullptr;
+  const Dims cd = C.lev[l + 1].d;
+  T* xout = C.lx[l][out_sel];
+  if (!ctl[c].active) return;
+  rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lb % gx, (lb / gx) % gy, lb / (gx * gy), buf);
 }
 
 // Residual of the 2^d children of every coarse cell of level 1, summed
@@ -1303,10 +1408,14 @@ __global__ void kb_dots(const SolveCase<T>* __restrict__ cs, const CaseCtl* __re
   write_partials<2>(v, C.partial, lb, nb);
 }
 
-// p_new = z + beta p_old; q = A p_new; partial p.q
+// gamma = z.r and beta from the dots' partials, then p_new = z + beta p_old,
+// q = A p_new, partial p.q (row 2).  Every block reduces the partials itself,
+// in the same fixed order, so no separate reduction launch is needed; block
+// 0 records gamma in the slot of this iteration's parity.
 template <typename T>
 __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
                                   int dc) {
+  __shared__ double sbeta;
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   const CaseCtl cc = ctl[c];
@@ -1314,7 +1423,24 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   const SolveCase<T>& C = cs[c];
   const FineOp op = C.op;
   const bool first = dc || cc.fresh;
-  const double beta = first ? 0.0 : C.sc->beta;
+  {
+    double g[3];
+    reduce_partials(C.partial, nb, 2, false, g);
+    if (threadIdx.x == 0) {
+      Scal* sc = C.sc;
+      const int so = cc.pi, sn = cc.pi ^ 1;
+      const double beta = first ? 0.0 : -sc->sa[so] * g[1] / sc->sg[so];
+      sbeta = beta;
+      if (lb == 0) {
+        sc->sg[sn] = g[0];
+        sc->gamma = g[0];
+        sc->beta = beta;
+        sc->zq = g[1];
+      }
+    }
+    __syncthreads();
+  }
+  const double beta = sbeta;
   const T* z = C.z[0];
   const double* p_old = C.p[cc.pi];
   double* p_new = C.p[cc.pi ^ 1];
@@ -1340,18 +1466,36 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
     q[i0] = s;
     v[0] += pc * s;
   }
-  write_partials<1>(v, C.partial, lb, nb);
+  write_partials<1>(v, C.partial + 2 * nb, lb, nb);
 }
 
-// x += alpha p; r -= alpha q; partial r.r
+// alpha = gamma / (p.q) from the p-update's partials (every block, fixed
+// order), then x += alpha p, r -= alpha q, partial r.r (row 3).
 template <typename T>
 __global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl) {
+  __shared__ double salpha;
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   const CaseCtl cc = ctl[c];
   if (!cc.active) return;
   const SolveCase<T>& C = cs[c];
-  const double alpha = C.sc->alpha;
+  {
+    double dlt[3];
+    reduce_partials(C.partial + 2 * nb, nb, 1, false, dlt);
+    if (threadIdx.x == 0) {
+      Scal* sc = C.sc;
+      const int sn = cc.pi ^ 1;
+      const double alpha = sc->sg[sn] / dlt[0];
+      salpha = alpha;
+      if (lb == 0) {
+        sc->sa[sn] = alpha;
+        sc->alpha = alpha;
+        sc->delta = dlt[0];
+      }
+    }
+    __syncthreads();
+  }
+  const double alpha = salpha;
   const double* p = C.p[cc.pi ^ 1];
   const double* q = C.q;
   double* x = C.x;
@@ -1363,56 +1507,39 @@ __global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, const CaseCtl*
     r[i] = rc;
     v[0] += rc * rc;
   }
-  write_partials<1>(v, C.partial, lb, nb);
+  write_partials<1>(v, C.partial + 3 * nb, lb, nb);
 }
 
-// One block per case: reduce its partials and advance its scalars.  FIN_RR
-// also ends the iteration: the direction slot flips, the restart flag
-// clears, and the case stops (active = 0) once r.r <= stop2 or on NaN/Inf.
+// One block per case: reduce its partials (nv rows from row `row`).
+// FIN_INIT records b.b, r.r and the floor norm; FIN_RR ends an iteration:
+// the direction slot flips, the restart flag clears, the iteration count
+// advances, and the case stops (active = 0) once r.r <= stop2 or on NaN/Inf.
 template <typename T>
 __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl,
-                            const double* __restrict__ stop2, int kind, int nv, int mask, int dc) {
+                            const double* __restrict__ stop2, int kind, int nv, int row, int mask) {
   const int c = blockIdx.x;
   const CaseCtl cc = ctl[c];
   if (!selected(cc, mask)) return;
   const SolveCase<T>& C = cs[c];
   double v[3];
-  reduce_partials(C.partial, C.nred, nv, false, v);
+  reduce_partials(C.partial + row * C.nred, C.nred, nv, false, v);
   if (threadIdx.x != 0) return;
   Scal* sc = C.sc;
   bool bad = false;
-  switch (kind) {
-    case FIN_INIT:
-      sc->bb = v[0];
-      sc->rr = v[1];
-      sc->aa = v[2];
-      bad = !isfinite(v[0]) || !isfinite(v[1]);
-      break;
-    case FIN_GAMMA: {
-      const bool first = dc || cc.fresh;
-      const double gnew = v[0];
-      sc->beta = first ? 0.0 : -sc->alpha * v[1] / sc->gamma;
-      sc->gamma = gnew;
-      sc->zq = v[1];
-      bad = !isfinite(gnew);
-      break;
-    }
-    case FIN_DELTA:
-      sc->delta = v[0];
-      sc->alpha = sc->gamma / v[0];
-      bad = !isfinite(sc->alpha);
-      break;
-    case FIN_RR: {
-      sc->rr = v[0];
-      sc->iters += 1;
-      bad = !isfinite(v[0]);
-      CaseCtl n = cc;
-      n.fresh = 0;
-      n.pi = cc.pi ^ 1;
-      if (v[0] <= stop2[c]) n.active = 0;
-      ctl[c] = n;
-      break;
-    }
+  if (kind == FIN_INIT) {
+    sc->bb = v[0];
+    sc->rr = v[1];
+    sc->aa = v[2];
+    bad = !isfinite(v[0]) || !isfinite(v[1]);
+  } else {
+    sc->rr = v[0];
+    sc->iters += 1;
+    bad = !isfinite(v[0]);
+    CaseCtl n = cc;
+    n.fresh = 0;
+    n.pi = cc.pi ^ 1;
+    if (v[0] <= stop2[c]) n.active = 0;
+    ctl[c] = n;
   }
   if (bad) {
     sc->err |= ERR_NAN;
@@ -1699,6 +1826,13 @@ HostList make_list(const std::vector<std::pair<int, int>>& ent, std::vector<int>
   L.w.start = dev + o;
   L.w.cid = dev + o + m + 1;
   L.w.n = m;
+  L.w.c0 = 0;
+  for (const auto& e : ent)
+    if (e.second > 0) {
+      L.w.c0 = e.first;
+      break;
+    }
+  L.w.total = tot;
   L.blocks = tot;
   return L;
 }
@@ -1779,22 +1913,18 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
     vcycle_b(P, cs, st, pf);
     hipLaunchKernelGGL(kb_dots<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl, P.red.w,
                        dc);
-    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
-                       (int)FIN_GAMMA, 2, (int)MASK_ACTIVE, dc);
     {
       ProfScope ps(pf, EBIT_KC_OUTER_APPLY, st);
       hipLaunchKernelGGL(kb_p_update_apply<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs,
                          (const CaseCtl*)P.d_ctl, P.red.w, dc);
     }
-    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
-                       (int)FIN_DELTA, 1, (int)MASK_ACTIVE, dc);
     {
       ProfScope ps(pf, EBIT_KC_OUTER_UPDATE, st);
       hipLaunchKernelGGL(kb_update_xr<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                          P.red.w);
     }
     hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
-                       (int)FIN_RR, 1, (int)MASK_ACTIVE, dc);
+                       (int)FIN_RR, 1, 3, (int)MASK_ACTIVE);
   }
 }
 
@@ -1990,7 +2120,7 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
   hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                      P.red.w, (int)MASK_ALL, use_guess ? 1 : 0);
   hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2, (int)FIN_INIT,
-                     3, (int)MASK_ALL, dc);
+                     3, 0, (int)MASK_ALL);
   PK(hipGetLastError());
   PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
   PK(hipStreamSynchronize(st));
@@ -2062,7 +2192,7 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
       hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                          P.red.w, (int)MASK_RECHECK, 1);
       hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
-                         (int)FIN_INIT, 3, (int)MASK_RECHECK, dc);
+                         (int)FIN_INIT, 3, 0, (int)MASK_RECHECK);
       PK(hipGetLastError());
       PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
       PK(hipStreamSynchronize(st));
