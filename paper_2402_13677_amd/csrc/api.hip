@@ -241,6 +241,16 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
     lv[l].x32b = cv.take<float>(n);
     lv[l].b32 = cv.take<float>(n);
   }
+  for (int l = 1; l < nlev; ++l)
+    if (lv[l].d.N <= EBIT_DENSE_MAX) {
+      const long long n2 = lv[l].d.N * lv[l].d.N;
+      for (int s = 0; s < 2; ++s) {
+        lv[l].inv64[s] = cv.take<double>(n2);
+        lv[l].inv32[s] = cv.take<float>(n2);
+      }
+      lv[l].inv_ok = cv.take<int>(2);
+      break;
+    }
   const size_t plan_bytes = ebit_plan_device_bytes(1, o ? o->precision : EBIT_FP64);
   char* plan_mem = cv.take<char>(plan_bytes);
   const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;

@@ -225,7 +225,16 @@ struct EbitLevelHost {
   float* x32;
   float* x32b;
   float* b32;
+  // the first level of at most EBIT_DENSE_MAX cells also holds the inverse
+  // of its operator per system (transposed, FP64 and FP32), used as the
+  // exact coarsest solve, and a flag per system: 1 if the inversion
+  // succeeded (null elsewhere)
+  double* inv64[2];
+  float* inv32[2];
+  int* inv_ok;
 };
+
+#define EBIT_DENSE_MAX 64
 
 // Optional per-kernel timing with hipEvents recorded around individual
 // launches on the context's stream (kernel classes: ebit_kernel_class).

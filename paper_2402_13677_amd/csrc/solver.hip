@@ -572,6 +572,7 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
 // ---------------------------------------------------------------------------
 #define EBIT_TAIL_MAX 16
 #define EBIT_TAIL_THREADS 1024
+#define TAIL_BATCH 8
 
 // LDS block of one tail level: x, b, diag, 1/diag, off[0 .. dim-1], N
 // elements each.
@@ -591,6 +592,9 @@ struct TailArgs {
   const T* off[EBIT_TAIL_MAX][3];
   const T* bg;  // right-hand side of the top tail level
   T* xg;        // its correction (output)
+  int dl;              // tail level solved exactly by its inverse, or -1
+  const T* inv;        // that inverse (transposed)
+  const int* inv_ok;   // 1 if the inversion succeeded
 };
 
 // Register copy of one tail level's shape (read once per level, so the
@@ -799,9 +803,9 @@ __device__ inline void wave_sweep(T* sm, const TLev& d, const LaneCells& lc, int
 // waits at the caller's barrier); level l0's right-hand side is in place and
 // its iterate zero.
 template <typename T>
-__device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0) {
+__device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0, int nl, const T* inv) {
   const int lane = threadIdx.x;
-  const int nl = a.nl, nu1 = a.nu1, nu2 = a.nu2;
+  const int nu1 = a.nu1, nu2 = a.nu2;
   for (int l = l0; l < nl - 1; ++l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
@@ -813,7 +817,18 @@ __device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0) {
     tail_restrict(sm, L, C, lane, 64);
     wave_sync();
   }
-  {
+  if (inv) {
+    // coarsest level solved exactly: x = A^-1 b, lane t forming row t
+    const TLev L = tlev(a.L[nl - 1]);
+    T* x = TAIL_X(L, sm);
+    const T* b = TAIL_B(L, sm);
+    T acc = 0;
+    if (lane < L.N)
+      for (int j = 0; j < L.N; ++j) acc += inv[j * L.N + lane] * b[j];
+    wave_sync();
+    if (lane < L.N) x[lane] = acc;
+    wave_sync();
+  } else {
     // coarsest level: symmetric Gauss-Seidel by one lane (exact for one cell)
     const TLev L = tlev(a.L[nl - 1]);
     if (lane == 0) {
@@ -850,31 +865,53 @@ template <typename T>
 __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nl = a.nl, nu2 = a.nu2, nu1 = a.nu1;
-  for (int l = 0; l < nl; ++l) {
-    const TLev L = tlev(a.L[l]);
-    const int N = L.N;
-    const T* dg = a.diag[l];
-    const T* o0 = a.off[l][0];
-    const T* o1 = a.off[l][1];
-    const T* o2 = a.off[l][2];
-    const T* bg = a.bg;
-    T* x = TAIL_X(L, sm);
-    for (int q = tid; q < N; q += nth) {
-      const T d = dg[q];
-      x[2 * N + q] = d;
-      x[3 * N + q] = (T)1 / d;
-      x[4 * N + q] = o0[q];
-      if (L.dim >= 2) x[5 * N + q] = o1[q];
-      if (L.dim == 3) x[6 * N + q] = o2[q];
-      if (l == 0) {
-        x[N + q] = bg[q];
+  // Staging: every (level, cell) pair of the tail is one item; a thread
+  // issues the global loads of TAIL_BATCH items before storing any, so the
+  // memory latency is paid a few times, not once per level and per cell.
+  int tot = 0;
+  for (int l = 0; l < nl; ++l) tot += (int)a.L[l].d.N;
+  for (int base = 0; base < tot; base += nth * TAIL_BATCH) {
+    T vd[TAIL_BATCH], v0[TAIL_BATCH], v1[TAIL_BATCH], v2[TAIL_BATCH], vb[TAIL_BATCH];
+    int lv[TAIL_BATCH], qv[TAIL_BATCH];
+#pragma unroll
+    for (int u = 0; u < TAIL_BATCH; ++u) {
+      int item = base + u * nth + tid;
+      lv[u] = -1;
+      if (item >= tot) continue;
+      int l = 0;
+      while (item >= (int)a.L[l].d.N) item -= (int)a.L[l++].d.N;
+      lv[u] = l;
+      qv[u] = item;
+      const int dim = a.L[l].d.dim;
+      vd[u] = a.diag[l][item];
+      v0[u] = a.off[l][0][item];
+      v1[u] = dim >= 2 ? a.off[l][1][item] : (T)0;
+      v2[u] = dim == 3 ? a.off[l][2][item] : (T)0;
+      vb[u] = l == 0 ? a.bg[item] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < TAIL_BATCH; ++u) {
+      if (lv[u] < 0) continue;
+      const TLev L = tlev(a.L[lv[u]]);
+      const int N = L.N, q = qv[u];
+      T* x = TAIL_X(L, sm);
+      x[2 * N + q] = vd[u];
+      x[3 * N + q] = (T)1 / vd[u];
+      x[4 * N + q] = v0[u];
+      if (L.dim >= 2) x[5 * N + q] = v1[u];
+      if (L.dim == 3) x[6 * N + q] = v2[u];
+      if (lv[u] == 0) {
+        x[N + q] = vb[u];
         x[q] = (T)0;
       }
     }
   }
   __syncthreads();
-  // levels l0 .. nl-1 are small enough for one wavefront
-  int l0 = nl - 1;
+  // with a usable inverse the V-cycle stops at its level
+  const T* inv = (a.dl >= 0 && *a.inv_ok) ? a.inv : nullptr;
+  const int nle = inv ? a.dl + 1 : nl;
+  // levels l0 .. nle-1 are small enough for one wavefront
+  int l0 = nle - 1;
   while (l0 > 0 && a.L[l0 - 1].d.N <= EBIT_TAIL_WAVE_CELLS) --l0;
   for (int l = 0; l < l0; ++l) {
     const TLev L = tlev(a.L[l]);
@@ -887,7 +924,7 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
     tail_restrict(sm, L, C, tid, nth);
     __syncthreads();
   }
-  if (tid < 64) tail_wave<T>(a, sm, l0);
+  if (tid < 64) tail_wave<T>(a, sm, l0, nle, inv);
   __syncthreads();
   for (int l = l0 - 1; l >= 0; --l) {
     const TLev L = tlev(a.L[l]);
@@ -1008,6 +1045,84 @@ __global__ void k_cast_level(long long n, int dim, const double* d64, const doub
   p0[t] = (float)o0[t];
   if (dim > 1) p1[t] = (float)o1[t];
   if (dim > 2) p2[t] = (float)o2[t];
+}
+
+
+// Inverse of the operator of a level of at most EBIT_DENSE_MAX cells (the
+// exact coarsest solve): assembled row by row with the couplings of
+// coarse_offsum, inverted in place by Gauss-Jordan elimination without
+// pivoting (the operator is symmetric positive definite), written
+// transposed so that lane t of a wave reads column t contiguously.  A
+// pivot that is not positive and finite (a singular level) clears *ok and
+// the tail keeps its Gauss-Seidel coarsest solve.
+__global__ __launch_bounds__(1024) void k_dense_inverse(CoarseOp<double> op, double* inv64, float* inv32, int* ok) {
+  __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
+  __shared__ double prow[EBIT_DENSE_MAX], pcol[EBIT_DENSE_MAX];
+  const int N = (int)op.d.N;
+  const int tid = threadIdx.x;
+  // thread (ti, tj) of a 32 x 32 grid owns elements (ti + 32 u, tj + 32 v)
+  const int ti = tid >> 5, tj = tid & 31;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) A[ti + 32 * u][tj + 32 * v] = 0.0;
+  __syncthreads();
+  if (tid < N) {
+    int i, j, k;
+    cell_ijk(op.d, tid, i, j, k);
+    A[tid][tid] = op.diag[tid];
+    for (int a = 0; a < op.d.dim; ++a) {
+      int ni, nj, nk;
+      if (neighbour(op.d, i, j, k, 2 * a + 1, ni, nj, nk)) A[tid][cell_index(op.d, ni, nj, nk)] += op.off[a][tid];
+      if (neighbour(op.d, i, j, k, 2 * a, ni, nj, nk)) {
+        const long long m = cell_index(op.d, ni, nj, nk);
+        A[tid][m] += op.off[a][m];
+      }
+    }
+  }
+  bool good = true;
+  for (int p = 0; p < N; ++p) {
+    __syncthreads();
+    if (tid < N) {
+      prow[tid] = A[p][tid];
+      pcol[tid] = A[tid][p];
+    }
+    __syncthreads();
+    const double piv = prow[p];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      good = false;
+      break;
+    }
+    const double ip = 1.0 / piv;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = ti + 32 * u, j = tj + 32 * v;
+        if (i >= N || j >= N) continue;
+        double w;
+        if (i == p && j == p)
+          w = ip;
+        else if (i == p)
+          w = prow[j] * ip;
+        else if (j == p)
+          w = -pcol[i] * ip;
+        else
+          w = A[i][j] - pcol[i] * prow[j] * ip;
+        A[i][j] = w;
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int i = ti + 32 * u, j = tj + 32 * v;
+      if (i >= N || j >= N) continue;
+      inv64[j * N + i] = A[i][j];
+      if (inv32) inv32[j * N + i] = (float)A[i][j];
+    }
+  if (tid == 0) *ok = good ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,6 +1708,15 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
                          o.diag, o.off[0], o.off[1], o.off[2], lv[l].diag32[sys], lv[l].off32[sys][0],
                          dim > 1 ? lv[l].off32[sys][1] : nullptr, dim > 2 ? lv[l].off32[sys][2] : nullptr);
     }
+    if (lv[l].inv64[sys]) {
+      CoarseOp<double> f;
+      f.d = lv[l].d;
+      f.diag = lv[l].diag64[sys];
+      f.mass = lv[l].mass64[sys];
+      for (int a = 0; a < 3; ++a) f.off[a] = (a < f.d.dim) ? lv[l].off64[sys][a] : nullptr;
+      hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, st, f, lv[l].inv64[sys],
+                         want32 ? lv[l].inv32[sys] : nullptr, lv[l].inv_ok + sys);
+    }
   }
   return hipGetLastError();
 }
@@ -1707,6 +1831,12 @@ template <>
 double* lvb<double>(const EbitLevelHost& L) { return L.b64; }
 template <>
 float* lvb<float>(const EbitLevelHost& L) { return L.b32; }
+template <typename T>
+const T* dense_inv(const EbitLevelHost& L, int sys);
+template <>
+const double* dense_inv<double>(const EbitLevelHost& L, int sys) { return L.inv64[sys]; }
+template <>
+const float* dense_inv<float>(const EbitLevelHost& L, int sys) { return L.inv32[sys]; }
 template <typename T>
 T* zb(const EbitSolveBufs& B, int s);
 template <>
@@ -2040,6 +2170,16 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
         for (int q = 0; q < 3; ++q) ta.off[m][q] = co.off[q];
         off += tail_level_elems(L.d);
       }
+      ta.dl = -1;
+      ta.inv = nullptr;
+      ta.inv_ok = nullptr;
+      for (int m = 0; m < ta.nl; ++m)
+        if (pc.lv[lt[c] + m].inv64[sys]) {
+          ta.dl = m;
+          ta.inv = dense_inv<T>(pc.lv[lt[c] + m], sys);
+          ta.inv_ok = pc.lv[lt[c] + m].inv_ok + sys;
+          break;
+        }
       ta.bg = lvb<T>(pc.lv[lt[c]]);
       ta.xg = lvx<T>(pc.lv[lt[c]], 0);
       if (sys == 0) {
