@@ -32,6 +32,8 @@ struct ebit_ctx {
   EbitPlan* plan;      // solve plan of this one case
   char* plan_mem;
   size_t plan_bytes;
+  char* build_tabs;    // device tables of the hierarchy build
+  int build_ls;        // first level built by one work-group
   hipError_t herr;
   char msg[512];
 };
@@ -253,10 +255,12 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
     }
   const size_t plan_bytes = ebit_plan_device_bytes(1, o ? o->precision : EBIT_FP64);
   char* plan_mem = cv.take<char>(plan_bytes);
+  char* build_tabs = cv.take<char>(ebit_build_table_bytes());
   const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;
   if (ctx) {
     ctx->plan_mem = plan_mem;
     ctx->plan_bytes = plan_bytes;
+    ctx->build_tabs = build_tabs;
     ctx->fd = fd;
     ctx->flags = flags;
     for (int a = 0; a < 3; ++a) ctx->th[a] = th[a];
@@ -381,8 +385,7 @@ ebit_status build_finish(ebit_ctx* c, const Scal& hs, hipStream_t st) {
   if (hs.err & ERR_GEOM_NOFACET) return fail(c, EBIT_EGEOM, "a cut link has no interface cell on either side");
   set_ops(c);
   const int want32 = c->opts.precision == EBIT_MIXED;
-  for (int sys = 0; sys < 2; ++sys)
-    HIPCK(c, ebit_build_hierarchy(&c->op[sys], c->lv, c->nlev, sys, want32, st), "hierarchy");
+  HIPCK(c, ebit_build_hierarchy(c->op, c->lv, c->nlev, want32, c->build_tabs, c->build_ls, st), "hierarchy");
   c->built = 1;
   return EBIT_OK;
 }
@@ -459,6 +462,25 @@ ebit_status ebit_create(ebit_ctx** out, const ebit_grid* g, const ebit_props* p,
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
     return EBIT_EHIP;
+  }
+  {
+    // hierarchy-build tables: fixed pointers, uploaded once
+    const size_t tb = ebit_build_table_bytes();
+    char* host = new (std::nothrow) char[tb];
+    hipError_t e = host ? hipSuccess : hipErrorOutOfMemory;
+    if (host) {
+      ebit_build_tables(c->lv, c->nlev, c->opts.precision == EBIT_MIXED, host);
+      c->build_ls = *(const int*)host;
+      e = hipMemcpy(c->build_tabs, host, tb, hipMemcpyHostToDevice);
+      delete[] host;
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipEventDestroy(c->ev0);
+      (void)hipEventDestroy(c->ev1);
+      delete c;
+      return EBIT_EHIP;
+    }
   }
   const EbitPlanCase pc{c->lv, c->nlev, c->op, c->B, c->bvec};
   if (ebit_plan_create(&c->plan, 1, &pc, &c->opts, c->B.tail_lds, c->plan_mem, c->plan_bytes) != hipSuccess) {

@@ -272,8 +272,13 @@ hipError_t ebit_launch_geometry(const ebit::Dims* d, double h, const double* con
                                 ebit::Scal* scal, hipStream_t st);
 hipError_t ebit_launch_fill_f64(long long n, double* x, double v, hipStream_t st);
 hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
-hipError_t ebit_build_hierarchy(const ebit::FineOp* op, EbitLevelHost* lv, int nlev, int sys, int want32,
-                                hipStream_t st);
+// Hierarchy builds: host tables of the one-work-group part (2 systems,
+// ebit_build_table_bytes() bytes) are filled once and uploaded by the
+// caller; ls is the first level that part builds.
+void ebit_build_tables(const EbitLevelHost* lv, int nlev, int want32, void* host_tabs);
+size_t ebit_build_table_bytes(void);
+hipError_t ebit_build_hierarchy(const ebit::FineOp* op, EbitLevelHost* lv, int nlev, int want32, const void* dev_tabs,
+                                int ls, hipStream_t st);
 hipError_t ebit_launch_apply(const ebit::FineOp* op, const double* x, double* y, hipStream_t st);
 hipError_t ebit_launch_heat_rhs(const ebit::FineOp* op, const double* Ts, double* b, hipStream_t st);
 hipError_t ebit_launch_finalize_max(const double* partial, int nb, ebit::Scal* sc, hipStream_t st);

@@ -956,12 +956,26 @@ struct BuildOut {
   double* diag;
   double* mass;
   double* off[3];
+  float* d32;     // FP32 copies of diag and off (null: none)
+  float* o32[3];
 };
 
-// aggregate index of a (wrapped) fine cell along each axis: q >> 1
-__global__ void k_build_from_fine(FineOp op, BuildOut o) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= o.cd.N) return;
+__device__ inline void store_built(const BuildOut& o, long long I, double M, double F, const double (&cross)[3]) {
+  const double dg = M + 0.5 * F;
+  o.diag[I] = dg;
+  o.mass[I] = M;
+  if (o.d32) o.d32[I] = (float)dg;
+  for (int a = 0; a < 3; ++a)
+    if (o.off[a]) {
+      const double v = 0.5 * cross[a];
+      o.off[a][I] = v;
+      if (o.o32[a]) o.o32[a][I] = (float)v;
+    }
+}
+
+// coarse cell I from the matrix-free fine operator (aggregate index of a
+// wrapped fine cell along each axis: q >> 1)
+__device__ inline void build_cell_from_fine(const FineOp& op, const BuildOut& o, long long I) {
   int ci, cj, ck;
   cell_ijk(o.cd, I, ci, cj, ck);
   double M = 0, F = 0, cross[3] = {0, 0, 0};
@@ -979,8 +993,9 @@ __global__ void k_build_from_fine(FineOp op, BuildOut o) {
         fine_row<double>(op, i, j, k, op.flags[c], diag, off, mass, rb);
         M += mass;
         F += diag - mass;
-        for (int s = 0; s < 2 * op.d.dim; ++s) {
-          if (off[s] == 0.0) continue;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          if (s >= 2 * op.d.dim || off[s] == 0.0) continue;
           int ni, nj, nk;
           neighbour(op.d, i, j, k, s, ni, nj, nk);
           const bool same = (ni >> 1) == ci && (nj >> 1) == cj && (nk >> 1) == ck;
@@ -992,15 +1007,11 @@ __global__ void k_build_from_fine(FineOp op, BuildOut o) {
       }
     }
   }
-  o.diag[I] = M + 0.5 * F;
-  o.mass[I] = M;
-  for (int a = 0; a < 3; ++a)
-    if (o.off[a]) o.off[a][I] = 0.5 * cross[a];
+  store_built(o, I, M, F, cross);
 }
 
-__global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= o.cd.N) return;
+// coarse cell I from the explicit level above
+__device__ inline void build_cell_from_coarse(const CoarseOp<double>& op, const BuildOut& o, long long I) {
   int ci, cj, ck;
   cell_ijk(o.cd, I, ci, cj, ck);
   double M = 0, F = 0, cross[3] = {0, 0, 0};
@@ -1016,7 +1027,9 @@ __global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
         const long long c = cell_index(op.d, i, j, k);
         M += op.mass[c];
         F += op.diag[c] - op.mass[c];
-        for (int s = 0; s < 2 * op.d.dim; ++s) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          if (s >= 2 * op.d.dim) continue;
           int ni, nj, nk;
           if (!neighbour(op.d, i, j, k, s, ni, nj, nk)) continue;
           const long long m = cell_index(op.d, ni, nj, nk);
@@ -1031,20 +1044,17 @@ __global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
       }
     }
   }
-  o.diag[I] = M + 0.5 * F;
-  o.mass[I] = M;
-  for (int a = 0; a < 3; ++a)
-    if (o.off[a]) o.off[a][I] = 0.5 * cross[a];
+  store_built(o, I, M, F, cross);
 }
 
-__global__ void k_cast_level(long long n, int dim, const double* d64, const double* o0, const double* o1,
-                             const double* o2, float* d32, float* p0, float* p1, float* p2) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  d32[t] = (float)d64[t];
-  p0[t] = (float)o0[t];
-  if (dim > 1) p1[t] = (float)o1[t];
-  if (dim > 2) p2[t] = (float)o2[t];
+__global__ void k_build_from_fine(FineOp op, BuildOut o) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I < o.cd.N) build_cell_from_fine(op, o, I);
+}
+
+__global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I < o.cd.N) build_cell_from_coarse(op, o, I);
 }
 
 
@@ -1055,9 +1065,8 @@ __global__ void k_cast_level(long long n, int dim, const double* d64, const doub
 // transposed so that lane t of a wave reads column t contiguously.  A
 // pivot that is not positive and finite (a singular level) clears *ok and
 // the tail keeps its Gauss-Seidel coarsest solve.
-__global__ __launch_bounds__(1024) void k_dense_inverse(CoarseOp<double> op, double* inv64, float* inv32, int* ok) {
-  __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
-  __shared__ double prow[EBIT_DENSE_MAX], pcol[EBIT_DENSE_MAX];
+__device__ inline void dense_inverse(const CoarseOp<double>& op, double* inv64, float* inv32, int* ok,
+                                     double (*A)[EBIT_DENSE_MAX + 1], double* prow, double* pcol) {
   const int N = (int)op.d.N;
   const int tid = threadIdx.x;
   // thread (ti, tj) of a 32 x 32 grid owns elements (ti + 32 u, tj + 32 v)
@@ -1123,6 +1132,56 @@ __global__ __launch_bounds__(1024) void k_dense_inverse(CoarseOp<double> op, dou
       if (inv32) inv32[j * N + i] = (float)A[i][j];
     }
   if (tid == 0) *ok = good ? 1 : 0;
+}
+
+// Per system, everything the one-work-group part of a hierarchy build needs
+// (filled once per context: the pointers do not change between builds).
+struct BuildTable {
+  int ls, nlev, dl;  // first level built by k_build_small, level count, dense level (-1: none)
+  Dims d[EBIT_MAX_LEVELS];
+  double* diag[EBIT_MAX_LEVELS];
+  double* mass[EBIT_MAX_LEVELS];
+  double* off[EBIT_MAX_LEVELS][3];
+  float* d32[EBIT_MAX_LEVELS];
+  float* o32[EBIT_MAX_LEVELS][3];
+  double* inv64;
+  float* inv32;
+  int* inv_ok;
+};
+
+// Levels ls .. nlev-1 (each from the one above), then the inverse of the
+// dense level: one work-group per system, a barrier between levels.
+__global__ __launch_bounds__(1024) void k_build_small(const BuildTable* __restrict__ tabs) {
+  __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
+  __shared__ double prow[EBIT_DENSE_MAX], pcol[EBIT_DENSE_MAX];
+  const BuildTable& t = tabs[blockIdx.x];
+  const int ls = t.ls, nlev = t.nlev, dl = t.dl;
+  for (int l = ls; l < nlev; ++l) {
+    CoarseOp<double> f;
+    f.d = t.d[l - 1];
+    f.diag = t.diag[l - 1];
+    f.mass = t.mass[l - 1];
+    for (int a = 0; a < 3; ++a) f.off[a] = t.off[l - 1][a];
+    BuildOut o;
+    o.cd = t.d[l];
+    o.diag = t.diag[l];
+    o.mass = t.mass[l];
+    o.d32 = t.d32[l];
+    for (int a = 0; a < 3; ++a) {
+      o.off[a] = t.off[l][a];
+      o.o32[a] = t.o32[l][a];
+    }
+    for (long long I = threadIdx.x; I < o.cd.N; I += blockDim.x) build_cell_from_coarse(f, o, I);
+    __syncthreads();
+  }
+  if (dl >= 0) {
+    CoarseOp<double> f;
+    f.d = t.d[dl];
+    f.diag = t.diag[dl];
+    f.mass = t.mass[dl];
+    for (int a = 0; a < 3; ++a) f.off[a] = t.off[dl][a];
+    dense_inverse(f, t.inv64, t.inv32, t.inv_ok, A, prow, pcol);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1682,42 +1741,79 @@ hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st) 
   return hipGetLastError();
 }
 
-// Build the coarse hierarchy of one system: level 1 from the matrix-free fine
-// operator, then each level from the one above; FP32 copies if wanted.
-hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, int sys, int want32,
-                                hipStream_t st) {
-  for (int l = 1; l < nlev; ++l) {
-    BuildOut o;
-    o.cd = lv[l].d;
-    o.diag = lv[l].diag64[sys];
-    o.mass = lv[l].mass64[sys];
-    for (int a = 0; a < 3; ++a) o.off[a] = (a < o.cd.dim) ? lv[l].off64[sys][a] : nullptr;
-    if (l == 1) {
-      hipLaunchKernelGGL(k_build_from_fine, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, *op, o);
-    } else {
-      CoarseOp<double> f;
-      f.d = lv[l - 1].d;
-      f.diag = lv[l - 1].diag64[sys];
-      f.mass = lv[l - 1].mass64[sys];
-      for (int a = 0; a < 3; ++a) f.off[a] = (a < f.d.dim) ? lv[l - 1].off64[sys][a] : nullptr;
-      hipLaunchKernelGGL(k_build_from_coarse, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, f, o);
+// The build plan of a context: the first level built by the one-work-group
+// kernel (>= 2; levels of at most EBIT_BUILD_SMALL cells go there) and the
+// per-system tables it reads (host copies; the caller uploads them).
+#define EBIT_BUILD_SMALL 4096
+void ebit_build_tables(const EbitLevelHost* lv, int nlev, int want32, void* host_tabs) {
+  BuildTable* tab = (BuildTable*)host_tabs;
+  int ls = nlev;
+  for (int l = 2; l < nlev; ++l)
+    if (lv[l].d.N <= EBIT_BUILD_SMALL) {
+      ls = l;
+      break;
     }
-    if (want32) {
-      const int dim = o.cd.dim;
-      hipLaunchKernelGGL(k_cast_level, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, o.cd.N, dim,
-                         o.diag, o.off[0], o.off[1], o.off[2], lv[l].diag32[sys], lv[l].off32[sys][0],
-                         dim > 1 ? lv[l].off32[sys][1] : nullptr, dim > 2 ? lv[l].off32[sys][2] : nullptr);
+  int dl = -1;
+  for (int l = 1; l < nlev; ++l)
+    if (lv[l].inv64[0]) dl = l;
+  for (int sys = 0; sys < 2; ++sys) {
+    BuildTable& t = tab[sys];
+    memset(&t, 0, sizeof(t));
+    t.ls = ls;
+    t.nlev = nlev;
+    t.dl = dl;
+    for (int l = 0; l < nlev; ++l) {
+      t.d[l] = lv[l].d;
+      if (l == 0) continue;
+      t.diag[l] = lv[l].diag64[sys];
+      t.mass[l] = lv[l].mass64[sys];
+      t.d32[l] = want32 ? lv[l].diag32[sys] : nullptr;
+      for (int a = 0; a < 3; ++a) {
+        const bool on = a < lv[l].d.dim;
+        t.off[l][a] = on ? lv[l].off64[sys][a] : nullptr;
+        t.o32[l][a] = (on && want32) ? lv[l].off32[sys][a] : nullptr;
+      }
     }
-    if (lv[l].inv64[sys]) {
-      CoarseOp<double> f;
-      f.d = lv[l].d;
-      f.diag = lv[l].diag64[sys];
-      f.mass = lv[l].mass64[sys];
-      for (int a = 0; a < 3; ++a) f.off[a] = (a < f.d.dim) ? lv[l].off64[sys][a] : nullptr;
-      hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, st, f, lv[l].inv64[sys],
-                         want32 ? lv[l].inv32[sys] : nullptr, lv[l].inv_ok + sys);
+    if (dl >= 0) {
+      t.inv64 = lv[dl].inv64[sys];
+      t.inv32 = want32 ? lv[dl].inv32[sys] : nullptr;
+      t.inv_ok = lv[dl].inv_ok + sys;
     }
   }
+}
+
+size_t ebit_build_table_bytes(void) { return 2 * sizeof(BuildTable); }
+
+// Build both systems' coarse hierarchies: level 1 from the matrix-free fine
+// operators, the larger levels one launch each, the small ones (and the
+// dense inverse) in one work-group per system; FP32 copies written with
+// the FP64 values when wanted.
+hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, int want32, const void* dev_tabs,
+                                int ls, hipStream_t st) {
+  for (int sys = 0; sys < 2; ++sys)
+    for (int l = 1; l < ls && l < nlev; ++l) {
+      BuildOut o;
+      o.cd = lv[l].d;
+      o.diag = lv[l].diag64[sys];
+      o.mass = lv[l].mass64[sys];
+      o.d32 = want32 ? lv[l].diag32[sys] : nullptr;
+      for (int a = 0; a < 3; ++a) {
+        const bool on = a < o.cd.dim;
+        o.off[a] = on ? lv[l].off64[sys][a] : nullptr;
+        o.o32[a] = (on && want32) ? lv[l].off32[sys][a] : nullptr;
+      }
+      if (l == 1) {
+        hipLaunchKernelGGL(k_build_from_fine, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, op[sys], o);
+      } else {
+        CoarseOp<double> f;
+        f.d = lv[l - 1].d;
+        f.diag = lv[l - 1].diag64[sys];
+        f.mass = lv[l - 1].mass64[sys];
+        for (int a = 0; a < 3; ++a) f.off[a] = (a < f.d.dim) ? lv[l - 1].off64[sys][a] : nullptr;
+        hipLaunchKernelGGL(k_build_from_coarse, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, f, o);
+      }
+    }
+  hipLaunchKernelGGL(k_build_small, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
   return hipGetLastError();
 }
 
