@@ -235,6 +235,107 @@ __device__ inline void rb_fused_body(const R& rows, const T* __restrict__ xin, c
   }
 }
 
+// wrap index v along axis a; false if it lies outside a non-periodic domain
+__device__ inline bool wrap_axis(const Dims& d, int a, int& v) {
+  if (v >= 0 && v < d.n[a]) return true;
+  if (!d.per[a]) return false;
+  v = (v % d.n[a] + d.n[a]) % d.n[a];
+  return true;
+}
+
+// 2D explicit coarse level: one plane, with the iterate (tile + 2-cell
+// ring), the couplings off[0], off[1] (the same window: a ring cell's lower
+// couplings sit one cell further out) and diag, b (tile + 1-cell ring) all
+// staged in LDS in one load phase, so the launch waits on global memory
+// once.  Positions outside the domain stage zero couplings and iterate.
+#define RB_QX (RB_TX + 2)
+#define RB_QY (RB_TY + 2)
+#define RB_QPLANE (RB_QX * RB_QY)
+#define RB_SBUF (3 * RB_PLANE + 2 * RB_QPLANE)
+
+template <typename T>
+__device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restrict__ b, const T* __restrict__ xin,
+                                        const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
+                                        T* sb) {
+  const Dims& d = op.d;
+  T* xs = sb;
+  T* o0 = sb + RB_PLANE;
+  T* o1 = sb + 2 * RB_PLANE;
+  T* dg = sb + 3 * RB_PLANE;
+  T* bb = dg + RB_QPLANE;
+  const int tx0 = bx * RB_TX, ty0 = by * RB_TY;
+  constexpr int NP = (RB_PLANE + RB_THREADS - 1) / RB_THREADS;
+  constexpr int NQ = (RB_QPLANE + RB_THREADS - 1) / RB_THREADS;
+  T vx[NP], v0[NP], v1[NP], vd[NQ], vb[NQ];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    vx[e] = v0[e] = v1[e] = (T)0;
+    int i = tx0 + t % RB_PX - 2, j = ty0 + t / RB_PX - 2;
+    if (t < RB_PLANE && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      const long long c = i + (long long)d.n[0] * j;
+      if (xin) vx[e] = xin[c];
+      if (xc) vx[e] += xc[(i >> 1) + (long long)cd.n[0] * (j >> 1)];
+      v0[e] = op.off[0][c];
+      v1[e] = op.off[1][c];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    vd[e] = (T)1;
+    vb[e] = (T)0;
+    int i = tx0 + t % RB_QX - 1, j = ty0 + t / RB_QX - 1;
+    if (t < RB_QPLANE && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      const long long c = i + (long long)d.n[0] * j;
+      vd[e] = op.diag[c];
+      vb[e] = b[c];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < RB_PLANE) {
+      xs[t] = vx[e];
+      o0[t] = v0[e];
+      o1[t] = v1[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < RB_QPLANE) {
+      dg[t] = vd[e];
+      bb[t] = vb[e];
+    }
+  }
+  __syncthreads();
+  // red on the tile + 1 ring, then black on the tile (cells outside a
+  // non-periodic domain are not updated)
+  for (int ph = 0; ph < 2; ++ph) {
+    const int ring = ph == 0 ? 1 : 0, color = ph;
+    const int hx = (RB_TX + 2 * ring) / 2, wy = RB_TY + 2 * ring;
+    for (int t = threadIdx.x; t < hx * wy; t += RB_THREADS) {
+      const int ly = t / hx - ring;
+      const int j = ty0 + ly;
+      const int lx = 2 * (t % hx) - ring + ((color + tx0 - ring + j) & 1);
+      int iw = tx0 + lx, jw = j;
+      if (!wrap_axis(d, 0, iw) || !wrap_axis(d, 1, jw)) continue;
+      const int q = (ly + 2) * RB_PX + (lx + 2);
+      const int qc = (ly + 1) * RB_QX + (lx + 1);
+      const T sum = bb[qc] - o0[q - 1] * xs[q - 1] - o0[q] * xs[q + 1] -
+                    (o1[q - RB_PX] * xs[q - RB_PX] + o1[q] * xs[q + RB_PX]);
+      xs[q] = sum / dg[qc];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < RB_TX * RB_TY; t += RB_THREADS) {
+    const int lx = t % RB_TX, ly = t / RB_TX;
+    const int i = tx0 + lx, j = ty0 + ly;
+    if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + 2) * RB_PX + (lx + 2)];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fine-level red-black sweep, software pipelined along z.
 //
@@ -252,14 +353,6 @@ struct FineTile {
   static constexpr int NX = (PL + RB_THREADS - 1) / RB_THREADS;
   static constexpr int NQ = (QL + RB_THREADS - 1) / RB_THREADS;
 };
-
-// wrap index v along axis a; false if it lies outside a non-periodic domain
-__device__ inline bool wrap_axis(const Dims& d, int a, int& v) {
-  if (v >= 0 && v < d.n[a]) return true;
-  if (!d.per[a]) return false;
-  v = (v % d.n[a] + d.n[a]) % d.n[a];
-  return true;
-}
 
 template <typename T, int TX, int TY>
 struct FineGeom;
@@ -1465,7 +1558,7 @@ template <typename T>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* __restrict__ cs,
                                                            const CaseCtl* __restrict__ ctl, WorkList wl, int l,
                                                            int in_sel, int out_sel, int add_xc) {
-  __shared__ T buf[4][RB_PLANE];
+  __shared__ T buf[RB_SBUF];
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   const SolveCase<T>& C = cs[c];
@@ -1476,7 +1569,11 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
   const Dims cd = C.lev[l + 1].d;
   T* xout = C.lx[l][out_sel];
   if (!ctl[c].active) return;
-  rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lb % gx, (lb / gx) % gy, lb / (gx * gy), buf);
+  if (rows.op.d.dim == 2)
+    rb_coarse2d_body<T>(rows.op, rows.b, xin, xc, cd, xout, lb % gx, (lb / gx) % gy, buf);
+  else
+    rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lb % gx, (lb / gx) % gy, lb / (gx * gy),
+                                    reinterpret_cast<T(*)[RB_PLANE]>(buf));
 }
 
 // Residual of the 2^d children of every coarse cell of level 1, summed
