@@ -243,99 +243,6 @@ __device__ inline bool wrap_axis(const Dims& d, int a, int& v) {
   return true;
 }
 
-// 2D explicit coarse level: one plane, with the iterate (tile + 2-cell
-// ring), the couplings off[0], off[1] (the same window: a ring cell's lower
-// couplings sit one cell further out) and diag, b (tile + 1-cell ring) all
-// staged in LDS in one load phase, so the launch waits on global memory
-// once.  Positions outside the domain stage zero couplings and iterate.
-#define RB_QX (RB_TX + 2)
-#define RB_QY (RB_TY + 2)
-#define RB_QPLANE (RB_QX * RB_QY)
-#define RB_SBUF (3 * RB_PLANE + 2 * RB_QPLANE)
-
-template <typename T>
-__device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restrict__ b, const T* __restrict__ xin,
-                                        const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
-                                        T* sb) {
-  const Dims& d = op.d;
-  T* xs = sb;
-  T* o0 = sb + RB_PLANE;
-  T* o1 = sb + 2 * RB_PLANE;
-  T* dg = sb + 3 * RB_PLANE;
-  T* bb = dg + RB_QPLANE;
-  const int tx0 = bx * RB_TX, ty0 = by * RB_TY;
-  constexpr int NP = (RB_PLANE + RB_THREADS - 1) / RB_THREADS;
-  constexpr int NQ = (RB_QPLANE + RB_THREADS - 1) / RB_THREADS;
-  T vx[NP], v0[NP], v1[NP], vd[NQ], vb[NQ];
-#pragma unroll
-  for (int e = 0; e < NP; ++e) {
-    const int t = threadIdx.x + e * RB_THREADS;
-    vx[e] = v0[e] = v1[e] = (T)0;
-    int i = tx0 + t % RB_PX - 2, j = ty0 + t / RB_PX - 2;
-    if (t < RB_PLANE && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
-      const long long c = i + (long long)d.n[0] * j;
-      if (xin) vx[e] = xin[c];
-      if (xc) vx[e] += xc[(i >> 1) + (long long)cd.n[0] * (j >> 1)];
-      v0[e] = op.off[0][c];
-      v1[e] = op.off[1][c];
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < NQ; ++e) {
-    const int t = threadIdx.x + e * RB_THREADS;
-    vd[e] = (T)1;
-    vb[e] = (T)0;
-    int i = tx0 + t % RB_QX - 1, j = ty0 + t / RB_QX - 1;
-    if (t < RB_QPLANE && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
-      const long long c = i + (long long)d.n[0] * j;
-      vd[e] = op.diag[c];
-      vb[e] = b[c];
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < NP; ++e) {
-    const int t = threadIdx.x + e * RB_THREADS;
-    if (t < RB_PLANE) {
-      xs[t] = vx[e];
-      o0[t] = v0[e];
-      o1[t] = v1[e];
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < NQ; ++e) {
-    const int t = threadIdx.x + e * RB_THREADS;
-    if (t < RB_QPLANE) {
-      dg[t] = vd[e];
-      bb[t] = vb[e];
-    }
-  }
-  __syncthreads();
-  // red on the tile + 1 ring, then black on the tile (cells outside a
-  // non-periodic domain are not updated)
-  for (int ph = 0; ph < 2; ++ph) {
-    const int ring = ph == 0 ? 1 : 0, color = ph;
-    const int hx = (RB_TX + 2 * ring) / 2, wy = RB_TY + 2 * ring;
-    for (int t = threadIdx.x; t < hx * wy; t += RB_THREADS) {
-      const int ly = t / hx - ring;
-      const int j = ty0 + ly;
-      const int lx = 2 * (t % hx) - ring + ((color + tx0 - ring + j) & 1);
-      int iw = tx0 + lx, jw = j;
-      if (!wrap_axis(d, 0, iw) || !wrap_axis(d, 1, jw)) continue;
-      const int q = (ly + 2) * RB_PX + (lx + 2);
-      const int qc = (ly + 1) * RB_QX + (lx + 1);
-      const T sum = bb[qc] - o0[q - 1] * xs[q - 1] - o0[q] * xs[q + 1] -
-                    (o1[q - RB_PX] * xs[q - RB_PX] + o1[q] * xs[q + RB_PX]);
-      xs[q] = sum / dg[qc];
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < RB_TX * RB_TY; t += RB_THREADS) {
-    const int lx = t % RB_TX, ly = t / RB_TX;
-    const int i = tx0 + lx, j = ty0 + ly;
-    if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + 2) * RB_PX + (lx + 2)];
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Fine-level red-black sweep, software pipelined along z.
 //
@@ -657,6 +564,196 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
 }
 #undef FINE_RED
 #undef FINE_BLACK
+
+// ---------------------------------------------------------------------------
+// 2D sweeps, NSW full red-black sweeps per launch.  A work-group stages its
+// tile with a ring of 2 NSW cells (iterate) and 2 NSW - 1 cells (the other
+// arrays), then runs 2 NSW colour phases on windows that shrink by one
+// cell each: the ring cells are recomputed from the same old values by
+// every tile that needs them, so the tile ends exactly as after NSW
+// whole-grid sweeps.  One launch and one global-memory wait instead of NSW.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int NSW>
+struct Win2 {
+  static constexpr int H = 2 * NSW, QR = 2 * NSW - 1;
+  static constexpr int PX = TX + 2 * H, PY = TY + 2 * H, PL = PX * PY;
+  static constexpr int QX = TX + 2 * QR, QY = TY + 2 * QR, QL = QX * QY;
+};
+
+// one colour phase on the window [-ring, T+ring); cells outside a
+// non-periodic domain are not updated; upd(q, qq, iw, jw) does the cell
+template <int TX, int TY, int NSW, int RING, typename U>
+__device__ inline void phase2(const Dims& d, int tx0, int ty0, int color, const U& upd) {
+  using W = Win2<TX, TY, NSW>;
+  constexpr int HX = (TX + 2 * RING) / 2, WY = TY + 2 * RING;
+  for (int t = threadIdx.x; t < HX * WY; t += RB_THREADS) {
+    const int ly = t / HX - RING;
+    const int j = ty0 + ly;
+    const int lx = 2 * (t % HX) - RING + ((color + tx0 - RING + j) & 1);
+    int iw = tx0 + lx, jw = j;
+    if (!wrap_axis(d, 0, iw) || !wrap_axis(d, 1, jw)) continue;
+    upd((ly + W::H) * W::PX + (lx + W::H), (ly + W::QR) * W::QX + (lx + W::QR), iw, jw);
+  }
+}
+
+template <int TX, int TY, int NSW, int P, typename U>
+__device__ inline void phases2(const Dims& d, int tx0, int ty0, const U& upd) {
+  if constexpr (P < 2 * NSW) {
+    phase2<TX, TY, NSW, 2 * NSW - 1 - P>(d, tx0, ty0, P & 1, upd);
+    __syncthreads();
+    phases2<TX, TY, NSW, P + 1>(d, tx0, ty0, upd);
+  }
+}
+
+// fine level, 2D
+template <typename T, int TX, int TY, int NSW>
+__device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
+                                      const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
+                                      T* xs, double* rs, uint8_t* fs) {
+  using W = Win2<TX, TY, NSW>;
+  const Dims& d = op.d;
+  const RegularRow<T> rr = regular_row<T>(op);
+  const int tx0 = bx * TX, ty0 = by * TY;
+  constexpr int NP = (W::PL + RB_THREADS - 1) / RB_THREADS, NQ = (W::QL + RB_THREADS - 1) / RB_THREADS;
+  T vx[NP];
+  double vr[NQ];
+  uint8_t vf[NQ];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    vx[e] = (T)0;
+    int i = tx0 + t % W::PX - W::H, j = ty0 + t / W::PX - W::H;
+    if (t < W::PL && (xin || xc) && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      if (xin) vx[e] = xin[i + (long long)d.n[0] * j];
+      if (xc) vx[e] += xc[(i >> 1) + (long long)cd.n[0] * (j >> 1)];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    vr[e] = 0.0;
+    vf[e] = 0;
+    int i = tx0 + t % W::QX - W::QR, j = ty0 + t / W::QX - W::QR;
+    if (t < W::QL && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      const long long c = i + (long long)d.n[0] * j;
+      vr[e] = rhs[c];
+      vf[e] = op.flags[c];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < W::PL) xs[t] = vx[e];
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < W::QL) {
+      rs[t] = vr[e];
+      fs[t] = vf[e];
+    }
+  }
+  __syncthreads();
+  auto upd = [&](int q, int qq, int iw, int jw) {
+    const uint8_t f = fs[qq];
+    const bool wall = (!d.per[0] && (iw == 0 || iw == d.n[0] - 1)) || (!d.per[1] && (jw == 0 || jw == d.n[1] - 1));
+    if (!(f & F_CUT) && !wall) {
+      const bool liq = (f & F_LIQ) != 0;
+      const T xn = (xs[q - 1] + xs[q + 1]) + (xs[q - W::PX] + xs[q + W::PX]);
+      xs[q] = ((T)rs[qq] + (liq ? rr.w1 : rr.w0) * xn) * (liq ? rr.inv1 : rr.inv0);
+    } else {
+      T diag, off[6], mass, rb = 0;
+      fine_row<T>(op, iw, jw, 0, f, diag, off, mass, rb);
+      T sum = (T)rs[qq] - off[0] * xs[q - 1] - off[1] * xs[q + 1];
+      sum -= off[2] * xs[q - W::PX] + off[3] * xs[q + W::PX];
+      xs[q] = sum / diag;
+    }
+  };
+  phases2<TX, TY, NSW, 0>(d, tx0, ty0, upd);
+  for (int t = threadIdx.x; t < TX * TY; t += RB_THREADS) {
+    const int lx = t % TX, ly = t / TX;
+    const int i = tx0 + lx, j = ty0 + ly;
+    if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + W::H) * W::PX + (lx + W::H)];
+  }
+}
+
+// explicit coarse level, 2D (couplings staged on the iterate's window: a
+// ring cell's lower couplings sit one cell further out)
+template <typename T, int NSW>
+__device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restrict__ b, const T* __restrict__ xin,
+                                        const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
+                                        T* sb) {
+  using W = Win2<RB_TX, RB_TY, NSW>;
+  const Dims& d = op.d;
+  T* xs = sb;
+  T* o0 = sb + W::PL;
+  T* o1 = sb + 2 * W::PL;
+  T* dg = sb + 3 * W::PL;
+  T* bb = dg + W::QL;
+  const int tx0 = bx * RB_TX, ty0 = by * RB_TY;
+  constexpr int NP = (W::PL + RB_THREADS - 1) / RB_THREADS, NQ = (W::QL + RB_THREADS - 1) / RB_THREADS;
+  T vx[NP], v0[NP], v1[NP], vd[NQ], vb[NQ];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    vx[e] = v0[e] = v1[e] = (T)0;
+    int i = tx0 + t % W::PX - W::H, j = ty0 + t / W::PX - W::H;
+    if (t < W::PL && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      const long long c = i + (long long)d.n[0] * j;
+      if (xin) vx[e] = xin[c];
+      if (xc) vx[e] += xc[(i >> 1) + (long long)cd.n[0] * (j >> 1)];
+      v0[e] = op.off[0][c];
+      v1[e] = op.off[1][c];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    vd[e] = (T)1;
+    vb[e] = (T)0;
+    int i = tx0 + t % W::QX - W::QR, j = ty0 + t / W::QX - W::QR;
+    if (t < W::QL && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+      const long long c = i + (long long)d.n[0] * j;
+      vd[e] = op.diag[c];
+      vb[e] = b[c];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < W::PL) {
+      xs[t] = vx[e];
+      o0[t] = v0[e];
+      o1[t] = v1[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < W::QL) {
+      dg[t] = vd[e];
+      bb[t] = vb[e];
+    }
+  }
+  __syncthreads();
+  auto upd = [&](int q, int qc, int, int) {
+    const T sum = bb[qc] - o0[q - 1] * xs[q - 1] - o0[q] * xs[q + 1] -
+                  (o1[q - W::PX] * xs[q - W::PX] + o1[q] * xs[q + W::PX]);
+    xs[q] = sum / dg[qc];
+  };
+  phases2<RB_TX, RB_TY, NSW, 0>(d, tx0, ty0, upd);
+  for (int t = threadIdx.x; t < RB_TX * RB_TY; t += RB_THREADS) {
+    const int lx = t % RB_TX, ly = t / RB_TX;
+    const int i = tx0 + lx, j = ty0 + ly;
+    if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + W::H) * W::PX + (lx + W::H)];
+  }
+}
+
+// shared buffer of the coarse sweep kernel: the 3D z-march's four planes or
+// the 2D double sweep's staged windows
+constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 2>::QL) > 4 * RB_PLANE
+                            ? (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 2>::QL)
+                            : 4 * RB_PLANE;
 
 // ---------------------------------------------------------------------------
 // tail of the V-cycle: every level small enough to sit in LDS, in one
@@ -1529,11 +1626,13 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
   resid_init_body(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb);
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, int NSW>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __restrict__ cs,
                                                          const CaseCtl* __restrict__ ctl, WorkList wl, int in_sel,
                                                          int out_sel, int add_xc) {
   using FT = FineTile<TX, TY>;
+  using W = Win2<TX, TY, NSW>;
+  static_assert(W::PL <= 4 * FT::PL && W::QL <= 2 * FT::QL, "2D windows must fit the z-march buffers");
   __shared__ T xs[4][FT::PL];
   __shared__ double rs[2][FT::QL];
   __shared__ uint8_t fs[2][FT::QL];
@@ -1551,10 +1650,13 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   const int fgx = C.fgx, fgy = C.fgy, fzc = C.fzc;
   if (!ctl[c].active) return;
   const int bx = lb % fgx, by = (lb / fgx) % fgy, bz = lb / (fgx * fgy);
-  rb_fine_body<T, TX, TY>(op, r, zin, xc, cd, zout, fzc, bx, by, bz, xs, rs, fs);
+  if (op.d.dim == 2)
+    rb_fine2d_body<T, TX, TY, NSW>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0]);
+  else
+    rb_fine_body<T, TX, TY>(op, r, zin, xc, cd, zout, fzc, bx, by, bz, xs, rs, fs);
 }
 
-template <typename T>
+template <typename T, int NSW>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* __restrict__ cs,
                                                            const CaseCtl* __restrict__ ctl, WorkList wl, int l,
                                                            int in_sel, int out_sel, int add_xc) {
@@ -1570,7 +1672,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
   T* xout = C.lx[l][out_sel];
   if (!ctl[c].active) return;
   if (rows.op.d.dim == 2)
-    rb_coarse2d_body<T>(rows.op, rows.b, xin, xc, cd, xout, lb % gx, (lb / gx) % gy, buf);
+    rb_coarse2d_body<T, NSW>(rows.op, rows.b, xin, xc, cd, xout, lb % gx, (lb / gx) % gy, buf);
   else
     rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lb % gx, (lb / gx) % gy, lb / (gx * gy),
                                     reinterpret_cast<T(*)[RB_PLANE]>(buf));
@@ -2161,13 +2263,48 @@ HostList make_list(const std::vector<std::pair<int, int>>& ent, std::vector<int>
 }
 
 template <typename T>
-void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, hipStream_t st) {
+void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, int nsw, hipStream_t st) {
+  const CaseCtl* ctl = P.d_ctl;
   if (P.dim == 3)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs,
-                       (const CaseCtl*)P.d_ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.fine.w, in,
+                       out, add);
+  else if (nsw == 2)
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.fine.w,
+                       in, out, add);
   else
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs,
-                       (const CaseCtl*)P.d_ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.fine.w,
+                       in, out, add);
+}
+
+template <typename T>
+void launch_coarse(const PlanT<T>& P, const SolveCase<T>* cs, int l, int in, int out, int add, int nsw,
+                   hipStream_t st) {
+  const CaseCtl* ctl = P.d_ctl;
+  if (nsw == 2)
+    hipLaunchKernelGGL((kb_rb_coarse<T, 2>), dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl,
+                       P.coarse[l].w, l, in, out, add);
+  else
+    hipLaunchKernelGGL((kb_rb_coarse<T, 1>), dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl,
+                       P.coarse[l].w, l, in, out, add);
+}
+
+// Sweeps s0 .. s1 (1-based, of S = nu1 + nu2 on a level): sweep s writes
+// buffer 0 when S - s is even, else buffer 1; in 2D two sweeps go in one
+// launch where the run allows it.  launch(in, out, add, nsw).  Returns the
+// number of launches.
+template <typename L>
+int sweep_run(int s0, int s1, int S, int in, int add_first, bool pairs, const L& launch) {
+  auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
+  int n = 0;
+  for (int s = s0; s <= s1;) {
+    const int nsw = (pairs && s + 1 <= s1) ? 2 : 1;
+    const int last = s + nsw - 1;
+    launch(in, slot(last), s == s0 ? add_first : 0, nsw);
+    in = slot(last);
+    s += nsw;
+    ++n;
+  }
+  return n;
 }
 
 // One V(nu1, nu2) cycle on A z = r (zero initial guess) for every active
@@ -2177,52 +2314,40 @@ template <typename T>
 void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitProfiler* pf) {
   const int nu1 = P.o.nu1, S = P.o.nu1 + P.o.nu2;
   const CaseCtl* ctl = P.d_ctl;
+  const bool pairs = P.dim == 2;
   auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
-  int in = -1;
+  auto fine = [&](int in, int out, int add, int nsw) { launch_fine(P, cs, in, out, add, nsw, st); };
   {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, nu1);
-    for (int s = 1; s <= nu1; ++s) {
-      launch_fine(P, cs, in, slot(s), 0, st);
-      in = slot(s);
-    }
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, pairs ? (nu1 + 1) / 2 : nu1);
+    sweep_run(1, nu1, S, -1, 0, pairs, fine);
   }
   {
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
     hipLaunchKernelGGL(kb_fine_restrict<T>, dim3(P.frestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                       P.frestrict.w, in);
+                       P.frestrict.w, slot(nu1));
   }
   for (int l = 1; l < P.Lmax; ++l) {
-    in = -1;
-    for (int s = 1; s <= nu1; ++s) {
-      ProfScope ps(pf, EBIT_KC_COARSE, st);
-      hipLaunchKernelGGL(kb_rb_coarse<T>, dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.coarse[l].w,
-                         l, in, slot(s), 0);
-      in = slot(s);
+    auto coarse = [&](int in, int out, int add, int nsw) { launch_coarse(P, cs, l, in, out, add, nsw, st); };
+    {
+      ProfScope ps(pf, EBIT_KC_COARSE, st, pairs ? (nu1 + 1) / 2 : nu1);
+      sweep_run(1, nu1, S, -1, 0, pairs, coarse);
     }
     ProfScope ps(pf, EBIT_KC_COARSE, st);
     hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                       P.crestrict[l].w, l, in);
+                       P.crestrict[l].w, l, slot(nu1));
   }
   {
     ProfScope ps(pf, EBIT_KC_TAIL, st);
     hipLaunchKernelGGL(kb_tail<T>, dim3(P.n), dim3(EBIT_TAIL_THREADS), P.tail_bytes, st, cs, ctl);
   }
   for (int l = P.Lmax - 1; l >= 1; --l) {
-    in = slot(nu1);
-    for (int s = nu1 + 1; s <= S; ++s) {
-      ProfScope ps(pf, EBIT_KC_COARSE, st);
-      hipLaunchKernelGGL(kb_rb_coarse<T>, dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.coarse[l].w,
-                         l, in, slot(s), s == nu1 + 1 ? 1 : 0);
-      in = slot(s);
-    }
+    auto coarse = [&](int in, int out, int add, int nsw) { launch_coarse(P, cs, l, in, out, add, nsw, st); };
+    ProfScope ps(pf, EBIT_KC_COARSE, st, pairs ? (S - nu1 + 1) / 2 : S - nu1);
+    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, coarse);
   }
-  in = slot(nu1);
   {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, S - nu1);
-    for (int s = nu1 + 1; s <= S; ++s) {
-      launch_fine(P, cs, in, slot(s), s == nu1 + 1 ? 1 : 0, st);
-      in = slot(s);
-    }
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, pairs ? (S - nu1 + 1) / 2 : S - nu1);
+    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, fine);
   }
 }
 
