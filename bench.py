@@ -54,7 +54,7 @@ def algorithmic_bytes_per_cell(kclass, precision, dim):
     on levels of varying size and have no per-fine-cell model (None)."""
     sx = 4 if precision == "mixed" else 8
     agg = 2 ** dim
-    if kclass == "fine_smooth":      # one full red-black sweep: read x, r (FP64), flags; write x
+    if kclass == "fine_smooth":      # per full red-black sweep: read x, r (FP64), flags; write x
         return sx + 8 + 1 + sx
     if kclass == "fine_restrict":    # read x, r, flags; write coarse b and clear coarse x
         return sx + 8 + 1 + 2 * sx / agg
@@ -253,11 +253,23 @@ def cpu_baseline(case, budget_s=15.0, max_steps=30):
             "sample": f"{steps} full steps of the same workload ({el:.1f} s, SciPy SuperLU direct solves, 1 thread)"}
 
 
+def sweeps_per_launch(dim, schedule):
+    """Red-black sweeps one fine smoothing launch performs: on 2D grids the
+    library runs the sweeps of a smoothing run in pairs (a run of nu sweeps
+    takes ceil(nu/2) launches), in 3D one per launch."""
+    if dim != 2:
+        return 1.0
+    nu1, nu2 = (schedule or {}).get("nu1", 2), (schedule or {}).get("nu2", 2)
+    return (nu1 + nu2) / ((nu1 + 1) // 2 + (nu2 + 1) // 2)
+
+
 def roofline(case, precision, steps, tune=True):
     """Profiled timed pass: average launch duration of each kernel class,
     measured with hipEvents on the library's stream; the class with the most
-    device time is the dominant kernel."""
-    _, _, kern, _ = run_gpu(case, precision, steps, 1, profile=True, tune=tune)
+    device time is the dominant kernel.  Algorithmic bytes per launch = the
+    per-sweep-per-cell figure x the sweeps x cells one launch processes."""
+    _, _, kern, sched = run_gpu(case, precision, steps, 1, profile=True, tune=tune)
+    spl = sweeps_per_launch(case.dim, sched)
     rows = {}
     for name, (n, ms) in kern.items():
         if n == 0:
@@ -266,9 +278,12 @@ def roofline(case, precision, steps, tune=True):
         avg_s = ms * 1e-3 / n
         rows[name] = {"launches": n, "total_ms": ms, "avg_us": avg_s * 1e6}
         if bpc is not None:
-            bytes_launch = bpc * case.ncells
+            units = spl if name == "fine_smooth" else 1.0
+            bytes_launch = bpc * case.ncells * units
             rows[name]["algorithmic_bytes_per_launch"] = bytes_launch
             rows[name]["achieved_GBps"] = bytes_launch / avg_s / 1e9
+            if name == "fine_smooth":
+                rows[name]["sweeps_per_launch"] = spl
     modelled = [k for k in rows if "achieved_GBps" in rows[k]]
     dom = max(modelled, key=lambda k: rows[k]["total_ms"])
     r = rows[dom]
@@ -283,6 +298,8 @@ def roofline(case, precision, steps, tune=True):
     ro = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS,
           "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
           "avg_launch_us": r["avg_us"], "algorithmic_bytes_per_launch": r["algorithmic_bytes_per_launch"]}
+    if "sweeps_per_launch" in r:
+        ro["sweeps_per_launch"] = r["sweeps_per_launch"]
     return ro, rows
 
 

@@ -243,16 +243,33 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
     lv[l].x32b = cv.take<float>(n);
     lv[l].b32 = cv.take<float>(n);
   }
-  for (int l = 1; l < nlev; ++l)
-    if (lv[l].d.N <= EBIT_DENSE_MAX) {
-      const long long n2 = lv[l].d.N * lv[l].d.N;
-      for (int s = 0; s < 2; ++s) {
-        lv[l].inv64[s] = cv.take<double>(n2);
-        lv[l].inv32[s] = cv.take<float>(n2);
+  // tail images, per system in FP32 and FP64: the coefficient blocks of the
+  // levels of at most EBIT_TAIL_IMG_CELLS cells, then the inverse of the
+  // first level of at most EBIT_DENSE_MAX cells
+  int img0 = nlev, dl = -1;
+  for (int l = nlev - 1; l >= 1 && lv[l].d.N <= EBIT_TAIL_IMG_CELLS; --l) img0 = l;
+  for (int l = 1; l < nlev && dl < 0; ++l)
+    if (lv[l].d.N <= EBIT_DENSE_MAX) dl = l;
+  if (img0 < nlev) {
+    long long tot = 0;
+    for (int l = img0; l < nlev; ++l) tot += ebit::tail_img_elems(lv[l].d);
+    const long long ninv = dl >= 0 ? ebit::tail_pad(lv[dl].d.N * lv[dl].d.N) : 0;
+    for (int s = 0; s < 2; ++s) {
+      float* i32 = cv.take<float>(tot + ninv);
+      double* i64 = cv.take<double>(tot + ninv);
+      long long off = 0;
+      for (int l = img0; l < nlev; ++l) {
+        lv[l].img32[s] = i32 ? i32 + off : nullptr;
+        lv[l].img64[s] = i64 ? i64 + off : nullptr;
+        off += ebit::tail_img_elems(lv[l].d);
       }
-      lv[l].inv_ok = cv.take<int>(2);
-      break;
+      if (dl >= 0) {
+        lv[dl].inv32[s] = i32 ? i32 + off : nullptr;
+        lv[dl].inv64[s] = i64 ? i64 + off : nullptr;
+      }
     }
+    if (dl >= 0) lv[dl].inv_ok = cv.take<int>(2);
+  }
   const size_t plan_bytes = ebit_plan_device_bytes(1, o ? o->precision : EBIT_FP64);
   char* plan_mem = cv.take<char>(plan_bytes);
   char* build_tabs = cv.take<char>(ebit_build_table_bytes());

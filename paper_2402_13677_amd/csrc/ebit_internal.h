@@ -41,6 +41,15 @@ struct Dims {
   long long N;
 };
 
+// Tail image: the coarse levels of at most EBIT_TAIL_IMG_CELLS cells keep,
+// per system, their coefficients in one contiguous array, level after level
+// from fine to coarse (diag, 1/diag, off[0 .. dim-1], each padded to a
+// multiple of four elements), followed by the dense coarsest inverse; the
+// tail kernel copies a suffix of it straight into LDS.
+#define EBIT_TAIL_IMG_CELLS 8192
+__host__ __device__ inline long long tail_pad(long long n) { return (n + 3) & ~3LL; }
+__host__ __device__ inline long long tail_img_elems(const Dims& d) { return (2 + d.dim) * tail_pad(d.N); }
+
 __host__ __device__ inline long long cell_index(const Dims& d, int i, int j, int k) {
   return (long long)i + (long long)d.n[0] * ((long long)j + (long long)d.n[1] * k);
 }
@@ -232,6 +241,10 @@ struct EbitLevelHost {
   double* inv64[2];
   float* inv32[2];
   int* inv_ok;
+  // this level's block of its system's tail image (FP32 and FP64; null
+  // above EBIT_TAIL_IMG_CELLS cells)
+  float* img32[2];
+  double* img64[2];
 };
 
 #define EBIT_DENSE_MAX 64

@@ -758,41 +758,49 @@ constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 
 // ---------------------------------------------------------------------------
 // tail of the V-cycle: every level small enough to sit in LDS, in one
 // work-group (no launch per smoothing sweep on the coarse levels).  The
-// coefficients of all tail levels are staged into LDS once, at the start.
+// hierarchy build leaves the coefficients of these levels (diag, 1/diag,
+// couplings) and the dense coarsest inverse in one contiguous image per
+// system, laid out as the kernel's LDS: the kernel starts with a straight
+// 16-byte copy of the suffix it needs.
 // ---------------------------------------------------------------------------
 #define EBIT_TAIL_MAX 16
 #define EBIT_TAIL_THREADS 1024
-#define TAIL_BATCH 8
+#define TAIL_COPY_BATCH 8
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// LDS block of one tail level: x, b, diag, 1/diag, off[0 .. dim-1], N
-// elements each.
+// One tail level in LDS: its coefficients (diag, 1/diag, off[0 .. dim-1],
+// np elements each) at cb, inside the copied image; its iterate x at xb and
+// right-hand side b at xb + np.
 struct TailLevel {
   Dims d;
-  int base;  // element offset of x
+  int np;  // padded cell count: the stride of the level's arrays
+  int cb;
+  int xb;
 };
-
-__host__ __device__ inline long long tail_level_elems(const Dims& d) { return (4 + d.dim) * d.N; }
 
 template <typename T>
 struct TailArgs {
   int nl;  // levels in the tail; the last one is the coarsest
   int nu1, nu2;
   TailLevel L[EBIT_TAIL_MAX];
-  const T* diag[EBIT_TAIL_MAX];
-  const T* off[EBIT_TAIL_MAX][3];
-  const T* bg;  // right-hand side of the top tail level
-  T* xg;        // its correction (output)
+  const T* img;        // coefficient image from the top tail level on (16-byte aligned)
+  int cvec;            // its length in 16-byte units
   int dl;              // tail level solved exactly by its inverse, or -1
-  const T* inv;        // that inverse (transposed)
+  int inv;             // element offset of that inverse (transposed) in LDS
   const int* inv_ok;   // 1 if the inversion succeeded
+  const T* bg;         // right-hand side of the top tail level
+  T* xg;               // its correction (output)
 };
 
 // Register copy of one tail level's shape (read once per level, so the
-// loops below do not go back to the case table), with float reciprocals of
-// the row and plane sizes for division-free index decoding.
+// loops below do not go back to the case table), with float reciprocals
+// for division-free index decoding.  A colour of the red-black ordering is
+// numbered row by row: hw slots per grid row, slot m at i = 2 m + parity
+// (the last slot of a row of odd length may fall off the row).
 struct TLev {
-  int n0, n1, n2, N, base, dim, p0, p1, p2;
-  float r0, r1, r01;  // 1/n0, 1/n1, 1/(n0 n1)
+  int n0, n1, n2, N, np, cb, xb, p0, p1, p2;
+  int hw, hc;         // colour slots per row and per level
+  float r0, r1, r01, rhw;  // 1/n0, 1/n1, 1/(n0 n1), 1/hw
 };
 
 __device__ inline TLev tlev(const TailLevel& L) {
@@ -801,14 +809,18 @@ __device__ inline TLev tlev(const TailLevel& L) {
   t.n1 = L.d.n[1];
   t.n2 = L.d.n[2];
   t.N = (int)L.d.N;
-  t.base = L.base;
-  t.dim = L.d.dim;
+  t.np = L.np;
+  t.cb = L.cb;
+  t.xb = L.xb;
   t.p0 = L.d.per[0];
   t.p1 = L.d.per[1];
   t.p2 = L.d.per[2];
+  t.hw = (t.n0 + 1) >> 1;
+  t.hc = t.hw * t.n1 * t.n2;
   t.r0 = 1.0f / (float)t.n0;
   t.r1 = 1.0f / (float)t.n1;
   t.r01 = 1.0f / (float)(t.n0 * t.n1);
+  t.rhw = 1.0f / (float)t.hw;
   return t;
 }
 
@@ -821,130 +833,199 @@ __device__ inline int qdiv(int c, int n, float r) {
   return q;
 }
 
+template <int DIM>
 __device__ inline void cell_of(const TLev& d, int c, int& i, int& j, int& k) {
-  const int s2 = d.n0 * d.n1;
-  k = qdiv(c, s2, d.r01);
-  const int r = c - k * s2;
-  j = qdiv(r, d.n0, d.r0);
-  i = r - j * d.n0;
+  if (DIM == 3) {
+    const int s2 = d.n0 * d.n1;
+    k = qdiv(c, s2, d.r01);
+    c -= k * s2;
+  } else {
+    k = 0;
+  }
+  j = qdiv(c, d.n0, d.r0);
+  i = c - j * d.n0;
 }
 
-// LDS block of a tail level: x, b, diag, 1/diag, couplings off[0 .. dim-1]
-#define TAIL_X(L, sm) ((sm) + (L).base)
-#define TAIL_B(L, sm) ((sm) + (L).base + (L).N)
-#define TAIL_D(L, sm) ((sm) + (L).base + 2 * (L).N)
-#define TAIL_DI(L, sm) ((sm) + (L).base + 3 * (L).N)
-#define TAIL_O(L, sm, a) ((sm) + (L).base + (4 + (a)) * (L).N)
+__device__ inline float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Sum over the neighbours of cell q = (i, j, k) of coupling x neighbour;
-// the same neighbour set as neighbour() (periodic wrap, none across a
-// wall).  With xc non-null, neighbour values are read as x + xc[parent]
-// (the prolongated coarse correction, C the coarse level).
-template <typename T>
-__device__ inline T tail_offsum(const T* sm, const TLev& d, int i, int j, int k, int q, const T* xc = nullptr,
-                                const TLev* C = nullptr) {
-  const T* x = TAIL_X(d, sm);
-  const int N = d.N;
-  const int n0 = d.n0, n1 = d.n1, n2 = d.n2;
-  const int s1 = n0, s2 = n0 * n1;
-  auto xv = [&](int m, int mi, int mj, int mk) {
-    T v = x[m];
-    if (xc) v += xc[(mi >> 1) + C->n0 * ((mj >> 1) + C->n1 * (mk >> 1))];
-    return v;
-  };
+// Sum over the neighbours of cell q = (i, j, k) of coupling x neighbour
+// value, over the neighbour set of neighbour() (periodic wrap, none across
+// a wall), in the order +x, -x, +y, -y, +z, -z.  Every load is issued
+// unconditionally, at a wrapped index (a missing neighbour's term is then
+// dropped by a select), so that all of them are in flight together.  With
+// XC the neighbour values are read as x + xc[parent]: the prolongated
+// correction of the coarse level C.
+template <typename T, int DIM, bool XC>
+__device__ inline T tail_nsum(const T* sm, const TLev& d, int i, int j, int k, int q, const TLev& C) {
+  const T* x = sm + d.xb;
+  const T* xc = sm + C.xb;
+  const int s2 = d.n0 * d.n1;
   T s = 0;
   {
-    const T* o = TAIL_O(d, sm, 0);
-    if (i + 1 < n0) s += o[q] * xv(q + 1, i + 1, j, k);
-    else if (d.p0) s += o[q] * xv(q + 1 - n0, 0, j, k);
-    if (i > 0) s += o[q - 1] * xv(q - 1, i - 1, j, k);
-    else if (d.p0) s += o[q + n0 - 1] * xv(q + n0 - 1, n0 - 1, j, k);
+    const T* o = sm + d.cb + 2 * d.np;
+    const bool e = i + 1 < d.n0, w = i > 0;
+    const int qe = e ? q + 1 : q + 1 - d.n0;
+    const int qw = w ? q - 1 : q - 1 + d.n0;
+    T ve = x[qe], vw = x[qw];
+    if (XC) {
+      const int cjk = C.n0 * ((j >> 1) + C.n1 * (k >> 1));
+      ve += xc[(e ? (i + 1) >> 1 : 0) + cjk];
+      vw += xc[(w ? (i - 1) >> 1 : (d.n0 - 1) >> 1) + cjk];
+    }
+    const T oe = o[q], ow = o[qw];
+    s = (e || d.p0) ? tfma(oe, ve, s) : s;
+    s = (w || d.p0) ? tfma(ow, vw, s) : s;
   }
-  if (d.dim >= 2) {
-    const T* o = TAIL_O(d, sm, 1);
-    if (j + 1 < n1) s += o[q] * xv(q + s1, i, j + 1, k);
-    else if (d.p1) s += o[q] * xv(q + s1 - s2, i, 0, k);
-    if (j > 0) s += o[q - s1] * xv(q - s1, i, j - 1, k);
-    else if (d.p1) s += o[q + s2 - s1] * xv(q + s2 - s1, i, n1 - 1, k);
+  {
+    const T* o = sm + d.cb + 3 * d.np;
+    const bool e = j + 1 < d.n1, w = j > 0;
+    const int qe = e ? q + d.n0 : q + d.n0 - s2;
+    const int qw = w ? q - d.n0 : q - d.n0 + s2;
+    T ve = x[qe], vw = x[qw];
+    if (XC) {
+      const int ci = i >> 1, ck = C.n1 * (k >> 1);
+      ve += xc[ci + C.n0 * ((e ? (j + 1) >> 1 : 0) + ck)];
+      vw += xc[ci + C.n0 * ((w ? (j - 1) >> 1 : (d.n1 - 1) >> 1) + ck)];
+    }
+    const T oe = o[q], ow = o[qw];
+    s = (e || d.p1) ? tfma(oe, ve, s) : s;
+    s = (w || d.p1) ? tfma(ow, vw, s) : s;
   }
-  if (d.dim == 3) {
-    const T* o = TAIL_O(d, sm, 2);
-    if (k + 1 < n2) s += o[q] * xv(q + s2, i, j, k + 1);
-    else if (d.p2) s += o[q] * xv(q + s2 - N, i, j, 0);
-    if (k > 0) s += o[q - s2] * xv(q - s2, i, j, k - 1);
-    else if (d.p2) s += o[q + N - s2] * xv(q + N - s2, i, j, n2 - 1);
+  if (DIM == 3) {
+    const T* o = sm + d.cb + 4 * d.np;
+    const bool e = k + 1 < d.n2, w = k > 0;
+    const int qe = e ? q + s2 : q + s2 - d.N;
+    const int qw = w ? q - s2 : q - s2 + d.N;
+    T ve = x[qe], vw = x[qw];
+    if (XC) {
+      const int cij = (i >> 1) + C.n0 * (j >> 1);
+      ve += xc[cij + C.n0 * C.n1 * (e ? (k + 1) >> 1 : 0)];
+      vw += xc[cij + C.n0 * C.n1 * (w ? (k - 1) >> 1 : (d.n2 - 1) >> 1)];
+    }
+    const T oe = o[q], ow = o[qw];
+    s = (e || d.p2) ? tfma(oe, ve, s) : s;
+    s = (w || d.p2) ? tfma(ow, vw, s) : s;
   }
   return s;
 }
 
-// One colour of a Gauss-Seidel sweep on a tail level by the work-group.
-// Only as many waves as half the level needs take part (the others go
-// straight to the caller's barrier); threads form rows of 32, the lane
-// taking cells i = 2 lane + parity, + 64, ... of its grid rows.  With xc,
-// the neighbours (all of the other colour) are read with the coarse
-// correction added: the first post-smoothing sweep, which makes a separate
-// prolongation pass unnecessary (a Gauss-Seidel update does not read the
-// cell's own old value, and the next sweep overwrites the other colour).
-template <typename T>
-__device__ inline void tail_sweep(T* sm, const TLev& d, int color, const T* xc = nullptr, const TLev* C = nullptr) {
-  int act = ((d.N + 1) / 2 + 63) / 64 * 64;
-  if (act > EBIT_TAIL_THREADS) act = EBIT_TAIL_THREADS;
-  if ((int)threadIdx.x >= act) return;
-  T* x = TAIL_X(d, sm);
-  const T* b = TAIL_B(d, sm);
-  const T* di = TAIL_DI(d, sm);
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5, rs = act >> 5;
-  const int rows = d.n1 * d.n2;
-  int j = 0, k = 0;
-  if (ty < rows) {
-    k = qdiv(ty, d.n1, d.r1);
-    j = ty - k * d.n1;
-  }
-  for (int row = ty; row < rows; row += rs) {
-    const int base = row * d.n0;
-    for (int i = 2 * tx + ((j + k + color) & 1); i < d.n0; i += 64) {
-      const int q = base + i;
-      x[q] = (b[q] - tail_offsum<T>(sm, d, i, j, k, q, xc, C)) * di[q];
+// Colour `color` of a red-black Gauss-Seidel sweep over level d by threads
+// t = 0 .. nth-1, K colour slots per thread at a time.  A thread computes
+// the new values of its K cells before storing any of them: within a
+// colour no update reads another, so no load waits for a store.  MODE 1:
+// the first sweep from a zero iterate (x = b / diag on this colour; the
+// neighbour sum vanishes, so the other colour need not be cleared);
+// MODE 2: neighbours read with the coarse correction added (the first
+// post-smoothing sweep: a Gauss-Seidel update does not read the cell's own
+// old value, and the next sweep recomputes the other colour, so no separate
+// prolongation pass is needed).
+template <typename T, int DIM, int K, int MODE>
+__device__ inline void tail_colour(T* sm, const TLev& d, int color, int t, int nth, const TLev& C) {
+  T* x = sm + d.xb;
+  const T* b = x + d.np;
+  const T* di = sm + d.cb + d.np;
+  for (int h0 = t; h0 < d.hc; h0 += K * nth) {
+    T nv[K];
+    int qs[K];
+    bool ok[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      int h = h0 + u * nth;
+      ok[u] = h < d.hc;
+      if (!ok[u]) h = h0;
+      const int row = qdiv(h, d.hw, d.rhw);
+      const int m = h - row * d.hw;
+      int j = row, k = 0;
+      if (DIM == 3) {
+        k = qdiv(row, d.n1, d.r1);
+        j = row - k * d.n1;
+      }
+      int i = 2 * m + ((j + k + color) & 1);
+      ok[u] = ok[u] && i < d.n0;
+      if (i >= d.n0) i = d.n0 - 1;
+      const int q = i + d.n0 * row;
+      qs[u] = q;
+      if (MODE == 1)
+        nv[u] = b[q] * di[q];
+      else
+        nv[u] = (b[q] - tail_nsum<T, DIM, MODE == 2>(sm, d, i, j, k, q, C)) * di[q];
     }
-    j += rs;
-    while (j >= d.n1) {
-      j -= d.n1;
-      ++k;
-    }
+#pragma unroll
+    for (int u = 0; u < K; ++u)
+      if (ok[u]) x[qs[u]] = nv[u];
   }
 }
 
-// Residual of the 2^d children of each cell of C, summed into C's
-// right-hand side; C's iterate cleared.  Thread t (of nth) takes coarse
-// cells t, t + nth, ...
-template <typename T>
+// (four cells at a time only for FP32 in 2D: more would not fit the
+// registers of a 1024-thread work-group)
+template <typename T, int DIM, int MODE>
+__device__ inline void tail_colour_n(T* sm, const TLev& d, int color, int t, int nth, const TLev& C) {
+  constexpr bool wide = sizeof(T) == 4 && DIM == 2;
+  const int per = (d.hc + nth - 1) / nth;
+  if (per <= 1)
+    tail_colour<T, DIM, 1, MODE>(sm, d, color, t, nth, C);
+  else if (per <= 2 || !wide)
+    tail_colour<T, DIM, 2, MODE>(sm, d, color, t, nth, C);
+  else
+    tail_colour<T, DIM, wide ? 4 : 2, MODE>(sm, d, color, t, nth, C);
+}
+
+// Residual of the children of each cell of C, summed into C's right-hand
+// side (C's iterate is not cleared: its first sweep starts from zero by
+// construction).  Thread t (of nth) takes coarse cells t, t + nth, ..., K
+// at a time; a missing child of a ragged level is loaded at a clamped index
+// and dropped.
+template <typename T, int DIM, int K>
 __device__ inline void tail_restrict(T* sm, const TLev& L, const TLev& C, int t, int nth) {
-  const T* x = TAIL_X(L, sm);
-  const T* b = TAIL_B(L, sm);
-  const T* dg = TAIL_D(L, sm);
-  T* xc = TAIL_X(C, sm);
-  T* bc = TAIL_B(C, sm);
-  for (int I = t; I < C.N; I += nth) {
-    int ci, cj, ck;
-    cell_of(C, I, ci, cj, ck);
-    T sum = 0;
-    for (int dk = 0; dk < 2; ++dk) {
-      const int k = 2 * ck + dk;
-      if (k >= L.n2) break;
-      for (int dj = 0; dj < 2; ++dj) {
-        const int j = 2 * cj + dj;
-        if (j >= L.n1) break;
-        for (int di = 0; di < 2; ++di) {
-          const int i = 2 * ci + di;
-          if (i >= L.n0) break;
-          const int q = i + L.n0 * (j + L.n1 * k);
-          sum += b[q] - dg[q] * x[q] - tail_offsum<T>(sm, L, i, j, k, q);
-        }
-      }
+  const T* x = sm + L.xb;
+  const T* b = x + L.np;
+  const T* dg = sm + L.cb;
+  T* bc = sm + C.xb + C.np;
+  for (int I0 = t; I0 < C.N; I0 += K * nth) {
+    T acc[K];
+    int Is[K];
+    bool ok[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      int I = I0 + u * nth;
+      ok[u] = I < C.N;
+      if (!ok[u]) I = I0;
+      Is[u] = I;
+      int ci, cj, ck;
+      cell_of<DIM>(C, I, ci, cj, ck);
+      T sum = 0;
+      // (in 3D one plane of four children at a time, for the registers)
+#pragma unroll 1
+      for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+          for (int di = 0; di < 2; ++di) {
+            int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+            const bool in = i < L.n0 && j < L.n1 && k < L.n2;
+            i = i < L.n0 ? i : L.n0 - 1;
+            j = j < L.n1 ? j : L.n1 - 1;
+            k = k < L.n2 ? k : L.n2 - 1;
+            const int q = i + L.n0 * (j + L.n1 * k);
+            const T r = b[q] - dg[q] * x[q] - tail_nsum<T, DIM, false>(sm, L, i, j, k, q, C);
+            sum = in ? sum + r : sum;
+          }
+      acc[u] = sum;
     }
-    bc[I] = sum;
-    xc[I] = (T)0;
+#pragma unroll
+    for (int u = 0; u < K; ++u)
+      if (ok[u]) bc[Is[u]] = acc[u];
   }
+}
+
+template <typename T, int DIM>
+__device__ inline void tail_restrict_n(T* sm, const TLev& L, const TLev& C, int t, int nth) {
+  const int per = (C.N + nth - 1) / nth;
+  if (per <= 1 || DIM == 3 || sizeof(T) == 8)
+    tail_restrict<T, DIM, 1>(sm, L, C, t, nth);
+  else
+    tail_restrict<T, DIM, 2>(sm, L, C, t, nth);
 }
 
 // ---- the smallest tail levels by one wavefront ----------------------------
@@ -952,7 +1033,6 @@ __device__ inline void tail_restrict(T* sm, const TLev& L, const TLev& C, int t,
 // its lanes synchronise through wave-scope fences instead of work-group
 // barriers (LDS operations of one wave complete in order).
 #define EBIT_TAIL_WAVE_CELLS 512
-#define EBIT_TAIL_WAVE_SLOTS (EBIT_TAIL_WAVE_CELLS / 64)
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -960,179 +1040,149 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cells of one level owned by this lane: lane + 64 m, with (i, j, k).
-struct LaneCells {
-  int n;
-  int i[EBIT_TAIL_WAVE_SLOTS], j[EBIT_TAIL_WAVE_SLOTS], k[EBIT_TAIL_WAVE_SLOTS];
-  __device__ LaneCells(const TLev& d, int lane) : n(0) {
-#pragma unroll
-    for (int m = 0; m < EBIT_TAIL_WAVE_SLOTS; ++m) {
-      const int c = lane + 64 * m;
-      cell_of(d, c < d.N ? c : 0, i[m], j[m], k[m]);
-      if (c < d.N) n = m + 1;
+// Smoothing on level L before (pre) or after (post) the coarse level C, by
+// threads t of nth; sync() after every colour.
+template <typename T, int DIM, typename Sync>
+__device__ inline void tail_pre(T* sm, const TLev& L, const TLev& C, int nu1, int t, int nth, Sync sync) {
+  tail_colour_n<T, DIM, 1>(sm, L, 0, t, nth, C);
+  sync();
+  tail_colour_n<T, DIM, 0>(sm, L, 1, t, nth, C);
+  sync();
+  for (int s = 1; s < nu1; ++s)
+    for (int col = 0; col < 2; ++col) {
+      tail_colour_n<T, DIM, 0>(sm, L, col, t, nth, C);
+      sync();
     }
-  }
-};
+}
 
-template <typename T>
-__device__ inline void wave_sweep(T* sm, const TLev& d, const LaneCells& lc, int lane, int color,
-                                  const T* xc = nullptr, const TLev* C = nullptr) {
-  T* x = TAIL_X(d, sm);
-  const T* b = TAIL_B(d, sm);
-  const T* di = TAIL_DI(d, sm);
-#pragma unroll
-  for (int m = 0; m < EBIT_TAIL_WAVE_SLOTS; ++m) {
-    if (m >= lc.n || ((lc.i[m] + lc.j[m] + lc.k[m]) & 1) != color) continue;
-    const int q = lane + 64 * m;
-    x[q] = (b[q] - tail_offsum<T>(sm, d, lc.i[m], lc.j[m], lc.k[m], q, xc, C)) * di[q];
-  }
-  wave_sync();
+template <typename T, int DIM, typename Sync>
+__device__ inline void tail_post(T* sm, const TLev& L, const TLev& C, int nu2, int t, int nth, Sync sync) {
+  tail_colour_n<T, DIM, 2>(sm, L, 1, t, nth, C);
+  sync();
+  tail_colour_n<T, DIM, 0>(sm, L, 0, t, nth, C);
+  sync();
+  for (int s = 1; s < nu2; ++s)
+    for (int col = 1; col >= 0; --col) {
+      tail_colour_n<T, DIM, 0>(sm, L, col, t, nth, C);
+      sync();
+    }
 }
 
 // V-cycle over tail levels l0 .. nl-1 by wave 0 (the rest of the work-group
-// waits at the caller's barrier); level l0's right-hand side is in place and
-// its iterate zero.
-template <typename T>
-__device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0, int nl, const T* inv) {
+// waits at the caller's barrier); level l0's right-hand side is in place.
+template <typename T, int DIM>
+__device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0, int nl, bool dense) {
   const int lane = threadIdx.x;
-  const int nu1 = a.nu1, nu2 = a.nu2;
+  auto sync = [] { wave_sync(); };
   for (int l = l0; l < nl - 1; ++l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
-    const LaneCells lc(L, lane);
-    for (int s = 0; s < nu1; ++s) {
-      wave_sweep(sm, L, lc, lane, 0);
-      wave_sweep(sm, L, lc, lane, 1);
-    }
-    tail_restrict(sm, L, C, lane, 64);
+    tail_pre<T, DIM>(sm, L, C, a.nu1, lane, 64, sync);
+    tail_restrict_n<T, DIM>(sm, L, C, lane, 64);
     wave_sync();
   }
-  if (inv) {
+  const TLev L = tlev(a.L[nl - 1]);
+  T* x = sm + L.xb;
+  const T* b = x + L.np;
+  if (dense) {
     // coarsest level solved exactly: x = A^-1 b, lane t forming row t
-    const TLev L = tlev(a.L[nl - 1]);
-    T* x = TAIL_X(L, sm);
-    const T* b = TAIL_B(L, sm);
+    const T* inv = sm + a.inv;
     T acc = 0;
-    if (lane < L.N)
-      for (int j = 0; j < L.N; ++j) acc += inv[j * L.N + lane] * b[j];
+    if (lane < L.N) {
+#pragma unroll 8
+      for (int j = 0; j < L.N; ++j) acc = tfma(inv[j * L.N + lane], b[j], acc);
+    }
     wave_sync();
     if (lane < L.N) x[lane] = acc;
     wave_sync();
   } else {
-    // coarsest level: symmetric Gauss-Seidel by one lane (exact for one cell)
-    const TLev L = tlev(a.L[nl - 1]);
+    // coarsest level: symmetric Gauss-Seidel from zero by one lane (exact
+    // for one cell)
+    for (int q = lane; q < L.N; q += 64) x[q] = (T)0;
+    wave_sync();
     if (lane == 0) {
-      T* x = TAIL_X(L, sm);
-      const T* b = TAIL_B(L, sm);
-      const T* di = TAIL_DI(L, sm);
+      const T* di = sm + L.cb + L.np;
       const int sweeps = L.N == 1 ? 1 : 50;
       for (int s = 0; s < sweeps; ++s)
         for (int dir = 0; dir < 2; ++dir)
           for (int qq = 0; qq < L.N; ++qq) {
             const int q = dir ? (L.N - 1 - qq) : qq;
             int i, j, k;
-            cell_of(L, q, i, j, k);
-            x[q] = (b[q] - tail_offsum<T>(sm, L, i, j, k, q)) * di[q];
+            cell_of<DIM>(L, q, i, j, k);
+            x[q] = (b[q] - tail_nsum<T, DIM, false>(sm, L, i, j, k, q, L)) * di[q];
           }
     }
     wave_sync();
   }
   for (int l = nl - 2; l >= l0; --l) {
-    const TLev L = tlev(a.L[l]);
+    const TLev F = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
-    const LaneCells lc(L, lane);
-    const T* xcs = TAIL_X(C, sm);
-    wave_sweep(sm, L, lc, lane, 1, xcs, &C);
-    wave_sweep(sm, L, lc, lane, 0);
-    for (int s = 1; s < nu2; ++s) {
-      wave_sweep(sm, L, lc, lane, 1);
-      wave_sweep(sm, L, lc, lane, 0);
-    }
+    tail_post<T, DIM>(sm, F, C, a.nu2, lane, 64, sync);
   }
 }
 
-template <typename T>
+template <typename T, int DIM>
 __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int nl = a.nl, nu2 = a.nu2, nu1 = a.nu1;
-  // Staging: every (level, cell) pair of the tail is one item; a thread
-  // issues the global loads of TAIL_BATCH items before storing any, so the
-  // memory latency is paid a few times, not once per level and per cell.
-  int tot = 0;
-  for (int l = 0; l < nl; ++l) tot += (int)a.L[l].d.N;
-  for (int base = 0; base < tot; base += nth * TAIL_BATCH) {
-    T vd[TAIL_BATCH], v0[TAIL_BATCH], v1[TAIL_BATCH], v2[TAIL_BATCH], vb[TAIL_BATCH];
-    int lv[TAIL_BATCH], qv[TAIL_BATCH];
+  const int nl = a.nl;
+  {
+    // the top level's right-hand side, then the coefficient image suffix:
+    // all loads of a batch issue before any store (an index past the end is
+    // clamped to the batch's first, whose value it then stores again)
+    const TLev L = tlev(a.L[0]);
+    T* bt = sm + L.xb + L.np;
+    const T* bg = a.bg;
+    for (int q0 = tid; q0 < L.N; q0 += 4 * nth) {
+      int qi[4];
+      T v[4];
 #pragma unroll
-    for (int u = 0; u < TAIL_BATCH; ++u) {
-      int item = base + u * nth + tid;
-      lv[u] = -1;
-      if (item >= tot) continue;
-      int l = 0;
-      while (item >= (int)a.L[l].d.N) item -= (int)a.L[l++].d.N;
-      lv[u] = l;
-      qv[u] = item;
-      const int dim = a.L[l].d.dim;
-      vd[u] = a.diag[l][item];
-      v0[u] = a.off[l][0][item];
-      v1[u] = dim >= 2 ? a.off[l][1][item] : (T)0;
-      v2[u] = dim == 3 ? a.off[l][2][item] : (T)0;
-      vb[u] = l == 0 ? a.bg[item] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < TAIL_BATCH; ++u) {
-      if (lv[u] < 0) continue;
-      const TLev L = tlev(a.L[lv[u]]);
-      const int N = L.N, q = qv[u];
-      T* x = TAIL_X(L, sm);
-      x[2 * N + q] = vd[u];
-      x[3 * N + q] = (T)1 / vd[u];
-      x[4 * N + q] = v0[u];
-      if (L.dim >= 2) x[5 * N + q] = v1[u];
-      if (L.dim == 3) x[6 * N + q] = v2[u];
-      if (lv[u] == 0) {
-        x[N + q] = vb[u];
-        x[q] = (T)0;
+      for (int u = 0; u < 4; ++u) {
+        qi[u] = q0 + u * nth < L.N ? q0 + u * nth : q0;
+        v[u] = bg[qi[u]];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bt[qi[u]] = v[u];
+    }
+    const u32x4* src = reinterpret_cast<const u32x4*>(a.img);
+    u32x4* dst = reinterpret_cast<u32x4*>(sm);
+    const int nv = a.cvec;
+    for (int e0 = tid; e0 < nv; e0 += TAIL_COPY_BATCH * nth) {
+      int ei[TAIL_COPY_BATCH];
+      u32x4 v[TAIL_COPY_BATCH];
+#pragma unroll
+      for (int u = 0; u < TAIL_COPY_BATCH; ++u) {
+        ei[u] = e0 + u * nth < nv ? e0 + u * nth : e0;
+        v[u] = src[ei[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < TAIL_COPY_BATCH; ++u) dst[ei[u]] = v[u];
     }
   }
   __syncthreads();
   // with a usable inverse the V-cycle stops at its level
-  const T* inv = (a.dl >= 0 && *a.inv_ok) ? a.inv : nullptr;
-  const int nle = inv ? a.dl + 1 : nl;
+  const bool dense = a.dl >= 0 && *a.inv_ok;
+  const int nle = dense ? a.dl + 1 : nl;
   // levels l0 .. nle-1 are small enough for one wavefront
   int l0 = nle - 1;
   while (l0 > 0 && a.L[l0 - 1].d.N <= EBIT_TAIL_WAVE_CELLS) --l0;
+  auto sync = [] { __syncthreads(); };
   for (int l = 0; l < l0; ++l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
-    for (int s = 0; s < nu1; ++s)
-      for (int col = 0; col < 2; ++col) {
-        tail_sweep(sm, L, col);
-        __syncthreads();
-      }
-    tail_restrict(sm, L, C, tid, nth);
+    tail_pre<T, DIM>(sm, L, C, a.nu1, tid, nth, sync);
+    tail_restrict_n<T, DIM>(sm, L, C, tid, nth);
     __syncthreads();
   }
-  if (tid < 64) tail_wave<T>(a, sm, l0, nle, inv);
+  if (tid < 64) tail_wave<T, DIM>(a, sm, l0, nle, dense);
   __syncthreads();
   for (int l = l0 - 1; l >= 0; --l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
-    // black sweep with the correction added to its (red) neighbours, then red
-    tail_sweep(sm, L, 1, TAIL_X(C, sm), &C);
-    __syncthreads();
-    tail_sweep(sm, L, 0);
-    __syncthreads();
-    for (int s = 1; s < nu2; ++s)
-      for (int col = 1; col >= 0; --col) {
-        tail_sweep(sm, L, col);
-        __syncthreads();
-      }
+    tail_post<T, DIM>(sm, L, C, a.nu2, tid, nth, sync);
   }
   {
     const TLev L = tlev(a.L[0]);
-    const T* x = TAIL_X(L, sm);
+    const T* x = sm + L.xb;
     T* xg = a.xg;
     for (int q = tid; q < L.N; q += nth) xg[q] = x[q];
   }
@@ -1148,18 +1198,32 @@ struct BuildOut {
   double* off[3];
   float* d32;     // FP32 copies of diag and off (null: none)
   float* o32[3];
+  float* i32;     // the level's block of the FP32 or FP64 tail image (null: none)
+  double* i64;
 };
 
 __device__ inline void store_built(const BuildOut& o, long long I, double M, double F, const double (&cross)[3]) {
   const double dg = M + 0.5 * F;
+  const long long P = tail_pad(o.cd.N);
   o.diag[I] = dg;
   o.mass[I] = M;
   if (o.d32) o.d32[I] = (float)dg;
+  if (o.i32) {
+    o.i32[I] = (float)dg;
+    o.i32[P + I] = 1.0f / (float)dg;
+  }
+  if (o.i64) {
+    o.i64[I] = dg;
+    o.i64[P + I] = 1.0 / dg;
+  }
+#pragma unroll
   for (int a = 0; a < 3; ++a)
     if (o.off[a]) {
       const double v = 0.5 * cross[a];
       o.off[a][I] = v;
       if (o.o32[a]) o.o32[a][I] = (float)v;
+      if (o.i32) o.i32[(2 + a) * P + I] = (float)v;
+      if (o.i64) o.i64[(2 + a) * P + I] = v;
     }
 }
 
@@ -1255,22 +1319,24 @@ __global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
 // transposed so that lane t of a wave reads column t contiguously.  A
 // pivot that is not positive and finite (a singular level) clears *ok and
 // the tail keeps its Gauss-Seidel coarsest solve.
-__device__ inline void dense_inverse(const CoarseOp<double>& op, double* inv64, float* inv32, int* ok,
-                                     double (*A)[EBIT_DENSE_MAX + 1], double* prow, double* pcol) {
+__device__ inline bool dense_inverse(const CoarseOp<double>& op, double* inv64, float* inv32, int* ok,
+                                     double (*A)[EBIT_DENSE_MAX + 1], double (*colb)[EBIT_DENSE_MAX],
+                                     double (*rowb)[EBIT_DENSE_MAX]) {
+  constexpr int M = EBIT_DENSE_MAX;
+  constexpr int CW = M / 4;  // columns per owning wave
   const int N = (int)op.d.N;
   const int tid = threadIdx.x;
-  // thread (ti, tj) of a 32 x 32 grid owns elements (ti + 32 u, tj + 32 v)
-  const int ti = tid >> 5, tj = tid & 31;
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) A[ti + 32 * u][tj + 32 * v] = 0.0;
+  const int w = tid >> 6, lane = tid & 63;
+  const bool owner = w < 4;  // waves 0-3 hold the matrix, the others only keep the barriers
+  for (int e = tid; e < M * M; e += blockDim.x) A[e / M][e % M] = 0.0;
   __syncthreads();
   if (tid < N) {
     int i, j, k;
     cell_ijk(op.d, tid, i, j, k);
     A[tid][tid] = op.diag[tid];
-    for (int a = 0; a < op.d.dim; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a >= op.d.dim) continue;
       int ni, nj, nk;
       if (neighbour(op.d, i, j, k, 2 * a + 1, ni, nj, nk)) A[tid][cell_index(op.d, ni, nj, nk)] += op.off[a][tid];
       if (neighbour(op.d, i, j, k, 2 * a, ni, nj, nk)) {
@@ -1279,49 +1345,55 @@ __device__ inline void dense_inverse(const CoarseOp<double>& op, double* inv64, 
       }
     }
   }
-  bool good = true;
-  for (int p = 0; p < N; ++p) {
-    __syncthreads();
-    if (tid < N) {
-      prow[tid] = A[p][tid];
-      pcol[tid] = A[tid][p];
-    }
-    __syncthreads();
-    const double piv = prow[p];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      good = false;
-      break;
-    }
-    const double ip = 1.0 / piv;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int i = ti + 32 * u, j = tj + 32 * v;
-        if (i >= N || j >= N) continue;
-        double w;
-        if (i == p && j == p)
-          w = ip;
-        else if (i == p)
-          w = prow[j] * ip;
-        else if (j == p)
-          w = -pcol[i] * ip;
-        else
-          w = A[i][j] - pcol[i] * prow[j] * ip;
-        A[i][j] = w;
-      }
-  }
   __syncthreads();
+  // lane i of wave w keeps A[i][CW w .. CW w + CW - 1] in registers
+  double r[CW];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int jj = 0; jj < CW; ++jj) r[jj] = owner ? A[lane][CW * w + jj] : 0.0;
+  bool good = true;
+  for (int pw = 0; pw < 4 && pw * CW < N && good; ++pw) {
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int i = ti + 32 * u, j = tj + 32 * v;
-      if (i >= N || j >= N) continue;
-      inv64[j * N + i] = A[i][j];
-      if (inv32) inv32[j * N + i] = (float)A[i][j];
+    for (int c = 0; c < CW; ++c) {
+      const int p = pw * CW + c;
+      if (p < N && good) {
+        // column p and row p of the current matrix go through LDS; the two
+        // buffers alternate so one barrier per pivot suffices
+        const int buf = c & 1;
+        if (w == pw) colb[buf][lane] = r[c];
+        if (owner && lane == p) {
+#pragma unroll
+          for (int jj = 0; jj < CW; ++jj) rowb[buf][CW * w + jj] = r[jj];
+        }
+        __syncthreads();
+        const double piv = colb[buf][p];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          good = false;
+        } else if (owner) {
+          const double ip = 1.0 / piv;
+          const double f = colb[buf][lane];
+#pragma unroll
+          for (int jj = 0; jj < CW; ++jj) {
+            const int j = CW * w + jj;
+            const double prj = rowb[buf][j] * ip;
+            if (lane == p) r[jj] = (j == p) ? ip : prj;
+            else r[jj] = (j == p) ? -f * ip : r[jj] - f * prj;
+          }
+        }
+      }
     }
+  }
+  if (owner && lane < N) {
+#pragma unroll
+    for (int jj = 0; jj < CW; ++jj) {
+      const int j = CW * w + jj;
+      if (j < N) {
+        inv64[j * N + lane] = r[jj];
+        if (inv32) inv32[j * N + lane] = (float)r[jj];
+      }
+    }
+  }
   if (tid == 0) *ok = good ? 1 : 0;
+  return good;
 }
 
 // Per system, everything the one-work-group part of a hierarchy build needs
@@ -1334,43 +1406,59 @@ struct BuildTable {
   double* off[EBIT_MAX_LEVELS][3];
   float* d32[EBIT_MAX_LEVELS];
   float* o32[EBIT_MAX_LEVELS][3];
+  float* i32[EBIT_MAX_LEVELS];
+  double* i64[EBIT_MAX_LEVELS];
   double* inv64;
   float* inv32;
   int* inv_ok;
 };
 
-// Levels ls .. nlev-1 (each from the one above), then the inverse of the
-// dense level: one work-group per system, a barrier between levels.
+// Levels ls .. nlev-1 (each from the one above) and the inverse of the
+// dense level: one work-group per system, a barrier between levels.  The
+// levels below the dense one serve only a failed inversion (the tail then
+// falls back to Gauss-Seidel on the coarsest level), so they are built
+// after it and only in that case.
+__device__ inline void build_small_level(const BuildTable& t, int l) {
+  CoarseOp<double> f;
+  f.d = t.d[l - 1];
+  f.diag = t.diag[l - 1];
+  f.mass = t.mass[l - 1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f.off[a] = t.off[l - 1][a];
+  BuildOut o;
+  o.cd = t.d[l];
+  o.diag = t.diag[l];
+  o.mass = t.mass[l];
+  o.d32 = t.d32[l];
+  o.i32 = t.i32[l];
+  o.i64 = t.i64[l];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    o.off[a] = t.off[l][a];
+    o.o32[a] = t.o32[l][a];
+  }
+  for (long long I = threadIdx.x; I < o.cd.N; I += blockDim.x) build_cell_from_coarse(f, o, I);
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(1024) void k_build_small(const BuildTable* __restrict__ tabs) {
   __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
-  __shared__ double prow[EBIT_DENSE_MAX], pcol[EBIT_DENSE_MAX];
+  __shared__ double colb[2][EBIT_DENSE_MAX], rowb[2][EBIT_DENSE_MAX];
   const BuildTable& t = tabs[blockIdx.x];
   const int ls = t.ls, nlev = t.nlev, dl = t.dl;
-  for (int l = ls; l < nlev; ++l) {
-    CoarseOp<double> f;
-    f.d = t.d[l - 1];
-    f.diag = t.diag[l - 1];
-    f.mass = t.mass[l - 1];
-    for (int a = 0; a < 3; ++a) f.off[a] = t.off[l - 1][a];
-    BuildOut o;
-    o.cd = t.d[l];
-    o.diag = t.diag[l];
-    o.mass = t.mass[l];
-    o.d32 = t.d32[l];
-    for (int a = 0; a < 3; ++a) {
-      o.off[a] = t.off[l][a];
-      o.o32[a] = t.o32[l][a];
-    }
-    for (long long I = threadIdx.x; I < o.cd.N; I += blockDim.x) build_cell_from_coarse(f, o, I);
+  const int upto = dl >= 0 ? dl + 1 : nlev;
+  for (int l = ls; l < upto; ++l) build_small_level(t, l);
+  if (dl < 0) return;
+  CoarseOp<double> f;
+  f.d = t.d[dl];
+  f.diag = t.diag[dl];
+  f.mass = t.mass[dl];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f.off[a] = t.off[dl][a];
+  const bool good = dense_inverse(f, t.inv64, t.inv32, t.inv_ok, A, colb, rowb);
+  if (!good) {
     __syncthreads();
-  }
-  if (dl >= 0) {
-    CoarseOp<double> f;
-    f.d = t.d[dl];
-    f.diag = t.diag[dl];
-    f.mass = t.mass[dl];
-    for (int a = 0; a < 3; ++a) f.off[a] = t.off[dl][a];
-    dense_inverse(f, t.inv64, t.inv32, t.inv_ok, A, prow, pcol);
+    for (int l = (ls > dl + 1 ? ls : dl + 1); l < nlev; ++l) build_small_level(t, l);
   }
 }
 
@@ -1751,13 +1839,13 @@ __global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const Ca
   }
 }
 
-template <typename T>
+template <typename T, int DIM>
 __global__ __launch_bounds__(EBIT_TAIL_THREADS) void kb_tail(const SolveCase<T>* __restrict__ cs,
                                                              const CaseCtl* __restrict__ ctl) {
   extern __shared__ __align__(16) unsigned char tail_smem[];
   const int c = blockIdx.x;
   if (!ctl[c].active) return;
-  tail_body<T>(cs[c].tail, reinterpret_cast<T*>(tail_smem));
+  tail_body<T, DIM>(cs[c].tail, reinterpret_cast<T*>(tail_smem));
 }
 
 // z.r and, unless the recurrence restarts, z.q (q = A p of the previous iteration)
@@ -1967,6 +2055,8 @@ void ebit_build_tables(const EbitLevelHost* lv, int nlev, int want32, void* host
       t.diag[l] = lv[l].diag64[sys];
       t.mass[l] = lv[l].mass64[sys];
       t.d32[l] = want32 ? lv[l].diag32[sys] : nullptr;
+      t.i32[l] = want32 ? lv[l].img32[sys] : nullptr;
+      t.i64[l] = want32 ? nullptr : lv[l].img64[sys];
       for (int a = 0; a < 3; ++a) {
         const bool on = a < lv[l].d.dim;
         t.off[l][a] = on ? lv[l].off64[sys][a] : nullptr;
@@ -1996,6 +2086,8 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
       o.diag = lv[l].diag64[sys];
       o.mass = lv[l].mass64[sys];
       o.d32 = want32 ? lv[l].diag32[sys] : nullptr;
+      o.i32 = want32 ? lv[l].img32[sys] : nullptr;
+      o.i64 = want32 ? nullptr : lv[l].img64[sys];
       for (int a = 0; a < 3; ++a) {
         const bool on = a < o.cd.dim;
         o.off[a] = on ? lv[l].off64[sys][a] : nullptr;
@@ -2039,9 +2131,13 @@ int ebit_tail_lds_setup(void) {
       hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
     return 64 * 1024;
   if (v > 64 * 1024) {
-    if (hipFuncSetAttribute((const void*)kb_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+    if (hipFuncSetAttribute((const void*)kb_tail<float, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
             hipSuccess ||
-        hipFuncSetAttribute((const void*)kb_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+        hipFuncSetAttribute((const void*)kb_tail<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)kb_tail<double, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)kb_tail<double, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
             hipSuccess) {
       (void)hipGetLastError();
       return 64 * 1024;
@@ -2127,11 +2223,11 @@ double* lvb<double>(const EbitLevelHost& L) { return L.b64; }
 template <>
 float* lvb<float>(const EbitLevelHost& L) { return L.b32; }
 template <typename T>
-const T* dense_inv(const EbitLevelHost& L, int sys);
+const T* timg(const EbitLevelHost& L, int sys);
 template <>
-const double* dense_inv<double>(const EbitLevelHost& L, int sys) { return L.inv64[sys]; }
+const float* timg<float>(const EbitLevelHost& L, int sys) { return L.img32[sys]; }
 template <>
-const float* dense_inv<float>(const EbitLevelHost& L, int sys) { return L.inv32[sys]; }
+const double* timg<double>(const EbitLevelHost& L, int sys) { return L.img64[sys]; }
 template <typename T>
 T* zb(const EbitSolveBufs& B, int s);
 template <>
@@ -2149,16 +2245,39 @@ int rb_zchunk(const Dims& d) {
   return zc;
 }
 
-// First level (>= 1) of the tail: the levels from there down (x, b and
-// coefficients) fit lds_bytes of LDS and the top one has at most tail_cells
-// cells; the coarsest level is always in the tail.
+// The dense level of a hierarchy (the first of at most EBIT_DENSE_MAX
+// cells, whose inverse the build computes), or -1.
+int dense_level(const EbitLevelHost* lv, int nlev) {
+  for (int l = 1; l < nlev; ++l)
+    if (lv[l].inv64[0]) return l;
+  return -1;
+}
+
+// LDS elements of a tail from level lt down: the copied coefficient image
+// (with the dense inverse at its end) and x and b of every level.
+long long tail_lds_elems(const EbitLevelHost* lv, int nlev, int lt, long long* coef) {
+  const int dl = dense_level(lv, nlev);
+  long long c = dl >= 0 ? tail_pad(lv[dl].d.N * lv[dl].d.N) : 0, xb = 0;
+  for (int l = lt; l < nlev; ++l) {
+    c += tail_img_elems(lv[l].d);
+    xb += 2 * tail_pad(lv[l].d.N);
+  }
+  if (coef) *coef = c;
+  return c + xb;
+}
+
+// First level (>= 1) of the tail: the levels from there down fit lds_bytes
+// of LDS and lie in the tail image, and the top one has at most tail_cells
+// cells; the coarsest level and the dense level are always in the tail.
 template <typename T>
 int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells, int lds_bytes) {
-  long long tot = tail_level_elems(lv[nlev - 1].d);
+  const int dl = dense_level(lv, nlev);
   int lt = nlev - 1;
   for (int l = nlev - 2; l >= 1; --l) {
-    tot += tail_level_elems(lv[l].d);
-    if (tot * (long long)sizeof(T) > lds_bytes || lv[l].d.N > tail_cells || nlev - l > EBIT_TAIL_MAX) break;
+    if (lv[l].d.N > EBIT_TAIL_IMG_CELLS || nlev - l > EBIT_TAIL_MAX ||
+        tail_lds_elems(lv, nlev, l, nullptr) * (long long)sizeof(T) > lds_bytes)
+      break;
+    if (lv[l].d.N > tail_cells && (dl < 0 || l < dl)) break;
     lt = l;
   }
   return lt;
@@ -2338,7 +2457,10 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   }
   {
     ProfScope ps(pf, EBIT_KC_TAIL, st);
-    hipLaunchKernelGGL(kb_tail<T>, dim3(P.n), dim3(EBIT_TAIL_THREADS), P.tail_bytes, st, cs, ctl);
+    if (P.dim == 3)
+      hipLaunchKernelGGL((kb_tail<T, 3>), dim3(P.n), dim3(EBIT_TAIL_THREADS), P.tail_bytes, st, cs, ctl);
+    else
+      hipLaunchKernelGGL((kb_tail<T, 2>), dim3(P.n), dim3(EBIT_TAIL_THREADS), P.tail_bytes, st, cs, ctl);
   }
   for (int l = P.Lmax - 1; l >= 1; --l) {
     auto coarse = [&](int in, int out, int add, int nsw) { launch_coarse(P, cs, l, in, out, add, nsw, st); };
@@ -2432,8 +2554,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
   for (int c = 0; c < n; ++c) {
     const EbitPlanCase& pc = cases[c];
     lt[c] = tail_start<T>(pc.lv, pc.nlev, o->tail_cells, tail_lds);
-    size_t el = 0;
-    for (int l = lt[c]; l < pc.nlev; ++l) el += tail_level_elems(pc.lv[l].d);
+    const size_t el = (size_t)tail_lds_elems(pc.lv, pc.nlev, lt[c], nullptr);
     if (el > tail_elems) tail_elems = el;
     if (lt[c] > P->Lmax) P->Lmax = lt[c];
   }
@@ -2478,26 +2599,24 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       ta.nl = pc.nlev - lt[c];
       ta.nu1 = o->nu1;
       ta.nu2 = o->nu2;
-      long long off = 0;
+      long long coef = 0;
+      tail_lds_elems(pc.lv, pc.nlev, lt[c], &coef);
+      long long cb = 0, xb = coef;
       for (int m = 0; m < ta.nl; ++m) {
         const EbitLevelHost& L = pc.lv[lt[c] + m];
         ta.L[m].d = L.d;
-        ta.L[m].base = (int)off;
-        const CoarseOp<T> co = coarse_op_of<T>(L, sys);
-        ta.diag[m] = co.diag;
-        for (int q = 0; q < 3; ++q) ta.off[m][q] = co.off[q];
-        off += tail_level_elems(L.d);
+        ta.L[m].np = (int)tail_pad(L.d.N);
+        ta.L[m].cb = (int)cb;
+        ta.L[m].xb = (int)xb;
+        cb += tail_img_elems(L.d);
+        xb += 2 * tail_pad(L.d.N);
       }
-      ta.dl = -1;
-      ta.inv = nullptr;
-      ta.inv_ok = nullptr;
-      for (int m = 0; m < ta.nl; ++m)
-        if (pc.lv[lt[c] + m].inv64[sys]) {
-          ta.dl = m;
-          ta.inv = dense_inv<T>(pc.lv[lt[c] + m], sys);
-          ta.inv_ok = pc.lv[lt[c] + m].inv_ok + sys;
-          break;
-        }
+      const int dl = dense_level(pc.lv, pc.nlev);
+      ta.dl = dl >= lt[c] ? dl - lt[c] : -1;
+      ta.inv = (int)cb;
+      ta.inv_ok = dl >= 0 ? pc.lv[dl].inv_ok + sys : nullptr;
+      ta.img = timg<T>(pc.lv[lt[c]], sys);
+      ta.cvec = (int)(coef * (long long)sizeof(T) / 16);
       ta.bg = lvb<T>(pc.lv[lt[c]]);
       ta.xg = lvx<T>(pc.lv[lt[c]], 0);
       if (sys == 0) {
