@@ -43,12 +43,21 @@ struct Dims {
 
 // Tail image: the coarse levels of at most EBIT_TAIL_IMG_CELLS cells keep,
 // per system, their coefficients in one contiguous array, level after level
-// from fine to coarse (diag, 1/diag, off[0 .. dim-1], each padded to a
-// multiple of four elements), followed by the dense coarsest inverse; the
-// tail kernel copies a suffix of it straight into LDS.
+// from fine to coarse (fields diag, 1/diag, off[0 .. dim-1]), followed by
+// the dense coarsest inverse; the tail kernel copies a suffix of it
+// straight into LDS.  Within a field the cells of colour 0 ((i + j + k)
+// even) come first, then those of colour 1, each half (hs elements, a
+// multiple of four) in row order at slot (i >> 1) + hw (j + n1 k) with
+// hw = (n0 + 1) / 2.
 #define EBIT_TAIL_IMG_CELLS 8192
 __host__ __device__ inline long long tail_pad(long long n) { return (n + 3) & ~3LL; }
-__host__ __device__ inline long long tail_img_elems(const Dims& d) { return (2 + d.dim) * tail_pad(d.N); }
+__host__ __device__ inline long long tail_half(const Dims& d) {
+  return tail_pad((long long)((d.n[0] + 1) / 2) * d.n[1] * d.n[2]);
+}
+__host__ __device__ inline long long tail_img_elems(const Dims& d) { return (2 + d.dim) * 2 * tail_half(d); }
+__host__ __device__ inline long long tail_el(const Dims& d, long long hs, int i, int j, int k) {
+  return ((i + j + k) & 1) * hs + (i >> 1) + (long long)((d.n[0] + 1) / 2) * (j + (long long)d.n[1] * k);
+}
 
 __host__ __device__ inline long long cell_index(const Dims& d, int i, int j, int k) {
   return (long long)i + (long long)d.n[0] * ((long long)j + (long long)d.n[1] * k);

@@ -758,22 +758,29 @@ constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 
 // ---------------------------------------------------------------------------
 // tail of the V-cycle: every level small enough to sit in LDS, in one
 // work-group (no launch per smoothing sweep on the coarse levels).  The
-// hierarchy build leaves the coefficients of these levels (diag, 1/diag,
-// couplings) and the dense coarsest inverse in one contiguous image per
-// system, laid out as the kernel's LDS: the kernel starts with a straight
-// 16-byte copy of the suffix it needs.
+// hierarchy build leaves the coefficients of these levels and the dense
+// coarsest inverse in one contiguous image per system, laid out as the
+// kernel's LDS: the kernel starts with a straight 16-byte copy of the
+// suffix it needs.
+//
+// Layout of a tail level: every field (diag, 1/diag, couplings off[a], the
+// iterate x, the right-hand side b) keeps the cells of colour 0 (i + j + k
+// even) in its first half and those of colour 1 in its second, each half
+// in row order with the cells (i, j, k) of a grid row at slots i >> 1:
+// element colour * hs + (i >> 1) + hw (j + n1 k), hw = (n0 + 1) / 2.  A
+// colour sweep then reads its own cells and its neighbours at consecutive
+// addresses across a wavefront (no LDS bank conflicts).
 // ---------------------------------------------------------------------------
 #define EBIT_TAIL_MAX 16
 #define EBIT_TAIL_THREADS 1024
 #define TAIL_COPY_BATCH 8
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// One tail level in LDS: its coefficients (diag, 1/diag, off[0 .. dim-1],
-// np elements each) at cb, inside the copied image; its iterate x at xb and
-// right-hand side b at xb + np.
+// One tail level in LDS: field f (0 diag, 1 1/diag, 2 + a off[a]) at
+// cb + 2 f hs, x at xb and b at xb + 2 hs.
 struct TailLevel {
   Dims d;
-  int np;  // padded cell count: the stride of the level's arrays
+  int hs;  // colour half length (hw rows, padded to four)
   int cb;
   int xb;
 };
@@ -786,20 +793,19 @@ struct TailArgs {
   const T* img;        // coefficient image from the top tail level on (16-byte aligned)
   int cvec;            // its length in 16-byte units
   int dl;              // tail level solved exactly by its inverse, or -1
-  int inv;             // element offset of that inverse (transposed) in LDS
+  int inv;             // element offset of that inverse (natural order, transposed) in LDS
+  int tmp;             // element offset of EBIT_DENSE_MAX scratch elements in LDS
   const int* inv_ok;   // 1 if the inversion succeeded
-  const T* bg;         // right-hand side of the top tail level
-  T* xg;               // its correction (output)
+  const T* bg;         // right-hand side of the top tail level (natural order)
+  T* xg;               // its correction (output, natural order)
 };
 
-// Register copy of one tail level's shape (read once per level, so the
-// loops below do not go back to the case table), with float reciprocals
-// for division-free index decoding.  A colour of the red-black ordering is
-// numbered row by row: hw slots per grid row, slot m at i = 2 m + parity
-// (the last slot of a row of odd length may fall off the row).
+// Register copy of one tail level's shape (read once per level visit, so
+// the loops below do not go back to the case table), with float
+// reciprocals for division-free index decoding.
 struct TLev {
-  int n0, n1, n2, N, np, cb, xb, p0, p1, p2;
-  int hw, hc;         // colour slots per row and per level
+  int n0, n1, n2, N, hs, cb, xb, p0, p1, p2;
+  int hw, hc;              // colour slots per grid row and per colour
   float r0, r1, r01, rhw;  // 1/n0, 1/n1, 1/(n0 n1), 1/hw
 };
 
@@ -809,7 +815,7 @@ __device__ inline TLev tlev(const TailLevel& L) {
   t.n1 = L.d.n[1];
   t.n2 = L.d.n[2];
   t.N = (int)L.d.N;
-  t.np = L.np;
+  t.hs = L.hs;
   t.cb = L.cb;
   t.xb = L.xb;
   t.p0 = L.d.per[0];
@@ -846,226 +852,228 @@ __device__ inline void cell_of(const TLev& d, int c, int& i, int& j, int& k) {
   i = c - j * d.n0;
 }
 
+// element of cell (i, j, k) within any field of level d
+__device__ inline int rb_el(const TLev& d, int i, int j, int k) {
+  return ((i + j + k) & 1) * d.hs + (i >> 1) + d.hw * (j + d.n1 * k);
+}
+
 __device__ inline float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Sum over the neighbours of cell q = (i, j, k) of coupling x neighbour
-// value, over the neighbour set of neighbour() (periodic wrap, none across
-// a wall), in the order +x, -x, +y, -y, +z, -z.  Every load is issued
-// unconditionally, at a wrapped index (a missing neighbour's term is then
-// dropped by a select), so that all of them are in flight together.  With
-// XC the neighbour values are read as x + xc[parent]: the prolongated
-// correction of the coarse level C.
-template <typename T, int DIM, bool XC>
-__device__ inline T tail_nsum(const T* sm, const TLev& d, int i, int j, int k, int q, const TLev& C) {
-  const T* x = sm + d.xb;
-  const T* xc = sm + C.xb;
-  const int s2 = d.n0 * d.n1;
-  T s = 0;
-  {
-    const T* o = sm + d.cb + 2 * d.np;
-    const bool e = i + 1 < d.n0, w = i > 0;
-    const int qe = e ? q + 1 : q + 1 - d.n0;
-    const int qw = w ? q - 1 : q - 1 + d.n0;
-    T ve = x[qe], vw = x[qw];
-    if (XC) {
-      const int cjk = C.n0 * ((j >> 1) + C.n1 * (k >> 1));
-      ve += xc[(e ? (i + 1) >> 1 : 0) + cjk];
-      vw += xc[(w ? (i - 1) >> 1 : (d.n0 - 1) >> 1) + cjk];
-    }
-    const T oe = o[q], ow = o[qw];
-    s = (e || d.p0) ? tfma(oe, ve, s) : s;
-    s = (w || d.p0) ? tfma(ow, vw, s) : s;
-  }
-  {
-    const T* o = sm + d.cb + 3 * d.np;
-    const bool e = j + 1 < d.n1, w = j > 0;
-    const int qe = e ? q + d.n0 : q + d.n0 - s2;
-    const int qw = w ? q - d.n0 : q - d.n0 + s2;
-    T ve = x[qe], vw = x[qw];
-    if (XC) {
-      const int ci = i >> 1, ck = C.n1 * (k >> 1);
-      ve += xc[ci + C.n0 * ((e ? (j + 1) >> 1 : 0) + ck)];
-      vw += xc[ci + C.n0 * ((w ? (j - 1) >> 1 : (d.n1 - 1) >> 1) + ck)];
-    }
-    const T oe = o[q], ow = o[qw];
-    s = (e || d.p1) ? tfma(oe, ve, s) : s;
-    s = (w || d.p1) ? tfma(ow, vw, s) : s;
-  }
+// Elements of the neighbours of cell (i, j, k) across sides +x, -x, +y, -y,
+// +z, -z, with the periodic wrap.  Across a wall the wrapped cell is named
+// too: the coupling stored there is exactly zero (the build adds no
+// coupling across a wall), so its term vanishes without a test.
+template <int DIM>
+__device__ inline void rb_nbrs(const TLev& d, int i, int j, int k, int (&nb)[6]) {
+  nb[0] = rb_el(d, i + 1 < d.n0 ? i + 1 : 0, j, k);
+  nb[1] = rb_el(d, i > 0 ? i - 1 : d.n0 - 1, j, k);
+  nb[2] = rb_el(d, i, j + 1 < d.n1 ? j + 1 : 0, k);
+  nb[3] = rb_el(d, i, j > 0 ? j - 1 : d.n1 - 1, k);
   if (DIM == 3) {
-    const T* o = sm + d.cb + 4 * d.np;
-    const bool e = k + 1 < d.n2, w = k > 0;
-    const int qe = e ? q + s2 : q + s2 - d.N;
-    const int qw = w ? q - s2 : q - s2 + d.N;
-    T ve = x[qe], vw = x[qw];
-    if (XC) {
-      const int cij = (i >> 1) + C.n0 * (j >> 1);
-      ve += xc[cij + C.n0 * C.n1 * (e ? (k + 1) >> 1 : 0)];
-      vw += xc[cij + C.n0 * C.n1 * (w ? (k - 1) >> 1 : (d.n2 - 1) >> 1)];
-    }
-    const T oe = o[q], ow = o[qw];
-    s = (e || d.p2) ? tfma(oe, ve, s) : s;
-    s = (w || d.p2) ? tfma(ow, vw, s) : s;
+    nb[4] = rb_el(d, i, j, k + 1 < d.n2 ? k + 1 : 0);
+    nb[5] = rb_el(d, i, j, k > 0 ? k - 1 : d.n2 - 1);
+  }
+}
+
+// sum of coupling x neighbour value at element e with neighbours nb, in
+// the order +x, -x, +y, -y, +z, -z (a coupling belongs to the cell on the
+// lower side of its link)
+template <typename T, int DIM>
+__device__ inline T rb_nsum(const T* sm, const TLev& d, int e, const int (&nb)[6]) {
+  const T* x = sm + d.xb;
+  const T* o0 = sm + d.cb + 4 * d.hs;
+  const T* o1 = o0 + 2 * d.hs;
+  T s = 0;
+  s = tfma(o0[e], x[nb[0]], s);
+  s = tfma(o0[nb[1]], x[nb[1]], s);
+  s = tfma(o1[e], x[nb[2]], s);
+  s = tfma(o1[nb[3]], x[nb[3]], s);
+  if (DIM == 3) {
+    const T* o2 = o1 + 2 * d.hs;
+    s = tfma(o2[e], x[nb[4]], s);
+    s = tfma(o2[nb[5]], x[nb[5]], s);
   }
   return s;
 }
 
-// Colour `color` of a red-black Gauss-Seidel sweep over level d by threads
-// t = 0 .. nth-1, K colour slots per thread at a time.  A thread computes
-// the new values of its K cells before storing any of them: within a
-// colour no update reads another, so no load waits for a store.  MODE 1:
-// the first sweep from a zero iterate (x = b / diag on this colour; the
-// neighbour sum vanishes, so the other colour need not be cleared);
-// MODE 2: neighbours read with the coarse correction added (the first
-// post-smoothing sweep: a Gauss-Seidel update does not read the cell's own
-// old value, and the next sweep recomputes the other colour, so no separate
-// prolongation pass is needed).
-template <typename T, int DIM, int K, int MODE>
-__device__ inline void tail_colour(T* sm, const TLev& d, int color, int t, int nth, const TLev& C) {
+// A thread's colour slot on a level: the elements of its cell and of the
+// cell's neighbours for either colour the slot is swept in, computed once
+// per level visit; ok bit c: the slot holds a cell in colour c (the last
+// slot of a row of odd length does not in one colour; a slot past the end
+// holds none); par: the element, on the coarse level, of the parent of the
+// slot's colour-0 cell.
+template <int DIM>
+struct Slot {
+  int el[2];
+  int nb[2][6];
+  int par;
+  unsigned ok;
+};
+
+template <int DIM>
+__device__ inline void slot_make(const TLev& d, int h, Slot<DIM>& s, const TLev* C) {
+  s.ok = 0;
+  if (h < d.hc) s.ok = 3;
+  else h = 0;
+  const int row = qdiv(h, d.hw, d.rhw);
+  const int m = h - row * d.hw;
+  int j = row, k = 0;
+  if (DIM == 3) {
+    k = qdiv(row, d.n1, d.r1);
+    j = row - k * d.n1;
+  }
+  const int pr = (j + k) & 1;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    int i = 2 * m + (c ^ pr);
+    if (i >= d.n0) {
+      s.ok &= ~(1u << c);
+      i = d.n0 - 1;
+    }
+    s.el[c] = c * d.hs + h;
+    rb_nbrs<DIM>(d, i, j, k, s.nb[c]);
+    if (c == 0 && C) s.par = rb_el(*C, i >> 1, j >> 1, k >> 1);
+  }
+}
+
+// One colour C of a red-black Gauss-Seidel sweep over the slots of this
+// thread.  A thread computes the new values of all its cells before storing
+// any: within a colour no update reads another, so no load waits for a
+// store.  FIRST: the first sweep from a zero iterate, x = b / diag on this
+// colour (the neighbour sum vanishes, so nothing needs clearing first).
+template <typename T, int DIM, int K, int C, bool FIRST>
+__device__ inline void rb_colour(T* sm, const TLev& d, const Slot<DIM> (&sl)[K]) {
   T* x = sm + d.xb;
-  const T* b = x + d.np;
-  const T* di = sm + d.cb + d.np;
-  for (int h0 = t; h0 < d.hc; h0 += K * nth) {
+  const T* b = x + 2 * d.hs;
+  const T* di = sm + d.cb + 2 * d.hs;
+  T nv[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int e = sl[u].el[C];
+    if (FIRST)
+      nv[u] = b[e] * di[e];
+    else
+      nv[u] = (b[e] - rb_nsum<T, DIM>(sm, d, e, sl[u].nb[C])) * di[e];
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u)
+    if ((sl[u].ok >> C) & 1) x[sl[u].el[C]] = nv[u];
+}
+
+// Pre-smoothing of level d (nu1 sweeps, colour 0 then 1, from zero) and
+// the restriction of its residual into the right-hand side of C: the
+// residual of the colour swept last vanishes (up to rounding) after a
+// Gauss-Seidel sweep, so only the colour-0 children are summed.
+template <typename T, int DIM, int K, typename Sync>
+__device__ inline void rb_pre(T* sm, const TLev& d, const TLev& C, int nu1, int t, int nth, Sync sync) {
+  Slot<DIM> sl[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) slot_make<DIM>(d, t + u * nth, sl[u], nullptr);
+  const bool act = t < d.hc;
+  if (act) rb_colour<T, DIM, K, 0, true>(sm, d, sl);
+  sync();
+  if (act) rb_colour<T, DIM, K, 1, false>(sm, d, sl);
+  sync();
+  for (int s = 1; s < nu1; ++s) {
+    if (act) rb_colour<T, DIM, K, 0, false>(sm, d, sl);
+    sync();
+    if (act) rb_colour<T, DIM, K, 1, false>(sm, d, sl);
+    sync();
+  }
+  // restriction: coarse cells I = t, t + nth, ... in natural order
+  const T* x = sm + d.xb;
+  const T* b = x + 2 * d.hs;
+  const T* dg = sm + d.cb;
+  T* bc = sm + C.xb + 2 * C.hs;
+  for (int I = t; I < C.N; I += nth) {
+    int ci, cj, ck;
+    cell_of<DIM>(C, I, ci, cj, ck);
+    T sum = 0;
+    // (two children at a time, for the registers in 3D)
+#pragma unroll 2
+    for (int ch = 0; ch < (DIM == 3 ? 4 : 2); ++ch) {
+      // colour-0 children: (0,0,0), (1,1,0), then in 3D (1,0,1), (0,1,1)
+      const int di_ = (ch == 1 || ch == 2) ? 1 : 0;
+      const int dj_ = (ch == 1 || ch == 3) ? 1 : 0;
+      const int dk_ = ch >= 2 ? 1 : 0;
+      int i = 2 * ci + di_, j = 2 * cj + dj_, k = 2 * ck + dk_;
+      const bool in = i < d.n0 && j < d.n1 && k < d.n2;
+      i = i < d.n0 ? i : d.n0 - 1;
+      j = j < d.n1 ? j : d.n1 - 1;
+      k = k < d.n2 ? k : d.n2 - 1;
+      int nb[6];
+      rb_nbrs<DIM>(d, i, j, k, nb);
+      const int e = rb_el(d, i, j, k);
+      const T r = b[e] - dg[e] * x[e] - rb_nsum<T, DIM>(sm, d, e, nb);
+      sum = in ? sum + r : sum;
+    }
+    bc[rb_el(C, ci, cj, ck)] = sum;
+  }
+  sync();
+}
+
+// Post-smoothing of level d after the coarse level C: the correction of C
+// added to the colour-0 cells (the only ones the first sweep, colour 1,
+// reads; colour 1 is recomputed from them and colour 0 again after it, so
+// neither needs the correction itself), then nu2 sweeps, colour 1 then 0.
+template <typename T, int DIM, int K, typename Sync>
+__device__ inline void rb_post(T* sm, const TLev& d, const TLev& C, int nu2, int t, int nth, Sync sync) {
+  Slot<DIM> sl[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) slot_make<DIM>(d, t + u * nth, sl[u], &C);
+  const bool act = t < d.hc;
+  if (act) {
+    T* x = sm + d.xb;
+    const T* xc = sm + C.xb;
     T nv[K];
-    int qs[K];
-    bool ok[K];
 #pragma unroll
-    for (int u = 0; u < K; ++u) {
-      int h = h0 + u * nth;
-      ok[u] = h < d.hc;
-      if (!ok[u]) h = h0;
-      const int row = qdiv(h, d.hw, d.rhw);
-      const int m = h - row * d.hw;
-      int j = row, k = 0;
-      if (DIM == 3) {
-        k = qdiv(row, d.n1, d.r1);
-        j = row - k * d.n1;
-      }
-      int i = 2 * m + ((j + k + color) & 1);
-      ok[u] = ok[u] && i < d.n0;
-      if (i >= d.n0) i = d.n0 - 1;
-      const int q = i + d.n0 * row;
-      qs[u] = q;
-      if (MODE == 1)
-        nv[u] = b[q] * di[q];
-      else
-        nv[u] = (b[q] - tail_nsum<T, DIM, MODE == 2>(sm, d, i, j, k, q, C)) * di[q];
-    }
+    for (int u = 0; u < K; ++u) nv[u] = x[sl[u].el[0]] + xc[sl[u].par];
 #pragma unroll
     for (int u = 0; u < K; ++u)
-      if (ok[u]) x[qs[u]] = nv[u];
+      if (sl[u].ok & 1) x[sl[u].el[0]] = nv[u];
+  }
+  sync();
+  for (int s = 0; s < nu2; ++s) {
+    if (act) rb_colour<T, DIM, K, 1, false>(sm, d, sl);
+    sync();
+    if (act) rb_colour<T, DIM, K, 0, false>(sm, d, sl);
+    sync();
   }
 }
 
-// (four cells at a time only for FP32 in 2D: more would not fit the
-// registers of a 1024-thread work-group)
-template <typename T, int DIM, int MODE>
-__device__ inline void tail_colour_n(T* sm, const TLev& d, int color, int t, int nth, const TLev& C) {
-  constexpr bool wide = sizeof(T) == 4 && DIM == 2;
-  const int per = (d.hc + nth - 1) / nth;
-  if (per <= 1)
-    tail_colour<T, DIM, 1, MODE>(sm, d, color, t, nth, C);
-  else if (per <= 2 || !wide)
-    tail_colour<T, DIM, 2, MODE>(sm, d, color, t, nth, C);
-  else
-    tail_colour<T, DIM, wide ? 4 : 2, MODE>(sm, d, color, t, nth, C);
-}
-
-// Residual of the children of each cell of C, summed into C's right-hand
-// side (C's iterate is not cleared: its first sweep starts from zero by
-// construction).  Thread t (of nth) takes coarse cells t, t + nth, ..., K
-// at a time; a missing child of a ragged level is loaded at a clamped index
-// and dropped.
-template <typename T, int DIM, int K>
-__device__ inline void tail_restrict(T* sm, const TLev& L, const TLev& C, int t, int nth) {
-  const T* x = sm + L.xb;
-  const T* b = x + L.np;
-  const T* dg = sm + L.cb;
-  T* bc = sm + C.xb + C.np;
-  for (int I0 = t; I0 < C.N; I0 += K * nth) {
-    T acc[K];
-    int Is[K];
-    bool ok[K];
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      int I = I0 + u * nth;
-      ok[u] = I < C.N;
-      if (!ok[u]) I = I0;
-      Is[u] = I;
-      int ci, cj, ck;
-      cell_of<DIM>(C, I, ci, cj, ck);
-      T sum = 0;
-      // (in 3D one plane of four children at a time, for the registers)
-#pragma unroll 1
-      for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
-#pragma unroll
-        for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-          for (int di = 0; di < 2; ++di) {
-            int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
-            const bool in = i < L.n0 && j < L.n1 && k < L.n2;
-            i = i < L.n0 ? i : L.n0 - 1;
-            j = j < L.n1 ? j : L.n1 - 1;
-            k = k < L.n2 ? k : L.n2 - 1;
-            const int q = i + L.n0 * (j + L.n1 * k);
-            const T r = b[q] - dg[q] * x[q] - tail_nsum<T, DIM, false>(sm, L, i, j, k, q, C);
-            sum = in ? sum + r : sum;
-          }
-      acc[u] = sum;
-    }
-#pragma unroll
-    for (int u = 0; u < K; ++u)
-      if (ok[u]) bc[Is[u]] = acc[u];
-  }
-}
-
+// colour slots per thread at most: two in FP32, one in FP64 (what the
+// registers of a 1024-thread work-group hold; the levels that LDS can take
+// need no more)
 template <typename T, int DIM>
-__device__ inline void tail_restrict_n(T* sm, const TLev& L, const TLev& C, int t, int nth) {
-  const int per = (C.N + nth - 1) / nth;
-  if (per <= 1 || DIM == 3 || sizeof(T) == 8)
-    tail_restrict<T, DIM, 1>(sm, L, C, t, nth);
+__host__ __device__ constexpr int tail_kmax() {
+  return sizeof(T) == 4 ? 2 : 1;
+}
+
+template <typename T, int DIM, typename Sync>
+__device__ inline void tail_pre(T* sm, const TLev& d, const TLev& C, int nu1, int t, int nth, Sync sync) {
+  if (tail_kmax<T, DIM>() == 1 || d.hc <= nth)
+    rb_pre<T, DIM, 1>(sm, d, C, nu1, t, nth, sync);
   else
-    tail_restrict<T, DIM, 2>(sm, L, C, t, nth);
+    rb_pre<T, DIM, tail_kmax<T, DIM>()>(sm, d, C, nu1, t, nth, sync);
+}
+
+template <typename T, int DIM, typename Sync>
+__device__ inline void tail_post(T* sm, const TLev& d, const TLev& C, int nu2, int t, int nth, Sync sync) {
+  if (tail_kmax<T, DIM>() == 1 || d.hc <= nth)
+    rb_post<T, DIM, 1>(sm, d, C, nu2, t, nth, sync);
+  else
+    rb_post<T, DIM, tail_kmax<T, DIM>()>(sm, d, C, nu2, t, nth, sync);
 }
 
 // ---- the smallest tail levels by one wavefront ----------------------------
-// Levels of at most EBIT_TAIL_WAVE_CELLS cells are processed by wave 0 alone:
-// its lanes synchronise through wave-scope fences instead of work-group
-// barriers (LDS operations of one wave complete in order).
-#define EBIT_TAIL_WAVE_CELLS 512
-
+// Levels of at most tail_kmax x 64 slots per colour are processed by wave 0
+// alone: its lanes synchronise through wave-scope fences instead of
+// work-group barriers (LDS operations of one wave complete in order).
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Smoothing on level L before (pre) or after (post) the coarse level C, by
-// threads t of nth; sync() after every colour.
-template <typename T, int DIM, typename Sync>
-__device__ inline void tail_pre(T* sm, const TLev& L, const TLev& C, int nu1, int t, int nth, Sync sync) {
-  tail_colour_n<T, DIM, 1>(sm, L, 0, t, nth, C);
-  sync();
-  tail_colour_n<T, DIM, 0>(sm, L, 1, t, nth, C);
-  sync();
-  for (int s = 1; s < nu1; ++s)
-    for (int col = 0; col < 2; ++col) {
-      tail_colour_n<T, DIM, 0>(sm, L, col, t, nth, C);
-      sync();
-    }
-}
-
-template <typename T, int DIM, typename Sync>
-__device__ inline void tail_post(T* sm, const TLev& L, const TLev& C, int nu2, int t, int nth, Sync sync) {
-  tail_colour_n<T, DIM, 2>(sm, L, 1, t, nth, C);
-  sync();
-  tail_colour_n<T, DIM, 0>(sm, L, 0, t, nth, C);
-  sync();
-  for (int s = 1; s < nu2; ++s)
-    for (int col = 1; col >= 0; --col) {
-      tail_colour_n<T, DIM, 0>(sm, L, col, t, nth, C);
-      sync();
-    }
 }
 
 // V-cycle over tail levels l0 .. nl-1 by wave 0 (the rest of the work-group
@@ -1078,38 +1086,47 @@ __device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0, int nl, bo
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
     tail_pre<T, DIM>(sm, L, C, a.nu1, lane, 64, sync);
-    tail_restrict_n<T, DIM>(sm, L, C, lane, 64);
-    wave_sync();
   }
   const TLev L = tlev(a.L[nl - 1]);
   T* x = sm + L.xb;
-  const T* b = x + L.np;
+  const T* b = x + 2 * L.hs;
   if (dense) {
-    // coarsest level solved exactly: x = A^-1 b, lane t forming row t
+    // coarsest level solved exactly, x = A^-1 b with the inverse in natural
+    // order: lane t gathers b of cell t, then forms row t
+    T* tb = sm + a.tmp;
     const T* inv = sm + a.inv;
+    int e = 0;
+    if (lane < L.N) {
+      int i, j, k;
+      cell_of<DIM>(L, lane, i, j, k);
+      e = rb_el(L, i, j, k);
+      tb[lane] = b[e];
+    }
+    wave_sync();
     T acc = 0;
     if (lane < L.N) {
 #pragma unroll 8
-      for (int j = 0; j < L.N; ++j) acc = tfma(inv[j * L.N + lane], b[j], acc);
+      for (int j = 0; j < L.N; ++j) acc = tfma(inv[j * L.N + lane], tb[j], acc);
+      x[e] = acc;
     }
-    wave_sync();
-    if (lane < L.N) x[lane] = acc;
     wave_sync();
   } else {
     // coarsest level: symmetric Gauss-Seidel from zero by one lane (exact
     // for one cell)
-    for (int q = lane; q < L.N; q += 64) x[q] = (T)0;
+    for (int q = lane; q < 2 * L.hs; q += 64) x[q] = (T)0;
     wave_sync();
     if (lane == 0) {
-      const T* di = sm + L.cb + L.np;
+      const T* di = sm + L.cb + 2 * L.hs;
       const int sweeps = L.N == 1 ? 1 : 50;
       for (int s = 0; s < sweeps; ++s)
         for (int dir = 0; dir < 2; ++dir)
           for (int qq = 0; qq < L.N; ++qq) {
             const int q = dir ? (L.N - 1 - qq) : qq;
-            int i, j, k;
+            int i, j, k, nb[6];
             cell_of<DIM>(L, q, i, j, k);
-            x[q] = (b[q] - tail_nsum<T, DIM, false>(sm, L, i, j, k, q, L)) * di[q];
+            rb_nbrs<DIM>(L, i, j, k, nb);
+            const int e = rb_el(L, i, j, k);
+            x[e] = (b[e] - rb_nsum<T, DIM>(sm, L, e, nb)) * di[e];
           }
     }
     wave_sync();
@@ -1126,23 +1143,9 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nl = a.nl;
   {
-    // the top level's right-hand side, then the coefficient image suffix:
-    // all loads of a batch issue before any store (an index past the end is
-    // clamped to the batch's first, whose value it then stores again)
-    const TLev L = tlev(a.L[0]);
-    T* bt = sm + L.xb + L.np;
-    const T* bg = a.bg;
-    for (int q0 = tid; q0 < L.N; q0 += 4 * nth) {
-      int qi[4];
-      T v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        qi[u] = q0 + u * nth < L.N ? q0 + u * nth : q0;
-        v[u] = bg[qi[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) bt[qi[u]] = v[u];
-    }
+    // the coefficient image suffix: all loads of a batch issue before any
+    // store (an index past the end is clamped to the batch's first, whose
+    // value it then stores again)
     const u32x4* src = reinterpret_cast<const u32x4*>(a.img);
     u32x4* dst = reinterpret_cast<u32x4*>(sm);
     const int nv = a.cvec;
@@ -1157,6 +1160,33 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
 #pragma unroll
       for (int u = 0; u < TAIL_COPY_BATCH; ++u) dst[ei[u]] = v[u];
     }
+    // every level's iterate cleared: a sweep may name a cell not yet swept
+    // (across a wall, with a zero coupling; on a level of odd length the
+    // wrapped cell there has the sweep's own colour)
+    for (int l = 0; l < nl; ++l) {
+      T* x = sm + a.L[l].xb;
+      const int n = 2 * a.L[l].hs;
+      for (int q = tid; q < n; q += nth) x[q] = (T)0;
+    }
+    // the top level's right-hand side, from natural order
+    const TLev L = tlev(a.L[0]);
+    T* bt = sm + L.xb + 2 * L.hs;
+    const T* bg = a.bg;
+    for (int q0 = tid; q0 < L.N; q0 += 4 * nth) {
+      int qi[4];
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        qi[u] = q0 + u * nth < L.N ? q0 + u * nth : q0;
+        v[u] = bg[qi[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int i, j, k;
+        cell_of<DIM>(L, qi[u], i, j, k);
+        bt[rb_el(L, i, j, k)] = v[u];
+      }
+    }
   }
   __syncthreads();
   // with a usable inverse the V-cycle stops at its level
@@ -1164,14 +1194,12 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
   const int nle = dense ? a.dl + 1 : nl;
   // levels l0 .. nle-1 are small enough for one wavefront
   int l0 = nle - 1;
-  while (l0 > 0 && a.L[l0 - 1].d.N <= EBIT_TAIL_WAVE_CELLS) --l0;
+  while (l0 > 0 && tlev(a.L[l0 - 1]).hc <= tail_kmax<T, DIM>() * 64) --l0;
   auto sync = [] { __syncthreads(); };
   for (int l = 0; l < l0; ++l) {
     const TLev L = tlev(a.L[l]);
     const TLev C = tlev(a.L[l + 1]);
     tail_pre<T, DIM>(sm, L, C, a.nu1, tid, nth, sync);
-    tail_restrict_n<T, DIM>(sm, L, C, tid, nth);
-    __syncthreads();
   }
   if (tid < 64) tail_wave<T, DIM>(a, sm, l0, nle, dense);
   __syncthreads();
@@ -1184,7 +1212,11 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
     const TLev L = tlev(a.L[0]);
     const T* x = sm + L.xb;
     T* xg = a.xg;
-    for (int q = tid; q < L.N; q += nth) xg[q] = x[q];
+    for (int q = tid; q < L.N; q += nth) {
+      int i, j, k;
+      cell_of<DIM>(L, q, i, j, k);
+      xg[q] = x[rb_el(L, i, j, k)];
+    }
   }
 }
 
@@ -1202,19 +1234,21 @@ struct BuildOut {
   double* i64;
 };
 
-__device__ inline void store_built(const BuildOut& o, long long I, double M, double F, const double (&cross)[3]) {
+__device__ inline void store_built(const BuildOut& o, long long I, int ci, int cj, int ck, double M, double F,
+                                   const double (&cross)[3]) {
   const double dg = M + 0.5 * F;
-  const long long P = tail_pad(o.cd.N);
+  const long long hs = tail_half(o.cd), P = 2 * hs;
+  const long long e = tail_el(o.cd, hs, ci, cj, ck);
   o.diag[I] = dg;
   o.mass[I] = M;
   if (o.d32) o.d32[I] = (float)dg;
   if (o.i32) {
-    o.i32[I] = (float)dg;
-    o.i32[P + I] = 1.0f / (float)dg;
+    o.i32[e] = (float)dg;
+    o.i32[P + e] = 1.0f / (float)dg;
   }
   if (o.i64) {
-    o.i64[I] = dg;
-    o.i64[P + I] = 1.0 / dg;
+    o.i64[e] = dg;
+    o.i64[P + e] = 1.0 / dg;
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -1222,8 +1256,8 @@ __device__ inline void store_built(const BuildOut& o, long long I, double M, dou
       const double v = 0.5 * cross[a];
       o.off[a][I] = v;
       if (o.o32[a]) o.o32[a][I] = (float)v;
-      if (o.i32) o.i32[(2 + a) * P + I] = (float)v;
-      if (o.i64) o.i64[(2 + a) * P + I] = v;
+      if (o.i32) o.i32[(2 + a) * P + e] = (float)v;
+      if (o.i64) o.i64[(2 + a) * P + e] = v;
     }
 }
 
@@ -1261,7 +1295,7 @@ __device__ inline void build_cell_from_fine(const FineOp& op, const BuildOut& o,
       }
     }
   }
-  store_built(o, I, M, F, cross);
+  store_built(o, I, ci, cj, ck, M, F, cross);
 }
 
 // coarse cell I from the explicit level above
@@ -1298,7 +1332,7 @@ __device__ inline void build_cell_from_coarse(const CoarseOp<double>& op, const 
       }
     }
   }
-  store_built(o, I, M, F, cross);
+  store_built(o, I, ci, cj, ck, M, F, cross);
 }
 
 __global__ void k_build_from_fine(FineOp op, BuildOut o) {
@@ -2254,16 +2288,17 @@ int dense_level(const EbitLevelHost* lv, int nlev) {
 }
 
 // LDS elements of a tail from level lt down: the copied coefficient image
-// (with the dense inverse at its end) and x and b of every level.
+// (with the dense inverse at its end), x and b of every level, and the
+// dense solve's scratch.
 long long tail_lds_elems(const EbitLevelHost* lv, int nlev, int lt, long long* coef) {
   const int dl = dense_level(lv, nlev);
   long long c = dl >= 0 ? tail_pad(lv[dl].d.N * lv[dl].d.N) : 0, xb = 0;
   for (int l = lt; l < nlev; ++l) {
     c += tail_img_elems(lv[l].d);
-    xb += 2 * tail_pad(lv[l].d.N);
+    xb += 4 * tail_half(lv[l].d);
   }
   if (coef) *coef = c;
-  return c + xb;
+  return c + xb + EBIT_DENSE_MAX;
 }
 
 // First level (>= 1) of the tail: the levels from there down fit lds_bytes
@@ -2274,7 +2309,10 @@ int tail_start(const EbitLevelHost* lv, int nlev, int tail_cells, int lds_bytes)
   const int dl = dense_level(lv, nlev);
   int lt = nlev - 1;
   for (int l = nlev - 2; l >= 1; --l) {
-    if (lv[l].d.N > EBIT_TAIL_IMG_CELLS || nlev - l > EBIT_TAIL_MAX ||
+    // a work-group level: at most tail_kmax cells per thread and colour
+    const long long hc = (long long)((lv[l].d.n[0] + 1) / 2) * lv[l].d.n[1] * lv[l].d.n[2];
+    const int kmax = lv[l].d.dim == 2 ? tail_kmax<T, 2>() : tail_kmax<T, 3>();
+    if (lv[l].d.N > EBIT_TAIL_IMG_CELLS || nlev - l > EBIT_TAIL_MAX || hc > (long long)kmax * EBIT_TAIL_THREADS ||
         tail_lds_elems(lv, nlev, l, nullptr) * (long long)sizeof(T) > lds_bytes)
       break;
     if (lv[l].d.N > tail_cells && (dl < 0 || l < dl)) break;
@@ -2605,12 +2643,13 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       for (int m = 0; m < ta.nl; ++m) {
         const EbitLevelHost& L = pc.lv[lt[c] + m];
         ta.L[m].d = L.d;
-        ta.L[m].np = (int)tail_pad(L.d.N);
+        ta.L[m].hs = (int)tail_half(L.d);
         ta.L[m].cb = (int)cb;
         ta.L[m].xb = (int)xb;
         cb += tail_img_elems(L.d);
-        xb += 2 * tail_pad(L.d.N);
+        xb += 4 * tail_half(L.d);
       }
+      ta.tmp = (int)xb;
       const int dl = dense_level(pc.lv, pc.nlev);
       ta.dl = dl >= lt[c] ? dl - lt[c] : -1;
       ta.inv = (int)cb;
