@@ -56,8 +56,8 @@ def algorithmic_bytes_per_cell(kclass, precision, dim):
     agg = 2 ** dim
     if kclass == "fine_smooth":      # per full red-black sweep: read x, r (FP64), flags; write x
         return sx + 8 + 1 + sx
-    if kclass == "fine_restrict":    # read x, r, flags; write coarse b and clear coarse x
-        return sx + 8 + 1 + 2 * sx / agg
+    if kclass == "fine_restrict":    # read x (all cells), r and flags (colour-0 cells); write coarse b, clear coarse x
+        return sx + (8 + 1) / 2 + 2 * sx / agg
     if kclass == "outer_apply":      # read z, p_old, flags; write p_new and q (FP64)
         return sx + 8 + 1 + 8 + 8
     if kclass == "outer_update":     # read x, p, r, q; write x, r (FP64)

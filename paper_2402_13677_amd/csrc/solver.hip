@@ -755,6 +755,18 @@ constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 
                             ? (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 2>::QL)
                             : 4 * RB_PLANE;
 
+// Children (di, dj, dk) of a coarse cell whose fine cell has colour 0
+// ((i + j + k) even): (0,0,0), (1,1,0), then in 3D (1,0,1), (0,1,1).  Every
+// pre-smoothing sweep ends with colour 1, whose residual then vanishes up
+// to rounding (a Gauss-Seidel update zeroes its cell's residual and no
+// later update touches a neighbour of it), so the restricted residual is
+// the sum over these children alone.
+__device__ inline void even_child(int ch, int& di, int& dj, int& dk) {
+  di = (ch == 1 || ch == 2) ? 1 : 0;
+  dj = (ch == 1 || ch == 3) ? 1 : 0;
+  dk = ch >= 2 ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // tail of the V-cycle: every level small enough to sit in LDS, in one
 // work-group (no launch per smoothing sweep on the coarse levels).  The
@@ -993,10 +1005,8 @@ __device__ inline void rb_pre(T* sm, const TLev& d, const TLev& C, int nu1, int 
     // (two children at a time, for the registers in 3D)
 #pragma unroll 2
     for (int ch = 0; ch < (DIM == 3 ? 4 : 2); ++ch) {
-      // colour-0 children: (0,0,0), (1,1,0), then in 3D (1,0,1), (0,1,1)
-      const int di_ = (ch == 1 || ch == 2) ? 1 : 0;
-      const int dj_ = (ch == 1 || ch == 3) ? 1 : 0;
-      const int dk_ = ch >= 2 ? 1 : 0;
+      int di_, dj_, dk_;
+      even_child(ch, di_, dj_, dk_);
       int i = 2 * ci + di_, j = 2 * cj + dj_, k = 2 * ck + dk_;
       const bool in = i < d.n0 && j < d.n1 && k < d.n2;
       i = i < d.n0 ? i : d.n0 - 1;
@@ -1800,8 +1810,8 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
                                     reinterpret_cast<T(*)[RB_PLANE]>(buf));
 }
 
-// Residual of the 2^d children of every coarse cell of level 1, summed
-// (= P^T r); also clears the level-1 iterate.
+// Restricted residual (P^T r over the colour-0 children) of every coarse
+// cell of level 1; also clears the level-1 iterate.
 template <typename T>
 __global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
                                  int src_sel) {
@@ -1814,22 +1824,17 @@ __global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const Case
   const T* x = C.z[src_sel];
   T* bc = C.lb[1];
   T* xc = C.lx[1][0];
+  const int nch = op.d.dim == 3 ? 4 : 2;
   CASE_STRIDE(I, cd.N) {
     int ci, cj, ck;
     cell_ijk(cd, I, ci, cj, ck);
     T sum = 0;
-    for (int dk = 0; dk < 2; ++dk) {
-      const int k = 2 * ck + dk;
-      if (k >= op.d.n[2]) break;
-      for (int dj = 0; dj < 2; ++dj) {
-        const int j = 2 * cj + dj;
-        if (j >= op.d.n[1]) break;
-        for (int di = 0; di < 2; ++di) {
-          const int i = 2 * ci + di;
-          if (i >= op.d.n[0]) break;
-          sum += fine_residual_at<T, double>(op, i, j, k, cell_index(op.d, i, j, k), C.r, x);
-        }
-      }
+    for (int ch = 0; ch < nch; ++ch) {
+      int di, dj, dk;
+      even_child(ch, di, dj, dk);
+      const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+      if (i < op.d.n[0] && j < op.d.n[1] && k < op.d.n[2])
+        sum += fine_residual_at<T, double>(op, i, j, k, cell_index(op.d, i, j, k), C.r, x);
     }
     bc[I] = sum;
     xc[I] = (T)0;
@@ -1850,22 +1855,18 @@ __global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const Ca
   const T* x = C.lx[l][src_sel];
   T* bc = C.lb[l + 1];
   T* xc = C.lx[l + 1][0];
+  const int nch = op.d.dim == 3 ? 4 : 2;
   CASE_STRIDE(I, cd.N) {
     int ci, cj, ck;
     cell_ijk(cd, I, ci, cj, ck);
     T sum = 0;
-    for (int dk = 0; dk < 2; ++dk) {
-      const int k = 2 * ck + dk;
-      if (k >= op.d.n[2]) break;
-      for (int dj = 0; dj < 2; ++dj) {
-        const int j = 2 * cj + dj;
-        if (j >= op.d.n[1]) break;
-        for (int di = 0; di < 2; ++di) {
-          const int i = 2 * ci + di;
-          if (i >= op.d.n[0]) break;
-          const long long q = cell_index(op.d, i, j, k);
-          sum += b[q] - op.diag[q] * x[q] - coarse_offsum<T>(op, i, j, k, q, x);
-        }
+    for (int ch = 0; ch < nch; ++ch) {
+      int di, dj, dk;
+      even_child(ch, di, dj, dk);
+      const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+      if (i < op.d.n[0] && j < op.d.n[1] && k < op.d.n[2]) {
+        const long long q = cell_index(op.d, i, j, k);
+        sum += b[q] - op.diag[q] * x[q] - coarse_offsum<T>(op, i, j, k, q, x);
       }
     }
     bc[I] = sum;
@@ -2269,13 +2270,16 @@ double* zb<double>(const EbitSolveBufs& B, int s) { return s ? B.z64b : B.z64; }
 template <>
 float* zb<float>(const EbitSolveBufs& B, int s) { return s ? B.z32b : B.z32; }
 
-// z-chunk of a 64 x 8-tiled sweep: enough work-groups to fill the chip, at
-// most 32 planes each
+// z-chunk of a 64 x 8-tiled sweep: about 16 work-groups per compute unit,
+// at most 32 planes each.  Work-groups that hold interface cells run
+// longer (their rows are assembled from the cut fractions); with several
+// rounds of short work-groups the others fill in around them, which more
+// than pays for the re-read planes at the chunk ends.
 int rb_zchunk(const Dims& d) {
   if (d.dim < 3) return 1;
   const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
   int zc = 32;
-  while (zc > 4 && tiles * ((d.n[2] + zc - 1) / zc) < 1024) zc >>= 1;
+  while (zc > 4 && tiles * ((d.n[2] + zc - 1) / zc) < 4096) zc >>= 1;
   return zc;
 }
 
