@@ -194,6 +194,15 @@ struct CoarseOp {
 };
 
 __device__ inline void cell_ijk(const Dims& d, long long c, int& i, int& j, int& k) {
+  if (c < 0x7fffffffLL) {
+    // 32-bit division (a 64-bit one is a long emulated sequence)
+    const unsigned u = (unsigned)c, n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
+    const unsigned r = u / n0;
+    i = (int)(u - r * n0);
+    k = (int)(r / n1);
+    j = (int)(r - (unsigned)k * n1);
+    return;
+  }
   i = (int)(c % d.n[0]);
   j = (int)((c / d.n[0]) % d.n[1]);
   k = (int)(c / ((long long)d.n[0] * d.n[1]));

@@ -45,19 +45,38 @@ __global__ void k_fill(long long n, T* x, T v) {
 // ---------------------------------------------------------------------------
 // fine level (matrix-free)
 // ---------------------------------------------------------------------------
+// Cells across sides s = 0 .. 2 dim - 1 of cell c = (i, j, k) (side 2a is
+// the lower one along axis a, 2a + 1 the upper, as in neighbour()), wrapped
+// around every axis: the neighbour() cell where there is one; across a wall
+// some in-range cell, whose term the caller drops (fine_row gives a wall
+// side a zero coupling).  Lets a kernel issue the neighbour loads together
+// with the flag byte instead of after fine_row has read it.
+__device__ inline void fine_nbrs(const Dims& d, int i, int j, int k, long long c, long long (&m)[6]) {
+  const long long s1 = d.n[0], s2 = (long long)d.n[0] * d.n[1];
+  m[0] = i > 0 ? c - 1 : c - 1 + d.n[0];
+  m[1] = i + 1 < d.n[0] ? c + 1 : c + 1 - d.n[0];
+  m[2] = j > 0 ? c - s1 : c - s1 + s2;
+  m[3] = j + 1 < d.n[1] ? c + s1 : c + s1 - s2;
+  m[4] = k > 0 ? c - s2 : c - s2 + d.N;
+  m[5] = k + 1 < d.n[2] ? c + s2 : c + s2 - d.N;
+}
+
 template <typename T, typename TB>
 __device__ inline T fine_residual_at(const FineOp& op, int i, int j, int k, long long c, const TB* b,
                                      const T* x) {
+  long long m[6];
+  fine_nbrs(op.d, i, j, k, c, m);
+  T xn[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) xn[q] = (q < 2 * op.d.dim) ? x[m[q]] : (T)0;
+  const T xc = x[c];
+  const T bc = (T)b[c];
   T diag, off[6], mass, rb = 0;
   fine_row<T>(op, i, j, k, op.flags[c], diag, off, mass, rb);
-  T s = (T)b[c] - diag * x[c];
+  T s = bc - diag * xc;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    if (q >= 2 * op.d.dim || off[q] == (T)0) continue;
-    int ni, nj, nk;
-    neighbour(op.d, i, j, k, q, ni, nj, nk);
-    s -= off[q] * x[cell_index(op.d, ni, nj, nk)];
-  }
+  for (int q = 0; q < 6; ++q)
+    if (q < 2 * op.d.dim && off[q] != (T)0) s -= off[q] * xn[q];
   return s;
 }
 
@@ -1945,19 +1964,21 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   CASE_STRIDE(i0, op.d.N) {
     int i, j, k;
     cell_ijk(op.d, i0, i, j, k);
+    // the direction at the cell and its neighbours, loaded before the row
+    // is assembled (see fine_nbrs)
+    long long m[6];
+    fine_nbrs(op.d, i, j, k, i0, m);
+    double pn[6];
+#pragma unroll
+    for (int qq = 0; qq < 6; ++qq)
+      pn[qq] = qq < 2 * op.d.dim ? (first ? (double)z[m[qq]] : (double)z[m[qq]] + beta * p_old[m[qq]]) : 0.0;
+    const double pc = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
     double diag, off[6], mass, rb = 0, mx;
     fine_row<double>(op, i, j, k, op.flags[i0], diag, off, mass, rb, &mx);
-    const double pc = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
     double s = mx * pc;
 #pragma unroll
-    for (int qq = 0; qq < 6; ++qq) {
-      if (qq >= 2 * op.d.dim || off[qq] == 0.0) continue;
-      int ni, nj, nk;
-      neighbour(op.d, i, j, k, qq, ni, nj, nk);
-      const long long m = cell_index(op.d, ni, nj, nk);
-      const double pm = first ? (double)z[m] : (double)z[m] + beta * p_old[m];
-      s -= off[qq] * (pc - pm);
-    }
+    for (int qq = 0; qq < 6; ++qq)
+      if (qq < 2 * op.d.dim && off[qq] != 0.0) s -= off[qq] * (pc - pn[qq]);
     p_new[i0] = pc;
     q[i0] = s;
     v[0] += pc * s;
