@@ -87,36 +87,44 @@ __global__ void k_check_seam_vertices(GeoArgs g) {
   }
 }
 
-// Smallest-eigenvalue eigenvector of a symmetric m x m matrix (m = 2 or 3) by
-// cyclic Jacobi rotations.
-__device__ inline void min_eigvec(double A[3][3], int m, double v[3]) {
+// Smallest-eigenvalue eigenvector of a symmetric M x M matrix (M = 2 or 3)
+// by cyclic Jacobi rotations.
+template <int M>
+__device__ inline void min_eigvec(double A[3][3], double v[3]) {
   double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   for (int sweep = 0; sweep < 32; ++sweep) {
     double offn = 0.0, tot = 0.0;
-    for (int p = 0; p < m; ++p)
-      for (int q = 0; q < m; ++q) {
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
         tot += A[p][q] * A[p][q];
         if (p != q) offn += A[p][q] * A[p][q];
       }
     if (offn <= 1e-36 * tot) break;
-    for (int p = 0; p < m - 1; ++p)
-      for (int q = p + 1; q < m; ++q) {
+#pragma unroll
+    for (int p = 0; p < M - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < M; ++q) {
         const double apq = A[p][q];
         if (apq == 0.0) continue;
         const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
         const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
-        for (int r = 0; r < m; ++r) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
           const double arp = A[r][p], arq = A[r][q];
           A[r][p] = c * arp - s * arq;
           A[r][q] = s * arp + c * arq;
         }
-        for (int r = 0; r < m; ++r) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
           const double apr = A[p][r], aqr = A[q][r];
           A[p][r] = c * apr - s * aqr;
           A[q][r] = s * apr + c * aqr;
         }
-        for (int r = 0; r < m; ++r) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
           const double vrp = V[r][p], vrq = V[r][q];
           V[r][p] = c * vrp - s * vrq;
           V[r][q] = s * vrp + c * vrq;
@@ -124,57 +132,96 @@ __device__ inline void min_eigvec(double A[3][3], int m, double v[3]) {
       }
   }
   int best = 0;
-  for (int p = 1; p < m; ++p)
-    if (A[p][p] < A[best][best]) best = p;
-  for (int r = 0; r < 3; ++r) v[r] = (r < m) ? V[r][best] : 0.0;
+#pragma unroll
+  for (int p = 1; p < M; ++p)
+    if (A[p][p] < (best == 0 ? A[0][0] : A[1][1])) best = p;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) v[r] = (r < M) ? (best == 0 ? V[r][0] : best == 1 ? V[r][1] : V[r][2]) : 0.0;
+}
+
+// Cell corner at which slot (a, o) of a cell's edge markers sits: the edge
+// along axis a, offset by o & 1 along the first other axis and by o >> 1
+// along the second (3D), in increasing axis order.
+__device__ inline void slot_corner(int a, int o, int i, int j, int k, int dim, int& q0, int& q1, int& q2) {
+  const int ob = o & 1, oc = o >> 1;
+  q0 = i;
+  q1 = j;
+  q2 = k;
+  if (a == 0) {
+    q1 += ob;
+    if (dim == 3) q2 += oc;
+  } else if (a == 1) {
+    q0 += ob;
+    if (dim == 3) q2 += oc;
+  } else {
+    q0 += ob;
+    q1 += oc;
+  }
 }
 
 // Facet of every interface cell; writes flags = liquid bit | interface bit.
+// The markers of the cell's edges are gathered into slot a * 4 + o (NaN: no
+// marker, or no such slot) with every index known at compile time, so a
+// cell without markers (almost all of them) finishes from registers.
 __global__ void k_facets(GeoArgs g) {
   const Dims& d = g.d;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
-  const int i = (int)(c % d.n[0]);
-  const int j = (int)((c / d.n[0]) % d.n[1]);
-  const int k = (int)(c / ((long long)d.n[0] * d.n[1]));
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
   const double h = g.h;
-  double P[12][3];
-  int cnt = 0;
   const int noff = (d.dim == 3) ? 4 : 2;
-  for (int a = 0; a < d.dim; ++a) {
-    int oth[2];
-    int no = 0;
-    for (int b = 0; b < d.dim; ++b)
-      if (b != a) oth[no++] = b;
-    for (int o = 0; o < noff; ++o) {
-      const int ob = o & 1, oc = o >> 1;
-      int q[3] = {i, j, k};
-      q[oth[0]] += ob;
-      if (d.dim == 3) q[oth[1]] += oc;
-      const double s = g.mk[a][eidx(d, a, q[0], q[1], q[2])];
-      if (isnan(s)) continue;
-      double pos[3] = {q[0] * h, q[1] * h, (d.dim == 3) ? q[2] * h : 0.0};
-      pos[a] = pos[a] + s * h;
-      P[cnt][0] = pos[0];
-      P[cnt][1] = pos[1];
-      P[cnt][2] = pos[2];
-      ++cnt;
+  double sv[12];
+  int cnt = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      double s = __builtin_nan("");
+      if (a < d.dim && o < noff) {
+        int q0, q1, q2;
+        slot_corner(a, o, i, j, k, d.dim, q0, q1, q2);
+        s = g.mk[a][eidx(d, a, q0, q1, q2)];
+      }
+      sv[a * 4 + o] = s;
+      cnt += isnan(s) ? 0 : 1;
     }
-  }
   const int need = (d.dim == 2) ? 2 : 3;
   const uint8_t liq = g.ccol[c] ? F_LIQ : 0;
   if (cnt < need) {
     g.flags[c] = liq;
     return;
   }
-  double cen[3] = {0, 0, 0};
-  for (int q = 0; q < cnt; ++q)
-    for (int r = 0; r < 3; ++r) cen[r] += P[q][r];
+  // marker points in slot order: centroid, and the first two (2D)
+  double cen[3] = {0, 0, 0}, p0[3] = {0, 0, 0}, p1[3] = {0, 0, 0};
+  double P[12][3];
+  int seen = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const double s = sv[a * 4 + o];
+      int q0, q1, q2;
+      slot_corner(a, o, i, j, k, d.dim, q0, q1, q2);
+      double pos[3] = {q0 * h, q1 * h, (d.dim == 3) ? q2 * h : 0.0};
+      pos[a] = pos[a] + s * h;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) P[a * 4 + o][r] = pos[r];
+      if (!isnan(s)) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          cen[r] += pos[r];
+          if (seen == 0) p0[r] = pos[r];
+          if (seen == 1) p1[r] = pos[r];
+        }
+        ++seen;
+      }
+    }
   for (int r = 0; r < 3; ++r) cen[r] = cen[r] / (double)cnt;
   double n[3] = {0, 0, 0};
   bool ok = false;
   if (d.dim == 2 && cnt == 2) {
-    const double dx = P[1][0] - P[0][0], dy = P[1][1] - P[0][1];
+    const double dx = p1[0] - p0[0], dy = p1[1] - p0[1];
     const double L = hypot(dx, dy);
     if (L > 0) {
       n[0] = -dy / L;
@@ -183,45 +230,65 @@ __global__ void k_facets(GeoArgs g) {
     }
   } else {
     double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int q = 0; q < cnt; ++q) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      if (isnan(sv[q])) continue;
       double x[3];
+#pragma unroll
       for (int r = 0; r < 3; ++r) x[r] = P[q][r] - cen[r];
+#pragma unroll
       for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int s2 = 0; s2 < 3; ++s2) C[r][s2] += x[r] * x[s2];
     }
     double mx = 0.0;
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
       for (int s2 = 0; s2 < 3; ++s2) mx = fmax(mx, fabs(C[r][s2]));
     if (mx > 0) {
-      min_eigvec(C, d.dim, n);
+      if (d.dim == 3)
+        min_eigvec<3>(C, n);
+      else
+        min_eigvec<2>(C, n);
       const double L = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
       for (int r = 0; r < 3; ++r) n[r] /= L;
       ok = true;
     }
   }
-  // corners, in the order (dk, dj, di)
+  // corners, in the order (dk, dj, di) (slots with dk = 1 unused in 2D)
   double gsum[3] = {0, 0, 0};
   double corner_pos[8][3];
   double corner_w[8];
-  int ncorner = 0;
-  for (int dk = 0; dk < (d.dim == 3 ? 2 : 1); ++dk)
+#pragma unroll
+  for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
     for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
       for (int di = 0; di < 2; ++di) {
-        const double col = (double)g.vcol[vidx(d, i + di, j + dj, k + dk)];
-        corner_pos[ncorner][0] = (i + di) * h;
-        corner_pos[ncorner][1] = (j + dj) * h;
-        corner_pos[ncorner][2] = (d.dim == 3) ? (k + dk) * h : 0.0;
-        corner_w[ncorner] = 2.0 * col - 1.0;
-        ++ncorner;
+        const int q = dk * 4 + dj * 2 + di;
+        const bool use = dk == 0 || d.dim == 3;
+        const double col = use ? (double)g.vcol[vidx(d, i + di, j + dj, k + dk)] : 0.0;
+        corner_pos[q][0] = (i + di) * h;
+        corner_pos[q][1] = (j + dj) * h;
+        corner_pos[q][2] = (d.dim == 3) ? (k + dk) * h : 0.0;
+        corner_w[q] = 2.0 * col - 1.0;
       }
+  const int ncorner = d.dim == 3 ? 8 : 4;
   if (!ok) {
-    for (int q = 0; q < ncorner; ++q)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q >= ncorner) continue;
+#pragma unroll
       for (int r = 0; r < 3; ++r) gsum[r] += corner_w[q] * (corner_pos[q][r] - cen[r]);
+    }
     const double L = sqrt(gsum[0] * gsum[0] + gsum[1] * gsum[1] + gsum[2] * gsum[2]);
     for (int r = 0; r < 3; ++r) n[r] = gsum[r] / L;
   }
   double s = 0.0;
-  for (int q = 0; q < ncorner; ++q) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (q >= ncorner) continue;
     const double dot = n[0] * (corner_pos[q][0] - cen[0]) + n[1] * (corner_pos[q][1] - cen[1]) +
                        n[2] * (corner_pos[q][2] - cen[2]);
     s += corner_w[q] * dot;

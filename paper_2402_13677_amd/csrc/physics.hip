@@ -33,10 +33,12 @@ struct FluxArgs {
 
 // T of phase k at cell (i,j,k) (periodic wrap), from the cell itself or its
 // ghost value (mean of Eq. ghost_T over its cut links); false if unavailable.
+template <int DIM>
 __device__ inline bool value_k(const FluxArgs& g, int kph, int i, int j, int k, double& v) {
   const Dims& d = g.d;
   int q[3] = {i, j, k};
-  for (int a = 0; a < d.dim; ++a) {
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
     if (q[a] < 0 || q[a] >= d.n[a]) {
       if (!d.per[a]) return false;
       q[a] = ((q[a] % d.n[a]) + d.n[a]) % d.n[a];
@@ -51,7 +53,8 @@ __device__ inline bool value_k(const FluxArgs& g, int kph, int i, int j, int k, 
   }
   double acc = 0.0;
   int cnt = 0;
-  for (int s = 0; s < 2 * d.dim; ++s) {
+#pragma unroll
+  for (int s = 0; s < 2 * DIM; ++s) {
     if (!((f >> s) & 1)) continue;
     int ni, nj, nk;
     neighbour(d, q[0], q[1], q[2], s, ni, nj, nk);
@@ -74,16 +77,22 @@ __device__ inline void lagrange3(double t, double w[3]) {
   w[2] = 0.5 * t * (t + 1.0);
 }
 
+template <int DIM>
 __device__ inline void clamp_block(const FluxArgs& g, int ctr[3]) {
-  for (int a = 0; a < g.d.dim; ++a)
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
     if (!g.d.per[a]) ctr[a] = min(max(ctr[a], 1), g.d.n[a] - 2);
 }
 
+template <int DIM>
 __device__ inline bool interp_block(const FluxArgs& g, int kph, const double P[3], const int ctr[3], double& out) {
   const double h = g.h;
+  // Lagrange weights per axis as scalars (picked by selects below, so the
+  // stencil loop indexes no local array)
   double w[3][3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (a < g.d.dim) {
+    if (a < DIM) {
       const double t = (P[a] - (ctr[a] + 0.5) * h) / h;
       lagrange3(t, w[a]);
     } else {
@@ -93,47 +102,68 @@ __device__ inline bool interp_block(const FluxArgs& g, int kph, const double P[3
     }
   }
   double tot = 0.0;
-  const int kr = (g.d.dim == 3) ? 1 : 0;
-  for (int dk = -kr; dk <= kr; ++dk)
-    for (int dj = -1; dj <= 1; ++dj)
+  constexpr int kr = (DIM == 3) ? 1 : 0;
+#pragma unroll 1
+  for (int dk = -kr; dk <= kr; ++dk) {
+    const double wz = dk < 0 ? w[2][0] : (dk == 0 ? w[2][1] : w[2][2]);
+#pragma unroll 1
+    for (int dj = -1; dj <= 1; ++dj) {
+      const double wy = dj < 0 ? w[1][0] : (dj == 0 ? w[1][1] : w[1][2]);
+#pragma unroll 1
       for (int di = -1; di <= 1; ++di) {
+        const double wx = di < 0 ? w[0][0] : (di == 0 ? w[0][1] : w[0][2]);
         double v;
-        if (!value_k(g, kph, ctr[0] + di, ctr[1] + dj, ctr[2] + dk, v)) return false;
-        tot += w[0][di + 1] * w[1][dj + 1] * w[2][dk + 1] * v;
+        if (!value_k<DIM>(g, kph, ctr[0] + di, ctr[1] + dj, ctr[2] + dk, v)) return false;
+        tot += wx * wy * wz * v;
       }
+    }
+  }
   out = tot;
   return true;
 }
 
+template <int DIM>
 __device__ inline bool point_value(const FluxArgs& g, int kph, const double P[3], const double sd[3], double& v) {
   int ctr[3] = {0, 0, 0};
-  for (int a = 0; a < g.d.dim; ++a) ctr[a] = (int)floor(P[a] / g.h);
-  clamp_block(g, ctr);
-  if (interp_block(g, kph, P, ctr, v)) return true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) ctr[a] = (int)floor(P[a] / g.h);
+  clamp_block<DIM>(g, ctr);
+  if (interp_block<DIM>(g, kph, P, ctr, v)) return true;
+  // step the block one cell along the dominant direction component
   int am = 0;
-  for (int a = 1; a < g.d.dim; ++a)
-    if (fabs(sd[a]) > fabs(sd[am])) am = a;
-  ctr[am] += (sd[am] > 0) ? 1 : -1;
-  clamp_block(g, ctr);
-  return interp_block(g, kph, P, ctr, v);
+#pragma unroll
+  for (int a = 1; a < DIM; ++a)
+    if (fabs(sd[a]) > fabs(am == 0 ? sd[0] : sd[1])) am = a;
+  const int step = (am == 0 ? sd[0] : am == 1 ? sd[1] : sd[2]) > 0 ? 1 : -1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (a == am) ctr[a] += step;
+  clamp_block<DIM>(g, ctr);
+  return interp_block<DIM>(g, kph, P, ctr, v);
 }
 
 // first-order fallback from the nearest phase-k centre around P1
+template <int DIM>
 __device__ inline double fallback_grad(const FluxArgs& g, int kph, const double cF[3], const double sd[3],
                                        const double P1[3]) {
   const Dims& d = g.d;
   const double h = g.h;
   int ctr[3] = {0, 0, 0};
-  for (int a = 0; a < d.dim; ++a) ctr[a] = (int)floor(P1[a] / h);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) ctr[a] = (int)floor(P1[a] / h);
   double best_d = 0.0, best_p = 0.0, best_T = 0.0;
   long long best_c = -1;
-  const int kr = (d.dim == 3) ? 1 : 0;
+  constexpr int kr = (DIM == 3) ? 1 : 0;
+#pragma unroll 1
   for (int dk = -kr; dk <= kr; ++dk)
+#pragma unroll 1
     for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll 1
       for (int di = -1; di <= 1; ++di) {
         int q[3] = {ctr[0] + di, ctr[1] + dj, ctr[2] + dk};
         bool ok = true;
-        for (int a = 0; a < d.dim; ++a)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
           if (q[a] < 0 || q[a] >= d.n[a]) {
             if (d.per[a])
               q[a] = ((q[a] % d.n[a]) + d.n[a]) % d.n[a];
@@ -160,6 +190,7 @@ __device__ inline double fallback_grad(const FluxArgs& g, int kph, const double 
   return (best_T - g.Tsat) / best_p;
 }
 
+template <int DIM>
 __global__ void k_mass_flux(FluxArgs g) {
   const Dims& d = g.d;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,6 +209,7 @@ __global__ void k_mass_flux(FluxArgs g) {
   const double d1 = h, d2 = 2.0 * h;
   double D[2];
   int fb = 0;
+#pragma unroll
   for (int kk = 0; kk < 2; ++kk) {
     const int kph = kk == 0 ? 1 : 0;  // liquid first, as the oracle does
     const double sg = kph ? 1.0 : -1.0;
@@ -188,13 +220,13 @@ __global__ void k_mass_flux(FluxArgs g) {
       P2[r] = cF[r] + d2 * sd[r];
     }
     double T1, T2;
-    const bool ok1 = point_value(g, kph, P1, sd, T1);
-    const bool ok2 = ok1 && point_value(g, kph, P2, sd, T2);
+    const bool ok1 = point_value<DIM>(g, kph, P1, sd, T1);
+    const bool ok2 = ok1 && point_value<DIM>(g, kph, P2, sd, T2);
     if (ok1 && ok2) {
       D[kph] = (d2 / d1 * (T1 - g.Tsat) - d1 / d2 * (T2 - g.Tsat)) / (d2 - d1);
     } else {
       ++fb;
-      D[kph] = fallback_grad(g, kph, cF, sd, P1);
+      D[kph] = fallback_grad<DIM>(g, kph, cF, sd, P1);
     }
   }
   g.mdot[c] = (g.lam[1] * D[1] + g.lam[0] * D[0]) / g.h_lg;
@@ -417,7 +449,10 @@ extern "C" hipError_t ebit_launch_mass_flux(const Dims* d, double h, const doubl
   g.T = T;
   g.mdot = mdot;
   g.scal = scal;
-  hipLaunchKernelGGL(k_mass_flux, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  if (d->dim == 3)
+    hipLaunchKernelGGL(k_mass_flux<3>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  else
+    hipLaunchKernelGGL(k_mass_flux<2>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   if (mface) hipLaunchKernelGGL(k_mass_flux_faces, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   return hipGetLastError();
 }
