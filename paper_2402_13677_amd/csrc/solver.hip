@@ -592,18 +592,18 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
 // every tile that needs them, so the tile ends exactly as after NSW
 // whole-grid sweeps.  One launch and one global-memory wait instead of NSW.
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int NSW>
+template <int TX, int TY, int NSW, int E = 0>
 struct Win2 {
-  static constexpr int H = 2 * NSW, QR = 2 * NSW - 1;
+  static constexpr int H = 2 * NSW + E, QR = 2 * NSW - 1 + E;
   static constexpr int PX = TX + 2 * H, PY = TY + 2 * H, PL = PX * PY;
   static constexpr int QX = TX + 2 * QR, QY = TY + 2 * QR, QL = QX * QY;
 };
 
 // one colour phase on the window [-ring, T+ring); cells outside a
 // non-periodic domain are not updated; upd(q, qq, iw, jw) does the cell
-template <int TX, int TY, int NSW, int RING, typename U>
+template <int TX, int TY, int NSW, int E, int RING, typename U>
 __device__ inline void phase2(const Dims& d, int tx0, int ty0, int color, const U& upd) {
-  using W = Win2<TX, TY, NSW>;
+  using W = Win2<TX, TY, NSW, E>;
   constexpr int HX = (TX + 2 * RING) / 2, WY = TY + 2 * RING;
   for (int t = threadIdx.x; t < HX * WY; t += RB_THREADS) {
     const int ly = t / HX - RING;
@@ -615,21 +615,49 @@ __device__ inline void phase2(const Dims& d, int tx0, int ty0, int color, const 
   }
 }
 
-template <int TX, int TY, int NSW, int P, typename U>
+template <int TX, int TY, int NSW, int E, int P, typename U>
 __device__ inline void phases2(const Dims& d, int tx0, int ty0, const U& upd) {
   if constexpr (P < 2 * NSW) {
-    phase2<TX, TY, NSW, 2 * NSW - 1 - P>(d, tx0, ty0, P & 1, upd);
+    phase2<TX, TY, NSW, E, 2 * NSW - 1 - P + E>(d, tx0, ty0, P & 1, upd);
     __syncthreads();
-    phases2<TX, TY, NSW, P + 1>(d, tx0, ty0, upd);
+    phases2<TX, TY, NSW, E, P + 1>(d, tx0, ty0, upd);
+  }
+}
+
+// Restriction fused into a tile's last pre-smoothing launch (2D): the
+// window then carries one more ring, so the last (black) phase also covers
+// ring 1 and the residual of every red cell of the tile is exact in LDS.
+// Tiles start at even coordinates, so the red children (0,0) and (1,1) of
+// each coarse cell of the tile lie in it; res(q, qq, i, j) gives a child's
+// residual from the window.
+template <typename T, int TX, int TY, int E, typename R>
+__device__ inline void restrict2(const Dims& d, const Dims& cd, int tx0, int ty0, int H, int PX, int QR, int QX,
+                                 T* __restrict__ bc, T* __restrict__ xcz, const R& res) {
+  constexpr int CX = TX / 2, CY = TY / 2;
+  for (int t = threadIdx.x; t < CX * CY; t += RB_THREADS) {
+    const int ci = tx0 / 2 + t % CX, cj = ty0 / 2 + t / CX;
+    if (ci >= cd.n[0] || cj >= cd.n[1]) continue;
+    T sum = 0;
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const int i = 2 * ci + ch, j = 2 * cj + ch;
+      if (i < d.n[0] && j < d.n[1]) {
+        const int lx = i - tx0, ly = j - ty0;
+        sum += res((ly + H) * PX + (lx + H), (ly + QR) * QX + (lx + QR), i, j);
+      }
+    }
+    const long long I = ci + (long long)cd.n[0] * cj;
+    bc[I] = sum;
+    xcz[I] = (T)0;
   }
 }
 
 // fine level, 2D
-template <typename T, int TX, int TY, int NSW>
+template <typename T, int TX, int TY, int NSW, int RES>
 __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
                                       const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
-                                      T* xs, double* rs, uint8_t* fs) {
-  using W = Win2<TX, TY, NSW>;
+                                      T* xs, double* rs, uint8_t* fs, T* __restrict__ bc, T* __restrict__ xcz) {
+  using W = Win2<TX, TY, NSW, RES>;
   const Dims& d = op.d;
   const RegularRow<T> rr = regular_row<T>(op);
   const int tx0 = bx * TX, ty0 = by * TY;
@@ -688,21 +716,35 @@ __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict
       xs[q] = sum / diag;
     }
   };
-  phases2<TX, TY, NSW, 0>(d, tx0, ty0, upd);
+  phases2<TX, TY, NSW, RES, 0>(d, tx0, ty0, upd);
   for (int t = threadIdx.x; t < TX * TY; t += RB_THREADS) {
     const int lx = t % TX, ly = t / TX;
     const int i = tx0 + lx, j = ty0 + ly;
     if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + W::H) * W::PX + (lx + W::H)];
   }
+  if constexpr (RES) {
+    // the fine residual r - A x of a child, as fine_residual_at forms it
+    auto res = [&](int q, int qq, int i, int j) {
+      T diag, off[6], mass, rb = 0;
+      fine_row<T>(op, i, j, 0, fs[qq], diag, off, mass, rb);
+      const T xn[4] = {xs[q - 1], xs[q + 1], xs[q - W::PX], xs[q + W::PX]};
+      T s = (T)rs[qq] - diag * xs[q];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (off[a] != (T)0) s -= off[a] * xn[a];
+      return s;
+    };
+    restrict2<T, TX, TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, res);
+  }
 }
 
 // explicit coarse level, 2D (couplings staged on the iterate's window: a
 // ring cell's lower couplings sit one cell further out)
-template <typename T, int NSW>
+template <typename T, int NSW, int RES>
 __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restrict__ b, const T* __restrict__ xin,
                                         const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
-                                        T* sb) {
-  using W = Win2<RB_TX, RB_TY, NSW>;
+                                        T* sb, T* __restrict__ bc, T* __restrict__ xcz) {
+  using W = Win2<RB_TX, RB_TY, NSW, RES>;
   const Dims& d = op.d;
   T* xs = sb;
   T* o0 = sb + W::PL;
@@ -760,18 +802,31 @@ __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restri
                   (o1[q - W::PX] * xs[q - W::PX] + o1[q] * xs[q + W::PX]);
     xs[q] = sum / dg[qc];
   };
-  phases2<RB_TX, RB_TY, NSW, 0>(d, tx0, ty0, upd);
+  phases2<RB_TX, RB_TY, NSW, RES, 0>(d, tx0, ty0, upd);
   for (int t = threadIdx.x; t < RB_TX * RB_TY; t += RB_THREADS) {
     const int lx = t % RB_TX, ly = t / RB_TX;
     const int i = tx0 + lx, j = ty0 + ly;
     if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + W::H) * W::PX + (lx + W::H)];
   }
+  if constexpr (RES) {
+    // b - diag x - couplings, in the order of coarse_offsum (a window cell
+    // outside a wall holds a zero iterate and couplings, so its term is zero)
+    auto res = [&](int q, int qc, int, int) {
+      T s = 0;
+      s += o0[q] * xs[q + 1];
+      s += o0[q - 1] * xs[q - 1];
+      s += o1[q] * xs[q + W::PX];
+      s += o1[q - W::PX] * xs[q - W::PX];
+      return bb[qc] - dg[qc] * xs[q] - s;
+    };
+    restrict2<T, RB_TX, RB_TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, res);
+  }
 }
 
 // shared buffer of the coarse sweep kernel: the 3D z-march's four planes or
 // the 2D double sweep's staged windows
-constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 2>::QL) > 4 * RB_PLANE
-                            ? (3 * Win2<RB_TX, RB_TY, 2>::PL + 2 * Win2<RB_TX, RB_TY, 2>::QL)
+constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_TY, 2, 1>::PL + 2 * Win2<RB_TX, RB_TY, 2, 1>::QL) > 4 * RB_PLANE
+                            ? (3 * Win2<RB_TX, RB_TY, 2, 1>::PL + 2 * Win2<RB_TX, RB_TY, 2, 1>::QL)
                             : 4 * RB_PLANE;
 
 // Children (di, dj, dk) of a coarse cell whose fine cell has colour 0
@@ -1777,16 +1832,19 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
   resid_init_body(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb);
 }
 
-template <typename T, int TX, int TY, int NSW>
+template <typename T, int TX, int TY, int NSW, int RES>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __restrict__ cs,
                                                          const CaseCtl* __restrict__ ctl, WorkList wl, int in_sel,
                                                          int out_sel, int add_xc) {
   using FT = FineTile<TX, TY>;
-  using W = Win2<TX, TY, NSW>;
-  static_assert(W::PL <= 4 * FT::PL && W::QL <= 2 * FT::QL, "2D windows must fit the z-march buffers");
+  using W = Win2<TX, TY, NSW, RES>;
+  // one set of buffers serves the 3D z-march (four iterate planes, two r /
+  // flag planes) and the 2D staged window
+  constexpr int QB = W::QL > 2 * FT::QL ? (W::QL + 1) / 2 : FT::QL;
+  static_assert(W::PL <= 4 * FT::PL && W::QL <= 2 * QB, "2D windows must fit the sweep buffers");
   __shared__ T xs[4][FT::PL];
-  __shared__ double rs[2][FT::QL];
-  __shared__ uint8_t fs[2][FT::QL];
+  __shared__ double rs[2][QB];
+  __shared__ uint8_t fs[2][QB];
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   // register copies, read together with the control word: the sweep never
@@ -1799,15 +1857,21 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   const T* xc = add_xc ? (const T*)C.lx[1][0] : nullptr;
   const Dims cd = C.lev[1].d;
   const int fgx = C.fgx, fgy = C.fgy, fzc = C.fzc;
+  T* bc = RES ? C.lb[1] : nullptr;
+  T* xcz = RES ? C.lx[1][0] : nullptr;
   if (!ctl[c].active) return;
   const int bx = lb % fgx, by = (lb / fgx) % fgy, bz = lb / (fgx * fgy);
-  if (op.d.dim == 2)
-    rb_fine2d_body<T, TX, TY, NSW>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0]);
-  else
-    rb_fine_body<T, TX, TY>(op, r, zin, xc, cd, zout, fzc, bx, by, bz, xs, rs, fs);
+  if constexpr (RES || TY == 4) {
+    rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz);
+  } else {
+    if (op.d.dim == 2)
+      rb_fine2d_body<T, TX, TY, NSW, 0>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz);
+    else
+      rb_fine_body<T, TX, TY>(op, r, zin, xc, cd, zout, fzc, bx, by, bz, xs, rs, fs);
+  }
 }
 
-template <typename T, int NSW>
+template <typename T, int NSW, int RES>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* __restrict__ cs,
                                                            const CaseCtl* __restrict__ ctl, WorkList wl, int l,
                                                            int in_sel, int out_sel, int add_xc) {
@@ -1821,9 +1885,11 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
   const T* xc = add_xc ? (const T*)C.lx[l + 1][0] : nullptr;
   const Dims cd = C.lev[l + 1].d;
   T* xout = C.lx[l][out_sel];
+  T* bc = RES ? C.lb[l + 1] : nullptr;
+  T* xcz = RES ? C.lx[l + 1][0] : nullptr;
   if (!ctl[c].active) return;
-  if (rows.op.d.dim == 2)
-    rb_coarse2d_body<T, NSW>(rows.op, rows.b, xin, xc, cd, xout, lb % gx, (lb / gx) % gy, buf);
+  if (RES || rows.op.d.dim == 2)
+    rb_coarse2d_body<T, NSW, RES>(rows.op, rows.b, xin, xc, cd, xout, lb % gx, (lb / gx) % gy, buf, bc, xcz);
   else
     rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lb % gx, (lb / gx) % gy, lb / (gx * gy),
                                     reinterpret_cast<T(*)[RB_PLANE]>(buf));
@@ -2444,44 +2510,51 @@ HostList make_list(const std::vector<std::pair<int, int>>& ent, std::vector<int>
   return L;
 }
 
+// res: also restrict the residual to the next level (2D only)
 template <typename T>
-void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, int nsw, hipStream_t st) {
+void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, int nsw, int res,
+                 hipStream_t st) {
   const CaseCtl* ctl = P.d_ctl;
+  const dim3 g(P.fine.blocks), b(RB_THREADS);
   if (P.dim == 3)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.fine.w, in,
-                       out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+  else if (nsw == 2 && res)
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
   else if (nsw == 2)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.fine.w,
-                       in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+  else if (res)
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
   else
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1>), dim3(P.fine.blocks), dim3(RB_THREADS), 0, st, cs, ctl, P.fine.w,
-                       in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
 }
 
 template <typename T>
-void launch_coarse(const PlanT<T>& P, const SolveCase<T>* cs, int l, int in, int out, int add, int nsw,
+void launch_coarse(const PlanT<T>& P, const SolveCase<T>* cs, int l, int in, int out, int add, int nsw, int res,
                    hipStream_t st) {
   const CaseCtl* ctl = P.d_ctl;
-  if (nsw == 2)
-    hipLaunchKernelGGL((kb_rb_coarse<T, 2>), dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl,
-                       P.coarse[l].w, l, in, out, add);
+  const dim3 g(P.coarse[l].blocks), b(RB_THREADS);
+  if (nsw == 2 && res)
+    hipLaunchKernelGGL((kb_rb_coarse<T, 2, 1>), g, b, 0, st, cs, ctl, P.coarse[l].w, l, in, out, add);
+  else if (nsw == 2)
+    hipLaunchKernelGGL((kb_rb_coarse<T, 2, 0>), g, b, 0, st, cs, ctl, P.coarse[l].w, l, in, out, add);
+  else if (res)
+    hipLaunchKernelGGL((kb_rb_coarse<T, 1, 1>), g, b, 0, st, cs, ctl, P.coarse[l].w, l, in, out, add);
   else
-    hipLaunchKernelGGL((kb_rb_coarse<T, 1>), dim3(P.coarse[l].blocks), dim3(RB_THREADS), 0, st, cs, ctl,
-                       P.coarse[l].w, l, in, out, add);
+    hipLaunchKernelGGL((kb_rb_coarse<T, 1, 0>), g, b, 0, st, cs, ctl, P.coarse[l].w, l, in, out, add);
 }
 
 // Sweeps s0 .. s1 (1-based, of S = nu1 + nu2 on a level): sweep s writes
 // buffer 0 when S - s is even, else buffer 1; in 2D two sweeps go in one
-// launch where the run allows it.  launch(in, out, add, nsw).  Returns the
-// number of launches.
+// launch where the run allows it.  launch(in, out, add, nsw, res), res set
+// on the run's last launch when res_last.  Returns the number of launches.
 template <typename L>
-int sweep_run(int s0, int s1, int S, int in, int add_first, bool pairs, const L& launch) {
+int sweep_run(int s0, int s1, int S, int in, int add_first, bool pairs, int res_last, const L& launch) {
   auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
   int n = 0;
   for (int s = s0; s <= s1;) {
     const int nsw = (pairs && s + 1 <= s1) ? 2 : 1;
     const int last = s + nsw - 1;
-    launch(in, slot(last), s == s0 ? add_first : 0, nsw);
+    launch(in, slot(last), s == s0 ? add_first : 0, nsw, (res_last && last == s1) ? 1 : 0);
     in = slot(last);
     s += nsw;
     ++n;
@@ -2498,25 +2571,31 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   const CaseCtl* ctl = P.d_ctl;
   const bool pairs = P.dim == 2;
   auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
-  auto fine = [&](int in, int out, int add, int nsw) { launch_fine(P, cs, in, out, add, nsw, st); };
+  // in 2D the last pre-smoothing launch of a level also restricts
+  const int fuse = pairs ? 1 : 0;
+  auto fine = [&](int in, int out, int add, int nsw, int res) { launch_fine(P, cs, in, out, add, nsw, res, st); };
   {
     ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, pairs ? (nu1 + 1) / 2 : nu1);
-    sweep_run(1, nu1, S, -1, 0, pairs, fine);
+    sweep_run(1, nu1, S, -1, 0, pairs, fuse, fine);
   }
-  {
+  if (!fuse) {
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
     hipLaunchKernelGGL(kb_fine_restrict<T>, dim3(P.frestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
                        P.frestrict.w, slot(nu1));
   }
   for (int l = 1; l < P.Lmax; ++l) {
-    auto coarse = [&](int in, int out, int add, int nsw) { launch_coarse(P, cs, l, in, out, add, nsw, st); };
+    auto coarse = [&](int in, int out, int add, int nsw, int res) {
+      launch_coarse(P, cs, l, in, out, add, nsw, res, st);
+    };
     {
       ProfScope ps(pf, EBIT_KC_COARSE, st, pairs ? (nu1 + 1) / 2 : nu1);
-      sweep_run(1, nu1, S, -1, 0, pairs, coarse);
+      sweep_run(1, nu1, S, -1, 0, pairs, fuse, coarse);
     }
-    ProfScope ps(pf, EBIT_KC_COARSE, st);
-    hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                       P.crestrict[l].w, l, slot(nu1));
+    if (!fuse) {
+      ProfScope ps(pf, EBIT_KC_COARSE, st);
+      hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                         P.crestrict[l].w, l, slot(nu1));
+    }
   }
   {
     ProfScope ps(pf, EBIT_KC_TAIL, st);
@@ -2526,13 +2605,15 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
       hipLaunchKernelGGL((kb_tail<T, 2>), dim3(P.n), dim3(EBIT_TAIL_THREADS), P.tail_bytes, st, cs, ctl);
   }
   for (int l = P.Lmax - 1; l >= 1; --l) {
-    auto coarse = [&](int in, int out, int add, int nsw) { launch_coarse(P, cs, l, in, out, add, nsw, st); };
+    auto coarse = [&](int in, int out, int add, int nsw, int res) {
+      launch_coarse(P, cs, l, in, out, add, nsw, res, st);
+    };
     ProfScope ps(pf, EBIT_KC_COARSE, st, pairs ? (S - nu1 + 1) / 2 : S - nu1);
-    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, coarse);
+    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, 0, coarse);
   }
   {
     ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, pairs ? (S - nu1 + 1) / 2 : S - nu1);
-    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, fine);
+    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, 0, fine);
   }
 }
 
