@@ -1695,7 +1695,7 @@ __global__ void k_heat_rhs(FineOp op, const double* __restrict__ Ts, double* __r
 }
 
 // finalize kinds
-enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5 };
+enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5, FIN_START = 6 };
 
 // Sum (or max) of nv rows of nb partials, in a fixed order; result in thread 0.
 __device__ inline void reduce_partials(const double* __restrict__ partial, int nb, int nv, bool mx,
@@ -1771,15 +1771,19 @@ __device__ inline int wl_find(const WorkList& w, int& lb, int& nb) {
 // control word of one case (host writes between iteration blocks, the
 // finalize kernels on the device)
 struct CaseCtl {
-  int active;   // iterating
-  int fresh;    // next iteration restarts the CG recurrence (beta = 0)
-  int pi;       // p[pi] holds the current search direction
-  int recheck;  // selected for a recomputation of the true residual
+  int active;    // iterating
+  int fresh;     // next iteration restarts the CG recurrence (beta = 0)
+  int pi;        // p[pi] holds the current search direction
+  int recheck;   // 1: selected for a recomputation of the true residual; 2: b = 0, x to be cleared
+  double stop2;  // the case stops once r.r falls to this level
 };
 
-enum { MASK_ACTIVE = 0, MASK_ALL = 1, MASK_RECHECK = 2 };
+enum { MASK_ACTIVE = 0, MASK_ALL = 1, MASK_RECHECK = 2, MASK_ZERO = 3 };
 __device__ inline bool selected(const CaseCtl& c, int mask) {
-  return mask == MASK_ALL || (mask == MASK_ACTIVE ? c.active : c.recheck) != 0;
+  if (mask == MASK_ALL) return true;
+  if (mask == MASK_ACTIVE) return c.active != 0;
+  if (mask == MASK_ZERO) return c.recheck == 2;
+  return c.recheck != 0;
 }
 
 // Device view of one solve of one case: operator, vectors, hierarchy.
@@ -1805,10 +1809,11 @@ struct SolveCase {
 };
 
 template <typename T>
-__global__ void kb_scal_reset(const SolveCase<T>* __restrict__ cs) {
+__global__ void kb_scal_reset(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl) {
   Scal* sc = cs[blockIdx.x].sc;
   int* w = reinterpret_cast<int*>(sc);
   for (int t = threadIdx.x; t < (int)(sizeof(Scal) / sizeof(int)); t += blockDim.x) w[t] = 0;
+  if (threadIdx.x == 0) ctl[blockIdx.x] = CaseCtl{1, 1, 0, 0, 0.0};
 }
 
 template <typename T>
@@ -2098,8 +2103,8 @@ __global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, const CaseCtl*
 // the direction slot flips, the restart flag clears, the iteration count
 // advances, and the case stops (active = 0) once r.r <= stop2 or on NaN/Inf.
 template <typename T>
-__global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl,
-                            const double* __restrict__ stop2, int kind, int nv, int row, int mask) {
+__global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl, int kind, int nv,
+                            int row, int mask, double rtol2) {
   const int c = blockIdx.x;
   const CaseCtl cc = ctl[c];
   if (!selected(cc, mask)) return;
@@ -2109,11 +2114,22 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
   if (threadIdx.x != 0) return;
   Scal* sc = C.sc;
   bool bad = false;
-  if (kind == FIN_INIT) {
+  if (kind == FIN_INIT || kind == FIN_START) {
     sc->bb = v[0];
     sc->rr = v[1];
     sc->aa = v[2];
     bad = !isfinite(v[0]) || !isfinite(v[1]);
+    if (kind == FIN_START) {
+      // the start of a solve: b = 0 gives x = 0; a residual already at
+      // rtol |b| stops before the first iteration (the host then confirms
+      // it like any other stop); otherwise iterate down to rtol^2 |b|^2
+      CaseCtl n{0, 1, 0, 0, rtol2 * v[0]};
+      if (v[0] == 0.0)
+        n.recheck = 2;
+      else if (!(v[1] <= n.stop2))
+        n.active = 1;
+      ctl[c] = n;
+    }
   } else {
     sc->rr = v[0];
     sc->iters += 1;
@@ -2121,7 +2137,7 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
     CaseCtl n = cc;
     n.fresh = 0;
     n.pi = cc.pi ^ 1;
-    if (v[0] <= stop2[c]) n.active = 0;
+    if (v[0] <= cc.stop2) n.active = 0;
     ctl[c] = n;
   }
   if (bad) {
@@ -2446,12 +2462,13 @@ struct PlanT {
   std::vector<EbitPlanCase> cases;
   SolveCase<T>* d_cs[2] = {nullptr, nullptr};
   SolveCase<T>* h_cs[2] = {nullptr, nullptr};
+  // control words and scalars of every case, one contiguous block on the
+  // device and its pinned host mirror (one copy each way)
   CaseCtl* d_ctl = nullptr;
   CaseCtl* h_ctl = nullptr;
-  double* d_stop2 = nullptr;
-  double* h_stop2 = nullptr;
   Scal* d_sc = nullptr;
   Scal* h_sc = nullptr;
+  void* h_blk = nullptr;
   HostList fine, frestrict, red;
   HostList coarse[EBIT_MAX_LEVELS], crestrict[EBIT_MAX_LEVELS];
   size_t tail_bytes = 0;
@@ -2465,15 +2482,14 @@ template <typename T>
 size_t plan_carve(int n, PCarver& cv, PlanT<T>* P, int** wl) {
   SolveCase<T>* cs0 = cv.take<SolveCase<T>>(n);
   SolveCase<T>* cs1 = cv.take<SolveCase<T>>(n);
-  CaseCtl* ctl = cv.take<CaseCtl>(n);
-  double* stop2 = cv.take<double>(n);
-  Scal* sc = cv.take<Scal>(n);
+  char* blk = cv.take<char>(n * (sizeof(CaseCtl) + sizeof(Scal)));
+  CaseCtl* ctl = (CaseCtl*)blk;
+  Scal* sc = blk ? (Scal*)(blk + n * sizeof(CaseCtl)) : nullptr;
   int* w = cv.take<int>((size_t)PLAN_LISTS * (2 * n + 1));
   if (P) {
     P->d_cs[0] = cs0;
     P->d_cs[1] = cs1;
     P->d_ctl = ctl;
-    P->d_stop2 = stop2;
     P->d_sc = sc;
     *wl = w;
   }
@@ -2637,8 +2653,8 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
       hipLaunchKernelGGL(kb_update_xr<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                          P.red.w);
     }
-    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
-                       (int)FIN_RR, 1, 3, (int)MASK_ACTIVE);
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_RR, 1, 3,
+                       (int)MASK_ACTIVE, 0.0);
   }
 }
 
@@ -2686,9 +2702,9 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
   hipError_t e;
   for (int s = 0; s < 2; ++s)
     if ((e = hipHostMalloc((void**)&P->h_cs[s], n * sizeof(SolveCase<T>), 0)) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&P->h_ctl, n * sizeof(CaseCtl), 0)) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&P->h_stop2, n * sizeof(double), 0)) != hipSuccess) return e;
-  if ((e = hipHostMalloc((void**)&P->h_sc, n * sizeof(Scal), 0)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&P->h_blk, n * (sizeof(CaseCtl) + sizeof(Scal)), 0)) != hipSuccess) return e;
+  P->h_ctl = (CaseCtl*)P->h_blk;
+  P->h_sc = (Scal*)((char*)P->h_blk + n * sizeof(CaseCtl));
   if ((e = hipStreamCreateWithFlags(&P->ist, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming)) != hipSuccess) return e;
@@ -2802,9 +2818,7 @@ void plan_destroy_t(PlanT<T>* P) {
   if (P->ev_out) (void)hipEventDestroy(P->ev_out);
   for (int s = 0; s < 2; ++s)
     if (P->h_cs[s]) (void)hipHostFree(P->h_cs[s]);
-  if (P->h_ctl) (void)hipHostFree(P->h_ctl);
-  if (P->h_stop2) (void)hipHostFree(P->h_stop2);
-  if (P->h_sc) (void)hipHostFree(P->h_sc);
+  if (P->h_blk) (void)hipHostFree(P->h_blk);
   delete P;
 }
 
@@ -2826,81 +2840,61 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
   for (int c = 0; c < n; ++c) {
     P.h_cs[sys][c].op = P.cases[c].op[sys];
     P.h_cs[sys][c].x = x[c];
-    P.h_ctl[c] = CaseCtl{1, 1, 0, 0};
-    P.h_stop2[c] = 0.0;
   }
   const SolveCase<T>* cs = P.d_cs[sys];
+  const size_t blk = n * (sizeof(CaseCtl) + sizeof(Scal));
   PK(hipEventRecord(P.ev_in, ust));
   PK(hipStreamWaitEvent(st, P.ev_in, 0));
   PK(hipMemcpyAsync(P.d_cs[sys], P.h_cs[sys], n * sizeof(SolveCase<T>), hipMemcpyHostToDevice, st));
-  PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
-  PK(hipMemcpyAsync(P.d_stop2, P.h_stop2, n * sizeof(double), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(kb_scal_reset<T>, dim3(n), dim3(64), 0, st, cs);
+  // start: the device clears the scalars, forms r = b - A x and decides per
+  // case (b = 0: x = 0; already converged: stopped; else iterate to
+  // rtol |b|); no host round trip before the first block of iterations
+  hipLaunchKernelGGL(kb_scal_reset<T>, dim3(n), dim3(64), 0, st, cs, P.d_ctl);
   if (!use_guess)
     hipLaunchKernelGGL(kb_zero_x<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                        P.red.w, (int)MASK_ALL);
   hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                      P.red.w, (int)MASK_ALL, use_guess ? 1 : 0);
-  hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2, (int)FIN_INIT,
-                     3, 0, (int)MASK_ALL);
+  hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_START, 3, 0, (int)MASK_ALL,
+                     o.rtol * o.rtol);
+  if (use_guess)
+    hipLaunchKernelGGL(kb_zero_x<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                       P.red.w, (int)MASK_ZERO);
   PK(hipGetLastError());
-  PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
-  PK(hipStreamSynchronize(st));
   const double fc = 2.220446049250313e-16;
   std::vector<int> status(n, -1), restarts(n, 0), at_floor(n, 0);
-  std::vector<double> tol2(n), floor2(n), last_true(n), bb(n);
-  bool zero_fill = false;
-  for (int c = 0; c < n; ++c) {
-    const Scal& S = P.h_sc[c];
-    bb[c] = S.bb;
-    tol2[c] = o.rtol * o.rtol * S.bb;
-    floor2[c] = fc * fc * S.aa;
-    last_true[c] = S.rr;
-    P.h_ctl[c] = CaseCtl{0, 1, 0, 0};
-    if (S.err & ERR_NAN) {
-      status[c] = 2;
-    } else if (S.bb == 0.0) {
-      status[c] = 0;  // b = 0: x = 0
-      P.h_ctl[c].recheck = 1;
-      zero_fill = true;
-    } else if (S.rr <= tol2[c]) {
-      status[c] = 0;
-    } else {
-      P.h_ctl[c].active = 1;
-      P.h_stop2[c] = tol2[c];
-    }
-  }
-  PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
-  PK(hipMemcpyAsync(P.d_stop2, P.h_stop2, n * sizeof(double), hipMemcpyHostToDevice, st));
-  if (zero_fill) {
-    hipLaunchKernelGGL(kb_zero_x<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                       P.red.w, (int)MASK_RECHECK);
-    for (int c = 0; c < n; ++c) P.h_ctl[c].recheck = 0;
-    PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
-  }
+  std::vector<double> tol2(n, 0.0), floor2(n, 0.0), last_true(n, 0.0), bb(n, 0.0);
   const int check = o.check_every > 0 ? o.check_every : 1;
-  for (;;) {
+  for (bool first = true;; first = false) {
     int K = check;
     int running = 0;
     for (int c = 0; c < n; ++c)
       if (status[c] < 0) {
         ++running;
-        const int left = o.max_iters - P.h_sc[c].iters;
+        const int left = o.max_iters - (first ? 0 : P.h_sc[c].iters);
         if (left < K) K = left;
       }
     if (running == 0) break;
     if (K < 1) K = 1;
     PK(run_block(P, sys, K, pf));
-    PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
-    PK(hipMemcpyAsync(P.h_ctl, P.d_ctl, n * sizeof(CaseCtl), hipMemcpyDeviceToHost, st));
+    PK(hipMemcpyAsync(P.h_blk, P.d_ctl, blk, hipMemcpyDeviceToHost, st));
     PK(hipStreamSynchronize(st));
     int nre = 0;
     for (int c = 0; c < n; ++c) {
       if (status[c] >= 0) continue;
       const Scal& S = P.h_sc[c];
+      if (first) {
+        bb[c] = S.bb;
+        tol2[c] = o.rtol * o.rtol * S.bb;
+        floor2[c] = fc * fc * S.aa;
+      }
       if (S.err & ERR_NAN) {
         status[c] = 2;
         P.h_ctl[c].active = 0;
+      } else if (S.bb == 0.0) {
+        status[c] = 0;  // b = 0: x = 0 (cleared on the device)
+        P.h_ctl[c].active = 0;
+        P.h_ctl[c].recheck = 0;
       } else if (!P.h_ctl[c].active) {
         P.h_ctl[c].recheck = 1;  // r.r reached its stop level: recompute the true residual
         ++nre;
@@ -2913,8 +2907,8 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
       PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
       hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
                          P.red.w, (int)MASK_RECHECK, 1);
-      hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (const double*)P.d_stop2,
-                         (int)FIN_INIT, 3, 0, (int)MASK_RECHECK);
+      hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_INIT, 3, 0,
+                         (int)MASK_RECHECK, 0.0);
       PK(hipGetLastError());
       PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
       PK(hipStreamSynchronize(st));
@@ -2943,12 +2937,11 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
           last_true[c] = rr;
           P.h_ctl[c].active = 1;
           P.h_ctl[c].fresh = 1;
-          P.h_stop2[c] = fmax(tol2[c], 1e-12 * rr);
+          P.h_ctl[c].stop2 = fmax(tol2[c], 1e-12 * rr);
         }
       }
     }
     PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
-    PK(hipMemcpyAsync(P.d_stop2, P.h_stop2, n * sizeof(double), hipMemcpyHostToDevice, st));
   }
   PK(hipEventRecord(P.ev_out, st));
   PK(hipStreamWaitEvent(ust, P.ev_out, 0));
