@@ -395,14 +395,29 @@ ebit_status build_launch(ebit_ctx* c, const double* const marker[3], const uint8
   return EBIT_OK;
 }
 
-// Second half: report geometry errors, then the operators and hierarchies.
-ebit_status build_finish(ebit_ctx* c, const Scal& hs, hipStream_t st) {
+// Geometry errors the geometry pass left in the status scalars.
+ebit_status geometry_check(ebit_ctx* c, const Scal& hs) {
   if (hs.err & ERR_GEOM_MARKER) return fail(c, EBIT_EGEOM, "a marker is inconsistent with the vertex colours");
   if (hs.err & ERR_GEOM_SEAM) return fail(c, EBIT_EGEOM, "periodic seam markers or colours disagree");
   if (hs.err & ERR_GEOM_NOFACET) return fail(c, EBIT_EGEOM, "a cut link has no interface cell on either side");
+  return EBIT_OK;
+}
+
+// the operators and hierarchies (every index stays in range whatever the
+// geometry, so this may run before the geometry status is known)
+ebit_status build_operators(ebit_ctx* c, hipStream_t st) {
   set_ops(c);
   const int want32 = c->opts.precision == EBIT_MIXED;
   HIPCK(c, ebit_build_hierarchy(c->op, c->lv, c->nlev, want32, c->build_tabs, c->build_ls, st), "hierarchy");
+  return EBIT_OK;
+}
+
+// Second half: report geometry errors, then the operators and hierarchies.
+ebit_status build_finish(ebit_ctx* c, const Scal& hs, hipStream_t st) {
+  ebit_status s = geometry_check(c, hs);
+  if (s != EBIT_OK) return s;
+  s = build_operators(c, st);
+  if (s != EBIT_OK) return s;
   c->built = 1;
   return EBIT_OK;
 }
@@ -533,10 +548,17 @@ ebit_status ebit_build_coeffs(ebit_ctx* c, const double* const marker[3], const 
                               double dt) {
   ebit_status s = build_launch(c, marker, vcol, ccol, dt, c ? c->st : nullptr);
   if (s != EBIT_OK) return s;
+  // operators and hierarchy go out behind the geometry pass; its status is
+  // read once, after them (an invalid geometry leaves the context unbuilt)
+  s = build_operators(c, c->st);
+  if (s != EBIT_OK) return s;
   Scal hs;
   HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "geometry status");
   HIPCK(c, hipStreamSynchronize(c->st), "geometry sync");
-  return build_finish(c, hs, c->st);
+  s = geometry_check(c, hs);
+  if (s != EBIT_OK) return s;
+  c->built = 1;
+  return EBIT_OK;
 }
 
 ebit_status ebit_heat_solve(ebit_ctx* c, const double* Ts, double* T, int use_guess, ebit_stats* st) {

@@ -2876,6 +2876,8 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
       }
     if (running == 0) break;
     if (K < 1) K = 1;
+    // the host's decisions of the last round (only needed before a block)
+    if (!first) PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
     PK(run_block(P, sys, K, pf));
     PK(hipMemcpyAsync(P.h_blk, P.d_ctl, blk, hipMemcpyDeviceToHost, st));
     PK(hipStreamSynchronize(st));
@@ -2941,7 +2943,6 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
         }
       }
     }
-    PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
   }
   PK(hipEventRecord(P.ev_out, st));
   PK(hipStreamWaitEvent(ust, P.ev_out, 0));
