@@ -1583,12 +1583,24 @@ __global__ __launch_bounds__(1024) void k_build_small(const BuildTable* __restri
 // ---------------------------------------------------------------------------
 // outer loop (FP64) with deterministic two-stage reductions
 // ---------------------------------------------------------------------------
+// Tile (or first row block) taken by the lb-th of a case's nb blocks.  The
+// chip hands work-groups to its 8 XCDs round-robin by global index, and each
+// XCD has its own L2; the blocks of one XCD (equal lb mod 8, whatever the
+// case's first global block) take a contiguous range of tiles, so the halo
+// rows and planes that neighbouring tiles share are read once per XCD
+// rather than once per tile.  A bijection of [0, nb) that depends on lb and
+// nb alone, so a case maps the same way alone and in a batch.
+__device__ inline int xcd_tile(int lb, int nb) {
+  const int r = lb & 7, B = nb >> 3, R = nb & 7;
+  return r * B + (r < R ? r : R) + (lb >> 3);
+}
+
 #define GRID_STRIDE(c, N) \
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < (N); c += (long long)gridDim.x * blockDim.x)
 // the same over the nb blocks one case owns in a batched launch (this block
-// is its lb-th)
-#define CASE_STRIDE(c, N) \
-  for (long long c = (long long)lb * blockDim.x + threadIdx.x; c < (N); c += (long long)nb * blockDim.x)
+// is its lb-th), the blocks of one XCD taking neighbouring rows (xcd_tile)
+#define CASE_STRIDE(c, N)                                                                                   \
+  for (long long c = (long long)xcd_tile(lb, nb) * blockDim.x + threadIdx.x; c < (N); c += (long long)nb * blockDim.x)
 
 template <int NV>
 __device__ inline void write_partials(double (&v)[NV], double* partial, int lb, int nb) {
@@ -1865,7 +1877,8 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   T* bc = RES ? C.lb[1] : nullptr;
   T* xcz = RES ? C.lx[1][0] : nullptr;
   if (!ctl[c].active) return;
-  const int bx = lb % fgx, by = (lb / fgx) % fgy, bz = lb / (fgx * fgy);
+  const int lt = xcd_tile(lb, nb);
+  const int bx = lt % fgx, by = (lt / fgx) % fgy, bz = lt / (fgx * fgy);
   if constexpr (RES || TY == 4) {
     rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz);
   } else {
@@ -1893,10 +1906,11 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
   T* bc = RES ? C.lb[l + 1] : nullptr;
   T* xcz = RES ? C.lx[l + 1][0] : nullptr;
   if (!ctl[c].active) return;
+  const int lt = xcd_tile(lb, nb);
   if (RES || rows.op.d.dim == 2)
-    rb_coarse2d_body<T, NSW, RES>(rows.op, rows.b, xin, xc, cd, xout, lb % gx, (lb / gx) % gy, buf, bc, xcz);
+    rb_coarse2d_body<T, NSW, RES>(rows.op, rows.b, xin, xc, cd, xout, lt % gx, (lt / gx) % gy, buf, bc, xcz);
   else
-    rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lb % gx, (lb / gx) % gy, lb / (gx * gy),
+    rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lt % gx, (lt / gx) % gy, lt / (gx * gy),
                                     reinterpret_cast<T(*)[RB_PLANE]>(buf));
 }
 
@@ -2559,58 +2573,62 @@ void launch_coarse(const PlanT<T>& P, const SolveCase<T>* cs, int l, int in, int
     hipLaunchKernelGGL((kb_rb_coarse<T, 1, 0>), g, b, 0, st, cs, ctl, P.coarse[l].w, l, in, out, add);
 }
 
-// Sweeps s0 .. s1 (1-based, of S = nu1 + nu2 on a level): sweep s writes
-// buffer 0 when S - s is even, else buffer 1; in 2D two sweeps go in one
-// launch where the run allows it.  launch(in, out, add, nsw, res), res set
-// on the run's last launch when res_last.  Returns the number of launches.
+// A run of ns sweeps on a level, as launches t0, t0 + 1, ... of the
+// level's m launches (1-based): launch t writes buffer 0 when m - t is even,
+// else buffer 1, so consecutive launches alternate (no launch reads the
+// buffer it writes: the tiles' halos come from the input) and the level's
+// last launch lands in buffer 0.  In 2D two sweeps go in one launch where
+// the run allows it.  launch(in, out, add, nsw, res), res set on the run's
+// last launch when res_last.  Returns the buffer the run's last launch
+// wrote.
 template <typename L>
-int sweep_run(int s0, int s1, int S, int in, int add_first, bool pairs, int res_last, const L& launch) {
-  auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
-  int n = 0;
-  for (int s = s0; s <= s1;) {
-    const int nsw = (pairs && s + 1 <= s1) ? 2 : 1;
-    const int last = s + nsw - 1;
-    launch(in, slot(last), s == s0 ? add_first : 0, nsw, (res_last && last == s1) ? 1 : 0);
-    in = slot(last);
+int sweep_run(int ns, int t0, int m, int in, int add_first, bool pairs, int res_last, const L& launch) {
+  int t = t0;
+  for (int s = 0; s < ns; ++t) {
+    const int nsw = (pairs && s + 1 < ns) ? 2 : 1;
+    const int out = ((m - t) % 2 == 0) ? 0 : 1;
+    launch(in, out, s == 0 ? add_first : 0, nsw, (res_last && s + nsw == ns) ? 1 : 0);
+    in = out;
     s += nsw;
-    ++n;
   }
-  return n;
+  return in;
 }
 
 // One V(nu1, nu2) cycle on A z = r (zero initial guess) for every active
-// case.  Sweep s of S = nu1 + nu2 on a level writes buffer 0 when S - s is
-// even, else buffer 1, so the last one lands in buffer 0.
+// case.  The launches of a level alternate between its two iterate buffers
+// (sweep_run), the last one landing in buffer 0.
 template <typename T>
 void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitProfiler* pf) {
-  const int nu1 = P.o.nu1, S = P.o.nu1 + P.o.nu2;
+  const int nu1 = P.o.nu1, nu2 = P.o.nu2;
   const CaseCtl* ctl = P.d_ctl;
   const bool pairs = P.dim == 2;
-  auto slot = [&](int s) { return ((S - s) % 2 == 0) ? 0 : 1; };
+  // launches per level before and after the correction
+  const int npre = pairs ? (nu1 + 1) / 2 : nu1, npost = pairs ? (nu2 + 1) / 2 : nu2, m = npre + npost;
+  const int preb = ((m - npre) % 2 == 0) ? 0 : 1;  // buffer of the pre-smoothed iterate
   // in 2D the last pre-smoothing launch of a level also restricts
   const int fuse = pairs ? 1 : 0;
   auto fine = [&](int in, int out, int add, int nsw, int res) { launch_fine(P, cs, in, out, add, nsw, res, st); };
   {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, pairs ? (nu1 + 1) / 2 : nu1);
-    sweep_run(1, nu1, S, -1, 0, pairs, fuse, fine);
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npre);
+    sweep_run(nu1, 1, m, -1, 0, pairs, fuse, fine);
   }
   if (!fuse) {
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
     hipLaunchKernelGGL(kb_fine_restrict<T>, dim3(P.frestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                       P.frestrict.w, slot(nu1));
+                       P.frestrict.w, preb);
   }
   for (int l = 1; l < P.Lmax; ++l) {
     auto coarse = [&](int in, int out, int add, int nsw, int res) {
       launch_coarse(P, cs, l, in, out, add, nsw, res, st);
     };
     {
-      ProfScope ps(pf, EBIT_KC_COARSE, st, pairs ? (nu1 + 1) / 2 : nu1);
-      sweep_run(1, nu1, S, -1, 0, pairs, fuse, coarse);
+      ProfScope ps(pf, EBIT_KC_COARSE, st, npre);
+      sweep_run(nu1, 1, m, -1, 0, pairs, fuse, coarse);
     }
     if (!fuse) {
       ProfScope ps(pf, EBIT_KC_COARSE, st);
       hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                         P.crestrict[l].w, l, slot(nu1));
+                         P.crestrict[l].w, l, preb);
     }
   }
   {
@@ -2624,12 +2642,12 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
     auto coarse = [&](int in, int out, int add, int nsw, int res) {
       launch_coarse(P, cs, l, in, out, add, nsw, res, st);
     };
-    ProfScope ps(pf, EBIT_KC_COARSE, st, pairs ? (S - nu1 + 1) / 2 : S - nu1);
-    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, 0, coarse);
+    ProfScope ps(pf, EBIT_KC_COARSE, st, npost);
+    sweep_run(nu2, npre + 1, m, preb, 1, pairs, 0, coarse);
   }
   {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, pairs ? (S - nu1 + 1) / 2 : S - nu1);
-    sweep_run(nu1 + 1, S, S, slot(nu1), 1, pairs, 0, fine);
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npost);
+    sweep_run(nu2, npre + 1, m, preb, 1, pairs, 0, fine);
   }
 }
 
