@@ -1383,36 +1383,60 @@ __device__ inline void build_cell_from_fine(const FineOp& op, const BuildOut& o,
 }
 
 // coarse cell I from the explicit level above
+template <int DIM>
 __device__ inline void build_cell_from_coarse(const CoarseOp<double>& op, const BuildOut& o, long long I) {
   int ci, cj, ck;
   cell_ijk(o.cd, I, ci, cj, ck);
+  const int n0 = op.d.n[0], n1 = op.d.n[1], n2 = op.d.n[2];
   double M = 0, F = 0, cross[3] = {0, 0, 0};
-  for (int dk = 0; dk < 2; ++dk) {
-    const int k = 2 * ck + dk;
-    if (k >= op.d.n[2]) break;
-    for (int dj = 0; dj < 2; ++dj) {
-      const int j = 2 * cj + dj;
-      if (j >= op.d.n[1]) break;
-      for (int di = 0; di < 2; ++di) {
-        const int i = 2 * ci + di;
-        if (i >= op.d.n[0]) break;
-        const long long c = cell_index(op.d, i, j, k);
-        M += op.mass[c];
-        F += op.diag[c] - op.mass[c];
+  // children in order (dk, dj, di), G at a time: every load of a group is
+  // issued before any is used.  Sides across a wall name the wrapped cell,
+  // whose stored coupling there is zero, so they drop out at the zero test
+  // like the missing neighbours they stand for.
+  constexpr int G = DIM == 3 ? 2 : 4, NCH = DIM == 3 ? 8 : 4;
+#pragma unroll 1
+  for (int g = 0; g < NCH; g += G) {
+    double mv[G], dv[G], ov[G][2 * DIM];
+    int ii[G], jj[G], kk[G];
+    bool in[G];
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-          if (s >= 2 * op.d.dim) continue;
-          int ni, nj, nk;
-          if (!neighbour(op.d, i, j, k, s, ni, nj, nk)) continue;
-          const long long m = cell_index(op.d, ni, nj, nk);
-          const double off = (s & 1) ? op.off[s >> 1][c] : op.off[s >> 1][m];
-          if (off == 0.0) continue;
-          const bool same = (ni >> 1) == ci && (nj >> 1) == cj && (nk >> 1) == ck;
-          if (same)
-            F += off;
-          else if (s & 1)
-            cross[s >> 1] += off;
-        }
+    for (int q = 0; q < G; ++q) {
+      const int ch = g + q;
+      int i = 2 * ci + (ch & 1), j = 2 * cj + ((ch >> 1) & 1), k = 2 * ck + (ch >> 2);
+      in[q] = i < n0 && j < n1 && k < n2;
+      i = i < n0 ? i : n0 - 1;
+      j = j < n1 ? j : n1 - 1;
+      k = k < n2 ? k : n2 - 1;
+      ii[q] = i;
+      jj[q] = j;
+      kk[q] = k;
+      const long long c = cell_index(op.d, i, j, k);
+      long long m[6];
+      fine_nbrs(op.d, i, j, k, c, m);
+      mv[q] = op.mass[c];
+      dv[q] = op.diag[c];
+#pragma unroll
+      for (int s = 0; s < 2 * DIM; ++s) ov[q][s] = (s & 1) ? op.off[s >> 1][c] : op.off[s >> 1][m[s]];
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      if (!in[q]) continue;
+      M += mv[q];
+      F += dv[q] - mv[q];
+#pragma unroll
+      for (int s = 0; s < 2 * DIM; ++s) {
+        const double off = ov[q][s];
+        if (off == 0.0) continue;
+        const int a = s >> 1, up = s & 1;
+        int ni = ii[q], nj = jj[q], nk = kk[q];
+        if (a == 0) ni = up ? (ni + 1 < n0 ? ni + 1 : 0) : (ni > 0 ? ni - 1 : n0 - 1);
+        if (a == 1) nj = up ? (nj + 1 < n1 ? nj + 1 : 0) : (nj > 0 ? nj - 1 : n1 - 1);
+        if (a == 2) nk = up ? (nk + 1 < n2 ? nk + 1 : 0) : (nk > 0 ? nk - 1 : n2 - 1);
+        const bool same = (ni >> 1) == ci && (nj >> 1) == cj && (nk >> 1) == ck;
+        if (same)
+          F += off;
+        else if (up)
+          cross[a] += off;
       }
     }
   }
@@ -1426,7 +1450,11 @@ __global__ void k_build_from_fine(FineOp op, BuildOut o) {
 
 __global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
   const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I < o.cd.N) build_cell_from_coarse(op, o, I);
+  if (I >= o.cd.N) return;
+  if (op.d.dim == 3)
+    build_cell_from_coarse<3>(op, o, I);
+  else
+    build_cell_from_coarse<2>(op, o, I);
 }
 
 
@@ -1536,6 +1564,7 @@ struct BuildTable {
 // levels below the dense one serve only a failed inversion (the tail then
 // falls back to Gauss-Seidel on the coarsest level), so they are built
 // after it and only in that case.
+template <int DIM>
 __device__ inline void build_small_level(const BuildTable& t, int l) {
   CoarseOp<double> f;
   f.d = t.d[l - 1];
@@ -1555,17 +1584,18 @@ __device__ inline void build_small_level(const BuildTable& t, int l) {
     o.off[a] = t.off[l][a];
     o.o32[a] = t.o32[l][a];
   }
-  for (long long I = threadIdx.x; I < o.cd.N; I += blockDim.x) build_cell_from_coarse(f, o, I);
+  for (long long I = threadIdx.x; I < o.cd.N; I += blockDim.x) build_cell_from_coarse<DIM>(f, o, I);
   __syncthreads();
 }
 
+template <int DIM>
 __global__ __launch_bounds__(1024) void k_build_small(const BuildTable* __restrict__ tabs) {
   __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
   __shared__ double colb[2][EBIT_DENSE_MAX], rowb[2][EBIT_DENSE_MAX];
   const BuildTable& t = tabs[blockIdx.x];
   const int ls = t.ls, nlev = t.nlev, dl = t.dl;
   const int upto = dl >= 0 ? dl + 1 : nlev;
-  for (int l = ls; l < upto; ++l) build_small_level(t, l);
+  for (int l = ls; l < upto; ++l) build_small_level<DIM>(t, l);
   if (dl < 0) return;
   CoarseOp<double> f;
   f.d = t.d[dl];
@@ -1576,7 +1606,7 @@ __global__ __launch_bounds__(1024) void k_build_small(const BuildTable* __restri
   const bool good = dense_inverse(f, t.inv64, t.inv32, t.inv_ok, A, colb, rowb);
   if (!good) {
     __syncthreads();
-    for (int l = (ls > dl + 1 ? ls : dl + 1); l < nlev; ++l) build_small_level(t, l);
+    for (int l = (ls > dl + 1 ? ls : dl + 1); l < nlev; ++l) build_small_level<DIM>(t, l);
   }
 }
 
@@ -2256,7 +2286,10 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
         hipLaunchKernelGGL(k_build_from_coarse, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, f, o);
       }
     }
-  hipLaunchKernelGGL(k_build_small, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
+  if (lv[0].d.dim == 3)
+    hipLaunchKernelGGL(k_build_small<3>, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
+  else
+    hipLaunchKernelGGL(k_build_small<2>, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
   return hipGetLastError();
 }
 
