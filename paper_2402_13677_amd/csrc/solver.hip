@@ -80,6 +80,15 @@ __device__ inline T fine_residual_at(const FineOp& op, int i, int j, int k, long
   return s;
 }
 
+// per-block partial sums of NV values: row q, slot lb of nb
+template <int NV>
+__device__ inline void write_partials(double (&v)[NV], double* partial, int lb, int nb) {
+  __shared__ double sh[NV * 4];
+  block_sum<NV>(v, sh);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NV; ++q) partial[q * nb + lb] = v[q];
+}
+
 // ---------------------------------------------------------------------------
 // coarse levels (explicit symmetric coefficients)
 // ---------------------------------------------------------------------------
@@ -656,7 +665,9 @@ __device__ inline void restrict2(const Dims& d, const Dims& cd, int tx0, int ty0
 template <typename T, int TX, int TY, int NSW, int RES>
 __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
                                       const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
-                                      T* xs, double* rs, uint8_t* fs, T* __restrict__ bc, T* __restrict__ xcz) {
+                                      T* xs, double* rs, uint8_t* fs, T* __restrict__ bc, T* __restrict__ xcz,
+                                      int dots = 0, const double* __restrict__ qv = nullptr,
+                                      double* __restrict__ partial = nullptr, int slot = 0, int nslot = 0) {
   using W = Win2<TX, TY, NSW, RES>;
   const Dims& d = op.d;
   const RegularRow<T> rr = regular_row<T>(op);
@@ -735,6 +746,21 @@ __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict
       return s;
     };
     restrict2<T, TX, TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, res);
+  }
+  if (dots) {
+    // the outer loop's z.r and (dots == 1) z.q over this tile, from the
+    // final iterate and r in LDS: one partial per tile
+    double v[2] = {0, 0};
+    for (int t = threadIdx.x; t < TX * TY; t += RB_THREADS) {
+      const int lx = t % TX, ly = t / TX;
+      const int i = tx0 + lx, j = ty0 + ly;
+      if (i < d.n[0] && j < d.n[1]) {
+        const double zc = (double)xs[(ly + W::H) * W::PX + (lx + W::H)];
+        v[0] += zc * rs[(ly + W::QR) * W::QX + (lx + W::QR)];
+        if (dots == 1) v[1] += zc * qv[i + (long long)d.n[0] * j];
+      }
+    }
+    write_partials<2>(v, partial, slot, nslot);
   }
 }
 
@@ -1632,13 +1658,6 @@ __device__ inline int xcd_tile(int lb, int nb) {
 #define CASE_STRIDE(c, N)                                                                                   \
   for (long long c = (long long)xcd_tile(lb, nb) * blockDim.x + threadIdx.x; c < (N); c += (long long)nb * blockDim.x)
 
-template <int NV>
-__device__ inline void write_partials(double (&v)[NV], double* partial, int lb, int nb) {
-  __shared__ double sh[NV * 4];
-  block_sum<NV>(v, sh);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < NV; ++q) partial[q * nb + lb] = v[q];
-}
 
 // Error-free transformations (Knuth TwoSum, FMA-based TwoProd) for a
 // residual evaluated in double-double arithmetic.
@@ -1841,6 +1860,7 @@ struct SolveCase {
   double* partial;   // [4][nred]: rows 0-1 z.r, z.q (0-2 at a residual recomputation), 2 p.q, 3 r.r
   Scal* sc;
   int nred;          // reduction blocks of this case
+  int ndot;          // > 0: the last fine sweep of a V-cycle writes the z.r, z.q partials (one per tile)
   int nlev, lt;      // levels; levels lt .. nlev-1 are solved by the tail kernel
   int fzc, fgx, fgy; // fine sweep: z-chunk and tile grid
   CoarseOp<T> lev[EBIT_MAX_LEVELS];  // explicit levels 1 .. lt-1 (and lt: its size)
@@ -1882,7 +1902,7 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
 template <typename T, int TX, int TY, int NSW, int RES>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __restrict__ cs,
                                                          const CaseCtl* __restrict__ ctl, WorkList wl, int in_sel,
-                                                         int out_sel, int add_xc) {
+                                                         int out_sel, int add_xc, int dots) {
   using FT = FineTile<TX, TY>;
   using W = Win2<TX, TY, NSW, RES>;
   // one set of buffers serves the 3D z-march (four iterate planes, two r /
@@ -1910,7 +1930,12 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   const int lt = xcd_tile(lb, nb);
   const int bx = lt % fgx, by = (lt / fgx) % fgy, bz = lt / (fgx * fgy);
   if constexpr (RES || TY == 4) {
-    rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz);
+    // dots (last post-smoothing launch): 1 + [defect correction]; the tile
+    // partials replace the separate dot kernel for cases with ndot > 0
+    int dm = 0;
+    if (dots && C.ndot > 0) dm = (dots == 2 || ctl[c].fresh) ? 2 : 1;
+    rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz,
+                                        dm, C.q, C.partial, lb, C.ndot);
   } else {
     if (op.d.dim == 2)
       rb_fine2d_body<T, TX, TY, NSW, 0>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz);
@@ -2025,6 +2050,7 @@ __global__ void kb_dots(const SolveCase<T>* __restrict__ cs, const CaseCtl* __re
   const CaseCtl cc = ctl[c];
   if (!cc.active) return;
   const SolveCase<T>& C = cs[c];
+  if (C.ndot > 0) return;  // formed by the last fine sweep
   const bool first = dc || cc.fresh;
   const T* z = C.z[0];
   const double* r = C.r;
@@ -2055,7 +2081,7 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   const bool first = dc || cc.fresh;
   {
     double g[3];
-    reduce_partials(C.partial, nb, 2, false, g);
+    reduce_partials(C.partial, C.ndot > 0 ? C.ndot : nb, 2, false, g);
     if (threadIdx.x == 0) {
       Scal* sc = C.sc;
       const int so = cc.pi, sn = cc.pi ^ 1;
@@ -2523,6 +2549,8 @@ struct PlanT {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t graph[2][PLAN_MAX_K + 1] = {};
   bool no_graph = false;
+  // 2D: some / all cases take their dot products from the last fine sweep
+  bool anydot = false, alldot = true;
 };
 
 template <typename T>
@@ -2574,21 +2602,23 @@ HostList make_list(const std::vector<std::pair<int, int>>& ent, std::vector<int>
 }
 
 // res: also restrict the residual to the next level (2D only)
+// dots: the outer loop's dot products in this launch (2D; 1 + [defect
+// correction], 0 none)
 template <typename T>
-void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, int nsw, int res,
+void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, int nsw, int res, int dots,
                  hipStream_t st) {
   const CaseCtl* ctl = P.d_ctl;
   const dim3 g(P.fine.blocks), b(RB_THREADS);
   if (P.dim == 3)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, 0);
   else if (nsw == 2 && res)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
   else if (nsw == 2)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
   else if (res)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
   else
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
 }
 
 template <typename T>
@@ -2640,7 +2670,12 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   const int preb = ((m - npre) % 2 == 0) ? 0 : 1;  // buffer of the pre-smoothed iterate
   // in 2D the last pre-smoothing launch of a level also restricts
   const int fuse = pairs ? 1 : 0;
-  auto fine = [&](int in, int out, int add, int nsw, int res) { launch_fine(P, cs, in, out, add, nsw, res, st); };
+  auto fine = [&](int in, int out, int add, int nsw, int res) { launch_fine(P, cs, in, out, add, nsw, res, 0, st); };
+  // the last post-smoothing launch also forms the dot products (2D)
+  const int dots = P.anydot ? 1 + (P.o.outer == EBIT_OUTER_DC ? 1 : 0) : 0;
+  auto fine_post = [&](int in, int out, int add, int nsw, int last) {
+    launch_fine(P, cs, in, out, add, nsw, 0, last ? dots : 0, st);
+  };
   {
     ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npre);
     sweep_run(nu1, 1, m, -1, 0, pairs, fuse, fine);
@@ -2680,7 +2715,7 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   }
   {
     ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npost);
-    sweep_run(nu2, npre + 1, m, preb, 1, pairs, 0, fine);
+    sweep_run(nu2, npre + 1, m, preb, 1, pairs, 1, fine_post);
   }
 }
 
@@ -2692,8 +2727,9 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
   const int dc = P.o.outer == EBIT_OUTER_DC;
   for (int k = 0; k < K; ++k) {
     vcycle_b(P, cs, st, pf);
-    hipLaunchKernelGGL(kb_dots<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl, P.red.w,
-                       dc);
+    if (!P.alldot)
+      hipLaunchKernelGGL(kb_dots<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                         P.red.w, dc);
     {
       ProfScope ps(pf, EBIT_KC_OUTER_APPLY, st);
       hipLaunchKernelGGL(kb_p_update_apply<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs,
@@ -2796,6 +2832,14 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       C.fzc = rb_zchunk(fd);
       C.fgx = (fd.n[0] + 63) / 64;
       C.fgy = (fd.n[1] + fty - 1) / fty;
+      // one dot partial per fine tile, while they fit the rows the
+      // reduction blocks leave (2D sweeps hold r and z of a tile in LDS)
+      const int tiles = C.fgx * C.fgy;
+      C.ndot = (P->dim == 2 && tiles <= C.nred) ? tiles : 0;
+      if (sys == 0) {
+        P->anydot = P->anydot || C.ndot > 0;
+        P->alldot = P->alldot && C.ndot > 0;
+      }
       for (int l = 1; l < pc.nlev; ++l) {
         const EbitLevelHost& L = pc.lv[l];
         C.lev[l] = coarse_op_of<T>(L, sys);
