@@ -1756,7 +1756,7 @@ __global__ void k_heat_rhs(FineOp op, const double* __restrict__ Ts, double* __r
 }
 
 // finalize kinds
-enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5, FIN_START = 6 };
+enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5, FIN_START = 6, FIN_PEND = 7 };
 
 // Sum (or max) of nv rows of nb partials, in a fixed order; result in thread 0.
 __device__ inline void reduce_partials(const double* __restrict__ partial, int nb, int nv, bool mx,
@@ -1836,6 +1836,8 @@ struct CaseCtl {
   int fresh;     // next iteration restarts the CG recurrence (beta = 0)
   int pi;        // p[pi] holds the current search direction
   int recheck;   // 1: selected for a recomputation of the true residual; 2: b = 0, x to be cleared
+  int pend;      // the x/r update's r.r is not yet taken (2D: the next V-cycle's first launch takes it)
+  int pad;
   double stop2;  // the case stops once r.r falls to this level
 };
 
@@ -1875,7 +1877,7 @@ __global__ void kb_scal_reset(const SolveCase<T>* __restrict__ cs, CaseCtl* __re
   Scal* sc = cs[blockIdx.x].sc;
   int* w = reinterpret_cast<int*>(sc);
   for (int t = threadIdx.x; t < (int)(sizeof(Scal) / sizeof(int)); t += blockDim.x) w[t] = 0;
-  if (threadIdx.x == 0) ctl[blockIdx.x] = CaseCtl{1, 1, 0, 0, 0.0};
+  if (threadIdx.x == 0) ctl[blockIdx.x] = CaseCtl{1, 1, 0, 0, 0, 0, 0.0};
 }
 
 template <typename T>
@@ -1901,8 +1903,8 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
 
 template <typename T, int TX, int TY, int NSW, int RES>
 __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __restrict__ cs,
-                                                         const CaseCtl* __restrict__ ctl, WorkList wl, int in_sel,
-                                                         int out_sel, int add_xc, int dots) {
+                                                         CaseCtl* __restrict__ ctl, WorkList wl, int in_sel,
+                                                         int out_sel, int add_xc, int dots, int settle) {
   using FT = FineTile<TX, TY>;
   using W = Win2<TX, TY, NSW, RES>;
   // one set of buffers serves the 3D z-march (four iterate planes, two r /
@@ -1926,7 +1928,23 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   const int fgx = C.fgx, fgy = C.fgy, fzc = C.fzc;
   T* bc = RES ? C.lb[1] : nullptr;
   T* xcz = RES ? C.lx[1][0] : nullptr;
-  if (!ctl[c].active) return;
+  if (settle && ctl[c].pend) {
+    // the previous iteration's r.r, reduced by every block in the same
+    // fixed order: a case at its stop level skips this V-cycle, and block 0
+    // ends the iteration in its control word
+    const CaseCtl cc = ctl[c];
+    __shared__ int sact;
+    double v[3];
+    reduce_partials(C.partial + 3 * C.nred, C.nred, 1, false, v);
+    if (threadIdx.x == 0) {
+      sact = (v[0] <= cc.stop2 || !isfinite(v[0])) ? 0 : 1;
+      if (lb == 0) end_iteration(C.sc, ctl + c, cc, v[0]);
+    }
+    __syncthreads();
+    if (!sact) return;
+  } else if (!ctl[c].active) {
+    return;
+  }
   const int lt = xcd_tile(lb, nb);
   const int bx = lt % fgx, by = (lt / fgx) % fgy, bz = lt / (fgx * fgy);
   if constexpr (RES || TY == 4) {
@@ -2064,6 +2082,24 @@ __global__ void kb_dots(const SolveCase<T>* __restrict__ cs, const CaseCtl* __re
   write_partials<2>(v, C.partial, lb, nb);
 }
 
+// End of an outer iteration, given r.r: record it, count the iteration,
+// flip the direction slot, clear the restart and pending flags, and stop
+// the case once r.r reaches its stop level (or is not finite).
+__device__ inline void end_iteration(Scal* sc, CaseCtl* ctl, const CaseCtl& cc, double rr) {
+  sc->rr = rr;
+  sc->iters += 1;
+  CaseCtl n = cc;
+  n.fresh = 0;
+  n.pend = 0;
+  n.pi = cc.pi ^ 1;
+  if (rr <= cc.stop2) n.active = 0;
+  if (!isfinite(rr)) {
+    sc->err |= ERR_NAN;
+    n.active = 0;
+  }
+  *ctl = n;
+}
+
 // gamma = z.r and beta from the dots' partials, then p_new = z + beta p_old,
 // q = A p_new, partial p.q (row 2).  Every block reduces the partials itself,
 // in the same fixed order, so no separate reduction launch is needed; block
@@ -2130,7 +2166,7 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
 // alpha = gamma / (p.q) from the p-update's partials (every block, fixed
 // order), then x += alpha p, r -= alpha q, partial r.r (row 3).
 template <typename T>
-__global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl) {
+__global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl, WorkList wl, int pend) {
   __shared__ double salpha;
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
@@ -2166,6 +2202,9 @@ __global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, const CaseCtl*
     v[0] += rc * rc;
   }
   write_partials<1>(v, C.partial + 3 * nb, lb, nb);
+  // the r.r partials are taken by the next V-cycle's first launch (no
+  // other field of the control word changes here)
+  if (pend && lb == 0 && threadIdx.x == 0) ctl[c].pend = 1;
 }
 
 // One block per case: reduce its partials (nv rows from row `row`).
@@ -2178,6 +2217,7 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
   const int c = blockIdx.x;
   const CaseCtl cc = ctl[c];
   if (!selected(cc, mask)) return;
+  if (kind == FIN_PEND && !cc.pend) return;
   const SolveCase<T>& C = cs[c];
   double v[3];
   reduce_partials(C.partial + row * C.nred, C.nred, nv, false, v);
@@ -2193,7 +2233,7 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
       // the start of a solve: b = 0 gives x = 0; a residual already at
       // rtol |b| stops before the first iteration (the host then confirms
       // it like any other stop); otherwise iterate down to rtol^2 |b|^2
-      CaseCtl n{0, 1, 0, 0, rtol2 * v[0]};
+      CaseCtl n{0, 1, 0, 0, 0, 0, rtol2 * v[0]};
       if (v[0] == 0.0)
         n.recheck = 2;
       else if (!(v[1] <= n.stop2))
@@ -2201,14 +2241,7 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
       ctl[c] = n;
     }
   } else {
-    sc->rr = v[0];
-    sc->iters += 1;
-    bad = !isfinite(v[0]);
-    CaseCtl n = cc;
-    n.fresh = 0;
-    n.pi = cc.pi ^ 1;
-    if (v[0] <= cc.stop2) n.active = 0;
-    ctl[c] = n;
+    end_iteration(sc, ctl + c, cc, v[0]);
   }
   if (bad) {
     sc->err |= ERR_NAN;
@@ -2607,18 +2640,20 @@ HostList make_list(const std::vector<std::pair<int, int>>& ent, std::vector<int>
 template <typename T>
 void launch_fine(const PlanT<T>& P, const SolveCase<T>* cs, int in, int out, int add, int nsw, int res, int dots,
                  hipStream_t st) {
-  const CaseCtl* ctl = P.d_ctl;
+  CaseCtl* ctl = P.d_ctl;
+  // the first pre-smoothing launch takes the pending r.r (2D)
+  const int settle = (P.dim == 2 && in < 0) ? 1 : 0;
   const dim3 g(P.fine.blocks), b(RB_THREADS);
   if (P.dim == 3)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, 0);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 8, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, 0, 0);
   else if (nsw == 2 && res)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots, settle);
   else if (nsw == 2)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 2, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots, settle);
   else if (res)
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 1>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots, settle);
   else
-    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots);
+    hipLaunchKernelGGL((kb_rb_fine<T, 64, 4, 1, 0>), g, b, 0, st, cs, ctl, P.fine.w, in, out, add, dots, settle);
 }
 
 template <typename T>
@@ -2737,12 +2772,18 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
     }
     {
       ProfScope ps(pf, EBIT_KC_OUTER_UPDATE, st);
-      hipLaunchKernelGGL(kb_update_xr<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                         P.red.w);
+      hipLaunchKernelGGL(kb_update_xr<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, P.d_ctl, P.red.w,
+                         P.dim == 2 ? 1 : 0);
     }
-    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_RR, 1, 3,
-                       (int)MASK_ACTIVE, 0.0);
+    // 3D: end the iteration here; 2D: the next V-cycle's first launch does
+    if (P.dim != 2)
+      hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_RR, 1, 3,
+                         (int)MASK_ACTIVE, 0.0);
   }
+  // the last iteration of the block is ended before the host reads it
+  if (P.dim == 2)
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_PEND, 1, 3, (int)MASK_ALL,
+                       0.0);
 }
 
 // Run K iterations: replay the captured graph of the block (captured on
