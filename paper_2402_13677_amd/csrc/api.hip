@@ -236,12 +236,15 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
       lv[l].diag32[s] = cv.take<float>(n);
       for (int a = 0; a < fd.dim; ++a) lv[l].off32[s][a] = cv.take<float>(n);
     }
+    // b holds, on the tail's top level, the colour-split order the tail
+    // copies straight into LDS (2 hs >= n elements)
+    const long long nb = 2 * ebit::tail_half(lv[l].d);
     lv[l].x64 = cv.take<double>(n);
     lv[l].x64b = cv.take<double>(n);
-    lv[l].b64 = cv.take<double>(n);
+    lv[l].b64 = cv.take<double>(nb > n ? nb : n);
     lv[l].x32 = cv.take<float>(n);
     lv[l].x32b = cv.take<float>(n);
-    lv[l].b32 = cv.take<float>(n);
+    lv[l].b32 = cv.take<float>(nb > n ? nb : n);
   }
   // tail images, per system in FP32 and FP64: the coefficient blocks of the
   // levels of at most EBIT_TAIL_IMG_CELLS cells, then the inverse of the

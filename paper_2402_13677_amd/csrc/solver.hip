@@ -641,7 +641,8 @@ __device__ inline void phases2(const Dims& d, int tx0, int ty0, const U& upd) {
 // residual from the window.
 template <typename T, int TX, int TY, int E, typename R>
 __device__ inline void restrict2(const Dims& d, const Dims& cd, int tx0, int ty0, int H, int PX, int QR, int QX,
-                                 T* __restrict__ bc, T* __restrict__ xcz, const R& res) {
+                                 T* __restrict__ bc, T* __restrict__ xcz, int split, const R& res) {
+  const long long chs = tail_half(cd);
   constexpr int CX = TX / 2, CY = TY / 2;
   for (int t = threadIdx.x; t < CX * CY; t += RB_THREADS) {
     const int ci = tx0 / 2 + t % CX, cj = ty0 / 2 + t / CX;
@@ -656,7 +657,7 @@ __device__ inline void restrict2(const Dims& d, const Dims& cd, int tx0, int ty0
       }
     }
     const long long I = ci + (long long)cd.n[0] * cj;
-    bc[I] = sum;
+    bc[split ? tail_el(cd, chs, ci, cj, 0) : I] = sum;
     xcz[I] = (T)0;
   }
 }
@@ -666,7 +667,7 @@ template <typename T, int TX, int TY, int NSW, int RES>
 __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
                                       const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
                                       T* xs, double* rs, uint8_t* fs, T* __restrict__ bc, T* __restrict__ xcz,
-                                      int dots = 0, const double* __restrict__ qv = nullptr,
+                                      int split, int dots = 0, const double* __restrict__ qv = nullptr,
                                       double* __restrict__ partial = nullptr, int slot = 0, int nslot = 0) {
   using W = Win2<TX, TY, NSW, RES>;
   const Dims& d = op.d;
@@ -745,7 +746,7 @@ __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict
         if (off[a] != (T)0) s -= off[a] * xn[a];
       return s;
     };
-    restrict2<T, TX, TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, res);
+    restrict2<T, TX, TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, split, res);
   }
   if (dots) {
     // the outer loop's z.r and (dots == 1) z.q over this tile, from the
@@ -769,7 +770,7 @@ __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict
 template <typename T, int NSW, int RES>
 __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restrict__ b, const T* __restrict__ xin,
                                         const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
-                                        T* sb, T* __restrict__ bc, T* __restrict__ xcz) {
+                                        T* sb, T* __restrict__ bc, T* __restrict__ xcz, int split) {
   using W = Win2<RB_TX, RB_TY, NSW, RES>;
   const Dims& d = op.d;
   T* xs = sb;
@@ -845,7 +846,7 @@ __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restri
       s += o1[q - W::PX] * xs[q - W::PX];
       return bb[qc] - dg[qc] * xs[q] - s;
     };
-    restrict2<T, RB_TX, RB_TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, res);
+    restrict2<T, RB_TX, RB_TY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, split, res);
   }
 }
 
@@ -889,12 +890,14 @@ __device__ inline void even_child(int ch, int& di, int& dj, int& dk) {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // One tail level in LDS: field f (0 diag, 1 1/diag, 2 + a off[a]) at
-// cb + 2 f hs, x at xb and b at xb + 2 hs.
+// cb + 2 f hs, x at xb and b at bb.  The iterates of all levels form one
+// region, [L[0].xb, L[0].bb), the right-hand sides the next.
 struct TailLevel {
   Dims d;
   int hs;  // colour half length (hw rows, padded to four)
   int cb;
   int xb;
+  int bb;
 };
 
 template <typename T>
@@ -908,7 +911,7 @@ struct TailArgs {
   int inv;             // element offset of that inverse (natural order, transposed) in LDS
   int tmp;             // element offset of EBIT_DENSE_MAX scratch elements in LDS
   const int* inv_ok;   // 1 if the inversion succeeded
-  const T* bg;         // right-hand side of the top tail level (natural order)
+  const T* bg;         // right-hand side of the top tail level (colour-split order, 2 hs elements)
   T* xg;               // its correction (output, natural order)
 };
 
@@ -916,7 +919,7 @@ struct TailArgs {
 // the loops below do not go back to the case table), with float
 // reciprocals for division-free index decoding.
 struct TLev {
-  int n0, n1, n2, N, hs, cb, xb, p0, p1, p2;
+  int n0, n1, n2, N, hs, cb, xb, bb, p0, p1, p2;
   int hw, hc;              // colour slots per grid row and per colour
   float r0, r1, r01, rhw;  // 1/n0, 1/n1, 1/(n0 n1), 1/hw
 };
@@ -930,6 +933,7 @@ __device__ inline TLev tlev(const TailLevel& L) {
   t.hs = L.hs;
   t.cb = L.cb;
   t.xb = L.xb;
+  t.bb = L.bb;
   t.p0 = L.d.per[0];
   t.p1 = L.d.per[1];
   t.p2 = L.d.per[2];
@@ -1057,7 +1061,7 @@ __device__ inline void slot_make(const TLev& d, int h, Slot<DIM>& s, const TLev*
 template <typename T, int DIM, int K, int C, bool FIRST>
 __device__ inline void rb_colour(T* sm, const TLev& d, const Slot<DIM> (&sl)[K]) {
   T* x = sm + d.xb;
-  const T* b = x + 2 * d.hs;
+  const T* b = sm + d.bb;
   const T* di = sm + d.cb + 2 * d.hs;
   T nv[K];
 #pragma unroll
@@ -1095,9 +1099,9 @@ __device__ inline void rb_pre(T* sm, const TLev& d, const TLev& C, int nu1, int 
   }
   // restriction: coarse cells I = t, t + nth, ... in natural order
   const T* x = sm + d.xb;
-  const T* b = x + 2 * d.hs;
+  const T* b = sm + d.bb;
   const T* dg = sm + d.cb;
-  T* bc = sm + C.xb + 2 * C.hs;
+  T* bc = sm + C.bb;
   for (int I = t; I < C.N; I += nth) {
     int ci, cj, ck;
     cell_of<DIM>(C, I, ci, cj, ck);
@@ -1199,7 +1203,7 @@ __device__ inline void tail_wave(const TailArgs<T>& a, T* sm, int l0, int nl, bo
   }
   const TLev L = tlev(a.L[nl - 1]);
   T* x = sm + L.xb;
-  const T* b = x + 2 * L.hs;
+  const T* b = sm + L.bb;
   if (dense) {
     // coarsest level solved exactly, x = A^-1 b with the inverse in natural
     // order: lane t gathers b of cell t, then forms row t
@@ -1270,32 +1274,28 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
 #pragma unroll
       for (int u = 0; u < TAIL_COPY_BATCH; ++u) dst[ei[u]] = v[u];
     }
-    // every level's iterate cleared: a sweep may name a cell not yet swept
-    // (across a wall, with a zero coupling; on a level of odd length the
-    // wrapped cell there has the sweep's own colour)
-    for (int l = 0; l < nl; ++l) {
-      T* x = sm + a.L[l].xb;
-      const int n = 2 * a.L[l].hs;
-      for (int q = tid; q < n; q += nth) x[q] = (T)0;
-    }
-    // the top level's right-hand side, from natural order
+    // every level's iterate cleared (one region): a sweep may name a cell
+    // not yet swept (across a wall, with a zero coupling; on a level of odd
+    // length the wrapped cell there has the sweep's own colour); then the
+    // top level's right-hand side, already in the colour-split order
     const TLev L = tlev(a.L[0]);
-    T* bt = sm + L.xb + 2 * L.hs;
-    const T* bg = a.bg;
-    for (int q0 = tid; q0 < L.N; q0 += 4 * nth) {
-      int qi[4];
-      T v[4];
+    u32x4* xz = reinterpret_cast<u32x4*>(sm + L.xb);
+    const int nz = (L.bb - L.xb) * (int)sizeof(T) / 16;
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int e = tid; e < nz; e += nth) xz[e] = zero;
+    const u32x4* bs = reinterpret_cast<const u32x4*>(a.bg);
+    u32x4* bd = reinterpret_cast<u32x4*>(sm + L.bb);
+    const int nbv = 2 * L.hs * (int)sizeof(T) / 16;
+    for (int e0 = tid; e0 < nbv; e0 += 4 * nth) {
+      int ei[4];
+      u32x4 v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        qi[u] = q0 + u * nth < L.N ? q0 + u * nth : q0;
-        v[u] = bg[qi[u]];
+        ei[u] = e0 + u * nth < nbv ? e0 + u * nth : e0;
+        v[u] = bs[ei[u]];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int i, j, k;
-        cell_of<DIM>(L, qi[u], i, j, k);
-        bt[rb_el(L, i, j, k)] = v[u];
-      }
+      for (int u = 0; u < 4; ++u) bd[ei[u]] = v[u];
     }
   }
   __syncthreads();
@@ -1953,10 +1953,11 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
     int dm = 0;
     if (dots && C.ndot > 0) dm = (dots == 2 || ctl[c].fresh) ? 2 : 1;
     rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz,
-                                        dm, C.q, C.partial, lb, C.ndot);
+                                        C.lt == 1, dm, C.q, C.partial, lb, C.ndot);
   } else {
     if (op.d.dim == 2)
-      rb_fine2d_body<T, TX, TY, NSW, 0>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz);
+      rb_fine2d_body<T, TX, TY, NSW, 0>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz,
+                                        0);
     else
       rb_fine_body<T, TX, TY>(op, r, zin, xc, cd, zout, fzc, bx, by, bz, xs, rs, fs);
   }
@@ -1981,7 +1982,8 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_coarse(const SolveCase<T>* _
   if (!ctl[c].active) return;
   const int lt = xcd_tile(lb, nb);
   if (RES || rows.op.d.dim == 2)
-    rb_coarse2d_body<T, NSW, RES>(rows.op, rows.b, xin, xc, cd, xout, lt % gx, (lt / gx) % gy, buf, bc, xcz);
+    rb_coarse2d_body<T, NSW, RES>(rows.op, rows.b, xin, xc, cd, xout, lt % gx, (lt / gx) % gy, buf, bc, xcz,
+                                  C.lt == l + 1);
   else
     rb_fused_body<T, CoarseRows<T>>(rows, xin, xc, cd, xout, zc, lt % gx, (lt / gx) % gy, lt / (gx * gy),
                                     reinterpret_cast<T(*)[RB_PLANE]>(buf));
@@ -2013,7 +2015,7 @@ __global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const Case
       if (i < op.d.n[0] && j < op.d.n[1] && k < op.d.n[2])
         sum += fine_residual_at<T, double>(op, i, j, k, cell_index(op.d, i, j, k), C.r, x);
     }
-    bc[I] = sum;
+    bc[C.lt == 1 ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = sum;
     xc[I] = (T)0;
   }
 }
@@ -2046,7 +2048,7 @@ __global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const Ca
         sum += b[q] - op.diag[q] * x[q] - coarse_offsum<T>(op, i, j, k, q, x);
       }
     }
-    bc[I] = sum;
+    bc[C.lt == l + 1 ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = sum;
     xc[I] = (T)0;
   }
 }
@@ -2897,17 +2899,21 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       ta.nu2 = o->nu2;
       long long coef = 0;
       tail_lds_elems(pc.lv, pc.nlev, lt[c], &coef);
-      long long cb = 0, xb = coef;
+      long long cb = 0, xr = 0;
+      for (int m = 0; m < ta.nl; ++m) xr += 2 * tail_half(pc.lv[lt[c] + m].d);
+      long long xb = coef, bb = coef + xr;
       for (int m = 0; m < ta.nl; ++m) {
         const EbitLevelHost& L = pc.lv[lt[c] + m];
         ta.L[m].d = L.d;
         ta.L[m].hs = (int)tail_half(L.d);
         ta.L[m].cb = (int)cb;
         ta.L[m].xb = (int)xb;
+        ta.L[m].bb = (int)bb;
         cb += tail_img_elems(L.d);
-        xb += 4 * tail_half(L.d);
+        xb += 2 * tail_half(L.d);
+        bb += 2 * tail_half(L.d);
       }
-      ta.tmp = (int)xb;
+      ta.tmp = (int)bb;
       const int dl = dense_level(pc.lv, pc.nlev);
       ta.dl = dl >= lt[c] ? dl - lt[c] : -1;
       ta.inv = (int)cb;
