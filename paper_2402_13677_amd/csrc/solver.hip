@@ -1081,12 +1081,22 @@ __device__ inline void rb_colour(T* sm, const TLev& d, const Slot<DIM> (&sl)[K])
 // the restriction of its residual into the right-hand side of C: the
 // residual of the colour swept last vanishes (up to rounding) after a
 // Gauss-Seidel sweep, so only the colour-0 children are summed.
-template <typename T, int DIM, int K, typename Sync>
+// Slot of thread t: h = t + u nth, or with PAIR (2D, two slots, one
+// thread per coarse cell) slot m of rows 2r and 2r + 1 for coarse cell
+// t = (m, r), whose colour-0 cells are that coarse cell's two red children.
+template <int DIM, bool PAIR>
+__device__ inline int slot_of(const TLev& d, int t, int u, int nth) {
+  if (!PAIR) return t + u * nth;
+  const int r = qdiv(t, d.hw, d.rhw);
+  return (t - r * d.hw) + d.hw * (2 * r + u);
+}
+
+template <typename T, int DIM, int K, bool PAIR, typename Sync>
 __device__ inline void rb_pre(T* sm, const TLev& d, const TLev& C, int nu1, int t, int nth, Sync sync) {
   Slot<DIM> sl[K];
 #pragma unroll
-  for (int u = 0; u < K; ++u) slot_make<DIM>(d, t + u * nth, sl[u], nullptr);
-  const bool act = t < d.hc;
+  for (int u = 0; u < K; ++u) slot_make<DIM>(d, slot_of<DIM, PAIR>(d, t, u, nth), sl[u], nullptr);
+  const bool act = PAIR ? t < C.N : t < d.hc;
   if (act) rb_colour<T, DIM, K, 0, true>(sm, d, sl);
   sync();
   if (act) rb_colour<T, DIM, K, 1, false>(sm, d, sl);
@@ -1097,11 +1107,28 @@ __device__ inline void rb_pre(T* sm, const TLev& d, const TLev& C, int nu1, int 
     if (act) rb_colour<T, DIM, K, 1, false>(sm, d, sl);
     sync();
   }
-  // restriction: coarse cells I = t, t + nth, ... in natural order
   const T* x = sm + d.xb;
   const T* b = sm + d.bb;
   const T* dg = sm + d.cb;
   T* bc = sm + C.bb;
+  if constexpr (PAIR) {
+    // restriction from the slot tables: the two red children of this
+    // thread's coarse cell, (0,0) then (1,1)
+    if (act) {
+      T sum = 0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = sl[u].el[0];
+        const T r = b[e] - dg[e] * x[e] - rb_nsum<T, DIM>(sm, d, e, sl[u].nb[0]);
+        sum = (sl[u].ok & 1) ? sum + r : sum;
+      }
+      const int cj = qdiv(t, C.n0, C.r0);
+      bc[rb_el(C, t - cj * C.n0, cj, 0)] = sum;
+    }
+    sync();
+    return;
+  }
+  // restriction: coarse cells I = t, t + nth, ... in natural order
   for (int I = t; I < C.N; I += nth) {
     int ci, cj, ck;
     cell_of<DIM>(C, I, ci, cj, ck);
@@ -1131,12 +1158,12 @@ __device__ inline void rb_pre(T* sm, const TLev& d, const TLev& C, int nu1, int 
 // added to the colour-0 cells (the only ones the first sweep, colour 1,
 // reads; colour 1 is recomputed from them and colour 0 again after it, so
 // neither needs the correction itself), then nu2 sweeps, colour 1 then 0.
-template <typename T, int DIM, int K, typename Sync>
+template <typename T, int DIM, int K, bool PAIR, typename Sync>
 __device__ inline void rb_post(T* sm, const TLev& d, const TLev& C, int nu2, int t, int nth, Sync sync) {
   Slot<DIM> sl[K];
 #pragma unroll
-  for (int u = 0; u < K; ++u) slot_make<DIM>(d, t + u * nth, sl[u], &C);
-  const bool act = t < d.hc;
+  for (int u = 0; u < K; ++u) slot_make<DIM>(d, slot_of<DIM, PAIR>(d, t, u, nth), sl[u], &C);
+  const bool act = PAIR ? t < C.N : t < d.hc;
   if (act) {
     T* x = sm + d.xb;
     const T* xc = sm + C.xb;
@@ -1164,20 +1191,29 @@ __host__ __device__ constexpr int tail_kmax() {
   return sizeof(T) == 4 ? 2 : 1;
 }
 
+// FP32 in 2D with one thread per coarse cell available: the row-pair
+// slots (restriction from the slot tables); else one or two slots per
+// thread at stride nth
 template <typename T, int DIM, typename Sync>
 __device__ inline void tail_pre(T* sm, const TLev& d, const TLev& C, int nu1, int t, int nth, Sync sync) {
-  if (tail_kmax<T, DIM>() == 1 || d.hc <= nth)
-    rb_pre<T, DIM, 1>(sm, d, C, nu1, t, nth, sync);
+  constexpr int KM = tail_kmax<T, DIM>();
+  if (DIM == 2 && KM == 2 && C.N <= nth)
+    rb_pre<T, DIM, KM, true>(sm, d, C, nu1, t, nth, sync);
+  else if (KM == 1 || d.hc <= nth)
+    rb_pre<T, DIM, 1, false>(sm, d, C, nu1, t, nth, sync);
   else
-    rb_pre<T, DIM, tail_kmax<T, DIM>()>(sm, d, C, nu1, t, nth, sync);
+    rb_pre<T, DIM, KM, false>(sm, d, C, nu1, t, nth, sync);
 }
 
 template <typename T, int DIM, typename Sync>
 __device__ inline void tail_post(T* sm, const TLev& d, const TLev& C, int nu2, int t, int nth, Sync sync) {
-  if (tail_kmax<T, DIM>() == 1 || d.hc <= nth)
-    rb_post<T, DIM, 1>(sm, d, C, nu2, t, nth, sync);
+  constexpr int KM = tail_kmax<T, DIM>();
+  if (DIM == 2 && KM == 2 && C.N <= nth)
+    rb_post<T, DIM, KM, true>(sm, d, C, nu2, t, nth, sync);
+  else if (KM == 1 || d.hc <= nth)
+    rb_post<T, DIM, 1, false>(sm, d, C, nu2, t, nth, sync);
   else
-    rb_post<T, DIM, tail_kmax<T, DIM>()>(sm, d, C, nu2, t, nth, sync);
+    rb_post<T, DIM, KM, false>(sm, d, C, nu2, t, nth, sync);
 }
 
 // ---- the smallest tail levels by one wavefront ----------------------------
