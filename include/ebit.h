@@ -111,7 +111,9 @@ typedef struct {
                          a block is captured once as a hipGraph and replayed;
                          a case that meets its stop level inside a block
                          skips the rest of it on the device, so results do
-                         not depend on this value, only the host round trips */
+                         not depend on this value, only the host round trips.
+                         The first block of a solve runs as many iterations
+                         as the previous solve of the same system took.     */
   int tail_cells;     /* levels with at most this many cells (and that fit
                          the work-group's LDS) are solved by one work-group
                          kernel; the coarsest level always is [4096]          */

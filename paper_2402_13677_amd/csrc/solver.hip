@@ -11,6 +11,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <utility>
 #include <vector>
@@ -1877,12 +1878,12 @@ struct CaseCtl {
   double stop2;  // the case stops once r.r falls to this level
 };
 
-enum { MASK_ACTIVE = 0, MASK_ALL = 1, MASK_RECHECK = 2, MASK_ZERO = 3 };
+enum { MASK_ACTIVE = 0, MASK_ALL = 1, MASK_ZERO = 3, MASK_STOPPED = 4 };
 __device__ inline bool selected(const CaseCtl& c, int mask) {
   if (mask == MASK_ALL) return true;
   if (mask == MASK_ACTIVE) return c.active != 0;
   if (mask == MASK_ZERO) return c.recheck == 2;
-  return c.recheck != 0;
+  return c.recheck == 1;  // MASK_STOPPED
 }
 
 // Device view of one solve of one case: operator, vectors, hierarchy.
@@ -2130,7 +2131,10 @@ __device__ inline void end_iteration(Scal* sc, CaseCtl* ctl, const CaseCtl& cc, 
   n.fresh = 0;
   n.pend = 0;
   n.pi = cc.pi ^ 1;
-  if (rr <= cc.stop2) n.active = 0;
+  if (rr <= cc.stop2) {
+    n.active = 0;
+    n.recheck = 1;  // its true residual is formed at the end of the block
+  }
   if (!isfinite(rr)) {
     sc->err |= ERR_NAN;
     n.active = 0;
@@ -2269,13 +2273,15 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
     bad = !isfinite(v[0]) || !isfinite(v[1]);
     if (kind == FIN_START) {
       // the start of a solve: b = 0 gives x = 0; a residual already at
-      // rtol |b| stops before the first iteration (the host then confirms
-      // it like any other stop); otherwise iterate down to rtol^2 |b|^2
+      // rtol |b| stops before the first iteration (and is confirmed like
+      // any other stop); otherwise iterate down to rtol^2 |b|^2
       CaseCtl n{0, 1, 0, 0, 0, 0, rtol2 * v[0]};
       if (v[0] == 0.0)
         n.recheck = 2;
       else if (!(v[1] <= n.stop2))
         n.active = 1;
+      else
+        n.recheck = 1;
       ctl[c] = n;
     }
   } else {
@@ -2620,6 +2626,9 @@ struct PlanT {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t graph[2][PLAN_MAX_K + 1] = {};
   bool no_graph = false;
+  // outer iterations of the last solve of each system (most over the
+  // cases): the first block of the next solve runs that many
+  int last_iters[2] = {0, 0};
   // 2D: some / all cases take their dot products from the last fine sweep
   bool anydot = false, alldot = true;
 };
@@ -2822,6 +2831,13 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
   if (P.dim == 2)
     hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_PEND, 1, 3, (int)MASK_ALL,
                        0.0);
+  // cases whose recurrence reached its stop level in this block: the true
+  // residual b - A x, its norm and the floor norm, for the host to judge
+  // from the same read-back
+  hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
+                     P.red.w, (int)MASK_STOPPED, 1);
+  hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_INIT, 3, 0,
+                     (int)MASK_STOPPED, 0.0);
 }
 
 // Run K iterations: replay the captured graph of the block (captured on
@@ -3044,7 +3060,10 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
   std::vector<double> tol2(n, 0.0), floor2(n, 0.0), last_true(n, 0.0), bb(n, 0.0);
   const int check = o.check_every > 0 ? o.check_every : 1;
   for (bool first = true;; first = false) {
-    int K = check;
+    // the first block runs as many iterations as the last solve of this
+    // system took (time steps change the systems little), later ones
+    // check_every
+    int K = first && P.last_iters[sys] > 0 ? std::min(P.last_iters[sys], PLAN_MAX_K) : check;
     int running = 0;
     for (int c = 0; c < n; ++c)
       if (status[c] < 0) {
@@ -3059,10 +3078,10 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
     PK(run_block(P, sys, K, pf));
     PK(hipMemcpyAsync(P.h_blk, P.d_ctl, blk, hipMemcpyDeviceToHost, st));
     PK(hipStreamSynchronize(st));
-    int nre = 0;
     for (int c = 0; c < n; ++c) {
       if (status[c] >= 0) continue;
       const Scal& S = P.h_sc[c];
+      CaseCtl& cc = P.h_ctl[c];
       if (first) {
         bb[c] = S.bb;
         tol2[c] = o.rtol * o.rtol * S.bb;
@@ -3070,36 +3089,15 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
       }
       if (S.err & ERR_NAN) {
         status[c] = 2;
-        P.h_ctl[c].active = 0;
+        cc.active = 0;
       } else if (S.bb == 0.0) {
         status[c] = 0;  // b = 0: x = 0 (cleared on the device)
-        P.h_ctl[c].active = 0;
-        P.h_ctl[c].recheck = 0;
-      } else if (!P.h_ctl[c].active) {
-        P.h_ctl[c].recheck = 1;  // r.r reached its stop level: recompute the true residual
-        ++nre;
-      } else if (S.iters >= o.max_iters) {
-        status[c] = 1;
-        P.h_ctl[c].active = 0;
-      }
-    }
-    if (nre) {
-      PK(hipMemcpyAsync(P.d_ctl, P.h_ctl, n * sizeof(CaseCtl), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                         P.red.w, (int)MASK_RECHECK, 1);
-      hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_INIT, 3, 0,
-                         (int)MASK_RECHECK, 0.0);
-      PK(hipGetLastError());
-      PK(hipMemcpyAsync(P.h_sc, P.d_sc, n * sizeof(Scal), hipMemcpyDeviceToHost, st));
-      PK(hipStreamSynchronize(st));
-      for (int c = 0; c < n; ++c) {
-        if (!P.h_ctl[c].recheck) continue;
-        P.h_ctl[c].recheck = 0;
-        const Scal& S = P.h_sc[c];
-        if (S.err & ERR_NAN) {
-          status[c] = 2;
-          continue;
-        }
+        cc.active = 0;
+        cc.recheck = 0;
+      } else if (cc.recheck == 1) {
+        // the recurrence stopped and the block's end formed the true
+        // residual (S.rr, S.aa)
+        cc.recheck = 0;
         const double rr = S.rr;
         floor2[c] = fc * fc * S.aa;
         // At the representability floor the residual no longer tracks the
@@ -3115,12 +3113,20 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
           // restart the recurrence from the recomputed residual
           ++restarts[c];
           last_true[c] = rr;
-          P.h_ctl[c].active = 1;
-          P.h_ctl[c].fresh = 1;
-          P.h_ctl[c].stop2 = fmax(tol2[c], 1e-12 * rr);
+          cc.active = 1;
+          cc.fresh = 1;
+          cc.stop2 = fmax(tol2[c], 1e-12 * rr);
         }
+      } else if (!cc.active || S.iters >= o.max_iters) {
+        status[c] = 1;
+        cc.active = 0;
       }
     }
+  }
+  {
+    int most = 0;
+    for (int c = 0; c < n; ++c) most = std::max(most, P.h_sc[c].iters);
+    P.last_iters[sys] = most;
   }
   PK(hipEventRecord(P.ev_out, st));
   PK(hipStreamWaitEvent(ust, P.ev_out, 0));
