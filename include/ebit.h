@@ -193,6 +193,27 @@ ebit_status ebit_mass_flux(ebit_ctx* ctx, const double* T, double* mdot_cell,
 ebit_status ebit_project(ebit_ctx* ctx, double* const u_l[3], double* const u_v[3],
                          const double* mdot_cell, double* p, int use_guess, ebit_stats* stats);
 
+/* Sec. 2.4, Eq. extrapolation: `iters` pseudo-time steps of the transport
+ * df/dtau + a . grad f = 0 that carries the cell field q across the interface
+ * into the narrow band (cells whose 3^d block holds an interface cell), with
+ * the geometry of the last ebit_build_coeffs.  a is the band cell's normal
+ * (the normalised sum of the facet normals in its 3^d block) pointing away
+ * from the interface into the cell's own phase.  mode selects the cells that
+ * change (every other cell keeps its value and serves as data):
+ *   EBIT_EXT_LIQ_TO_VAP    vapour band cells, from the liquid values;
+ *   EBIT_EXT_VAP_TO_LIQ    liquid band cells, from the vapour values;
+ *   EBIT_EXT_IFACE_TO_BAND band cells off the interface, from the interface
+ *                          cells (the mass flux).
+ * Steps: first-order upwind, explicit, dtau = h / dim (monotone), every
+ * changing cell from the previous iterate; a term whose upwind cell is beyond
+ * a wall or is neither data nor changing drops out.  q: device, cells,
+ * updated in place (caller-owned).  iters >= 0.  Asynchronous on the context
+ * stream; it reuses the context's solver scratch, so it is not to overlap a
+ * solve of the same context.  EBIT_EINVAL for a NULL q, a bad mode or a
+ * negative count; EBIT_ESTATE before ebit_build_coeffs. */
+typedef enum { EBIT_EXT_LIQ_TO_VAP = 0, EBIT_EXT_VAP_TO_LIQ = 1, EBIT_EXT_IFACE_TO_BAND = 2 } ebit_ext_mode;
+ebit_status ebit_extend(ebit_ctx* ctx, double* q, int mode, int iters);
+
 /* ---- inspection entry points (same conventions) --------------------------- */
 
 /* Copy the geometry of the last ebit_build_coeffs: theta[a] (axis-a faces,

@@ -75,20 +75,23 @@ def _neighbour(case, idx, off):
 
 def band(case, geo):
     """Band membership [N] bool and band normals [N, 3] (zero where the sum
-    of the block's facet normals vanishes or the cell is outside the band)."""
+    of the block's facet normals vanishes or the cell is outside the band).
+
+    Each interface cell is handed to every cell of its 3^d block: the cell c
+    that sees interface cell m at offset o is c = m - o, so looping over the
+    offsets o (x slowest) adds each cell's terms in its own block order."""
     dim = case.dim
     is_if = np.asarray(geo["is_if"]).ravel().astype(bool)
     nF = np.asarray(geo["nF"]).reshape(-1, 3)
     N = is_if.size
-    idx = np.arange(N)
+    src = np.nonzero(is_if)[0]
     inb = np.zeros(N, bool)
     s = np.zeros((N, 3))
     for off in itertools.product((-1, 0, 1), repeat=dim):
-        off = list(off) + [0] * (3 - dim)
-        m, ok = _neighbour(case, idx, off)
-        hit = ok & is_if[m]
-        inb |= hit
-        s += np.where(hit[:, None], nF[m], 0.0)
+        back = [-o for o in off] + [0] * (3 - dim)
+        c, ok = _neighbour(case, src, back)
+        inb[c[ok]] = True
+        np.add.at(s, c[ok], nF[src[ok]])
     L = np.sqrt((s * s).sum(axis=1))
     n = np.where((inb & (L > 0))[:, None], s / np.where(L > 0, L, 1.0)[:, None], 0.0)
     return inb, n

@@ -686,6 +686,22 @@ ebit_status ebit_apply(ebit_ctx* c, int sys, const double* x, double* y) {
   return EBIT_OK;
 }
 
+ebit_status ebit_extend(ebit_ctx* c, double* q, int mode, int iters) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!q) return fail(c, EBIT_EINVAL, "NULL field");
+  if (mode != EBIT_EXT_LIQ_TO_VAP && mode != EBIT_EXT_VAP_TO_LIQ && mode != EBIT_EXT_IFACE_TO_BAND)
+    return fail(c, EBIT_EINVAL, "bad extension mode");
+  if (iters < 0) return fail(c, EBIT_EINVAL, "negative step count");
+  // solver scratch: the codes in the FP32 iterate (4 N bytes), the weights
+  // in the direction and product vectors, the other iterate in b
+  double* w[3] = {c->B.p[0], c->B.p[1], c->B.q};
+  HIPCK(c,
+        ebit_launch_extend(&c->fd, mode, iters, c->flags, c->nF, q, c->bvec, (uint16_t*)c->B.z32, w, c->st),
+        "extend");
+  return EBIT_OK;
+}
+
 ebit_status ebit_heat_rhs(ebit_ctx* c, const double* Ts, double* b) {
   ebit_status s = check_ready(c);
   if (s != EBIT_OK) return s;

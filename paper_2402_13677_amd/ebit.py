@@ -77,6 +77,7 @@ def load():
         "ebit_get_geometry": (i, [vp, vp, vp, vp]),
         "ebit_apply": (i, [vp, i, vp, vp]),
         "ebit_heat_rhs": (i, [vp, vp, vp]),
+        "ebit_extend": (i, [vp, vp, i, i]),
         "ebit_project_rhs": (i, [vp, _P3, _P3, vp, vp]),
         "ebit_levels": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "ebit_profile": (i, [vp, i]),
@@ -105,11 +106,12 @@ def load():
 
 EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "ebit_create", "ebit_destroy",
             "ebit_last_error", "ebit_build_coeffs", "ebit_heat_solve", "ebit_mass_flux", "ebit_project",
-            "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_project_rhs", "ebit_levels",
+            "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_extend", "ebit_project_rhs", "ebit_levels",
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
             "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune"]
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
+EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ, EXT_IFACE_TO_BAND = range(3)
 
 
 class EbitError(RuntimeError):
@@ -245,6 +247,12 @@ class Context:
     def apply(self, system, x, y):
         self._check(self.lib.ebit_apply(self.h, int(system), _ptr(x, torch.float64), _ptr(y, torch.float64)),
                     "ebit_apply")
+
+    def extend(self, q, mode, iters):
+        """Eq. extrapolation: `iters` pseudo-time steps carrying q (cells,
+        in place) into the narrow band; mode EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ
+        or EXT_IFACE_TO_BAND."""
+        self._check(self.lib.ebit_extend(self.h, _ptr(q, torch.float64), int(mode), int(iters)), "ebit_extend")
 
     def heat_rhs(self, T_star, b):
         self._check(self.lib.ebit_heat_rhs(self.h, _ptr(T_star, torch.float64), _ptr(b, torch.float64)),
