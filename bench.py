@@ -303,6 +303,66 @@ def roofline(case, precision, steps, tune=True):
     return ro, rows
 
 
+def extension_bench(case, steps=40, reps=5):
+    """Eq. extrapolation (ebit_extend) on the workload's geometry, each mode
+    with `steps` pseudo-time steps, timed with events on the library's stream
+    (the current torch stream).  Per step: the call's time less that of a
+    call with no steps (the band set-up), over the steps.  Algorithmic bytes
+    of one step, per changing cell: its list entry (8 B), dim weights (8 B
+    each), its value and result (16 B) and up to dim upwind values (8 B
+    each; counted as dim)."""
+    import numpy as np
+    import torch
+    from paper_2402_13677_amd import ebit
+
+    ctx, dc = ebit.context_for(case)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    rng = np.random.default_rng(11)
+    q0 = torch.from_numpy(rng.uniform(-1.0, 1.0, case.ncells)).to("cuda")
+    names = {ebit.EXT_LIQ_TO_VAP: "liq_to_vap", ebit.EXT_VAP_TO_LIQ: "vap_to_liq",
+             ebit.EXT_IFACE_TO_BAND: "iface_to_band"}
+    out = {"steps": steps}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(q, mode, t):
+        ms = []
+        for _ in range(reps):
+            q.copy_(q0)
+            ev[0].record()
+            ctx.extend(q, mode, t)
+            ev[1].record()
+            ev[1].synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        return statistics.median(ms)
+
+    q = q0.clone()
+    for mode, name in names.items():
+        ctx.extend(q, mode, 1)
+        moved = int((q != q0).sum().item())
+        t_full, t_set = timed(q, mode, steps), timed(q, mode, 0)
+        step_s = max(t_full - t_set, 1e-9) * 1e-3 / steps
+        byts = moved * (24.0 + 16.0 * case.dim)
+        out[name] = {"changing_cells": moved, "call_ms": t_full, "setup_ms": t_set, "step_us": step_s * 1e6,
+                     "algorithmic_bytes_per_step": byts, "achieved_GBps": byts / step_s / 1e9,
+                     "frac": byts / step_s / 1e9 / HBM_PEAK_GBS}
+    ctx.close()
+    return out
+
+
+def extension_cpu_baseline(case, steps=40):
+    """The oracle's extension on the same geometry (1 thread): ms per call."""
+    import numpy as np
+    import oracle
+    geo = oracle.geometry.build(case)
+    q0 = np.random.default_rng(11).uniform(-1.0, 1.0, case.ncells)
+    t0 = time.perf_counter()
+    for mode in (0, 1, 2):
+        oracle.extend.extend(case, geo, q0, mode, steps)
+    el = time.perf_counter() - t0
+    return {"ms_per_call": el / 3 * 1e3, "cores": 1, "kind": "oracle",
+            "sample": f"the three modes once each, {steps} steps, on the workload's geometry"}
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -330,6 +390,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default solve schedule")
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
+    ap.add_argument("--no-extension", action="store_true", help="skip the narrow-band extension timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -380,6 +441,10 @@ def main():
     if not args.no_roofline:
         out["roofline"], extra["kernels"] = roofline(case, args.precision, max(5, args.steps // 5),
                                                      tune=schedule if schedule else False)
+    if not args.no_extension:
+        extra["extension"] = extension_bench(case)
+        if not args.no_cpu_baseline:
+            extra["extension"]["cpu_oracle"] = extension_cpu_baseline(case)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))

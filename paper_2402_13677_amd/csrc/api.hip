@@ -693,11 +693,14 @@ ebit_status ebit_extend(ebit_ctx* c, double* q, int mode, int iters) {
   if (mode != EBIT_EXT_LIQ_TO_VAP && mode != EBIT_EXT_VAP_TO_LIQ && mode != EBIT_EXT_IFACE_TO_BAND)
     return fail(c, EBIT_EINVAL, "bad extension mode");
   if (iters < 0) return fail(c, EBIT_EINVAL, "negative step count");
-  // solver scratch: the codes in the FP32 iterate (4 N bytes), the weights
-  // in the direction and product vectors, the other iterate in b
+  // solver scratch: the band and target bytes in the FP32 iterate (4 N
+  // bytes), the target list in the FP64 iterate, the weights in the
+  // direction and product vectors, the list length in the reduction
+  // partials, the other iterate in b
   double* w[3] = {c->B.p[0], c->B.p[1], c->B.q};
   HIPCK(c,
-        ebit_launch_extend(&c->fd, mode, iters, c->flags, c->nF, q, c->bvec, (uint16_t*)c->B.z32, w, c->st),
+        ebit_launch_extend(&c->fd, mode, iters, c->flags, c->nF, q, c->bvec, (uint8_t*)c->B.z32,
+                           (unsigned long long*)c->B.z64, w, (int*)c->B.partial, c->st),
         "extend");
   return EBIT_OK;
 }

@@ -302,10 +302,12 @@ hipError_t ebit_launch_geometry(const ebit::Dims* d, double h, const double* con
                                 const uint8_t* ccol, uint8_t* flags, double* cF, double* nF, double* const th[3],
                                 ebit::Scal* scal, hipStream_t st);
 hipError_t ebit_launch_fill_f64(long long n, double* x, double v, hipStream_t st);
-// Narrow-band extension: code (2 N bytes) and w[0..dim-1] (N doubles each)
-// are scratch; work (N doubles) holds every other iterate.
+// Narrow-band extension.  Scratch: bytes (2 N), list (N entries),
+// w[0..dim-1] (N doubles each), counter (one int); work (N doubles) holds
+// every other iterate.
 hipError_t ebit_launch_extend(const ebit::Dims* d, int mode, int iters, const uint8_t* flags, const double* nF,
-                              double* q, double* work, uint16_t* code, double* const w[3], hipStream_t st);
+                              double* q, double* work, uint8_t* bytes, unsigned long long* list,
+                              double* const w[3], int* counter, hipStream_t st);
 hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
 // Hierarchy builds: host tables of the one-work-group part (2 systems,
 // ebit_build_table_bytes() bytes) are filled once and uploaded by the

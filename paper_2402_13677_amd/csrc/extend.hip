@@ -17,12 +17,16 @@
 //     wrap) and holds data or is a target; all targets from the previous
 //     iterate.
 //
-// Layout.  Per cell a 16-bit code: bit 0 target; per axis d three bits at
-// 1 + 3d: term kept, upwind side is c + e_d, upwind cell is a target.  The
-// weights |a_d| sit in three cell arrays (only targets' entries are written
-// or read).  The iterate alternates between q and a work array: a target
-// reads targets from the current source and every other cell from q, whose
-// non-target entries never change.
+// Layout.  The band comes from a separable dilation of the interface bit
+// (one pass per axis over byte arrays), then a byte per cell marks the
+// targets.  The targets are then listed compactly (order immaterial: every
+// target is updated from the previous iterate): per entry the cell index and
+// a code (per axis d three bits at 3d: term kept, upwind side is c + e_d,
+// upwind cell is a target), and per axis the weight |a_d| (0 when the term
+// is dropped).  A step touches only the listed cells.  The iterate
+// alternates between q and a work array: a target reads targets from the
+// current source and every other cell from q, whose non-target entries
+// never change.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -62,118 +66,163 @@ __device__ inline bool ext_nbr(const Dims& d, int i, int j, int k, int di, int d
   return true;
 }
 
+// OR of the per-cell bit over the three cells c - e_AX, c, c + e_AX; the
+// first pass takes the interface bit of the flags (and clears the list
+// counter)
+__global__ void k_ext_dilate(Dims d, int ax, const uint8_t* __restrict__ flags, const uint8_t* __restrict__ in,
+                             uint8_t* __restrict__ out, int* counter) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.N) return;
+  if (!in && c == 0) *counter = 0;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  uint8_t v = 0;
+#pragma unroll
+  for (int s = -1; s <= 1; ++s) {
+    long long m = c;
+    if (s != 0 && !ext_nbr(d, i, j, k, ax == 0 ? s : 0, ax == 1 ? s : 0, ax == 2 ? s : 0, m)) continue;
+    v |= in ? in[m] : (uint8_t)((flags[m] >> 7) & 1);
+  }
+  out[c] = v;
+}
+
+// Sum of the facet normals of the interface cells in the 3^d block of
+// (i, j, k), the x offset slowest; false if it vanishes
+__device__ inline bool ext_normal(const Dims& d, const uint8_t* flags, const double* nF, int i, int j, int k,
+                                  double s[3]) {
+  const int rz = d.dim == 3 ? 1 : 0;
+  s[0] = s[1] = s[2] = 0.0;
+  for (int di = -1; di <= 1; ++di)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int dk = -rz; dk <= rz; ++dk) {
+        long long m;
+        if (!ext_nbr(d, i, j, k, di, dj, dk, m)) continue;
+        if (!((flags[m] >> 7) & 1)) continue;
+        s[0] += nF[m];
+        s[1] += nF[d.N + m];
+        if (d.dim == 3) s[2] += nF[2 * d.N + m];
+      }
+  return sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) > 0.0;
+}
+
 struct ExtArgs {
   Dims d;
   int mode;
   const uint8_t* flags;
   const double* nF;  // 3 arrays of N: x, y, z
-  uint16_t* code;
+  const uint8_t* band;
+  uint8_t* tgt;
+  unsigned long long* list;
   double* w[3];
+  int* counter;
 };
 
-// pass 1: target bit and the signed velocity a = +-n per target
+// target byte per cell: in the band, of the mode's colour, a normal
 __global__ void k_ext_mark(ExtArgs g) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const Dims& d = g.d;
   if (c >= d.N) return;
-  const uint8_t fc = g.flags[c];
-  uint16_t out = 0;
-  if (ext_candidate(g.mode, fc)) {
+  uint8_t t = 0;
+  if (g.band[c] && ext_candidate(g.mode, g.flags[c])) {
     int i, j, k;
     cell_ijk(d, c, i, j, k);
-    const int rz = d.dim == 3 ? 1 : 0;
-    bool inb = false;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int di = -1; di <= 1; ++di)
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int dk = -rz; dk <= rz; ++dk) {
-          long long m;
-          if (!ext_nbr(d, i, j, k, di, dj, dk, m)) continue;
-          if (!((g.flags[m] >> 7) & 1)) continue;
-          inb = true;
-          s[0] += g.nF[m];
-          s[1] += g.nF[d.N + m];
-          if (d.dim == 3) s[2] += g.nF[2 * d.N + m];
-        }
-    const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-    if (inb && L > 0.0) {
-      out = 1;
-      const double sg = ((fc >> 6) & 1) ? 1.0 : -1.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        if (a < d.dim) g.w[a][c] = sg * (s[a] / L);
-    }
+    double s[3];
+    t = ext_normal(d, g.flags, g.nF, i, j, k, s) ? 1 : 0;
   }
-  g.code[c] = out;
+  g.tgt[c] = t;
 }
 
-// pass 2: which upwind terms a target keeps, and where they are read from.
-// It reads neighbours' target bits and rewrites its own code; a rewrite
-// keeps bit 0, so what a neighbour reads does not depend on the order.
-__global__ void k_ext_terms(ExtArgs g) {
+// the list: every target's kept upwind terms and weights, appended at a slot
+// taken per wave
+__global__ __launch_bounds__(EXT_BLOCK) void k_ext_list(ExtArgs g) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const Dims& d = g.d;
-  if (c >= d.N) return;
-  uint16_t code = g.code[c];
-  if (!(code & 1)) return;
-  int i, j, k;
-  cell_ijk(d, c, i, j, k);
+  const bool act = c < d.N && g.tgt[c];
+  unsigned code = 0;
+  double wt[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
+    double s[3];
+    ext_normal(d, g.flags, g.nF, i, j, k, s);
+    const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const double sg = ((g.flags[c] >> 6) & 1) ? 1.0 : -1.0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (a >= d.dim) continue;
-    const double av = g.w[a][c];
-    bool keep = false, plus = av < 0.0, tgt = false;
-    if (av != 0.0) {
-      const int s = plus ? 1 : -1;
-      long long m;
-      if (ext_nbr(d, i, j, k, a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0, m)) {
-        tgt = g.code[m] & 1;
-        keep = tgt || ext_data(g.mode, g.flags[m]);
+    for (int a = 0; a < 3; ++a) {
+      if (a >= d.dim) continue;
+      const double av = sg * (s[a] / L);
+      bool keep = false, tg = false;
+      const bool plus = av < 0.0;
+      if (av != 0.0) {
+        const int sd = plus ? 1 : -1;
+        long long m;
+        if (ext_nbr(d, i, j, k, a == 0 ? sd : 0, a == 1 ? sd : 0, a == 2 ? sd : 0, m)) {
+          tg = g.tgt[m] != 0;
+          keep = tg || ext_data(g.mode, g.flags[m]);
+        }
       }
+      wt[a] = keep ? fabs(av) : 0.0;
+      code |= (unsigned)((keep ? 1 : 0) | (plus ? 2 : 0) | (tg ? 4 : 0)) << (3 * a);
     }
-    g.w[a][c] = keep ? fabs(av) : 0.0;
-    code |= (uint16_t)((keep ? 1 : 0) | (plus ? 2 : 0) | (tgt ? 4 : 0)) << (1 + 3 * a);
   }
-  g.code[c] = code;
+  // one atomic per wave for the wave's targets
+  const unsigned long long mask = __ballot(act);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(g.counter, __popcll(mask));
+  base = __shfl(base, leader);
+  if (!act) return;
+  const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+  g.list[slot] = (unsigned long long)c | ((unsigned long long)code << 40);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < d.dim) g.w[a][slot] = wt[a];
 }
 
 template <int DIM>
-__global__ __launch_bounds__(EXT_BLOCK) void k_ext_step(Dims d, const uint16_t* __restrict__ code,
+__global__ __launch_bounds__(EXT_BLOCK) void k_ext_step(Dims d, const unsigned long long* __restrict__ list,
+                                                        const int* __restrict__ counter,
                                                         const double* __restrict__ w0, const double* __restrict__ w1,
                                                         const double* __restrict__ w2, const double* q,
                                                         const double* src, double* dst, double lam) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= d.N) return;
-  const uint16_t cd = code[c];
-  if (!(cd & 1)) return;
-  int i, j, k;
-  cell_ijk(d, c, i, j, k);
-  const double f = src[c];
-  double up[DIM], wt[DIM];
-  // every load first
+  const int T = *counter;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long e = list[t];
+    const long long c = (long long)(e & ((1ull << 40) - 1));
+    const unsigned cd = (unsigned)(e >> 40);
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
+    const double f = src[c];
+    double up[DIM], wt[DIM];
+    // every load first
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const int bits = (cd >> (1 + 3 * a)) & 7;
-    up[a] = f;
-    wt[a] = 0.0;
-    if (bits & 1) {
-      const int s = (bits & 2) ? 1 : -1;
-      long long m = c;
-      ext_nbr(d, i, j, k, a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0, m);
-      up[a] = (bits & 4) ? src[m] : q[m];
-      wt[a] = (a == 0 ? w0 : a == 1 ? w1 : w2)[c];
+    for (int a = 0; a < DIM; ++a) {
+      const unsigned bits = (cd >> (3 * a)) & 7;
+      up[a] = f;
+      wt[a] = (a == 0 ? w0 : a == 1 ? w1 : w2)[t];
+      if (bits & 1) {
+        const int s = (bits & 2) ? 1 : -1;
+        long long m = c;
+        ext_nbr(d, i, j, k, a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0, m);
+        up[a] = (bits & 4) ? src[m] : q[m];
+      }
     }
-  }
-  double acc = 0.0;
+    double acc = 0.0;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) acc += wt[a] * (f - up[a]);
-  dst[c] = f - lam * acc;
+    for (int a = 0; a < DIM; ++a) acc += wt[a] * (f - up[a]);
+    dst[c] = f - lam * acc;
+  }
 }
 
-__global__ void k_ext_copy(long long N, const uint16_t* __restrict__ code, const double* __restrict__ src,
-                           double* __restrict__ dst) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < N && (code[c] & 1)) dst[c] = src[c];
+__global__ void k_ext_copy(const unsigned long long* __restrict__ list, const int* __restrict__ counter,
+                           const double* __restrict__ src, double* __restrict__ dst) {
+  const int T = *counter;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (long long)gridDim.x * blockDim.x) {
+    const long long c = (long long)(list[t] & ((1ull << 40) - 1));
+    dst[c] = src[c];
+  }
 }
 
 }  // namespace
@@ -182,35 +231,51 @@ __global__ void k_ext_copy(long long N, const uint16_t* __restrict__ code, const
 using namespace ebit;
 
 extern "C" hipError_t ebit_launch_extend(const Dims* d, int mode, int iters, const uint8_t* flags, const double* nF,
-                                         double* q, double* work, uint16_t* code, double* const w[3],
-                                         hipStream_t st) {
+                                         double* q, double* work, uint8_t* bytes, unsigned long long* list,
+                                         double* const w[3], int* counter, hipStream_t st) {
+  const unsigned nb = (unsigned)((d->N + EXT_BLOCK - 1) / EXT_BLOCK);
+  const unsigned nl = nb < 2048u ? nb : 2048u;
+  uint8_t* A = bytes;
+  uint8_t* B = bytes + d->N;
+  // band = the interface bit dilated along each axis in turn
+  const uint8_t* in = nullptr;
+  uint8_t* out = A;
+  for (int ax = 0; ax < d->dim; ++ax) {
+    hipLaunchKernelGGL(k_ext_dilate, dim3(nb), dim3(EXT_BLOCK), 0, st, *d, ax, flags, in, out, counter);
+    in = out;
+    out = (out == A) ? B : A;
+  }
   ExtArgs g;
   g.d = *d;
   g.mode = mode;
   g.flags = flags;
   g.nF = nF;
-  g.code = code;
+  g.band = in;
+  g.tgt = out;
+  g.list = list;
   for (int a = 0; a < 3; ++a) g.w[a] = w[a];
-  const unsigned nb = (unsigned)((d->N + EXT_BLOCK - 1) / EXT_BLOCK);
+  g.counter = counter;
   hipLaunchKernelGGL(k_ext_mark, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_ext_terms, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_ext_list, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
   const double lam = 1.0 / d->dim;
   const double* w2 = d->dim == 3 ? w[2] : w[0];
   const double* src = q;
   double* dst = work;
   for (int t = 0; t < iters; ++t) {
     if (d->dim == 3)
-      hipLaunchKernelGGL(k_ext_step<3>, dim3(nb), dim3(EXT_BLOCK), 0, st, *d, (const uint16_t*)code,
-                         (const double*)w[0], (const double*)w[1], w2, (const double*)q, src, dst, lam);
+      hipLaunchKernelGGL(k_ext_step<3>, dim3(nl), dim3(EXT_BLOCK), 0, st, *d, (const unsigned long long*)list,
+                         (const int*)counter, (const double*)w[0], (const double*)w[1], w2, (const double*)q, src,
+                         dst, lam);
     else
-      hipLaunchKernelGGL(k_ext_step<2>, dim3(nb), dim3(EXT_BLOCK), 0, st, *d, (const uint16_t*)code,
-                         (const double*)w[0], (const double*)w[1], w2, (const double*)q, src, dst, lam);
+      hipLaunchKernelGGL(k_ext_step<2>, dim3(nl), dim3(EXT_BLOCK), 0, st, *d, (const unsigned long long*)list,
+                         (const int*)counter, (const double*)w[0], (const double*)w[1], w2, (const double*)q, src,
+                         dst, lam);
     src = dst;
     dst = (dst == work) ? q : work;
   }
   // an odd count leaves the last iterate in the work array
   if (src == work)
-    hipLaunchKernelGGL(k_ext_copy, dim3(nb), dim3(EXT_BLOCK), 0, st, d->N, (const uint16_t*)code,
-                       (const double*)work, q);
+    hipLaunchKernelGGL(k_ext_copy, dim3(nl), dim3(EXT_BLOCK), 0, st, (const unsigned long long*)list,
+                       (const int*)counter, (const double*)work, q);
   return hipGetLastError();
 }
