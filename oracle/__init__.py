@@ -22,11 +22,13 @@ approach for phase change: the EBIT method") defines on a uniform grid:
   solve.py     sparse direct solve (SciPy SuperLU) of the assembled systems
   extend.py    narrow-band extension of a cell field across the interface by
                pseudo-time upwind transport (Eq. extrapolation)
+  onefluid.py  one-fluid projection: one face velocity field and the
+               phase-change source in the interface cells (Eq. pc_source)
   closed.py    closed forms used as pins (Stefan problem, Sec. 3.1)
 
 Parity unpinned: the 3D facet rule beyond planar exactness (the paper's EBIT
 is 2D only), saddle cells, and the first-order fallback of the mass-flux
 stencil.  Every other function is pinned by tests under tests/.
 """
-from . import geometry, heat, flux, project, solve, closed, pipeline, extend  # noqa: F401
+from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid  # noqa: F401
 from .geometry import GeometryError  # noqa: F401
