@@ -214,6 +214,20 @@ ebit_status ebit_project(ebit_ctx* ctx, double* const u_l[3], double* const u_v[
 typedef enum { EBIT_EXT_LIQ_TO_VAP = 0, EBIT_EXT_VAP_TO_LIQ = 1, EBIT_EXT_IFACE_TO_BAND = 2 } ebit_ext_mode;
 ebit_status ebit_extend(ebit_ctx* ctx, double* q, int mode, int iters);
 
+/* Sec. 2.3, the one-fluid projection the paper sets against the ghost-fluid
+ * one (Eqs. Poisson_equation and pc_source): one face velocity field u (a <
+ * dim, axis-a face arrays; in: u*, out: u^{n+1}) and, in each interface
+ * cell, the volume source S_pc = mdot S_Gamma / V (1/rho_v - 1/rho_l) on the
+ * right-hand side of div u^{n+1} = S_pc, with S_Gamma the area (3D) or
+ * length (2D) of the cell's facet plane clipped to the cell and V = h^dim
+ * (an evaporating cell is a source).  Face densities, walls and the solve are
+ * those of ebit_project.  mdot_cell: from ebit_mass_flux.  p: output
+ * pressure (cells); if use_guess != 0 it also holds the initial guess.
+ * stats->div_max reports max |div u - S_pc| after the update.  Errors as
+ * ebit_project. */
+ebit_status ebit_project_one_fluid(ebit_ctx* ctx, double* const u[3], const double* mdot_cell, double* p,
+                                   int use_guess, ebit_stats* stats);
+
 /* ---- inspection entry points (same conventions) --------------------------- */
 
 /* Copy the geometry of the last ebit_build_coeffs: theta[a] (axis-a faces,

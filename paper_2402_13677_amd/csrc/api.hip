@@ -658,6 +658,40 @@ ebit_status ebit_project(ebit_ctx* c, double* const ul[3], double* const uv[3], 
   return s;
 }
 
+ebit_status ebit_project_one_fluid(ebit_ctx* c, double* const u[3], const double* mdot, double* p, int use_guess,
+                                   ebit_stats* st) {
+  stats_init(st);
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!u || !mdot || !p) return fail(c, EBIT_EINVAL, "NULL field");
+  for (int a = 0; a < c->grid.dim; ++a)
+    if (!u[a]) return fail(c, EBIT_EINVAL, "NULL velocity array");
+  const double rho[2] = {c->props.rho_v, c->props.rho_l};
+  HIPCK(c, hipEventRecord(c->ev0, c->st), "event");
+  HIPCK(c,
+        ebit_launch_proj_rhs_one(&c->fd, c->grid.h, rho, c->dt, c->grid.p_bc, c->grid.p_val, c->flags, c->th, c->cF,
+                                 c->nF, mdot, u, c->bvec, c->st),
+        "one-fluid rhs");
+  s = run_solve(c, EBIT_SYS_PRESSURE, p, use_guess, st);
+  if (s == EBIT_EHIP) return s;
+  HIPCK(c,
+        ebit_launch_face_update_one(&c->fd, c->grid.h, rho, c->dt, c->grid.p_bc, c->grid.p_val, c->flags, c->th,
+                                    c->cF, c->nF, mdot, u, p, c->B.partial, c->B.scal, c->st),
+        "one-fluid face update");
+  HIPCK(c, hipEventRecord(c->ev1, c->st), "event");
+  Scal hs;
+  HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "status");
+  HIPCK(c, hipStreamSynchronize(c->st), "sync");
+  if (st) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    st->seconds = ms * 1e-3;
+    st->div_max = hs.divmax;
+    st->status = s;
+  }
+  return s;
+}
+
 ebit_status ebit_get_geometry(ebit_ctx* c, double* const theta[3], uint8_t* flags, double* facet) {
   ebit_status s = check_ready(c);
   if (s != EBIT_OK) return s;

@@ -327,6 +327,15 @@ hipError_t ebit_launch_proj_rhs(const ebit::Dims* d, double h, const double rho[
                                 const double pval[6], const uint8_t* flags, const double* const th[3],
                                 const double* nF, const double* mdot, double* const ul[3], double* const uv[3],
                                 double* b, hipStream_t st);
+hipError_t ebit_launch_proj_rhs_one(const ebit::Dims* d, double h, const double rho[2], double dt,
+                                   const int pbc[6], const double pval[6], const uint8_t* flags,
+                                   const double* const th[3], const double* cF, const double* nF,
+                                   const double* mdot, double* const u[3], double* b, hipStream_t st);
+hipError_t ebit_launch_face_update_one(const ebit::Dims* d, double h, const double rho[2], double dt,
+                                      const int pbc[6], const double pval[6], const uint8_t* flags,
+                                      const double* const th[3], const double* cF, const double* nF,
+                                      const double* mdot, double* const u[3], const double* p, double* partial,
+                                      ebit::Scal* scal, hipStream_t st);
 hipError_t ebit_launch_face_update(const ebit::Dims* d, double h, const double rho[2], double dt, const int pbc[6],
                                    const double pval[6], const uint8_t* flags, const double* const th[3],
                                    double* const ul[3], double* const uv[3], const double* p, double* partial,

@@ -283,7 +283,118 @@ struct ProjArgs {
   const double* p;
   double* b;
   double* partial;
+  // one-fluid mode: the single field is ul; cF and the source factor
+  // (1/rho_v - 1/rho_l) / h^d serve the interface cells' volume source
+  int one;
+  const double* cF;
+  double src;
 };
+
+// Area (3D) or length (2D) of the facet plane of interface cell (i, j, k)
+// clipped to the cell: the plane's crossings of the cell's edges (and the
+// cell corners on it) are the clipped polygon's corners.  2D: the distance
+// between the two extreme crossings along the facet.  3D: the corners in
+// angular order about their mean, shoelace sum.
+template <int DIM>
+__device__ double facet_area(const Dims& d, double h, int i, int j, int k, const double* cF, const double* nF) {
+  constexpr int NV = DIM == 3 ? 8 : 4;
+  double c[3], n[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    c[r] = cF[r * d.N + cell_index(d, i, j, k)];
+    n[r] = DIM == 3 || r < 2 ? nF[r * d.N + cell_index(d, i, j, k)] : 0.0;
+  }
+  if (DIM == 2) c[2] = 0.0;
+  double V[NV][3], s[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    V[q][0] = (i + (q & 1)) * h;
+    V[q][1] = (j + ((q >> 1) & 1)) * h;
+    V[q][2] = DIM == 3 ? (k + (q >> 2)) * h : 0.0;
+    s[q] = (V[q][0] - c[0]) * n[0] + (V[q][1] - c[1]) * n[1] + (V[q][2] - c[2]) * n[2];
+  }
+  double P[12][3];
+  int m = 0;
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    if (s[q] == 0.0 && m < 12) {
+      P[m][0] = V[q][0];
+      P[m][1] = V[q][1];
+      P[m][2] = V[q][2];
+      ++m;
+    }
+#pragma unroll
+  for (int a = 0; a < NV; ++a)
+#pragma unroll
+    for (int bit = 1; bit < NV; bit <<= 1) {
+      if (a & bit) continue;
+      const int b = a | bit;
+      if (!(s[a] * s[b] < 0.0) || m >= 12) continue;
+      const double t = s[a] / (s[a] - s[b]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) P[m][r] = V[a][r] + t * (V[b][r] - V[a][r]);
+      ++m;
+    }
+  if (m < DIM) return 0.0;
+  double o[3] = {0.0, 0.0, 0.0};
+  for (int p = 0; p < m; ++p)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) o[r] += P[p][r];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) o[r] /= m;
+  if (DIM == 2) {
+    double tmin = 0.0, tmax = 0.0;
+    for (int p = 0; p < m; ++p) {
+      const double t = -(P[p][0] - o[0]) * n[1] + (P[p][1] - o[1]) * n[0];
+      tmin = p == 0 ? t : fmin(tmin, t);
+      tmax = p == 0 ? t : fmax(tmax, t);
+    }
+    return tmax - tmin;
+  }
+  // in-plane basis: e1 = n x (axis of the smallest |n_r|), e2 = n x e1
+  const int ax = (fabs(n[0]) <= fabs(n[1]) && fabs(n[0]) <= fabs(n[2])) ? 0 : (fabs(n[1]) <= fabs(n[2]) ? 1 : 2);
+  double e1[3] = {ax == 2 ? n[1] : (ax == 1 ? -n[2] : 0.0), ax == 0 ? n[2] : (ax == 2 ? -n[0] : 0.0),
+                  ax == 1 ? n[0] : (ax == 0 ? -n[1] : 0.0)};
+  const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) e1[r] /= l1;
+  const double e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2], n[0] * e1[1] - n[1] * e1[0]};
+  double ang[12], R[12][2];
+  for (int p = 0; p < m; ++p) {
+    const double x[3] = {P[p][0] - o[0], P[p][1] - o[1], P[p][2] - o[2]};
+    R[p][0] = x[0] * e1[0] + x[1] * e1[1] + x[2] * e1[2];
+    R[p][1] = x[0] * e2[0] + x[1] * e2[1] + x[2] * e2[2];
+    ang[p] = atan2(R[p][1], R[p][0]);
+  }
+  // insertion sort by angle
+  for (int p = 1; p < m; ++p) {
+    const double a0 = ang[p], r0 = R[p][0], r1 = R[p][1];
+    int q = p - 1;
+    while (q >= 0 && ang[q] > a0) {
+      ang[q + 1] = ang[q];
+      R[q + 1][0] = R[q][0];
+      R[q + 1][1] = R[q][1];
+      --q;
+    }
+    ang[q + 1] = a0;
+    R[q + 1][0] = r0;
+    R[q + 1][1] = r1;
+  }
+  double acc = 0.0;
+  for (int p = 0; p < m; ++p) {
+    const int nx = p + 1 < m ? p + 1 : 0;
+    acc += R[p][0] * R[nx][1] - R[p][1] * R[nx][0];
+  }
+  return 0.5 * fabs(acc);
+}
+
+// the one-fluid volume source of cell c (zero off the interface)
+__device__ inline double one_fluid_source(const ProjArgs& g, int i, int j, int k, long long c) {
+  if (!(g.flags[c] & F_IF)) return 0.0;
+  const double A = g.d.dim == 3 ? facet_area<3>(g.d, g.h, i, j, k, g.cF, g.nF)
+                                : facet_area<2>(g.d, g.h, i, j, k, g.cF, g.nF);
+  return g.mdot[c] * A * g.src;
+}
 
 // Ghost value on every cut face (Eq. ghost_velocity).  Each cell handles its
 // + faces and, on the first layer, face 0 (the periodic copy of face n).
@@ -328,10 +439,12 @@ __global__ void k_proj_rhs(ProjArgs g) {
   const int ph = (f & F_LIQ) ? 1 : 0;
   double div = 0.0;
   for (int a = 0; a < d.dim; ++a) {
-    const double* u = ph ? g.ul[a] : g.uv[a];
+    const double* u = (ph || g.one) ? g.ul[a] : g.uv[a];
     div += u[face_of_side(d, i, j, k, 2 * a + 1)] - u[face_of_side(d, i, j, k, 2 * a)];
   }
   div = div / g.h;
+  // one-fluid: div u = S_pc in the interface cells
+  if (g.one) div -= one_fluid_source(g, i, j, k, c);
   double bc = 0.0;
   const double ih2 = 1.0 / (g.h * g.h);
   for (int s = 0; s < 2 * d.dim; ++s) {
@@ -391,7 +504,7 @@ __global__ void k_face_update(ProjArgs g) {
     const long long fi = face_of_side(d, i, j, k, s);
     const double dl = beta * grad;
     g.ul[a][fi] = g.ul[a][fi] - dl;
-    g.uv[a][fi] = g.uv[a][fi] - dl;
+    if (!g.one) g.uv[a][fi] = g.uv[a][fi] - dl;
   }
 }
 
@@ -407,10 +520,11 @@ __global__ void k_divmax(ProjArgs g) {
     const int ph = (g.flags[c] & F_LIQ) ? 1 : 0;
     double div = 0.0;
     for (int a = 0; a < d.dim; ++a) {
-      const double* u = ph ? g.ul[a] : g.uv[a];
+      const double* u = (ph || g.one) ? g.ul[a] : g.uv[a];
       div += u[face_of_side(d, i, j, k, 2 * a + 1)] - u[face_of_side(d, i, j, k, 2 * a)];
     }
     div = div / g.h;
+    if (g.one) div -= one_fluid_source(g, i, j, k, c);
     vmax = fmax(vmax, fabs(div));
   }
   __shared__ double sh[4];
@@ -483,6 +597,9 @@ static ProjArgs make_proj(const Dims* d, double h, const double rho[2], double d
   g.p = p;
   g.b = b;
   g.partial = partial;
+  g.one = 0;
+  g.cF = nullptr;
+  g.src = 0.0;
   return g;
 }
 
@@ -494,6 +611,37 @@ extern "C" hipError_t ebit_launch_proj_rhs(const Dims* d, double h, const double
   hipLaunchKernelGGL(k_ghost_vel, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   hipLaunchKernelGGL(k_proj_rhs, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   return hipGetLastError();
+}
+
+// One-fluid mode: the right-hand side from the single field u and the
+// interface cells' volume source; the face update of u alone and the largest
+// |div u - S_pc| after it.
+extern "C" hipError_t ebit_launch_proj_rhs_one(const Dims* d, double h, const double rho[2], double dt,
+                                               const int pbc[6], const double pval[6], const uint8_t* flags,
+                                               const double* const th[3], const double* cF, const double* nF,
+                                               const double* mdot, double* const u[3], double* b, hipStream_t st) {
+  ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nF, mdot, u, u, nullptr, b, nullptr);
+  g.one = 1;
+  g.cF = cF;
+  g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
+  hipLaunchKernelGGL(k_proj_rhs, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t ebit_launch_face_update_one(const Dims* d, double h, const double rho[2], double dt,
+                                                  const int pbc[6], const double pval[6], const uint8_t* flags,
+                                                  const double* const th[3], const double* cF, const double* nF,
+                                                  const double* mdot, double* const u[3], const double* p,
+                                                  double* partial, Scal* scal, hipStream_t st) {
+  ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nF, mdot, u, u, p, nullptr, partial);
+  g.one = 1;
+  g.cF = cF;
+  g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
+  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_divmax, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
 }
 
 extern "C" hipError_t ebit_launch_face_update(const Dims* d, double h, const double rho[2], double dt,

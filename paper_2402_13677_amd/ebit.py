@@ -78,6 +78,7 @@ def load():
         "ebit_apply": (i, [vp, i, vp, vp]),
         "ebit_heat_rhs": (i, [vp, vp, vp]),
         "ebit_extend": (i, [vp, vp, i, i]),
+        "ebit_project_one_fluid": (i, [vp, _P3, vp, vp, i, ctypes.POINTER(Stats)]),
         "ebit_project_rhs": (i, [vp, _P3, _P3, vp, vp]),
         "ebit_levels": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "ebit_profile": (i, [vp, i]),
@@ -106,7 +107,7 @@ def load():
 
 EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "ebit_create", "ebit_destroy",
             "ebit_last_error", "ebit_build_coeffs", "ebit_heat_solve", "ebit_mass_flux", "ebit_project",
-            "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_extend", "ebit_project_rhs", "ebit_levels",
+            "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_extend", "ebit_project_one_fluid", "ebit_project_rhs", "ebit_levels",
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
             "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune"]
@@ -238,6 +239,16 @@ class Context:
                                    _ptr(p, torch.float64), int(use_guess), ctypes.byref(s))
         if check:
             self._check(st, "ebit_project")
+        return s.as_dict()
+
+    def project_one_fluid(self, u, mdot, p, use_guess=False, check=True):
+        """One-fluid projection (Eq. pc_source): u (dim face arrays, in
+        place), mdot per cell, p output; returns the stats as a dict."""
+        s = Stats()
+        st = self.lib.ebit_project_one_fluid(self.h, _p3(u), _ptr(mdot, torch.float64), _ptr(p, torch.float64),
+                                             int(use_guess), ctypes.byref(s))
+        if check:
+            self._check(st, "ebit_project_one_fluid")
         return s.as_dict()
 
     def get_geometry(self, theta=None, flags=None, facet=None):
