@@ -363,6 +363,52 @@ def extension_cpu_baseline(case, steps=40):
             "sample": f"the three modes once each, {steps} steps, on the workload's geometry"}
 
 
+def one_fluid_bench(case, precision, schedule, reps=10):
+    """The one-fluid projection (ebit_project_one_fluid) beside the
+    ghost-fluid one on the workload: median ms per call (right-hand side,
+    solve to 1e-9, face update, divergence check) and outer iterations, with
+    the mass flux of the input temperature."""
+    import torch
+    from paper_2402_13677_amd import ebit
+
+    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
+                             **(schedule or {}))
+    ctx, dc = ebit.context_for(case, opts)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    m = torch.zeros_like(dc.T0)
+    ctx.mass_flux(dc.T0, m)
+    out = {}
+    for name in ("one_fluid", "ghost_fluid"):
+        ms, its, div = [], [], []
+        for r in range(reps + 1):
+            p = torch.zeros_like(dc.T0)
+            ul = [u.clone() for u in dc.u_l]
+            if name == "one_fluid":
+                st = ctx.project_one_fluid(ul, m, p)
+            else:
+                st = ctx.project(ul, [u.clone() for u in dc.u_v], m, p)
+            if r:
+                ms.append(st["seconds"] * 1e3)
+                its.append(st["iters"])
+                div.append(st["div_max"])
+        out[name] = {"ms": statistics.median(ms), "iters": statistics.median(its), "div_max": max(div)}
+    ctx.close()
+    return out
+
+
+def one_fluid_cpu_baseline(case):
+    """The oracle's one-fluid projection (SuperLU direct solve, 1 thread)."""
+    import oracle
+    from oracle import onefluid
+    geo = oracle.geometry.build(case)
+    mdot, _ = oracle.flux.mass_flux(case, geo, case.T0)
+    t0 = time.perf_counter()
+    onefluid.project_one_fluid(case, geo, mdot, case.u_l, oracle.solve.direct)
+    el = time.perf_counter() - t0
+    return {"ms_per_call": el * 1e3, "cores": 1, "kind": "oracle",
+            "sample": "one call on the workload (SciPy SuperLU direct solve)"}
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -391,6 +437,7 @@ def main():
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
     ap.add_argument("--no-extension", action="store_true", help="skip the narrow-band extension timing")
+    ap.add_argument("--no-one-fluid", action="store_true", help="skip the one-fluid projection timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -445,6 +492,10 @@ def main():
         extra["extension"] = extension_bench(case)
         if not args.no_cpu_baseline:
             extra["extension"]["cpu_oracle"] = extension_cpu_baseline(case)
+    if not args.no_one_fluid:
+        extra["one_fluid"] = one_fluid_bench(case, args.precision, schedule)
+        if not args.no_cpu_baseline and case.dim == 2:
+            extra["one_fluid"]["cpu_oracle"] = one_fluid_cpu_baseline(case)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out))
