@@ -438,6 +438,8 @@ def main():
                     help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
     ap.add_argument("--no-extension", action="store_true", help="skip the narrow-band extension timing")
     ap.add_argument("--no-one-fluid", action="store_true", help="skip the one-fluid projection timing")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="time only the narrow-band extension and the one-fluid projection (for profiling them)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -451,6 +453,11 @@ def main():
     case = make_case(args.workload)
     if isinstance(case, list):
         return main_batch(args, case)
+    if args.extras_only:
+        sched = parse_schedule(args.schedule) if args.schedule else None
+        print(json.dumps({"workload": case.name, "extension": extension_bench(case),
+                          "one_fluid": one_fluid_bench(case, args.precision, sched)}))
+        return
     tune = parse_schedule(args.schedule) if args.schedule else (not args.no_autotune)
     elapsed, rec, _, schedule = run_gpu(case, args.precision, args.steps, args.warmup, tune=tune)
     ms_per_step = elapsed / args.steps * 1e3

@@ -169,6 +169,22 @@ __global__ void k_facets(GeoArgs g) {
   if (c >= d.N) return;
   int i, j, k;
   cell_ijk(d, c, i, j, k);
+  const uint8_t liq = g.ccol[c] ? F_LIQ : 0;
+  {
+    // corners of one colour: no edge of the cell carries a marker (markers
+    // sit exactly on the edges whose end colours differ; the marker check
+    // rejects inputs that break this), so the 12 marker loads are skipped
+    const long long vx = d.n[0] + 1, vxy = vx * (d.n[1] + 1), v0 = vidx(d, i, j, k);
+    const uint8_t c0 = g.vcol[v0];
+    bool same = g.vcol[v0 + 1] == c0 && g.vcol[v0 + vx] == c0 && g.vcol[v0 + vx + 1] == c0;
+    if (d.dim == 3)
+      same = same && g.vcol[v0 + vxy] == c0 && g.vcol[v0 + vxy + 1] == c0 && g.vcol[v0 + vxy + vx] == c0 &&
+             g.vcol[v0 + vxy + vx + 1] == c0;
+    if (same) {
+      g.flags[c] = liq;
+      return;
+    }
+  }
   const double h = g.h;
   const int noff = (d.dim == 3) ? 4 : 2;
   double sv[12];
@@ -187,7 +203,6 @@ __global__ void k_facets(GeoArgs g) {
       cnt += isnan(s) ? 0 : 1;
     }
   const int need = (d.dim == 2) ? 2 : 3;
-  const uint8_t liq = g.ccol[c] ? F_LIQ : 0;
   if (cnt < need) {
     g.flags[c] = liq;
     return;
