@@ -1965,12 +1965,20 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   const int fgx = C.fgx, fgy = C.fgy, fzc = C.fzc;
   T* bc = RES ? C.lb[1] : nullptr;
   T* xcz = RES ? C.lx[1][0] : nullptr;
-  if (settle && ctl[c].pend) {
+  // The control word, read once for the whole block: block 0 of the case
+  // may rewrite it (ending the previous iteration) while other blocks start,
+  // and every wave of a block must take the same branch (barriers follow).
+  __shared__ CaseCtl sctl;
+  __shared__ int sact;
+  if (threadIdx.x == 0) sctl = ctl[c];
+  __syncthreads();
+  const CaseCtl cc = sctl;
+  if (settle && cc.pend) {
     // the previous iteration's r.r, reduced by every block in the same
     // fixed order: a case at its stop level skips this V-cycle, and block 0
-    // ends the iteration in its control word
-    const CaseCtl cc = ctl[c];
-    __shared__ int sact;
+    // ends the iteration in its control word.  A block that read the word
+    // after block 0 rewrote it sees pend = 0 and the new active flag: the
+    // same decision.
     double v[3];
     reduce_partials(C.partial + 3 * C.nred, C.nred, 1, false, v);
     if (threadIdx.x == 0) {
@@ -1979,7 +1987,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
     }
     __syncthreads();
     if (!sact) return;
-  } else if (!ctl[c].active) {
+  } else if (!cc.active) {
     return;
   }
   const int lt = xcd_tile(lb, nb);
@@ -1988,7 +1996,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
     // dots (last post-smoothing launch): 1 + [defect correction]; the tile
     // partials replace the separate dot kernel for cases with ndot > 0
     int dm = 0;
-    if (dots && C.ndot > 0) dm = (dots == 2 || ctl[c].fresh) ? 2 : 1;
+    if (dots && C.ndot > 0) dm = (dots == 2 || cc.fresh) ? 2 : 1;
     rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz,
                                         C.lt == 1, dm, C.q, C.partial, lb, C.ndot);
   } else {

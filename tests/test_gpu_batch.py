@@ -204,3 +204,36 @@ def test_c4_uneven_batch_full_size():
         mo, _ = oracle.flux.mass_flux(c, geo, Tn.reshape(c.T0.shape))
         m = b[i][0][0][1].cpu().numpy().ravel()
         assert rel(m, mo) < 1e-12
+
+
+def test_c4_batch_every_schedule_many_steps():
+    """The 64-case batch over every candidate schedule (nu x tail x block
+    length), 8 steps each: every solve converges (a block of the first fine
+    sweep that read the case's control word while block 0 was ending the
+    previous iteration once took the other branch, so its waves missed each
+    other's barriers; such a case ended in NaN now and then)."""
+    import itertools
+    ebit = _ebit()
+    say("[gpu] C4 batch, every schedule, 8 steps")
+    cases = ei.config(3)
+    for nu, tail, k in itertools.product((1, 2, 3), (256, 1024, 4096, 16384), (1, 2, 4)):
+        opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED, nu1=nu, nu2=nu, tail_cells=tail, check_every=k)
+        ctxs, dcs = [], []
+        for c in cases:
+            ctx, dc = ebit.context_for(c, opts)
+            ctxs.append(ctx)
+            dcs.append(dc)
+        fs = [Fields(dc) for dc in dcs]
+        b = ebit.Batch(ctxs)
+        for s in range(8):
+            b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs],
+                           [c.dt for c in cases])
+            sh = b.heat_solve([f.T for f in fs], [f.Tn for f in fs])
+            b.mass_flux([f.Tn for f in fs], [f.m for f in fs])
+            sp = b.project([f.u_l for f in fs], [f.u_v for f in fs], [f.m for f in fs], [f.p for f in fs])
+            assert all(x["status"] == 0 for x in sh + sp), (nu, tail, k, s)
+            for f in fs:
+                f.T.copy_(f.Tn)
+        b.close()
+        for c in ctxs:
+            c.close()
