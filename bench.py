@@ -103,11 +103,13 @@ def parse_schedule(text):
     return {"nu1": nu, "nu2": nu, "tail_cells": tail, "check_every": k}
 
 
-def run_gpu(case, precision, steps, warmup, profile=False, tune=True):
+def run_gpu(case, precision, steps, warmup, profile=False, tune=True, warm=False):
     """Time `steps` full steps after `warmup` untimed ones (and, with tune,
     the untimed schedule autotuning).  With profile, the library also times
-    every launch of each kernel class with hipEvents on its stream; returns
-    (elapsed, records, per-class (launches, ms), schedule)."""
+    every launch of each kernel class with hipEvents on its stream; with
+    warm, each solve starts from the previous step's T and p instead of
+    zero.  Returns (elapsed, records, per-class (launches, ms), schedule);
+    the records also hold the level sizes."""
     import torch
     from paper_2402_13677_amd import ebit
 
@@ -125,9 +127,9 @@ def run_gpu(case, precision, steps, warmup, profile=False, tune=True):
 
     def step(record):
         ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
-        sh = ctx.heat_solve(T, T)
+        sh = ctx.heat_solve(T, T, use_guess=warm)
         sm = ctx.mass_flux(T, mdot)
-        sp = ctx.project(u_l, u_v, mdot, p)
+        sp = ctx.project(u_l, u_v, mdot, p, use_guess=warm)
         if record:
             rec["heat_ms"].append(sh["seconds"] * 1e3)
             rec["proj_ms"].append(sp["seconds"] * 1e3)
@@ -153,8 +155,21 @@ def run_gpu(case, precision, steps, warmup, profile=False, tune=True):
         for kc, name in enumerate(KERNEL_CLASSES):
             kern[name] = ctx.profile_read(kc)
         ctx.profile(False)
+    rec["levels"] = [a * b * c for a, b, c in ctx.levels()]
     ctx.close()
     return elapsed, rec, kern, schedule
+
+
+def cell_updates(rec, schedule, ms_step):
+    """Smoother cell updates per second: per V-cycle nu1 + nu2 sweeps of
+    every level above the exactly solved one (at most 64 cells), over the
+    whole step's time and over the solves' time alone."""
+    sch = schedule or {"nu1": 2, "nu2": 2}
+    per_cycle = (sch["nu1"] + sch["nu2"]) * sum(n for n in rec["levels"] if n > 64)
+    cycles = statistics.mean(h + p for h, p in zip(rec["heat_it"], rec["proj_it"]))
+    solve_ms = statistics.mean(h + p for h, p in zip(rec["heat_ms"], rec["proj_ms"]))
+    upd = cycles * per_cycle
+    return {"per_step": upd, "over_step": upd / (ms_step * 1e-3), "over_solves": upd / (solve_ms * 1e-3)}
 
 
 def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
@@ -469,6 +484,10 @@ def main():
         "div_max": max(rec["div"]),
         "mass_flux_fallbacks": max(rec["fallbacks"]),
     }
+    extra["cell_updates_per_s"] = cell_updates(rec, schedule, ms_per_step)
+    _, recw, _, _ = run_gpu(case, args.precision, max(5, args.steps // 5), 1, tune=schedule or False, warm=True)
+    extra["warm_start"] = {"time_to_1e9_ms": {"heat": med(recw["heat_ms"]), "projection": med(recw["proj_ms"])},
+                           "outer_iters": {"heat": med(recw["heat_it"]), "projection": med(recw["proj_it"])}}
     if args.compare:
         other = "fp64" if args.precision == "mixed" else "mixed"
         el2, rec2, _, _ = run_gpu(case, other, max(5, args.steps // 5), 1, tune=tune)
