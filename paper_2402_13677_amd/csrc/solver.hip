@@ -1506,18 +1506,28 @@ __device__ inline void build_cell_from_coarse(const CoarseOp<double>& op, const 
   store_built(o, I, ci, cj, ck, M, F, cross);
 }
 
-__global__ void k_build_from_fine(FineOp op, BuildOut o) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I < o.cd.N) build_cell_from_fine(op, o, I);
+// One level of both systems in one launch: blocks [0, nb) build the
+// heat system's cells, blocks [nb, 2 nb) the pressure system's.
+__global__ void k_build_from_fine2(FineOp op0, FineOp op1, BuildOut o0, BuildOut o1, unsigned nb) {
+  const bool s1 = blockIdx.x >= nb;
+  const long long I = (long long)(blockIdx.x - (s1 ? nb : 0u)) * blockDim.x + threadIdx.x;
+  if (I >= o0.cd.N) return;
+  if (s1)
+    build_cell_from_fine(op1, o1, I);
+  else
+    build_cell_from_fine(op0, o0, I);
 }
 
-__global__ void k_build_from_coarse(CoarseOp<double> op, BuildOut o) {
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= o.cd.N) return;
-  if (op.d.dim == 3)
-    build_cell_from_coarse<3>(op, o, I);
+template <int DIM>
+__global__ void k_build_from_coarse2(CoarseOp<double> op0, CoarseOp<double> op1, BuildOut o0, BuildOut o1,
+                                     unsigned nb) {
+  const bool s1 = blockIdx.x >= nb;
+  const long long I = (long long)(blockIdx.x - (s1 ? nb : 0u)) * blockDim.x + threadIdx.x;
+  if (I >= o0.cd.N) return;
+  if (s1)
+    build_cell_from_coarse<DIM>(op1, o1, I);
   else
-    build_cell_from_coarse<2>(op, o, I);
+    build_cell_from_coarse<DIM>(op0, o0, I);
 }
 
 
@@ -2324,7 +2334,7 @@ hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st) 
 // The build plan of a context: the first level built by the one-work-group
 // kernel (>= 2; levels of at most EBIT_BUILD_SMALL cells go there) and the
 // per-system tables it reads (host copies; the caller uploads them).
-#define EBIT_BUILD_SMALL 4096
+#define EBIT_BUILD_SMALL 1024
 void ebit_build_tables(const EbitLevelHost* lv, int nlev, int want32, void* host_tabs) {
   BuildTable* tab = (BuildTable*)host_tabs;
   int ls = nlev;
@@ -2372,31 +2382,37 @@ size_t ebit_build_table_bytes(void) { return 2 * sizeof(BuildTable); }
 // the FP64 values when wanted.
 hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, int want32, const void* dev_tabs,
                                 int ls, hipStream_t st) {
-  for (int sys = 0; sys < 2; ++sys)
-    for (int l = 1; l < ls && l < nlev; ++l) {
-      BuildOut o;
-      o.cd = lv[l].d;
-      o.diag = lv[l].diag64[sys];
-      o.mass = lv[l].mass64[sys];
-      o.d32 = want32 ? lv[l].diag32[sys] : nullptr;
-      o.i32 = want32 ? lv[l].img32[sys] : nullptr;
-      o.i64 = want32 ? nullptr : lv[l].img64[sys];
+  // one launch per level for both systems
+  for (int l = 1; l < ls && l < nlev; ++l) {
+    BuildOut o[2];
+    CoarseOp<double> f[2];
+    for (int sys = 0; sys < 2; ++sys) {
+      o[sys].cd = lv[l].d;
+      o[sys].diag = lv[l].diag64[sys];
+      o[sys].mass = lv[l].mass64[sys];
+      o[sys].d32 = want32 ? lv[l].diag32[sys] : nullptr;
+      o[sys].i32 = want32 ? lv[l].img32[sys] : nullptr;
+      o[sys].i64 = want32 ? nullptr : lv[l].img64[sys];
       for (int a = 0; a < 3; ++a) {
-        const bool on = a < o.cd.dim;
-        o.off[a] = on ? lv[l].off64[sys][a] : nullptr;
-        o.o32[a] = (on && want32) ? lv[l].off32[sys][a] : nullptr;
+        const bool on = a < o[sys].cd.dim;
+        o[sys].off[a] = on ? lv[l].off64[sys][a] : nullptr;
+        o[sys].o32[a] = (on && want32) ? lv[l].off32[sys][a] : nullptr;
       }
-      if (l == 1) {
-        hipLaunchKernelGGL(k_build_from_fine, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, op[sys], o);
-      } else {
-        CoarseOp<double> f;
-        f.d = lv[l - 1].d;
-        f.diag = lv[l - 1].diag64[sys];
-        f.mass = lv[l - 1].mass64[sys];
-        for (int a = 0; a < 3; ++a) f.off[a] = (a < f.d.dim) ? lv[l - 1].off64[sys][a] : nullptr;
-        hipLaunchKernelGGL(k_build_from_coarse, dim3(nblk(o.cd.N)), dim3(EBIT_BLOCK), 0, st, f, o);
+      if (l > 1) {
+        f[sys].d = lv[l - 1].d;
+        f[sys].diag = lv[l - 1].diag64[sys];
+        f[sys].mass = lv[l - 1].mass64[sys];
+        for (int a = 0; a < 3; ++a) f[sys].off[a] = (a < f[sys].d.dim) ? lv[l - 1].off64[sys][a] : nullptr;
       }
     }
+    const unsigned nb = nblk(o[0].cd.N);
+    if (l == 1)
+      hipLaunchKernelGGL(k_build_from_fine2, dim3(2 * nb), dim3(EBIT_BLOCK), 0, st, op[0], op[1], o[0], o[1], nb);
+    else if (lv[0].d.dim == 3)
+      hipLaunchKernelGGL(k_build_from_coarse2<3>, dim3(2 * nb), dim3(EBIT_BLOCK), 0, st, f[0], f[1], o[0], o[1], nb);
+    else
+      hipLaunchKernelGGL(k_build_from_coarse2<2>, dim3(2 * nb), dim3(EBIT_BLOCK), 0, st, f[0], f[1], o[0], o[1], nb);
+  }
   if (lv[0].d.dim == 3)
     hipLaunchKernelGGL(k_build_small<3>, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
   else
