@@ -1728,10 +1728,12 @@ __device__ inline void dd_add(double& hi, double& lo, double p, double pe) {
 // of that size).  With the compensated residual the outer loop's restarts
 // steer x to the correctly rounded discrete solution.
 __device__ inline void resid_init_body(const FineOp& op, const double* __restrict__ b, const double* __restrict__ x,
-                                       double* __restrict__ r, double* partial, int lb, int nb) {
+                                       double* __restrict__ r, double* partial, int lb, int nb,
+                                       double* __restrict__ xzero = nullptr) {
   double v[3] = {0, 0, 0};
   CASE_STRIDE(c, op.d.N) {
     const double bc = b[c];
+    if (xzero) xzero[c] = 0.0;  // a cold start: x = 0, so r = b
     double rc = bc, ac = fabs(bc);
     if (x) {
       int i, j, k;
@@ -1920,14 +1922,6 @@ struct SolveCase {
 };
 
 template <typename T>
-__global__ void kb_scal_reset(const SolveCase<T>* __restrict__ cs, CaseCtl* __restrict__ ctl) {
-  Scal* sc = cs[blockIdx.x].sc;
-  int* w = reinterpret_cast<int*>(sc);
-  for (int t = threadIdx.x; t < (int)(sizeof(Scal) / sizeof(int)); t += blockDim.x) w[t] = 0;
-  if (threadIdx.x == 0) ctl[blockIdx.x] = CaseCtl{1, 1, 0, 0, 0, 0, 0.0};
-}
-
-template <typename T>
 __global__ void kb_zero_x(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
                           int mask) {
   int lb, nb;
@@ -1939,13 +1933,13 @@ __global__ void kb_zero_x(const SolveCase<T>* __restrict__ cs, const CaseCtl* __
 
 template <typename T>
 __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
-                              int mask, int use_x) {
+                              int mask, int use_x, int zero_x) {
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   if (!selected(ctl[c], mask)) return;
   const SolveCase<T>& C = cs[c];
   const FineOp op = C.op;
-  resid_init_body(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb);
+  resid_init_body(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb, zero_x ? C.x : nullptr);
 }
 
 template <typename T, int TX, int TY, int NSW, int RES>
@@ -2284,6 +2278,11 @@ __global__ void kb_finalize(const SolveCase<T>* __restrict__ cs, CaseCtl* __rest
   if (threadIdx.x != 0) return;
   Scal* sc = C.sc;
   bool bad = false;
+  if (kind == FIN_START) {
+    // the start of a solve clears the case's scalars
+    int* w = reinterpret_cast<int*>(sc);
+    for (int t = 0; t < (int)(sizeof(Scal) / sizeof(int)); ++t) w[t] = 0;
+  }
   if (kind == FIN_INIT || kind == FIN_START) {
     sc->bb = v[0];
     sc->rr = v[1];
@@ -2859,7 +2858,7 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
   // residual b - A x, its norm and the floor norm, for the host to judge
   // from the same read-back
   hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                     P.red.w, (int)MASK_STOPPED, 1);
+                     P.red.w, (int)MASK_STOPPED, 1, 0);
   hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_INIT, 3, 0,
                      (int)MASK_STOPPED, 0.0);
 }
@@ -3064,15 +3063,12 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
   PK(hipEventRecord(P.ev_in, ust));
   PK(hipStreamWaitEvent(st, P.ev_in, 0));
   PK(hipMemcpyAsync(P.d_cs[sys], P.h_cs[sys], n * sizeof(SolveCase<T>), hipMemcpyHostToDevice, st));
-  // start: the device clears the scalars, forms r = b - A x and decides per
-  // case (b = 0: x = 0; already converged: stopped; else iterate to
-  // rtol |b|); no host round trip before the first block of iterations
-  hipLaunchKernelGGL(kb_scal_reset<T>, dim3(n), dim3(64), 0, st, cs, P.d_ctl);
-  if (!use_guess)
-    hipLaunchKernelGGL(kb_zero_x<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                       P.red.w, (int)MASK_ALL);
+  // start: the device forms r = b - A x (a cold start clears x in the same
+  // pass), then clears the scalars and decides per case (b = 0: x = 0;
+  // already converged: stopped; else iterate to rtol |b|); no host round
+  // trip before the first block of iterations
   hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                     P.red.w, (int)MASK_ALL, use_guess ? 1 : 0);
+                     P.red.w, (int)MASK_ALL, use_guess ? 1 : 0, use_guess ? 0 : 1);
   hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_START, 3, 0, (int)MASK_ALL,
                      o.rtol * o.rtol);
   if (use_guess)
