@@ -459,7 +459,7 @@ def main():
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "one GPU only: sharding over several GPUs is a design note (DESIGN.md, section 11)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
