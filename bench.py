@@ -265,7 +265,21 @@ def cpu_baseline(case, budget_s=15.0, max_steps=30):
     if limiter is not None:
         limiter.unregister() if hasattr(limiter, "unregister") else None
     return {"value": case.ncells * steps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full steps of the same workload ({el:.1f} s, SciPy SuperLU direct solves, 1 thread)"}
+            "sample": f"{steps} full steps of the same workload ({el:.1f} s, SciPy SuperLU direct solves, 1 thread "
+                      f"of {host_cpu()})"}
+
+
+def host_cpu():
+    """The host CPU's model name and logical core count."""
+    name = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical cores"
 
 
 def sweeps_per_launch(dim, schedule):
