@@ -66,6 +66,17 @@ def _check_case(case, counts, seed=0):
     ctx.close()
 
 
+def _aniso3d():
+    """70 x 21 x 19 cells, a ball in the middle: several list blocks."""
+    dim, n = 3, (70, 21, 19)
+    h = 1.0 / 70
+    ls = ei.Ball((0.47, 0.151, 0.137), 0.095, -1.0, dim)
+    vcol, ccol, mk = ei.colours_and_markers(dim, n, h, ls)
+    zero = [np.zeros(ei.face_shape(dim, n, a)) for a in range(dim)]
+    return ei.Case("aniso3d", dim, n, h, ei.Props(), 2e-4, [(0, 0.0)] * 6, [(1, 0.0)] * 6, mk, vcol, ccol,
+                   np.zeros(ei.cell_shape(dim, n)), zero, [z.copy() for z in zero])
+
+
 SMALL = [
     lambda: ei.config(0),
     lambda: ei.random_case(2, 37, 3),
@@ -74,6 +85,7 @@ SMALL = [
     lambda: ei.random_case(3, 16, 8, kind="plane"),
     lambda: ei.film_3d(32, name="film3d_32"),
     lambda: ei.config(1, n=96),
+    _aniso3d,
 ]
 
 

@@ -5,7 +5,8 @@
   by the oracle's mass flux of the input temperature: p to relative L2
   1e-12; u within what the face update, linear in p, makes of the measured
   difference dp of the two pressures (per face beta_f (|dp_lo| + |dp_up|)/h,
-  2 beta_f |dp_c|/h on outflow walls) plus rounding; the reported
+  2 beta_f |dp_c|/h on outflow walls), plus 1e-12 of the update for the face
+  density on cut faces (theta agrees to ~1e-13), plus rounding; the reported
   max |div u - S_pc| at the solve's rounding level.
 * No mass flux: the one-fluid call equals the ghost-fluid call on u_l = u_v
   bit for bit.
@@ -55,6 +56,19 @@ def _aniso():
                    [(0, 0.0)] * 4, [(1, 0.0)] * 4, mk, vcol, ccol, T0, u, [x.copy() for x in u])
 
 
+def _aniso3d():
+    """70 x 21 x 19 cells: two 64-wide tiles in x (the second ragged)."""
+    dim, n = 3, (70, 21, 19)
+    h = 1.0 / 70
+    ls = ei.Ball((0.47, 0.151, 0.137), 0.095, -1.0, dim)
+    vcol, ccol, mk = ei.colours_and_markers(dim, n, h, ls)
+    rng = np.random.default_rng(11)
+    T0 = rng.uniform(-1, 1, ei.cell_shape(dim, n))
+    u = [rng.normal(0, 1e-2, ei.face_shape(dim, n, a)) for a in range(dim)]
+    return ei.Case("aniso3d", dim, n, h, ei.Props(rho_v=0.02, lam_v=0.25, h_lg=40.0), 2e-4,
+                   [(0, 0.0)] * 6, [(1, 0.0)] * 6, mk, vcol, ccol, T0, u, [x.copy() for x in u])
+
+
 CASES = {
     "stefan64": lambda: ei.config(0),
     "ball2d_37": lambda: ei.random_case(2, 37, 3),
@@ -64,6 +78,7 @@ CASES = {
     "plane3d_17_mixedbc": lambda: ei.random_case(3, 17, 6, kind="plane", bc="mixed"),
     "film3d_16_periodic": lambda: ei.film_3d(16),
     "bubble2d_40": lambda: ei.bubble(2, 40, 0.17, 1.0, 0.05, 1000.0, 0.1, sigma_u=1e-3, seed=9),
+    "ball3d_70x21x19_aniso": _aniso3d,
 }
 
 
@@ -97,6 +112,14 @@ def update_bound(case, geo, dp):
         b[only] = 2.0 * beta[only] * adp[cell[only]] / case.h
         out.append(b)
     return out
+
+
+def face_slack(bnd, u_ref, u_star):
+    """Per-face allowance for |u_GPU - u_oracle|: what the pressure
+    difference makes of it (bnd), plus the face density's own difference on
+    cut faces (each side's theta agrees to ~1e-13, so beta_f to ~1e-12 of
+    itself: that much of the update u_ref - u*), plus rounding."""
+    return 1.001 * bnd + 1e-12 * np.abs(u_ref - u_star) + 4e-16 * (np.abs(u_ref) + np.max(np.abs(u_ref)))
 
 
 def reference(case):
@@ -136,7 +159,7 @@ def test_one_fluid_parity(name, precision):
     bnd = update_bound(case, geo, p - ref["p"])
     for a in range(case.dim):
         du = np.abs(u[a] - ref["u"][a])
-        assert np.all(du <= 1.001 * bnd[a] + 4e-16 * (np.abs(ref["u"][a]) + np.max(np.abs(ref["u"][a])))), a
+        assert np.all(du <= face_slack(bnd[a], ref["u"][a], case.u_l[a])), a
     assert st["div_max"] <= 1e-9 * max(np.max(np.abs(ref["b"])), 1e-300)
 
 
@@ -175,7 +198,7 @@ def test_one_fluid_bubble2d_256_full():
         bnd = update_bound(case, geo, p - ref["p"])
         for a in range(case.dim):
             du = np.abs(u[a] - ref["u"][a])
-            assert np.all(du <= 1.001 * bnd[a] + 4e-16 * (np.abs(ref["u"][a]) + np.max(np.abs(ref["u"][a])))), a
+            assert np.all(du <= face_slack(bnd[a], ref["u"][a], case.u_l[a])), a
 
 
 def test_one_fluid_film3d_256_residual():

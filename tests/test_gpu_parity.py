@@ -46,6 +46,7 @@ CASES = {
     "plane3d_17_mixedbc": lambda: ei.random_case(3, 17, 6, kind="plane", bc="mixed"),
     "film3d_16_periodic": lambda: ei.film_3d(16),
     "bubble2d_40": lambda: ei.bubble(2, 40, 0.17, 1.0, 0.05, 1000.0, 0.1, sigma_u=1e-3, seed=9),
+    "ball3d_70x21x19_aniso": lambda: _aniso3d(),
 }
 
 
@@ -60,6 +61,20 @@ def _aniso():
     u = [rng.normal(0, 1e-2, ei.face_shape(dim, n, a)) for a in range(dim)]
     return ei.Case("aniso", dim, n, h, ei.Props(rho_v=0.01, lam_v=0.3, h_lg=50.0), 2e-4,
                    [(0, 0.0)] * 4, [(1, 0.0)] * 4, mk, vcol, ccol, T0, u, [x.copy() for x in u])
+
+
+def _aniso3d():
+    """3D grid of 70 x 21 x 19 cells: two 64-wide tiles in x with a ragged
+    second one, ragged y tiles and z-chunks, odd coarse levels."""
+    dim, n = 3, (70, 21, 19, )
+    h = 1.0 / 70
+    ls = ei.Ball((0.47, 0.151, 0.137), 0.095, -1.0, dim)
+    vcol, ccol, mk = ei.colours_and_markers(dim, n, h, ls)
+    rng = np.random.default_rng(11)
+    T0 = rng.uniform(-1, 1, ei.cell_shape(dim, n))
+    u = [rng.normal(0, 1e-2, ei.face_shape(dim, n, a)) for a in range(dim)]
+    return ei.Case("aniso3d", dim, n, h, ei.Props(rho_v=0.02, lam_v=0.25, h_lg=40.0), 2e-4,
+                   [(0, 0.0)] * 6, [(1, 0.0)] * 6, mk, vcol, ccol, T0, u, [x.copy() for x in u])
 
 
 def gpu_geometry(case):
