@@ -237,3 +237,22 @@ def test_c4_batch_every_schedule_many_steps():
         b.close()
         for c in ctxs:
             c.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_3d_equals_single_contexts(precision):
+    """An uneven 3D batch (walls and a periodic film; sides 12 to 21): the
+    3D work lists (tiles x z-chunks per case) give each case exactly the
+    single-context results."""
+    ebit = _ebit()
+    say(f"[gpu] 3D batch == single contexts ({precision})")
+    cases = [ei.random_case(3, 12, 21), ei.random_case(3, 17, 22, kind="plane"), ei.film_3d(16, name="film16"),
+             ei.random_case(3, 21, 23)]
+    opts = ebit.default_opts(rtol=1e-12, precision=ebit.MIXED if precision == "mixed" else ebit.FP64)
+    a = run_single(cases, opts, 2)
+    b = run_batch(cases, opts, 2)
+    for i, ((sa, ia), (sb, ib)) in enumerate(zip(a, b)):
+        assert ia == ib, (i, ia, ib)
+        for step, (xa, xb) in enumerate(zip(sa, sb)):
+            for q, (u, v) in enumerate(zip(xa, xb)):
+                assert torch.equal(u, v), (i, step, q)
