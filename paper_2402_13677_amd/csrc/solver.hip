@@ -922,6 +922,7 @@ struct TailArgs {
 struct TLev {
   int n0, n1, n2, N, hs, cb, xb, bb, p0, p1, p2;
   int hw, hc;              // colour slots per grid row and per colour
+  int rs1, wy, wz;         // slots per z-plane, and the row offsets of a y / z wrap
   float r0, r1, r01, rhw;  // 1/n0, 1/n1, 1/(n0 n1), 1/hw
 };
 
@@ -940,6 +941,9 @@ __device__ inline TLev tlev(const TailLevel& L) {
   t.p2 = L.d.per[2];
   t.hw = (t.n0 + 1) >> 1;
   t.hc = t.hw * t.n1 * t.n2;
+  t.rs1 = t.hw * t.n1;
+  t.wy = t.hw * (t.n1 - 1);
+  t.wz = t.rs1 * (t.n2 - 1);
   t.r0 = 1.0f / (float)t.n0;
   t.r1 = 1.0f / (float)t.n1;
   t.r01 = 1.0f / (float)(t.n0 * t.n1);
@@ -980,16 +984,27 @@ __device__ inline double tfma(double a, double b, double c) { return __builtin_f
 // Elements of the neighbours of cell (i, j, k) across sides +x, -x, +y, -y,
 // +z, -z, with the periodic wrap.  Across a wall the wrapped cell is named
 // too: the coupling stored there is exactly zero (the build adds no
-// coupling across a wall), so its term vanishes without a test.
+// coupling across a wall), so its term vanishes without a test.  Each one
+// is the cell's row base plus an offset: a neighbour is of the other
+// colour, except across a wrap of a row, column or pile of odd length,
+// where the parity does not change.
 template <int DIM>
 __device__ inline void rb_nbrs(const TLev& d, int i, int j, int k, int (&nb)[6]) {
-  nb[0] = rb_el(d, i + 1 < d.n0 ? i + 1 : 0, j, k);
-  nb[1] = rb_el(d, i > 0 ? i - 1 : d.n0 - 1, j, k);
-  nb[2] = rb_el(d, i, j + 1 < d.n1 ? j + 1 : 0, k);
-  nb[3] = rb_el(d, i, j > 0 ? j - 1 : d.n1 - 1, k);
+  const int c = (i + j + k) & 1;
+  const int R = d.hw * (j + d.n1 * k);
+  const int oth = c ? 0 : d.hs;  // base of the other colour
+  const int sam = c ? d.hs : 0;  // base of this colour
+  const int h = i >> 1;
+  const int cx = ((d.n0 - 1) & 1) ? oth : sam;
+  nb[0] = R + (i + 1 < d.n0 ? oth + ((i + 1) >> 1) : cx);
+  nb[1] = R + (i > 0 ? oth + ((i - 1) >> 1) : cx + ((d.n0 - 1) >> 1));
+  const int cy = ((d.n1 - 1) & 1) ? oth : sam;
+  nb[2] = h + (j + 1 < d.n1 ? oth + R + d.hw : cy + R - d.wy);
+  nb[3] = h + (j > 0 ? oth + R - d.hw : cy + R + d.wy);
   if (DIM == 3) {
-    nb[4] = rb_el(d, i, j, k + 1 < d.n2 ? k + 1 : 0);
-    nb[5] = rb_el(d, i, j, k > 0 ? k - 1 : d.n2 - 1);
+    const int cz = ((d.n2 - 1) & 1) ? oth : sam;
+    nb[4] = h + (k + 1 < d.n2 ? oth + R + d.rs1 : cz + R - d.wz);
+    nb[5] = h + (k > 0 ? oth + R - d.rs1 : cz + R + d.wz);
   }
 }
 
