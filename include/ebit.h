@@ -173,7 +173,9 @@ ebit_status ebit_heat_solve(ebit_ctx* ctx, const double* T_star, double* T, int 
                             ebit_stats* stats);
 
 /* Eqs. mass_flux_computation and normal_gradient.  T: cells, each holding
- * its own phase's temperature.  mdot_cell: output, mdot per cell (0 off the
+ * its own phase's temperature.  With stats NULL the call returns without
+ * waiting for the device (the work is queued on the context stream); with
+ * stats it waits and reports the fallback count.  mdot_cell: output, mdot per cell (0 off the
  * interface), positive for evaporation.  mdot_face[a]: optional outputs
  * (NULL to skip, else all dim non-NULL): mdot on cut faces of axis a (the
  * value of the cell holding the crossing), NaN elsewhere.  The stencil takes

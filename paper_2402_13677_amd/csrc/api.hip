@@ -600,6 +600,8 @@ ebit_status ebit_mass_flux(ebit_ctx* c, const double* T, double* mdot, double* c
         ebit_launch_mass_flux(&c->fd, c->grid.h, lam, c->props.h_lg, c->props.T_sat, c->opts.theta_min, c->flags,
                               c->th, c->cF, c->nF, T, mdot, mface, c->B.scal, c->st),
         "mass flux");
+  // without stats the call does not wait for the device
+  if (!st) return EBIT_OK;
   HIPCK(c, hipEventRecord(c->ev1, c->st), "event");
   Scal hs;
   HIPCK(c, hipMemcpyAsync(&hs, c->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, c->st), "status");

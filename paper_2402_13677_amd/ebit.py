@@ -226,12 +226,14 @@ class Context:
             self._check(st, "ebit_heat_solve")
         return s.as_dict()
 
-    def mass_flux(self, T, mdot, mdot_face=None):
+    def mass_flux(self, T, mdot, mdot_face=None, stats=True):
+        """mdot from T; with stats=False the call does not wait for the
+        device and returns None."""
         s = Stats()
         st = self.lib.ebit_mass_flux(self.h, _ptr(T, torch.float64), _ptr(mdot, torch.float64),
-                                     _p3(mdot_face), ctypes.byref(s))
+                                     _p3(mdot_face), ctypes.byref(s) if stats else None)
         self._check(st, "ebit_mass_flux")
-        return s.as_dict()
+        return s.as_dict() if stats else None
 
     def project(self, u_l, u_v, mdot, p, use_guess=False, check=True):
         s = Stats()
