@@ -305,7 +305,8 @@ ebit_status ebit_batch_build_coeffs(ebit_batch* batch, const double* const marke
                                     const uint8_t* const ccol[], const double dt[]);
 /* ebit_heat_solve / ebit_mass_flux / ebit_project of every case; stats[]
  * (may be NULL) gets each case's figures and status, seconds = the whole
- * batch call; the return value is the first failing case's status. */
+ * batch call; the return value is the first failing case's status.  The
+ * batched mass flux with stats NULL does not wait for the device. */
 ebit_status ebit_batch_heat_solve(ebit_batch* batch, const double* const T_star[], double* const T[], int use_guess,
                                   ebit_stats stats[]);
 ebit_status ebit_batch_mass_flux(ebit_batch* batch, const double* const T[], double* const mdot[], ebit_stats stats[]);

@@ -993,6 +993,8 @@ ebit_status ebit_batch_mass_flux(ebit_batch* b, const double* const T[], double*
                                  x->th, x->cF, x->nF, T[c], mdot[c], nullptr, x->B.scal, b->st),
            "mass flux");
   }
+  // without stats the call does not wait for the device
+  if (!stats) return EBIT_OK;
   BHIPCK(b, hipEventRecord(b->ev1, b->st), "event");
   s = batch_read_scal(b);
   if (s != EBIT_OK) return s;

@@ -369,10 +369,12 @@ class Batch:
             self._check(st, "ebit_batch_heat_solve")
         return [x.as_dict() for x in s]
 
-    def mass_flux(self, T, mdot):
-        s = self._stats()
+    def mass_flux(self, T, mdot, stats=True):
+        """Per-case mdot; with stats=False the call does not wait for the
+        device and returns None."""
+        s = self._stats() if stats else None
         self._check(self.lib.ebit_batch_mass_flux(self.h, _ptrs(T), _ptrs(mdot), s), "ebit_batch_mass_flux")
-        return [x.as_dict() for x in s]
+        return [x.as_dict() for x in s] if stats else None
 
     def autotune(self, b_heat=None, b_press=None, x=None):
         """Batch counterpart of Context.autotune (per-case lists)."""
