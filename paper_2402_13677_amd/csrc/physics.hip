@@ -429,6 +429,7 @@ __global__ void k_ghost_vel(ProjArgs g) {
 }
 
 // b = bc - div_c u_{k(c)}  (right-hand side of the SPD system -L p = b)
+template <bool ONE>
 __global__ void k_proj_rhs(ProjArgs g) {
   const Dims& d = g.d;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,12 +440,12 @@ __global__ void k_proj_rhs(ProjArgs g) {
   const int ph = (f & F_LIQ) ? 1 : 0;
   double div = 0.0;
   for (int a = 0; a < d.dim; ++a) {
-    const double* u = (ph || g.one) ? g.ul[a] : g.uv[a];
+    const double* u = (ph || ONE) ? g.ul[a] : g.uv[a];
     div += u[face_of_side(d, i, j, k, 2 * a + 1)] - u[face_of_side(d, i, j, k, 2 * a)];
   }
   div = div / g.h;
   // one-fluid: div u = S_pc in the interface cells
-  if (g.one) div -= one_fluid_source(g, i, j, k, c);
+  if constexpr (ONE) div -= one_fluid_source(g, i, j, k, c);
   double bc = 0.0;
   const double ih2 = 1.0 / (g.h * g.h);
   for (int s = 0; s < 2 * d.dim; ++s) {
@@ -510,6 +511,7 @@ __global__ void k_face_update(ProjArgs g) {
 
 // max_c |div_c u_{k(c)}| of the updated fields (a separate pass: every face
 // is final when it is read)
+template <bool ONE>
 __global__ void k_divmax(ProjArgs g) {
   const Dims& d = g.d;
   double vmax = 0.0;
@@ -520,11 +522,11 @@ __global__ void k_divmax(ProjArgs g) {
     const int ph = (g.flags[c] & F_LIQ) ? 1 : 0;
     double div = 0.0;
     for (int a = 0; a < d.dim; ++a) {
-      const double* u = (ph || g.one) ? g.ul[a] : g.uv[a];
+      const double* u = (ph || ONE) ? g.ul[a] : g.uv[a];
       div += u[face_of_side(d, i, j, k, 2 * a + 1)] - u[face_of_side(d, i, j, k, 2 * a)];
     }
     div = div / g.h;
-    if (g.one) div -= one_fluid_source(g, i, j, k, c);
+    if constexpr (ONE) div -= one_fluid_source(g, i, j, k, c);
     vmax = fmax(vmax, fabs(div));
   }
   __shared__ double sh[4];
@@ -609,7 +611,7 @@ extern "C" hipError_t ebit_launch_proj_rhs(const Dims* d, double h, const double
                                            double* const uv[3], double* b, hipStream_t st) {
   ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nF, mdot, ul, uv, nullptr, b, nullptr);
   hipLaunchKernelGGL(k_ghost_vel, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_proj_rhs, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_proj_rhs<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   return hipGetLastError();
 }
 
@@ -624,7 +626,7 @@ extern "C" hipError_t ebit_launch_proj_rhs_one(const Dims* d, double h, const do
   g.one = 1;
   g.cF = cF;
   g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
-  hipLaunchKernelGGL(k_proj_rhs, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_proj_rhs<true>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   return hipGetLastError();
 }
 
@@ -638,7 +640,7 @@ extern "C" hipError_t ebit_launch_face_update_one(const Dims* d, double h, const
   g.cF = cF;
   g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
   hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_divmax, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_divmax<true>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
@@ -650,7 +652,7 @@ extern "C" hipError_t ebit_launch_face_update(const Dims* d, double h, const dou
                                               const double* p, double* partial, Scal* scal, hipStream_t st) {
   ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nullptr, nullptr, ul, uv, p, nullptr, partial);
   hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_divmax, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_divmax<false>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
