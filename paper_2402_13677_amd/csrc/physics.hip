@@ -291,20 +291,25 @@ struct ProjArgs {
 };
 
 // Area (3D) or length (2D) of the facet plane of interface cell (i, j, k)
-// clipped to the cell: the plane's crossings of the cell's edges (and the
-// cell corners on it) are the clipped polygon's corners.  2D: the distance
-// between the two extreme crossings along the facet.  3D: the corners in
-// angular order about their mean, shoelace sum.
+// clipped to the cell.  The plane meets the cell's edges (strict sign
+// change of the signed distance) and corners (distance zero) in the
+// clipped polygon's corners.  2D: the distance between the two extreme
+// ones along the facet.  3D: the polygon's side on each face of the cell
+// is the segment between that face's two points, oriented along n x F for
+// the face's outward normal F (counter-clockwise about n); the area is half
+// the sum of (a - c) x (b - c) . n over the sides.  A face lying in the
+// plane contributes no side (its four edges are the neighbouring faces'
+// sides).  Static indices only.
 template <int DIM>
 __device__ double facet_area(const Dims& d, double h, int i, int j, int k, const double* cF, const double* nF) {
   constexpr int NV = DIM == 3 ? 8 : 4;
+  const long long cc = cell_index(d, i, j, k);
   double c[3], n[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    c[r] = cF[r * d.N + cell_index(d, i, j, k)];
-    n[r] = DIM == 3 || r < 2 ? nF[r * d.N + cell_index(d, i, j, k)] : 0.0;
+    c[r] = (DIM == 3 || r < 2) ? cF[r * d.N + cc] : 0.0;
+    n[r] = (DIM == 3 || r < 2) ? nF[r * d.N + cc] : 0.0;
   }
-  if (DIM == 2) c[2] = 0.0;
   double V[NV][3], s[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -313,78 +318,83 @@ __device__ double facet_area(const Dims& d, double h, int i, int j, int k, const
     V[q][2] = DIM == 3 ? (k + (q >> 2)) * h : 0.0;
     s[q] = (V[q][0] - c[0]) * n[0] + (V[q][1] - c[1]) * n[1] + (V[q][2] - c[2]) * n[2];
   }
-  double P[12][3];
-  int m = 0;
-#pragma unroll
-  for (int q = 0; q < NV; ++q)
-    if (s[q] == 0.0 && m < 12) {
-      P[m][0] = V[q][0];
-      P[m][1] = V[q][1];
-      P[m][2] = V[q][2];
-      ++m;
-    }
-#pragma unroll
-  for (int a = 0; a < NV; ++a)
-#pragma unroll
-    for (int bit = 1; bit < NV; bit <<= 1) {
-      if (a & bit) continue;
-      const int b = a | bit;
-      if (!(s[a] * s[b] < 0.0) || m >= 12) continue;
-      const double t = s[a] / (s[a] - s[b]);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) P[m][r] = V[a][r] + t * (V[b][r] - V[a][r]);
-      ++m;
-    }
-  if (m < DIM) return 0.0;
-  double o[3] = {0.0, 0.0, 0.0};
-  for (int p = 0; p < m; ++p)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) o[r] += P[p][r];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) o[r] /= m;
   if (DIM == 2) {
+    // the corners in cyclic order 0, 1, 3, 2 and the edges between them
+    constexpr int cyc[4] = {0, 1, 3, 2};
     double tmin = 0.0, tmax = 0.0;
-    for (int p = 0; p < m; ++p) {
-      const double t = -(P[p][0] - o[0]) * n[1] + (P[p][1] - o[1]) * n[0];
-      tmin = p == 0 ? t : fmin(tmin, t);
-      tmax = p == 0 ? t : fmax(tmax, t);
-    }
-    return tmax - tmin;
-  }
-  // in-plane basis: e1 = n x (axis of the smallest |n_r|), e2 = n x e1
-  const int ax = (fabs(n[0]) <= fabs(n[1]) && fabs(n[0]) <= fabs(n[2])) ? 0 : (fabs(n[1]) <= fabs(n[2]) ? 1 : 2);
-  double e1[3] = {ax == 2 ? n[1] : (ax == 1 ? -n[2] : 0.0), ax == 0 ? n[2] : (ax == 2 ? -n[0] : 0.0),
-                  ax == 1 ? n[0] : (ax == 0 ? -n[1] : 0.0)};
-  const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    int cnt = 0;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) e1[r] /= l1;
-  const double e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2], n[0] * e1[1] - n[1] * e1[0]};
-  double ang[12], R[12][2];
-  for (int p = 0; p < m; ++p) {
-    const double x[3] = {P[p][0] - o[0], P[p][1] - o[1], P[p][2] - o[2]};
-    R[p][0] = x[0] * e1[0] + x[1] * e1[1] + x[2] * e1[2];
-    R[p][1] = x[0] * e2[0] + x[1] * e2[1] + x[2] * e2[2];
-    ang[p] = atan2(R[p][1], R[p][0]);
-  }
-  // insertion sort by angle
-  for (int p = 1; p < m; ++p) {
-    const double a0 = ang[p], r0 = R[p][0], r1 = R[p][1];
-    int q = p - 1;
-    while (q >= 0 && ang[q] > a0) {
-      ang[q + 1] = ang[q];
-      R[q + 1][0] = R[q][0];
-      R[q + 1][1] = R[q][1];
-      --q;
+    for (int m = 0; m < 4; ++m) {
+      const int qa = cyc[m], qb = cyc[(m + 1) & 3];
+      if (s[qa] == 0.0) {
+        const double t = -(V[qa][0] - c[0]) * n[1] + (V[qa][1] - c[1]) * n[0];
+        tmin = cnt ? fmin(tmin, t) : t;
+        tmax = cnt ? fmax(tmax, t) : t;
+        ++cnt;
+      }
+      if (s[qa] * s[qb] < 0.0) {
+        const double w = s[qa] / (s[qa] - s[qb]);
+        const double X = V[qa][0] + w * (V[qb][0] - V[qa][0]), Y = V[qa][1] + w * (V[qb][1] - V[qa][1]);
+        const double tc = -(X - c[0]) * n[1] + (Y - c[1]) * n[0];
+        tmin = cnt ? fmin(tmin, tc) : tc;
+        tmax = cnt ? fmax(tmax, tc) : tc;
+        ++cnt;
+      }
     }
-    ang[q + 1] = a0;
-    R[q + 1][0] = r0;
-    R[q + 1][1] = r1;
+    return cnt >= 2 ? tmax - tmin : 0.0;
   }
   double acc = 0.0;
-  for (int p = 0; p < m; ++p) {
-    const int nx = p + 1 < m ? p + 1 : 0;
-    acc += R[p][0] * R[nx][1] - R[p][1] * R[nx][0];
-  }
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+      int fq[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int bu = (m == 1 || m == 2) ? 1 : 0, bv = (m >= 2) ? 1 : 0;
+        fq[m] = (sd << ax) | (bu << u) | (bv << v);
+      }
+      double A[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
+      int cnt = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int qa = fq[m], qb = fq[(m + 1) & 3];
+        if (s[qa] == 0.0) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            A[r] = cnt == 0 ? V[qa][r] : A[r];
+            B[r] = cnt == 1 ? V[qa][r] : B[r];
+          }
+          ++cnt;
+        }
+        if (s[qa] * s[qb] < 0.0) {
+          const double w = s[qa] / (s[qa] - s[qb]);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const double p = V[qa][r] + w * (V[qb][r] - V[qa][r]);
+            A[r] = cnt == 0 ? p : A[r];
+            B[r] = cnt == 1 ? p : B[r];
+          }
+          ++cnt;
+        }
+      }
+      if (cnt != 2) continue;
+      // direction n x F with F = +-e_ax
+      double dv[3] = {0.0, 0.0, 0.0};
+      const double F = sd ? 1.0 : -1.0;
+      dv[(ax + 2) % 3] = n[(ax + 1) % 3] * F;
+      dv[(ax + 1) % 3] = -n[(ax + 2) % 3] * F;
+      const double along = (B[0] - A[0]) * dv[0] + (B[1] - A[1]) * dv[1] + (B[2] - A[2]) * dv[2];
+      double a3[3], b3[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        a3[r] = (along < 0.0 ? B[r] : A[r]) - c[r];
+        b3[r] = (along < 0.0 ? A[r] : B[r]) - c[r];
+      }
+      acc += (a3[1] * b3[2] - a3[2] * b3[1]) * n[0] + (a3[2] * b3[0] - a3[0] * b3[2]) * n[1] +
+             (a3[0] * b3[1] - a3[1] * b3[0]) * n[2];
+    }
   return 0.5 * fabs(acc);
 }
 
