@@ -116,9 +116,12 @@ struct FineOp {
 // the caller initialises rhs_bc.  mexc = diag + sum_s off[s] accumulated
 // without cancellation (mass, interface and wall terms only): the row in
 // difference form is  A x = mexc x_c + sum_s (-off[s]) (x_c - x_nb(s)).
-template <typename T>
+// SYS >= 0 fixes the system at compile time (a kernel specialised per
+// system carries only that system's terms); -1 reads it from op.
+template <typename T, int SYS = -1>
 __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f, T& diag, T off[6],
                                 T& mass, T& rhs_bc, T* mexc = nullptr) {
+  const int sys = SYS >= 0 ? SYS : op.sys;
   // per-phase values by selection, not by a run-time index, so a register
   // copy of the operator never needs a memory home
   const bool liq = (f & F_LIQ) != 0;
@@ -137,7 +140,7 @@ __device__ inline void fine_row(const FineOp& op, int i, int j, int k, uint8_t f
     const int a = s >> 1, up = s & 1;
     const int ia = (a == 0) ? i : (a == 1) ? j : k;
     const bool wall = !op.d.per[a] && (up ? (ia == op.d.n[a] - 1) : (ia == 0));
-    if (op.sys == EBIT_SYS_HEAT) {
+    if (sys == EBIT_SYS_HEAT) {
       const T lam = (T)coef;
       if (wall) {
         if (op.bc[s] == EBIT_BC_DIRICHLET) {

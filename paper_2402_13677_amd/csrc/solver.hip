@@ -1742,6 +1742,7 @@ __device__ inline void dd_add(double& hi, double& lo, double p, double pe) {
 // rounding of x itself, eps |x| per entry and not smooth, leaves a residual
 // of that size).  With the compensated residual the outer loop's restarts
 // steer x to the correctly rounded discrete solution.
+template <int SYS>
 __device__ inline void resid_init_body(const FineOp& op, const double* __restrict__ b, const double* __restrict__ x,
                                        double* __restrict__ r, double* partial, int lb, int nb,
                                        double* __restrict__ xzero = nullptr) {
@@ -1754,7 +1755,7 @@ __device__ inline void resid_init_body(const FineOp& op, const double* __restric
       int i, j, k;
       cell_ijk(op.d, c, i, j, k);
       double diag, off[6], mass, rb = 0, mx;
-      fine_row<double>(op, i, j, k, op.flags[c], diag, off, mass, rb, &mx);
+      fine_row<double, SYS>(op, i, j, k, op.flags[c], diag, off, mass, rb, &mx);
       const double xc = x[c];
       double hi = bc, lo = 0.0;
       {
@@ -1946,7 +1947,8 @@ __global__ void kb_zero_x(const SolveCase<T>* __restrict__ cs, const CaseCtl* __
   CASE_STRIDE(i, C.op.d.N) C.x[i] = 0.0;
 }
 
-template <typename T>
+// compiled per system (SYS), as the p-update
+template <typename T, int SYS>
 __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
                               int mask, int use_x, int zero_x) {
   int lb, nb;
@@ -1954,7 +1956,19 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
   if (!selected(ctl[c], mask)) return;
   const SolveCase<T>& C = cs[c];
   const FineOp op = C.op;
-  resid_init_body(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb, zero_x ? C.x : nullptr);
+  resid_init_body<SYS>(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb,
+                       zero_x ? C.x : nullptr);
+}
+
+template <typename T>
+void launch_resid_init(int blocks, const SolveCase<T>* cs, const CaseCtl* ctl, WorkList w, int sys, int mask,
+                       int use_x, int zero_x, hipStream_t st) {
+  if (sys == EBIT_SYS_HEAT)
+    hipLaunchKernelGGL((kb_resid_init<T, EBIT_SYS_HEAT>), dim3(blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, w, mask,
+                       use_x, zero_x);
+  else
+    hipLaunchKernelGGL((kb_resid_init<T, EBIT_SYS_PRESSURE>), dim3(blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, w,
+                       mask, use_x, zero_x);
 }
 
 template <typename T, int TX, int TY, int NSW, int RES>
@@ -2172,8 +2186,23 @@ __device__ inline void end_iteration(Scal* sc, CaseCtl* ctl, const CaseCtl& cc, 
 // gamma = z.r and beta from the dots' partials, then p_new = z + beta p_old,
 // q = A p_new, partial p.q (row 2).  Every block reduces the partials itself,
 // in the same fixed order, so no separate reduction launch is needed; block
-// 0 records gamma in the slot of this iteration's parity.
-template <typename T>
+// 0 records gamma in the slot of this iteration's parity.  Compiled per
+// system (SYS) and cell-offset width (I: int below 2^30 cells): the loop is
+// bound by the latency of its gathers, and a row that carries one system's
+// terms with 32-bit offsets needs fewer registers, so more waves are in
+// flight.
+template <typename I>
+__device__ inline void fine_nbrs_t(const Dims& d, int i, int j, int k, I c, I (&m)[6]) {
+  const I s1 = d.n[0], s2 = (I)d.n[0] * d.n[1], N = (I)d.N;
+  m[0] = i > 0 ? c - 1 : c - 1 + s1;
+  m[1] = i + 1 < d.n[0] ? c + 1 : c + 1 - s1;
+  m[2] = j > 0 ? c - s1 : c - s1 + s2;
+  m[3] = j + 1 < d.n[1] ? c + s1 : c + s1 - s2;
+  m[4] = k > 0 ? c - s2 : c - s2 + N;
+  m[5] = k + 1 < d.n[2] ? c + s2 : c + s2 - N;
+}
+
+template <typename T, int SYS, typename I>
 __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
                                   int dc) {
   __shared__ double sbeta;
@@ -2207,20 +2236,21 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   double* p_new = C.p[cc.pi ^ 1];
   double* q = C.q;
   double v[1] = {0};
-  CASE_STRIDE(i0, op.d.N) {
+  const I N = (I)op.d.N, stride = (I)nb * (I)blockDim.x;
+  for (I i0 = (I)xcd_tile(lb, nb) * (I)blockDim.x + (I)threadIdx.x; i0 < N; i0 += stride) {
     int i, j, k;
     cell_ijk(op.d, i0, i, j, k);
     // the direction at the cell and its neighbours, loaded before the row
     // is assembled (see fine_nbrs)
-    long long m[6];
-    fine_nbrs(op.d, i, j, k, i0, m);
+    I m[6];
+    fine_nbrs_t<I>(op.d, i, j, k, i0, m);
     double pn[6];
 #pragma unroll
     for (int qq = 0; qq < 6; ++qq)
       pn[qq] = qq < 2 * op.d.dim ? (first ? (double)z[m[qq]] : (double)z[m[qq]] + beta * p_old[m[qq]]) : 0.0;
     const double pc = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
     double diag, off[6], mass, rb = 0, mx;
-    fine_row<double>(op, i, j, k, op.flags[i0], diag, off, mass, rb, &mx);
+    fine_row<double, SYS>(op, i, j, k, op.flags[i0], diag, off, mass, rb, &mx);
     double s = mx * pc;
 #pragma unroll
     for (int qq = 0; qq < 6; ++qq)
@@ -2669,6 +2699,8 @@ struct PlanT {
   int last_iters[2] = {0, 0};
   // 2D: some / all cases take their dot products from the last fine sweep
   bool anydot = false, alldot = true;
+  // some case has 2^30 cells or more: 64-bit cell offsets in the p-update
+  bool wide = false;
 };
 
 template <typename T>
@@ -2843,7 +2875,24 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
 // correction is the same loop with beta = 0 (x += alpha V(r) with the
 // energy-optimal step alpha = (r.z)/(z.Az), which contracts for any SPD A).
 template <typename T>
-void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st, EbitProfiler* pf) {
+void launch_p_update(const PlanT<T>& P, const SolveCase<T>* cs, int sys, int dc, hipStream_t st) {
+  const dim3 g(P.red.blocks), b(EBIT_BLOCK);
+  const CaseCtl* ctl = P.d_ctl;
+  if (P.wide) {
+    if (sys == EBIT_SYS_HEAT)
+      hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_HEAT, long long>), g, b, 0, st, cs, ctl, P.red.w, dc);
+    else
+      hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_PRESSURE, long long>), g, b, 0, st, cs, ctl, P.red.w, dc);
+  } else {
+    if (sys == EBIT_SYS_HEAT)
+      hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_HEAT, int>), g, b, 0, st, cs, ctl, P.red.w, dc);
+    else
+      hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_PRESSURE, int>), g, b, 0, st, cs, ctl, P.red.w, dc);
+  }
+}
+
+template <typename T>
+void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int sys, int K, hipStream_t st, EbitProfiler* pf) {
   const int dc = P.o.outer == EBIT_OUTER_DC;
   for (int k = 0; k < K; ++k) {
     vcycle_b(P, cs, st, pf);
@@ -2852,8 +2901,7 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
                          P.red.w, dc);
     {
       ProfScope ps(pf, EBIT_KC_OUTER_APPLY, st);
-      hipLaunchKernelGGL(kb_p_update_apply<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs,
-                         (const CaseCtl*)P.d_ctl, P.red.w, dc);
+      launch_p_update(P, cs, sys, dc, st);
     }
     {
       ProfScope ps(pf, EBIT_KC_OUTER_UPDATE, st);
@@ -2872,8 +2920,7 @@ void iterations(const PlanT<T>& P, const SolveCase<T>* cs, int K, hipStream_t st
   // cases whose recurrence reached its stop level in this block: the true
   // residual b - A x, its norm and the floor norm, for the host to judge
   // from the same read-back
-  hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                     P.red.w, (int)MASK_STOPPED, 1, 0);
+  launch_resid_init(P.red.blocks, cs, P.d_ctl, P.red.w, sys, (int)MASK_STOPPED, 1, 0, st);
   hipLaunchKernelGGL(kb_finalize<T>, dim3(P.n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_INIT, 3, 0,
                      (int)MASK_STOPPED, 0.0);
 }
@@ -2884,7 +2931,7 @@ template <typename T>
 hipError_t run_block(PlanT<T>& P, int sys, int K, EbitProfiler* pf) {
   const SolveCase<T>* cs = P.d_cs[sys];
   if ((pf && pf->on) || P.no_graph || K > PLAN_MAX_K) {
-    iterations(P, cs, K, P.ist, pf);
+    iterations(P, cs, sys, K, P.ist, pf);
     return hipGetLastError();
   }
   hipGraphExec_t& ge = P.graph[sys][K];
@@ -2892,7 +2939,7 @@ hipError_t run_block(PlanT<T>& P, int sys, int K, EbitProfiler* pf) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(P.ist, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-      iterations(P, cs, K, P.ist, nullptr);
+      iterations(P, cs, sys, K, P.ist, nullptr);
       e = hipStreamEndCapture(P.ist, &g);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -2902,7 +2949,7 @@ hipError_t run_block(PlanT<T>& P, int sys, int K, EbitProfiler* pf) {
       (void)hipGetLastError();
       ge = nullptr;
       P.no_graph = true;
-      iterations(P, cs, K, P.ist, nullptr);
+      iterations(P, cs, sys, K, P.ist, nullptr);
       return hipGetLastError();
     }
   }
@@ -2959,6 +3006,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       C.sc = P->d_sc + c;
       const Dims& fd = pc.lv[0].d;
       C.nred = red_blocks(fd.N);
+      if (fd.N >= (1LL << 30)) P->wide = true;
       C.nlev = pc.nlev;
       C.lt = lt[c];
       const int fty = P->dim == 3 ? 8 : 4;
@@ -3082,8 +3130,8 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
   // pass), then clears the scalars and decides per case (b = 0: x = 0;
   // already converged: stopped; else iterate to rtol |b|); no host round
   // trip before the first block of iterations
-  hipLaunchKernelGGL(kb_resid_init<T>, dim3(P.red.blocks), dim3(EBIT_BLOCK), 0, st, cs, (const CaseCtl*)P.d_ctl,
-                     P.red.w, (int)MASK_ALL, use_guess ? 1 : 0, use_guess ? 0 : 1);
+  launch_resid_init(P.red.blocks, cs, P.d_ctl, P.red.w, sys, (int)MASK_ALL, use_guess ? 1 : 0, use_guess ? 0 : 1,
+                    st);
   hipLaunchKernelGGL(kb_finalize<T>, dim3(n), dim3(256), 0, st, cs, P.d_ctl, (int)FIN_START, 3, 0, (int)MASK_ALL,
                      o.rtol * o.rtol);
   if (use_guess)
