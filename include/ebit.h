@@ -41,6 +41,10 @@
  *     ebit_status_string() gives a static text; ebit_last_error() gives the
  *     text of the last failure on a context (HIP error strings included).
  *   - Calls on one context must not overlap (one stream, one workspace).
+ *   - Environment: EBIT_WIDE_OFFSETS=1, read when a context or batch is
+ *     created, makes the outer-loop kernels use 64-bit cell offsets at any
+ *     grid size (the form they take from 2^30 cells on); results are the
+ *     same bits.  It exists to test that form on small grids.
  */
 #ifndef EBIT_H
 #define EBIT_H

@@ -8,6 +8,7 @@
 // symmetric and scales like a re-discretisation on the coarse grid.
 // Smoother: red-black Gauss-Seidel (red then black before the correction,
 // black then red after, so the V-cycle is a symmetric preconditioner).
+#include <cstdlib>
 #include <math.h>
 #include <string.h>
 
@@ -2956,10 +2957,18 @@ hipError_t run_block(PlanT<T>& P, int sys, int K, EbitProfiler* pf) {
   return hipGraphLaunch(ge, P.ist);
 }
 
+// EBIT_WIDE_OFFSETS=1 in the environment selects the 64-bit-offset kernels
+// at any size (a test of the form the large grids take; same results).
+bool wide_offsets_env() {
+  const char* e = std::getenv("EBIT_WIDE_OFFSETS");
+  return e && e[0] == '1';
+}
+
 template <typename T>
 hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const ebit_opts* o, int tail_lds, void* mem,
                          size_t bytes) {
   P->n = n;
+  const bool wide_env = wide_offsets_env();
   P->o = *o;
   P->cases.assign(cases, cases + n);
   P->dim = cases[0].lv[0].d.dim;
@@ -3006,7 +3015,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       C.sc = P->d_sc + c;
       const Dims& fd = pc.lv[0].d;
       C.nred = red_blocks(fd.N);
-      if (fd.N >= (1LL << 30)) P->wide = true;
+      if (fd.N >= (1LL << 30) || wide_env) P->wide = true;
       C.nlev = pc.nlev;
       C.lt = lt[c];
       const int fty = P->dim == 3 ? 8 : 4;

@@ -6,7 +6,12 @@ iterate buffers), so the results cannot depend on the order in which the
 work-groups run.  Checked over two steps (graph capture, then replay) for a
 2D bubble in FP64 and mixed precision, a 2D grid of odd size, and a small
 3D film that is periodic along x and z.
+
+The kernels with 64-bit cell offsets (used from 2^30 cells on) give the
+same bits as the 32-bit ones: forced on with EBIT_WIDE_OFFSETS=1 for small
+2D and 3D cases, heat and pressure, FP64 and mixed.
 """
+import os
 import sys
 
 import pytest
@@ -61,6 +66,30 @@ def test_repeat_is_bit_identical(name, idx, n, prec):
     opts = ebit.default_opts(rtol=1e-10, precision=ebit.MIXED if prec == "mixed" else ebit.FP64)
     a, ia = run(case, opts, 2)
     b, ib = run(case, opts, 2)
+    assert ia == ib, (ia, ib)
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert torch.equal(x, y), (name, k)
+
+
+WIDE = [
+    ("bubble2d_96_mixed", 1, 96, "mixed"),
+    ("film3d_32_mixed", 4, 32, "mixed"),
+    ("film3d_32_fp64", 4, 32, "fp64"),
+]
+
+
+@pytest.mark.parametrize("name,idx,n,prec", WIDE, ids=[c[0] for c in WIDE])
+def test_wide_offsets_are_bit_identical(name, idx, n, prec):
+    from paper_2402_13677_amd import ebit
+    say(f"[gpu] 64-bit offsets {name}")
+    case = ei.config(idx, n)
+    opts = ebit.default_opts(rtol=1e-10, precision=ebit.MIXED if prec == "mixed" else ebit.FP64)
+    a, ia = run(case, opts, 2)
+    os.environ["EBIT_WIDE_OFFSETS"] = "1"
+    try:
+        b, ib = run(case, opts, 2)
+    finally:
+        del os.environ["EBIT_WIDE_OFFSETS"]
     assert ia == ib, (ia, ib)
     for k, (x, y) in enumerate(zip(a, b)):
         assert torch.equal(x, y), (name, k)
