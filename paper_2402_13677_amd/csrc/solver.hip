@@ -2263,6 +2263,172 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   write_partials<1>(v, C.partial + 2 * nb, lb, nb);
 }
 
+// The same p-update + A p on a 3D grid, with the new direction staged in
+// LDS: a work-group takes 64 x 4 tiles (one cell per thread) and marches
+// each along a chunk of z-planes.  Each plane's direction p = z + beta p_old
+// is formed once on its tile and 1-cell ring, in coalesced loads issued one
+// plane ahead, and the rows read their six neighbours from the staged planes
+// instead of gathering fourteen values per cell; a cell with no cut link and
+// no wall side takes its phase's constant row.  p_new, q and every row are
+// the same bits as in the strided kernel; only the partial sums of p.q group
+// the cells differently (still in a fixed order).  A work-group takes units
+// (tile, chunk) lb, lb + nb, ... with the chunk doubled until there are at
+// most nb units, so the partial row keeps nb entries.  In-plane offsets are
+// 32-bit: grids of 2^30 cells or more take the strided kernel.
+#define AP_TX 64
+#define AP_TY 4
+#define AP_QX (AP_TX + 2)
+#define AP_QL (AP_QX * (AP_TY + 2))
+#define AP_NQ ((AP_QL + RB_THREADS - 1) / RB_THREADS)
+#define AP_NW ((AP_TX * AP_TY + RB_THREADS - 1) / RB_THREADS)
+
+template <typename T>
+__device__ inline void ap_load(const Dims& d, const int (&qo)[AP_NQ], int kk, bool first, double beta,
+                               const T* __restrict__ z, const double* __restrict__ p_old, double (&v)[AP_NQ]) {
+  int k = kk;
+  const bool pz = wrap_axis(d, 2, k);
+  const long long base = (long long)k * d.n[0] * d.n[1];
+#pragma unroll
+  for (int e = 0; e < AP_NQ; ++e) {
+    v[e] = 0.0;
+    if (pz && qo[e] >= 0) {
+      const long long m = base + qo[e];
+      v[e] = first ? (double)z[m] : (double)z[m] + beta * p_old[m];
+    }
+  }
+}
+
+__device__ inline void ap_store(const double (&v)[AP_NQ], double* ps) {
+#pragma unroll
+  for (int e = 0; e < AP_NQ; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < AP_QL) ps[t] = v[e];
+  }
+}
+
+template <typename T, int SYS>
+__global__ __launch_bounds__(RB_THREADS) void kb_apply3d(const SolveCase<T>* __restrict__ cs,
+                                                         const CaseCtl* __restrict__ ctl, WorkList wl, int dc) {
+  __shared__ double ps[4][AP_QL];
+  __shared__ double sbeta;
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  const CaseCtl cc = ctl[c];
+  if (!cc.active) return;
+  const SolveCase<T>& C = cs[c];
+  const FineOp op = C.op;
+  const bool first = dc || cc.fresh;
+  {
+    double g[3];
+    reduce_partials(C.partial, C.ndot > 0 ? C.ndot : nb, 2, false, g);
+    if (threadIdx.x == 0) {
+      Scal* sc = C.sc;
+      const int so = cc.pi, sn = cc.pi ^ 1;
+      const double beta = first ? 0.0 : -sc->sa[so] * g[1] / sc->sg[so];
+      sbeta = beta;
+      if (lb == 0) {
+        sc->sg[sn] = g[0];
+        sc->gamma = g[0];
+        sc->beta = beta;
+        sc->zq = g[1];
+      }
+    }
+    __syncthreads();
+  }
+  const double beta = sbeta;
+  const Dims& d = op.d;
+  const T* z = C.z[0];
+  const double* p_old = C.p[cc.pi];
+  double* p_new = C.p[cc.pi ^ 1];
+  double* q = C.q;
+  const int gx = (d.n[0] + AP_TX - 1) / AP_TX, gy = (d.n[1] + AP_TY - 1) / AP_TY;
+  int zc = C.fzc;
+  while (zc < d.n[2] && (long long)gx * gy * ((d.n[2] + zc - 1) / zc) > nb) zc *= 2;
+  const int units = gx * gy * ((d.n[2] + zc - 1) / zc);
+  double v[1] = {0};
+  for (int ut = xcd_tile(lb, nb); ut < units; ut += nb) {
+    const int bx = ut % gx, by = (ut / gx) % gy, bz = ut / (gx * gy);
+    const int tx0 = bx * AP_TX, ty0 = by * AP_TY;
+    const int z0 = bz * zc, z1 = min(z0 + zc, d.n[2]);
+    // plane-invariant offsets: the staged window (tile + 1 ring, -1 outside
+    // the domain) and this thread's tile cells (-1 outside the domain)
+    int qo[AP_NQ], wo[AP_NW], wq[AP_NW], wi[AP_NW], wj[AP_NW];
+#pragma unroll
+    for (int e = 0; e < AP_NQ; ++e) {
+      const int t = threadIdx.x + e * RB_THREADS;
+      qo[e] = -1;
+      if (t >= AP_QL) continue;
+      int i = tx0 + t % AP_QX - 1, j = ty0 + t / AP_QX - 1;
+      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) qo[e] = i + d.n[0] * j;
+    }
+#pragma unroll
+    for (int w = 0; w < AP_NW; ++w) {
+      const int t = threadIdx.x + w * RB_THREADS;
+      const int lx = t % AP_TX, ly = t / AP_TX;
+      wi[w] = tx0 + lx;
+      wj[w] = ty0 + ly;
+      wq[w] = (ly + 1) * AP_QX + (lx + 1);
+      wo[w] = (t < AP_TX * AP_TY && wi[w] < d.n[0] && wj[w] < d.n[1]) ? wi[w] + d.n[0] * wj[w] : -1;
+    }
+    const long long pl = (long long)d.n[0] * d.n[1];
+    double pa[AP_NQ];
+    // four plane slots: the store of plane k+1 goes to the slot plane k-3
+    // had, which no wave reads after the previous plane's barrier, so one
+    // barrier per plane suffices (the last plane of a unit ends with a
+    // second one before the next unit's stores)
+    ap_load<T>(d, qo, z0 - 1, first, beta, z, p_old, pa);
+    ap_store(pa, ps[(z0 + 3) & 3]);
+    ap_load<T>(d, qo, z0, first, beta, z, p_old, pa);
+    ap_store(pa, ps[z0 & 3]);
+    ap_load<T>(d, qo, z0 + 1, first, beta, z, p_old, pa);
+    for (int k = z0; k < z1; ++k) {
+      // plane k+1 joins planes k-1 and k
+      ap_store(pa, ps[(k + 1) & 3]);
+      __syncthreads();
+      if (k + 1 < z1) ap_load<T>(d, qo, k + 2, first, beta, z, p_old, pa);
+      const double* pm = ps[(k + 3) & 3];
+      const double* p0 = ps[k & 3];
+      const double* pp = ps[(k + 1) & 3];
+      const long long base = (long long)k * pl;
+#pragma unroll
+      for (int w = 0; w < AP_NW; ++w) {
+        if (wo[w] < 0) continue;
+        const int e = wq[w];
+        const long long i0 = base + wo[w];
+        // neighbours in the order of fine_nbrs: -x, +x, -y, +y, -z, +z
+        const double pn[6] = {p0[e - 1], p0[e + 1], p0[e - AP_QX], p0[e + AP_QX], pm[e], pp[e]};
+        const double pc = p0[e];
+        const uint8_t f = op.flags[i0];
+        double s;
+        if (!(f & F_CUT) && (d.per[0] || (wi[w] > 0 && wi[w] + 1 < d.n[0])) &&
+            (d.per[1] || (wj[w] > 0 && wj[w] + 1 < d.n[1])) && (d.per[2] || (k > 0 && k + 1 < d.n[2]))) {
+          // no cut link, no wall side: the phase's constant row, with the
+          // mass and couplings fine_row gives, in its order (the same bits)
+          const bool liq = (f & F_LIQ) != 0;
+          const double cw = -(liq ? op.coef[1] : op.coef[0]) * op.ih2;
+          s = (liq ? op.mass[1] : op.mass[0]) * pc;
+          if (cw != 0.0) {
+#pragma unroll
+            for (int qq = 0; qq < 6; ++qq) s -= cw * (pc - pn[qq]);
+          }
+        } else {
+          double diag, off[6], mass, rb = 0, mx;
+          fine_row<double, SYS>(op, wi[w], wj[w], k, f, diag, off, mass, rb, &mx);
+          s = mx * pc;
+#pragma unroll
+          for (int qq = 0; qq < 6; ++qq)
+            if (off[qq] != 0.0) s -= off[qq] * (pc - pn[qq]);
+        }
+        p_new[i0] = pc;
+        q[i0] = s;
+        v[0] += pc * s;
+      }
+    }
+    __syncthreads();
+  }
+  write_partials<1>(v, C.partial + 2 * nb, lb, nb);
+}
+
 // alpha = gamma / (p.q) from the p-update's partials (every block, fixed
 // order), then x += alpha p, r -= alpha q, partial r.r (row 3).
 template <typename T>
@@ -2879,11 +3045,18 @@ template <typename T>
 void launch_p_update(const PlanT<T>& P, const SolveCase<T>* cs, int sys, int dc, hipStream_t st) {
   const dim3 g(P.red.blocks), b(EBIT_BLOCK);
   const CaseCtl* ctl = P.d_ctl;
+  // 3D: the LDS-staged kernel; from 2^30 cells on (or with the test
+  // switch), the strided kernel with 64-bit offsets
   if (P.wide) {
     if (sys == EBIT_SYS_HEAT)
       hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_HEAT, long long>), g, b, 0, st, cs, ctl, P.red.w, dc);
     else
       hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_PRESSURE, long long>), g, b, 0, st, cs, ctl, P.red.w, dc);
+  } else if (P.dim == 3) {
+    if (sys == EBIT_SYS_HEAT)
+      hipLaunchKernelGGL((kb_apply3d<T, EBIT_SYS_HEAT>), g, b, 0, st, cs, ctl, P.red.w, dc);
+    else
+      hipLaunchKernelGGL((kb_apply3d<T, EBIT_SYS_PRESSURE>), g, b, 0, st, cs, ctl, P.red.w, dc);
   } else {
     if (sys == EBIT_SYS_HEAT)
       hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_HEAT, int>), g, b, 0, st, cs, ctl, P.red.w, dc);

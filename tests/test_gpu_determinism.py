@@ -7,9 +7,11 @@ work-groups run.  Checked over two steps (graph capture, then replay) for a
 2D bubble in FP64 and mixed precision, a 2D grid of odd size, and a small
 3D film that is periodic along x and z.
 
-The kernels with 64-bit cell offsets (used from 2^30 cells on) give the
-same bits as the 32-bit ones: forced on with EBIT_WIDE_OFFSETS=1 for small
-2D and 3D cases, heat and pressure, FP64 and mixed.
+In 2D the strided p-update with 64-bit cell offsets (used from 2^30 cells
+on) gives the same bits as the 32-bit one: forced on with
+EBIT_WIDE_OFFSETS=1, heat and pressure, FP64 and mixed.  (In 3D the switch
+replaces the LDS-staged p-update, whose p.q partial sums group the cells
+differently; the parity tests run that form against the oracle.)
 """
 import os
 import sys
@@ -73,8 +75,7 @@ def test_repeat_is_bit_identical(name, idx, n, prec):
 
 WIDE = [
     ("bubble2d_96_mixed", 1, 96, "mixed"),
-    ("film3d_32_mixed", 4, 32, "mixed"),
-    ("film3d_32_fp64", 4, 32, "fp64"),
+    ("bubble2d_45_fp64", 1, 45, "fp64"),
 ]
 
 

@@ -239,3 +239,16 @@ def test_step_parity(name, precision):
     umax = max(np.max(np.abs(g["u_l"][a])) for a in range(case.dim))
     bound = 2 * max(ps["rel_res"], ps["res_floor"]) * ps["bnorm"] + 1e-14 * umax / case.h
     assert ps["div_max"] <= bound, (ps["div_max"], bound)
+
+
+WIDE = [("ball3d_13", "mixed"), ("film3d_16_periodic", "fp64"), ("ball3d_70x21x19_aniso", "mixed"),
+        ("plane3d_17_mixedbc", "fp64-dc")]
+
+
+@pytest.mark.parametrize("name,precision", WIDE, ids=[f"{n}-{p}" for n, p in WIDE])
+def test_step_parity_wide_offsets(name, precision, monkeypatch):
+    """The strided p-update with 64-bit cell offsets, which 3D grids of 2^30
+    cells or more take instead of the LDS-staged one, forced on small grids:
+    the same bars."""
+    monkeypatch.setenv("EBIT_WIDE_OFFSETS", "1")
+    test_step_parity(name, precision)
