@@ -324,9 +324,11 @@ ebit_status ebit_batch_project(ebit_batch* batch, double* const u_l[], double* c
  * timing cold-start solves to rtol of the caller's right-hand sides of the
  * current coefficients (after ebit_build_coeffs): b_heat and b_press are
  * device arrays of a heat and a pressure right-hand side (either may be
- * NULL), x a device array the solves write.  The fastest candidate whose
- * solves all converge becomes the context's (batch's) schedule and is
- * returned in *chosen with its summed solve time (ms) in *best_ms.
+ * NULL), x a device array the solves write.  Each candidate solves each
+ * system three times (the first captures its graphs) and counts the faster
+ * of the last two.  The fastest candidate whose solves all converge becomes
+ * the context's (batch's) schedule and is returned in *chosen with its
+ * summed solve time (ms) in *best_ms.
  * Clobbers the contexts' internal right-hand-side buffers.  A batch's
  * contexts keep their own options. */
 ebit_status ebit_autotune(ebit_ctx* ctx, const double* b_heat, const double* b_press, double* x, ebit_opts* chosen,
