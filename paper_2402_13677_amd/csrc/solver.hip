@@ -184,6 +184,54 @@ __device__ inline void rb_load_plane(const R& rows, int kk, int tx0, int ty0, co
   }
 }
 
+// rb_load_plane in two halves: the loads into registers (issued a plane
+// ahead of their use) and the stores into the LDS plane
+#define RB_NPL ((RB_PLANE + RB_THREADS - 1) / RB_THREADS)
+template <typename T, typename R>
+__device__ inline void rb_issue_plane(const R& rows, int kk, int tx0, int ty0, const T* __restrict__ xin,
+                                      const T* __restrict__ xc, const Dims& cd, T (&v)[RB_NPL]) {
+  const Dims& d = rows.dims();
+  int k = kk;
+  bool present = true;
+  if (k < 0 || k >= d.n[2]) {
+    if (d.per[2] && d.dim == 3)
+      k = (k % d.n[2] + d.n[2]) % d.n[2];
+    else
+      present = false;
+  }
+#pragma unroll
+  for (int e = 0; e < RB_NPL; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    const int ly = t / RB_PX - 2, lx = t % RB_PX - 2;
+    int i = tx0 + lx, j = ty0 + ly;
+    T w = (T)0;
+    bool ok = present && t < RB_PLANE;
+    if (ok && (i < 0 || i >= d.n[0])) {
+      if (d.per[0]) i = (i % d.n[0] + d.n[0]) % d.n[0];
+      else ok = false;
+    }
+    if (ok && (j < 0 || j >= d.n[1])) {
+      if (d.per[1]) j = (j % d.n[1] + d.n[1]) % d.n[1];
+      else ok = false;
+    }
+    if (ok) {
+      const long long c = cell_index(d, i, j, k);
+      if (xin) w = xin[c];
+      if (xc) w += xc[cell_index(cd, i >> 1, j >> 1, k >> 1)];
+    }
+    v[e] = w;
+  }
+}
+
+template <typename T>
+__device__ inline void rb_put_plane(const T (&v)[RB_NPL], T* plane) {
+#pragma unroll
+  for (int e = 0; e < RB_NPL; ++e) {
+    const int t = threadIdx.x + e * RB_THREADS;
+    if (t < RB_PLANE) plane[t] = v[e];
+  }
+}
+
 // update the cells of one colour of plane k on the tile (RING = 0) or on the
 // tile + 1 ring (RING = 1); threads walk only the cells of the colour
 template <typename T, int RING, typename R>
@@ -230,6 +278,8 @@ __device__ inline void rb_fused_body(const R& rows, const T* __restrict__ xin, c
   const int z1 = min(z0 + zchunk, d.n[2]);
   const bool zdim = d.dim == 3;
   auto slot = [&](int k) { return buf[((k % 4) + 4) % 4]; };
+  // plane k+2, loaded into registers during plane k-1 (3D)
+  T pv[RB_NPL];
   if (zdim) {
     for (int k = z0 - 2; k <= z0 + 1; ++k) rb_load_plane<T>(rows, k, tx0, ty0, xin, xc, cd, slot(k));
     __syncthreads();
@@ -238,6 +288,7 @@ __device__ inline void rb_fused_body(const R& rows, const T* __restrict__ xin, c
                        slot(z0));
     __syncthreads();
     rb_update_plane<T, 1>(rows, z0, tx0, ty0, 0, slot(z0 - 1), slot(z0), slot(z0 + 1));
+    rb_issue_plane<T>(rows, z0 + 2, tx0, ty0, xin, xc, cd, pv);
     __syncthreads();
   } else {
     rb_load_plane<T>(rows, 0, tx0, ty0, xin, xc, cd, buf[0]);
@@ -248,8 +299,9 @@ __device__ inline void rb_fused_body(const R& rows, const T* __restrict__ xin, c
   for (int k = z0; k < z1; ++k) {
     T* p0 = zdim ? slot(k) : buf[0];
     if (zdim) {
-      rb_load_plane<T>(rows, k + 2, tx0, ty0, xin, xc, cd, slot(k + 2));
+      rb_put_plane<T>(pv, slot(k + 2));
       __syncthreads();
+      if (k + 1 < z1) rb_issue_plane<T>(rows, k + 3, tx0, ty0, xin, xc, cd, pv);
       rb_update_plane<T, 1>(rows, k + 1, tx0, ty0, 0, slot(k), slot(k + 1), slot(k + 2));
       __syncthreads();
     }
