@@ -136,16 +136,25 @@ struct CoarseRows {
   CoarseOp<T> op;
   const T* b;
   __device__ const Dims& dims() const { return op.d; }
+  // the coupling across the upper side of axis a is stored at the cell, the
+  // one across the lower side at the lower neighbour (wrapped on a periodic
+  // axis); none across a wall or along an axis of one cell
   __device__ inline void row(int i, int j, int k, long long c, T& diag, T off[6], T& rhs) const {
+    const Dims& d = op.d;
+    const long long s1 = d.n[0], s2 = (long long)d.n[0] * d.n[1];
+    const int ia[3] = {i, j, k};
+    const long long st[3] = {1, s1, s2}, ln[3] = {s1, s2, d.N};
     diag = op.diag[c];
     rhs = b[c];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       off[2 * a] = off[2 * a + 1] = (T)0;
-      if (a >= op.d.dim) continue;
-      int ni, nj, nk;
-      if (neighbour(op.d, i, j, k, 2 * a + 1, ni, nj, nk) && op.d.n[a] > 1) off[2 * a + 1] = op.off[a][c];
-      if (neighbour(op.d, i, j, k, 2 * a, ni, nj, nk) && op.d.n[a] > 1)
-        off[2 * a] = op.off[a][cell_index(op.d, ni, nj, nk)];
+      if (a >= d.dim || d.n[a] < 2) continue;
+      if (ia[a] + 1 < d.n[a] || d.per[a]) off[2 * a + 1] = op.off[a][c];
+      if (ia[a] > 0)
+        off[2 * a] = op.off[a][c - st[a]];
+      else if (d.per[a])
+        off[2 * a] = op.off[a][c - st[a] + ln[a]];
     }
   }
 };
