@@ -2832,6 +2832,17 @@ int rb_zchunk(const Dims& d) {
   return zc;
 }
 
+// z-chunk of an explicit coarse level: as the fine level's, but a level
+// that would still have fewer than 1024 work-groups at 4 planes takes 2
+// (its launches are short, and more work-groups in flight pay for the
+// re-read planes; measured on the 256^3 film).
+int rb_zchunk_coarse(const Dims& d) {
+  const int zc = rb_zchunk(d);
+  if (d.dim < 3 || zc != 4) return zc;
+  const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
+  return tiles * ((d.n[2] + 3) / 4) < 1024 ? 2 : 4;
+}
+
 // The dense level of a hierarchy (the first of at most EBIT_DENSE_MAX
 // cells, whose inverse the build computes), or -1.
 int dense_level(const EbitLevelHost* lv, int nlev) {
@@ -3270,7 +3281,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
         C.lb[l] = lvb<T>(L);
         C.lx[l][0] = lvx<T>(L, 0);
         C.lx[l][1] = lvx<T>(L, 1);
-        C.lzc[l] = rb_zchunk(L.d);
+        C.lzc[l] = rb_zchunk_coarse(L.d);
         C.lgx[l] = (L.d.n[0] + RB_TX - 1) / RB_TX;
         C.lgy[l] = (L.d.n[1] + RB_TY - 1) / RB_TY;
       }
