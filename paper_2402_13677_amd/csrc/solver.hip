@@ -128,6 +128,7 @@ __device__ inline T coarse_offsum(const CoarseOp<T>& op, int i, int j, int k, lo
 // tile height of the 2D coarse-level double sweep (the 3D z-march uses
 // RB_TY): short tiles give a small coarse level more work-groups
 #define RB_CTY 2
+#define RB_CTX 32
 #define RB_PX (RB_TX + 4)
 #define RB_PY (RB_TY + 4)
 #define RB_PLANE (RB_PX * RB_PY)
@@ -837,14 +838,14 @@ template <typename T, int NSW, int RES>
 __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restrict__ b, const T* __restrict__ xin,
                                         const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
                                         T* sb, T* __restrict__ bc, T* __restrict__ xcz, int split) {
-  using W = Win2<RB_TX, RB_CTY, NSW, RES>;
+  using W = Win2<RB_CTX, RB_CTY, NSW, RES>;
   const Dims& d = op.d;
   T* xs = sb;
   T* o0 = sb + W::PL;
   T* o1 = sb + 2 * W::PL;
   T* dg = sb + 3 * W::PL;
   T* bb = dg + W::QL;
-  const int tx0 = bx * RB_TX, ty0 = by * RB_CTY;
+  const int tx0 = bx * RB_CTX, ty0 = by * RB_CTY;
   constexpr int NP = (W::PL + RB_THREADS - 1) / RB_THREADS, NQ = (W::QL + RB_THREADS - 1) / RB_THREADS;
   T vx[NP], v0[NP], v1[NP], vd[NQ], vb[NQ];
 #pragma unroll
@@ -895,9 +896,9 @@ __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restri
                   (o1[q - W::PX] * xs[q - W::PX] + o1[q] * xs[q + W::PX]);
     xs[q] = sum / dg[qc];
   };
-  phases2<RB_TX, RB_CTY, NSW, RES, 0>(d, tx0, ty0, upd);
-  for (int t = threadIdx.x; t < RB_TX * RB_CTY; t += RB_THREADS) {
-    const int lx = t % RB_TX, ly = t / RB_TX;
+  phases2<RB_CTX, RB_CTY, NSW, RES, 0>(d, tx0, ty0, upd);
+  for (int t = threadIdx.x; t < RB_CTX * RB_CTY; t += RB_THREADS) {
+    const int lx = t % RB_CTX, ly = t / RB_CTX;
     const int i = tx0 + lx, j = ty0 + ly;
     if (i < d.n[0] && j < d.n[1]) xout[i + (long long)d.n[0] * j] = xs[(ly + W::H) * W::PX + (lx + W::H)];
   }
@@ -912,14 +913,14 @@ __device__ inline void rb_coarse2d_body(const CoarseOp<T>& op, const T* __restri
       s += o1[q - W::PX] * xs[q - W::PX];
       return bb[qc] - dg[qc] * xs[q] - s;
     };
-    restrict2<T, RB_TX, RB_CTY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, split, res);
+    restrict2<T, RB_CTX, RB_CTY, RES>(d, cd, tx0, ty0, W::H, W::PX, W::QR, W::QX, bc, xcz, split, res);
   }
 }
 
 // shared buffer of the coarse sweep kernel: the 3D z-march's four planes or
 // the 2D double sweep's staged windows
-constexpr int RB_SBUF = (3 * Win2<RB_TX, RB_CTY, 2, 1>::PL + 2 * Win2<RB_TX, RB_CTY, 2, 1>::QL) > 4 * RB_PLANE
-                            ? (3 * Win2<RB_TX, RB_CTY, 2, 1>::PL + 2 * Win2<RB_TX, RB_CTY, 2, 1>::QL)
+constexpr int RB_SBUF = (3 * Win2<RB_CTX, RB_CTY, 2, 1>::PL + 2 * Win2<RB_CTX, RB_CTY, 2, 1>::QL) > 4 * RB_PLANE
+                            ? (3 * Win2<RB_CTX, RB_CTY, 2, 1>::PL + 2 * Win2<RB_CTX, RB_CTY, 2, 1>::QL)
                             : 4 * RB_PLANE;
 
 // Children (di, dj, dk) of a coarse cell whose fine cell has colour 0
@@ -3285,7 +3286,8 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
         C.lx[l][0] = lvx<T>(L, 0);
         C.lx[l][1] = lvx<T>(L, 1);
         C.lzc[l] = rb_zchunk_coarse(L.d);
-        C.lgx[l] = (L.d.n[0] + RB_TX - 1) / RB_TX;
+        const int ctx = L.d.dim == 2 ? RB_CTX : RB_TX;
+        C.lgx[l] = (L.d.n[0] + ctx - 1) / ctx;
         const int cty = L.d.dim == 2 ? RB_CTY : RB_TY;
         C.lgy[l] = (L.d.n[1] + cty - 1) / cty;
       }
