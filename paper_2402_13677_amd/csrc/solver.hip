@@ -125,8 +125,8 @@ __device__ inline T coarse_offsum(const CoarseOp<T>& op, int i, int j, int k, lo
 // ---------------------------------------------------------------------------
 #define RB_TX 64
 #define RB_TY 8
-// tile height of the 2D coarse-level double sweep (the 3D z-march uses
-// RB_TY): short tiles give a small coarse level more work-groups
+// tile of the 2D coarse-level double sweep (the 3D z-march uses RB_TX x
+// RB_TY): small tiles give a small coarse level more work-groups
 #define RB_CTY 2
 #define RB_CTX 32
 #define RB_PX (RB_TX + 4)
