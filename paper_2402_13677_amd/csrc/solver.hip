@@ -124,7 +124,7 @@ __device__ inline T coarse_offsum(const CoarseOp<T>& op, int i, int j, int k, lo
 // (fused prolongation).
 // ---------------------------------------------------------------------------
 #define RB_TX 64
-#define RB_TY 8
+#define RB_TY 4
 // tile of the 2D coarse-level double sweep (the 3D z-march uses RB_TX x
 // RB_TY): small tiles give a small coarse level more work-groups
 #define RB_CTY 2
@@ -2823,14 +2823,15 @@ double* zb<double>(const EbitSolveBufs& B, int s) { return s ? B.z64b : B.z64; }
 template <>
 float* zb<float>(const EbitSolveBufs& B, int s) { return s ? B.z32b : B.z32; }
 
-// z-chunk of a 64 x 8-tiled sweep: about 16 work-groups per compute unit,
+// z-chunk of a tx x ty-tiled sweep (the fine one: 64 x 8): about 16
+// work-groups per compute unit,
 // at most 32 planes each.  Work-groups that hold interface cells run
 // longer (their rows are assembled from the cut fractions); with several
 // rounds of short work-groups the others fill in around them, which more
 // than pays for the re-read planes at the chunk ends.
-int rb_zchunk(const Dims& d) {
+int rb_zchunk(const Dims& d, int tx = 64, int ty = 8) {
   if (d.dim < 3) return 1;
-  const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
+  const long long tiles = (long long)((d.n[0] + tx - 1) / tx) * ((d.n[1] + ty - 1) / ty);
   int zc = 32;
   while (zc > 4 && tiles * ((d.n[2] + zc - 1) / zc) < 4096) zc >>= 1;
   return zc;
@@ -2841,7 +2842,7 @@ int rb_zchunk(const Dims& d) {
 // (its launches are short, and more work-groups in flight pay for the
 // re-read planes; measured on the 256^3 film).
 int rb_zchunk_coarse(const Dims& d) {
-  const int zc = rb_zchunk(d);
+  const int zc = rb_zchunk(d, RB_TX, RB_TY);
   if (d.dim < 3 || zc != 4) return zc;
   const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
   return tiles * ((d.n[2] + 3) / 4) < 1024 ? 2 : 4;
