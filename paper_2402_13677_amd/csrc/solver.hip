@@ -2824,8 +2824,7 @@ template <>
 float* zb<float>(const EbitSolveBufs& B, int s) { return s ? B.z32b : B.z32; }
 
 // z-chunk of a tx x ty-tiled sweep (the fine one: 64 x 8): about 16
-// work-groups per compute unit,
-// at most 32 planes each.  Work-groups that hold interface cells run
+// work-groups per compute unit, at most 32 planes each.  Work-groups that hold interface cells run
 // longer (their rows are assembled from the cut fractions); with several
 // rounds of short work-groups the others fill in around them, which more
 // than pays for the re-read planes at the chunk ends.
