@@ -2837,13 +2837,15 @@ int rb_zchunk(const Dims& d, int tx = 64, int ty = 8) {
 }
 
 // z-chunk of an explicit coarse level: as the fine level's, but a level
-// that would still have fewer than 1024 work-groups at 4 planes takes 2
+// that still has 1024 work-groups at 8 planes takes 8 (fewer re-read
+// planes), and one that would have fewer than 1024 at 4 planes takes 2
 // (its launches are short, and more work-groups in flight pay for the
-// re-read planes; measured on the 256^3 film).
+// re-read planes); measured on the 256^3 film.
 int rb_zchunk_coarse(const Dims& d) {
   const int zc = rb_zchunk(d, RB_TX, RB_TY);
   if (d.dim < 3 || zc != 4) return zc;
   const long long tiles = (long long)((d.n[0] + RB_TX - 1) / RB_TX) * ((d.n[1] + RB_TY - 1) / RB_TY);
+  if (tiles * ((d.n[2] + 7) / 8) >= 1024) return 8;
   return tiles * ((d.n[2] + 3) / 4) < 1024 ? 2 : 4;
 }
 
