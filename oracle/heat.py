@@ -68,6 +68,7 @@ def operator(case, geo, theta_min=1e-3):
     lam = np.where(col == 1, pr.lam_l, pr.lam_v)
     mexc = rho * cp / dt
     rows, cols, w = [], [], []
+    plus = []
     for a in range(dim):
         for sgn, side in ((-1, 2 * a), (+1, 2 * a + 1)):
             ids, nb = side_neighbours(case, a, sgn)
@@ -82,12 +83,23 @@ def operator(case, geo, theta_min=1e-3):
             rows.append(ids[same])
             cols.append(nb[same])
             w.append(lam[same] / h ** 2)
+            if sgn > 0:
+                wp = np.zeros(col.size)
+                wp[ids[same]] = lam[same] / h ** 2
+                plus.append(wp)
             th = theta_from_cell(geo["theta"], case, a, sgn)
             if np.any(np.isnan(th[cut])):
                 raise ValueError("cut link without theta")
             tc = np.maximum(th[cut], theta_min)
             mexc[cut] += lam[cut] / (tc * h ** 2)
-    return FluxOp(mexc, np.concatenate(rows), np.concatenate(cols), np.concatenate(w))
+    return FluxOp(mexc, np.concatenate(rows), np.concatenate(cols), np.concatenate(w),
+                  plus, grid_shape(case))
+
+
+def grid_shape(case):
+    """(cells per axis, periodic flag per axis) of the case's grid."""
+    return (tuple(case.n), tuple(case.T_bc[2 * a][0] == PERIODIC if a < case.dim else False
+                                 for a in range(3)))
 
 
 def rhs(case, geo, T_star, theta_min=1e-3):

@@ -25,7 +25,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .flux import _face_cells
-from .heat import side_neighbours, face_of_side
+from .heat import side_neighbours, face_of_side, grid_shape
 
 NEUMANN, DIRICHLET, PERIODIC = 0, 1, 2
 
@@ -103,6 +103,7 @@ def operator(case, geo):
     N = case.ccol.size
     mexc = np.zeros(N)
     rows, cols, w = [], [], []
+    plus = []
     for a in range(dim):
         beta = face_beta(case, geo, a)
         for sgn, side in ((-1, 2 * a), (+1, 2 * a + 1)):
@@ -116,7 +117,12 @@ def operator(case, geo):
             rows.append(ids[inner])
             cols.append(nb[inner])
             w.append(bf[inner] / h ** 2)
-    return FluxOp(mexc, np.concatenate(rows), np.concatenate(cols), np.concatenate(w))
+            if sgn > 0:
+                wp = np.zeros(N)
+                wp[ids[inner]] = bf[inner] / h ** 2
+                plus.append(wp)
+    return FluxOp(mexc, np.concatenate(rows), np.concatenate(cols), np.concatenate(w),
+                  plus, grid_shape(case))
 
 
 def bc_rhs(case, geo):

@@ -19,13 +19,20 @@ import scipy.sparse.linalg as spla
 
 class FluxOp:
     """(A x)_i = mexc_i x_i + sum_j w_ij (x_i - x_j); rows/cols/w list every
-    coupling in both directions."""
+    coupling in both directions.
 
-    def __init__(self, mexc, rows, cols, w):
+    ``plus`` (optional) holds the same couplings per axis on the grid: plus[a][c]
+    is the weight of the link from cell c to its +a neighbour (wrapping on a
+    periodic axis), 0 where there is no link.  ``shape`` is (n, periodic) of
+    the grid.  The structured multigrid solve reads this form."""
+
+    def __init__(self, mexc, rows, cols, w, plus=None, shape=None):
         self.mexc = np.asarray(mexc, dtype=float)
         self.rows = np.asarray(rows)
         self.cols = np.asarray(cols)
         self.w = np.asarray(w, dtype=float)
+        self.plus = plus
+        self.shape = shape
 
     def matvec(self, x, dtype=np.float64):
         x = np.asarray(x, dtype=dtype)
