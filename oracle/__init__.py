@@ -20,6 +20,8 @@ approach for phase change: the EBIT method") defines on a uniform grid:
                the variable-density Poisson problem (Eqs. Poisson_equation,
                poisson_ghost_fluid) and the face-velocity update
   solve.py     sparse direct solve (SciPy SuperLU) of the assembled systems
+  mg.py, mg.c  plain FP64 geometric multigrid (Galerkin aggregation, PCG,
+               long-double refinement) for grids too large to factor
   extend.py    narrow-band extension of a cell field across the interface by
                pseudo-time upwind transport (Eq. extrapolation)
   onefluid.py  one-fluid projection: one face velocity field and the
@@ -30,5 +32,5 @@ Parity unpinned: the 3D facet rule beyond planar exactness (the paper's EBIT
 is 2D only), saddle cells, and the first-order fallback of the mass-flux
 stencil.  Every other function is pinned by tests under tests/.
 """
-from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid  # noqa: F401
+from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid, mg  # noqa: F401
 from .geometry import GeometryError  # noqa: F401
