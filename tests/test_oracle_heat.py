@@ -137,3 +137,54 @@ def test_manufactured_converges_3d():
     # about 0.45, is seen with exact crossings in place of the facet ones)
     errs = [_manufactured_error(3, n) for n in (16, 32)]
     assert errs[1] < 0.5 * errs[0], errs
+
+
+def test_planar_layer_reduces_to_tridiagonal_rows():
+    """Input uniform in y with a planar interface (the Stefan layer, x_Gamma
+    = 19.2 h): every row of the 2D system is the 1D system below, written
+    here from Eqs. energy_diffusion and Txx_ghost (backward Euler, sharp
+    T = T_sat through theta), and solved with scipy.linalg.solve_banded.
+    Cells 0..18 are vapour, 19..63 liquid; the link 18-19 is cut at
+    theta = 0.7 from cell 18 and 0.3 from cell 19; x = 0 is a wall at T_w
+    (ghost 2 T_w - T_0), x = 1 a zero-flux wall."""
+    from scipy.linalg import solve_banded
+    c = ei.config(0)
+    pr = c.props
+    rng = np.random.default_rng(21)
+    row = rng.uniform(-1.0, 1.0, 64)
+    Tstar = np.repeat(row[None, :], 64, axis=0)[None]
+    g = geometry.build(c)
+    A, b = heat.assemble(c, g, Tstar)
+    T = solve.direct(A, b, heat.operator(c, g)).reshape(64, 64)
+    n, h, dt = 64, c.h, c.dt
+    Tw = c.T_bc[0][1]
+    ab = np.zeros((3, n))
+    rhs = np.zeros(n)
+    for i in range(n):
+        liq = i >= 19
+        lam = pr.lam_l if liq else pr.lam_v
+        m = (pr.rho_l * pr.cp_l if liq else pr.rho_v * pr.cp_v) / dt
+        d = m
+        rhs[i] = m * row[i]
+        # left side
+        if i == 0:
+            d += 2 * lam / h ** 2
+            rhs[i] += 2 * lam * Tw / h ** 2
+        elif i == 19:
+            d += lam / (0.3 * h ** 2)
+            rhs[i] += lam * pr.T_sat / (0.3 * h ** 2)
+        else:
+            d += lam / h ** 2
+            ab[2, i - 1] = -lam / h ** 2
+        # right side
+        if i == n - 1:
+            pass
+        elif i == 18:
+            d += lam / (0.7 * h ** 2)
+            rhs[i] += lam * pr.T_sat / (0.7 * h ** 2)
+        else:
+            d += lam / h ** 2
+            ab[0, i + 1] = -lam / h ** 2
+        ab[1, i] = d
+    ref = solve_banded((1, 1), ab, rhs)
+    assert np.max(np.abs(T - ref[None, :])) <= 1e-13 * np.max(np.abs(ref))
