@@ -130,6 +130,15 @@ bool valid_grid(const ebit_grid* g, char* msg, size_t ml) {
       return false;
     }
   }
+  // The pressure operator has no mass term: with no outflow (Dirichlet) side
+  // it is singular (constants are its null space), and phase change in a
+  // closed domain has no compatible right-hand side.  Such a grid is refused.
+  bool p_dirichlet = false;
+  for (int s = 0; s < 2 * g->dim; ++s) p_dirichlet = p_dirichlet || g->p_bc[s] == EBIT_BC_DIRICHLET;
+  if (!p_dirichlet) {
+    snprintf(msg, ml, "the pressure needs at least one outflow (Dirichlet) side");
+    return false;
+  }
   return true;
 }
 
@@ -939,6 +948,13 @@ ebit_status ebit_batch_build_coeffs(ebit_batch* b, const double* const marker[],
   if (!b) return EBIT_EINVAL;
   if (b->herr != hipSuccess) return EBIT_EHIP;
   if (!marker || !vcol || !ccol || !dt) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  // every case's arguments are checked before the first launch
+  for (int c = 0; c < b->n; ++c) {
+    if (!vcol[c] || !ccol[c]) return bfail(b, EBIT_EINVAL, c, "NULL colour array");
+    for (int a = 0; a < b->ctx[c]->grid.dim; ++a)
+      if (!marker[3 * c + a]) return bfail(b, EBIT_EINVAL, c, "NULL marker array");
+    if (!(dt[c] > 0) || !isfinite(dt[c])) return bfail(b, EBIT_EINVAL, c, "dt must be positive");
+  }
   for (int c = 0; c < b->n; ++c) {
     const ebit_status s = build_launch(b->ctx[c], marker + 3 * c, vcol[c], ccol[c], dt[c], b->st);
     if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
@@ -981,10 +997,11 @@ ebit_status ebit_batch_mass_flux(ebit_batch* b, const double* const T[], double*
   ebit_status s = batch_ready(b);
   if (s != EBIT_OK) return s;
   if (!T || !mdot) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  for (int c = 0; c < b->n; ++c)
+    if (!T[c] || !mdot[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
   BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
   for (int c = 0; c < b->n; ++c) {
     ebit_ctx* x = b->ctx[c];
-    if (!T[c] || !mdot[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
     BHIPCK(b, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)x->B.scal, 0.0, b->st),
            "reset");
     const double lam[2] = {x->props.lam_v, x->props.lam_l};
@@ -1014,12 +1031,14 @@ ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const
   ebit_status s = batch_ready(b);
   if (s != EBIT_OK) return s;
   if (!u_l || !u_v || !mdot || !p) return bfail(b, EBIT_EINVAL, -1, "NULL argument array");
+  for (int c = 0; c < b->n; ++c) {
+    if (!mdot[c] || !p[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
+    for (int a = 0; a < b->ctx[c]->grid.dim; ++a)
+      if (!u_l[3 * c + a] || !u_v[3 * c + a]) return bfail(b, EBIT_EINVAL, c, "NULL velocity array");
+  }
   BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
   for (int c = 0; c < b->n; ++c) {
     ebit_ctx* x = b->ctx[c];
-    if (!mdot[c] || !p[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
-    for (int a = 0; a < x->grid.dim; ++a)
-      if (!u_l[3 * c + a] || !u_v[3 * c + a]) return bfail(b, EBIT_EINVAL, c, "NULL velocity array");
     const double rho[2] = {x->props.rho_v, x->props.rho_l};
     BHIPCK(b,
            ebit_launch_proj_rhs(&x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val, x->flags, x->th, x->nF,

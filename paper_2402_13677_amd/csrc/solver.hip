@@ -6,8 +6,11 @@
 // mass part and half of the aggregated flux part (couplings, interface and
 // wall terms), i.e. A_c = P^T M P + 1/2 P^T (A - M) P, which stays 5/7-point,
 // symmetric and scales like a re-discretisation on the coarse grid.
-// Smoother: red-black Gauss-Seidel (red then black before the correction,
-// black then red after, so the V-cycle is a symmetric preconditioner).
+// Smoother: red-black Gauss-Seidel.  The launched levels sweep red then black
+// both before and after the coarse correction (the single-work-group tail
+// sweeps black then red after it), so the V-cycle is not a symmetric
+// preconditioner; the outer loop is flexible CG (Polak-Ribiere beta), which
+// does not need one.
 #include <cstdlib>
 #include <math.h>
 #include <string.h>

@@ -55,8 +55,14 @@ def test_workspace_bytes_valid_and_invalid_grids():
     onlyT = [(2, 0.0), (2, 0.0), (0, 0.0), (0, 0.0)]
     bad = ebit.make_grid(2, (64, 64, 1), 1 / 64, onlyT, c.p_bc)      # periodic for T only
     assert _bytes(bad) == 0
-    ok = ebit.make_grid(2, (64, 64, 1), 1 / 64, per, per)
+    per_out = [(2, 0.0), (2, 0.0), (0, 0.0), (1, 0.0)]
+    ok = ebit.make_grid(2, (64, 64, 1), 1 / 64, per, per_out)
     assert _bytes(ok) > 0
+    # a pressure with no outflow (Dirichlet) side is singular: refused
+    closed = ebit.make_grid(2, (64, 64, 1), 1 / 64, per, per)
+    assert _bytes(closed) == 0
+    walls = [(0, 0.0)] * 4
+    assert _bytes(ebit.make_grid(2, (64, 64, 1), 1 / 64, walls, walls)) == 0
 
 
 def test_workspace_scales_with_cells():

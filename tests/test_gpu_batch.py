@@ -256,3 +256,39 @@ def test_batch_3d_equals_single_contexts(precision):
         for step, (xa, xb) in enumerate(zip(sa, sb)):
             for q, (u, v) in enumerate(zip(xa, xb)):
                 assert torch.equal(u, v), (i, step, q)
+
+
+def test_batch_null_argument_launches_nothing():
+    """A NULL field for a later case is refused with EBIT_EINVAL before any
+    case's kernels are queued: the earlier cases' outputs stay untouched."""
+    import ctypes
+    ebit = _ebit()
+    say("[gpu] batch NULL argument of case 1 launches nothing")
+    cases = [ei.random_case(2, 20, 3), ei.random_case(2, 24, 4)]
+    ctxs, dcs = zip(*[ebit.context_for(c) for c in cases])
+    b = ebit.Batch(list(ctxs))
+    b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs],
+                   [c.dt for c in cases])
+    T = [torch.zeros_like(d.T0) for d in dcs]
+    b.heat_solve([d.T0 for d in dcs], T)
+    m0 = torch.full_like(T[0], 7.0)
+    arr_T = (ctypes.c_void_p * 2)(T[0].data_ptr(), T[1].data_ptr())
+    arr_m = (ctypes.c_void_p * 2)(m0.data_ptr(), None)
+    st = b.lib.ebit_batch_mass_flux(b.h, arr_T, arr_m, None)
+    torch.cuda.synchronize()
+    assert st == ebit.EINVAL
+    assert torch.all(m0 == 7.0)
+    p0 = torch.full_like(T[0], 5.0)
+    u0 = [u.clone() for u in dcs[0].u_l]
+    arr_p = (ctypes.c_void_p * 2)(p0.data_ptr(), None)
+    arr_md = (ctypes.c_void_p * 2)(m0.data_ptr(), m0.data_ptr())
+    st = b.lib.ebit_batch_project(b.h, ebit._ptrs([d.u_l for d in dcs], per=3),
+                                  ebit._ptrs([d.u_v for d in dcs], per=3), arr_md, arr_p, 0, None)
+    torch.cuda.synchronize()
+    assert st == ebit.EINVAL
+    assert torch.all(p0 == 5.0)
+    for a in range(2):
+        assert torch.equal(u0[a], dcs[0].u_l[a])
+    b.close()
+    for x in ctxs:
+        x.close()
