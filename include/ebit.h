@@ -336,6 +336,32 @@ ebit_status ebit_autotune(ebit_ctx* ctx, const double* b_heat, const double* b_p
 ebit_status ebit_batch_autotune(ebit_batch* batch, const double* const b_heat[], const double* const b_press[],
                                 double* const x[], ebit_opts* chosen, double* best_ms);
 
+/* ---- the geometry pass without allocation --------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the cut
+ * fractions theta and the flags of ebit_build_coeffs (Sec. 2.1 and the
+ * theta of Eq. ghost_T, through the same kernels and the same arithmetic)
+ * for a grid of at most EBIT_NOALLOC_MAX_CELLS cells, with no context and no
+ * workspace.  The interface facets and the status word live in a file-scope
+ * device array of the library (12 MiB + 256 B per GPU, held by every GPU the
+ * call runs on until the process ends); the call makes no device or host
+ * allocation.
+ * Arguments: grid as for ebit_create (only dim, n, h and the periodic sides
+ * are used); marker[a], vertex_colour, cell_colour as for
+ * ebit_build_coeffs; theta[a] (axis-a face arrays) and flags (one byte per
+ * cell) are caller-owned device outputs with the layout of
+ * ebit_get_geometry.  Work is enqueued on hip_stream (NULL = the null
+ * stream) and the call waits for it to read the status word.
+ * Errors: EBIT_EINVAL for a bad grid or argument, or more than
+ * EBIT_NOALLOC_MAX_CELLS cells (nothing is launched); EBIT_EGEOM as for
+ * ebit_build_coeffs; EBIT_EHIP if a HIP call fails (no context holds the
+ * text).  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (two streams, two host threads) race and must not. */
+#define EBIT_NOALLOC_MAX_CELLS (1 << 18)
+ebit_status ebit_cut_fractions_noalloc(const ebit_grid* grid, const double* const marker[3],
+                                       const uint8_t* vertex_colour, const uint8_t* cell_colour,
+                                       double* const theta[3], uint8_t* flags, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

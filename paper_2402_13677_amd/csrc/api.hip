@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "ebit_internal.h"
 
 using namespace ebit;
@@ -1201,6 +1203,80 @@ ebit_status ebit_batch_autotune(ebit_batch* b, const double* const b_heat[], con
   if (chosen) *chosen = best;
   if (best_ms) *best_ms = ms;
   if (!isfinite(ms)) return bfail(b, EBIT_ENOCONV, -1, "no candidate schedule converged");
+  return EBIT_OK;
+}
+
+/* ---- the geometry pass without allocation --------------------------------
+ * The facets and the status word of ebit_cut_fractions_noalloc live in one
+ * file-scope device array.  Host code must not pass its name to a kernel:
+ * in host code the name is a host-side stand-in.  The array's device
+ * address is looked up once per device with hipGetSymbolAddress (on the
+ * entry point's first call on that device, with the device current) and
+ * only that address is used. */
+
+}  // extern "C"
+
+namespace {
+
+constexpr size_t NOALLOC_STATUS_BYTES = 256;   // one Scal, rounded up to the array's alignment
+constexpr size_t NOALLOC_BYTES = NOALLOC_STATUS_BYTES + (size_t)6 * EBIT_NOALLOC_MAX_CELLS * sizeof(double);
+static_assert(sizeof(Scal) <= NOALLOC_STATUS_BYTES, "the status word must fit its slot");
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this device's copy of the scratch array (nullptr on failure).
+hipError_t noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+ebit_status ebit_cut_fractions_noalloc(const ebit_grid* grid, const double* const marker[3],
+                                       const uint8_t* vertex_colour, const uint8_t* cell_colour,
+                                       double* const theta[3], uint8_t* flags, void* hip_stream) {
+  char msg[160];
+  if (!valid_grid(grid, msg, sizeof msg)) return EBIT_EINVAL;
+  if (!marker || !vertex_colour || !cell_colour || !theta || !flags) return EBIT_EINVAL;
+  for (int a = 0; a < grid->dim; ++a)
+    if (!marker[a] || !theta[a]) return EBIT_EINVAL;
+  const Dims d = dims_of(grid);
+  if (d.N > (long long)EBIT_NOALLOC_MAX_CELLS) return EBIT_EINVAL;
+  void* base = nullptr;
+  if (noalloc_scratch(&base) != hipSuccess) return EBIT_EHIP;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Scal* scal = (Scal*)base;
+  double* cF = (double*)((char*)base + NOALLOC_STATUS_BYTES);
+  double* nF = cF + 3 * d.N;
+  // the error bits are ORed in by the kernels: clear the status word first
+  // (a fill kernel, not a memset node, so the call may be captured)
+  if (ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)scal, 0.0, st) != hipSuccess)
+    return EBIT_EHIP;
+  if (ebit_launch_geometry(&d, grid->h, marker, vertex_colour, cell_colour, flags, cF, nF, theta, scal, st) !=
+      hipSuccess)
+    return EBIT_EHIP;
+  int err = 0;
+  if (hipMemcpyAsync(&err, &scal->err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return EBIT_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return EBIT_EHIP;
+  if (err & (ERR_GEOM_MARKER | ERR_GEOM_SEAM | ERR_GEOM_NOFACET)) return EBIT_EGEOM;
   return EBIT_OK;
 }
 

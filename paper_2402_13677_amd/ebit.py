@@ -96,6 +96,7 @@ def load():
         "ebit_autotune": (i, [vp, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(d)]),
         "ebit_batch_autotune": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(Opts), ctypes.POINTER(d)]),
+        "ebit_cut_fractions_noalloc": (i, [ctypes.POINTER(Grid), _P3, vp, vp, _P3, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -110,7 +111,9 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_get_geometry", "ebit_apply", "ebit_heat_rhs", "ebit_extend", "ebit_project_one_fluid", "ebit_project_rhs", "ebit_levels",
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
-            "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune"]
+            "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune",
+            "ebit_cut_fractions_noalloc"]
+NOALLOC_MAX_CELLS = 1 << 18
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ, EXT_IFACE_TO_BAND = range(3)
 
@@ -303,6 +306,17 @@ class Context:
         sizes = (ctypes.c_int * (3 * 32))()
         self._check(self.lib.ebit_levels(self.h, ctypes.byref(n), sizes), "ebit_levels")
         return [tuple(sizes[3 * l: 3 * l + 3]) for l in range(n.value)]
+
+
+def cut_fractions_noalloc(grid, markers, vcol, ccol, theta, flags, stream=None):
+    """ebit_cut_fractions_noalloc: theta (per-axis face arrays) and flags of
+    the geometry pass with no context, workspace or allocation; returns the
+    status code (0 = EBIT_OK)."""
+    lib = load()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return lib.ebit_cut_fractions_noalloc(ctypes.byref(grid), _p3(markers), _ptr(vcol, torch.uint8),
+                                          _ptr(ccol, torch.uint8), _p3(theta), _ptr(flags, torch.uint8),
+                                          ctypes.c_void_p(st.cuda_stream))
 
 
 def _ptrs(ts, dtype=torch.float64, per=1):
