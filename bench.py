@@ -3,15 +3,16 @@
 
 A step is one pass of the whole hot path over the workload: cut fractions
 and multigrid hierarchies from the markers (ebit_build_coeffs), the implicit
-heat solve (cold start, to rel. residual 1e-9), the mass flux, and the
-ghost-fluid projection (cold start, to 1e-9).  T* = T^n and u* = u^n: the
-advection and momentum predictor are outside the path.  The default workload
-is the 2D bubble: 256 x 256 cells, circle R = 0.1 at the centre, liquid
-T = erf((r - 0.1)/0.02), density ratio 1000, conductivity ratio 0.1, face
-velocities seeded N(0, 1e-3^2), 50 time steps.
+heat solve (cold start, to the workload's relative residual), the mass flux,
+and the ghost-fluid projection (cold start, same target).  T* = T^n and
+u* = u^n: the advection and momentum predictor are outside the path.  The
+default workload is the largest single-GPU one, the 3D film: 256^3 cells,
+interface y = 0.25 + 0.02 cos(2 pi x) cos(2 pi z) + 1e-3 noise (PCG64(5)),
+heated wall T = 1 at y = 0, outflow at y = 1, periodic in x and z, density
+ratio 200, conductivity ratio 0.2, mixed precision, rtol 1e-9.
 
 Prints ONE JSON line.  value = fine cells advanced through one full step per
-second (cell-steps/s).
+second (cell-steps/s).  Progress lines go to stderr.
 """
 from __future__ import annotations
 
@@ -32,6 +33,13 @@ WORKLOADS = {
     "film3d_256": (4, None),
     "batch64_2d": (3, None),
 }
+# relative residual target of each workload's solves
+RTOL = {"stefan2d_64": 1e-10}
+DEFAULT_RTOL = 1e-9
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "coarse", "outer_apply", "outer_update", "tail"]
@@ -49,20 +57,36 @@ KERNEL_NAMES = {
 def algorithmic_bytes_per_cell(kclass, precision, dim):
     """Bytes one launch of a kernel class must move per fine cell (sparse
     theta reads on cut links, O(interface), are not counted).  sx: size of
-    the inner iterate (4 in mixed precision, 8 in FP64); the residual r the
-    V-cycle smooths against is FP64.  The coarse-level and tail classes work
-    on levels of varying size and have no per-fine-cell model (None)."""
+    the inner iterate and of the right-hand side the V-cycle smooths against
+    (4 in mixed precision, 8 in FP64).  The coarse-level and tail classes
+    work on levels of varying size and have no per-fine-cell model (None)."""
     sx = 4 if precision == "mixed" else 8
     agg = 2 ** dim
-    if kclass == "fine_smooth":      # per full red-black sweep: read x, r (FP64), flags; write x
-        return sx + 8 + 1 + sx
+    if kclass == "fine_smooth":      # per full red-black sweep: read x, r, flags; write x
+        return sx + sx + 1 + sx
     if kclass == "fine_restrict":    # read x (all cells), r and flags (colour-0 cells); write coarse b, clear coarse x
-        return sx + (8 + 1) / 2 + 2 * sx / agg
+        return sx + (sx + 1) / 2 + 2 * sx / agg
     if kclass == "outer_apply":      # read z, p_old, flags; write p_new and q (FP64)
         return sx + 8 + 1 + 8 + 8
     if kclass == "outer_update":     # read x, p, r, q; write x, r (FP64)
         return 48.0
     return None
+
+
+def solve_model_bytes_per_iteration(precision, dim, schedule):
+    """Algorithmic bytes per fine cell of one outer iteration (one V-cycle
+    plus the outer update), by the table of the design: a full red-black
+    sweep 2 sx + sx + 1 (read x, r, flag; write x), residual + restriction
+    and prolongation + correction 18 (FP64) / 9.5 (FP32) each, all levels
+    x 8/7 (3D) or x 4/3 (2D), plus the FP64 outer residual and correction
+    (about 33 B)."""
+    sx = 4 if precision == "mixed" else 8
+    sch = schedule or {"nu1": 2, "nu2": 2}
+    sweep = 3 * sx + 1
+    transfer = 9.5 if precision == "mixed" else 18.0
+    fine = (sch["nu1"] + sch["nu2"]) * sweep + 2 * transfer
+    levels = 8.0 / 7.0 if dim == 3 else 4.0 / 3.0
+    return fine * levels + 33.0
 
 
 def kernel_source_digest():
@@ -103,6 +127,10 @@ def parse_schedule(text):
     return {"nu1": nu, "nu2": nu, "tail_cells": tail, "check_every": k}
 
 
+def workload_rtol(case):
+    return RTOL.get(case.name, DEFAULT_RTOL)
+
+
 def run_gpu(case, precision, steps, warmup, profile=False, tune=True, warm=False):
     """Time `steps` full steps after `warmup` untimed ones (and, with tune,
     the untimed schedule autotuning).  With profile, the library also times
@@ -114,7 +142,8 @@ def run_gpu(case, precision, steps, warmup, profile=False, tune=True, warm=False
     from paper_2402_13677_amd import ebit
 
     fixed = tune if isinstance(tune, dict) else {}
-    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64, **fixed)
+    opts = ebit.default_opts(rtol=workload_rtol(case), precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
+                             **fixed)
     ctx, dc = ebit.context_for(case, opts)
     schedule = autotune(ctx, dc, case) if tune is True else (fixed or None)
     T = dc.T0.clone()
@@ -182,7 +211,7 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
     import torch
     from paper_2402_13677_amd import ebit
 
-    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
+    opts = ebit.default_opts(rtol=DEFAULT_RTOL, precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
                              **(schedule or {}))
     ctxs, dcs = [], []
     for c in cases:
@@ -242,32 +271,110 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
     return el, its, schedule
 
 
-def cpu_baseline(case, budget_s=15.0, max_steps=30):
-    """The oracle (plain FP64, direct solves) on a bounded sample of steps."""
+def gpu_first_step(case, precision, schedule):
+    """The first step of the workload from its seeded inputs, solved to the
+    workload's rtol as benchmarked: host copies of T, mdot, p, u_l, u_v."""
+    import torch
+    from paper_2402_13677_amd import ebit
+
+    opts = ebit.default_opts(rtol=workload_rtol(case), precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
+                             **(schedule or {}))
+    ctx, dc = ebit.context_for(case, opts)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    T = torch.zeros_like(dc.T0)
+    ctx.heat_solve(dc.T0, T)
+    m = torch.zeros_like(T)
+    ctx.mass_flux(T, m)
+    p = torch.zeros_like(T)
+    ctx.project(dc.u_l, dc.u_v, m, p)
+    torch.cuda.synchronize()
+    out = {"T": T.cpu().numpy().ravel(), "mdot": m.cpu().numpy().ravel(), "p": p.cpu().numpy().ravel(),
+           "u_l": [u.cpu().numpy() for u in dc.u_l], "u_v": [u.cpu().numpy() for u in dc.u_v]}
+    ctx.close()
+    del dc
+    torch.cuda.empty_cache()
+    return out
+
+
+def _oracle_step(case, threads):
+    """One full step of the oracle (plain FP64) on the workload's seeded
+    inputs: geometry, heat solve, mass flux, ghost velocities, pressure
+    solve, face update; the solves by its multigrid (oracle/mg.c) on
+    `threads` OpenMP threads.  Returns (fields, seconds per phase)."""
+    from oracle import flux, geometry, heat, mg, project
+    t = {}
+    t0 = time.perf_counter()
+    geo = geometry.build(case)
+    opH = heat.operator(case, geo)
+    bH = heat.rhs(case, geo, case.T0)
+    t["setup"] = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    T = mg.solve_op(opH, bH, threads=threads)
+    t["heat_solve"] = time.perf_counter() - t1
+    del opH
+    t1 = time.perf_counter()
+    mdot, _ = flux.mass_flux(case, geo, T)
+    ulg, uvg = project.ghost_velocities(case, geo, mdot, case.u_l, case.u_v)
+    rhs = project.divergence(case, ulg, uvg) - project.bc_rhs(case, geo)
+    opP = project.operator(case, geo)
+    t["flux_and_rhs"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    p = mg.solve_op(opP, -rhs, threads=threads)
+    t["pressure_solve"] = time.perf_counter() - t1
+    del opP
+    ul1, uv1 = project.face_update(case, geo, p, ulg, uvg)
+    t["step"] = time.perf_counter() - t0
+    return {"T": T, "mdot": mdot, "p": p, "u_l": ul1, "u_v": uv1}, t
+
+
+def cpu_baseline_leg(case, gpu_steps, one_thread=True):
+    """The oracle timed on the host's cores, and the GPU's first step against
+    it.  (1) one full oracle step with as many OpenMP threads as the host has
+    cores: the reported baseline (cell-steps/s) and the reference for the
+    error of each GPU precision at the benchmarked rtol; (2) the oracle on
+    one thread over a bounded sample: the full step on grids up to 2^21
+    cells, the heat solve alone above."""
+    import numpy as np
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        threadpool_limits(1)
     except Exception:  # pragma: no cover
-        limiter = None
-    import oracle
-    T = case.T0.copy()
-    u_l = [u.copy() for u in case.u_l]
-    u_v = [u.copy() for u in case.u_v]
-    steps = 0
-    t0 = time.perf_counter()
-    while steps < max_steps:
-        r = oracle.pipeline.run_step(case, T, u_l, u_v)
-        T = r["T"].reshape(case.T0.shape)
-        u_l, u_v = r["u_l"], r["u_v"]
-        steps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": case.ncells * steps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full steps of the same workload ({el:.1f} s, SciPy SuperLU direct solves, 1 thread "
-                      f"of {host_cpu()})"}
+        pass
+    cores = os.cpu_count() or 1
+    log(f"oracle step on {cores} threads")
+    ref, t = _oracle_step(case, cores)
+    base = {"value": case.ncells / t["step"], "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full step of the workload ({t['step']:.1f} s: geometry, multigrid heat and pressure "
+                      f"solves to the discrete solution, mass flux, projection) on {cores} threads of {host_cpu()}",
+            "phases_s": t}
+
+    def rel(a, b):
+        a = np.concatenate([np.ravel(x) for x in a]) if isinstance(a, list) else np.ravel(a)
+        b = np.concatenate([np.ravel(x) for x in b]) if isinstance(b, list) else np.ravel(b)
+        nb = np.linalg.norm(b)
+        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+    err = {prec: {k: rel(g[k], ref[k]) for k in ("T", "p", "mdot", "u_l", "u_v")} for prec, g in gpu_steps.items()}
+    del ref
+    if one_thread:
+        if case.ncells <= (1 << 21):
+            log("oracle step on 1 thread")
+            _, t1 = _oracle_step(case, 1)
+            base["one_thread"] = {"value": case.ncells / t1["step"], "unit": "cell-steps/s", "cores": 1,
+                                  "sample": f"one full step ({t1['step']:.1f} s)"}
+        else:
+            log("oracle heat solve on 1 thread")
+            from oracle import geometry, heat, mg
+            geo = geometry.build(case)
+            opH = heat.operator(case, geo)
+            bH = heat.rhs(case, geo, case.T0)
+            t0 = time.perf_counter()
+            mg.solve_op(opH, bH, threads=1)
+            el = time.perf_counter() - t0
+            base["one_thread"] = {"heat_solve_s": el, "cells_per_s": case.ncells / el, "cores": 1,
+                                  "sample": f"the heat solve of one step alone ({el:.1f} s; the full step on one "
+                                            "thread would take minutes)"}
+    return base, err
 
 
 def host_cpu():
@@ -327,6 +434,9 @@ def roofline(case, precision, steps, tune=True):
             traffic = ent["hbm_bytes_per_launch"]
     ro = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS,
           "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+          "traffic_source": ("stored profile value: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel on this "
+                             "workload (profiles/traffic.json), scaled by a plain copy of known size; reported only "
+                             "while the kernel sources match the digest it was taken with") if traffic else None,
           "avg_launch_us": r["avg_us"], "algorithmic_bytes_per_launch": r["algorithmic_bytes_per_launch"]}
     if "sweeps_per_launch" in r:
         ro["sweeps_per_launch"] = r["sweeps_per_launch"]
@@ -401,7 +511,7 @@ def one_fluid_bench(case, precision, schedule, reps=10):
     import torch
     from paper_2402_13677_amd import ebit
 
-    opts = ebit.default_opts(rtol=1e-9, precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
+    opts = ebit.default_opts(rtol=workload_rtol(case), precision=ebit.MIXED if precision == "mixed" else ebit.FP64,
                              **(schedule or {}))
     ctx, dc = ebit.context_for(case, opts)
     ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
@@ -451,18 +561,50 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
 
 
+def repeats(case, precision, schedule, reps=5, steps=4):
+    """Time-to-rtol of each solve in `reps` separate timed runs of `steps`
+    steps (fresh context each, fixed schedule): the median per run and the
+    median of those medians."""
+    out = {"heat": [], "projection": [], "ms_per_step": []}
+    for _ in range(reps):
+        el, rec, _, _ = run_gpu(case, precision, steps, 1, tune=schedule or False)
+        out["heat"].append(statistics.median(rec["heat_ms"]))
+        out["projection"].append(statistics.median(rec["proj_ms"]))
+        out["ms_per_step"].append(el / steps * 1e3)
+        its = (statistics.median(rec["heat_it"]), statistics.median(rec["proj_it"]))
+    return {"time_to_rtol_ms": {k: statistics.median(out[k]) for k in ("heat", "projection")},
+            "ms_per_step": statistics.median(out["ms_per_step"]),
+            "spread_ms": {k: [min(out[k]), max(out[k])] for k in ("heat", "projection")},
+            "outer_iters": {"heat": its[0], "projection": its[1]}, "runs": reps, "steps_per_run": steps}
+
+
+def solve_roofline(case, precision, schedule, rep):
+    """Whole-solve figure: the design's algorithmic bytes of every outer
+    iteration (V-cycle on all levels plus the outer update) over the
+    measured time-to-rtol, against the HBM peak."""
+    bpc = solve_model_bytes_per_iteration(precision, case.dim, schedule)
+    out = {"model_bytes_per_cell_per_iteration": bpc}
+    for k in ("heat", "projection"):
+        byts = bpc * case.ncells * rep["outer_iters"][k]
+        gbs = byts / (rep["time_to_rtol_ms"][k] * 1e-3) / 1e9
+        out[k] = {"algorithmic_GB": byts / 1e9, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bubble2d_256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="film3d_256", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--compare", action="store_true", default=True,
                     help="also time the plain FP64 solve (reported beside the value)")
     ap.add_argument("--no-compare", dest="compare", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-one-thread", action="store_true", help="skip the one-thread oracle sample")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-repeats", action="store_true", help="skip the five repeated timed runs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default solve schedule")
     ap.add_argument("--schedule", default=None,
                     help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
@@ -474,7 +616,8 @@ def main():
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "one GPU only: sharding over several GPUs is a design note (DESIGN.md, section 11)",
+        print(json.dumps({"error": "one GPU only: this build runs and measures the path on a single GPU; "
+                                   "how it would shard is a design note (DESIGN.md, section 11)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
@@ -488,26 +631,37 @@ def main():
         print(json.dumps({"workload": case.name, "extension": extension_bench(case),
                           "one_fluid": one_fluid_bench(case, args.precision, sched)}))
         return
+    rtol = workload_rtol(case)
     tune = parse_schedule(args.schedule) if args.schedule else (not args.no_autotune)
+    log(f"{case.name}: {case.ncells} cells, {args.precision}, rtol {rtol:g}; timed steps")
     elapsed, rec, _, schedule = run_gpu(case, args.precision, args.steps, args.warmup, tune=tune)
     ms_per_step = elapsed / args.steps * 1e3
     med = lambda v: statistics.median(v) if v else None
     extra = {
-        "time_to_1e9_ms": {"heat": med(rec["heat_ms"]), "projection": med(rec["proj_ms"])},
+        "time_to_rtol_ms": {"heat": med(rec["heat_ms"]), "projection": med(rec["proj_ms"])},
         "outer_iters": {"heat": med(rec["heat_it"]), "projection": med(rec["proj_it"])},
         "rel_res_max": {"heat": max(rec["heat_res"]), "projection": max(rec["proj_res"])},
         "div_max": max(rec["div"]),
         "mass_flux_fallbacks": max(rec["fallbacks"]),
     }
     extra["cell_updates_per_s"] = cell_updates(rec, schedule, ms_per_step)
-    _, recw, _, _ = run_gpu(case, args.precision, max(5, args.steps // 5), 1, tune=schedule or False, warm=True)
-    extra["warm_start"] = {"time_to_1e9_ms": {"heat": med(recw["heat_ms"]), "projection": med(recw["proj_ms"])},
+    fixed = schedule or False
+    if not args.no_repeats:
+        log("five repeated runs per precision")
+        extra["repeats"] = {args.precision: repeats(case, args.precision, fixed)}
+        if args.compare:
+            other = "fp64" if args.precision == "mixed" else "mixed"
+            extra["repeats"][other] = repeats(case, other, fixed)
+            mine, theirs = extra["repeats"][args.precision], extra["repeats"][other]
+            mixed, fp64 = (mine, theirs) if args.precision == "mixed" else (theirs, mine)
+            extra["mixed_over_fp64_speedup"] = {
+                k: fp64["time_to_rtol_ms"][k] / mixed["time_to_rtol_ms"][k] for k in ("heat", "projection")}
+            extra["mixed_over_fp64_speedup"]["step"] = fp64["ms_per_step"] / mixed["ms_per_step"]
+        extra["solve_roofline"] = solve_roofline(case, args.precision, schedule, extra["repeats"][args.precision])
+    log("warm-start run")
+    _, recw, _, _ = run_gpu(case, args.precision, max(5, args.steps // 5), 1, tune=fixed, warm=True)
+    extra["warm_start"] = {"time_to_rtol_ms": {"heat": med(recw["heat_ms"]), "projection": med(recw["proj_ms"])},
                            "outer_iters": {"heat": med(recw["heat_it"]), "projection": med(recw["proj_it"])}}
-    if args.compare:
-        other = "fp64" if args.precision == "mixed" else "mixed"
-        el2, rec2, _, _ = run_gpu(case, other, max(5, args.steps // 5), 1, tune=tune)
-        extra[f"{other}_time_to_1e9_ms"] = {"heat": med(rec2["heat_ms"]), "projection": med(rec2["proj_ms"])}
-        extra[f"{other}_ms_per_step"] = el2 / max(5, args.steps // 5) * 1e3
     out = {
         "metric": "time-to-1e-9 residual per solve (mixed vs FP64) + cell-updates/s, % HBM peak",
         "value": case.ncells * args.steps / elapsed,
@@ -522,23 +676,29 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": case.name, "cells": case.ncells, "precision": args.precision,
-                   "rtol": 1e-9, "parallelism": "single GPU", "schedule": schedule},
+                   "rtol": rtol, "parallelism": "single GPU", "schedule": schedule},
         "extra": extra,
         "roofline": None,
     }
     if not args.no_roofline:
-        out["roofline"], extra["kernels"] = roofline(case, args.precision, max(5, args.steps // 5),
-                                                     tune=schedule if schedule else False)
+        log("profiled pass (hipEvents per kernel class)")
+        out["roofline"], extra["kernels"] = roofline(case, args.precision, max(5, args.steps // 5), tune=fixed)
     if not args.no_extension:
+        log("narrow-band extension")
         extra["extension"] = extension_bench(case)
-        if not args.no_cpu_baseline:
+        if not args.no_cpu_baseline and case.dim == 2:
             extra["extension"]["cpu_oracle"] = extension_cpu_baseline(case)
     if not args.no_one_fluid:
+        log("one-fluid projection")
         extra["one_fluid"] = one_fluid_bench(case, args.precision, schedule)
         if not args.no_cpu_baseline and case.dim == 2:
             extra["one_fluid"]["cpu_oracle"] = one_fluid_cpu_baseline(case)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        log("first step of each precision for the error against the oracle")
+        gsteps = {"mixed": gpu_first_step(case, "mixed", schedule), "fp64": gpu_first_step(case, "fp64", schedule)}
+        out["cpu_baseline"], errs = cpu_baseline_leg(case, gsteps, one_thread=not args.no_one_thread)
+        extra["error_vs_oracle_at_rtol"] = errs
+        extra["mixed_error_vs_oracle"] = errs["mixed"]
     print(json.dumps(out))
 
 
@@ -563,7 +723,7 @@ def main_batch(args, cases):
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "batch64_2d", "cases": len(cases), "cells": ncells, "precision": args.precision,
-                   "rtol": 1e-9, "parallelism": "single GPU", "schedule": schedule},
+                   "rtol": DEFAULT_RTOL, "parallelism": "single GPU", "schedule": schedule},
         "extra": {"sequential_ms_per_step": el_seq / seq_steps * 1e3,
                   "batched_speedup": (el_seq / seq_steps) / (el / args.steps),
                   "max_outer_iters": {"heat": max(i[0] for i in its), "projection": max(i[1] for i in its)}},

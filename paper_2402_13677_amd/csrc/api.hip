@@ -213,6 +213,7 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
   double* bvec = cv.take<double>(N);
   EbitSolveBufs B;
   B.r = cv.take<double>(N);
+  B.r32 = cv.take<float>(N);
   B.z64 = cv.take<double>(N);
   B.z64b = cv.take<double>(N);
   B.z32 = cv.take<float>(N);

@@ -288,6 +288,7 @@ struct EbitProfiler {
 // Work vectors of the outer loop (fine level).
 struct EbitSolveBufs {
   double* r;
+  float* r32;          // FP32 copy of r: the right-hand side the mixed-precision V-cycle reads
   double* z64;
   double* z64b;
   float* z32;

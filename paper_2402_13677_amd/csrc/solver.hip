@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -471,9 +472,9 @@ __device__ inline void fine_load_x(const Dims& d, const Dims& cd, const FineSlot
   }
 }
 
-template <int TX, int TY>
-__device__ inline void fine_load_rf(const Dims& d, const FineSlots<TX, TY>& S, int kk, const double* __restrict__ rhs,
-                                    const uint8_t* __restrict__ flags, double (&r)[FineTile<TX, TY>::NQ],
+template <typename T, int TX, int TY>
+__device__ inline void fine_load_rf(const Dims& d, const FineSlots<TX, TY>& S, int kk, const T* __restrict__ rhs,
+                                    const uint8_t* __restrict__ flags, T (&r)[FineTile<TX, TY>::NQ],
                                     uint8_t (&f)[FineTile<TX, TY>::NQ]) {
   using FT = FineTile<TX, TY>;
   int k = kk;
@@ -481,7 +482,7 @@ __device__ inline void fine_load_rf(const Dims& d, const FineSlots<TX, TY>& S, i
   const long long base = (long long)k * d.n[0] * d.n[1];
 #pragma unroll
   for (int e = 0; e < FT::NQ; ++e) {
-    r[e] = 0.0;
+    r[e] = (T)0;
     f[e] = 0;
     if (pz && S.qo[e] >= 0) {
       r[e] = rhs[base + S.qo[e]];
@@ -500,9 +501,9 @@ __device__ inline void fine_store(const T (&v)[FineTile<TX, TY>::NX], T* xs) {
   }
 }
 
-template <int TX, int TY>
-__device__ inline void fine_store_rf(const double (&r)[FineTile<TX, TY>::NQ], const uint8_t (&f)[FineTile<TX, TY>::NQ],
-                                     double* rs, uint8_t* fs) {
+template <typename T, int TX, int TY>
+__device__ inline void fine_store_rf(const T (&r)[FineTile<TX, TY>::NQ], const uint8_t (&f)[FineTile<TX, TY>::NQ],
+                                     T* rs, uint8_t* fs) {
   using FT = FineTile<TX, TY>;
 #pragma unroll
   for (int e = 0; e < FT::NQ; ++e) {
@@ -541,7 +542,7 @@ template <typename T, int TX, int TY, int NS>
 __device__ inline void fine_update(const FineOp& op, const RegularRow<T>& rr, int k, const int (&q0)[NS],
                                    const int (&dq)[NS], const int (&i0)[NS], const int (&i1)[NS], const int (&jj)[NS],
                                    const int (&pb)[NS], const int (&bits)[NS], const T* pm, T* p0, const T* pp,
-                                   const double* rq, const uint8_t* fq) {
+                                   const T* rq, const uint8_t* fq) {
   using FT = FineTile<TX, TY>;
   const Dims& d = op.d;
   int kw = k;
@@ -590,10 +591,10 @@ __device__ inline void fine_write(const Dims& d, const FineSlots<TX, TY>& S, int
                                  (RS), (FS_))
 
 template <typename T, int TX, int TY>
-__device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
+__device__ inline void rb_fine_body(const FineOp& op, const T* __restrict__ rhs, const T* __restrict__ xin,
                                     const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int zchunk,
                                     int bx, int by, int bz, T (*xs)[FineTile<TX, TY>::PL],
-                                    double (*rs)[FineTile<TX, TY>::QL], uint8_t (*fs)[FineTile<TX, TY>::QL]) {
+                                    T (*rs)[FineTile<TX, TY>::QL], uint8_t (*fs)[FineTile<TX, TY>::QL]) {
   using FT = FineTile<TX, TY>;
   using FS = FineSlots<TX, TY>;
   const Dims& d = op.d;
@@ -602,13 +603,13 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
   FS S;
   fine_slots<TX, TY>(d, cd, tx0, ty0, S);
   T xv[FT::NX];
-  double rv[FT::NQ];
+  T rv[FT::NQ];
   uint8_t fv[FT::NQ];
   if (d.dim < 3) {
     fine_load_x<T, TX, TY>(d, cd, S, 0, xin, xc, xv);
-    fine_load_rf<TX, TY>(d, S, 0, rhs, op.flags, rv, fv);
+    fine_load_rf<T, TX, TY>(d, S, 0, rhs, op.flags, rv, fv);
     fine_store<T, TX, TY>(xv, xs[0]);
-    fine_store_rf<TX, TY>(rv, fv, rs[0], fs[0]);
+    fine_store_rf<T, TX, TY>(rv, fv, rs[0], fs[0]);
     __syncthreads();
     FINE_RED(0, xs[0], xs[0], xs[0], rs[0], fs[0]);
     __syncthreads();
@@ -622,18 +623,18 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
   const int z1 = min(z0 + zchunk, d.n[2]);
   {
     T xa[FT::NX], xb[FT::NX];
-    double ra[FT::NQ];
+    T ra[FT::NQ];
     uint8_t fa[FT::NQ];
     fine_load_x<T, TX, TY>(d, cd, S, z0 - 2, xin, xc, xv);
     fine_load_x<T, TX, TY>(d, cd, S, z0 - 1, xin, xc, xa);
     fine_load_x<T, TX, TY>(d, cd, S, z0, xin, xc, xb);
-    fine_load_rf<TX, TY>(d, S, z0 - 1, rhs, op.flags, rv, fv);
-    fine_load_rf<TX, TY>(d, S, z0, rhs, op.flags, ra, fa);
+    fine_load_rf<T, TX, TY>(d, S, z0 - 1, rhs, op.flags, rv, fv);
+    fine_load_rf<T, TX, TY>(d, S, z0, rhs, op.flags, ra, fa);
     fine_store<T, TX, TY>(xv, xs[(z0 - 2) & 3]);
     fine_store<T, TX, TY>(xa, xs[(z0 - 1) & 3]);
     fine_store<T, TX, TY>(xb, xs[z0 & 3]);
-    fine_store_rf<TX, TY>(rv, fv, rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
-    fine_store_rf<TX, TY>(ra, fa, rs[z0 & 1], fs[z0 & 1]);
+    fine_store_rf<T, TX, TY>(rv, fv, rs[(z0 - 1) & 1], fs[(z0 - 1) & 1]);
+    fine_store_rf<T, TX, TY>(ra, fa, rs[z0 & 1], fs[z0 & 1]);
     fine_load_x<T, TX, TY>(d, cd, S, z0 + 1, xin, xc, xv);
     fine_store<T, TX, TY>(xv, xs[(z0 + 1) & 3]);
   }
@@ -642,16 +643,16 @@ __device__ inline void rb_fine_body(const FineOp& op, const double* __restrict__
   __syncthreads();
   FINE_RED(z0, xs[(z0 - 1) & 3], xs[z0 & 3], xs[(z0 + 1) & 3], rs[z0 & 1], fs[z0 & 1]);
   fine_load_x<T, TX, TY>(d, cd, S, z0 + 2, xin, xc, xv);
-  fine_load_rf<TX, TY>(d, S, z0 + 1, rhs, op.flags, rv, fv);
+  fine_load_rf<T, TX, TY>(d, S, z0 + 1, rhs, op.flags, rv, fv);
   __syncthreads();
   for (int k = z0; k < z1; ++k) {
     // plane k+2's iterate replaces plane k-2's, plane k+1's r / flags replace plane k-1's
     fine_store<T, TX, TY>(xv, xs[(k + 2) & 3]);
-    fine_store_rf<TX, TY>(rv, fv, rs[(k + 1) & 1], fs[(k + 1) & 1]);
+    fine_store_rf<T, TX, TY>(rv, fv, rs[(k + 1) & 1], fs[(k + 1) & 1]);
     __syncthreads();
     if (k + 1 < z1) {
       fine_load_x<T, TX, TY>(d, cd, S, k + 3, xin, xc, xv);
-      fine_load_rf<TX, TY>(d, S, k + 2, rhs, op.flags, rv, fv);
+      fine_load_rf<T, TX, TY>(d, S, k + 2, rhs, op.flags, rv, fv);
     }
     FINE_RED(k + 1, xs[k & 3], xs[(k + 1) & 3], xs[(k + 2) & 3], rs[(k + 1) & 1], fs[(k + 1) & 1]);
     __syncthreads();
@@ -734,18 +735,19 @@ __device__ inline void restrict2(const Dims& d, const Dims& cd, int tx0, int ty0
 
 // fine level, 2D
 template <typename T, int TX, int TY, int NSW, int RES>
-__device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict__ rhs, const T* __restrict__ xin,
+__device__ inline void rb_fine2d_body(const FineOp& op, const T* __restrict__ rhs, const T* __restrict__ xin,
                                       const T* __restrict__ xc, const Dims& cd, T* __restrict__ xout, int bx, int by,
-                                      T* xs, double* rs, uint8_t* fs, T* __restrict__ bc, T* __restrict__ xcz,
+                                      T* xs, T* rs, uint8_t* fs, T* __restrict__ bc, T* __restrict__ xcz,
                                       int split, int dots = 0, const double* __restrict__ qv = nullptr,
-                                      double* __restrict__ partial = nullptr, int slot = 0, int nslot = 0) {
+                                      double* __restrict__ partial = nullptr, int slot = 0, int nslot = 0,
+                                      const double* __restrict__ r64 = nullptr) {
   using W = Win2<TX, TY, NSW, RES>;
   const Dims& d = op.d;
   const RegularRow<T> rr = regular_row<T>(op);
   const int tx0 = bx * TX, ty0 = by * TY;
   constexpr int NP = (W::PL + RB_THREADS - 1) / RB_THREADS, NQ = (W::QL + RB_THREADS - 1) / RB_THREADS;
   T vx[NP];
-  double vr[NQ];
+  T vr[NQ];
   uint8_t vf[NQ];
 #pragma unroll
   for (int e = 0; e < NP; ++e) {
@@ -760,7 +762,7 @@ __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict
 #pragma unroll
   for (int e = 0; e < NQ; ++e) {
     const int t = threadIdx.x + e * RB_THREADS;
-    vr[e] = 0.0;
+    vr[e] = (T)0;
     vf[e] = 0;
     int i = tx0 + t % W::QX - W::QR, j = ty0 + t / W::QX - W::QR;
     if (t < W::QL && wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
@@ -820,14 +822,18 @@ __device__ inline void rb_fine2d_body(const FineOp& op, const double* __restrict
   }
   if (dots) {
     // the outer loop's z.r and (dots == 1) z.q over this tile, from the
-    // final iterate and r in LDS: one partial per tile
+    // final iterate and the FP64 r (in LDS when the sweep smooths against
+    // it, else read here): one partial per tile
     double v[2] = {0, 0};
     for (int t = threadIdx.x; t < TX * TY; t += RB_THREADS) {
       const int lx = t % TX, ly = t / TX;
       const int i = tx0 + lx, j = ty0 + ly;
       if (i < d.n[0] && j < d.n[1]) {
         const double zc = (double)xs[(ly + W::H) * W::PX + (lx + W::H)];
-        v[0] += zc * rs[(ly + W::QR) * W::QX + (lx + W::QR)];
+        if constexpr (std::is_same<T, double>::value)
+          v[0] += zc * rs[(ly + W::QR) * W::QX + (lx + W::QR)];
+        else
+          v[0] += zc * r64[i + (long long)d.n[0] * j];
         if (dots == 1) v[1] += zc * qv[i + (long long)d.n[0] * j];
       }
     }
@@ -1811,10 +1817,10 @@ __device__ inline void dd_add(double& hi, double& lo, double p, double pe) {
 // rounding of x itself, eps |x| per entry and not smooth, leaves a residual
 // of that size).  With the compensated residual the outer loop's restarts
 // steer x to the correctly rounded discrete solution.
-template <int SYS>
+template <int SYS, typename T = double>
 __device__ inline void resid_init_body(const FineOp& op, const double* __restrict__ b, const double* __restrict__ x,
                                        double* __restrict__ r, double* partial, int lb, int nb,
-                                       double* __restrict__ xzero = nullptr) {
+                                       double* __restrict__ xzero = nullptr, T* __restrict__ rv = nullptr) {
   double v[3] = {0, 0, 0};
   CASE_STRIDE(c, op.d.N) {
     const double bc = b[c];
@@ -1849,6 +1855,8 @@ __device__ inline void resid_init_body(const FineOp& op, const double* __restric
       rc = hi + lo;
     }
     if (r) r[c] = rc;
+    if constexpr (!std::is_same<T, double>::value)
+      if (rv) rv[c] = (T)rc;
     v[0] += bc * bc;
     v[1] += rc * rc;
     v[2] += ac * ac;
@@ -1990,6 +1998,7 @@ struct SolveCase {
   const double* b;
   double* x;
   double* r;
+  T* rv;             // the V-cycle's fine right-hand side: r itself (FP64) or its FP32 copy (mixed)
   T* z[2];           // V-cycle result (z[0]) and the second sweep buffer
   double* p[2];
   double* q;
@@ -2025,8 +2034,8 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
   if (!selected(ctl[c], mask)) return;
   const SolveCase<T>& C = cs[c];
   const FineOp op = C.op;
-  resid_init_body<SYS>(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb,
-                       zero_x ? C.x : nullptr);
+  resid_init_body<SYS, T>(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb,
+                       zero_x ? C.x : nullptr, C.rv);
 }
 
 template <typename T>
@@ -2051,7 +2060,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   constexpr int QB = W::QL > 2 * FT::QL ? (W::QL + 1) / 2 : FT::QL;
   static_assert(W::PL <= 4 * FT::PL && W::QL <= 2 * QB, "2D windows must fit the sweep buffers");
   __shared__ T xs[4][FT::PL];
-  __shared__ double rs[2][QB];
+  __shared__ T rs[2][QB];
   __shared__ uint8_t fs[2][QB];
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
@@ -2059,7 +2068,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
   // goes back to the table
   const SolveCase<T>& C = cs[c];
   const FineOp op = C.op;
-  const double* r = C.r;
+  const T* r = C.rv;
   const T* zin = in_sel < 0 ? nullptr : (const T*)C.z[in_sel];
   T* zout = C.z[out_sel];
   const T* xc = add_xc ? (const T*)C.lx[1][0] : nullptr;
@@ -2100,7 +2109,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_rb_fine(const SolveCase<T>* __r
     int dm = 0;
     if (dots && C.ndot > 0) dm = (dots == 2 || cc.fresh) ? 2 : 1;
     rb_fine2d_body<T, TX, TY, NSW, RES>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz,
-                                        C.lt == 1, dm, C.q, C.partial, lb, C.ndot);
+                                        C.lt == 1, dm, C.q, C.partial, lb, C.ndot, C.r);
   } else {
     if (op.d.dim == 2)
       rb_fine2d_body<T, TX, TY, NSW, 0>(op, r, zin, xc, cd, zout, bx, by, &xs[0][0], &rs[0][0], &fs[0][0], bc, xcz,
@@ -2160,7 +2169,7 @@ __global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const Case
       even_child(ch, di, dj, dk);
       const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
       if (i < op.d.n[0] && j < op.d.n[1] && k < op.d.n[2])
-        sum += fine_residual_at<T, double>(op, i, j, k, cell_index(op.d, i, j, k), C.r, x);
+        sum += fine_residual_at<T, T>(op, i, j, k, cell_index(op.d, i, j, k), C.rv, x);
     }
     bc[C.lt == 1 ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = sum;
     xc[I] = (T)0;
@@ -2528,11 +2537,14 @@ __global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, CaseCtl* __res
   const double* q = C.q;
   double* x = C.x;
   double* r = C.r;
+  T* rv = C.rv;
   double v[1] = {0};
   CASE_STRIDE(i, C.op.d.N) {
     x[i] += alpha * p[i];
     const double rc = r[i] - alpha * q[i];
     r[i] = rc;
+    // the mixed-precision V-cycle reads r rounded once to FP32, here
+    if constexpr (!std::is_same<T, double>::value) rv[i] = (T)rc;
     v[0] += rc * rc;
   }
   write_partials<1>(v, C.partial + 3 * nb, lb, nb);
@@ -2821,6 +2833,12 @@ template <>
 const double* timg<double>(const EbitLevelHost& L, int sys) { return L.img64[sys]; }
 template <typename T>
 T* zb(const EbitSolveBufs& B, int s);
+template <typename T>
+T* rvb(const EbitSolveBufs& B);
+template <>
+double* rvb<double>(const EbitSolveBufs& B) { return B.r; }
+template <>
+float* rvb<float>(const EbitSolveBufs& B) { return B.r32; }
 template <>
 double* zb<double>(const EbitSolveBufs& B, int s) { return s ? B.z64b : B.z64; }
 template <>
@@ -3260,6 +3278,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       C.b = pc.b;
       C.x = nullptr;
       C.r = pc.B.r;
+      C.rv = rvb<T>(pc.B);
       C.z[0] = zb<T>(pc.B, 0);
       C.z[1] = zb<T>(pc.B, 1);
       C.p[0] = pc.B.p[0];
