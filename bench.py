@@ -393,9 +393,10 @@ def host_cpu():
 def sweeps_per_launch(dim, schedule):
     """Red-black sweeps one fine smoothing launch performs: on 2D grids the
     library runs the sweeps of a smoothing run in pairs (a run of nu sweeps
-    takes ceil(nu/2) launches), in 3D one per launch."""
+    takes ceil(nu/2) launches); in 3D a launch is one colour of a sweep (the
+    colour-split half-sweeps)."""
     if dim != 2:
-        return 1.0
+        return 0.5
     nu1, nu2 = (schedule or {}).get("nu1", 2), (schedule or {}).get("nu2", 2)
     return (nu1 + nu2) / ((nu1 + 1) // 2 + (nu2 + 1) // 2)
 

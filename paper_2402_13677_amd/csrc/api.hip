@@ -212,11 +212,17 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
   double* nF = cv.take<double>(3 * N);
   double* bvec = cv.take<double>(N);
   EbitSolveBufs B;
+  // 3D: the fine smoother's iterate, right-hand side and flags are kept in
+  // the colour-split order, 2 H entries (N, plus one row per (j, k) when n0
+  // is odd)
+  const long long NS = fd.dim == 3 ? 2 * split_half(fd) : N;
   B.r = cv.take<double>(N);
-  B.r32 = cv.take<float>(N);
-  B.z64 = cv.take<double>(N);
+  B.r32 = cv.take<float>(NS);
+  B.r64s = cv.take<double>(fd.dim == 3 ? NS : 0);
+  B.fsplit = cv.take<uint8_t>(fd.dim == 3 ? NS : 0);
+  B.z64 = cv.take<double>(NS);
   B.z64b = cv.take<double>(N);
-  B.z32 = cv.take<float>(N);
+  B.z32 = cv.take<float>(NS);
   B.z32b = cv.take<float>(N);
   B.p[0] = cv.take<double>(N);
   B.p[1] = cv.take<double>(N);
@@ -424,6 +430,7 @@ ebit_status build_operators(ebit_ctx* c, hipStream_t st) {
   set_ops(c);
   const int want32 = c->opts.precision == EBIT_MIXED;
   HIPCK(c, ebit_build_hierarchy(c->op, c->lv, c->nlev, want32, c->build_tabs, c->build_ls, st), "hierarchy");
+  if (c->fd.dim == 3) HIPCK(c, ebit_launch_split_flags(&c->fd, c->flags, c->B.fsplit, st), "split flags");
   return EBIT_OK;
 }
 

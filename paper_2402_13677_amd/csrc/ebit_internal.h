@@ -41,6 +41,18 @@ struct Dims {
   long long N;
 };
 
+// Colour-split order of the 3D fine level: the cells of colour c
+// ((i + j + k) & 1 == c) sit at slot (i >> 1) + hw (j + n1 k), hw = (n0 + 1) / 2,
+// of the half c * H .. c * H + H - 1 of an array of 2 H entries, H = hw n1 n2.
+// A red or black half-sweep then reads the other colour's half and writes
+// its own, both contiguous.
+__host__ __device__ inline long long split_half(const Dims& d) {
+  return (long long)((d.n[0] + 1) / 2) * d.n[1] * d.n[2];
+}
+__host__ __device__ inline long long split_index(const Dims& d, long long H, int i, int j, int k) {
+  return ((i + j + k) & 1) * H + (i >> 1) + (long long)((d.n[0] + 1) / 2) * (j + (long long)d.n[1] * k);
+}
+
 // Tail image: the coarse levels of at most EBIT_TAIL_IMG_CELLS cells keep,
 // per system, their coefficients in one contiguous array, level after level
 // from fine to coarse (fields diag, 1/diag, off[0 .. dim-1]), followed by
@@ -289,6 +301,9 @@ struct EbitProfiler {
 struct EbitSolveBufs {
   double* r;
   float* r32;          // FP32 copy of r: the right-hand side the mixed-precision V-cycle reads
+                       // (3D: in the colour-split order of the fine smoother)
+  double* r64s;        // 3D, FP64 V-cycles: r in the colour-split order
+  uint8_t* fsplit;     // 3D: the cell flags in the colour-split order
   double* z64;
   double* z64b;
   float* z32;
@@ -306,6 +321,7 @@ hipError_t ebit_launch_geometry(const ebit::Dims* d, double h, const double* con
                                 const uint8_t* ccol, uint8_t* flags, double* cF, double* nF, double* const th[3],
                                 ebit::Scal* scal, hipStream_t st);
 hipError_t ebit_launch_fill_f64(long long n, double* x, double v, hipStream_t st);
+hipError_t ebit_launch_split_flags(const ebit::Dims* d, const uint8_t* flags, uint8_t* fsplit, hipStream_t st);
 // Narrow-band extension.  Scratch: bytes (2 N), list (N entries),
 // w[0..dim-1] (N doubles each), counter (one int); work (N doubles) holds
 // every other iterate.

@@ -1820,7 +1820,9 @@ __device__ inline void dd_add(double& hi, double& lo, double p, double pe) {
 template <int SYS, typename T = double>
 __device__ inline void resid_init_body(const FineOp& op, const double* __restrict__ b, const double* __restrict__ x,
                                        double* __restrict__ r, double* partial, int lb, int nb,
-                                       double* __restrict__ xzero = nullptr, T* __restrict__ rv = nullptr) {
+                                       double* __restrict__ xzero = nullptr, T* __restrict__ rv = nullptr,
+                                       int split = 0) {
+  const long long H = split ? split_half(op.d) : 0;
   double v[3] = {0, 0, 0};
   CASE_STRIDE(c, op.d.N) {
     const double bc = b[c];
@@ -1855,8 +1857,15 @@ __device__ inline void resid_init_body(const FineOp& op, const double* __restric
       rc = hi + lo;
     }
     if (r) r[c] = rc;
-    if constexpr (!std::is_same<T, double>::value)
-      if (rv) rv[c] = (T)rc;
+    if (rv) {
+      if (split) {
+        int i, j, k;
+        cell_ijk(op.d, c, i, j, k);
+        rv[split_index(op.d, H, i, j, k)] = (T)rc;
+      } else {
+        rv[c] = (T)rc;
+      }
+    }
     v[0] += bc * bc;
     v[1] += rc * rc;
     v[2] += ac * ac;
@@ -1998,7 +2007,10 @@ struct SolveCase {
   const double* b;
   double* x;
   double* r;
-  T* rv;             // the V-cycle's fine right-hand side: r itself (FP64) or its FP32 copy (mixed)
+  T* rv;             // the V-cycle's fine right-hand side: r itself (2D FP64) or its copy (FP32, or 3D
+                     // in the colour-split order)
+  const uint8_t* fs; // 3D: the flags in the colour-split order
+  int split;         // 3D: the fine iterate z[0], rv and fs are in the colour-split order
   T* z[2];           // V-cycle result (z[0]) and the second sweep buffer
   double* p[2];
   double* q;
@@ -2035,7 +2047,8 @@ __global__ void kb_resid_init(const SolveCase<T>* __restrict__ cs, const CaseCtl
   const SolveCase<T>& C = cs[c];
   const FineOp op = C.op;
   resid_init_body<SYS, T>(op, C.b, use_x ? (const double*)C.x : nullptr, C.r, C.partial, lb, nb,
-                       zero_x ? C.x : nullptr, C.rv);
+                       zero_x ? C.x : nullptr,
+                          (C.split || !std::is_same<T, double>::value) ? C.rv : nullptr, C.split);
 }
 
 template <typename T>
@@ -2176,6 +2189,311 @@ __global__ void kb_fine_restrict(const SolveCase<T>* __restrict__ cs, const Case
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3D fine level in the colour-split order (split_index): a red-black sweep
+// is two launches, one per colour.  A half-sweep reads the other colour's
+// half of the iterate and writes its own: every access is a coalesced
+// stream, 13 bytes per cell and full sweep in FP32 (read x of the other
+// colour, r and the flag; write x), with the six neighbour reads of a cell
+// served from the caches.
+// ---------------------------------------------------------------------------
+
+// the other-colour neighbours of cell (i, j, k) (slot s of its colour):
+// -x, +x, -y, +y, -z, +z; q < 0 where the neighbour is beyond a wall.  A
+// step of one cell wraps by adding or subtracting the axis length.
+__device__ inline void split_nbrs(const Dims& d, int hw, int i, int j, int k, long long s, long long (&q)[6],
+                                  int (&ni)[6], int (&nj)[6], int (&nk)[6]) {
+  const long long row = hw, plane = (long long)hw * d.n[1];
+  const long long rs = s - (i >> 1);  // slot of the row's first cell
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    ni[e] = i;
+    nj[e] = j;
+    nk[e] = k;
+    q[e] = s;
+  }
+  // -x / +x: the other colour's slot in the same row
+  int a = i - 1;
+  if (a < 0) a = d.per[0] ? a + d.n[0] : -1;
+  ni[0] = a;
+  q[0] = a >= 0 ? rs + (a >> 1) : -1;
+  a = i + 1;
+  if (a >= d.n[0]) a = d.per[0] ? a - d.n[0] : -1;
+  ni[1] = a;
+  q[1] = a >= 0 ? rs + (a >> 1) : -1;
+  // -y / +y
+  a = j - 1;
+  if (a < 0) a = d.per[1] ? a + d.n[1] : -1;
+  nj[2] = a;
+  q[2] = a >= 0 ? s + row * (a - j) : -1;
+  a = j + 1;
+  if (a >= d.n[1]) a = d.per[1] ? a - d.n[1] : -1;
+  nj[3] = a;
+  q[3] = a >= 0 ? s + row * (a - j) : -1;
+  // -z / +z
+  a = k - 1;
+  if (a < 0) a = d.per[2] ? a + d.n[2] : -1;
+  nk[4] = a;
+  q[4] = a >= 0 ? s + plane * (a - k) : -1;
+  a = k + 1;
+  if (a >= d.n[2]) a = d.per[2] ? a - d.n[2] : -1;
+  nk[5] = a;
+  q[5] = a >= 0 ? s + plane * (a - k) : -1;
+}
+
+// Tiles of the colour-split kernels: 64 slots of a row x 4 rows (j) of one
+// plane (k); a wave takes 64 consecutive slots.  The block -> tile mapping
+// needs no per-thread division.
+#define SP_TX 64
+#define SP_TY 4
+__host__ __device__ inline int split_tiles(int nx, int ny, int nz) {
+  return ((nx + SP_TX - 1) / SP_TX) * ((ny + SP_TY - 1) / SP_TY) * nz;
+}
+// A work-group takes SP_TPB consecutive tiles: the per-block set-up (work
+// list, control word, operator, constants) is paid once for all of them, and
+// the tiles of one XCD's work-groups are contiguous (xcd_tile).
+#define SP_TPB 8
+#define SP_TPB_R 2  // the restriction: four children per thread, fewer tiles per work-group
+__host__ __device__ inline int split_blocks(int tiles, int tpb = SP_TPB) { return (tiles + tpb - 1) / tpb; }
+__device__ inline void split_tile(int t, int nx, int ny, int& x, int& y, int& z) {
+  const int gx = (nx + SP_TX - 1) / SP_TX, gy = (ny + SP_TY - 1) / SP_TY;
+  const int bx = t % gx, r = t / gx;
+  x = bx * SP_TX + (int)(threadIdx.x % SP_TX);
+  y = (r % gy) * SP_TY + (int)(threadIdx.x / SP_TX);
+  z = r / gy;
+}
+
+// pointers the compiler may address as global memory (global_load /
+// global_store instead of the generic flat forms)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// Buffer-resource access to the colour-split arrays: a 32-bit byte offset
+// per lane (one add per neighbour instead of a 64-bit address), and a load
+// past the end of the buffer returns 0.  Every array addressed this way has
+// fewer than 2^31 bytes (the plan keeps larger grids on the LDS sweeps).
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+__device__ inline BufRsrc buf_rsrc(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline T buf_load(BufRsrc r, int off);
+template <>
+__device__ inline float buf_load<float>(BufRsrc r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ inline double buf_load<double>(BufRsrc r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline void buf_store(float v, BufRsrc r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline void buf_store(double v, BufRsrc r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// One colour of a red-black Gauss-Seidel sweep of the 3D fine level: every
+// cell of colour `color` takes its new value from the other colour's current
+// values.  first: the other colour is zero (the first half-sweep of a V-cycle
+// from a zero guess: no neighbour is read).  add_xc: the other colour's
+// values take the coarse-grid correction of their level-1 parent (the first
+// post-smoothing half-sweep; the correction of this colour's own values is
+// never needed, a Gauss-Seidel update does not read the old value).  Rows
+// and the neighbour sum are formed as in the LDS sweeps, so each new value
+// has the same bits as in a whole-grid half-sweep of the natural order.
+//
+// A wave takes 64 consecutive slots of one row (j, k): in the colour-split
+// order the x-neighbours of slot s (cell i = 2 ih + par) are the other
+// colour's slots s + par - 1 and s + par, the y- and z-neighbours s -+ hw
+// and s -+ hw n1.  j, k and par are the same for the whole wave, so the y/z
+// offsets and their boundary cases are scalar; only the first and last cell
+// of a row wrap (periodic) or lose a neighbour (wall: it reads as 0).
+template <typename T>
+__global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __restrict__ cs,
+                                                       const CaseCtl* __restrict__ ctl, WorkList wl, int color,
+                                                       int first, int add_xc) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const FineOp op = C.op;
+  const Dims& d = op.d;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const int hw = (n0 + 1) >> 1;
+  const int plane = hw * n1;
+  const long long H = split_half(d);
+  constexpr int TS = (int)sizeof(T);
+  const BufRsrc bxo = buf_rsrc(C.z[0] + color * H, H * TS);
+  const BufRsrc bxn = buf_rsrc(C.z[0] + (color ^ 1) * H, H * TS);
+  const BufRsrc brv = buf_rsrc(C.rv + color * H, H * TS);
+  const BufRsrc bfl = buf_rsrc(C.fs + color * H, H);
+  const gptr<const T> xc = (gptr<const T>)(add_xc ? (const T*)C.lx[1][0] : nullptr);
+  const int cn0 = C.lev[1].d.n[0], cn1 = C.lev[1].d.n[1];
+  // the per-phase constant row, formed once per work-group and read back
+  // from LDS (kept out of the per-cell code, where the compiler would
+  // otherwise divide again)
+  __shared__ RegularRow<T> srr;
+  if (threadIdx.x == 0) srr = regular_row<T>(op);
+  __syncthreads();
+  const RegularRow<T> rr = srr;
+  const bool p0 = d.per[0], p1 = d.per[1], p2 = d.per[2];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int gx = (hw + SP_TX - 1) / SP_TX, gy = (n1 + SP_TY - 1) / SP_TY;
+  const int tiles = gx * gy * n2;
+  const int t0 = xcd_tile(lb, nb) * SP_TPB, t1 = min(t0 + SP_TPB, tiles);
+  // tile coordinates of the first tile, then stepped (the scalar unit is
+  // shared by the CU's waves: no division per tile)
+  int bx = t0 % gx, by = (t0 / gx) % gy, k = t0 / (gx * gy);
+  for (int t = t0; t < t1; ++t) {
+    if (t > t0 && ++bx == gx) {
+      bx = 0;
+      if (++by == gy) {
+        by = 0;
+        ++k;
+      }
+    }
+    const int j = by * SP_TY + wv;
+    if (j >= n1) continue;  // the whole wave
+    const int par = (color + j + k) & 1;
+    const int ih = bx * SP_TX + lane;
+    const int i = 2 * ih + par;
+    const bool ok = ih < hw && i < n0;
+    const int s = hw * (j + n1 * k) + ih;
+    const int sb = s * TS;
+    const uint8_t f = __builtin_amdgcn_raw_buffer_load_b8(bfl, s, 0, 0);
+    const T rc = buf_load<T>(brv, sb);
+    const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
+    T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+    if (!first) {
+      // offsets of the six neighbours (slots) and whether each exists
+      const int dx0 = xm ? (p0 ? hw - 1 : 0) : par - 1;
+      const int dx1 = xp ? (p0 ? -ih : 0) : par;
+      const int dy0 = ym ? (p1 ? hw * (n1 - 1) : 0) : -hw;
+      const int dy1 = yp ? (p1 ? -hw * (n1 - 1) : 0) : hw;
+      const int dz0 = zm ? (p2 ? plane * (n2 - 1) : 0) : -plane;
+      const int dz1 = zp ? (p2 ? -plane * (n2 - 1) : 0) : plane;
+      T w[6];
+      w[0] = buf_load<T>(bxn, sb + dx0 * TS);
+      w[1] = buf_load<T>(bxn, sb + dx1 * TS);
+      w[2] = buf_load<T>(bxn, sb + dy0 * TS);
+      w[3] = buf_load<T>(bxn, sb + dy1 * TS);
+      w[4] = buf_load<T>(bxn, sb + dz0 * TS);
+      w[5] = buf_load<T>(bxn, sb + dz1 * TS);
+      if (xc) {
+        // parent cells of the neighbours on level 1 (the wrapped index on a
+        // periodic axis; any in-range cell beyond a wall)
+        const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
+        const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
+        const int km = zm ? n2 - 1 : k - 1, kp = zp ? 0 : k + 1;
+        const int pj = (j >> 1) * cn0, pk = (k >> 1) * cn0 * cn1;
+        const int pi = min(i, n0 - 1) >> 1;
+        const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
+                             pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
+                             pi + pj + (kp >> 1) * cn0 * cn1};
+        T e6[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) e6[e] = xc[ok ? par6[e] : 0];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) w[e] += e6[e];
+      }
+      const bool h[6] = {!xm || p0, !xp || p0, !ym || p1, !yp || p1, !zm || p2, !zp || p2};
+#pragma unroll
+      for (int e = 0; e < 6; ++e) v[e] = h[e] ? w[e] : (T)0;
+    }
+    if (!ok) continue;
+    const bool wall = (!p0 && (xm || xp)) || (!p1 && (ym || yp)) || (!p2 && (zm || zp));
+    T x;
+    if (!(f & F_CUT) && !wall) {
+      const bool liq = (f & F_LIQ) != 0;
+      T xs = (v[0] + v[1]) + (v[2] + v[3]);
+      xs += v[4] + v[5];
+      x = (rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0);
+    } else {
+      T diag, off[6], mass, rb = 0;
+      fine_row<T>(op, i, j, k, f, diag, off, mass, rb);
+      T sum = rc - off[0] * v[0] - off[1] * v[1];
+      sum -= off[2] * v[2] + off[3] * v[3];
+      sum -= off[4] * v[4] + off[5] * v[5];
+      x = sum / diag;
+    }
+    buf_store(x, bxo, sb);
+  }
+}
+
+// Residual + restriction of the 3D fine level in the colour-split order:
+// after a pre-smoothing that ends with the black half-sweep only the red
+// children carry a residual (even_child), r - A x as fine_residual_at forms
+// it; also clears the level-1 iterate.  One thread per coarse cell, in
+// tiles of the coarse grid.
+template <typename T>
+__global__ void kb_fine_restrict_split(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl,
+                                       WorkList wl) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const FineOp op = C.op;
+  const Dims& d = op.d;
+  const Dims cd = C.lev[1].d;
+  const int hw = (d.n[0] + 1) >> 1;
+  const long long H = split_half(d);
+  const T* z = C.z[0];
+  const T* rv = C.rv;
+  const uint8_t* fl = C.fs;
+  T* bc = C.lb[1];
+  T* xcz = C.lx[1][0];
+  const int tiles = split_tiles(cd.n[0], cd.n[1], cd.n[2]);
+  const int t0 = xcd_tile(lb, nb) * SP_TPB_R, t1 = min(t0 + SP_TPB_R, tiles);
+  for (int t = t0; t < t1; ++t) {
+    int ci, cj, ck;
+    split_tile(t, cd.n[0], cd.n[1], ci, cj, ck);
+    if (ci >= cd.n[0] || cj >= cd.n[1]) continue;
+    T sum = 0;
+    for (int ch = 0; ch < 4; ++ch) {
+      int di, dj, dk;
+      even_child(ch, di, dj, dk);
+      const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+      if (i < d.n[0] && j < d.n[1] && k < d.n[2]) {
+        const long long sc = split_index(d, H, i, j, k);  // colour 0
+        long long q[6];
+        int ni[6], nj[6], nk[6];
+        split_nbrs(d, hw, i, j, k, sc, q, ni, nj, nk);
+        T xn[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) xn[e] = q[e] >= 0 ? z[H + q[e]] : (T)0;
+        T diag, off[6], mass, rb = 0;
+        fine_row<T>(op, i, j, k, fl[sc], diag, off, mass, rb);
+        T r = rv[sc] - diag * z[sc];
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+          if (off[e] != (T)0) r -= off[e] * xn[e];
+        sum += r;
+      }
+    }
+    const long long I = ci + (long long)cd.n[0] * (cj + (long long)cd.n[1] * ck);
+    bc[C.lt == 1 ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = sum;
+    xcz[I] = (T)0;
+  }
+}
+
+// the cell flags in the colour-split order (padding slots of odd n0: 0)
+__global__ void k_split_flags(Dims d, const uint8_t* __restrict__ flags, uint8_t* __restrict__ fs) {
+  const long long H = split_half(d);
+  const int hw = (d.n[0] + 1) >> 1;
+  GRID_STRIDE(t, 2 * H) {
+    const int color = t >= H ? 1 : 0;
+    const long long s = t - color * H;
+    const int ih = (int)(s % hw);
+    const long long jk = s / hw;
+    const int j = (int)(jk % d.n[1]), k = (int)(jk / d.n[1]);
+    const int i = 2 * ih + ((color + j + k) & 1);
+    fs[t] = i < d.n[0] ? flags[i + (long long)d.n[0] * jk] : (uint8_t)0;
+  }
+}
+
 // the same from explicit level l to level l + 1
 template <typename T>
 __global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
@@ -2231,9 +2549,16 @@ __global__ void kb_dots(const SolveCase<T>* __restrict__ cs, const CaseCtl* __re
   const T* z = C.z[0];
   const double* r = C.r;
   const double* q = C.q;
+  const long long H = C.split ? split_half(C.op.d) : 0;
   double v[2] = {0, 0};
   CASE_STRIDE(i, C.op.d.N) {
-    const double zc = (double)z[i];
+    long long zi = i;
+    if (C.split) {
+      int ci, cj, ck;
+      cell_ijk(C.op.d, i, ci, cj, ck);
+      zi = split_index(C.op.d, H, ci, cj, ck);
+    }
+    const double zc = (double)z[zi];
     v[0] += zc * r[i];
     if (!first) v[1] += zc * q[i];
   }
@@ -2313,6 +2638,7 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
   const double* p_old = C.p[cc.pi];
   double* p_new = C.p[cc.pi ^ 1];
   double* q = C.q;
+  const long long HS = C.split ? split_half(op.d) : 0;
   double v[1] = {0};
   const I N = (I)op.d.N, stride = (I)nb * (I)blockDim.x;
   for (I i0 = (I)xcd_tile(lb, nb) * (I)blockDim.x + (I)threadIdx.x; i0 < N; i0 += stride) {
@@ -2322,11 +2648,18 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
     // is assembled (see fine_nbrs)
     I m[6];
     fine_nbrs_t<I>(op.d, i, j, k, i0, m);
+    // z of a cell: natural order, or the colour-split order (3D)
+    auto zat = [&](I mm) -> double {
+      if (!C.split) return (double)z[mm];
+      int ci, cj, ck;
+      cell_ijk(op.d, (long long)mm, ci, cj, ck);
+      return (double)z[split_index(op.d, HS, ci, cj, ck)];
+    };
     double pn[6];
 #pragma unroll
     for (int qq = 0; qq < 6; ++qq)
-      pn[qq] = qq < 2 * op.d.dim ? (first ? (double)z[m[qq]] : (double)z[m[qq]] + beta * p_old[m[qq]]) : 0.0;
-    const double pc = first ? (double)z[i0] : (double)z[i0] + beta * p_old[i0];
+      pn[qq] = qq < 2 * op.d.dim ? (first ? zat(m[qq]) : zat(m[qq]) + beta * p_old[m[qq]]) : 0.0;
+    const double pc = first ? zat(i0) : zat(i0) + beta * p_old[i0];
     double diag, off[6], mass, rb = 0, mx;
     fine_row<double, SYS>(op, i, j, k, op.flags[i0], diag, off, mass, rb, &mx);
     double s = mx * pc;
@@ -2359,18 +2692,24 @@ __global__ void kb_p_update_apply(const SolveCase<T>* __restrict__ cs, const Cas
 #define AP_NQ ((AP_QL + RB_THREADS - 1) / RB_THREADS)
 #define AP_NW ((AP_TX * AP_TY + RB_THREADS - 1) / RB_THREADS)
 
+// z is in the colour-split order when H > 0: the window cell of offset
+// qo[e] (i + n0 j) sits at slot zo[e] ((i >> 1) + hw j) of its plane, in the
+// half of colour (zp[e] + k) & 1
 template <typename T>
-__device__ inline void ap_load(const Dims& d, const int (&qo)[AP_NQ], int kk, bool first, double beta,
-                               const T* __restrict__ z, const double* __restrict__ p_old, double (&v)[AP_NQ]) {
+__device__ inline void ap_load(const Dims& d, const int (&qo)[AP_NQ], const int (&zo)[AP_NQ], const int (&zp)[AP_NQ],
+                               long long H, int kk, bool first, double beta, const T* __restrict__ z,
+                               const double* __restrict__ p_old, double (&v)[AP_NQ]) {
   int k = kk;
   const bool pz = wrap_axis(d, 2, k);
   const long long base = (long long)k * d.n[0] * d.n[1];
+  const long long zbase = (long long)k * ((d.n[0] + 1) / 2) * d.n[1];
 #pragma unroll
   for (int e = 0; e < AP_NQ; ++e) {
     v[e] = 0.0;
     if (pz && qo[e] >= 0) {
       const long long m = base + qo[e];
-      v[e] = first ? (double)z[m] : (double)z[m] + beta * p_old[m];
+      const long long mz = H ? ((zp[e] + k) & 1) * H + zbase + zo[e] : m;
+      v[e] = first ? (double)z[mz] : (double)z[mz] + beta * p_old[m];
     }
   }
 }
@@ -2415,6 +2754,7 @@ __global__ __launch_bounds__(RB_THREADS) void kb_apply3d(const SolveCase<T>* __r
   const double beta = sbeta;
   const Dims& d = op.d;
   const T* z = C.z[0];
+  const long long HS = C.split ? split_half(d) : 0;
   const double* p_old = C.p[cc.pi];
   double* p_new = C.p[cc.pi ^ 1];
   double* q = C.q;
@@ -2429,14 +2769,20 @@ __global__ __launch_bounds__(RB_THREADS) void kb_apply3d(const SolveCase<T>* __r
     const int z0 = bz * zc, z1 = min(z0 + zc, d.n[2]);
     // plane-invariant offsets: the staged window (tile + 1 ring, -1 outside
     // the domain) and this thread's tile cells (-1 outside the domain)
-    int qo[AP_NQ], wo[AP_NW], wq[AP_NW], wi[AP_NW], wj[AP_NW];
+    int qo[AP_NQ], zo[AP_NQ], zp[AP_NQ], wo[AP_NW], wq[AP_NW], wi[AP_NW], wj[AP_NW];
 #pragma unroll
     for (int e = 0; e < AP_NQ; ++e) {
       const int t = threadIdx.x + e * RB_THREADS;
       qo[e] = -1;
+      zo[e] = 0;
+      zp[e] = 0;
       if (t >= AP_QL) continue;
       int i = tx0 + t % AP_QX - 1, j = ty0 + t / AP_QX - 1;
-      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) qo[e] = i + d.n[0] * j;
+      if (wrap_axis(d, 0, i) && wrap_axis(d, 1, j)) {
+        qo[e] = i + d.n[0] * j;
+        zo[e] = (i >> 1) + ((d.n[0] + 1) / 2) * j;
+        zp[e] = (i + j) & 1;
+      }
     }
 #pragma unroll
     for (int w = 0; w < AP_NW; ++w) {
@@ -2453,16 +2799,16 @@ __global__ __launch_bounds__(RB_THREADS) void kb_apply3d(const SolveCase<T>* __r
     // had, which no wave reads after the previous plane's barrier, so one
     // barrier per plane suffices (the last plane of a unit ends with a
     // second one before the next unit's stores)
-    ap_load<T>(d, qo, z0 - 1, first, beta, z, p_old, pa);
+    ap_load<T>(d, qo, zo, zp, HS, z0 - 1, first, beta, z, p_old, pa);
     ap_store(pa, ps[(z0 + 3) & 3]);
-    ap_load<T>(d, qo, z0, first, beta, z, p_old, pa);
+    ap_load<T>(d, qo, zo, zp, HS, z0, first, beta, z, p_old, pa);
     ap_store(pa, ps[z0 & 3]);
-    ap_load<T>(d, qo, z0 + 1, first, beta, z, p_old, pa);
+    ap_load<T>(d, qo, zo, zp, HS, z0 + 1, first, beta, z, p_old, pa);
     for (int k = z0; k < z1; ++k) {
       // plane k+1 joins planes k-1 and k
       ap_store(pa, ps[(k + 1) & 3]);
       __syncthreads();
-      if (k + 1 < z1) ap_load<T>(d, qo, k + 2, first, beta, z, p_old, pa);
+      if (k + 1 < z1) ap_load<T>(d, qo, zo, zp, HS, k + 2, first, beta, z, p_old, pa);
       const double* pm = ps[(k + 3) & 3];
       const double* p0 = ps[k & 3];
       const double* pp = ps[(k + 1) & 3];
@@ -2538,13 +2884,21 @@ __global__ void kb_update_xr(const SolveCase<T>* __restrict__ cs, CaseCtl* __res
   double* x = C.x;
   double* r = C.r;
   T* rv = C.rv;
+  const long long H = C.split ? split_half(C.op.d) : 0;
   double v[1] = {0};
   CASE_STRIDE(i, C.op.d.N) {
     x[i] += alpha * p[i];
     const double rc = r[i] - alpha * q[i];
     r[i] = rc;
-    // the mixed-precision V-cycle reads r rounded once to FP32, here
-    if constexpr (!std::is_same<T, double>::value) rv[i] = (T)rc;
+    // the V-cycle's copy of r (rounded once to FP32 in mixed precision;
+    // in the colour-split order in 3D)
+    if (C.split) {
+      int ci, cj, ck;
+      cell_ijk(C.op.d, i, ci, cj, ck);
+      rv[split_index(C.op.d, H, ci, cj, ck)] = (T)rc;
+    } else if constexpr (!std::is_same<T, double>::value) {
+      rv[i] = (T)rc;
+    }
     v[0] += rc * rc;
   }
   write_partials<1>(v, C.partial + 3 * nb, lb, nb);
@@ -2612,6 +2966,12 @@ static inline unsigned nblk(long long n) { return (unsigned)((n + EBIT_BLOCK - 1
 using namespace ebit;
 
 extern "C" {
+
+hipError_t ebit_launch_split_flags(const Dims* d, const uint8_t* flags, uint8_t* fsplit, hipStream_t st) {
+  const long long n = 2 * split_half(*d);
+  hipLaunchKernelGGL(k_split_flags, dim3(nblk(n)), dim3(EBIT_BLOCK), 0, st, *d, flags, fsplit);
+  return hipGetLastError();
+}
 
 hipError_t ebit_launch_fill_f64(long long n, double* x, double v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<double>, dim3(nblk(n)), dim3(EBIT_BLOCK), 0, st, n, x, v);
@@ -2834,11 +3194,11 @@ const double* timg<double>(const EbitLevelHost& L, int sys) { return L.img64[sys
 template <typename T>
 T* zb(const EbitSolveBufs& B, int s);
 template <typename T>
-T* rvb(const EbitSolveBufs& B);
+T* rvb(const EbitSolveBufs& B, int dim);
 template <>
-double* rvb<double>(const EbitSolveBufs& B) { return B.r; }
+double* rvb<double>(const EbitSolveBufs& B, int dim) { return dim == 3 ? B.r64s : B.r; }
 template <>
-float* rvb<float>(const EbitSolveBufs& B) { return B.r32; }
+float* rvb<float>(const EbitSolveBufs& B, int) { return B.r32; }
 template <>
 double* zb<double>(const EbitSolveBufs& B, int s) { return s ? B.z64b : B.z64; }
 template <>
@@ -2932,7 +3292,7 @@ struct PCarver {
 };
 
 constexpr int PLAN_MAX_K = 16;                     // outer iterations per graph block
-constexpr int PLAN_LISTS = 3 + 2 * EBIT_MAX_LEVELS;  // work lists of a plan
+constexpr int PLAN_LISTS = 5 + 2 * EBIT_MAX_LEVELS;  // work lists of a plan
 
 struct HostList {
   WorkList w;
@@ -2954,6 +3314,8 @@ struct PlanT {
   Scal* h_sc = nullptr;
   void* h_blk = nullptr;
   HostList fine, frestrict, red;
+  HostList half;       // 3D: the colour-split half-sweeps (tiles of one colour's slots)
+  HostList hrestrict;  // 3D: their restriction (tiles of level 1)
   HostList coarse[EBIT_MAX_LEVELS], crestrict[EBIT_MAX_LEVELS];
   size_t tail_bytes = 0;
   hipStream_t ist = nullptr;
@@ -2967,6 +3329,8 @@ struct PlanT {
   bool anydot = false, alldot = true;
   // some case has 2^30 cells or more: 64-bit cell offsets in the p-update
   bool wide = false;
+  // 3D: the fine level is smoothed in the colour-split order
+  bool split = false;
 };
 
 template <typename T>
@@ -3094,14 +3458,32 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   auto fine_post = [&](int in, int out, int add, int nsw, int last) {
     launch_fine(P, cs, in, out, add, nsw, 0, last ? dots : 0, st);
   };
-  {
-    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npre);
-    sweep_run(nu1, 1, m, -1, 0, pairs, fuse, fine);
-  }
-  if (!fuse) {
+  // 3D: a sweep is two colour-split half-sweeps (red, then black)
+  auto half = [&](int color, int first, int add) {
+    hipLaunchKernelGGL(kb_half3<T>, dim3(P.half.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, P.half.w, color, first,
+                       add);
+  };
+  if (P.split) {
+    {
+      ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, 2 * nu1);
+      for (int sw = 0; sw < nu1; ++sw) {
+        half(0, sw == 0 ? 1 : 0, 0);
+        half(1, 0, 0);
+      }
+    }
     ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
-    hipLaunchKernelGGL(kb_fine_restrict<T>, dim3(P.frestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                       P.frestrict.w, preb);
+    hipLaunchKernelGGL(kb_fine_restrict_split<T>, dim3(P.hrestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                       P.hrestrict.w);
+  } else {
+    {
+      ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npre);
+      sweep_run(nu1, 1, m, -1, 0, pairs, fuse, fine);
+    }
+    if (!fuse) {
+      ProfScope ps(pf, EBIT_KC_FINE_RESTRICT, st);
+      hipLaunchKernelGGL(kb_fine_restrict<T>, dim3(P.frestrict.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                         P.frestrict.w, preb);
+    }
   }
   for (int l = 1; l < P.Lmax; ++l) {
     auto coarse = [&](int in, int out, int add, int nsw, int res) {
@@ -3131,7 +3513,13 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
     ProfScope ps(pf, EBIT_KC_COARSE, st, npost);
     sweep_run(nu2, npre + 1, m, preb, 1, pairs, 0, coarse);
   }
-  {
+  if (P.split) {
+    ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, 2 * nu2);
+    for (int sw = 0; sw < nu2; ++sw) {
+      half(0, 0, sw == 0 ? 1 : 0);
+      half(1, 0, 0);
+    }
+  } else {
     ProfScope ps(pf, EBIT_KC_FINE_SMOOTH, st, npost);
     sweep_run(nu2, npre + 1, m, preb, 1, pairs, 1, fine_post);
   }
@@ -3267,7 +3655,13 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
     if (lt[c] > P->Lmax) P->Lmax = lt[c];
   }
   P->tail_bytes = tail_elems * sizeof(T);
-  std::vector<std::pair<int, int>> efine, efr, ered;
+  std::vector<std::pair<int, int>> efine, efr, ered, ehalf, ehres;
+  // 3D grids smooth the fine level in the colour-split order, addressed by
+  // 32-bit buffer offsets: every colour half must stay below 2^31 bytes (in
+  // FP64), else the grids keep the LDS z-march sweeps
+  P->split = P->dim == 3;
+  for (int c = 0; c < n; ++c)
+    if (split_half(cases[c].lv[0].d) * (long long)sizeof(double) >= (1LL << 31)) P->split = false;
   std::vector<std::pair<int, int>> ecs[EBIT_MAX_LEVELS], ecr[EBIT_MAX_LEVELS];
   for (int sys = 0; sys < 2; ++sys)
     for (int c = 0; c < n; ++c) {
@@ -3278,7 +3672,9 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       C.b = pc.b;
       C.x = nullptr;
       C.r = pc.B.r;
-      C.rv = rvb<T>(pc.B);
+      C.rv = rvb<T>(pc.B, P->split ? 3 : 2);
+      C.split = P->split ? 1 : 0;
+      C.fs = pc.B.fsplit;
       C.z[0] = zb<T>(pc.B, 0);
       C.z[1] = zb<T>(pc.B, 1);
       C.p[0] = pc.B.p[0];
@@ -3347,6 +3743,9 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
       if (sys == 0) {
         const int fgz = (fd.n[2] + C.fzc - 1) / C.fzc;
         efine.push_back({c, C.fgx * C.fgy * fgz});
+        ehalf.push_back({c, P->split ? split_blocks(split_tiles((fd.n[0] + 1) / 2, fd.n[1], fd.n[2])) : 0});
+        const Dims& d1 = pc.lv[1].d;
+        ehres.push_back({c, P->split ? split_blocks(split_tiles(d1.n[0], d1.n[1], d1.n[2]), SP_TPB_R) : 0});
         efr.push_back({c, (int)nblk(pc.lv[1].d.N)});
         ered.push_back({c, C.nred});
         for (int l = 1; l < lt[c]; ++l) {
@@ -3360,6 +3759,8 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
   P->fine = make_list(efine, host, d_wl);
   P->frestrict = make_list(efr, host, d_wl);
   P->red = make_list(ered, host, d_wl);
+  P->half = make_list(ehalf, host, d_wl);
+  P->hrestrict = make_list(ehres, host, d_wl);
   for (int l = 1; l < P->Lmax; ++l) {
     P->coarse[l] = make_list(ecs[l], host, d_wl);
     P->crestrict[l] = make_list(ecr[l], host, d_wl);
