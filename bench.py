@@ -43,7 +43,8 @@ def log(*a):
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_CLASSES = ["fine_smooth", "fine_restrict", "coarse", "outer_apply", "outer_update", "tail"]
-# the HIP kernels of each class (names as rocprofv3 reports them)
+# the HIP kernels of each class (names as rocprofv3 reports them): 2D grids,
+# and 3D grids (colour-split fine level, streaming p-update and A p)
 KERNEL_NAMES = {
     "fine_smooth": "kb_rb_fine",
     "fine_restrict": "kb_fine_restrict",
@@ -52,6 +53,8 @@ KERNEL_NAMES = {
     "outer_apply": "kb_p_update_apply",
     "outer_update": "kb_update_xr",
 }
+KERNEL_NAMES_3D = dict(KERNEL_NAMES, fine_smooth="kb_half3", fine_restrict="kb_fine_restrict_split",
+                       outer_apply="kb_p_update3 + kb_apply_q3")
 
 
 def algorithmic_bytes_per_cell(kclass, precision, dim):
@@ -67,7 +70,7 @@ def algorithmic_bytes_per_cell(kclass, precision, dim):
     if kclass == "fine_restrict":    # read x (all cells), r and flags (colour-0 cells); write coarse b, clear coarse x
         return sx + (sx + 1) / 2 + 2 * sx / agg
     if kclass == "outer_apply":      # read z, p_old, flags; write p_new and q (FP64)
-        return sx + 8 + 1 + 8 + 8
+        return sx + 8 + 1 + 8 + 8 if dim == 2 else sx + 8 + 8 + 8 + 1 + 8  # 3D: p_new written, then read back
     if kclass == "outer_update":     # read x, p, r, q; write x, r (FP64)
         return 48.0
     return None
@@ -429,11 +432,12 @@ def roofline(case, precision, steps, tune=True):
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         t = json.load(open(tfile))
-        key = f"{case.name}:{precision}:{KERNEL_NAMES[dom]}"
+        key = f"{case.name}:{precision}:{(KERNEL_NAMES_3D if case.dim == 3 else KERNEL_NAMES)[dom]}"
         ent = t.get("kernels", {}).get(key)
         if ent and t.get("source_digest") == kernel_source_digest():
             traffic = ent["hbm_bytes_per_launch"]
-    ro = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS,
+    names = KERNEL_NAMES_3D if case.dim == 3 else KERNEL_NAMES
+    ro = {"bound": "hbm", "kernel": names[dom], "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS,
           "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
           "traffic_source": ("stored profile value: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel on this "
                              "workload (profiles/traffic.json), scaled by a plain copy of known size; reported only "

@@ -2347,79 +2347,107 @@ __global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __res
   // tile coordinates of the first tile, then stepped (the scalar unit is
   // shared by the CU's waves: no division per tile)
   int bx = t0 % gx, by = (t0 / gx) % gy, k = t0 / (gx * gy);
-  for (int t = t0; t < t1; ++t) {
-    if (t > t0 && ++bx == gx) {
-      bx = 0;
-      if (++by == gy) {
-        by = 0;
-        ++k;
+  // tiles in batches of U: every load of a batch is issued before its first
+  // store (the stores could alias the loads, so the compiler would otherwise
+  // wait per tile)
+  constexpr int U = 1;
+  for (int tb = t0; tb < t1; tb += U) {
+    int sbv[U], iv[U], jv[U], kv[U];
+    bool okv[U];
+    uint8_t fv[U];
+    T rcv[U], wv6[U][6];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (tb + u > t0 && ++bx == gx) {
+        bx = 0;
+        if (++by == gy) {
+          by = 0;
+          ++k;
+        }
+      }
+      const int j = by * SP_TY + wv;
+      const int par = (color + j + k) & 1;
+      const int ih = bx * SP_TX + lane;
+      const int i = 2 * ih + par;
+      const bool ok = tb + u < t1 && j < n1 && ih < hw && i < n0;
+      // a lane with no cell reads slot 0 (in range) and stores nothing
+      const int s = ok ? hw * (j + n1 * k) + ih : 0;
+      const int sb = s * TS;
+      okv[u] = ok;
+      sbv[u] = sb;
+      iv[u] = i;
+      jv[u] = j;
+      kv[u] = k;
+      fv[u] = __builtin_amdgcn_raw_buffer_load_b8(bfl, s, 0, 0);
+      rcv[u] = buf_load<T>(brv, sb);
+      if (!first) {
+        // offsets of the six neighbours (slots); a missing one loads the
+        // cell's own slot index and reads as 0 (below)
+        const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
+        const int dx0 = !ok ? 0 : xm ? (p0 ? hw - 1 : 0) : par - 1;
+        const int dx1 = !ok ? 0 : xp ? (p0 ? -ih : 0) : par;
+        const int dy0 = !ok ? 0 : ym ? (p1 ? hw * (n1 - 1) : 0) : -hw;
+        const int dy1 = !ok ? 0 : yp ? (p1 ? -hw * (n1 - 1) : 0) : hw;
+        const int dz0 = !ok ? 0 : zm ? (p2 ? plane * (n2 - 1) : 0) : -plane;
+        const int dz1 = !ok ? 0 : zp ? (p2 ? -plane * (n2 - 1) : 0) : plane;
+        wv6[u][0] = buf_load<T>(bxn, sb + dx0 * TS);
+        wv6[u][1] = buf_load<T>(bxn, sb + dx1 * TS);
+        wv6[u][2] = buf_load<T>(bxn, sb + dy0 * TS);
+        wv6[u][3] = buf_load<T>(bxn, sb + dy1 * TS);
+        wv6[u][4] = buf_load<T>(bxn, sb + dz0 * TS);
+        wv6[u][5] = buf_load<T>(bxn, sb + dz1 * TS);
       }
     }
-    const int j = by * SP_TY + wv;
-    if (j >= n1) continue;  // the whole wave
-    const int par = (color + j + k) & 1;
-    const int ih = bx * SP_TX + lane;
-    const int i = 2 * ih + par;
-    const bool ok = ih < hw && i < n0;
-    const int s = hw * (j + n1 * k) + ih;
-    const int sb = s * TS;
-    const uint8_t f = __builtin_amdgcn_raw_buffer_load_b8(bfl, s, 0, 0);
-    const T rc = buf_load<T>(brv, sb);
-    const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
-    T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-    if (!first) {
-      // offsets of the six neighbours (slots) and whether each exists
-      const int dx0 = xm ? (p0 ? hw - 1 : 0) : par - 1;
-      const int dx1 = xp ? (p0 ? -ih : 0) : par;
-      const int dy0 = ym ? (p1 ? hw * (n1 - 1) : 0) : -hw;
-      const int dy1 = yp ? (p1 ? -hw * (n1 - 1) : 0) : hw;
-      const int dz0 = zm ? (p2 ? plane * (n2 - 1) : 0) : -plane;
-      const int dz1 = zp ? (p2 ? -plane * (n2 - 1) : 0) : plane;
-      T w[6];
-      w[0] = buf_load<T>(bxn, sb + dx0 * TS);
-      w[1] = buf_load<T>(bxn, sb + dx1 * TS);
-      w[2] = buf_load<T>(bxn, sb + dy0 * TS);
-      w[3] = buf_load<T>(bxn, sb + dy1 * TS);
-      w[4] = buf_load<T>(bxn, sb + dz0 * TS);
-      w[5] = buf_load<T>(bxn, sb + dz1 * TS);
-      if (xc) {
-        // parent cells of the neighbours on level 1 (the wrapped index on a
-        // periodic axis; any in-range cell beyond a wall)
-        const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
-        const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
-        const int km = zm ? n2 - 1 : k - 1, kp = zp ? 0 : k + 1;
-        const int pj = (j >> 1) * cn0, pk = (k >> 1) * cn0 * cn1;
-        const int pi = min(i, n0 - 1) >> 1;
-        const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
-                             pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
-                             pi + pj + (kp >> 1) * cn0 * cn1};
-        T e6[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) e6[e] = xc[ok ? par6[e] : 0];
+    for (int u = 0; u < U; ++u) {
+      if (!okv[u]) continue;
+      const int i = iv[u], j = jv[u], k2 = kv[u];
+      const uint8_t f = fv[u];
+      const T rc = rcv[u];
+      const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k2 == 0, zp = k2 == n2 - 1;
+      T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+      if (!first) {
+        T w[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) w[e] += e6[e];
+        for (int e = 0; e < 6; ++e) w[e] = wv6[u][e];
+        if (xc) {
+          // parent cells of the neighbours on level 1 (the wrapped index on
+          // a periodic axis; any in-range cell beyond a wall)
+          const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
+          const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
+          const int km = zm ? n2 - 1 : k2 - 1, kp = zp ? 0 : k2 + 1;
+          const int pj = (j >> 1) * cn0, pk = (k2 >> 1) * cn0 * cn1;
+          const int pi = i >> 1;
+          const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
+                               pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
+                               pi + pj + (kp >> 1) * cn0 * cn1};
+          T e6[6];
+#pragma unroll
+          for (int e = 0; e < 6; ++e) e6[e] = xc[par6[e]];
+#pragma unroll
+          for (int e = 0; e < 6; ++e) w[e] += e6[e];
+        }
+        const bool h[6] = {!xm || p0, !xp || p0, !ym || p1, !yp || p1, !zm || p2, !zp || p2};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = h[e] ? w[e] : (T)0;
       }
-      const bool h[6] = {!xm || p0, !xp || p0, !ym || p1, !yp || p1, !zm || p2, !zp || p2};
-#pragma unroll
-      for (int e = 0; e < 6; ++e) v[e] = h[e] ? w[e] : (T)0;
+      const bool wall = (!p0 && (xm || xp)) || (!p1 && (ym || yp)) || (!p2 && (zm || zp));
+      T x;
+      if (!(f & F_CUT) && !wall) {
+        const bool liq = (f & F_LIQ) != 0;
+        T xs = (v[0] + v[1]) + (v[2] + v[3]);
+        xs += v[4] + v[5];
+        x = (rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0);
+      } else {
+        T diag, off[6], mass, rb = 0;
+        fine_row<T>(op, i, j, k2, f, diag, off, mass, rb);
+        T sum = rc - off[0] * v[0] - off[1] * v[1];
+        sum -= off[2] * v[2] + off[3] * v[3];
+        sum -= off[4] * v[4] + off[5] * v[5];
+        x = sum / diag;
+      }
+      buf_store(x, bxo, sbv[u]);
     }
-    if (!ok) continue;
-    const bool wall = (!p0 && (xm || xp)) || (!p1 && (ym || yp)) || (!p2 && (zm || zp));
-    T x;
-    if (!(f & F_CUT) && !wall) {
-      const bool liq = (f & F_LIQ) != 0;
-      T xs = (v[0] + v[1]) + (v[2] + v[3]);
-      xs += v[4] + v[5];
-      x = (rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0);
-    } else {
-      T diag, off[6], mass, rb = 0;
-      fine_row<T>(op, i, j, k, f, diag, off, mass, rb);
-      T sum = rc - off[0] * v[0] - off[1] * v[1];
-      sum -= off[2] * v[2] + off[3] * v[3];
-      sum -= off[4] * v[4] + off[5] * v[5];
-      x = sum / diag;
-    }
-    buf_store(x, bxo, sb);
   }
 }
 
@@ -2848,6 +2876,200 @@ __global__ __launch_bounds__(RB_THREADS) void kb_apply3d(const SolveCase<T>* __r
       }
     }
     __syncthreads();
+  }
+  write_partials<1>(v, C.partial + 2 * nb, lb, nb);
+}
+
+// 3D grids whose fine iterate is in the colour-split order: the p-update and
+// A p as two streaming passes (they replace kb_apply3d there).
+//
+// kb_p_update3: gamma = z.r and beta from the dots' partials (every block
+// reduces them in the same fixed order; block 0 records gamma), then
+// p_new = z + beta p_old over the natural order.  A wave takes 64
+// consecutive cells of a row; z is read through the colour-split order.
+#define PU_TPB 8
+template <typename T>
+__global__ __launch_bounds__(EBIT_BLOCK) void kb_p_update3(const SolveCase<T>* __restrict__ cs,
+                                                           const CaseCtl* __restrict__ ctl, WorkList wl, int dc) {
+  __shared__ double sbeta;
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  const CaseCtl cc = ctl[c];
+  if (!cc.active) return;
+  const SolveCase<T>& C = cs[c];
+  const bool first = dc || cc.fresh;
+  {
+    double g[3];
+    reduce_partials(C.partial, C.ndot > 0 ? C.ndot : C.nred, 2, false, g);
+    if (threadIdx.x == 0) {
+      Scal* sc = C.sc;
+      const int so = cc.pi, sn = cc.pi ^ 1;
+      const double beta = first ? 0.0 : -sc->sa[so] * g[1] / sc->sg[so];
+      sbeta = beta;
+      if (lb == 0) {
+        sc->sg[sn] = g[0];
+        sc->gamma = g[0];
+        sc->beta = beta;
+        sc->zq = g[1];
+      }
+    }
+    __syncthreads();
+  }
+  const double beta = sbeta;
+  const Dims& d = C.op.d;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const int hw = (n0 + 1) >> 1;
+  const long long H = split_half(d);
+  constexpr int TS = (int)sizeof(T);
+  const BufRsrc bz0 = buf_rsrc(C.z[0], H * TS);
+  const BufRsrc bz1 = buf_rsrc(C.z[0] + H, H * TS);
+  const BufRsrc bpo = buf_rsrc(C.p[cc.pi], d.N * 8);
+  const BufRsrc bpn = buf_rsrc(C.p[cc.pi ^ 1], d.N * 8);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int gx = (n0 + SP_TX - 1) / SP_TX, gy = (n1 + SP_TY - 1) / SP_TY;
+  const int tiles = gx * gy * n2;
+  const int t0 = xcd_tile(lb, nb) * PU_TPB, t1 = min(t0 + PU_TPB, tiles);
+  int bx = t0 % gx, by = (t0 / gx) % gy, k = t0 / (gx * gy);
+  // every tile's loads are issued before the first store (the stores could
+  // alias the loads, so the compiler would otherwise wait per tile)
+  int cnv[PU_TPB];
+  bool okv[PU_TPB];
+  T zv[PU_TPB];
+  double pov[PU_TPB];
+#pragma unroll
+  for (int u = 0; u < PU_TPB; ++u) {
+    if (u > 0 && ++bx == gx) {
+      bx = 0;
+      if (++by == gy) {
+        by = 0;
+        ++k;
+      }
+    }
+    const int j = by * SP_TY + wv;
+    const int i = bx * SP_TX + lane;
+    okv[u] = t0 + u < t1 && j < n1 && i < n0;
+    const int cn = okv[u] ? i + n0 * (j + n1 * k) : 0;
+    const int zs = okv[u] ? (i >> 1) + hw * (j + n1 * k) : 0;
+    cnv[u] = cn;
+    zv[u] = ((i + j + k) & 1) ? buf_load<T>(bz1, zs * TS) : buf_load<T>(bz0, zs * TS);
+    pov[u] = first ? 0.0 : buf_load<double>(bpo, cn * 8);
+  }
+#pragma unroll
+  for (int u = 0; u < PU_TPB; ++u)
+    if (okv[u]) buf_store(first ? (double)zv[u] : (double)zv[u] + beta * pov[u], bpn, cnv[u] * 8);
+}
+
+// kb_apply_q3: q = A p_new with p_new read at the cell and its six
+// neighbours (cache hits but the cell's own), and the partial sums of p.q
+// (row 2, one per reduction work-group: this kernel runs on the reduction
+// work list).  Rows as in kb_apply3d: a cell with no cut link and no wall
+// side takes its phase's constant row, the others fine_row; the same bits.
+template <typename T, int SYS>
+__global__ __launch_bounds__(EBIT_BLOCK) void kb_apply_q3(const SolveCase<T>* __restrict__ cs,
+                                                          const CaseCtl* __restrict__ ctl, WorkList wl) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  const CaseCtl cc = ctl[c];
+  if (!cc.active) return;
+  const SolveCase<T>& C = cs[c];
+  const FineOp op = C.op;
+  const Dims& d = op.d;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const int pl = n0 * n1;
+  const BufRsrc bp = buf_rsrc(C.p[cc.pi ^ 1], d.N * 8);
+  const BufRsrc bq = buf_rsrc(C.q, d.N * 8);
+  const BufRsrc bf = buf_rsrc(op.flags, d.N);
+  const bool p0 = d.per[0], p1 = d.per[1], p2 = d.per[2];
+  // the phases' constant rows (kept out of the per-cell code)
+  __shared__ double srow[4];
+  if (threadIdx.x == 0) {
+    srow[0] = op.mass[0];
+    srow[1] = op.mass[1];
+    srow[2] = -op.coef[0] * op.ih2;
+    srow[3] = -op.coef[1] * op.ih2;
+  }
+  __syncthreads();
+  const double m0 = srow[0], m1 = srow[1], cw0 = srow[2], cw1 = srow[3];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int gx = (n0 + SP_TX - 1) / SP_TX, gy = (n1 + SP_TY - 1) / SP_TY;
+  const int tiles = gx * gy * n2;
+  const int tpb = (tiles + nb - 1) / nb;
+  const int t0 = xcd_tile(lb, nb) * tpb, t1 = min(t0 + tpb, tiles);
+  double v[1] = {0};
+  constexpr int U = 2;  // tiles whose loads are issued before any store
+  int bx = t0 % gx, by = (t0 / gx) % gy, k = t0 / (gx * gy);
+  for (int tb = t0; tb < t1; tb += U) {
+    int cnv[U], iv[U], jv[U], kv[U];
+    bool okv[U];
+    uint8_t fv[U];
+    double pcv[U], pnv[U][6];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (tb + u > t0 && ++bx == gx) {
+        bx = 0;
+        if (++by == gy) {
+          by = 0;
+          ++k;
+        }
+      }
+      const int j = by * SP_TY + wv;
+      const int i = bx * SP_TX + lane;
+      const bool ok = tb + u < t1 && j < n1 && i < n0;
+      const int cn = ok ? i + n0 * (j + n1 * k) : 0;
+      okv[u] = ok;
+      cnv[u] = cn;
+      iv[u] = i;
+      jv[u] = j;
+      kv[u] = k;
+      const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
+      // neighbours in the order of fine_nbrs: -x, +x, -y, +y, -z, +z (the
+      // wrapped cell on a periodic axis; the cell itself beyond a wall, where
+      // the row has no coupling)
+      int q[6];
+      q[0] = xm ? (p0 ? cn + n0 - 1 : cn) : cn - 1;
+      q[1] = xp ? (p0 ? cn - n0 + 1 : cn) : cn + 1;
+      q[2] = ym ? (p1 ? cn + pl - n0 : cn) : cn - n0;
+      q[3] = yp ? (p1 ? cn - pl + n0 : cn) : cn + n0;
+      q[4] = zm ? (p2 ? cn + pl * (n2 - 1) : cn) : cn - pl;
+      q[5] = zp ? (p2 ? cn - pl * (n2 - 1) : cn) : cn + pl;
+      if (!ok) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) q[e] = 0;
+      }
+      fv[u] = __builtin_amdgcn_raw_buffer_load_b8(bf, cn, 0, 0);
+      pcv[u] = buf_load<double>(bp, cn * 8);
+#pragma unroll
+      for (int e = 0; e < 6; ++e) pnv[u][e] = buf_load<double>(bp, q[e] * 8);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!okv[u]) continue;
+      const int i = iv[u], j = jv[u], k2 = kv[u];
+      const uint8_t f = fv[u];
+      const double pc = pcv[u];
+      const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k2 == 0, zp = k2 == n2 - 1;
+      double sq;
+      if (!(f & F_CUT) && (p0 || (!xm && !xp)) && (p1 || (!ym && !yp)) && (p2 || (!zm && !zp))) {
+        const bool liq = (f & F_LIQ) != 0;
+        const double cw = liq ? cw1 : cw0;
+        sq = (liq ? m1 : m0) * pc;
+        if (cw != 0.0) {
+#pragma unroll
+          for (int qq = 0; qq < 6; ++qq) sq -= cw * (pc - pnv[u][qq]);
+        }
+      } else {
+        double diag, off[6], mass, rb = 0, mx;
+        fine_row<double, SYS>(op, i, j, k2, f, diag, off, mass, rb, &mx);
+        sq = mx * pc;
+#pragma unroll
+        for (int qq = 0; qq < 6; ++qq)
+          if (off[qq] != 0.0) sq -= off[qq] * (pc - pnv[u][qq]);
+      }
+      buf_store(sq, bq, cnv[u] * 8);
+      v[0] += pc * sq;
+    }
   }
   write_partials<1>(v, C.partial + 2 * nb, lb, nb);
 }
@@ -3292,7 +3514,7 @@ struct PCarver {
 };
 
 constexpr int PLAN_MAX_K = 16;                     // outer iterations per graph block
-constexpr int PLAN_LISTS = 5 + 2 * EBIT_MAX_LEVELS;  // work lists of a plan
+constexpr int PLAN_LISTS = 6 + 2 * EBIT_MAX_LEVELS;  // work lists of a plan
 
 struct HostList {
   WorkList w;
@@ -3316,6 +3538,7 @@ struct PlanT {
   HostList fine, frestrict, red;
   HostList half;       // 3D: the colour-split half-sweeps (tiles of one colour's slots)
   HostList hrestrict;  // 3D: their restriction (tiles of level 1)
+  HostList pupd;       // 3D split: the p-update (tiles of the natural order)
   HostList coarse[EBIT_MAX_LEVELS], crestrict[EBIT_MAX_LEVELS];
   size_t tail_bytes = 0;
   hipStream_t ist = nullptr;
@@ -3539,6 +3762,13 @@ void launch_p_update(const PlanT<T>& P, const SolveCase<T>* cs, int sys, int dc,
       hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_HEAT, long long>), g, b, 0, st, cs, ctl, P.red.w, dc);
     else
       hipLaunchKernelGGL((kb_p_update_apply<T, EBIT_SYS_PRESSURE, long long>), g, b, 0, st, cs, ctl, P.red.w, dc);
+  } else if (P.split) {
+    // p-update, then q = A p with the p.q partials on the reduction work list
+    hipLaunchKernelGGL(kb_p_update3<T>, dim3(P.pupd.blocks), b, 0, st, cs, ctl, P.pupd.w, dc);
+    if (sys == EBIT_SYS_HEAT)
+      hipLaunchKernelGGL((kb_apply_q3<T, EBIT_SYS_HEAT>), g, b, 0, st, cs, ctl, P.red.w);
+    else
+      hipLaunchKernelGGL((kb_apply_q3<T, EBIT_SYS_PRESSURE>), g, b, 0, st, cs, ctl, P.red.w);
   } else if (P.dim == 3) {
     if (sys == EBIT_SYS_HEAT)
       hipLaunchKernelGGL((kb_apply3d<T, EBIT_SYS_HEAT>), g, b, 0, st, cs, ctl, P.red.w, dc);
@@ -3655,13 +3885,14 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
     if (lt[c] > P->Lmax) P->Lmax = lt[c];
   }
   P->tail_bytes = tail_elems * sizeof(T);
-  std::vector<std::pair<int, int>> efine, efr, ered, ehalf, ehres;
-  // 3D grids smooth the fine level in the colour-split order, addressed by
-  // 32-bit buffer offsets: every colour half must stay below 2^31 bytes (in
-  // FP64), else the grids keep the LDS z-march sweeps
+  std::vector<std::pair<int, int>> efine, efr, ered, ehalf, ehres, epu;
+  // 3D grids smooth the fine level in the colour-split order and run the
+  // p-update and A p as streaming passes, addressed by 32-bit buffer
+  // offsets: every FP64 fine array must stay below 2^31 bytes (fewer than
+  // 2^28 cells), else the grids keep the LDS z-march kernels
   P->split = P->dim == 3;
   for (int c = 0; c < n; ++c)
-    if (split_half(cases[c].lv[0].d) * (long long)sizeof(double) >= (1LL << 31)) P->split = false;
+    if (cases[c].lv[0].d.N * (long long)sizeof(double) >= (1LL << 31)) P->split = false;
   std::vector<std::pair<int, int>> ecs[EBIT_MAX_LEVELS], ecr[EBIT_MAX_LEVELS];
   for (int sys = 0; sys < 2; ++sys)
     for (int c = 0; c < n; ++c) {
@@ -3746,6 +3977,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
         ehalf.push_back({c, P->split ? split_blocks(split_tiles((fd.n[0] + 1) / 2, fd.n[1], fd.n[2])) : 0});
         const Dims& d1 = pc.lv[1].d;
         ehres.push_back({c, P->split ? split_blocks(split_tiles(d1.n[0], d1.n[1], d1.n[2]), SP_TPB_R) : 0});
+        epu.push_back({c, P->split ? split_blocks(split_tiles(fd.n[0], fd.n[1], fd.n[2]), PU_TPB) : 0});
         efr.push_back({c, (int)nblk(pc.lv[1].d.N)});
         ered.push_back({c, C.nred});
         for (int l = 1; l < lt[c]; ++l) {
@@ -3761,6 +3993,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
   P->red = make_list(ered, host, d_wl);
   P->half = make_list(ehalf, host, d_wl);
   P->hrestrict = make_list(ehres, host, d_wl);
+  P->pupd = make_list(epu, host, d_wl);
   for (int l = 1; l < P->Lmax; ++l) {
     P->coarse[l] = make_list(ecs[l], host, d_wl);
     P->crestrict[l] = make_list(ecr[l], host, d_wl);
