@@ -330,7 +330,10 @@ def advect_pass(case, markers, vcol, ug, dt, a):
     # aligned markers: along their own line (R25)
     al = old[a]
     nlines = al.shape[0] if a == 0 else al.shape[1]
+    per_b = _periodic(case)[b]
     for line in range(nlines):
+        if per_b and line == n[b]:
+            continue                         # the seam line: a copy of line 0, below
         land = {}
         for e_idx in range(n[a]):
             r, c = (line, e_idx) if a == 0 else (e_idx, line)
@@ -351,6 +354,14 @@ def advect_pass(case, markers, vcol, ug, dt, a):
             if len(ss) == 1:                 # two markers on one edge cancel
                 r, c = (line, k) if a == 0 else (k, line)
                 new[a][r, c] = ss[0]
+    if per_b:
+        # the seam line across b is line 0 stored twice
+        if a == 0:
+            new[a][n[b], :] = new[a][0, :]
+            vc[n[b], :] = vc[0, :]
+        else:
+            new[a][:, n[b]] = new[a][:, 0]
+            vc[:, n[b]] = vc[:, 0]
     # unaligned markers (R21): an unaligned edge holds a marker when its end
     # vertices (on aligned lines) now differ in colour; the marker sits at
     # the mean of the crossings of the moved interface with the edge's line,
@@ -415,17 +426,18 @@ def cell_colours(case, markers, vcol):
                 continue
             pts = []
             for (e, r, c) in segs[(j, i)]:
-                s = np.asarray(markers[e])[0][r, c]
-                pts.append(np.array([(c + s) * h, r * h]) if e == 0 else np.array([c * h, (r + s) * h]))
-            p1, p2 = pts
-            d = p2 - p1
-            nrm = np.array([-d[1], d[0]])
+                s = float(np.asarray(markers[e])[0][r, c])
+                pts.append(((c + s) * h, r * h) if e == 0 else (c * h, (r + s) * h))
+            (x1, y1), (x2, y2) = pts
+            # the segment's normal, turned towards the liquid corners
+            nxs, nys = -(y2 - y1), x2 - x1
             side = 0.0
             for (dx, dy), col in zip(((0, 0), (1, 0), (0, 1), (1, 1)), corners):
-                side += (2 * col - 1) * np.dot(nrm, np.array([(i + dx) * h, (j + dy) * h]) - p1)
+                side += (2 * col - 1) * (nxs * ((i + dx) * h - x1) + nys * ((j + dy) * h - y1))
             if side < 0:
-                nrm = -nrm
-            cc[j, i] = 1 if np.dot(nrm, np.array([(i + 0.5) * h, (j + 0.5) * h]) - p1) >= 0 else 0
+                nxs, nys = -nxs, -nys
+            centre = nxs * ((i + 0.5) * h - x1) + nys * ((j + 0.5) * h - y1)
+            cc[j, i] = 1 if centre >= 0 else 0
     return cc[None]
 
 

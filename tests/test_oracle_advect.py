@@ -154,6 +154,10 @@ def test_periodic_stripe_translates_exactly(u):
     shift = u[0] * dt - u[1] * dt                   # x - y of a moved point
     moved = stripe_case(n, c1 + shift, c2 + shift)
     _check_against(case, mk, vc, cc, moved)
+    # each seam line is one grid line stored twice: the copies agree bit for bit
+    assert np.array_equal(mk[0][0][n, :], mk[0][0][0, :], equal_nan=True)
+    assert np.array_equal(mk[1][0][:, n], mk[1][0][:, 0], equal_nan=True)
+    assert np.array_equal(vc[0][n, :], vc[0][0, :]) and np.array_equal(vc[0][:, n], vc[0][:, 0])
 
 
 def _grow(case, V, steps, dt):
