@@ -17,6 +17,9 @@
  *                      ghost_velocity), the variable-density Poisson problem
  *                      (Eqs. Poisson_equation, poisson_ghost_fluid) solved by
  *                      geometric multigrid, and the face-velocity update
+ *   ebit_interface_velocity, ebit_advect_markers
+ *                      the interfacial velocity (Eq. jump_interfacial_vel)
+ *                      and the EBIT marker motion of one time step (Sec. 2.1)
  *
  * Conventions (all calls):
  *   - Every array argument is a DEVICE pointer owned by the caller, contiguous,
@@ -233,6 +236,58 @@ ebit_status ebit_extend(ebit_ctx* ctx, double* q, int mode, int iters);
  * ebit_project. */
 ebit_status ebit_project_one_fluid(ebit_ctx* ctx, double* const u[3], const double* mdot_cell, double* p,
                                    int use_guess, ebit_stats* stats);
+
+/* Sec. 2.3, Eq. jump_interfacial_vel: the interfacial velocity at every cell
+ * centre, with the geometry of the last ebit_build_coeffs (2D and 3D).  A
+ * cell takes its own phase's velocity (the mean of its two faces per axis
+ * in u_l for a liquid cell, in u_v for a vapour cell) plus mdot / rho_k
+ * times the band normal n (the normalised sum of the facet normals, vapour
+ * -> liquid, of the interface cells in its 3^d block; 0 off that band):
+ *   u_gamma = u_k + (mdot / rho_k) n,
+ * the paper's relation with its normal pointing into the vapour.  u_l[a],
+ * u_v[a] (a < dim): axis-a face arrays; mdot_cell: cells, the mass flux
+ * carried into the band (ebit_mass_flux, then ebit_extend with
+ * EBIT_EXT_IFACE_TO_BAND); u_gamma[a]: outputs, cells, component a.  All
+ * device, caller-owned.  Asynchronous on the context stream.  EBIT_EINVAL
+ * for a NULL pointer among the first dim entries; EBIT_ESTATE before
+ * ebit_build_coeffs. */
+ebit_status ebit_interface_velocity(ebit_ctx* ctx, const double* const u_l[3], const double* const u_v[3],
+                                    const double* mdot_cell, double* const u_gamma[3]);
+
+/* Sec. 2.1, Eqs. marker_motion and discrete_marker_motion: one explicit
+ * Euler step of the EBIT markers of a 2D grid, split into an x pass and a y
+ * pass.  In the pass along axis a every marker moves along a by
+ * u_gamma,a dt, bilinear in the four nearest cell centres (the stencil kept
+ * inside walls, wrapped on periodic axes; a marker on a wall across a stays
+ * on it; the y pass reads the same cell field at the moved positions).
+ *   - A marker on a grid line along a (aligned) lands on the edge of its
+ *     line that holds its new coordinate (clamped to a wall, wrapped on a
+ *     periodic axis); two landings on one edge cancel; the vertices between
+ *     the old and the new edge change colour.
+ *   - An edge across a (unaligned) then holds a marker exactly when its end
+ *     vertices differ in colour.  It sits where the moved interface meets
+ *     the edge's line: on each moved segment (a cell's two markers) that
+ *     reaches the line, the mean of the points met on the circles through
+ *     the segment and the far end of each neighbouring segment (the chord
+ *     when the interface ends there); the mean over such segments; the
+ *     edge's midpoint if none reaches it.
+ *   - Then each cell takes its corners' colour, or for a two-marker cell the
+ *     side of its segment's line that the corners mark as liquid (a centre
+ *     on the line is liquid).
+ * u_gamma[0..1]: cells (ebit_interface_velocity).  marker[0..1]: the x- and
+ * y-edge arrays, in/out.  vertex_colour: in/out.  cell_colour: output.  All
+ * device, caller-owned; the periodic seams of the input must agree (as
+ * ebit_build_coeffs requires).  The call does not need ebit_build_coeffs;
+ * it uses the context's scratch, so it must not overlap another call on the
+ * context, and it synchronises the context stream to report errors.
+ * Errors: EBIT_EINVAL for a 3D grid, fewer than 4 cells on an axis, a NULL
+ * pointer, dt negative or not finite, or a marker that would move by more
+ * than one cell (h) in a pass or by a non-finite amount; EBIT_EGEOM when a
+ * cell holds other than 0 or 2 markers (a saddle) before a pass or after
+ * the step, or a marker lies outside [0, 1].  After an error the marker and
+ * colour arrays are unspecified. */
+ebit_status ebit_advect_markers(ebit_ctx* ctx, const double* const u_gamma[3], double* const marker[3],
+                                uint8_t* vertex_colour, uint8_t* cell_colour, double dt);
 
 /* ---- inspection entry points (same conventions) --------------------------- */
 

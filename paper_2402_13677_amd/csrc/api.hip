@@ -35,6 +35,8 @@ struct ebit_ctx {
   char* plan_mem;
   size_t plan_bytes;
   char* build_tabs;    // device tables of the hierarchy build
+  double* adv;         // 2D: marker-motion scratch (4 edge arrays)
+  int* adv_err;        // 2D: marker-motion error bits
   int build_ls;        // first level built by one work-group
   hipError_t herr;
   char msg[512];
@@ -294,11 +296,18 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
   const size_t plan_bytes = ebit_plan_device_bytes(1, o ? o->precision : EBIT_FP64);
   char* plan_mem = cv.take<char>(plan_bytes);
   char* build_tabs = cv.take<char>(ebit_build_table_bytes());
+  // 2D marker motion: moved and fixed coordinates of every edge of both
+  // families, and the error word
+  const long long nedges = fd.dim == 2 ? (long long)fd.n[0] * (fd.n[1] + 1) + (long long)(fd.n[0] + 1) * fd.n[1] : 0;
+  double* adv = cv.take<double>(2 * nedges);
+  int* adv_err = cv.take<int>(fd.dim == 2 ? 4 : 0);
   const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;
   if (ctx) {
     ctx->plan_mem = plan_mem;
     ctx->plan_bytes = plan_bytes;
     ctx->build_tabs = build_tabs;
+    ctx->adv = adv;
+    ctx->adv_err = adv_err;
     ctx->fd = fd;
     ctx->flags = flags;
     for (int a = 0; a < 3; ++a) ctx->th[a] = th[a];
@@ -757,6 +766,46 @@ ebit_status ebit_extend(ebit_ctx* c, double* q, int mode, int iters) {
         ebit_launch_extend(&c->fd, mode, iters, c->flags, c->nF, q, c->bvec, (uint8_t*)c->B.z32,
                            (unsigned long long*)c->B.z64, w, (int*)c->B.partial, c->st),
         "extend");
+  return EBIT_OK;
+}
+
+ebit_status ebit_interface_velocity(ebit_ctx* c, const double* const u_l[3], const double* const u_v[3],
+                                    const double* mdot_cell, double* const u_gamma[3]) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  const int dim = c->fd.dim;
+  if (!u_l || !u_v || !u_gamma || !mdot_cell) return fail(c, EBIT_EINVAL, "NULL argument");
+  for (int a = 0; a < dim; ++a)
+    if (!u_l[a] || !u_v[a] || !u_gamma[a]) return fail(c, EBIT_EINVAL, "NULL field");
+  const double* ul[3] = {u_l[0], u_l[1], dim == 3 ? u_l[2] : nullptr};
+  const double* uv[3] = {u_v[0], u_v[1], dim == 3 ? u_v[2] : nullptr};
+  double* out[3] = {u_gamma[0], u_gamma[1], dim == 3 ? u_gamma[2] : nullptr};
+  HIPCK(c,
+        ebit_launch_iface_velocity(&c->fd, c->flags, c->nF, ul, uv, mdot_cell, c->props.rho_l, c->props.rho_v,
+                                   out, c->st),
+        "interface velocity");
+  return EBIT_OK;
+}
+
+ebit_status ebit_advect_markers(ebit_ctx* c, const double* const u_gamma[3], double* const marker[3],
+                                uint8_t* vertex_colour, uint8_t* cell_colour, double dt) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  if (c->fd.dim != 2) return fail(c, EBIT_EINVAL, "marker motion is two-dimensional");
+  if (c->fd.n[0] < 4 || c->fd.n[1] < 4) return fail(c, EBIT_EINVAL, "marker motion needs 4 cells per axis");
+  if (!u_gamma || !marker || !u_gamma[0] || !u_gamma[1] || !marker[0] || !marker[1] || !vertex_colour ||
+      !cell_colour)
+    return fail(c, EBIT_EINVAL, "NULL argument");
+  if (!(dt >= 0.0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be finite and >= 0");
+  HIPCK(c,
+        ebit_launch_advect(&c->fd, c->grid.h, dt, u_gamma, marker, vertex_colour, cell_colour, c->adv,
+                           c->adv_err, c->st),
+        "advect");
+  int herr = 0;
+  HIPCK(c, hipMemcpyAsync(&herr, c->adv_err, sizeof(int), hipMemcpyDeviceToHost, c->st), "advect status");
+  HIPCK(c, hipStreamSynchronize(c->st), "advect sync");
+  if (herr & 1) return fail(c, EBIT_EINVAL, "a marker moves more than one cell in a pass (or by a non-finite amount)");
+  if (herr & 2) return fail(c, EBIT_EGEOM, "a cell holds other than 0 or 2 markers (a saddle)");
   return EBIT_OK;
 }
 

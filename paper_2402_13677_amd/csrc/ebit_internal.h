@@ -223,6 +223,42 @@ __device__ inline void cell_ijk(const Dims& d, long long c, int& i, int& j, int&
   k = (int)(c / ((long long)d.n[0] * d.n[1]));
 }
 
+// Neighbour of (i, j, k) at offsets (di, dj, dk): false beyond a wall,
+// periodic axes wrap.
+__device__ inline bool nbr_cell(const Dims& d, int i, int j, int k, int di, int dj, int dk, long long& m) {
+  int p[3] = {i + di, j + dj, k + dk};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= d.dim) continue;
+    if (p[a] < 0 || p[a] >= d.n[a]) {
+      if (!d.per[a]) return false;
+      p[a] = p[a] < 0 ? p[a] + d.n[a] : p[a] - d.n[a];
+    }
+  }
+  m = (long long)p[0] + (long long)d.n[0] * ((long long)p[1] + (long long)d.n[1] * p[2]);
+  return true;
+}
+
+// Sum of the facet normals (nF: 3 arrays of N) of the interface cells in
+// the 3^d block of (i, j, k), the x offset slowest, z fastest (the band
+// normal of Eq. extrapolation before normalisation); false if it vanishes.
+__device__ inline bool band_normal_sum(const Dims& d, const uint8_t* flags, const double* nF, int i, int j, int k,
+                                       double s[3]) {
+  const int rz = d.dim == 3 ? 1 : 0;
+  s[0] = s[1] = s[2] = 0.0;
+  for (int di = -1; di <= 1; ++di)
+    for (int dj = -1; dj <= 1; ++dj)
+      for (int dk = -rz; dk <= rz; ++dk) {
+        long long m;
+        if (!nbr_cell(d, i, j, k, di, dj, dk, m)) continue;
+        if (!((flags[m] >> 7) & 1)) continue;
+        s[0] += nF[m];
+        s[1] += nF[d.N + m];
+        if (d.dim == 3) s[2] += nF[2 * d.N + m];
+      }
+  return sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) > 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // reductions (deterministic: fixed grid, fixed order)
 // ---------------------------------------------------------------------------
@@ -329,6 +365,15 @@ hipError_t ebit_launch_extend(const ebit::Dims* d, int mode, int iters, const ui
                               double* q, double* work, uint8_t* bytes, unsigned long long* list,
                               double* const w[3], int* counter, hipStream_t st);
 hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
+// Interfacial velocity at the cell centres (out[a], a < dim).
+hipError_t ebit_launch_iface_velocity(const ebit::Dims* d, const uint8_t* flags, const double* nF,
+                                      const double* const ul[3], const double* const uv[3], const double* mdot,
+                                      double rho_l, double rho_v, double* const out[3], hipStream_t st);
+// 2D marker motion (x pass, y pass, cell colours).  scratch: 2 (E0 + E1)
+// doubles, E0 = nx (ny + 1), E1 = (nx + 1) ny; err: one int, cleared here.
+hipError_t ebit_launch_advect(const ebit::Dims* d, double h, double dt, const double* const ug[3],
+                              double* const mk[3], uint8_t* vcol, uint8_t* ccol, double* scratch, int* err,
+                              hipStream_t st);
 // Hierarchy builds: host tables of the one-work-group part (2 systems,
 // ebit_build_table_bytes() bytes) are filled once and uploaded by the
 // caller; ls is the first level that part builds.

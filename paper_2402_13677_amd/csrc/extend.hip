@@ -51,21 +51,6 @@ __device__ inline bool ext_candidate(int mode, uint8_t fl) {
   return !((fl >> 7) & 1);
 }
 
-// neighbour of (i, j, k) at offsets (di, dj, dk); false beyond a wall
-__device__ inline bool ext_nbr(const Dims& d, int i, int j, int k, int di, int dj, int dk, long long& m) {
-  int p[3] = {i + di, j + dj, k + dk};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (a >= d.dim) continue;
-    if (p[a] < 0 || p[a] >= d.n[a]) {
-      if (!d.per[a]) return false;
-      p[a] = p[a] < 0 ? p[a] + d.n[a] : p[a] - d.n[a];
-    }
-  }
-  m = (long long)p[0] + (long long)d.n[0] * ((long long)p[1] + (long long)d.n[1] * p[2]);
-  return true;
-}
-
 // OR of the per-cell bit over the three cells c - e_AX, c, c + e_AX; the
 // first pass takes the interface bit of the flags (and clears the list
 // counter)
@@ -80,29 +65,10 @@ __global__ void k_ext_dilate(Dims d, int ax, const uint8_t* __restrict__ flags, 
 #pragma unroll
   for (int s = -1; s <= 1; ++s) {
     long long m = c;
-    if (s != 0 && !ext_nbr(d, i, j, k, ax == 0 ? s : 0, ax == 1 ? s : 0, ax == 2 ? s : 0, m)) continue;
+    if (s != 0 && !nbr_cell(d, i, j, k, ax == 0 ? s : 0, ax == 1 ? s : 0, ax == 2 ? s : 0, m)) continue;
     v |= in ? in[m] : (uint8_t)((flags[m] >> 7) & 1);
   }
   out[c] = v;
-}
-
-// Sum of the facet normals of the interface cells in the 3^d block of
-// (i, j, k), the x offset slowest; false if it vanishes
-__device__ inline bool ext_normal(const Dims& d, const uint8_t* flags, const double* nF, int i, int j, int k,
-                                  double s[3]) {
-  const int rz = d.dim == 3 ? 1 : 0;
-  s[0] = s[1] = s[2] = 0.0;
-  for (int di = -1; di <= 1; ++di)
-    for (int dj = -1; dj <= 1; ++dj)
-      for (int dk = -rz; dk <= rz; ++dk) {
-        long long m;
-        if (!ext_nbr(d, i, j, k, di, dj, dk, m)) continue;
-        if (!((flags[m] >> 7) & 1)) continue;
-        s[0] += nF[m];
-        s[1] += nF[d.N + m];
-        if (d.dim == 3) s[2] += nF[2 * d.N + m];
-      }
-  return sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) > 0.0;
 }
 
 struct ExtArgs {
@@ -127,7 +93,7 @@ __global__ void k_ext_mark(ExtArgs g) {
     int i, j, k;
     cell_ijk(d, c, i, j, k);
     double s[3];
-    t = ext_normal(d, g.flags, g.nF, i, j, k, s) ? 1 : 0;
+    t = band_normal_sum(d, g.flags, g.nF, i, j, k, s) ? 1 : 0;
   }
   g.tgt[c] = t;
 }
@@ -144,7 +110,7 @@ __global__ __launch_bounds__(EXT_BLOCK) void k_ext_list(ExtArgs g) {
     int i, j, k;
     cell_ijk(d, c, i, j, k);
     double s[3];
-    ext_normal(d, g.flags, g.nF, i, j, k, s);
+    band_normal_sum(d, g.flags, g.nF, i, j, k, s);
     const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
     const double sg = ((g.flags[c] >> 6) & 1) ? 1.0 : -1.0;
 #pragma unroll
@@ -156,7 +122,7 @@ __global__ __launch_bounds__(EXT_BLOCK) void k_ext_list(ExtArgs g) {
       if (av != 0.0) {
         const int sd = plus ? 1 : -1;
         long long m;
-        if (ext_nbr(d, i, j, k, a == 0 ? sd : 0, a == 1 ? sd : 0, a == 2 ? sd : 0, m)) {
+        if (nbr_cell(d, i, j, k, a == 0 ? sd : 0, a == 1 ? sd : 0, a == 2 ? sd : 0, m)) {
           tg = g.tgt[m] != 0;
           keep = tg || ext_data(g.mode, g.flags[m]);
         }
@@ -205,7 +171,7 @@ __global__ __launch_bounds__(EXT_BLOCK) void k_ext_step(Dims d, const unsigned l
       if (bits & 1) {
         const int s = (bits & 2) ? 1 : -1;
         long long m = c;
-        ext_nbr(d, i, j, k, a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0, m);
+        nbr_cell(d, i, j, k, a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0, m);
         up[a] = (bits & 4) ? src[m] : q[m];
       }
     }

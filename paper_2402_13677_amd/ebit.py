@@ -97,6 +97,8 @@ def load():
         "ebit_batch_autotune": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(Opts), ctypes.POINTER(d)]),
         "ebit_cut_fractions_noalloc": (i, [ctypes.POINTER(Grid), _P3, vp, vp, _P3, vp, vp]),
+        "ebit_interface_velocity": (i, [vp, _P3, _P3, vp, _P3]),
+        "ebit_advect_markers": (i, [vp, _P3, _P3, vp, vp, d]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -112,7 +114,7 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
             "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune",
-            "ebit_cut_fractions_noalloc"]
+            "ebit_cut_fractions_noalloc", "ebit_interface_velocity", "ebit_advect_markers"]
 NOALLOC_MAX_CELLS = 1 << 18
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ, EXT_IFACE_TO_BAND = range(3)
@@ -269,6 +271,22 @@ class Context:
         in place) into the narrow band; mode EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ
         or EXT_IFACE_TO_BAND."""
         self._check(self.lib.ebit_extend(self.h, _ptr(q, torch.float64), int(mode), int(iters)), "ebit_extend")
+
+    def interface_velocity(self, u_l, u_v, mdot, u_gamma):
+        """Eq. jump_interfacial_vel at the cell centres: u_gamma (dim cell
+        arrays, written) from the face fields u_l, u_v and the
+        band-extended mdot."""
+        self._check(self.lib.ebit_interface_velocity(self.h, _p3(u_l), _p3(u_v), _ptr(mdot, torch.float64),
+                                                     _p3(u_gamma)), "ebit_interface_velocity")
+
+    def advect_markers(self, u_gamma, markers, vcol, ccol, dt, check=True):
+        """One step of the EBIT markers (2D, x pass then y pass): markers and
+        vcol in place, ccol written; returns the status code."""
+        st = self.lib.ebit_advect_markers(self.h, _p3(u_gamma), _p3(markers), _ptr(vcol, torch.uint8),
+                                          _ptr(ccol, torch.uint8), float(dt))
+        if check:
+            self._check(st, "ebit_advect_markers")
+        return st
 
     def heat_rhs(self, T_star, b):
         self._check(self.lib.ebit_heat_rhs(self.h, _ptr(T_star, torch.float64), _ptr(b, torch.float64)),

@@ -109,6 +109,7 @@ def line_case(n, normal, point, periodic=(False, False), seed=0, rho=(1.0, 1.0))
 
 
 def _case_from(n, h, nn, vcol, ccol, markers, periodic, rho):
+    """Walls: T Neumann, p Dirichlet (an outflow); periodic axes: both periodic."""
     pr = ei.Props(rho_l=rho[0], rho_v=rho[1])
     T_bc, p_bc = [], []
     for a in range(2):
@@ -129,10 +130,11 @@ def circle_case(n, centre, R, inside_vapour=True, rho=(1.0, 1.0)):
     return _case_from(n, h, nn, vcol, ccol, markers, (False, False), rho)
 
 
-def stripe_case(n, c1, c2):
-    """A doubly periodic unit square crossed by two lines of slope 1,
-    x - y = c1 and x - y = c2 (mod 1); liquid where (x - y - c1) mod 1 lies
-    in (0, (c2 - c1) mod 1)."""
+def stripe_case(n, c1, c2, periodic=(True, True)):
+    """A unit square crossed by two lines of slope 1, x - y = c1 and
+    x - y = c2 (mod 1); liquid where (x - y - c1) mod 1 lies in
+    (0, (c2 - c1) mod 1).  Periodic axes store their seam line as a copy of
+    line 0; a wall axis cuts the stripe."""
     h = 1.0 / n
     nn = (n, n, 1)
     w = (c2 - c1) % 1.0
@@ -142,9 +144,10 @@ def stripe_case(n, c1, c2):
 
     vx, vy = np.meshgrid(np.arange(n + 1) * h, np.arange(n + 1) * h)
     vcol = liquid(vx, vy).astype(np.uint8)
-    # the seam vertices repeat the first ones
-    vcol[:, n] = vcol[:, 0]
-    vcol[n, :] = vcol[0, :]
+    if periodic[0]:
+        vcol[:, n] = vcol[:, 0]
+    if periodic[1]:
+        vcol[n, :] = vcol[0, :]
     vcol = vcol[None]
     cx, cy = np.meshgrid((np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h)
     ccol = liquid(cx, cy).astype(np.uint8)[None]
@@ -166,7 +169,11 @@ def stripe_case(n, c1, c2):
                     s = y / h - j
                     if -1e-12 <= s <= 1 + 1e-12:
                         my[0, j, i] = min(max(s, 0.0), 1.0)
-    return _case_from(n, h, nn, vcol, ccol, [mx, my], (True, True), (1.0, 1.0))
+    if periodic[0]:
+        my[0, :, n] = my[0, :, 0]
+    if periodic[1]:
+        mx[0, n, :] = mx[0, 0, :]
+    return _case_from(n, h, nn, vcol, ccol, [mx, my], periodic, (1.0, 1.0))
 
 
 # ----------------------------------------------------------------------------

@@ -1,0 +1,371 @@
+"""GPU parity of the interfacial velocity and the EBIT marker motion with
+the oracle (oracle/advect.py), through the C ABI.
+
+* ebit_interface_velocity against the oracle's cell-centre field, element by
+  element: 1e-13 of the largest value when the oracle's formula is fed the
+  library's facet normals, 1e-11 end to end (3D facet normals agree to
+  ~1e-13 and a band normal summed from nearly cancelling ones magnifies
+  that); 2D and 3D, walls and periodic axes;
+* ebit_advect_markers against the oracle's x pass, y pass and cell colours
+  from the same cell field: marker coordinates line by line within 1e-12
+  cells, the same number of markers on every line, vertex colours equal
+  except at vertices within 1e-9 cells of a marker (which side such a vertex
+  takes is a matter of rounding on either side), cell colours equal except
+  where the oracle's segment passes within 1e-9 h of the centre; periodic
+  seams identical; circles, lines, stripes periodic along one axis, ragged grids
+  and the 256 x 256 bubble;
+* the Stefan time loop (Sec. 3.1) run on the GPU (interfacial velocity,
+  marker motion, extensions, heat solve, mass flux, projection) follows the
+  oracle's loop: the front within 1e-9 relative after every step;
+* errors: a displacement above one cell, a saddle, a marker outside
+  [0, 1], a 3D grid.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import ebit_inputs as ei
+from advect_util import (EXT_ITERS, circle_case, compare_markers, interface_x, line_case,
+                         near_marker_vertices, oracle_time_loop, stefan_case, stripe_case)
+from oracle import advect, extend, geometry
+from parity_util import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _ebit():
+    from paper_2402_13677_amd import ebit
+    return ebit
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).to("cuda")
+
+
+# ----------------------------------------------------------------------------
+# interfacial velocity at the cell centres
+# ----------------------------------------------------------------------------
+
+def _iface_case(name):
+    if name == "film3d_32":
+        case = ei.config(4, n=32)
+        rng = np.random.Generator(np.random.PCG64(9))
+        ul = [rng.normal(0.0, 1e-2, ei.face_shape(3, case.n, a)) for a in range(3)]
+        uv = [u + rng.normal(0.0, 1e-3, u.shape) for u in ul]
+        return dataclasses.replace(case, u_l=ul, u_v=uv)
+    dim, n, seed, kind = name
+    return ei.random_case(dim, n, seed, kind=kind)
+
+
+@pytest.mark.parametrize("name", [(2, 40, 1, "ball"), (2, 37, 2, "plane"), (3, 20, 3, "ball"),
+                                  (3, 17, 4, "plane"), "film3d_32"])
+def test_interface_velocity_parity(name):
+    ebit = _ebit()
+    case = _iface_case(name)
+    say(f"[gpu] interface velocity {case.name}")
+    geo = geometry.build(case)
+    inb, _ = extend.band(case, geo)
+    rng = np.random.Generator(np.random.PCG64(21))
+    mdot = np.where(inb, rng.uniform(-2.0, 2.0, case.ncells), 0.0)
+    ref = advect.cell_interface_velocity(case, geo, case.u_l, case.u_v, mdot)
+    ctx, dc = ebit.context_for(case)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    out = [torch.full((case.ncells,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(case.dim)]
+    ctx.interface_velocity(dc.u_l, dc.u_v, dev(mdot), out)
+    facet = torch.empty(6 * case.ncells, dtype=torch.float64, device="cuda")
+    ctx.get_geometry(None, None, facet)
+    torch.cuda.synchronize()
+    got = np.stack([o.cpu().numpy() for o in out], axis=1)
+    nF_gpu = facet.cpu().numpy().reshape(6, -1)[3:].T.copy()
+    ctx.close()
+    scale = np.max(np.abs(ref))
+    # the kernel's arithmetic: the oracle's formula on the library's own
+    # facet normals (the normals themselves are held to 1e-12 by the
+    # geometry parity tests)
+    iface = geo["is_if"]
+    nF_gpu[~iface] = 0.0
+    ref_own = advect.cell_interface_velocity(case, dict(geo, nF=nF_gpu), case.u_l, case.u_v, mdot)
+    err_own = np.max(np.abs(got - ref_own)) / scale
+    # end to end: 3D facet normals agree to ~1e-13, and the band normal of a
+    # cell whose block sums nearly cancelling normals magnifies that
+    err = np.max(np.abs(got - ref)) / scale
+    say(f"   max |GPU - oracle| / max |u_G| = {err:.1e} ({err_own:.1e} on the library's facet normals)")
+    assert err_own <= 1e-13
+    assert err <= 1e-11
+
+
+# ----------------------------------------------------------------------------
+# marker motion
+# ----------------------------------------------------------------------------
+
+def _smooth_field(case, seed, cfl):
+    """A smooth random cell field scaled to the given CFL number."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, _ = case.n
+    h = case.h
+    x, y = np.meshgrid((np.arange(nx) + 0.5) * h, (np.arange(ny) + 0.5) * h)
+    k = rng.normal(size=(2, 4))
+    ux = k[0, 0] + k[0, 1] * np.sin(2 * math.pi * y + k[0, 3]) + k[0, 2] * np.cos(2 * math.pi * x)
+    uy = k[1, 0] + k[1, 1] * np.cos(2 * math.pi * x + k[1, 3]) + k[1, 2] * np.sin(2 * math.pi * y)
+    ug = np.stack([ux.ravel(), uy.ravel()], axis=1)
+    dt = cfl * h / np.max(np.abs(ug))
+    return ug, dt
+
+
+def _oracle_motion(case, ug, dt):
+    mk, vc = case.markers, case.vcol
+    for a in range(2):
+        mk, vc = advect.advect_pass(case, mk, vc, ug, dt, a)
+    return mk, vc, advect.cell_colours(case, mk, vc)
+
+
+def _gpu_motion(case, ug, dt, ctx=None):
+    ebit = _ebit()
+    own = ctx is None
+    if own:
+        ctx, dc = ebit.context_for(case)
+    mk = [dev(m) for m in case.markers]
+    vc = dev(case.vcol, torch.uint8)
+    cc = torch.full(ei.cell_shape(2, case.n), 7, dtype=torch.uint8, device="cuda")
+    u = [dev(ug[:, a]) for a in range(2)]
+    st = ctx.advect_markers(u, mk, vc, cc, dt, check=False)
+    torch.cuda.synchronize()
+    out = ([m.cpu().numpy() for m in mk], vc.cpu().numpy(), cc.cpu().numpy(), st,
+           ctx.lib.ebit_last_error(ctx.h).decode())
+    if own:
+        ctx.close()
+    return out
+
+
+def _ambiguous_cells(case, mk):
+    """Cells whose centre lies within 1e-9 h of their segment's line."""
+    nx, ny, _ = case.n
+    h = case.h
+    out = np.zeros((ny, nx), bool)
+    mx, my = np.asarray(mk[0])[0], np.asarray(mk[1])[0]
+    for j in range(ny):
+        for i in range(nx):
+            pts = []
+            for (e, r, c) in ((0, j, i), (0, j + 1, i), (1, j, i), (1, j, i + 1)):
+                s = (mx if e == 0 else my)[r, c]
+                if not np.isnan(s):
+                    pts.append(((c + s) * h, r * h) if e == 0 else (c * h, (r + s) * h))
+            if len(pts) == 2:
+                (x1, y1), (x2, y2) = pts
+                L = math.hypot(x2 - x1, y2 - y1)
+                if L == 0.0:
+                    out[j, i] = True
+                    continue
+                d = abs(-(y2 - y1) * ((i + 0.5) * h - x1) + (x2 - x1) * ((j + 0.5) * h - y1)) / L
+                out[j, i] = d <= 1e-9 * h
+    return out
+
+
+def _check_motion(case, got, ref, label):
+    mk, vc, cc, st, msg = got
+    rmk, rvc, rcc = ref
+    assert st == 0, (label, st, msg)
+    worst = compare_markers(mk, rmk, 1e-12)
+    near = near_marker_vertices(rmk, case.n[:2], 1e-9)
+    vdiff = (vc[0] != rvc[0]) & ~near
+    assert not np.any(vdiff), (label, np.argwhere(vdiff)[:5])
+    amb = _ambiguous_cells(case, rmk)
+    cdiff = (cc[0] != rcc[0]) & ~amb
+    assert not np.any(cdiff), (label, np.argwhere(cdiff)[:5])
+    # periodic seams: one grid line stored twice
+    nx, ny, _ = case.n
+    if case.T_bc[0][0] == ei.PERIODIC:
+        assert np.array_equal(mk[1][0][:, nx], mk[1][0][:, 0], equal_nan=True)
+        assert np.array_equal(vc[0][:, nx], vc[0][:, 0])
+    if case.T_bc[2][0] == ei.PERIODIC:
+        assert np.array_equal(mk[0][0][ny, :], mk[0][0][0, :], equal_nan=True)
+        assert np.array_equal(vc[0][ny, :], vc[0][0, :])
+    nm = sum(int(np.count_nonzero(~np.isnan(m))) for m in mk)
+    say(f"   {label}: {nm} markers, max coordinate difference {worst:.1e} cells, "
+        f"{int(np.count_nonzero(near))} near-marker vertices, {int(np.count_nonzero(amb))} on-line centres")
+
+
+MOTION_CASES = [
+    ("circle_vapour_24", lambda: circle_case(24, (0.48, 0.53), 0.27), 31, 0.9),
+    ("circle_liquid_37", lambda: circle_case(37, (0.55, 0.45), 0.2, inside_vapour=False), 32, 0.6),
+    ("circle_small_64", lambda: circle_case(64, (0.31, 0.62), 0.09), 33, 0.95),
+    ("line_steep_41", lambda: line_case(41, (1.0, 0.37), (0.52, 0.5)), 34, 0.8),
+    ("line_flat_50", lambda: line_case(50, (-0.2, 1.0), (0.5, 0.44)), 35, 0.7),
+    ("line_diag_33", lambda: line_case(33, (1.0, 1.0), (0.5, 0.5)), 36, 0.99),
+    ("stripe_periodic_x_32", lambda: stripe_case(32, 0.137, 0.583, (True, False)), 37, 0.9),
+    ("stripe_periodic_x_16", lambda: stripe_case(16, 0.71, 0.05, (True, False)), 38, 0.5),
+    ("stripe_periodic_y_32", lambda: stripe_case(32, 0.29, 0.66, (False, True)), 42, 0.85),
+    ("stefan_thin_32", lambda: stefan_case(32), 39, 0.8),
+    ("circle_ragged_130", lambda: circle_case(130, (0.5, 0.5), 0.33), 40, 0.9),
+]
+
+
+@pytest.mark.parametrize("label,make,seed,cfl", MOTION_CASES, ids=[c[0] for c in MOTION_CASES])
+def test_marker_motion_parity(label, make, seed, cfl):
+    case = make()
+    ug, dt = _smooth_field(case, seed, cfl)
+    say(f"[gpu] marker motion {label}: CFL {cfl}, dt {dt:.3e}")
+    ref = _oracle_motion(case, ug, dt)
+    got = _gpu_motion(case, ug, dt)
+    _check_motion(case, got, ref, label)
+
+
+def test_marker_motion_parity_bubble2d_256():
+    """The 256 x 256 bubble with the interfacial velocity of its own fields
+    (the oracle's cell field, a band-extended random mass flux)."""
+    case = ei.config(1)
+    say("[gpu] marker motion bubble2d_256")
+    geo = geometry.build(case)
+    inb, _ = extend.band(case, geo)
+    rng = np.random.Generator(np.random.PCG64(41))
+    mdot = np.where(inb, rng.uniform(0.5, 1.5, case.ncells), 0.0)
+    ug = advect.cell_interface_velocity(case, geo, case.u_l, case.u_v, mdot)
+    dt = 0.8 * case.h / np.max(np.abs(ug))
+    ref = _oracle_motion(case, ug, dt)
+    got = _gpu_motion(case, ug, dt)
+    _check_motion(case, got, ref, "bubble2d_256")
+
+
+def test_repeated_steps_follow_the_oracle():
+    """Ten steps of a growing circle, each from the oracle's previous state,
+    on one context (the scratch of one call must not leak into the next)."""
+    ebit = _ebit()
+    case = circle_case(48, (0.5, 0.5), 0.2)
+    ctx, dc = ebit.context_for(case)
+    for step in range(10):
+        geo = geometry.build(case)
+        inb, _ = extend.band(case, geo)
+        z = [np.zeros(ei.face_shape(2, case.n, a)) for a in range(2)]
+        ug = advect.cell_interface_velocity(case, geo, z, z, np.where(inb, 1.0, 0.0))
+        dt = 0.5 * case.h
+        ref = _oracle_motion(case, ug, dt)
+        got = _gpu_motion(case, ug, dt, ctx)
+        _check_motion(case, got, ref, f"step {step}")
+        case = dataclasses.replace(case, markers=list(ref[0]), vcol=ref[1], ccol=ref[2])
+    ctx.close()
+
+
+def test_zero_velocity_leaves_the_markers():
+    case = circle_case(40, (0.47, 0.52), 0.23)
+    ug = np.zeros((case.ncells, 2))
+    mk, vc, cc, st, _ = _gpu_motion(case, ug, 1e-3)
+    assert st == 0
+    compare_markers(mk, case.markers, 1e-14)
+    assert np.array_equal(vc, case.vcol)
+    # the colours of the segments (a centre between the chord and the arc
+    # takes the chord's side)
+    assert np.array_equal(cc, advect.cell_colours(case, case.markers, case.vcol))
+
+
+# ----------------------------------------------------------------------------
+# errors
+# ----------------------------------------------------------------------------
+
+def test_motion_errors():
+    ebit = _ebit()
+    case = circle_case(24, (0.5, 0.5), 0.25)
+    ug, dt = _smooth_field(case, 51, 0.5)
+    # more than one cell in a pass
+    *_, st, msg = _gpu_motion(case, ug, 3.0 * dt)
+    assert st == ebit.EINVAL, (st, msg)
+    # a saddle: two liquid vertices on a diagonal of one cell
+    sad = line_case(8, (1.0, 0.0), (2.0, 0.5))
+    vcol = sad.vcol.copy()
+    mx, my = (m.copy() for m in sad.markers)
+    for (vi, vj) in ((3, 3), (4, 4)):
+        vcol[0, vj, vi] = 1
+        mx[0, vj, vi - 1] = mx[0, vj, vi] = 0.5
+        my[0, vj - 1, vi] = my[0, vj, vi] = 0.5
+    sad = dataclasses.replace(sad, markers=[mx, my], vcol=vcol)
+    *_, st, msg = _gpu_motion(sad, np.zeros((64, 2)), 1e-3)
+    assert st == ebit.EGEOM, (st, msg)
+    # a marker outside [0, 1]
+    bad = circle_case(24, (0.5, 0.5), 0.25)
+    m0 = bad.markers[0].copy()
+    k = np.argwhere(~np.isnan(m0))[0]
+    m0[tuple(k)] = 1.5
+    bad = dataclasses.replace(bad, markers=[m0, bad.markers[1]])
+    *_, st, msg = _gpu_motion(bad, np.zeros((576, 2)), 1e-3)
+    assert st == ebit.EGEOM, (st, msg)
+    # three dimensions
+    c3 = ei.random_case(3, 8, 1)
+    ctx, dc = ebit.context_for(c3)
+    u = [torch.zeros(c3.ncells, dtype=torch.float64, device="cuda") for _ in range(3)]
+    cc = torch.empty_like(dc.ccol)
+    st = ctx.advect_markers(u, dc.markers, dc.vcol, cc, 1e-3, check=False)
+    assert st == ebit.EINVAL
+    ctx.close()
+    # a clean call on a context after an error succeeds
+    got = _gpu_motion(case, ug, dt)
+    _check_motion(case, got, _oracle_motion(case, ug, dt), "after errors")
+
+
+# ----------------------------------------------------------------------------
+# the Stefan time loop on the GPU
+# ----------------------------------------------------------------------------
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("nx,steps", [(16, 60), (32, 60)])
+def test_stefan_time_loop_parity(nx, steps):
+    """The loop of Sec. 2.5 with every step on the GPU, against the oracle's
+    loop from the same state: after every step the front agrees to 1e-9
+    relative and the markers line by line to 1e-8 cells."""
+    ebit = _ebit()
+    dt = 0.01
+    case0 = stefan_case(nx, dt=dt)
+    fronts = []
+    states = []
+
+    def watch(s, t, case, T, mdot):
+        fronts.append(interface_x(case))
+        states.append((list(case.markers), case.vcol.copy()))
+
+    t_end = 0.282 + steps * dt
+    oracle_time_loop(case0, t_end, on_step=watch)
+
+    opts = ebit.default_opts(rtol=1e-14, max_iters=400)
+    ctx, dc = ebit.context_for(case0, opts)
+    N = case0.ncells
+    T = dc.T0.reshape(-1).clone()
+    mk, vc, cc = dc.markers, dc.vcol, dc.ccol
+    ul, uv = dc.u_l, dc.u_v
+    mdot = torch.zeros(N, dtype=torch.float64, device="cuda")
+    p = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ug = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(2)]
+    ctx.build_coeffs(mk, vc, cc, dt)
+    ctx.mass_flux(T, mdot)
+    mb = mdot.clone()
+    ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, EXT_ITERS)
+    ctx.project(ul, uv, mdot, p)
+    worst = 0.0
+    for s in range(steps):
+        Tl = T.clone()
+        ctx.extend(Tl, ebit.EXT_LIQ_TO_VAP, EXT_ITERS)
+        Tv = T.clone()
+        ctx.extend(Tv, ebit.EXT_VAP_TO_LIQ, EXT_ITERS)
+        ctx.interface_velocity(ul, uv, mb, ug)
+        old = cc.reshape(-1).clone()
+        ctx.advect_markers(ug, mk, vc, cc, dt)
+        new = cc.reshape(-1)
+        Ts = torch.where(new == old, T, torch.where(new == 1, Tl, Tv))
+        ctx.build_coeffs(mk, vc, cc, dt)
+        st = ctx.heat_solve(Ts, T)
+        assert st["status"] == 0
+        ctx.mass_flux(T, mdot)
+        mb = mdot.clone()
+        ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, EXT_ITERS)
+        st = ctx.project(ul, uv, mdot, p)
+        assert st["status"] == 0
+        torch.cuda.synchronize()
+        mk_h = [m.cpu().numpy() for m in mk]
+        g = dataclasses.replace(case0, markers=mk_h)
+        X = interface_x(g)
+        e = abs(X - fronts[s]) / fronts[s]
+        worst = max(worst, e)
+        assert e <= 1e-9, (s, X, fronts[s])
+        compare_markers(mk_h, states[s][0], 1e-8)
+    ctx.close()
+    say(f"[gpu] Stefan loop nx={nx}: {steps} steps, front within {worst:.1e} of the oracle's")

@@ -244,7 +244,8 @@ def test_zero_velocity_leaves_the_interface():
     for a in range(2):
         mk, vc = advect.advect_pass(case, mk, vc, ug, 1e-3, a)
     compare_markers(mk, case.markers, 1e-14)
-    assert np.array_equal(advect.cell_colours(case, mk, vc), case.ccol)
+    assert np.array_equal(vc, case.vcol)
+    assert np.array_equal(advect.cell_colours(case, mk, vc), advect.cell_colours(case, case.markers, case.vcol))
 
 
 def test_saddle_cells_are_rejected():
