@@ -554,6 +554,112 @@ def one_fluid_cpu_baseline(case):
             "sample": "one call on the workload (SciPy SuperLU direct solve)"}
 
 
+def iface_velocity_bytes_per_cell(dim):
+    """Algorithmic bytes of ebit_interface_velocity per cell: the own
+    phase's face velocity per axis (8 B, each face shared by two cells),
+    the flags (1 B), the mass flux (8 B) and the dim outputs (8 B each); the
+    facet normals of the few interface cells are not counted."""
+    return 8 * dim + 1 + 8 + 8 * dim
+
+
+def marker_motion_bytes(ncells_x, ncells_y, markers):
+    """Algorithmic bytes of one ebit_advect_markers step on an nx x ny grid:
+    one read of both marker arrays (8 B per edge, the only part that grows
+    with the grid: the markers have to be found), and per marker 64 B (its
+    old and new coordinates, the vertex colours of its edge, the cells it
+    bounds)."""
+    edges = ncells_x * (ncells_y + 1) + (ncells_x + 1) * ncells_y
+    return 8 * edges + 64 * markers
+
+
+def marker_motion_bench(names=("bubble2d_256", "bubble2d_4096"), reps=20):
+    """The interfacial velocity (ebit_interface_velocity) and one marker
+    step (ebit_advect_markers) on 2D bubbles: the mass flux of the initial
+    temperature carried into the band, the interfacial velocity of the
+    workload's face fields, dt for a CFL number of 0.5.  Median of `reps`
+    calls timed with events on the library's stream (the marker step
+    includes its status read-back); the markers are restored between
+    calls outside the timed region."""
+    import torch
+    import ebit_inputs as ei
+    from paper_2402_13677_amd import ebit
+
+    out = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for name in names:
+        n = int(name.split("_")[1])
+        case = ei.config(1, n=n)
+        ctx, dc = ebit.context_for(case)
+        ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+        N = case.ncells
+        mdot = torch.zeros(N, dtype=torch.float64, device="cuda")
+        ctx.mass_flux(dc.T0, mdot)
+        ctx.extend(mdot, ebit.EXT_IFACE_TO_BAND, 8)
+        ug = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(2)]
+        ctx.interface_velocity(dc.u_l, dc.u_v, mdot, ug)
+        torch.cuda.synchronize()
+        umax = max(float(u.abs().max()) for u in ug)
+        dt = 0.5 * case.h / umax
+        mk0 = [m.clone() for m in dc.markers]
+        vc0 = dc.vcol.clone()
+        cc = torch.empty_like(dc.ccol)
+        t_iv, t_mv = [], []
+        for r in range(reps + 2):
+            ev[0].record()
+            ctx.interface_velocity(dc.u_l, dc.u_v, mdot, ug)
+            ev[1].record()
+            ev[1].synchronize()
+            t_iv.append(ev[0].elapsed_time(ev[1]))
+            for m, m0 in zip(dc.markers, mk0):
+                m.copy_(m0)
+            dc.vcol.copy_(vc0)
+            torch.cuda.synchronize()
+            ev[0].record()
+            ctx.advect_markers(ug, dc.markers, dc.vcol, cc, dt)
+            ev[1].record()
+            ev[1].synchronize()
+            t_mv.append(ev[0].elapsed_time(ev[1]))
+        nmark = sum(int((~torch.isnan(m)).sum()) for m in dc.markers)
+        iv = statistics.median(t_iv[2:])
+        mv = statistics.median(t_mv[2:])
+        b_iv = iface_velocity_bytes_per_cell(2) * N
+        b_mv = marker_motion_bytes(n, n, nmark)
+        out[name] = {"cells": N, "markers": nmark, "dt": dt,
+                     "interface_velocity": {"us": iv * 1e3, "algorithmic_bytes": b_iv,
+                                            "achieved_GBps": b_iv / (iv * 1e-3) / 1e9,
+                                            "frac": b_iv / (iv * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "advect_markers": {"us": mv * 1e3, "algorithmic_bytes": b_mv,
+                                        "achieved_GBps": b_mv / (mv * 1e-3) / 1e9,
+                                        "frac": b_mv / (mv * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                        "launches": 10, "note": "whole call: ten launches and the status "
+                                        "read-back; the scan of the marker arrays is the only grid-sized part"}}
+        ctx.close()
+    return out
+
+
+def marker_motion_cpu_baseline():
+    """The oracle's interfacial velocity and marker step on bubble2d_256
+    (1 thread): ms per call."""
+    import numpy as np
+    import ebit_inputs as ei
+    import oracle
+    case = ei.config(1)
+    geo = oracle.geometry.build(case)
+    inb, _ = oracle.extend.band(case, geo)
+    mdot = np.where(inb, 1.0, 0.0)
+    t0 = time.perf_counter()
+    ug = oracle.advect.cell_interface_velocity(case, geo, case.u_l, case.u_v, mdot)
+    t1 = time.perf_counter()
+    dt = 0.5 * case.h / np.max(np.abs(ug))
+    mk, vc = case.markers, case.vcol
+    for a in range(2):
+        mk, vc = oracle.advect.advect_pass(case, mk, vc, ug, dt, a)
+    oracle.advect.cell_colours(case, mk, vc)
+    t2 = time.perf_counter()
+    return {"interface_velocity_ms": (t1 - t0) * 1e3, "advect_markers_ms": (t2 - t1) * 1e3, "cores": 1,
+            "kind": "oracle", "sample": "one call each on bubble2d_256 (mdot = 1 in the band)"}
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -615,6 +721,10 @@ def main():
                     help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
     ap.add_argument("--no-extension", action="store_true", help="skip the narrow-band extension timing")
     ap.add_argument("--no-one-fluid", action="store_true", help="skip the one-fluid projection timing")
+    ap.add_argument("--no-marker-motion", action="store_true",
+                    help="skip the interfacial-velocity and marker-motion timing")
+    ap.add_argument("--marker-motion-only", action="store_true",
+                    help="run only the interfacial-velocity and marker-motion timing (2D bubbles)")
     ap.add_argument("--extras-only", action="store_true",
                     help="time only the narrow-band extension and the one-fluid projection (for profiling them)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -628,13 +738,17 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.marker_motion_only:
+        print(json.dumps({"marker_motion": marker_motion_bench()}))
+        return
     case = make_case(args.workload)
     if isinstance(case, list):
         return main_batch(args, case)
     if args.extras_only:
         sched = parse_schedule(args.schedule) if args.schedule else None
         print(json.dumps({"workload": case.name, "extension": extension_bench(case),
-                          "one_fluid": one_fluid_bench(case, args.precision, sched)}))
+                          "one_fluid": one_fluid_bench(case, args.precision, sched),
+                          "marker_motion": marker_motion_bench()}))
         return
     rtol = workload_rtol(case)
     tune = parse_schedule(args.schedule) if args.schedule else (not args.no_autotune)
@@ -698,6 +812,11 @@ def main():
         extra["one_fluid"] = one_fluid_bench(case, args.precision, schedule)
         if not args.no_cpu_baseline and case.dim == 2:
             extra["one_fluid"]["cpu_oracle"] = one_fluid_cpu_baseline(case)
+    if not args.no_marker_motion:
+        log("interfacial velocity and marker motion (2D bubbles)")
+        extra["marker_motion"] = marker_motion_bench()
+        if not args.no_cpu_baseline:
+            extra["marker_motion"]["cpu_oracle"] = marker_motion_cpu_baseline()
     if not args.no_cpu_baseline:
         log("first step of each precision for the error against the oracle")
         gsteps = {"mixed": gpu_first_step(case, "mixed", schedule), "fp64": gpu_first_step(case, "fp64", schedule)}

@@ -275,12 +275,18 @@ ebit_status ebit_interface_velocity(ebit_ctx* ctx, const double* const u_l[3], c
  *     side of its segment's line that the corners mark as liquid (a centre
  *     on the line is liquid).
  * u_gamma[0..1]: cells (ebit_interface_velocity).  marker[0..1]: the x- and
- * y-edge arrays, in/out.  vertex_colour: in/out.  cell_colour: output.  All
+ * y-edge arrays, in/out.  vertex_colour: in/out.  cell_colour: in/out: the
+ * cells within 3 cells of a marker (before the step or between its passes)
+ * are recomputed, every other cell keeps its colour (in a consistent input
+ * that is its corners' colour, which the step leaves unchanged there).  All
  * device, caller-owned; the periodic seams of the input must agree (as
- * ebit_build_coeffs requires).  The call does not need ebit_build_coeffs;
- * it uses the context's scratch, so it must not overlap another call on the
- * context, and it synchronises the context stream to report errors.
- * Errors: EBIT_EINVAL for a 3D grid, fewer than 4 cells on an axis, a NULL
+ * ebit_build_coeffs requires).  The work is one scan of the marker arrays,
+ * then kernels over the listed markers only.  The call does not need
+ * ebit_build_coeffs; it uses the context's scratch, so it must not overlap
+ * another call on the context, and it synchronises the context stream to
+ * report errors.
+ * Errors: EBIT_EINVAL for a 3D grid, fewer than 4 cells on an axis, 2^31
+ * edges or more, a NULL
  * pointer, dt negative or not finite, or a marker that would move by more
  * than one cell (h) in a pass or by a non-finite amount; EBIT_EGEOM when a
  * cell holds other than 0 or 2 markers (a saddle) before a pass or after

@@ -90,7 +90,8 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_iface_velocity(Dims d, const uint
 
 // Error bits of a motion call.
 constexpr int ADV_ERR_CFL = 1;   // a displacement above one cell, or not finite
-constexpr int ADV_ERR_GEOM = 2;  // a cell with other than 0 or 2 markers
+constexpr int ADV_ERR_GEOM = 2;  // a cell with other than 0 or 2 markers, or a marker outside [0, 1]
+constexpr int ADV_LIST_BLOCKS = 512;
 
 struct Adv {
   int nx, ny;
@@ -102,17 +103,35 @@ struct Adv {
   uint8_t* ccol;                // [ny][nx]
   const double* ug;             // cell field, component a
   double* X[2];                 // per edge: moved coordinate along a (NaN: no marker)
-  double* Y[2];                 // per edge: coordinate across a
+  double* Y[2];                 // per edge: coordinate across a (NaN: no marker)
+  int* list[2];                 // marker edge ids: before the x pass, before the y pass
+  int* count;                   // [2] list lengths
   int* err;
+  int cur, next;                // list this pass reads; list it fills (-1: none)
 };
 
 __device__ inline long long xedge(const Adv& A, int i, int j) { return (long long)i + (long long)A.nx * j; }
 __device__ inline long long yedge(const Adv& A, int i, int j) { return (long long)i + (long long)(A.nx + 1) * j; }
 __device__ inline long long vtx(const Adv& A, int i, int j) { return (long long)i + (long long)(A.nx + 1) * j; }
+// global edge id: the x-edges, then the y-edges
+__device__ inline int xedge_id(const Adv& A, int i, int j) { return i + A.nx * j; }
+__device__ inline int yedge_id(const Adv& A, int i, int j) { return A.nx * (A.ny + 1) + i + (A.nx + 1) * j; }
 
 __device__ inline int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
+}
+
+// Append id to a list, one atomic per wave (the wave's active lanes).
+__device__ inline void append(int* list, int* count, int id, bool act) {
+  const unsigned long long mask = __ballot(act);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(mask));
+  base = __shfl(base, leader);
+  if (act) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = id;
 }
 
 // Bilinear value of the cell field at (px, py): the four centres around the
@@ -154,33 +173,17 @@ __device__ inline double bilinear(const Adv& A, const double* g, double px, doub
   return (1.0 - fx) * (1.0 - fy) * g00 + (1.0 - fx) * fy * g10 + fx * (1.0 - fy) * g01 + fx * fy * g11;
 }
 
-// Every edge of both families: the marker's moved coordinate along a and
-// its coordinate across a.
-__global__ __launch_bounds__(ADV_BLOCK) void k_adv_move(Adv A) {
-  const long long E0 = (long long)A.nx * (A.ny + 1);
-  const long long E1 = (long long)(A.nx + 1) * A.ny;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E0 + E1) return;
-  const int fam = t < E0 ? 0 : 1;
-  const long long e = fam == 0 ? t : t - E0;
-  const double s = A.mk[fam][e];
-  if (!(s >= 0.0 && s <= 1.0)) {
-    // no marker (NaN); a value outside [0, 1] is reported and dropped
-    if (!isnan(s)) atomicOr(A.err, ADV_ERR_GEOM);
-    A.X[fam][e] = NAN;
-    A.Y[fam][e] = NAN;
-    return;
-  }
-  int i, j;
+// Move the marker s of edge e of family fam along a: its moved coordinate
+// along a and its coordinate across a.  False (and X, Y left NaN) for a
+// displacement above one cell.
+__device__ inline bool move_marker(const Adv& A, int fam, long long e, double s) {
   double px, py;
   if (fam == 0) {
-    i = (int)(e % A.nx);
-    j = (int)(e / A.nx);
+    const int i = (int)(e % A.nx), j = (int)(e / A.nx);
     px = ((double)i + s) * A.h;
     py = (double)j * A.h;
   } else {
-    i = (int)(e % (A.nx + 1));
-    j = (int)(e / (A.nx + 1));
+    const int i = (int)(e % (A.nx + 1)), j = (int)(e / (A.nx + 1));
     px = (double)i * A.h;
     py = ((double)j + s) * A.h;
   }
@@ -195,13 +198,44 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_adv_move(Adv A) {
       // reported; the marker is dropped so that every later index stays
       // within one cell of where it was
       atomicOr(A.err, ADV_ERR_CFL);
-      A.X[fam][e] = NAN;
-      A.Y[fam][e] = NAN;
-      return;
+      return false;
     }
   }
   A.X[fam][e] = x1;
   A.Y[fam][e] = a == 0 ? py : px;
+  return true;
+}
+
+// x pass: every edge of both families; each marker is moved and listed.
+__global__ __launch_bounds__(ADV_BLOCK) void k_adv_scan(Adv A) {
+  const long long E0 = (long long)A.nx * (A.ny + 1);
+  const long long E1 = (long long)(A.nx + 1) * A.ny;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool listed = false;
+  if (t < E0 + E1) {
+    const int fam = t < E0 ? 0 : 1;
+    const long long e = fam == 0 ? t : t - E0;
+    const double s = A.mk[fam][e];
+    if (!isnan(s)) {
+      if (!(s >= 0.0 && s <= 1.0))
+        atomicOr(A.err, ADV_ERR_GEOM);  // reported and dropped
+      else
+        listed = move_marker(A, fam, e, s);
+    }
+  }
+  append(A.list[0], &A.count[0], (int)t, listed);
+}
+
+// y pass: the markers the x pass wrote, from its list.
+__global__ __launch_bounds__(ADV_BLOCK) void k_adv_move_list(Adv A) {
+  const int T = A.count[A.cur];
+  const int E0 = A.nx * (A.ny + 1);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < T; q += gridDim.x * blockDim.x) {
+    const int t = A.list[A.cur][q];
+    const int fam = t < E0 ? 0 : 1;
+    const long long e = fam == 0 ? t : t - E0;
+    move_marker(A, fam, e, A.mk[fam][e]);
+  }
 }
 
 // Aligned marker at the moved coordinate x1, old edge e: its landing edge
@@ -236,53 +270,95 @@ __device__ inline void landing(const Adv& A, double x1, int n, int& dk, double& 
   dk = k - e;
 }
 
-// One thread per (aligned line, position v in 0..n): the colour of vertex v
-// and the marker of edge v (v < n), gathered from the old edges v-2 .. v+1
-// of the line.  The seam line of a periodic axis across a is computed from
-// line 0.
+// Moved coordinate of the aligned marker on edge position e of line `line`
+// (NaN: none); false beyond a wall.
+__device__ inline bool aligned_x(const Adv& A, int line, int eu, int n, int& e, double& x1) {
+  e = eu;
+  if (A.per[A.a])
+    e = wrapi(eu, n);
+  else if (eu < 0 || eu >= n)
+    return false;
+  x1 = A.X[A.a][A.a == 0 ? xedge(A, e, line) : yedge(A, line, e)];
+  return true;
+}
+
+// Aligned markers: each listed marker of the pass family at edge p of its
+// line settles the positions v = p-1 .. p+2 it can reach (vertex v, edge v)
+// that no marker at a smaller offset in v-2 .. v+1 settles: the vertex
+// changes colour once per marker whose old and new edges lie on either side
+// of it, the edge takes the one marker landing on it (none if two do).  The
+// seam line of a periodic axis across a is computed from line 0, and the
+// seam vertex of a periodic axis along a is written with vertex 0.
 __global__ __launch_bounds__(ADV_BLOCK) void k_adv_aligned(Adv A) {
   const int a = A.a;
-  const int n = a == 0 ? A.nx : A.ny;        // edges per aligned line
-  const int nl = a == 0 ? A.ny + 1 : A.nx + 1;  // aligned lines
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)nl * (n + 1)) return;
-  const int line = (int)(t / (n + 1));
-  const int v = (int)(t % (n + 1));
-  const int nb = a == 0 ? A.ny : A.nx;
-  const int src = (A.per[1 - a] && line == nb) ? 0 : line;
-  const int per = A.per[a];
-  int par = 0, cnt = 0;
-  double snew = NAN;
-  for (int o = -2; o <= 1; ++o) {
-    const int eu = v + o;
-    int e = eu;
-    if (per)
-      e = wrapi(eu, n);
-    else if (eu < 0 || eu >= n)
-      continue;
-    const long long ei = a == 0 ? xedge(A, e, src) : yedge(A, src, e);
-    const double x1 = A.X[a][ei];
-    if (isnan(x1)) continue;
-    int dk;
-    double s;
-    landing(A, x1, n, dk, s, e);
-    const int land = eu + dk;
-    if (land > eu) {
-      if (eu < v && v <= land) par ^= 1;
-    } else if (land < eu) {
-      if (land < v && v <= eu) par ^= 1;
+  const int n = a == 0 ? A.nx : A.ny;          // edges per aligned line
+  const int nb = a == 0 ? A.ny : A.nx;         // index of the last aligned line
+  const int T = A.count[A.cur];
+  const int E0 = A.nx * (A.ny + 1);
+  // one thread per (listed marker, position offset dv = -1 .. 2)
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < 4LL * T;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int t = A.list[A.cur][q >> 2];
+    const int fam = t < E0 ? 0 : 1;
+    if (fam != a) continue;
+    const int e0 = fam == 0 ? t : t - E0;
+    const int line = a == 0 ? e0 / A.nx : e0 % (A.nx + 1);
+    const int pos = a == 0 ? e0 % A.nx : e0 / (A.nx + 1);
+    const int src = (A.per[1 - a] && line == nb) ? 0 : line;
+    {
+      const int dv = (int)(q & 3) - 1;
+      const int vu = pos + dv;
+      int v = vu;
+      if (A.per[a])
+        v = wrapi(vu, n);
+      else if (vu < 0 || vu > n)
+        continue;
+      // settled by the marker at the smallest offset o in -2 .. 1 from v
+      bool mine = true;
+      for (int o = -2; o < -dv; ++o) {
+        int e;
+        double x1;
+        if (aligned_x(A, src, v + o, n, e, x1) && !isnan(x1)) {
+          mine = false;
+          break;
+        }
+      }
+      if (!mine) continue;
+      int par = 0, cnt = 0;
+      double snew = NAN;
+      for (int o = -2; o <= 1; ++o) {
+        const int eu = v + o;
+        int e;
+        double x1;
+        if (!aligned_x(A, src, eu, n, e, x1) || isnan(x1)) continue;
+        int dk;
+        double s;
+        landing(A, x1, n, dk, s, e);
+        const int land = eu + dk;
+        if (land > eu) {
+          if (eu < v && v <= land) par ^= 1;
+        } else if (land < eu) {
+          if (land < v && v <= eu) par ^= 1;
+        }
+        if (v < n && land == v) {
+          ++cnt;
+          snew = s;
+        }
+      }
+      const long long vi = a == 0 ? vtx(A, v, line) : vtx(A, line, v);
+      const uint8_t nc = (uint8_t)(A.vcol[vi] ^ par);
+      A.vcol[vi] = nc;
+      if (A.per[a] && v == 0) A.vcol[a == 0 ? vtx(A, n, line) : vtx(A, line, n)] = nc;
+      bool wrote = false;
+      int id = 0;
+      if (v < n) {
+        const double m = cnt == 1 ? snew : NAN;
+        A.mk[a][a == 0 ? xedge(A, v, line) : yedge(A, line, v)] = m;
+        wrote = !isnan(m);
+        id = a == 0 ? xedge_id(A, v, line) : yedge_id(A, line, v);
+      }
+      if (A.next >= 0) append(A.list[A.next], &A.count[A.next], id, wrote);
     }
-    if (v < n && land == v) {
-      ++cnt;
-      snew = s;
-    }
-  }
-  // (a seam line's old colours are line 0's: the input's seams agree)
-  const long long vi = a == 0 ? vtx(A, v, line) : vtx(A, line, v);
-  A.vcol[vi] = (uint8_t)(A.vcol[vi] ^ par);
-  if (v < n) {
-    const long long ei = a == 0 ? xedge(A, v, line) : yedge(A, line, v);
-    A.mk[a][ei] = cnt == 1 ? snew : NAN;
   }
 }
 
@@ -305,6 +381,11 @@ __device__ inline int cell_markers(const Adv& A, int i, int j, double px[4], dou
     ++m;
   }
   return m;
+}
+
+__device__ inline bool cell_has_marker(const Adv& A, int i, int j) {
+  return !isnan(A.X[0][xedge(A, i, j)]) || !isnan(A.X[0][xedge(A, i, j + 1)]) || !isnan(A.X[1][yedge(A, i, j)]) ||
+         !isnan(A.X[1][yedge(A, i + 1, j)]);
 }
 
 // The far end of the segment continuing cell (i, j)'s segment through its
@@ -380,36 +461,19 @@ __device__ inline double arc_point(double ax, double ay, double bx, double by, d
   return a == 0 ? (ay + u * ty + w * ny) : (ax + u * tx + w * nx);
 }
 
-// One thread per unaligned edge (row across a, position g along a): its
-// marker from the new vertex colours and the crossings of the moved
-// segments of cells g-2 .. g+1 of its row; the thread with g < n also
-// checks that cell (row, g) holds 0 or 2 markers.
-__global__ __launch_bounds__(ADV_BLOCK) void k_adv_unaligned(Adv A) {
+// The marker of unaligned edge (row, g) after the pass: NaN unless its end
+// vertices (on aligned lines row and row + 1) now differ in colour, else the
+// mean crossing of the moved segments of cells g-2 .. g+1 of its row.
+__device__ inline double unaligned_marker(const Adv& A, int row, int g, int n) {
   const int a = A.a;
-  const int n = a == 0 ? A.nx : A.ny;        // cells along a
-  const int rows = a == 0 ? A.ny : A.nx;     // rows across a
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)rows * (n + 1)) return;
-  const int row = (int)(t / (n + 1));
-  const int g = (int)(t % (n + 1));
-  double px[4], py[4];
-  int side[4];
-  if (g < n) {
-    const int ci = a == 0 ? g : row, cj = a == 0 ? row : g;
-    const int m = cell_markers(A, ci, cj, px, py, side);
-    if (m != 0 && m != 2) atomicOr(A.err, ADV_ERR_GEOM);
-  }
-  // end vertices of the edge (on aligned lines row and row + 1)
   const uint8_t c0 = a == 0 ? A.vcol[vtx(A, g, row)] : A.vcol[vtx(A, row, g)];
   const uint8_t c1 = a == 0 ? A.vcol[vtx(A, g, row + 1)] : A.vcol[vtx(A, row + 1, g)];
-  const long long eo = a == 0 ? yedge(A, g, row) : xedge(A, row, g);
-  const int b = 1 - a;
-  if (c0 == c1) {
-    A.mk[b][eo] = NAN;
-    return;
-  }
+  if (c0 == c1) return NAN;
+  double px[4], py[4];
+  int side[4];
   double sum = 0.0;
   int cnt = 0;
+#pragma unroll
   for (int o = -2; o <= 1; ++o) {
     const int iu = g + o;
     int ic = iu;
@@ -444,14 +508,114 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_adv_unaligned(Adv A) {
     ++cnt;
   }
   const double sb = cnt ? sum / (double)cnt : 0.5;
-  A.mk[b][eo] = fmin(fmax(sb, 0.0), 1.0);
+  return fmin(fmax(sb, 0.0), 1.0);
 }
 
-// Cell colours after both passes.
-__global__ __launch_bounds__(ADV_BLOCK) void k_adv_colours(Adv A) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (long long)A.nx * A.ny) return;
-  const int i = (int)(c % A.nx), j = (int)(c / A.nx);
+// Unaligned markers: each listed marker settles, for each cell it borders
+// whose first marker (bottom, top, left, right) it is, that cell's check
+// (0 or 2 markers) and the unaligned edges g = i-1 .. i+2 of the cell's row
+// (i its index along a) whose first cell with a marker in g-2 .. g+1 is
+// this cell.  Every unaligned edge that can hold a marker after the pass,
+// or held one before it, is such an edge.  The seam edge of a periodic axis
+// along a is written with edge 0.
+__global__ __launch_bounds__(ADV_BLOCK) void k_adv_unaligned(Adv A) {
+  const int a = A.a;
+  const int b = 1 - a;
+  const int n = a == 0 ? A.nx : A.ny;          // cells along a
+  const int T = A.count[A.cur];
+  const int E0 = A.nx * (A.ny + 1);
+  // one thread per (listed marker, cell side, edge offset dg = -1 .. 2)
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < 8LL * T;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int t = A.list[A.cur][q >> 3];
+    const int fam = t < E0 ? 0 : 1;
+    const int e0 = fam == 0 ? t : t - E0;
+    int ei, ej;                                 // the edge's (i, j)
+    if (fam == 0) {
+      ei = e0 % A.nx;
+      ej = e0 / A.nx;
+    } else {
+      ei = e0 % (A.nx + 1);
+      ej = e0 / (A.nx + 1);
+    }
+    {
+      const int side = (int)((q >> 2) & 1);
+      // the cells this edge bounds (below / above an x-edge, left / right of a y-edge)
+      int ci = ei, cj = ej;
+      if (fam == 0) {
+        cj = ej - 1 + side;
+        if (cj < 0 || cj >= A.ny) continue;
+      } else {
+        ci = ei - 1 + side;
+        if (ci < 0 || ci >= A.nx) continue;
+      }
+      // the cell's first marker must be this one
+      const int ids[4] = {xedge_id(A, ci, cj), xedge_id(A, ci, cj + 1), yedge_id(A, ci, cj),
+                          yedge_id(A, ci + 1, cj)};
+      const double xs[4] = {A.X[0][xedge(A, ci, cj)], A.X[0][xedge(A, ci, cj + 1)], A.X[1][yedge(A, ci, cj)],
+                            A.X[1][yedge(A, ci + 1, cj)]};
+      int first = -1, m = 0;
+      for (int k = 0; k < 4; ++k)
+        if (!isnan(xs[k])) {
+          if (first < 0) first = ids[k];
+          ++m;
+        }
+      if (first != t) continue;
+      const int dg = (int)(q & 3) - 1;
+      if (m != 2 && dg == -1) atomicOr(A.err, ADV_ERR_GEOM);
+      const int row = a == 0 ? cj : ci;
+      const int ipos = a == 0 ? ci : cj;
+      {
+        const int gu = ipos + dg;
+        int g = gu;
+        if (A.per[a])
+          g = wrapi(gu, n);
+        else if (gu < 0 || gu > n)
+          continue;
+        // settled by the cell with a marker at the smallest offset in g-2 .. g+1
+        bool mine = true;
+        for (int o = -2; o < -dg; ++o) {
+          const int iu = g + o;
+          int ic = iu;
+          if (A.per[a])
+            ic = wrapi(iu, n);
+          else if (iu < 0 || iu >= n)
+            continue;
+          if (a == 0 ? cell_has_marker(A, ic, row) : cell_has_marker(A, row, ic)) {
+            mine = false;
+            break;
+          }
+        }
+        if (!mine) continue;
+        const double mv = unaligned_marker(A, row, g, n);
+        A.mk[b][a == 0 ? yedge(A, g, row) : xedge(A, row, g)] = mv;
+        const bool seam = A.per[a] && g == 0;
+        if (seam) A.mk[b][a == 0 ? yedge(A, n, row) : xedge(A, row, n)] = mv;
+        if (A.next >= 0) {
+          append(A.list[A.next], &A.count[A.next], a == 0 ? yedge_id(A, g, row) : xedge_id(A, row, g), !isnan(mv));
+          append(A.list[A.next], &A.count[A.next], a == 0 ? yedge_id(A, n, row) : xedge_id(A, row, n),
+                 seam && !isnan(mv));
+        }
+      }
+    }
+  }
+}
+
+// Back to the no-marker state of the coordinate arrays for a list's edges.
+__global__ __launch_bounds__(ADV_BLOCK) void k_adv_reset(Adv A, int which) {
+  const int T = A.count[which];
+  const int E0 = A.nx * (A.ny + 1);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < T; q += gridDim.x * blockDim.x) {
+    const int t = A.list[which][q];
+    const int fam = t < E0 ? 0 : 1;
+    const int e = fam == 0 ? t : t - E0;
+    A.X[fam][e] = NAN;
+    A.Y[fam][e] = NAN;
+  }
+}
+
+// Colour of cell (i, j) from the final markers and its corners.
+__device__ inline void cell_colour(const Adv& A, int i, int j) {
   const double h = A.h;
   const long long e[4] = {xedge(A, i, j), xedge(A, i, j + 1), yedge(A, i, j), yedge(A, i + 1, j)};
   double x[2], y[2];
@@ -470,6 +634,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_adv_colours(Adv A) {
     }
     ++m;
   }
+  const long long c = (long long)i + (long long)A.nx * j;
   const uint8_t v00 = A.vcol[vtx(A, i, j)], v10 = A.vcol[vtx(A, i + 1, j)];
   const uint8_t v01 = A.vcol[vtx(A, i, j + 1)], v11 = A.vcol[vtx(A, i + 1, j + 1)];
   if (m == 0) {
@@ -496,8 +661,43 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_adv_colours(Adv A) {
   A.ccol[c] = centre >= 0.0 ? 1 : 0;
 }
 
-__global__ void k_adv_clear(int* err) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *err = 0;
+// Cell colours after both passes: the cells within 3 of a marker of either
+// list (every cell whose corners or markers the step changed); a cell away
+// from them keeps its colour.
+constexpr int ADV_COLOUR_R = 3;
+__global__ __launch_bounds__(ADV_BLOCK) void k_adv_colours(Adv A) {
+  const int T0 = A.count[0], T = T0 + A.count[1];
+  const int E0 = A.nx * (A.ny + 1);
+  constexpr int W = 2 * ADV_COLOUR_R + 1;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < (long long)T * W * W;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(q / (W * W));
+    const int w = (int)(q % (W * W));
+    const int t = k < T0 ? A.list[0][k] : A.list[1][k - T0];
+    const int fam = t < E0 ? 0 : 1;
+    const int e0 = fam == 0 ? t : t - E0;
+    int ci = fam == 0 ? e0 % A.nx : e0 % (A.nx + 1);
+    int cj = fam == 0 ? e0 / A.nx : e0 / (A.nx + 1);
+    ci += w % W - ADV_COLOUR_R;
+    cj += w / W - ADV_COLOUR_R;
+    if (ci < 0 || ci >= A.nx) {
+      if (!A.per[0]) continue;
+      ci = wrapi(ci, A.nx);
+    }
+    if (cj < 0 || cj >= A.ny) {
+      if (!A.per[1]) continue;
+      cj = wrapi(cj, A.ny);
+    }
+    cell_colour(A, ci, cj);
+  }
+}
+
+__global__ void k_adv_clear(int* err, int* count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *err = 0;
+    count[0] = 0;
+    count[1] = 0;
+  }
 }
 
 unsigned blocks_for(long long n) { return (unsigned)((n + ADV_BLOCK - 1) / ADV_BLOCK); }
@@ -521,9 +721,14 @@ extern "C" hipError_t ebit_launch_iface_velocity(const Dims* d, const uint8_t* f
   return hipGetLastError();
 }
 
+extern "C" size_t ebit_advect_scratch_bytes(const Dims* d) {
+  const long long E = (long long)d->n[0] * (d->n[1] + 1) + (long long)(d->n[0] + 1) * d->n[1];
+  return (size_t)(2 * E) * sizeof(double) + (size_t)(2 * E) * sizeof(int) + 4 * sizeof(int);
+}
+
 extern "C" hipError_t ebit_launch_advect(const Dims* d, double h, double dt, const double* const ug[3],
-                                         double* const mk[3], uint8_t* vcol, uint8_t* ccol, double* scratch,
-                                         int* err, hipStream_t st) {
+                                         double* const mk[3], uint8_t* vcol, uint8_t* ccol, void* scratch,
+                                         int init, int* err, hipStream_t st) {
   Adv A;
   A.nx = d->n[0];
   A.ny = d->n[1];
@@ -537,21 +742,36 @@ extern "C" hipError_t ebit_launch_advect(const Dims* d, double h, double dt, con
   A.ccol = ccol;
   A.err = err;
   const long long E0 = (long long)A.nx * (A.ny + 1), E1 = (long long)(A.nx + 1) * A.ny;
-  A.X[0] = scratch;
-  A.X[1] = scratch + E0;
-  A.Y[0] = scratch + E0 + E1;
-  A.Y[1] = scratch + 2 * E0 + E1;
-  hipLaunchKernelGGL(k_adv_clear, dim3(1), dim3(64), 0, st, err);
+  double* xy = (double*)scratch;
+  A.X[0] = xy;
+  A.X[1] = xy + E0;
+  A.Y[0] = xy + E0 + E1;
+  A.Y[1] = xy + 2 * E0 + E1;
+  int* li = (int*)(xy + 2 * (E0 + E1));
+  A.list[0] = li;
+  A.list[1] = li + (E0 + E1);
+  A.count = li + 2 * (E0 + E1);
+  // the coordinate arrays hold NaN between calls; set once per context
+  if (init) {
+    hipError_t e = ebit_launch_fill_f64(2 * (E0 + E1), xy, NAN, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adv_clear, dim3(1), dim3(64), 0, st, err, A.count);
+  const unsigned lb = blocks_for(8 * (E0 + E1)) < (unsigned)ADV_LIST_BLOCKS ? blocks_for(8 * (E0 + E1))
+                                                                             : ADV_LIST_BLOCKS;
   for (int a = 0; a < 2; ++a) {
     A.a = a;
     A.ug = ug[a];
-    const int n = a == 0 ? A.nx : A.ny;
-    const long long nal = (long long)(a == 0 ? A.ny + 1 : A.nx + 1) * (n + 1);
-    const long long nun = (long long)(a == 0 ? A.ny : A.nx) * (n + 1);
-    hipLaunchKernelGGL(k_adv_move, dim3(blocks_for(E0 + E1)), dim3(ADV_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(k_adv_aligned, dim3(blocks_for(nal)), dim3(ADV_BLOCK), 0, st, A);
-    hipLaunchKernelGGL(k_adv_unaligned, dim3(blocks_for(nun)), dim3(ADV_BLOCK), 0, st, A);
+    A.cur = a;
+    A.next = a == 0 ? 1 : -1;
+    if (a == 0)
+      hipLaunchKernelGGL(k_adv_scan, dim3(blocks_for(E0 + E1)), dim3(ADV_BLOCK), 0, st, A);
+    else
+      hipLaunchKernelGGL(k_adv_move_list, dim3(lb), dim3(ADV_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(k_adv_aligned, dim3(lb), dim3(ADV_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(k_adv_unaligned, dim3(lb), dim3(ADV_BLOCK), 0, st, A);
+    hipLaunchKernelGGL(k_adv_reset, dim3(lb), dim3(ADV_BLOCK), 0, st, A, a);
   }
-  hipLaunchKernelGGL(k_adv_colours, dim3(blocks_for((long long)A.nx * A.ny)), dim3(ADV_BLOCK), 0, st, A);
+  hipLaunchKernelGGL(k_adv_colours, dim3(lb), dim3(ADV_BLOCK), 0, st, A);
   return hipGetLastError();
 }

@@ -35,8 +35,9 @@ struct ebit_ctx {
   char* plan_mem;
   size_t plan_bytes;
   char* build_tabs;    // device tables of the hierarchy build
-  double* adv;         // 2D: marker-motion scratch (4 edge arrays)
+  void* adv;           // 2D: marker-motion scratch (edge coordinates and lists)
   int* adv_err;        // 2D: marker-motion error bits
+  int adv_ready;       // its coordinate arrays have been set to NaN
   int build_ls;        // first level built by one work-group
   hipError_t herr;
   char msg[512];
@@ -297,9 +298,8 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
   char* plan_mem = cv.take<char>(plan_bytes);
   char* build_tabs = cv.take<char>(ebit_build_table_bytes());
   // 2D marker motion: moved and fixed coordinates of every edge of both
-  // families, and the error word
-  const long long nedges = fd.dim == 2 ? (long long)fd.n[0] * (fd.n[1] + 1) + (long long)(fd.n[0] + 1) * fd.n[1] : 0;
-  double* adv = cv.take<double>(2 * nedges);
+  // families, two marker lists, and the error word
+  char* adv = cv.take<char>(fd.dim == 2 ? ebit_advect_scratch_bytes(&fd) : 0);
   int* adv_err = cv.take<int>(fd.dim == 2 ? 4 : 0);
   const size_t total = (cv.off + ALIGN - 1) / ALIGN * ALIGN;
   if (ctx) {
@@ -308,6 +308,7 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
     ctx->build_tabs = build_tabs;
     ctx->adv = adv;
     ctx->adv_err = adv_err;
+    ctx->adv_ready = 0;
     ctx->fd = fd;
     ctx->flags = flags;
     for (int a = 0; a < 3; ++a) ctx->th[a] = th[a];
@@ -793,14 +794,17 @@ ebit_status ebit_advect_markers(ebit_ctx* c, const double* const u_gamma[3], dou
   if (c->herr != hipSuccess) return EBIT_EHIP;
   if (c->fd.dim != 2) return fail(c, EBIT_EINVAL, "marker motion is two-dimensional");
   if (c->fd.n[0] < 4 || c->fd.n[1] < 4) return fail(c, EBIT_EINVAL, "marker motion needs 4 cells per axis");
+  if ((long long)c->fd.n[0] * (c->fd.n[1] + 1) + (long long)(c->fd.n[0] + 1) * c->fd.n[1] >= (1LL << 31))
+    return fail(c, EBIT_EINVAL, "marker motion needs fewer than 2^31 edges");
   if (!u_gamma || !marker || !u_gamma[0] || !u_gamma[1] || !marker[0] || !marker[1] || !vertex_colour ||
       !cell_colour)
     return fail(c, EBIT_EINVAL, "NULL argument");
   if (!(dt >= 0.0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be finite and >= 0");
   HIPCK(c,
         ebit_launch_advect(&c->fd, c->grid.h, dt, u_gamma, marker, vertex_colour, cell_colour, c->adv,
-                           c->adv_err, c->st),
+                           !c->adv_ready, c->adv_err, c->st),
         "advect");
+  c->adv_ready = 1;
   int herr = 0;
   HIPCK(c, hipMemcpyAsync(&herr, c->adv_err, sizeof(int), hipMemcpyDeviceToHost, c->st), "advect status");
   HIPCK(c, hipStreamSynchronize(c->st), "advect sync");

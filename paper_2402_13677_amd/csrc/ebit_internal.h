@@ -369,11 +369,13 @@ hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
 hipError_t ebit_launch_iface_velocity(const ebit::Dims* d, const uint8_t* flags, const double* nF,
                                       const double* const ul[3], const double* const uv[3], const double* mdot,
                                       double rho_l, double rho_v, double* const out[3], hipStream_t st);
-// 2D marker motion (x pass, y pass, cell colours).  scratch: 2 (E0 + E1)
-// doubles, E0 = nx (ny + 1), E1 = (nx + 1) ny; err: one int, cleared here.
+// 2D marker motion (x pass, y pass, cell colours).  scratch:
+// ebit_advect_scratch_bytes(d) bytes whose coordinate arrays hold NaN
+// between calls (init != 0 sets them first); err: one int, cleared here.
+size_t ebit_advect_scratch_bytes(const ebit::Dims* d);
 hipError_t ebit_launch_advect(const ebit::Dims* d, double h, double dt, const double* const ug[3],
-                              double* const mk[3], uint8_t* vcol, uint8_t* ccol, double* scratch, int* err,
-                              hipStream_t st);
+                              double* const mk[3], uint8_t* vcol, uint8_t* ccol, void* scratch, int init,
+                              int* err, hipStream_t st);
 // Hierarchy builds: host tables of the one-work-group part (2 systems,
 // ebit_build_table_bytes() bytes) are filled once and uploaded by the
 // caller; ls is the first level that part builds.

@@ -280,8 +280,8 @@ class Context:
                                                      _p3(u_gamma)), "ebit_interface_velocity")
 
     def advect_markers(self, u_gamma, markers, vcol, ccol, dt, check=True):
-        """One step of the EBIT markers (2D, x pass then y pass): markers and
-        vcol in place, ccol written; returns the status code."""
+        """One step of the EBIT markers (2D, x pass then y pass): markers,
+        vcol and ccol in place; returns the status code."""
         st = self.lib.ebit_advect_markers(self.h, _p3(u_gamma), _p3(markers), _ptr(vcol, torch.uint8),
                                           _ptr(ccol, torch.uint8), float(dt))
         if check:

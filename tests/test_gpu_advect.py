@@ -129,7 +129,7 @@ def _gpu_motion(case, ug, dt, ctx=None):
         ctx, dc = ebit.context_for(case)
     mk = [dev(m) for m in case.markers]
     vc = dev(case.vcol, torch.uint8)
-    cc = torch.full(ei.cell_shape(2, case.n), 7, dtype=torch.uint8, device="cuda")
+    cc = dev(case.ccol, torch.uint8)
     u = [dev(ug[:, a]) for a in range(2)]
     st = ctx.advect_markers(u, mk, vc, cc, dt, check=False)
     torch.cuda.synchronize()
