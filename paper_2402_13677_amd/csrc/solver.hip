@@ -2347,107 +2347,80 @@ __global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __res
   // tile coordinates of the first tile, then stepped (the scalar unit is
   // shared by the CU's waves: no division per tile)
   int bx = t0 % gx, by = (t0 / gx) % gy, k = t0 / (gx * gy);
-  // tiles in batches of U: every load of a batch is issued before its first
-  // store (the stores could alias the loads, so the compiler would otherwise
-  // wait per tile)
-  constexpr int U = 1;
-  for (int tb = t0; tb < t1; tb += U) {
-    int sbv[U], iv[U], jv[U], kv[U];
-    bool okv[U];
-    uint8_t fv[U];
-    T rcv[U], wv6[U][6];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (tb + u > t0 && ++bx == gx) {
-        bx = 0;
-        if (++by == gy) {
-          by = 0;
-          ++k;
-        }
-      }
-      const int j = by * SP_TY + wv;
-      const int par = (color + j + k) & 1;
-      const int ih = bx * SP_TX + lane;
-      const int i = 2 * ih + par;
-      const bool ok = tb + u < t1 && j < n1 && ih < hw && i < n0;
-      // a lane with no cell reads slot 0 (in range) and stores nothing
-      const int s = ok ? hw * (j + n1 * k) + ih : 0;
-      const int sb = s * TS;
-      okv[u] = ok;
-      sbv[u] = sb;
-      iv[u] = i;
-      jv[u] = j;
-      kv[u] = k;
-      fv[u] = __builtin_amdgcn_raw_buffer_load_b8(bfl, s, 0, 0);
-      rcv[u] = buf_load<T>(brv, sb);
-      if (!first) {
-        // offsets of the six neighbours (slots); a missing one loads the
-        // cell's own slot index and reads as 0 (below)
-        const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
-        const int dx0 = !ok ? 0 : xm ? (p0 ? hw - 1 : 0) : par - 1;
-        const int dx1 = !ok ? 0 : xp ? (p0 ? -ih : 0) : par;
-        const int dy0 = !ok ? 0 : ym ? (p1 ? hw * (n1 - 1) : 0) : -hw;
-        const int dy1 = !ok ? 0 : yp ? (p1 ? -hw * (n1 - 1) : 0) : hw;
-        const int dz0 = !ok ? 0 : zm ? (p2 ? plane * (n2 - 1) : 0) : -plane;
-        const int dz1 = !ok ? 0 : zp ? (p2 ? -plane * (n2 - 1) : 0) : plane;
-        wv6[u][0] = buf_load<T>(bxn, sb + dx0 * TS);
-        wv6[u][1] = buf_load<T>(bxn, sb + dx1 * TS);
-        wv6[u][2] = buf_load<T>(bxn, sb + dy0 * TS);
-        wv6[u][3] = buf_load<T>(bxn, sb + dy1 * TS);
-        wv6[u][4] = buf_load<T>(bxn, sb + dz0 * TS);
-        wv6[u][5] = buf_load<T>(bxn, sb + dz1 * TS);
+  // a wall side's neighbour offset points past the end of the half, where
+  // a buffer load reads 0 (the value a wall term takes)
+  const int Hb = (int)(H * TS);
+  for (int tb = t0; tb < t1; ++tb) {
+    if (tb > t0 && ++bx == gx) {
+      bx = 0;
+      if (++by == gy) {
+        by = 0;
+        ++k;
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!okv[u]) continue;
-      const int i = iv[u], j = jv[u], k2 = kv[u];
-      const uint8_t f = fv[u];
-      const T rc = rcv[u];
-      const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k2 == 0, zp = k2 == n2 - 1;
-      T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-      if (!first) {
-        T w[6];
-#pragma unroll
-        for (int e = 0; e < 6; ++e) w[e] = wv6[u][e];
-        if (xc) {
-          // parent cells of the neighbours on level 1 (the wrapped index on
-          // a periodic axis; any in-range cell beyond a wall)
-          const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
-          const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
-          const int km = zm ? n2 - 1 : k2 - 1, kp = zp ? 0 : k2 + 1;
-          const int pj = (j >> 1) * cn0, pk = (k2 >> 1) * cn0 * cn1;
-          const int pi = i >> 1;
-          const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
-                               pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
-                               pi + pj + (kp >> 1) * cn0 * cn1};
-          T e6[6];
-#pragma unroll
-          for (int e = 0; e < 6; ++e) e6[e] = xc[par6[e]];
-#pragma unroll
-          for (int e = 0; e < 6; ++e) w[e] += e6[e];
-        }
+    const int j = by * SP_TY + wv;
+    const int par = (color + j + k) & 1;
+    const int ih = bx * SP_TX + lane;
+    const int i = 2 * ih + par;
+    const bool ok = j < n1 && ih < hw && i < n0;
+    // lanes with no cell load whatever their offset reads (nothing is stored)
+    const int sb = (hw * (j + n1 * k) + ih) * TS;
+    const uint8_t f = __builtin_amdgcn_raw_buffer_load_b8(bfl, sb / TS, 0, 0);
+    const T rc = buf_load<T>(brv, sb);
+    const bool xm = i == 0, xp = i == n0 - 1;
+    // j and k are the wave's: the y and z cases are scalar
+    const bool ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
+    T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+    if (!first) {
+      const int dx0 = xm ? (p0 ? (hw - 1) * TS : Hb) : (par - 1) * TS;
+      const int dx1 = xp ? (p0 ? -ih * TS : Hb) : par * TS;
+      const int dy0 = ym ? (p1 ? hw * (n1 - 1) * TS : Hb) : -hw * TS;
+      const int dy1 = yp ? (p1 ? -hw * (n1 - 1) * TS : Hb) : hw * TS;
+      const int dz0 = zm ? (p2 ? plane * (n2 - 1) * TS : Hb) : -plane * TS;
+      const int dz1 = zp ? (p2 ? -plane * (n2 - 1) * TS : Hb) : plane * TS;
+      v[0] = buf_load<T>(bxn, sb + dx0);
+      v[1] = buf_load<T>(bxn, sb + dx1);
+      v[2] = buf_load<T>(bxn, sb + dy0);
+      v[3] = buf_load<T>(bxn, sb + dy1);
+      v[4] = buf_load<T>(bxn, sb + dz0);
+      v[5] = buf_load<T>(bxn, sb + dz1);
+      if (xc && ok) {
+        // parent cells of the neighbours on level 1 (the wrapped index on
+        // a periodic axis; any in-range cell beyond a wall, whose term is
+        // dropped)
+        const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
+        const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
+        const int km = zm ? n2 - 1 : k - 1, kp = zp ? 0 : k + 1;
+        const int pj = (j >> 1) * cn0, pk = (k >> 1) * cn0 * cn1;
+        const int pi = i >> 1;
+        const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
+                             pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
+                             pi + pj + (kp >> 1) * cn0 * cn1};
         const bool h[6] = {!xm || p0, !xp || p0, !ym || p1, !yp || p1, !zm || p2, !zp || p2};
+        T e6[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) v[e] = h[e] ? w[e] : (T)0;
+        for (int e = 0; e < 6; ++e) e6[e] = xc[par6[e]];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = h[e] ? v[e] + e6[e] : (T)0;
       }
-      const bool wall = (!p0 && (xm || xp)) || (!p1 && (ym || yp)) || (!p2 && (zm || zp));
-      T x;
-      if (!(f & F_CUT) && !wall) {
-        const bool liq = (f & F_LIQ) != 0;
-        T xs = (v[0] + v[1]) + (v[2] + v[3]);
-        xs += v[4] + v[5];
-        x = (rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0);
-      } else {
-        T diag, off[6], mass, rb = 0;
-        fine_row<T>(op, i, j, k2, f, diag, off, mass, rb);
-        T sum = rc - off[0] * v[0] - off[1] * v[1];
-        sum -= off[2] * v[2] + off[3] * v[3];
-        sum -= off[4] * v[4] + off[5] * v[5];
-        x = sum / diag;
-      }
-      buf_store(x, bxo, sbv[u]);
     }
+    if (!ok) continue;
+    const bool wall = (!p0 && (xm || xp)) || (!p1 && (ym || yp)) || (!p2 && (zm || zp));
+    T x;
+    if (!(f & F_CUT) && !wall) {
+      const bool liq = (f & F_LIQ) != 0;
+      T xs = (v[0] + v[1]) + (v[2] + v[3]);
+      xs += v[4] + v[5];
+      x = (rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0);
+    } else {
+      T diag, off[6], mass, rb = 0;
+      fine_row<T>(op, i, j, k, f, diag, off, mass, rb);
+      T sum = rc - off[0] * v[0] - off[1] * v[1];
+      sum -= off[2] * v[2] + off[3] * v[3];
+      sum -= off[4] * v[4] + off[5] * v[5];
+      x = sum / diag;
+    }
+    buf_store(x, bxo, sb);
   }
 }
 
