@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "ebit_internal.h"
 
@@ -45,6 +46,36 @@ struct ebit_ctx {
 
 // A batch of contexts whose solves share one plan: every kernel of a solve
 // is one launch over all cases.
+// A device table of a batched per-case launch and its host image: the table
+// is uploaded only when its content changed since the last upload.
+struct Tab {
+  char* dev;
+  char* host;
+  size_t cap, len;
+  int valid;
+};
+
+// The tables of one batch (carved after the plan's part of the batch
+// workspace).  Block offsets depend on the grids only and are uploaded at
+// creation; argument tables follow the callers' pointers.
+struct BatchTabs {
+  Tab geo, fine, small, split, heat, flux, proj, projfu, fin, scal0, scalg;
+  Tab coarse[EBIT_MAX_LEVELS];
+  int* geo_start[5];
+  int* cell_start;
+  int* red_start;
+  int* fine_start;
+  int* coarse_start[EBIT_MAX_LEVELS];
+  int* small_start;
+  int* unit_start;
+  int* split_start;
+  int geo_blocks[5], cell_blocks, red_blocks, fine_blocks, split_blocks;
+  int fine_n;
+  int coarse_n[EBIT_MAX_LEVELS], coarse_blocks[EBIT_MAX_LEVELS];
+  int ncoarse;
+  Scal* gather;  // the cases' status scalars side by side
+};
+
 struct ebit_batch {
   int n;
   ebit_ctx** ctx;
@@ -55,6 +86,7 @@ struct ebit_batch {
   size_t ws_bytes;
   hipEvent_t ev0, ev1;
   Scal* hsc;  // host copies of the contexts' status scalars
+  BatchTabs t;
   hipError_t herr;
   char msg[512];
 };
@@ -457,6 +489,139 @@ ebit_status build_finish(ebit_ctx* c, const Scal& hs, hipStream_t st) {
 void stats_init(ebit_stats* s) {
   if (!s) return;
   memset(s, 0, sizeof(*s));
+}
+
+// ---- batched per-case launches ------------------------------------------
+
+unsigned blocks_of(long long n) { return (unsigned)((n + EBIT_BLOCK - 1) / EBIT_BLOCK); }
+
+// Carve the batch tables (base == nullptr only measures); fills t when given.
+size_t batch_tabs_layout(int n, char* base, BatchTabs* t) {
+  Carver cv{base, 0};
+  BatchTabs tt;
+  memset(&tt, 0, sizeof(tt));
+  auto tab = [&](Tab& x, size_t bytes) {
+    x.dev = cv.take<char>(bytes);
+    x.cap = bytes;
+  };
+  tab(tt.geo, n * sizeof(GeoArgs));
+  tab(tt.fine, n * sizeof(BuildFineArgs));
+  for (int q = 0; q < EBIT_MAX_LEVELS; ++q) tab(tt.coarse[q], n * sizeof(BuildCoarseArgs));
+  tab(tt.small, n * sizeof(BuildSmallArgs));
+  tab(tt.split, n * sizeof(SplitArgs));
+  tab(tt.heat, n * sizeof(HeatRhsArgs));
+  tab(tt.flux, n * sizeof(FluxArgs));
+  tab(tt.proj, n * sizeof(ProjArgs));
+  tab(tt.projfu, n * sizeof(ProjArgs));
+  tab(tt.fin, n * sizeof(FinArgs));
+  tab(tt.scal0, n * sizeof(ScalArgs));
+  tab(tt.scalg, n * sizeof(ScalArgs));
+  for (int k = 0; k < 5; ++k) tt.geo_start[k] = cv.take<int>(n + 1);
+  tt.cell_start = cv.take<int>(n + 1);
+  tt.red_start = cv.take<int>(n + 1);
+  tt.fine_start = cv.take<int>(n + 1);
+  for (int q = 0; q < EBIT_MAX_LEVELS; ++q) tt.coarse_start[q] = cv.take<int>(n + 1);
+  tt.small_start = cv.take<int>(n + 1);
+  tt.unit_start = cv.take<int>(n + 1);
+  tt.split_start = cv.take<int>(n + 1);
+  tt.gather = cv.take<Scal>(n);
+  if (t) *t = tt;
+  return (cv.off + ALIGN - 1) / ALIGN * ALIGN;
+}
+
+void batch_tabs_free(ebit_batch* b) {
+  BatchTabs& t = b->t;
+  Tab* all[] = {&t.geo, &t.fine, &t.small, &t.split, &t.heat, &t.flux, &t.proj, &t.projfu, &t.fin, &t.scal0,
+                &t.scalg};
+  for (Tab* x : all) {
+    delete[] x->host;
+    x->host = nullptr;
+  }
+  for (int q = 0; q < EBIT_MAX_LEVELS; ++q) {
+    delete[] t.coarse[q].host;
+    t.coarse[q].host = nullptr;
+  }
+}
+
+// The tables' host images and the block offsets of every launch (uploaded
+// here, once: they depend on the grids only).
+bool batch_tabs_create(ebit_batch* b, char* base) {
+  const int n = b->n;
+  BatchTabs& t = b->t;
+  batch_tabs_layout(n, base, &t);
+  Tab* all[] = {&t.geo, &t.fine, &t.small, &t.split, &t.heat, &t.flux, &t.proj, &t.projfu, &t.fin, &t.scal0,
+                &t.scalg};
+  for (Tab* x : all) {
+    x->host = new (std::nothrow) char[x->cap];
+    if (!x->host) return false;
+  }
+  for (int q = 0; q < EBIT_MAX_LEVELS; ++q) {
+    t.coarse[q].host = new (std::nothrow) char[t.coarse[q].cap];
+    if (!t.coarse[q].host) return false;
+  }
+  const int stride = n + 1;
+  const int nstarts = 5 + 3 + EBIT_MAX_LEVELS + 3;
+  int* h = new (std::nothrow) int[(size_t)nstarts * stride];
+  if (!h) return false;
+  memset(h, 0, sizeof(int) * (size_t)nstarts * stride);
+  int* geo = h;                        // 5 x stride
+  int* cell = h + 5 * stride;
+  int* red = cell + stride;
+  int* fine = red + stride;
+  int* coarse = fine + stride;         // EBIT_MAX_LEVELS x stride
+  int* small = coarse + EBIT_MAX_LEVELS * stride;
+  int* unit = small + stride;
+  int* split = unit + stride;
+  t.fine_n = 0;
+  t.ncoarse = 0;
+  for (int q = 0; q < EBIT_MAX_LEVELS; ++q) t.coarse_n[q] = 0;
+  for (int c = 0; c < n; ++c) {
+    const ebit_ctx* x = b->ctx[c];
+    for (int k = 0; k < 5; ++k) geo[k * stride + c + 1] = geo[k * stride + c] + (int)ebit_geo_blocks(&x->fd, k);
+    const int cb = (int)blocks_of(x->fd.N);
+    cell[c + 1] = cell[c] + cb;
+    red[c + 1] = red[c] + (cb < EBIT_RED_BLOCKS ? cb : EBIT_RED_BLOCKS);
+    small[c + 1] = small[c] + 2;
+    unit[c + 1] = unit[c] + 1;
+    split[c + 1] = split[c] + (x->fd.dim == 3 ? (int)blocks_of(2 * split_half(x->fd)) : 0);
+    if (x->build_ls > 1 && x->nlev > 1) {
+      fine[t.fine_n + 1] = fine[t.fine_n] + 2 * (int)blocks_of(x->lv[1].d.N);
+      ++t.fine_n;
+    }
+    for (int l = 2; l < x->build_ls && l < x->nlev; ++l) {
+      const int q = l - 2;
+      int* s = coarse + q * stride;
+      s[t.coarse_n[q] + 1] = s[t.coarse_n[q]] + 2 * (int)blocks_of(x->lv[l].d.N);
+      ++t.coarse_n[q];
+      if (q + 1 > t.ncoarse) t.ncoarse = q + 1;
+    }
+  }
+  for (int k = 0; k < 5; ++k) t.geo_blocks[k] = geo[k * stride + n];
+  t.cell_blocks = cell[n];
+  t.red_blocks = red[n];
+  t.fine_blocks = fine[t.fine_n];
+  for (int q = 0; q < EBIT_MAX_LEVELS; ++q) t.coarse_blocks[q] = coarse[q * stride + t.coarse_n[q]];
+  t.split_blocks = split[n];
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 5 && e == hipSuccess; ++k)
+    e = hipMemcpy(t.geo_start[k], geo + k * stride, sizeof(int) * stride, hipMemcpyHostToDevice);
+  int* const src[] = {cell, red, fine, small, unit, split};
+  int* const dst[] = {t.cell_start, t.red_start, t.fine_start, t.small_start, t.unit_start, t.split_start};
+  for (int k = 0; k < 6 && e == hipSuccess; ++k)
+    e = hipMemcpy(dst[k], src[k], sizeof(int) * stride, hipMemcpyHostToDevice);
+  for (int q = 0; q < EBIT_MAX_LEVELS && e == hipSuccess; ++q)
+    e = hipMemcpy(t.coarse_start[q], coarse + q * stride, sizeof(int) * stride, hipMemcpyHostToDevice);
+  delete[] h;
+  return e == hipSuccess;
+}
+
+// Upload a table's new content (len bytes at src) unless it is unchanged.
+hipError_t tab_put(ebit_batch* b, Tab& x, const void* src, size_t len) {
+  if (x.valid && x.len == len && memcmp(x.host, src, len) == 0) return hipSuccess;
+  memcpy(x.host, src, len);
+  x.len = len;
+  x.valid = 1;
+  return hipMemcpyAsync(x.dev, x.host, len, hipMemcpyHostToDevice, b->st);
 }
 
 }  // namespace
@@ -876,7 +1041,7 @@ ebit_status ebit_levels(const ebit_ctx* c, int* nlevels, int* sizes) {
 size_t ebit_batch_workspace_bytes(int ncases, const ebit_opts* o) {
   if (ncases < 1) return 0;
   const size_t b = ebit_plan_device_bytes(ncases, o ? o->precision : EBIT_FP64);
-  return (b + ALIGN - 1) / ALIGN * ALIGN;
+  return (b + ALIGN - 1) / ALIGN * ALIGN + batch_tabs_layout(ncases, nullptr, nullptr);
 }
 
 ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[], void* ws, size_t bytes,
@@ -918,10 +1083,12 @@ ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[
     b->ctx[c] = ctx[c];
     pc[c] = EbitPlanCase{ctx[c]->lv, ctx[c]->nlev, ctx[c]->op, ctx[c]->B, ctx[c]->bvec};
   }
+  const size_t pb = (ebit_plan_device_bytes(ncases, b->opts.precision) + ALIGN - 1) / ALIGN * ALIGN;
   hipError_t e = hipEventCreate(&b->ev0);
   if (e == hipSuccess) e = hipEventCreate(&b->ev1);
-  if (e == hipSuccess) e = ebit_plan_create(&b->plan, ncases, pc, &b->opts, ctx[0]->B.tail_lds, ws, bytes);
+  if (e == hipSuccess) e = ebit_plan_create(&b->plan, ncases, pc, &b->opts, ctx[0]->B.tail_lds, ws, pb);
   delete[] pc;
+  if (e == hipSuccess && !batch_tabs_create(b, (char*)ws + pb)) e = hipErrorOutOfMemory;
   if (e != hipSuccess) {
     (void)hipGetLastError();
     ebit_batch_destroy(b);
@@ -933,6 +1100,7 @@ ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[
 
 ebit_status ebit_batch_destroy(ebit_batch* b) {
   if (!b) return EBIT_EINVAL;
+  batch_tabs_free(b);
   ebit_plan_destroy(b->plan);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
@@ -965,10 +1133,23 @@ ebit_status bhip(ebit_batch* b, hipError_t e, const char* where) {
     if (_e != hipSuccess) return bhip(b, _e, where);    \
   } while (0)
 
-// copy every context's status scalars to b->hsc (one synchronisation)
+// the cases' status scalars: cleared, or gathered side by side (one launch)
+ebit_status batch_scal(ebit_batch* b, bool gather) {
+  BatchTabs& t = b->t;
+  std::vector<ScalArgs> v(b->n);
+  for (int c = 0; c < b->n; ++c) v[c] = ScalArgs{b->ctx[c]->B.scal, gather ? t.gather + c : nullptr};
+  Tab& x = gather ? t.scalg : t.scal0;
+  BHIPCK(b, tab_put(b, x, v.data(), v.size() * sizeof(ScalArgs)), "status table");
+  BHIPCK(b, ebit_launch_scal_many(b->n, (const ScalArgs*)x.dev, t.unit_start, b->st), "status");
+  return EBIT_OK;
+}
+
+// copy every context's status scalars to b->hsc (one gather, one copy, one
+// synchronisation)
 ebit_status batch_read_scal(ebit_batch* b) {
-  for (int c = 0; c < b->n; ++c)
-    BHIPCK(b, hipMemcpyAsync(&b->hsc[c], b->ctx[c]->B.scal, sizeof(Scal), hipMemcpyDeviceToHost, b->st), "status");
+  ebit_status s = batch_scal(b, true);
+  if (s != EBIT_OK) return s;
+  BHIPCK(b, hipMemcpyAsync(b->hsc, b->t.gather, b->n * sizeof(Scal), hipMemcpyDeviceToHost, b->st), "status");
   BHIPCK(b, hipStreamSynchronize(b->st), "sync");
   return EBIT_OK;
 }
@@ -1018,16 +1199,67 @@ ebit_status ebit_batch_build_coeffs(ebit_batch* b, const double* const marker[],
       if (!marker[3 * c + a]) return bfail(b, EBIT_EINVAL, c, "NULL marker array");
     if (!(dt[c] > 0) || !isfinite(dt[c])) return bfail(b, EBIT_EINVAL, c, "dt must be positive");
   }
-  for (int c = 0; c < b->n; ++c) {
-    const ebit_status s = build_launch(b->ctx[c], marker + 3 * c, vcol[c], ccol[c], dt[c], b->st);
-    if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
+  const int n = b->n;
+  BatchTabs& t = b->t;
+  const int dim = b->ctx[0]->fd.dim;
+  const int want32 = b->opts.precision == EBIT_MIXED;
+  std::vector<GeoArgs> geo(n);
+  std::vector<BuildFineArgs> fine(t.fine_n > 0 ? t.fine_n : 1);
+  std::vector<BuildCoarseArgs> coarse((size_t)EBIT_MAX_LEVELS * n);
+  std::vector<BuildSmallArgs> small(n);
+  std::vector<SplitArgs> split(n);
+  int nf = 0, nc[EBIT_MAX_LEVELS] = {0};
+  for (int c = 0; c < n; ++c) {
+    ebit_ctx* x = b->ctx[c];
+    x->built = 0;
+    x->dt = dt[c];
+    set_ops(x);
+    ebit_geo_args(&geo[c], &x->fd, x->grid.h, marker + 3 * c, vcol[c], ccol[c], x->flags, x->cF, x->nF, x->th,
+                  x->B.scal);
+    BuildFineArgs f;
+    BuildCoarseArgs cl[EBIT_MAX_LEVELS];
+    const int ncl = ebit_build_args(x->op, x->lv, x->nlev, want32, x->build_ls, &f, cl);
+    if (x->build_ls > 1 && x->nlev > 1) fine[nf++] = f;
+    for (int q = 0; q < ncl; ++q) coarse[(size_t)q * n + nc[q]++] = cl[q];
+    small[c].tabs = x->build_tabs;
+    split[c] = SplitArgs{x->fd, x->flags, x->B.fsplit};
   }
-  ebit_status s = batch_read_scal(b);
+  // the geometry of every case, then its status
+  ebit_status s = batch_scal(b, false);
   if (s != EBIT_OK) return s;
-  for (int c = 0; c < b->n; ++c) {
-    s = build_finish(b->ctx[c], b->hsc[c], b->st);
+  BHIPCK(b, tab_put(b, t.geo, geo.data(), n * sizeof(GeoArgs)), "geometry table");
+  const int* gs[5] = {t.geo_start[0], t.geo_start[1], t.geo_start[2], t.geo_start[3], t.geo_start[4]};
+  BHIPCK(b, ebit_launch_geometry_many(n, dim, (const GeoArgs*)t.geo.dev, gs, t.geo_blocks, b->st), "geometry");
+  // the hierarchies (every index stays in range whatever the geometry)
+  if (nf > 0) {
+    BHIPCK(b, tab_put(b, t.fine, fine.data(), nf * sizeof(BuildFineArgs)), "build table");
+    BHIPCK(b, ebit_launch_build_fine_many(nf, (const BuildFineArgs*)t.fine.dev, t.fine_start, t.fine_blocks, b->st),
+           "hierarchy");
+  }
+  for (int q = 0; q < t.ncoarse; ++q) {
+    if (!nc[q]) continue;
+    BHIPCK(b, tab_put(b, t.coarse[q], &coarse[(size_t)q * n], nc[q] * sizeof(BuildCoarseArgs)), "build table");
+    BHIPCK(b,
+           ebit_launch_build_coarse_many(nc[q], dim, (const BuildCoarseArgs*)t.coarse[q].dev, t.coarse_start[q],
+                                         t.coarse_blocks[q], b->st),
+           "hierarchy");
+  }
+  BHIPCK(b, tab_put(b, t.small, small.data(), n * sizeof(BuildSmallArgs)), "build table");
+  BHIPCK(b, ebit_launch_build_small_many(n, dim, (const BuildSmallArgs*)t.small.dev, t.small_start, b->st),
+         "hierarchy");
+  if (dim == 3) {
+    BHIPCK(b, tab_put(b, t.split, split.data(), n * sizeof(SplitArgs)), "split table");
+    BHIPCK(b,
+           ebit_launch_split_flags_many(n, (const SplitArgs*)t.split.dev, t.split_start, t.split_blocks, b->st),
+           "split flags");
+  }
+  s = batch_read_scal(b);
+  if (s != EBIT_OK) return s;
+  for (int c = 0; c < n; ++c) {
+    s = geometry_check(b->ctx[c], b->hsc[c]);
     if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
   }
+  for (int c = 0; c < n; ++c) b->ctx[c]->built = 1;
   return EBIT_OK;
 }
 
@@ -1039,8 +1271,15 @@ ebit_status ebit_batch_heat_solve(ebit_batch* b, const double* const T_star[], d
   for (int c = 0; c < b->n; ++c)
     if (!T_star[c] || !T[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
   BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
-  for (int c = 0; c < b->n; ++c)
-    BHIPCK(b, ebit_launch_heat_rhs(&b->ctx[c]->op[EBIT_SYS_HEAT], T_star[c], b->ctx[c]->bvec, b->st), "heat rhs");
+  {
+    std::vector<HeatRhsArgs> v(b->n);
+    for (int c = 0; c < b->n; ++c) v[c] = HeatRhsArgs{b->ctx[c]->op[EBIT_SYS_HEAT], T_star[c], b->ctx[c]->bvec};
+    BHIPCK(b, tab_put(b, b->t.heat, v.data(), v.size() * sizeof(HeatRhsArgs)), "heat table");
+    BHIPCK(b,
+           ebit_launch_heat_rhs_many(b->n, (const HeatRhsArgs*)b->t.heat.dev, b->t.cell_start, b->t.cell_blocks,
+                                     b->st),
+           "heat rhs");
+  }
   EbitSolveOut* r = new (std::nothrow) EbitSolveOut[b->n];
   if (!r) return EBIT_ENOMEM;
   const hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_HEAT, T, use_guess, b->st, nullptr, r);
@@ -1063,14 +1302,20 @@ ebit_status ebit_batch_mass_flux(ebit_batch* b, const double* const T[], double*
   for (int c = 0; c < b->n; ++c)
     if (!T[c] || !mdot[c]) return bfail(b, EBIT_EINVAL, c, "NULL field");
   BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
-  for (int c = 0; c < b->n; ++c) {
-    ebit_ctx* x = b->ctx[c];
-    BHIPCK(b, ebit_launch_fill_f64((long long)(sizeof(Scal) / sizeof(double)), (double*)x->B.scal, 0.0, b->st),
-           "reset");
-    const double lam[2] = {x->props.lam_v, x->props.lam_l};
+  s = batch_scal(b, false);
+  if (s != EBIT_OK) return s;
+  {
+    std::vector<FluxArgs> v(b->n);
+    for (int c = 0; c < b->n; ++c) {
+      ebit_ctx* x = b->ctx[c];
+      const double lam[2] = {x->props.lam_v, x->props.lam_l};
+      ebit_flux_args(&v[c], &x->fd, x->grid.h, lam, x->props.h_lg, x->props.T_sat, x->opts.theta_min, x->flags,
+                     x->th, x->cF, x->nF, T[c], mdot[c], nullptr, x->B.scal);
+    }
+    BHIPCK(b, tab_put(b, b->t.flux, v.data(), v.size() * sizeof(FluxArgs)), "flux table");
     BHIPCK(b,
-           ebit_launch_mass_flux(&x->fd, x->grid.h, lam, x->props.h_lg, x->props.T_sat, x->opts.theta_min, x->flags,
-                                 x->th, x->cF, x->nF, T[c], mdot[c], nullptr, x->B.scal, b->st),
+           ebit_launch_mass_flux_many(b->n, b->ctx[0]->fd.dim, (const FluxArgs*)b->t.flux.dev, b->t.cell_start,
+                                      b->t.cell_blocks, b->st),
            "mass flux");
   }
   // without stats the call does not wait for the device
@@ -1100,12 +1345,17 @@ ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const
       if (!u_l[3 * c + a] || !u_v[3 * c + a]) return bfail(b, EBIT_EINVAL, c, "NULL velocity array");
   }
   BHIPCK(b, hipEventRecord(b->ev0, b->st), "event");
-  for (int c = 0; c < b->n; ++c) {
-    ebit_ctx* x = b->ctx[c];
-    const double rho[2] = {x->props.rho_v, x->props.rho_l};
+  {
+    std::vector<ProjArgs> v(b->n);
+    for (int c = 0; c < b->n; ++c) {
+      ebit_ctx* x = b->ctx[c];
+      const double rho[2] = {x->props.rho_v, x->props.rho_l};
+      ebit_proj_args(&v[c], &x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val, x->flags, x->th, x->nF,
+                     mdot[c], u_l + 3 * c, u_v + 3 * c, nullptr, x->bvec, nullptr);
+    }
+    BHIPCK(b, tab_put(b, b->t.proj, v.data(), v.size() * sizeof(ProjArgs)), "projection table");
     BHIPCK(b,
-           ebit_launch_proj_rhs(&x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val, x->flags, x->th, x->nF,
-                                mdot[c], u_l + 3 * c, u_v + 3 * c, x->bvec, b->st),
+           ebit_launch_proj_rhs_many(b->n, (const ProjArgs*)b->t.proj.dev, b->t.cell_start, b->t.cell_blocks, b->st),
            "projection rhs");
   }
   EbitSolveOut* r = new (std::nothrow) EbitSolveOut[b->n];
@@ -1115,12 +1365,23 @@ ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const
     delete[] r;
     return bhip(b, e, "solve");
   }
-  for (int c = 0; c < b->n; ++c) {
-    ebit_ctx* x = b->ctx[c];
-    const double rho[2] = {x->props.rho_v, x->props.rho_l};
-    const hipError_t e2 = ebit_launch_face_update(&x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val,
-                                                  x->flags, x->th, u_l + 3 * c, u_v + 3 * c, p[c], x->B.partial,
-                                                  x->B.scal, b->st);
+  {
+    std::vector<ProjArgs> v(b->n);
+    std::vector<FinArgs> fv(b->n);
+    for (int c = 0; c < b->n; ++c) {
+      ebit_ctx* x = b->ctx[c];
+      const double rho[2] = {x->props.rho_v, x->props.rho_l};
+      ebit_proj_args(&v[c], &x->fd, x->grid.h, rho, x->dt, x->grid.p_bc, x->grid.p_val, x->flags, x->th, nullptr,
+                     nullptr, u_l + 3 * c, u_v + 3 * c, p[c], nullptr, x->B.partial);
+      const int cb = (int)blocks_of(x->fd.N);
+      fv[c] = FinArgs{x->B.partial, cb < EBIT_RED_BLOCKS ? cb : EBIT_RED_BLOCKS, 1, FIN_MAX, x->B.scal};
+    }
+    hipError_t e2 = tab_put(b, b->t.projfu, v.data(), v.size() * sizeof(ProjArgs));
+    if (e2 == hipSuccess) e2 = tab_put(b, b->t.fin, fv.data(), fv.size() * sizeof(FinArgs));
+    if (e2 == hipSuccess)
+      e2 = ebit_launch_face_update_many(b->n, (const ProjArgs*)b->t.projfu.dev, b->t.cell_start, b->t.cell_blocks,
+                                        b->t.red_start, b->t.red_blocks, b->st);
+    if (e2 == hipSuccess) e2 = ebit_launch_finalize_many(b->n, (const FinArgs*)b->t.fin.dev, b->t.unit_start, b->st);
     if (e2 != hipSuccess) {
       delete[] r;
       return bhip(b, e2, "face update");

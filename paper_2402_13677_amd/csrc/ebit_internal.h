@@ -7,6 +7,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <string.h>
 #include <stdint.h>
 
 #include "ebit.h"
@@ -223,6 +224,170 @@ __device__ inline void cell_ijk(const Dims& d, long long c, int& i, int& j, int&
   k = (int)(c / ((long long)d.n[0] * d.n[1]));
 }
 
+// ---------------------------------------------------------------------------
+// Arguments of the per-case kernels outside the solves, and their launch over
+// many cases: case e of a batch owns the blocks start[e] .. start[e+1]-1 of
+// the grid (start[n] = the grid).  A single-case launch passes n = 0 and
+// its arguments in `one`; a batch passes a device table of n entries.
+// ---------------------------------------------------------------------------
+template <typename A>
+struct Many {
+  A one;
+  const A* tab;
+  const int* start;
+  int n;
+};
+
+// The block's case arguments, its block index within the case and the
+// case's block count.
+template <typename A>
+__device__ inline A many_case(const Many<A>& m, long long& lb, long long& nb) {
+  if (m.n == 0) {
+    lb = blockIdx.x;
+    nb = gridDim.x;
+    return m.one;
+  }
+  const int b = blockIdx.x;
+  int lo = 0, hi = m.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (m.start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  lb = b - m.start[lo];
+  nb = m.start[lo + 1] - m.start[lo];
+  return m.tab[lo];
+}
+
+template <typename A>
+inline Many<A> many_one(const A& a) {
+  Many<A> m;
+  m.one = a;
+  m.tab = nullptr;
+  m.start = nullptr;
+  m.n = 0;
+  return m;
+}
+
+template <typename A>
+inline Many<A> many_tab(const A* tab, const int* start, int n) {
+  Many<A> m;
+  memset(&m.one, 0, sizeof(A));
+  m.tab = tab;
+  m.start = start;
+  m.n = n;
+  return m;
+}
+
+struct GeoArgs {
+  Dims d;
+  double h;
+  const double* mk[3];
+  const uint8_t* vcol;
+  const uint8_t* ccol;
+  uint8_t* flags;
+  double* cF;  // [3][N]
+  double* nF;  // [3][N]
+  double* th[3];
+  Scal* scal;
+};
+
+struct FluxArgs {
+  Dims d;
+  double h;
+  double lam[2];  // [vapour, liquid]
+  double h_lg, Tsat, theta_min;
+  const uint8_t* flags;
+  const double* th[3];
+  const double* cF;  // [3][N]
+  const double* nF;
+  const double* T;
+  double* mdot;
+  double* mface[3];
+  Scal* scal;
+};
+
+struct ProjArgs {
+  Dims d;
+  double h;
+  double jump;  // [1/rho] = 1/rho_l - 1/rho_v
+  double rho[2];
+  double dt;
+  int pbc[6];
+  double pval[6];
+  const uint8_t* flags;
+  const double* th[3];
+  const double* nF;
+  const double* mdot;
+  double* ul[3];
+  double* uv[3];
+  const double* p;
+  double* b;
+  double* partial;
+  // one-fluid mode: the single field is ul; cF and the source factor
+  // (1/rho_v - 1/rho_l) / h^d serve the interface cells' volume source
+  int one;
+  const double* cF;
+  double src;
+};
+
+struct BuildOut {
+  Dims cd;
+  double* diag;
+  double* mass;
+  double* off[3];
+  float* d32;     // FP32 copies of diag and off (null: none)
+  float* o32[3];
+  float* i32;     // the level's block of the FP32 or FP64 tail image (null: none)
+  double* i64;
+};
+
+// heat right-hand side of one case
+struct HeatRhsArgs {
+  FineOp op;
+  const double* Ts;
+  double* b;
+};
+
+// finalize kinds
+enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5, FIN_START = 6, FIN_PEND = 7 };
+
+// a single-block reduction of a case's partials into its status scalars
+struct FinArgs {
+  const double* partial;
+  int nb, nv, kind;
+  Scal* sc;
+};
+
+// one hierarchy level of both systems of a case: from the fine operator
+// (level 1) or from the level above
+struct BuildFineArgs {
+  FineOp op[2];
+  BuildOut o[2];
+  unsigned nb;
+};
+struct BuildCoarseArgs {
+  CoarseOp<double> op[2];
+  BuildOut o[2];
+  unsigned nb;
+};
+// the one-work-group part of a case's build: its two device tables
+struct BuildSmallArgs {
+  const void* tabs;
+};
+struct SplitArgs {
+  Dims d;
+  const uint8_t* flags;
+  uint8_t* fs;
+};
+// a case's status scalars: cleared, or copied into a gathered array
+struct ScalArgs {
+  Scal* scal;
+  Scal* dst;
+};
+
 // Neighbour of (i, j, k) at offsets (di, dj, dk): false beyond a wall,
 // periodic axes wrap.
 __device__ inline bool nbr_cell(const Dims& d, int i, int j, int k, int di, int dj, int dk, long long& m) {
@@ -365,6 +530,41 @@ hipError_t ebit_launch_extend(const ebit::Dims* d, int mode, int iters, const ui
                               double* q, double* work, uint8_t* bytes, unsigned long long* list,
                               double* const w[3], int* counter, hipStream_t st);
 hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
+// Batched (many-case) forms of the per-case kernels: a device table of
+// arguments and n + 1 block offsets (start) per launch.
+void ebit_geo_args(ebit::GeoArgs* g, const ebit::Dims* d, double h, const double* const mk[3], const uint8_t* vcol,
+                   const uint8_t* ccol, uint8_t* flags, double* cF, double* nF, double* const th[3],
+                   ebit::Scal* scal);
+long long ebit_geo_blocks(const ebit::Dims* d, int kind);
+hipError_t ebit_launch_geometry_many(int n, int dim, const ebit::GeoArgs* tab, const int* const start[5],
+                                     const int blocks[5], hipStream_t st);
+void ebit_flux_args(ebit::FluxArgs* g, const ebit::Dims* d, double h, const double lam[2], double h_lg, double Tsat,
+                    double theta_min, const uint8_t* flags, const double* const th[3], const double* cF,
+                    const double* nF, const double* T, double* mdot, double* const mface[3], ebit::Scal* scal);
+hipError_t ebit_launch_mass_flux_many(int n, int dim, const ebit::FluxArgs* tab, const int* start, int blocks,
+                                      hipStream_t st);
+void ebit_proj_args(ebit::ProjArgs* g, const ebit::Dims* d, double h, const double rho[2], double dt,
+                    const int pbc[6], const double pval[6], const uint8_t* flags, const double* const th[3],
+                    const double* nF, const double* mdot, double* const ul[3], double* const uv[3],
+                    const double* p, double* b, double* partial);
+hipError_t ebit_launch_proj_rhs_many(int n, const ebit::ProjArgs* tab, const int* start, int blocks,
+                                     hipStream_t st);
+hipError_t ebit_launch_face_update_many(int n, const ebit::ProjArgs* tab, const int* start, int blocks,
+                                        const int* rstart, int rblocks, hipStream_t st);
+int ebit_build_args(const ebit::FineOp* op, const EbitLevelHost* lv, int nlev, int want32, int ls,
+                    ebit::BuildFineArgs* fine, ebit::BuildCoarseArgs* coarse);
+hipError_t ebit_launch_build_fine_many(int n, const ebit::BuildFineArgs* tab, const int* start, int blocks,
+                                       hipStream_t st);
+hipError_t ebit_launch_build_coarse_many(int n, int dim, const ebit::BuildCoarseArgs* tab, const int* start,
+                                         int blocks, hipStream_t st);
+hipError_t ebit_launch_build_small_many(int n, int dim, const ebit::BuildSmallArgs* tab, const int* start,
+                                        hipStream_t st);
+hipError_t ebit_launch_heat_rhs_many(int n, const ebit::HeatRhsArgs* tab, const int* start, int blocks,
+                                     hipStream_t st);
+hipError_t ebit_launch_finalize_many(int n, const ebit::FinArgs* tab, const int* start, hipStream_t st);
+hipError_t ebit_launch_scal_many(int n, const ebit::ScalArgs* tab, const int* start, hipStream_t st);
+hipError_t ebit_launch_split_flags_many(int n, const ebit::SplitArgs* tab, const int* start, int blocks,
+                                        hipStream_t st);
 // Interfacial velocity at the cell centres (out[a], a < dim).
 hipError_t ebit_launch_iface_velocity(const ebit::Dims* d, const uint8_t* flags, const double* nF,
                                       const double* const ul[3], const double* const uv[3], const double* mdot,

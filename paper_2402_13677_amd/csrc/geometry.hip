@@ -11,19 +11,6 @@
 
 namespace ebit {
 
-struct GeoArgs {
-  Dims d;
-  double h;
-  const double* mk[3];
-  const uint8_t* vcol;
-  const uint8_t* ccol;
-  uint8_t* flags;
-  double* cF;  // [3][N]
-  double* nF;  // [3][N]
-  double* th[3];
-  Scal* scal;
-};
-
 __host__ __device__ inline int nvz_of(const Dims& d) { return d.dim == 3 ? d.n[2] + 1 : 1; }
 
 __device__ inline long long vidx(const Dims& d, int i, int j, int k) {
@@ -38,12 +25,14 @@ __device__ inline long long eidx(const Dims& d, int a, int i, int j, int k) {
 }
 
 // Marker present <=> end colours differ; s in [0, 1]; periodic seams agree.
-__global__ void k_check_markers(GeoArgs g, int a) {
+__global__ void k_check_markers(Many<GeoArgs> m, int a) {
+  long long lb, nb;
+  const GeoArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
   const int ex = d.n[0] + (a == 0 ? 0 : 1);
   const int ey = d.n[1] + (a == 1 ? 0 : 1);
   const int ez = (d.dim == 3) ? d.n[2] + (a == 2 ? 0 : 1) : 1;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = lb * blockDim.x + threadIdx.x;
   if (t >= (long long)ex * ey * ez) return;
   const int i = (int)(t % ex);
   const int j = (int)((t / ex) % ey);
@@ -70,10 +59,12 @@ __global__ void k_check_markers(GeoArgs g, int a) {
   if (bad) atomicOr(&g.scal->err, bad);
 }
 
-__global__ void k_check_seam_vertices(GeoArgs g) {
+__global__ void k_check_seam_vertices(Many<GeoArgs> m) {
+  long long lb, nb;
+  const GeoArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
   const int vx = d.n[0] + 1, vy = d.n[1] + 1, vz = nvz_of(d);
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = lb * blockDim.x + threadIdx.x;
   if (t >= (long long)vx * vy * vz) return;
   const int i = (int)(t % vx);
   const int j = (int)((t / vx) % vy);
@@ -163,9 +154,11 @@ __device__ inline void slot_corner(int a, int o, int i, int j, int k, int dim, i
 // The markers of the cell's edges are gathered into slot a * 4 + o (NaN: no
 // marker, or no such slot) with every index known at compile time, so a
 // cell without markers (almost all of them) finishes from registers.
-__global__ void k_facets(GeoArgs g) {
+__global__ void k_facets(Many<GeoArgs> m) {
+  long long lb, nb;
+  const GeoArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
   int i, j, k;
   cell_ijk(d, c, i, j, k);
@@ -380,9 +373,11 @@ __device__ inline bool link_theta(const GeoArgs& g, int a, int li, int lj, int l
 }
 
 // Cut bits of every side, and theta on the + faces (and face 0 of each axis).
-__global__ void k_theta_flags(GeoArgs g) {
+__global__ void k_theta_flags(Many<GeoArgs> m) {
+  long long lb, nb;
+  const GeoArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
   const int i = (int)(c % d.n[0]);
   const int j = (int)((c / d.n[0]) % d.n[1]);
@@ -424,29 +419,62 @@ extern "C" hipError_t ebit_launch_geometry(const Dims* d, double h, const double
                                            double* cF, double* nF, double* const th[3], Scal* scal,
                                            hipStream_t st) {
   GeoArgs g;
-  g.d = *d;
-  g.h = h;
+  ebit_geo_args(&g, d, h, mk, vcol, ccol, flags, cF, nF, th, scal);
+  const Many<GeoArgs> m = many_one(g);
+  for (int a = 0; a < d->dim; ++a)
+    hipLaunchKernelGGL(k_check_markers, dim3((unsigned)ebit_geo_blocks(d, a)), dim3(EBIT_BLOCK), 0, st, m, a);
+  hipLaunchKernelGGL(k_check_seam_vertices, dim3((unsigned)ebit_geo_blocks(d, 3)), dim3(EBIT_BLOCK), 0, st, m);
+  const unsigned nb = (unsigned)ebit_geo_blocks(d, 4);
+  hipLaunchKernelGGL(k_facets, dim3(nb), dim3(EBIT_BLOCK), 0, st, m);
+  hipLaunchKernelGGL(k_theta_flags, dim3(nb), dim3(EBIT_BLOCK), 0, st, m);
+  return hipGetLastError();
+}
+
+extern "C" void ebit_geo_args(GeoArgs* g, const Dims* d, double h, const double* const mk[3], const uint8_t* vcol,
+                              const uint8_t* ccol, uint8_t* flags, double* cF, double* nF, double* const th[3],
+                              Scal* scal) {
+  memset(g, 0, sizeof(*g));
+  g->d = *d;
+  g->h = h;
   for (int a = 0; a < 3; ++a) {
-    g.mk[a] = (a < d->dim) ? mk[a] : nullptr;
-    g.th[a] = (a < d->dim) ? th[a] : nullptr;
+    g->mk[a] = (a < d->dim) ? mk[a] : nullptr;
+    g->th[a] = (a < d->dim) ? th[a] : nullptr;
   }
-  g.vcol = vcol;
-  g.ccol = ccol;
-  g.flags = flags;
-  g.cF = cF;
-  g.nF = nF;
-  g.scal = scal;
-  for (int a = 0; a < d->dim; ++a) {
-    const long long ne = (long long)(d->n[0] + (a == 0 ? 0 : 1)) * (d->n[1] + (a == 1 ? 0 : 1)) *
-                         ((d->dim == 3) ? d->n[2] + (a == 2 ? 0 : 1) : 1);
-    hipLaunchKernelGGL(k_check_markers, dim3((unsigned)((ne + EBIT_BLOCK - 1) / EBIT_BLOCK)),
-                       dim3(EBIT_BLOCK), 0, st, g, a);
-  }
-  const long long nv = (long long)(d->n[0] + 1) * (d->n[1] + 1) * nvz_of(*d);
-  hipLaunchKernelGGL(k_check_seam_vertices, dim3((unsigned)((nv + EBIT_BLOCK - 1) / EBIT_BLOCK)),
-                     dim3(EBIT_BLOCK), 0, st, g);
-  const unsigned nb = (unsigned)((d->N + EBIT_BLOCK - 1) / EBIT_BLOCK);
-  hipLaunchKernelGGL(k_facets, dim3(nb), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_theta_flags, dim3(nb), dim3(EBIT_BLOCK), 0, st, g);
+  g->vcol = vcol;
+  g->ccol = ccol;
+  g->flags = flags;
+  g->cF = cF;
+  g->nF = nF;
+  g->scal = scal;
+}
+
+// Blocks of the geometry pass's index spaces: the axis-a edges (kind a < 3),
+// the vertices (3), the cells (4).
+extern "C" long long ebit_geo_blocks(const Dims* d, int kind) {
+  long long n;
+  if (kind < 3)
+    n = kind >= d->dim ? 0
+                       : (long long)(d->n[0] + (kind == 0 ? 0 : 1)) * (d->n[1] + (kind == 1 ? 0 : 1)) *
+                             ((d->dim == 3) ? d->n[2] + (kind == 2 ? 0 : 1) : 1);
+  else if (kind == 3)
+    n = (long long)(d->n[0] + 1) * (d->n[1] + 1) * nvz_of(*d);
+  else
+    n = d->N;
+  return (n + EBIT_BLOCK - 1) / EBIT_BLOCK;
+}
+
+// The geometry pass of n cases in one launch per kernel: tab (device, n
+// entries), start[kind] (device, n + 1 block offsets for each index space)
+// and blocks[kind] (their totals).
+extern "C" hipError_t ebit_launch_geometry_many(int n, int dim, const GeoArgs* tab, const int* const start[5],
+                                                const int blocks[5], hipStream_t st) {
+  for (int a = 0; a < dim; ++a)
+    hipLaunchKernelGGL(k_check_markers, dim3((unsigned)blocks[a]), dim3(EBIT_BLOCK), 0, st,
+                       many_tab(tab, start[a], n), a);
+  hipLaunchKernelGGL(k_check_seam_vertices, dim3((unsigned)blocks[3]), dim3(EBIT_BLOCK), 0, st,
+                     many_tab(tab, start[3], n));
+  hipLaunchKernelGGL(k_facets, dim3((unsigned)blocks[4]), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start[4], n));
+  hipLaunchKernelGGL(k_theta_flags, dim3((unsigned)blocks[4]), dim3(EBIT_BLOCK), 0, st,
+                     many_tab(tab, start[4], n));
   return hipGetLastError();
 }

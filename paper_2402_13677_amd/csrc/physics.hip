@@ -16,21 +16,6 @@
 
 namespace ebit {
 
-struct FluxArgs {
-  Dims d;
-  double h;
-  double lam[2];  // [vapour, liquid]
-  double h_lg, Tsat, theta_min;
-  const uint8_t* flags;
-  const double* th[3];
-  const double* cF;  // [3][N]
-  const double* nF;
-  const double* T;
-  double* mdot;
-  double* mface[3];
-  Scal* scal;
-};
-
 // T of phase k at cell (i,j,k) (periodic wrap), from the cell itself or its
 // ghost value (mean of Eq. ghost_T over its cut links); false if unavailable.
 template <int DIM>
@@ -191,9 +176,11 @@ __device__ inline double fallback_grad(const FluxArgs& g, int kph, const double 
 }
 
 template <int DIM>
-__global__ void k_mass_flux(FluxArgs g) {
+__global__ void k_mass_flux(Many<FluxArgs> m) {
+  long long lb, nb;
+  const FluxArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
   const uint8_t f = g.flags[c];
   if (!(f & F_IF)) {
@@ -266,30 +253,6 @@ __global__ void k_mass_flux_faces(FluxArgs g) {
 // ---------------------------------------------------------------------------
 // projection
 // ---------------------------------------------------------------------------
-struct ProjArgs {
-  Dims d;
-  double h;
-  double jump;  // [1/rho] = 1/rho_l - 1/rho_v
-  double rho[2];
-  double dt;
-  int pbc[6];
-  double pval[6];
-  const uint8_t* flags;
-  const double* th[3];
-  const double* nF;
-  const double* mdot;
-  double* ul[3];
-  double* uv[3];
-  const double* p;
-  double* b;
-  double* partial;
-  // one-fluid mode: the single field is ul; cF and the source factor
-  // (1/rho_v - 1/rho_l) / h^d serve the interface cells' volume source
-  int one;
-  const double* cF;
-  double src;
-};
-
 // Area (3D) or length (2D) of the facet plane of interface cell (i, j, k)
 // clipped to the cell.  The plane meets the cell's edges (strict sign
 // change of the signed distance) and corners (distance zero) in the
@@ -408,9 +371,11 @@ __device__ inline double one_fluid_source(const ProjArgs& g, int i, int j, int k
 
 // Ghost value on every cut face (Eq. ghost_velocity).  Each cell handles its
 // + faces and, on the first layer, face 0 (the periodic copy of face n).
-__global__ void k_ghost_vel(ProjArgs g) {
+__global__ void k_ghost_vel(Many<ProjArgs> m) {
+  long long lb, nb;
+  const ProjArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
   int i, j, k;
   cell_ijk(d, c, i, j, k);
@@ -440,9 +405,11 @@ __global__ void k_ghost_vel(ProjArgs g) {
 
 // b = bc - div_c u_{k(c)}  (right-hand side of the SPD system -L p = b)
 template <bool ONE>
-__global__ void k_proj_rhs(ProjArgs g) {
+__global__ void k_proj_rhs(Many<ProjArgs> m) {
+  long long lb, nb;
+  const ProjArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
   int i, j, k;
   cell_ijk(d, c, i, j, k);
@@ -500,9 +467,11 @@ __device__ inline bool face_grad(const ProjArgs& g, int i, int j, int k, long lo
 
 // u <- u - beta_f grad p on both fields; each cell writes its + faces and, on
 // the first layer, face 0 (so every face is written exactly once).
-__global__ void k_face_update(ProjArgs g) {
+__global__ void k_face_update(Many<ProjArgs> m) {
+  long long lb, nb;
+  const ProjArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
   int i, j, k;
   cell_ijk(d, c, i, j, k);
@@ -522,11 +491,12 @@ __global__ void k_face_update(ProjArgs g) {
 // max_c |div_c u_{k(c)}| of the updated fields (a separate pass: every face
 // is final when it is read)
 template <bool ONE>
-__global__ void k_divmax(ProjArgs g) {
+__global__ void k_divmax(Many<ProjArgs> m) {
+  long long lb, nb;
+  const ProjArgs g = many_case(m, lb, nb);
   const Dims& d = g.d;
   double vmax = 0.0;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < d.N;
-       c += (long long)gridDim.x * blockDim.x) {
+  for (long long c = lb * blockDim.x + threadIdx.x; c < d.N; c += nb * blockDim.x) {
     int i, j, k;
     cell_ijk(d, c, i, j, k);
     const int ph = (g.flags[c] & F_LIQ) ? 1 : 0;
@@ -541,10 +511,10 @@ __global__ void k_divmax(ProjArgs g) {
   }
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double m = wave_max(vmax);
-  if (lane == 0) sh[w] = m;
+  const double wm = wave_max(vmax);
+  if (lane == 0) sh[w] = wm;
   __syncthreads();
-  if (threadIdx.x == 0) g.partial[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  if (threadIdx.x == 0) g.partial[lb] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
 static inline unsigned nblk(long long n) { return (unsigned)((n + EBIT_BLOCK - 1) / EBIT_BLOCK); }
@@ -553,34 +523,83 @@ static inline unsigned nblk(long long n) { return (unsigned)((n + EBIT_BLOCK - 1
 
 using namespace ebit;
 
+extern "C" void ebit_flux_args(FluxArgs* g, const Dims* d, double h, const double lam[2], double h_lg, double Tsat,
+                               double theta_min, const uint8_t* flags, const double* const th[3], const double* cF,
+                               const double* nF, const double* T, double* mdot, double* const mface[3], Scal* scal) {
+  memset(g, 0, sizeof(*g));
+  g->d = *d;
+  g->h = h;
+  g->lam[0] = lam[0];
+  g->lam[1] = lam[1];
+  g->h_lg = h_lg;
+  g->Tsat = Tsat;
+  g->theta_min = theta_min;
+  g->flags = flags;
+  for (int a = 0; a < 3; ++a) {
+    g->th[a] = (a < d->dim) ? th[a] : nullptr;
+    g->mface[a] = (mface && a < d->dim) ? mface[a] : nullptr;
+  }
+  g->cF = cF;
+  g->nF = nF;
+  g->T = T;
+  g->mdot = mdot;
+  g->scal = scal;
+}
+
 extern "C" hipError_t ebit_launch_mass_flux(const Dims* d, double h, const double lam[2], double h_lg, double Tsat,
                                             double theta_min, const uint8_t* flags, const double* const th[3],
                                             const double* cF, const double* nF, const double* T, double* mdot,
                                             double* const mface[3], Scal* scal, hipStream_t st) {
   FluxArgs g;
-  g.d = *d;
-  g.h = h;
-  g.lam[0] = lam[0];
-  g.lam[1] = lam[1];
-  g.h_lg = h_lg;
-  g.Tsat = Tsat;
-  g.theta_min = theta_min;
-  g.flags = flags;
-  for (int a = 0; a < 3; ++a) {
-    g.th[a] = (a < d->dim) ? th[a] : nullptr;
-    g.mface[a] = (mface && a < d->dim) ? mface[a] : nullptr;
-  }
-  g.cF = cF;
-  g.nF = nF;
-  g.T = T;
-  g.mdot = mdot;
-  g.scal = scal;
+  ebit_flux_args(&g, d, h, lam, h_lg, Tsat, theta_min, flags, th, cF, nF, T, mdot, mface, scal);
   if (d->dim == 3)
-    hipLaunchKernelGGL(k_mass_flux<3>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+    hipLaunchKernelGGL(k_mass_flux<3>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   else
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+    hipLaunchKernelGGL(k_mass_flux<2>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   if (mface) hipLaunchKernelGGL(k_mass_flux_faces, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   return hipGetLastError();
+}
+
+// n cases' mass fluxes in one launch: start (n + 1 block offsets, one block
+// per EBIT_BLOCK cells of each case), blocks = start[n]
+extern "C" hipError_t ebit_launch_mass_flux_many(int n, int dim, const FluxArgs* tab, const int* start, int blocks,
+                                                 hipStream_t st) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_mass_flux<3>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  else
+    hipLaunchKernelGGL(k_mass_flux<2>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  return hipGetLastError();
+}
+
+extern "C" void ebit_proj_args(ProjArgs* g, const Dims* d, double h, const double rho[2], double dt,
+                               const int pbc[6], const double pval[6], const uint8_t* flags,
+                               const double* const th[3], const double* nF, const double* mdot, double* const ul[3],
+                               double* const uv[3], const double* p, double* b, double* partial) {
+  memset(g, 0, sizeof(*g));
+  g->d = *d;
+  g->h = h;
+  g->rho[0] = rho[0];
+  g->rho[1] = rho[1];
+  g->jump = 1.0 / rho[1] - 1.0 / rho[0];
+  g->dt = dt;
+  for (int s = 0; s < 6; ++s) {
+    g->pbc[s] = pbc[s];
+    g->pval[s] = pval[s];
+  }
+  g->flags = flags;
+  for (int a = 0; a < 3; ++a) {
+    g->th[a] = (a < d->dim) ? th[a] : nullptr;
+    g->ul[a] = (a < d->dim && ul) ? ul[a] : nullptr;
+    g->uv[a] = (a < d->dim && uv) ? uv[a] : nullptr;
+  }
+  g->nF = nF;
+  g->mdot = mdot;
+  g->p = p;
+  g->b = b;
+  g->partial = partial;
+  g->one = 0;
+  g->cF = nullptr;
+  g->src = 0.0;
 }
 
 static ProjArgs make_proj(const Dims* d, double h, const double rho[2], double dt, const int pbc[6],
@@ -588,30 +607,7 @@ static ProjArgs make_proj(const Dims* d, double h, const double rho[2], double d
                           const double* mdot, double* const ul[3], double* const uv[3], const double* p, double* b,
                           double* partial) {
   ProjArgs g;
-  g.d = *d;
-  g.h = h;
-  g.rho[0] = rho[0];
-  g.rho[1] = rho[1];
-  g.jump = 1.0 / rho[1] - 1.0 / rho[0];
-  g.dt = dt;
-  for (int s = 0; s < 6; ++s) {
-    g.pbc[s] = pbc[s];
-    g.pval[s] = pval[s];
-  }
-  g.flags = flags;
-  for (int a = 0; a < 3; ++a) {
-    g.th[a] = (a < d->dim) ? th[a] : nullptr;
-    g.ul[a] = (a < d->dim) ? ul[a] : nullptr;
-    g.uv[a] = (a < d->dim) ? uv[a] : nullptr;
-  }
-  g.nF = nF;
-  g.mdot = mdot;
-  g.p = p;
-  g.b = b;
-  g.partial = partial;
-  g.one = 0;
-  g.cF = nullptr;
-  g.src = 0.0;
+  ebit_proj_args(&g, d, h, rho, dt, pbc, pval, flags, th, nF, mdot, ul, uv, p, b, partial);
   return g;
 }
 
@@ -620,8 +616,16 @@ extern "C" hipError_t ebit_launch_proj_rhs(const Dims* d, double h, const double
                                            const double* nF, const double* mdot, double* const ul[3],
                                            double* const uv[3], double* b, hipStream_t st) {
   ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nF, mdot, ul, uv, nullptr, b, nullptr);
-  hipLaunchKernelGGL(k_ghost_vel, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_proj_rhs<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_ghost_vel, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL(k_proj_rhs<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  return hipGetLastError();
+}
+
+// n cases' ghost velocities and right-hand sides, one launch each
+extern "C" hipError_t ebit_launch_proj_rhs_many(int n, const ProjArgs* tab, const int* start, int blocks,
+                                                hipStream_t st) {
+  hipLaunchKernelGGL(k_ghost_vel, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_proj_rhs<false>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 
@@ -636,7 +640,7 @@ extern "C" hipError_t ebit_launch_proj_rhs_one(const Dims* d, double h, const do
   g.one = 1;
   g.cF = cF;
   g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
-  hipLaunchKernelGGL(k_proj_rhs<true>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_proj_rhs<true>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   return hipGetLastError();
 }
 
@@ -649,8 +653,8 @@ extern "C" hipError_t ebit_launch_face_update_one(const Dims* d, double h, const
   g.one = 1;
   g.cF = cF;
   g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
-  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_divmax<true>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL(k_divmax<true>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(g));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
@@ -661,9 +665,19 @@ extern "C" hipError_t ebit_launch_face_update(const Dims* d, double h, const dou
                                               const double* const th[3], double* const ul[3], double* const uv[3],
                                               const double* p, double* partial, Scal* scal, hipStream_t st) {
   ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nullptr, nullptr, ul, uv, p, nullptr, partial);
-  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
-  hipLaunchKernelGGL(k_divmax<false>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL(k_divmax<false>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(g));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
+}
+
+// n cases' face updates (start: one block per EBIT_BLOCK cells) and
+// divergence maxima (rstart: each case's reduction blocks, as many as its
+// finalize entry reduces), one launch each
+extern "C" hipError_t ebit_launch_face_update_many(int n, const ProjArgs* tab, const int* start, int blocks,
+                                                   const int* rstart, int rblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_face_update, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_divmax<false>, dim3((unsigned)rblocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, rstart, n));
+  return hipGetLastError();
 }

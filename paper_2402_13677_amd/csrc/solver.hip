@@ -1460,17 +1460,6 @@ __device__ inline void tail_body(const TailArgs<T>& a, T* sm) {
 // ---------------------------------------------------------------------------
 // hierarchy construction
 // ---------------------------------------------------------------------------
-struct BuildOut {
-  Dims cd;
-  double* diag;
-  double* mass;
-  double* off[3];
-  float* d32;     // FP32 copies of diag and off (null: none)
-  float* o32[3];
-  float* i32;     // the level's block of the FP32 or FP64 tail image (null: none)
-  double* i64;
-};
-
 __device__ inline void store_built(const BuildOut& o, long long I, int ci, int cj, int ck, double M, double F,
                                    const double (&cross)[3]) {
   const double dg = M + 0.5 * F;
@@ -1598,26 +1587,29 @@ __device__ inline void build_cell_from_coarse(const CoarseOp<double>& op, const 
 
 // One level of both systems in one launch: blocks [0, nb) build the
 // heat system's cells, blocks [nb, 2 nb) the pressure system's.
-__global__ void k_build_from_fine2(FineOp op0, FineOp op1, BuildOut o0, BuildOut o1, unsigned nb) {
-  const bool s1 = blockIdx.x >= nb;
-  const long long I = (long long)(blockIdx.x - (s1 ? nb : 0u)) * blockDim.x + threadIdx.x;
-  if (I >= o0.cd.N) return;
+__global__ void k_build_from_fine2(Many<BuildFineArgs> m) {
+  long long lb, nbc;
+  const BuildFineArgs a = many_case(m, lb, nbc);
+  const bool s1 = lb >= a.nb;
+  const long long I = (lb - (s1 ? a.nb : 0u)) * blockDim.x + threadIdx.x;
+  if (I >= a.o[0].cd.N) return;
   if (s1)
-    build_cell_from_fine(op1, o1, I);
+    build_cell_from_fine(a.op[1], a.o[1], I);
   else
-    build_cell_from_fine(op0, o0, I);
+    build_cell_from_fine(a.op[0], a.o[0], I);
 }
 
 template <int DIM>
-__global__ void k_build_from_coarse2(CoarseOp<double> op0, CoarseOp<double> op1, BuildOut o0, BuildOut o1,
-                                     unsigned nb) {
-  const bool s1 = blockIdx.x >= nb;
-  const long long I = (long long)(blockIdx.x - (s1 ? nb : 0u)) * blockDim.x + threadIdx.x;
-  if (I >= o0.cd.N) return;
+__global__ void k_build_from_coarse2(Many<BuildCoarseArgs> m) {
+  long long lb, nbc;
+  const BuildCoarseArgs a = many_case(m, lb, nbc);
+  const bool s1 = lb >= a.nb;
+  const long long I = (lb - (s1 ? a.nb : 0u)) * blockDim.x + threadIdx.x;
+  if (I >= a.o[0].cd.N) return;
   if (s1)
-    build_cell_from_coarse<DIM>(op1, o1, I);
+    build_cell_from_coarse<DIM>(a.op[1], a.o[1], I);
   else
-    build_cell_from_coarse<DIM>(op0, o0, I);
+    build_cell_from_coarse<DIM>(a.op[0], a.o[0], I);
 }
 
 
@@ -1752,10 +1744,12 @@ __device__ inline void build_small_level(const BuildTable& t, int l) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(1024) void k_build_small(const BuildTable* __restrict__ tabs) {
+__global__ __launch_bounds__(1024) void k_build_small(Many<BuildSmallArgs> m) {
   __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
   __shared__ double colb[2][EBIT_DENSE_MAX], rowb[2][EBIT_DENSE_MAX];
-  const BuildTable& t = tabs[blockIdx.x];
+  long long lb, nbc;
+  const BuildSmallArgs a = many_case(m, lb, nbc);
+  const BuildTable& t = ((const BuildTable*)a.tabs)[lb];
   const int ls = t.ls, nlev = t.nlev, dl = t.dl;
   const int upto = dl >= 0 ? dl + 1 : nlev;
   for (int l = ls; l < upto; ++l) build_small_level<DIM>(t, l);
@@ -1894,8 +1888,13 @@ __global__ void k_apply(FineOp op, const double* __restrict__ x, double* __restr
 }
 
 // heat right-hand side: b = rho cp/dt T* + interface and wall terms
-__global__ void k_heat_rhs(FineOp op, const double* __restrict__ Ts, double* __restrict__ b) {
-  GRID_STRIDE(c, op.d.N) {
+__global__ void k_heat_rhs(Many<HeatRhsArgs> m) {
+  long long lb, nb;
+  const HeatRhsArgs a = many_case(m, lb, nb);
+  const FineOp& op = a.op;
+  const double* __restrict__ Ts = a.Ts;
+  double* __restrict__ b = a.b;
+  for (long long c = lb * blockDim.x + threadIdx.x; c < op.d.N; c += nb * blockDim.x) {
     int i, j, k;
     cell_ijk(op.d, c, i, j, k);
     const uint8_t f = op.flags[c];
@@ -1906,8 +1905,6 @@ __global__ void k_heat_rhs(FineOp op, const double* __restrict__ Ts, double* __r
   }
 }
 
-// finalize kinds
-enum { FIN_INIT = 0, FIN_GAMMA = 1, FIN_DELTA = 2, FIN_RR = 3, FIN_MAX = 4, FIN_SUM1 = 5, FIN_START = 6, FIN_PEND = 7 };
 
 // Sum (or max) of nv rows of nb partials, in a fixed order; result in thread 0.
 __device__ inline void reduce_partials(const double* __restrict__ partial, int nb, int nv, bool mx,
@@ -1936,12 +1933,24 @@ __device__ inline void reduce_partials(const double* __restrict__ partial, int n
 }
 
 // single-system reductions outside the solves (divergence maximum)
-__global__ void k_finalize(const double* __restrict__ partial, int nb, int nv, Scal* sc, int kind) {
+__global__ void k_finalize(Many<FinArgs> m) {
+  long long lb, nbc;
+  const FinArgs a = many_case(m, lb, nbc);
   double v[3];
-  reduce_partials(partial, nb, nv, kind == FIN_MAX, v);
+  reduce_partials(a.partial, a.nb, a.nv, a.kind == FIN_MAX, v);
   if (threadIdx.x != 0) return;
-  if (kind == FIN_MAX) sc->divmax = v[0];
-  if (kind == FIN_SUM1) sc->red[0] = v[0];
+  if (a.kind == FIN_MAX) a.sc->divmax = v[0];
+  if (a.kind == FIN_SUM1) a.sc->red[0] = v[0];
+}
+
+// a case's status scalars: cleared (dst null) or copied to dst
+__global__ void k_scal(Many<ScalArgs> m) {
+  long long lb, nbc;
+  const ScalArgs a = many_case(m, lb, nbc);
+  constexpr int W = (int)(sizeof(Scal) / sizeof(double));
+  const double* src = (const double*)a.scal;
+  double* dst = a.dst ? (double*)a.dst : (double*)a.scal;
+  for (int t = threadIdx.x; t < W; t += blockDim.x) dst[t] = a.dst ? src[t] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2481,10 +2490,15 @@ __global__ void kb_fine_restrict_split(const SolveCase<T>* __restrict__ cs, cons
 }
 
 // the cell flags in the colour-split order (padding slots of odd n0: 0)
-__global__ void k_split_flags(Dims d, const uint8_t* __restrict__ flags, uint8_t* __restrict__ fs) {
+__global__ void k_split_flags(Many<SplitArgs> m) {
+  long long lb, nb;
+  const SplitArgs a = many_case(m, lb, nb);
+  const Dims& d = a.d;
+  const uint8_t* __restrict__ flags = a.flags;
+  uint8_t* __restrict__ fs = a.fs;
   const long long H = split_half(d);
   const int hw = (d.n[0] + 1) >> 1;
-  GRID_STRIDE(t, 2 * H) {
+  for (long long t = lb * blockDim.x + threadIdx.x; t < 2 * H; t += nb * blockDim.x) {
     const int color = t >= H ? 1 : 0;
     const long long s = t - color * H;
     const int ih = (int)(s % hw);
@@ -3164,7 +3178,11 @@ extern "C" {
 
 hipError_t ebit_launch_split_flags(const Dims* d, const uint8_t* flags, uint8_t* fsplit, hipStream_t st) {
   const long long n = 2 * split_half(*d);
-  hipLaunchKernelGGL(k_split_flags, dim3(nblk(n)), dim3(EBIT_BLOCK), 0, st, *d, flags, fsplit);
+  SplitArgs a;
+  a.d = *d;
+  a.flags = flags;
+  a.fs = fsplit;
+  hipLaunchKernelGGL(k_split_flags, dim3(nblk(n)), dim3(EBIT_BLOCK), 0, st, many_one(a));
   return hipGetLastError();
 }
 
@@ -3226,12 +3244,17 @@ size_t ebit_build_table_bytes(void) { return 2 * sizeof(BuildTable); }
 // operators, the larger levels one launch each, the small ones (and the
 // dense inverse) in one work-group per system; FP32 copies written with
 // the FP64 values when wanted.
-hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, int want32, const void* dev_tabs,
-                                int ls, hipStream_t st) {
-  // one launch per level for both systems
+// The launched levels of a hierarchy build (levels 1 .. ls-1): level 1 from
+// the fine operators, the others each from the level above.  Returns how
+// many levels past the first were described.
+int ebit_build_args(const FineOp* op, const EbitLevelHost* lv, int nlev, int want32, int ls, BuildFineArgs* fine,
+                    BuildCoarseArgs* coarse) {
+  int nc = 0;
   for (int l = 1; l < ls && l < nlev; ++l) {
     BuildOut o[2];
     CoarseOp<double> f[2];
+    memset(o, 0, sizeof(o));
+    memset(f, 0, sizeof(f));
     for (int sys = 0; sys < 2; ++sys) {
       o[sys].cd = lv[l].d;
       o[sys].diag = lv[l].diag64[sys];
@@ -3252,17 +3275,92 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
       }
     }
     const unsigned nb = nblk(o[0].cd.N);
-    if (l == 1)
-      hipLaunchKernelGGL(k_build_from_fine2, dim3(2 * nb), dim3(EBIT_BLOCK), 0, st, op[0], op[1], o[0], o[1], nb);
-    else if (lv[0].d.dim == 3)
-      hipLaunchKernelGGL(k_build_from_coarse2<3>, dim3(2 * nb), dim3(EBIT_BLOCK), 0, st, f[0], f[1], o[0], o[1], nb);
-    else
-      hipLaunchKernelGGL(k_build_from_coarse2<2>, dim3(2 * nb), dim3(EBIT_BLOCK), 0, st, f[0], f[1], o[0], o[1], nb);
+    if (l == 1) {
+      memset(fine, 0, sizeof(*fine));
+      fine->op[0] = op[0];
+      fine->op[1] = op[1];
+      fine->o[0] = o[0];
+      fine->o[1] = o[1];
+      fine->nb = nb;
+    } else {
+      BuildCoarseArgs& a = coarse[nc++];
+      memset(&a, 0, sizeof(a));
+      a.op[0] = f[0];
+      a.op[1] = f[1];
+      a.o[0] = o[0];
+      a.o[1] = o[1];
+      a.nb = nb;
+    }
   }
+  return nc;
+}
+
+hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, int want32, const void* dev_tabs,
+                                int ls, hipStream_t st) {
+  // one launch per level for both systems
+  BuildFineArgs fine;
+  BuildCoarseArgs coarse[EBIT_MAX_LEVELS];
+  const int nc = ebit_build_args(op, lv, nlev, want32, ls, &fine, coarse);
+  if (ls > 1 && nlev > 1)
+    hipLaunchKernelGGL(k_build_from_fine2, dim3(2 * fine.nb), dim3(EBIT_BLOCK), 0, st, many_one(fine));
+  for (int q = 0; q < nc; ++q) {
+    if (lv[0].d.dim == 3)
+      hipLaunchKernelGGL(k_build_from_coarse2<3>, dim3(2 * coarse[q].nb), dim3(EBIT_BLOCK), 0, st,
+                         many_one(coarse[q]));
+    else
+      hipLaunchKernelGGL(k_build_from_coarse2<2>, dim3(2 * coarse[q].nb), dim3(EBIT_BLOCK), 0, st,
+                         many_one(coarse[q]));
+  }
+  BuildSmallArgs a;
+  a.tabs = dev_tabs;
   if (lv[0].d.dim == 3)
-    hipLaunchKernelGGL(k_build_small<3>, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
+    hipLaunchKernelGGL(k_build_small<3>, dim3(2), dim3(1024), 0, st, many_one(a));
   else
-    hipLaunchKernelGGL(k_build_small<2>, dim3(2), dim3(1024), 0, st, (const BuildTable*)dev_tabs);
+    hipLaunchKernelGGL(k_build_small<2>, dim3(2), dim3(1024), 0, st, many_one(a));
+  return hipGetLastError();
+}
+
+// Batched forms: n cases per launch (tab: device table; start: n + 1 block
+// offsets; blocks = start[n]).
+hipError_t ebit_launch_build_fine_many(int n, const BuildFineArgs* tab, const int* start, int blocks,
+                                       hipStream_t st) {
+  hipLaunchKernelGGL(k_build_from_fine2, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  return hipGetLastError();
+}
+hipError_t ebit_launch_build_coarse_many(int n, int dim, const BuildCoarseArgs* tab, const int* start, int blocks,
+                                         hipStream_t st) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_build_from_coarse2<3>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st,
+                       many_tab(tab, start, n));
+  else
+    hipLaunchKernelGGL(k_build_from_coarse2<2>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st,
+                       many_tab(tab, start, n));
+  return hipGetLastError();
+}
+// two blocks (one per system) per case
+hipError_t ebit_launch_build_small_many(int n, int dim, const BuildSmallArgs* tab, const int* start,
+                                        hipStream_t st) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_build_small<3>, dim3((unsigned)(2 * n)), dim3(1024), 0, st, many_tab(tab, start, n));
+  else
+    hipLaunchKernelGGL(k_build_small<2>, dim3((unsigned)(2 * n)), dim3(1024), 0, st, many_tab(tab, start, n));
+  return hipGetLastError();
+}
+hipError_t ebit_launch_heat_rhs_many(int n, const HeatRhsArgs* tab, const int* start, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_heat_rhs, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  return hipGetLastError();
+}
+// one block per case
+hipError_t ebit_launch_finalize_many(int n, const FinArgs* tab, const int* start, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)n), dim3(256), 0, st, many_tab(tab, start, n));
+  return hipGetLastError();
+}
+hipError_t ebit_launch_scal_many(int n, const ScalArgs* tab, const int* start, hipStream_t st) {
+  hipLaunchKernelGGL(k_scal, dim3((unsigned)n), dim3(64), 0, st, many_tab(tab, start, n));
+  return hipGetLastError();
+}
+hipError_t ebit_launch_split_flags_many(int n, const SplitArgs* tab, const int* start, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_flags, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 
@@ -3272,12 +3370,22 @@ hipError_t ebit_launch_apply(const FineOp* op, const double* x, double* y, hipSt
 }
 
 hipError_t ebit_launch_heat_rhs(const FineOp* op, const double* Ts, double* b, hipStream_t st) {
-  hipLaunchKernelGGL(k_heat_rhs, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, *op, Ts, b);
+  HeatRhsArgs a;
+  a.op = *op;
+  a.Ts = Ts;
+  a.b = b;
+  hipLaunchKernelGGL(k_heat_rhs, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(a));
   return hipGetLastError();
 }
 
 hipError_t ebit_launch_finalize_max(const double* partial, int nb, Scal* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partial, nb, 1, sc, (int)FIN_MAX);
+  FinArgs a;
+  a.partial = partial;
+  a.nb = nb;
+  a.nv = 1;
+  a.kind = FIN_MAX;
+  a.sc = sc;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, many_one(a));
   return hipGetLastError();
 }
 
