@@ -208,7 +208,7 @@ def cell_updates(rec, schedule, ms_step):
     return {"per_step": upd, "over_step": upd / (ms_step * 1e-3), "over_solves": upd / (solve_ms * 1e-3)}
 
 
-def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
+def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None, keep_solves=None):
     """The uneven batch: one step = build + heat + mass flux + projection
     of every case; batched (one launch per solve kernel over all cases, the
     schedule autotuned untimed on the first step's right-hand sides) or one
@@ -247,6 +247,8 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
         chosen, _ = b.autotune(bh, bp)
         schedule = {k: chosen[k] for k in ("nu1", "nu2", "tail_cells", "check_every")}
 
+    solve = {"heat_s": [], "proj_s": [], "heat_iters": [], "proj_iters": []}
+
     def step():
         if batched:
             b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs],
@@ -255,12 +257,25 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
             b.mass_flux(T, m, stats=False)
             sp = b.project(u_l, u_v, m, p)
             its.append((max(x["iters"] for x in sh), max(x["iters"] for x in sp)))
+            solve["heat_s"].append(sh[0]["seconds"])
+            solve["proj_s"].append(sp[0]["seconds"])
+            solve["heat_iters"].append([x["iters"] for x in sh])
+            solve["proj_iters"].append([x["iters"] for x in sp])
         else:
+            hs, ps, hi, pi = [], [], [], []
             for i, (ctx, d, c) in enumerate(zip(ctxs, dcs, cases)):
                 ctx.build_coeffs(d.markers, d.vcol, d.ccol, c.dt)
-                ctx.heat_solve(T[i], T[i])
+                st = ctx.heat_solve(T[i], T[i])
+                hs.append(st["seconds"])
+                hi.append(st["iters"])
                 ctx.mass_flux(T[i], m[i], stats=False)
-                ctx.project(u_l[i], u_v[i], m[i], p[i])
+                st = ctx.project(u_l[i], u_v[i], m[i], p[i])
+                ps.append(st["seconds"])
+                pi.append(st["iters"])
+            solve["heat_s"].append(hs)
+            solve["proj_s"].append(ps)
+            solve["heat_iters"].append(hi)
+            solve["proj_iters"].append(pi)
 
     for _ in range(warmup):
         step()
@@ -274,6 +289,8 @@ def run_gpu_batch(cases, precision, steps, warmup, batched=True, schedule=None):
         b.close()
     for c in ctxs:
         c.close()
+    if keep_solves is not None:
+        keep_solves.update({k: v[warmup:] for k, v in solve.items()})
     return el, its, schedule
 
 
@@ -829,13 +846,93 @@ def main():
     print(json.dumps(out))
 
 
+def batch_cpu_baseline(cases, one_thread_cases=8):
+    """The oracle on the batch: one full step of every case (multigrid solves
+    to the discrete solution) with as many OpenMP threads as the host has
+    cores, and the first `one_thread_cases` cases on one thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+    cores = os.cpu_count() or 1
+    log(f"oracle steps of the {len(cases)} cases on {cores} threads")
+    tot = 0.0
+    for c in cases:
+        _, t = _oracle_step(c, cores)
+        tot += t["step"]
+    ncells = sum(c.ncells for c in cases)
+    base = {"value": ncells / tot, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full step of each of the {len(cases)} cases ({tot:.1f} s in all: geometry, multigrid "
+                      f"heat and pressure solves to the discrete solution, mass flux, projection) on {cores} "
+                      f"threads of {host_cpu()}"}
+    log(f"oracle steps of {one_thread_cases} cases on 1 thread")
+    t1, n1 = 0.0, 0
+    for c in cases[:one_thread_cases]:
+        _, t = _oracle_step(c, 1)
+        t1 += t["step"]
+        n1 += c.ncells
+    base["one_thread"] = {"value": n1 / t1, "unit": "cell-steps/s", "cores": 1,
+                          "sample": f"one full step of the first {one_thread_cases} cases ({t1:.1f} s)"}
+    return base
+
+
 def main_batch(args, cases):
     """The 64-case uneven 2D batch (sides 64..256): batched solves, with the
-    same cases one context after another beside it."""
+    same cases one context after another beside it, in the benchmarked
+    precision and in FP64.  The roofline is the design's algorithmic bytes
+    of every outer iteration of every case (a V-cycle on all levels plus the
+    outer update, per fine cell) over the batched solve time: the batch's
+    solves are single launches over all cases, so no one kernel stands for
+    them."""
+    import statistics
     ncells = sum(c.ncells for c in cases)
-    el, its, schedule = run_gpu_batch(cases, args.precision, args.steps, args.warmup, batched=True)
+    log(f"batch of {len(cases)} cases, {ncells} cells: batched steps")
+    bs = {}
+    el, its, schedule = run_gpu_batch(cases, args.precision, args.steps, args.warmup, batched=True, keep_solves=bs)
     seq_steps = max(2, args.steps // 5)
-    el_seq, _, _ = run_gpu_batch(cases, args.precision, seq_steps, 1, batched=False, schedule=schedule)
+    log("the same cases one context after another")
+    ss = {}
+    el_seq, _, _ = run_gpu_batch(cases, args.precision, seq_steps, 1, batched=False, schedule=schedule,
+                                 keep_solves=ss)
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    s64 = {}
+    el_seq64, _, _ = run_gpu_batch(cases, other, seq_steps, 1, batched=False, schedule=schedule, keep_solves=s64)
+    med = statistics.median
+    per_step_sum = lambda lst: med([sum(x) for x in lst])
+    per_case = lambda lst: med([v for x in lst for v in x])
+    extra = {
+        "sequential_ms_per_step": el_seq / seq_steps * 1e3,
+        "batched_speedup": (el_seq / seq_steps) / (el / args.steps),
+        "max_outer_iters": {"heat": max(i[0] for i in its), "projection": max(i[1] for i in its)},
+        "time_to_rtol_ms": {
+            "batched": {"heat": med(bs["heat_s"]) * 1e3, "projection": med(bs["proj_s"]) * 1e3,
+                        "note": "one solve call over all 64 cases"},
+            f"sequential_{args.precision}": {
+                "heat_all_cases": per_step_sum(ss["heat_s"]) * 1e3,
+                "projection_all_cases": per_step_sum(ss["proj_s"]) * 1e3,
+                "heat_median_case": per_case(ss["heat_s"]) * 1e3,
+                "projection_median_case": per_case(ss["proj_s"]) * 1e3},
+            f"sequential_{other}": {
+                "heat_all_cases": per_step_sum(s64["heat_s"]) * 1e3,
+                "projection_all_cases": per_step_sum(s64["proj_s"]) * 1e3,
+                "heat_median_case": per_case(s64["heat_s"]) * 1e3,
+                "projection_median_case": per_case(s64["proj_s"]) * 1e3},
+        },
+        f"sequential_{other}_ms_per_step": el_seq64 / seq_steps * 1e3,
+    }
+    bpc = solve_model_bytes_per_iteration(args.precision, 2, schedule)
+    sizes = [c.ncells for c in cases]
+    ro = {}
+    for k, sk, ik in (("heat", "heat_s", "heat_iters"), ("projection", "proj_s", "proj_iters")):
+        byts = med([sum(n * it for n, it in zip(sizes, its_)) for its_ in bs[ik]]) * bpc
+        gbs = byts / med(bs[sk]) / 1e9
+        ro[k] = {"algorithmic_GB": byts / 1e9, "achieved_GBps": gbs}
+    dom = max(ro, key=lambda k: med(bs["heat_s" if k == "heat" else "proj_s"]))
+    roofline = {"bound": "hbm", "kernel": f"batched {dom} solve (every solve kernel, design byte model)",
+                "achieved": ro[dom]["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ro[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                "model_bytes_per_cell_per_iteration": bpc, "solves": ro}
     out = {
         "metric": "time-to-1e-9 residual per solve (mixed vs FP64) + cell-updates/s, % HBM peak",
         "value": ncells * args.steps / el,
@@ -851,11 +948,11 @@ def main_batch(args, cases):
         "data": "synthetic",
         "config": {"workload": "batch64_2d", "cases": len(cases), "cells": ncells, "precision": args.precision,
                    "rtol": DEFAULT_RTOL, "parallelism": "single GPU", "schedule": schedule},
-        "extra": {"sequential_ms_per_step": el_seq / seq_steps * 1e3,
-                  "batched_speedup": (el_seq / seq_steps) / (el / args.steps),
-                  "max_outer_iters": {"heat": max(i[0] for i in its), "projection": max(i[1] for i in its)}},
-        "roofline": None,
+        "extra": extra,
+        "roofline": roofline,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(cases)
     print(json.dumps(out))
 
 
