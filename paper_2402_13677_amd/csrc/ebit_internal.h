@@ -239,26 +239,30 @@ struct Many {
 };
 
 // The block's case arguments, its block index within the case and the
-// case's block count.
-template <typename A>
-__device__ inline A many_case(const Many<A>& m, long long& lb, long long& nb) {
-  if (m.n == 0) {
+// case's block count.  B is the kernel's compile-time choice between the
+// two forms: a single case reads its arguments straight from the kernel
+// argument, a batch from the device table, so no copy of the (large)
+// argument struct is ever made in private memory.
+template <bool B, typename A>
+__device__ inline const A& many_case(const Many<A>& m, long long& lb, long long& nb) {
+  if constexpr (!B) {
     lb = blockIdx.x;
     nb = gridDim.x;
     return m.one;
+  } else {
+    const int b = blockIdx.x;
+    int lo = 0, hi = m.n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (m.start[mid] <= b)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    lb = b - m.start[lo];
+    nb = m.start[lo + 1] - m.start[lo];
+    return m.tab[lo];
   }
-  const int b = blockIdx.x;
-  int lo = 0, hi = m.n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (m.start[mid] <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  lb = b - m.start[lo];
-  nb = m.start[lo + 1] - m.start[lo];
-  return m.tab[lo];
 }
 
 template <typename A>

@@ -25,9 +25,10 @@ __device__ inline long long eidx(const Dims& d, int a, int i, int j, int k) {
 }
 
 // Marker present <=> end colours differ; s in [0, 1]; periodic seams agree.
+template <bool B>
 __global__ void k_check_markers(Many<GeoArgs> m, int a) {
   long long lb, nb;
-  const GeoArgs g = many_case(m, lb, nb);
+  const GeoArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const int ex = d.n[0] + (a == 0 ? 0 : 1);
   const int ey = d.n[1] + (a == 1 ? 0 : 1);
@@ -59,9 +60,10 @@ __global__ void k_check_markers(Many<GeoArgs> m, int a) {
   if (bad) atomicOr(&g.scal->err, bad);
 }
 
+template <bool B>
 __global__ void k_check_seam_vertices(Many<GeoArgs> m) {
   long long lb, nb;
-  const GeoArgs g = many_case(m, lb, nb);
+  const GeoArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const int vx = d.n[0] + 1, vy = d.n[1] + 1, vz = nvz_of(d);
   const long long t = lb * blockDim.x + threadIdx.x;
@@ -154,9 +156,10 @@ __device__ inline void slot_corner(int a, int o, int i, int j, int k, int dim, i
 // The markers of the cell's edges are gathered into slot a * 4 + o (NaN: no
 // marker, or no such slot) with every index known at compile time, so a
 // cell without markers (almost all of them) finishes from registers.
+template <bool B>
 __global__ void k_facets(Many<GeoArgs> m) {
   long long lb, nb;
-  const GeoArgs g = many_case(m, lb, nb);
+  const GeoArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
@@ -373,9 +376,10 @@ __device__ inline bool link_theta(const GeoArgs& g, int a, int li, int lj, int l
 }
 
 // Cut bits of every side, and theta on the + faces (and face 0 of each axis).
+template <bool B>
 __global__ void k_theta_flags(Many<GeoArgs> m) {
   long long lb, nb;
-  const GeoArgs g = many_case(m, lb, nb);
+  const GeoArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
@@ -422,11 +426,11 @@ extern "C" hipError_t ebit_launch_geometry(const Dims* d, double h, const double
   ebit_geo_args(&g, d, h, mk, vcol, ccol, flags, cF, nF, th, scal);
   const Many<GeoArgs> m = many_one(g);
   for (int a = 0; a < d->dim; ++a)
-    hipLaunchKernelGGL(k_check_markers, dim3((unsigned)ebit_geo_blocks(d, a)), dim3(EBIT_BLOCK), 0, st, m, a);
-  hipLaunchKernelGGL(k_check_seam_vertices, dim3((unsigned)ebit_geo_blocks(d, 3)), dim3(EBIT_BLOCK), 0, st, m);
+    hipLaunchKernelGGL(k_check_markers<false>, dim3((unsigned)ebit_geo_blocks(d, a)), dim3(EBIT_BLOCK), 0, st, m, a);
+  hipLaunchKernelGGL(k_check_seam_vertices<false>, dim3((unsigned)ebit_geo_blocks(d, 3)), dim3(EBIT_BLOCK), 0, st, m);
   const unsigned nb = (unsigned)ebit_geo_blocks(d, 4);
-  hipLaunchKernelGGL(k_facets, dim3(nb), dim3(EBIT_BLOCK), 0, st, m);
-  hipLaunchKernelGGL(k_theta_flags, dim3(nb), dim3(EBIT_BLOCK), 0, st, m);
+  hipLaunchKernelGGL(k_facets<false>, dim3(nb), dim3(EBIT_BLOCK), 0, st, m);
+  hipLaunchKernelGGL(k_theta_flags<false>, dim3(nb), dim3(EBIT_BLOCK), 0, st, m);
   return hipGetLastError();
 }
 
@@ -469,12 +473,12 @@ extern "C" long long ebit_geo_blocks(const Dims* d, int kind) {
 extern "C" hipError_t ebit_launch_geometry_many(int n, int dim, const GeoArgs* tab, const int* const start[5],
                                                 const int blocks[5], hipStream_t st) {
   for (int a = 0; a < dim; ++a)
-    hipLaunchKernelGGL(k_check_markers, dim3((unsigned)blocks[a]), dim3(EBIT_BLOCK), 0, st,
+    hipLaunchKernelGGL(k_check_markers<true>, dim3((unsigned)blocks[a]), dim3(EBIT_BLOCK), 0, st,
                        many_tab(tab, start[a], n), a);
-  hipLaunchKernelGGL(k_check_seam_vertices, dim3((unsigned)blocks[3]), dim3(EBIT_BLOCK), 0, st,
+  hipLaunchKernelGGL(k_check_seam_vertices<true>, dim3((unsigned)blocks[3]), dim3(EBIT_BLOCK), 0, st,
                      many_tab(tab, start[3], n));
-  hipLaunchKernelGGL(k_facets, dim3((unsigned)blocks[4]), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start[4], n));
-  hipLaunchKernelGGL(k_theta_flags, dim3((unsigned)blocks[4]), dim3(EBIT_BLOCK), 0, st,
+  hipLaunchKernelGGL(k_facets<true>, dim3((unsigned)blocks[4]), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start[4], n));
+  hipLaunchKernelGGL(k_theta_flags<true>, dim3((unsigned)blocks[4]), dim3(EBIT_BLOCK), 0, st,
                      many_tab(tab, start[4], n));
   return hipGetLastError();
 }

@@ -175,10 +175,10 @@ __device__ inline double fallback_grad(const FluxArgs& g, int kph, const double 
   return (best_T - g.Tsat) / best_p;
 }
 
-template <int DIM>
+template <int DIM, bool B>
 __global__ void k_mass_flux(Many<FluxArgs> m) {
   long long lb, nb;
-  const FluxArgs g = many_case(m, lb, nb);
+  const FluxArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
@@ -371,9 +371,10 @@ __device__ inline double one_fluid_source(const ProjArgs& g, int i, int j, int k
 
 // Ghost value on every cut face (Eq. ghost_velocity).  Each cell handles its
 // + faces and, on the first layer, face 0 (the periodic copy of face n).
+template <bool B>
 __global__ void k_ghost_vel(Many<ProjArgs> m) {
   long long lb, nb;
-  const ProjArgs g = many_case(m, lb, nb);
+  const ProjArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
@@ -404,10 +405,10 @@ __global__ void k_ghost_vel(Many<ProjArgs> m) {
 }
 
 // b = bc - div_c u_{k(c)}  (right-hand side of the SPD system -L p = b)
-template <bool ONE>
+template <bool ONE, bool B>
 __global__ void k_proj_rhs(Many<ProjArgs> m) {
   long long lb, nb;
-  const ProjArgs g = many_case(m, lb, nb);
+  const ProjArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
@@ -467,9 +468,10 @@ __device__ inline bool face_grad(const ProjArgs& g, int i, int j, int k, long lo
 
 // u <- u - beta_f grad p on both fields; each cell writes its + faces and, on
 // the first layer, face 0 (so every face is written exactly once).
+template <bool B>
 __global__ void k_face_update(Many<ProjArgs> m) {
   long long lb, nb;
-  const ProjArgs g = many_case(m, lb, nb);
+  const ProjArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   const long long c = lb * blockDim.x + threadIdx.x;
   if (c >= d.N) return;
@@ -490,10 +492,10 @@ __global__ void k_face_update(Many<ProjArgs> m) {
 
 // max_c |div_c u_{k(c)}| of the updated fields (a separate pass: every face
 // is final when it is read)
-template <bool ONE>
+template <bool ONE, bool B>
 __global__ void k_divmax(Many<ProjArgs> m) {
   long long lb, nb;
-  const ProjArgs g = many_case(m, lb, nb);
+  const ProjArgs& g = many_case<B>(m, lb, nb);
   const Dims& d = g.d;
   double vmax = 0.0;
   for (long long c = lb * blockDim.x + threadIdx.x; c < d.N; c += nb * blockDim.x) {
@@ -553,9 +555,9 @@ extern "C" hipError_t ebit_launch_mass_flux(const Dims* d, double h, const doubl
   FluxArgs g;
   ebit_flux_args(&g, d, h, lam, h_lg, Tsat, theta_min, flags, th, cF, nF, T, mdot, mface, scal);
   if (d->dim == 3)
-    hipLaunchKernelGGL(k_mass_flux<3>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+    hipLaunchKernelGGL((k_mass_flux<3, false>), dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   else
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+    hipLaunchKernelGGL((k_mass_flux<2, false>), dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   if (mface) hipLaunchKernelGGL(k_mass_flux_faces, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
   return hipGetLastError();
 }
@@ -565,9 +567,9 @@ extern "C" hipError_t ebit_launch_mass_flux(const Dims* d, double h, const doubl
 extern "C" hipError_t ebit_launch_mass_flux_many(int n, int dim, const FluxArgs* tab, const int* start, int blocks,
                                                  hipStream_t st) {
   if (dim == 3)
-    hipLaunchKernelGGL(k_mass_flux<3>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+    hipLaunchKernelGGL((k_mass_flux<3, true>), dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   else
-    hipLaunchKernelGGL(k_mass_flux<2>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+    hipLaunchKernelGGL((k_mass_flux<2, true>), dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 
@@ -616,16 +618,16 @@ extern "C" hipError_t ebit_launch_proj_rhs(const Dims* d, double h, const double
                                            const double* nF, const double* mdot, double* const ul[3],
                                            double* const uv[3], double* b, hipStream_t st) {
   ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nF, mdot, ul, uv, nullptr, b, nullptr);
-  hipLaunchKernelGGL(k_ghost_vel, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
-  hipLaunchKernelGGL(k_proj_rhs<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL(k_ghost_vel<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL((k_proj_rhs<false, false>), dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   return hipGetLastError();
 }
 
 // n cases' ghost velocities and right-hand sides, one launch each
 extern "C" hipError_t ebit_launch_proj_rhs_many(int n, const ProjArgs* tab, const int* start, int blocks,
                                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_ghost_vel, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
-  hipLaunchKernelGGL(k_proj_rhs<false>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_ghost_vel<true>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL((k_proj_rhs<false, true>), dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 
@@ -640,7 +642,7 @@ extern "C" hipError_t ebit_launch_proj_rhs_one(const Dims* d, double h, const do
   g.one = 1;
   g.cF = cF;
   g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
-  hipLaunchKernelGGL(k_proj_rhs<true>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL((k_proj_rhs<true, false>), dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   return hipGetLastError();
 }
 
@@ -653,8 +655,8 @@ extern "C" hipError_t ebit_launch_face_update_one(const Dims* d, double h, const
   g.one = 1;
   g.cF = cF;
   g.src = (1.0 / rho[0] - 1.0 / rho[1]) / (d->dim == 3 ? h * h * h : h * h);
-  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
-  hipLaunchKernelGGL(k_divmax<true>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL(k_face_update<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL((k_divmax<true, false>), dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(g));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
@@ -665,8 +667,8 @@ extern "C" hipError_t ebit_launch_face_update(const Dims* d, double h, const dou
                                               const double* const th[3], double* const ul[3], double* const uv[3],
                                               const double* p, double* partial, Scal* scal, hipStream_t st) {
   ProjArgs g = make_proj(d, h, rho, dt, pbc, pval, flags, th, nullptr, nullptr, ul, uv, p, nullptr, partial);
-  hipLaunchKernelGGL(k_face_update, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
-  hipLaunchKernelGGL(k_divmax<false>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL(k_face_update<false>, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+  hipLaunchKernelGGL((k_divmax<false, false>), dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(g));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return ebit_launch_finalize_max(partial, EBIT_RED_BLOCKS, scal, st);
@@ -677,7 +679,7 @@ extern "C" hipError_t ebit_launch_face_update(const Dims* d, double h, const dou
 // finalize entry reduces), one launch each
 extern "C" hipError_t ebit_launch_face_update_many(int n, const ProjArgs* tab, const int* start, int blocks,
                                                    const int* rstart, int rblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_face_update, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
-  hipLaunchKernelGGL(k_divmax<false>, dim3((unsigned)rblocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, rstart, n));
+  hipLaunchKernelGGL(k_face_update<true>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL((k_divmax<false, true>), dim3((unsigned)rblocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, rstart, n));
   return hipGetLastError();
 }

@@ -1587,9 +1587,10 @@ __device__ inline void build_cell_from_coarse(const CoarseOp<double>& op, const 
 
 // One level of both systems in one launch: blocks [0, nb) build the
 // heat system's cells, blocks [nb, 2 nb) the pressure system's.
+template <bool B>
 __global__ void k_build_from_fine2(Many<BuildFineArgs> m) {
   long long lb, nbc;
-  const BuildFineArgs a = many_case(m, lb, nbc);
+  const BuildFineArgs& a = many_case<B>(m, lb, nbc);
   const bool s1 = lb >= a.nb;
   const long long I = (lb - (s1 ? a.nb : 0u)) * blockDim.x + threadIdx.x;
   if (I >= a.o[0].cd.N) return;
@@ -1599,10 +1600,10 @@ __global__ void k_build_from_fine2(Many<BuildFineArgs> m) {
     build_cell_from_fine(a.op[0], a.o[0], I);
 }
 
-template <int DIM>
+template <int DIM, bool B>
 __global__ void k_build_from_coarse2(Many<BuildCoarseArgs> m) {
   long long lb, nbc;
-  const BuildCoarseArgs a = many_case(m, lb, nbc);
+  const BuildCoarseArgs& a = many_case<B>(m, lb, nbc);
   const bool s1 = lb >= a.nb;
   const long long I = (lb - (s1 ? a.nb : 0u)) * blockDim.x + threadIdx.x;
   if (I >= a.o[0].cd.N) return;
@@ -1743,12 +1744,12 @@ __device__ inline void build_small_level(const BuildTable& t, int l) {
   __syncthreads();
 }
 
-template <int DIM>
+template <int DIM, bool B>
 __global__ __launch_bounds__(1024) void k_build_small(Many<BuildSmallArgs> m) {
   __shared__ double A[EBIT_DENSE_MAX][EBIT_DENSE_MAX + 1];
   __shared__ double colb[2][EBIT_DENSE_MAX], rowb[2][EBIT_DENSE_MAX];
   long long lb, nbc;
-  const BuildSmallArgs a = many_case(m, lb, nbc);
+  const BuildSmallArgs& a = many_case<B>(m, lb, nbc);
   const BuildTable& t = ((const BuildTable*)a.tabs)[lb];
   const int ls = t.ls, nlev = t.nlev, dl = t.dl;
   const int upto = dl >= 0 ? dl + 1 : nlev;
@@ -1888,9 +1889,10 @@ __global__ void k_apply(FineOp op, const double* __restrict__ x, double* __restr
 }
 
 // heat right-hand side: b = rho cp/dt T* + interface and wall terms
+template <bool B>
 __global__ void k_heat_rhs(Many<HeatRhsArgs> m) {
   long long lb, nb;
-  const HeatRhsArgs a = many_case(m, lb, nb);
+  const HeatRhsArgs& a = many_case<B>(m, lb, nb);
   const FineOp& op = a.op;
   const double* __restrict__ Ts = a.Ts;
   double* __restrict__ b = a.b;
@@ -1933,9 +1935,10 @@ __device__ inline void reduce_partials(const double* __restrict__ partial, int n
 }
 
 // single-system reductions outside the solves (divergence maximum)
+template <bool B>
 __global__ void k_finalize(Many<FinArgs> m) {
   long long lb, nbc;
-  const FinArgs a = many_case(m, lb, nbc);
+  const FinArgs& a = many_case<B>(m, lb, nbc);
   double v[3];
   reduce_partials(a.partial, a.nb, a.nv, a.kind == FIN_MAX, v);
   if (threadIdx.x != 0) return;
@@ -1944,9 +1947,10 @@ __global__ void k_finalize(Many<FinArgs> m) {
 }
 
 // a case's status scalars: cleared (dst null) or copied to dst
+template <bool B>
 __global__ void k_scal(Many<ScalArgs> m) {
   long long lb, nbc;
-  const ScalArgs a = many_case(m, lb, nbc);
+  const ScalArgs& a = many_case<B>(m, lb, nbc);
   constexpr int W = (int)(sizeof(Scal) / sizeof(double));
   const double* src = (const double*)a.scal;
   double* dst = a.dst ? (double*)a.dst : (double*)a.scal;
@@ -2303,32 +2307,84 @@ __device__ inline void buf_store(double v, BufRsrc r, int off) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
+// The six other-colour neighbour values of slot sb (bytes) of cell
+// (i, j, k) in a colour-split half-sweep: wall sides read past the end of
+// the half (0); MODE 1 reads none (a zero start), MODE 2 adds the coarse
+// correction of each neighbour's level-1 parent.
+template <typename T, int MODE>
+__device__ inline void half3_nbrs(BufRsrc bxn, int Hb, int n0, int n1, int n2, int hw, int plane, bool p0, bool p1,
+                                  bool p2, int i, int j, int k, int par, int ih, int sb, bool ok,
+                                  gptr<const T> xc, int cn0, int cn1, T (&v)[6]) {
+  constexpr int TS = (int)sizeof(T);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) v[e] = (T)0;
+  if constexpr (MODE == 1) return;
+  const bool xm = i == 0, xp = i == n0 - 1, ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
+  const int dx0 = xm ? (p0 ? (hw - 1) * TS : Hb) : (par - 1) * TS;
+  const int dx1 = xp ? (p0 ? -ih * TS : Hb) : par * TS;
+  const int dy0 = ym ? (p1 ? hw * (n1 - 1) * TS : Hb) : -hw * TS;
+  const int dy1 = yp ? (p1 ? -hw * (n1 - 1) * TS : Hb) : hw * TS;
+  const int dz0 = zm ? (p2 ? plane * (n2 - 1) * TS : Hb) : -plane * TS;
+  const int dz1 = zp ? (p2 ? -plane * (n2 - 1) * TS : Hb) : plane * TS;
+  v[0] = buf_load<T>(bxn, sb + dx0);
+  v[1] = buf_load<T>(bxn, sb + dx1);
+  v[2] = buf_load<T>(bxn, sb + dy0);
+  v[3] = buf_load<T>(bxn, sb + dy1);
+  v[4] = buf_load<T>(bxn, sb + dz0);
+  v[5] = buf_load<T>(bxn, sb + dz1);
+  if constexpr (MODE == 2) {
+    if (ok) {
+      // parent cells of the neighbours on level 1 (the wrapped index on a
+      // periodic axis; any in-range cell beyond a wall, whose term is
+      // dropped)
+      const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
+      const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
+      const int km = zm ? n2 - 1 : k - 1, kp = zp ? 0 : k + 1;
+      const int pj = (j >> 1) * cn0, pk = (k >> 1) * cn0 * cn1;
+      const int pi = i >> 1;
+      const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
+                           pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
+                           pi + pj + (kp >> 1) * cn0 * cn1};
+      const bool h[6] = {!xm || p0, !xp || p0, !ym || p1, !yp || p1, !zm || p2, !zp || p2};
+      T e6[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) e6[e] = xc[par6[e]];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) v[e] = h[e] ? v[e] + e6[e] : (T)0;
+    }
+  }
+}
+
 // One colour of a red-black Gauss-Seidel sweep of the 3D fine level: every
 // cell of colour `color` takes its new value from the other colour's current
-// values.  first: the other colour is zero (the first half-sweep of a V-cycle
-// from a zero guess: no neighbour is read).  add_xc: the other colour's
-// values take the coarse-grid correction of their level-1 parent (the first
-// post-smoothing half-sweep; the correction of this colour's own values is
-// never needed, a Gauss-Seidel update does not read the old value).  Rows
-// and the neighbour sum are formed as in the LDS sweeps, so each new value
-// has the same bits as in a whole-grid half-sweep of the natural order.
+// values.  MODE 1: the other colour is zero (the first half-sweep of a
+// V-cycle from a zero guess: no neighbour is read).  MODE 2: the other
+// colour's values take the coarse-grid correction of their level-1 parent
+// (the first post-smoothing half-sweep; the correction of this colour's own
+// values is never needed, a Gauss-Seidel update does not read the old
+// value).  Rows and the neighbour sum are formed as in the LDS sweeps, so
+// each new value has the same bits as in a whole-grid half-sweep of the
+// natural order.
 //
 // A wave takes 64 consecutive slots of one row (j, k): in the colour-split
 // order the x-neighbours of slot s (cell i = 2 ih + par) are the other
 // colour's slots s + par - 1 and s + par, the y- and z-neighbours s -+ hw
 // and s -+ hw n1.  j, k and par are the same for the whole wave, so the y/z
 // offsets and their boundary cases are scalar; only the first and last cell
-// of a row wrap (periodic) or lose a neighbour (wall: it reads as 0).
-template <typename T>
-__global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __restrict__ cs,
-                                                       const CaseCtl* __restrict__ ctl, WorkList wl, int color,
-                                                       int first, int add_xc) {
+// of a row wrap (periodic) or lose a neighbour (wall: it reads as 0).  A
+// cell with a cut link or a wall side is queued in LDS and updated after
+// the work-group's tiles (every cell of a half-sweep reads only the other
+// colour, so the order is free): the tile loop then holds the constant-row
+// update alone.  Six waves per SIMD leave the compiler 80 VGPRs, enough to
+// keep a tile's loads in flight without spilling the row pointers.
+template <typename T, int MODE>
+__global__ __launch_bounds__(EBIT_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void kb_half3(
+    const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl, int color) {
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   if (!ctl[c].active) return;
   const SolveCase<T>& C = cs[c];
-  const FineOp op = C.op;
-  const Dims& d = op.d;
+  const Dims d = C.op.d;
   const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
   const int hw = (n0 + 1) >> 1;
   const int plane = hw * n1;
@@ -2338,13 +2394,18 @@ __global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __res
   const BufRsrc bxn = buf_rsrc(C.z[0] + (color ^ 1) * H, H * TS);
   const BufRsrc brv = buf_rsrc(C.rv + color * H, H * TS);
   const BufRsrc bfl = buf_rsrc(C.fs + color * H, H);
-  const gptr<const T> xc = (gptr<const T>)(add_xc ? (const T*)C.lx[1][0] : nullptr);
+  const gptr<const T> xc = (gptr<const T>)(MODE == 2 ? (const T*)C.lx[1][0] : nullptr);
   const int cn0 = C.lev[1].d.n[0], cn1 = C.lev[1].d.n[1];
   // the per-phase constant row, formed once per work-group and read back
   // from LDS (kept out of the per-cell code, where the compiler would
-  // otherwise divide again)
+  // otherwise divide again); the queue of cut and wall cells
   __shared__ RegularRow<T> srr;
-  if (threadIdx.x == 0) srr = regular_row<T>(op);
+  __shared__ int nq;
+  __shared__ int queue[SP_TPB * SP_TX * SP_TY];
+  if (threadIdx.x == 0) {
+    srr = regular_row<T>(C.op);
+    nq = 0;
+  }
   __syncthreads();
   const RegularRow<T> rr = srr;
   const bool p0 = d.per[0], p1 = d.per[1], p2 = d.per[2];
@@ -2356,8 +2417,6 @@ __global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __res
   // tile coordinates of the first tile, then stepped (the scalar unit is
   // shared by the CU's waves: no division per tile)
   int bx = t0 % gx, by = (t0 / gx) % gy, k = t0 / (gx * gy);
-  // a wall side's neighbour offset points past the end of the half, where
-  // a buffer load reads 0 (the value a wall term takes)
   const int Hb = (int)(H * TS);
   for (int tb = t0; tb < t1; ++tb) {
     if (tb > t0 && ++bx == gx) {
@@ -2373,63 +2432,45 @@ __global__ __launch_bounds__(EBIT_BLOCK) void kb_half3(const SolveCase<T>* __res
     const int i = 2 * ih + par;
     const bool ok = j < n1 && ih < hw && i < n0;
     // lanes with no cell load whatever their offset reads (nothing is stored)
-    const int sb = (hw * (j + n1 * k) + ih) * TS;
-    const uint8_t f = __builtin_amdgcn_raw_buffer_load_b8(bfl, sb / TS, 0, 0);
+    const int s = hw * (j + n1 * k) + ih;
+    const int sb = s * TS;
+    const uint8_t f = __builtin_amdgcn_raw_buffer_load_b8(bfl, s, 0, 0);
     const T rc = buf_load<T>(brv, sb);
-    const bool xm = i == 0, xp = i == n0 - 1;
-    // j and k are the wave's: the y and z cases are scalar
-    const bool ym = j == 0, yp = j == n1 - 1, zm = k == 0, zp = k == n2 - 1;
-    T v[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-    if (!first) {
-      const int dx0 = xm ? (p0 ? (hw - 1) * TS : Hb) : (par - 1) * TS;
-      const int dx1 = xp ? (p0 ? -ih * TS : Hb) : par * TS;
-      const int dy0 = ym ? (p1 ? hw * (n1 - 1) * TS : Hb) : -hw * TS;
-      const int dy1 = yp ? (p1 ? -hw * (n1 - 1) * TS : Hb) : hw * TS;
-      const int dz0 = zm ? (p2 ? plane * (n2 - 1) * TS : Hb) : -plane * TS;
-      const int dz1 = zp ? (p2 ? -plane * (n2 - 1) * TS : Hb) : plane * TS;
-      v[0] = buf_load<T>(bxn, sb + dx0);
-      v[1] = buf_load<T>(bxn, sb + dx1);
-      v[2] = buf_load<T>(bxn, sb + dy0);
-      v[3] = buf_load<T>(bxn, sb + dy1);
-      v[4] = buf_load<T>(bxn, sb + dz0);
-      v[5] = buf_load<T>(bxn, sb + dz1);
-      if (xc && ok) {
-        // parent cells of the neighbours on level 1 (the wrapped index on
-        // a periodic axis; any in-range cell beyond a wall, whose term is
-        // dropped)
-        const int im = xm ? n0 - 1 : i - 1, ip = xp ? 0 : i + 1;
-        const int jm = ym ? n1 - 1 : j - 1, jp = yp ? 0 : j + 1;
-        const int km = zm ? n2 - 1 : k - 1, kp = zp ? 0 : k + 1;
-        const int pj = (j >> 1) * cn0, pk = (k >> 1) * cn0 * cn1;
-        const int pi = i >> 1;
-        const int par6[6] = {(im >> 1) + pj + pk,       (ip >> 1) + pj + pk,       pi + (jm >> 1) * cn0 + pk,
-                             pi + (jp >> 1) * cn0 + pk, pi + pj + (km >> 1) * cn0 * cn1,
-                             pi + pj + (kp >> 1) * cn0 * cn1};
-        const bool h[6] = {!xm || p0, !xp || p0, !ym || p1, !yp || p1, !zm || p2, !zp || p2};
-        T e6[6];
-#pragma unroll
-        for (int e = 0; e < 6; ++e) e6[e] = xc[par6[e]];
-#pragma unroll
-        for (int e = 0; e < 6; ++e) v[e] = h[e] ? v[e] + e6[e] : (T)0;
-      }
-    }
+    T v[6];
+    half3_nbrs<T, MODE>(bxn, Hb, n0, n1, n2, hw, plane, p0, p1, p2, i, j, k, par, ih, sb, ok, xc, cn0, cn1, v);
     if (!ok) continue;
-    const bool wall = (!p0 && (xm || xp)) || (!p1 && (ym || yp)) || (!p2 && (zm || zp));
-    T x;
-    if (!(f & F_CUT) && !wall) {
-      const bool liq = (f & F_LIQ) != 0;
-      T xs = (v[0] + v[1]) + (v[2] + v[3]);
-      xs += v[4] + v[5];
-      x = (rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0);
-    } else {
-      T diag, off[6], mass, rb = 0;
-      fine_row<T>(op, i, j, k, f, diag, off, mass, rb);
-      T sum = rc - off[0] * v[0] - off[1] * v[1];
-      sum -= off[2] * v[2] + off[3] * v[3];
-      sum -= off[4] * v[4] + off[5] * v[5];
-      x = sum / diag;
+    const bool wall = (!p0 && (i == 0 || i == n0 - 1)) || (!p1 && (j == 0 || j == n1 - 1)) ||
+                      (!p2 && (k == 0 || k == n2 - 1));
+    if ((f & F_CUT) || wall) {
+      queue[atomicAdd(&nq, 1)] = s;
+      continue;
     }
-    buf_store(x, bxo, sb);
+    const bool liq = (f & F_LIQ) != 0;
+    T xs = (v[0] + v[1]) + (v[2] + v[3]);
+    xs += v[4] + v[5];
+    buf_store((rc + (liq ? rr.w1 : rr.w0) * xs) * (liq ? rr.inv1 : rr.inv0), bxo, sb);
+  }
+  __syncthreads();
+  const int nqc = nq;
+  if (nqc == 0) return;
+  const FineOp& op = C.op;
+  for (int q = threadIdx.x; q < nqc; q += blockDim.x) {
+    const int s = queue[q];
+    const int ih = s % hw, jk = s / hw;
+    const int j = jk % n1, kk = jk / n1;
+    const int par = (color + j + kk) & 1;
+    const int i = 2 * ih + par;
+    const int sb = s * TS;
+    const uint8_t f = __builtin_amdgcn_raw_buffer_load_b8(bfl, s, 0, 0);
+    const T rc = buf_load<T>(brv, sb);
+    T v[6];
+    half3_nbrs<T, MODE>(bxn, Hb, n0, n1, n2, hw, plane, p0, p1, p2, i, j, kk, par, ih, sb, true, xc, cn0, cn1, v);
+    T diag, off[6], mass, rb = 0;
+    fine_row<T>(op, i, j, kk, f, diag, off, mass, rb);
+    T sum = rc - off[0] * v[0] - off[1] * v[1];
+    sum -= off[2] * v[2] + off[3] * v[3];
+    sum -= off[4] * v[4] + off[5] * v[5];
+    buf_store(sum / diag, bxo, sb);
   }
 }
 
@@ -2490,9 +2531,10 @@ __global__ void kb_fine_restrict_split(const SolveCase<T>* __restrict__ cs, cons
 }
 
 // the cell flags in the colour-split order (padding slots of odd n0: 0)
+template <bool B>
 __global__ void k_split_flags(Many<SplitArgs> m) {
   long long lb, nb;
-  const SplitArgs a = many_case(m, lb, nb);
+  const SplitArgs& a = many_case<B>(m, lb, nb);
   const Dims& d = a.d;
   const uint8_t* __restrict__ flags = a.flags;
   uint8_t* __restrict__ fs = a.fs;
@@ -3182,7 +3224,7 @@ hipError_t ebit_launch_split_flags(const Dims* d, const uint8_t* flags, uint8_t*
   a.d = *d;
   a.flags = flags;
   a.fs = fsplit;
-  hipLaunchKernelGGL(k_split_flags, dim3(nblk(n)), dim3(EBIT_BLOCK), 0, st, many_one(a));
+  hipLaunchKernelGGL(k_split_flags<false>, dim3(nblk(n)), dim3(EBIT_BLOCK), 0, st, many_one(a));
   return hipGetLastError();
 }
 
@@ -3302,21 +3344,21 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
   BuildCoarseArgs coarse[EBIT_MAX_LEVELS];
   const int nc = ebit_build_args(op, lv, nlev, want32, ls, &fine, coarse);
   if (ls > 1 && nlev > 1)
-    hipLaunchKernelGGL(k_build_from_fine2, dim3(2 * fine.nb), dim3(EBIT_BLOCK), 0, st, many_one(fine));
+    hipLaunchKernelGGL(k_build_from_fine2<false>, dim3(2 * fine.nb), dim3(EBIT_BLOCK), 0, st, many_one(fine));
   for (int q = 0; q < nc; ++q) {
     if (lv[0].d.dim == 3)
-      hipLaunchKernelGGL(k_build_from_coarse2<3>, dim3(2 * coarse[q].nb), dim3(EBIT_BLOCK), 0, st,
+      hipLaunchKernelGGL((k_build_from_coarse2<3, false>), dim3(2 * coarse[q].nb), dim3(EBIT_BLOCK), 0, st,
                          many_one(coarse[q]));
     else
-      hipLaunchKernelGGL(k_build_from_coarse2<2>, dim3(2 * coarse[q].nb), dim3(EBIT_BLOCK), 0, st,
+      hipLaunchKernelGGL((k_build_from_coarse2<2, false>), dim3(2 * coarse[q].nb), dim3(EBIT_BLOCK), 0, st,
                          many_one(coarse[q]));
   }
   BuildSmallArgs a;
   a.tabs = dev_tabs;
   if (lv[0].d.dim == 3)
-    hipLaunchKernelGGL(k_build_small<3>, dim3(2), dim3(1024), 0, st, many_one(a));
+    hipLaunchKernelGGL((k_build_small<3, false>), dim3(2), dim3(1024), 0, st, many_one(a));
   else
-    hipLaunchKernelGGL(k_build_small<2>, dim3(2), dim3(1024), 0, st, many_one(a));
+    hipLaunchKernelGGL((k_build_small<2, false>), dim3(2), dim3(1024), 0, st, many_one(a));
   return hipGetLastError();
 }
 
@@ -3324,16 +3366,16 @@ hipError_t ebit_build_hierarchy(const FineOp* op, EbitLevelHost* lv, int nlev, i
 // offsets; blocks = start[n]).
 hipError_t ebit_launch_build_fine_many(int n, const BuildFineArgs* tab, const int* start, int blocks,
                                        hipStream_t st) {
-  hipLaunchKernelGGL(k_build_from_fine2, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_build_from_fine2<true>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 hipError_t ebit_launch_build_coarse_many(int n, int dim, const BuildCoarseArgs* tab, const int* start, int blocks,
                                          hipStream_t st) {
   if (dim == 3)
-    hipLaunchKernelGGL(k_build_from_coarse2<3>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st,
+    hipLaunchKernelGGL((k_build_from_coarse2<3, true>), dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st,
                        many_tab(tab, start, n));
   else
-    hipLaunchKernelGGL(k_build_from_coarse2<2>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st,
+    hipLaunchKernelGGL((k_build_from_coarse2<2, true>), dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st,
                        many_tab(tab, start, n));
   return hipGetLastError();
 }
@@ -3341,26 +3383,26 @@ hipError_t ebit_launch_build_coarse_many(int n, int dim, const BuildCoarseArgs* 
 hipError_t ebit_launch_build_small_many(int n, int dim, const BuildSmallArgs* tab, const int* start,
                                         hipStream_t st) {
   if (dim == 3)
-    hipLaunchKernelGGL(k_build_small<3>, dim3((unsigned)(2 * n)), dim3(1024), 0, st, many_tab(tab, start, n));
+    hipLaunchKernelGGL((k_build_small<3, true>), dim3((unsigned)(2 * n)), dim3(1024), 0, st, many_tab(tab, start, n));
   else
-    hipLaunchKernelGGL(k_build_small<2>, dim3((unsigned)(2 * n)), dim3(1024), 0, st, many_tab(tab, start, n));
+    hipLaunchKernelGGL((k_build_small<2, true>), dim3((unsigned)(2 * n)), dim3(1024), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 hipError_t ebit_launch_heat_rhs_many(int n, const HeatRhsArgs* tab, const int* start, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_heat_rhs, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_heat_rhs<true>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 // one block per case
 hipError_t ebit_launch_finalize_many(int n, const FinArgs* tab, const int* start, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)n), dim3(256), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_finalize<true>, dim3((unsigned)n), dim3(256), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 hipError_t ebit_launch_scal_many(int n, const ScalArgs* tab, const int* start, hipStream_t st) {
-  hipLaunchKernelGGL(k_scal, dim3((unsigned)n), dim3(64), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_scal<true>, dim3((unsigned)n), dim3(64), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 hipError_t ebit_launch_split_flags_many(int n, const SplitArgs* tab, const int* start, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_split_flags, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
+  hipLaunchKernelGGL(k_split_flags<true>, dim3((unsigned)blocks), dim3(EBIT_BLOCK), 0, st, many_tab(tab, start, n));
   return hipGetLastError();
 }
 
@@ -3374,7 +3416,7 @@ hipError_t ebit_launch_heat_rhs(const FineOp* op, const double* Ts, double* b, h
   a.op = *op;
   a.Ts = Ts;
   a.b = b;
-  hipLaunchKernelGGL(k_heat_rhs, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(a));
+  hipLaunchKernelGGL(k_heat_rhs<false>, dim3(EBIT_RED_BLOCKS), dim3(EBIT_BLOCK), 0, st, many_one(a));
   return hipGetLastError();
 }
 
@@ -3385,7 +3427,7 @@ hipError_t ebit_launch_finalize_max(const double* partial, int nb, Scal* sc, hip
   a.nv = 1;
   a.kind = FIN_MAX;
   a.sc = sc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, many_one(a));
+  hipLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(256), 0, st, many_one(a));
   return hipGetLastError();
 }
 
@@ -3764,8 +3806,12 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
   };
   // 3D: a sweep is two colour-split half-sweeps (red, then black)
   auto half = [&](int color, int first, int add) {
-    hipLaunchKernelGGL(kb_half3<T>, dim3(P.half.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, P.half.w, color, first,
-                       add);
+    if (first)
+      hipLaunchKernelGGL((kb_half3<T, 1>), dim3(P.half.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, P.half.w, color);
+    else if (add)
+      hipLaunchKernelGGL((kb_half3<T, 2>), dim3(P.half.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, P.half.w, color);
+    else
+      hipLaunchKernelGGL((kb_half3<T, 0>), dim3(P.half.blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl, P.half.w, color);
   };
   if (P.split) {
     {
