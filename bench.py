@@ -413,6 +413,25 @@ def host_cpu():
     return f"{name}, {os.cpu_count()} logical cores"
 
 
+def half_sweep_mix(schedule):
+    """Launches of each form of the 3D colour-split half-sweep in one
+    V-cycle: form 1 (the first half-sweep, from a zero guess: no iterate
+    read), form 2 (the first post-smoothing half-sweep: the other colour
+    takes its parent's coarse correction) and form 0 (the rest)."""
+    nu1, nu2 = (schedule or {}).get("nu1", 2), (schedule or {}).get("nu2", 2)
+    return {0: 2 * (nu1 + nu2) - 2, 1: 1, 2: 1}
+
+
+def half_sweep_bytes_per_cell(form, precision):
+    """Algorithmic bytes of one half-sweep launch per fine cell: half the
+    cells are updated, each reading the other colour's iterate (not in form
+    1), r and the flag and writing its iterate; form 2 also reads the level-1
+    correction (one coarse value per 8 fine cells)."""
+    sx = 4 if precision == "mixed" else 8
+    b = (sx + sx + 1 + sx) / 2.0 if form != 1 else (sx + 1 + sx) / 2.0
+    return b + (sx / 8.0 if form == 2 else 0.0)
+
+
 def sweeps_per_launch(dim, schedule):
     """Red-black sweeps one fine smoothing launch performs: on 2D grids the
     library runs the sweeps of a smoothing run in pairs (a run of nu sweeps
@@ -441,6 +460,11 @@ def roofline(case, precision, steps, tune=True):
         if bpc is not None:
             units = spl if name == "fine_smooth" else 1.0
             bytes_launch = bpc * case.ncells * units
+            if name == "fine_smooth" and case.dim == 3:
+                # the launch-weighted mean of the three half-sweep forms
+                mix = half_sweep_mix(sched)
+                bytes_launch = case.ncells * sum(n * half_sweep_bytes_per_cell(f, precision)
+                                                 for f, n in mix.items()) / sum(mix.values())
             rows[name]["algorithmic_bytes_per_launch"] = bytes_launch
             rows[name]["achieved_GBps"] = bytes_launch / avg_s / 1e9
             if name == "fine_smooth":
@@ -455,7 +479,13 @@ def roofline(case, precision, steps, tune=True):
         key = f"{case.name}:{precision}:{(KERNEL_NAMES_3D if case.dim == 3 else KERNEL_NAMES)[dom]}"
         ent = t.get("kernels", {}).get(key)
         if ent and t.get("source_digest") == kernel_source_digest():
-            traffic = ent["hbm_bytes_per_launch"]
+            if "hbm_bytes_per_launch_by_form" in ent:
+                # measured per form, weighted like the algorithmic bytes
+                mix = half_sweep_mix(sched)
+                by = ent["hbm_bytes_per_launch_by_form"]
+                traffic = sum(n * by[str(f)] for f, n in mix.items()) / sum(mix.values())
+            else:
+                traffic = ent["hbm_bytes_per_launch"]
     names = KERNEL_NAMES_3D if case.dim == 3 else KERNEL_NAMES
     ro = {"bound": "hbm", "kernel": names[dom], "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS,
           "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
