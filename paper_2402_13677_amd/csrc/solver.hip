@@ -2551,6 +2551,81 @@ __global__ void k_split_flags(Many<SplitArgs> m) {
   }
 }
 
+// Half-sweep of an explicit 3D coarse level l in the natural order, in
+// place on its iterate buffer 0: the cells of one colour ((i + j + k) & 1 ==
+// color) take their Gauss-Seidel update from the other colour's values.
+// One thread per slot (ih, j, k) of the colour (cell i = 2 ih + parity), so
+// a wave covers 64 consecutive cells of the colour and every thread works
+// alone: no barrier, all loads of a cell in flight together.  MODE 1: the
+// other colour is zero (the first half-sweep from the zero guess: only b and
+// the diagonal are read); MODE 2: the other colour's values take their
+// level l+1 parent's correction (the first post-smoothing half-sweep; this
+// colour's corrected values are never needed); MODE 0: plain.  Every axis
+// that is periodic has even length (a same-colour neighbour across the seam
+// would be read while it is written): the plan uses the LDS z-march kernel
+// on the other levels.
+template <typename T, int MODE>
+__global__ __launch_bounds__(EBIT_BLOCK) void kb_chalf(const SolveCase<T>* __restrict__ cs,
+                                                       const CaseCtl* __restrict__ ctl, WorkList wl, int l,
+                                                       int color) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const CoarseOp<T>& op = C.lev[l];
+  const Dims d = op.d;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const unsigned hw = (unsigned)(n0 + 1) >> 1;
+  const unsigned slots = hw * (unsigned)n1 * (unsigned)n2;
+  const T* __restrict__ b = C.lb[l];
+  T* __restrict__ x = C.lx[l][0];
+  const T* __restrict__ xc = MODE == 2 ? (const T*)C.lx[l + 1][0] : nullptr;
+  const Dims cd = C.lev[l + 1].d;
+  const int s1 = n0, s2 = n0 * n1;
+  for (unsigned t = (unsigned)xcd_tile(lb, nb) * blockDim.x + threadIdx.x; t < slots;
+       t += (unsigned)nb * blockDim.x) {
+    const unsigned ih = t % hw, jk = t / hw;
+    const int j = (int)(jk % (unsigned)n1), k = (int)(jk / (unsigned)n1);
+    const int i = 2 * (int)ih + ((color + j + k) & 1);
+    if (i >= n0) continue;
+    const int q = i + s1 * j + s2 * k;
+    // the six sides -x +x -y +y -z +z: the neighbour's coordinate (wrapped;
+    // across a wall it names a cell whose value is not used), whether the
+    // side couples (not across a wall, not along an axis of one cell) and
+    // its coefficient (the lower side's is stored at the neighbour)
+    const int ia[3] = {i, j, k}, st[3] = {1, s1, s2}, ln[3] = {n0, n1, n2};
+    int nc[6], nq[6];
+    bool has[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const bool one = ln[a] < 2;
+      nc[2 * a] = ia[a] > 0 ? ia[a] - 1 : ln[a] - 1;
+      nc[2 * a + 1] = ia[a] + 1 < ln[a] ? ia[a] + 1 : 0;
+      nq[2 * a] = q + (nc[2 * a] - ia[a]) * st[a];
+      nq[2 * a + 1] = q + (nc[2 * a + 1] - ia[a]) * st[a];
+      has[2 * a] = !one && (ia[a] > 0 || d.per[a]);
+      has[2 * a + 1] = !one && (ia[a] + 1 < ln[a] || d.per[a]);
+    }
+    T off[6], v[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      off[e] = has[e] ? ((e & 1) ? op.off[e >> 1][q] : op.off[e >> 1][nq[e]]) : (T)0;
+      v[e] = (T)0;
+      if (MODE != 1 && has[e]) {
+        v[e] = x[nq[e]];
+        if (MODE == 2) {
+          const int pi = (e >> 1) == 0 ? nc[e] : i, pj = (e >> 1) == 1 ? nc[e] : j, pk = (e >> 1) == 2 ? nc[e] : k;
+          v[e] += xc[cell_index(cd, pi >> 1, pj >> 1, pk >> 1)];
+        }
+      }
+    }
+    T sum = b[q] - off[0] * v[0] - off[1] * v[1];
+    sum -= off[2] * v[2] + off[3] * v[3];
+    sum -= off[4] * v[4] + off[5] * v[5];
+    x[q] = sum / op.diag[q];
+  }
+}
+
 // the same from explicit level l to level l + 1
 template <typename T>
 __global__ void kb_coarse_restrict(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl, WorkList wl,
@@ -3637,7 +3712,7 @@ struct PCarver {
 };
 
 constexpr int PLAN_MAX_K = 16;                     // outer iterations per graph block
-constexpr int PLAN_LISTS = 6 + 2 * EBIT_MAX_LEVELS;  // work lists of a plan
+constexpr int PLAN_LISTS = 6 + 3 * EBIT_MAX_LEVELS;  // work lists of a plan
 
 struct HostList {
   WorkList w;
@@ -3663,6 +3738,10 @@ struct PlanT {
   HostList hrestrict;  // 3D: their restriction (tiles of level 1)
   HostList pupd;       // 3D split: the p-update (tiles of the natural order)
   HostList coarse[EBIT_MAX_LEVELS], crestrict[EBIT_MAX_LEVELS];
+  // 3D split: coarse levels smoothed by natural-order half-sweeps (every
+  // periodic axis of even length in every case), and their work lists
+  bool chalf_on[EBIT_MAX_LEVELS] = {};
+  HostList chalf[EBIT_MAX_LEVELS];
   size_t tail_bytes = 0;
   hipStream_t ist = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -3835,10 +3914,31 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
                          P.frestrict.w, preb);
     }
   }
+  // 3D coarse levels of even periodic lengths: half-sweeps in place on
+  // buffer 0 (red, then black), like the fine level
+  auto chalf = [&](int l, int color, int mode) {
+    const dim3 g(P.chalf[l].blocks), b(EBIT_BLOCK);
+    if (mode == 1)
+      hipLaunchKernelGGL((kb_chalf<T, 1>), g, b, 0, st, cs, ctl, P.chalf[l].w, l, color);
+    else if (mode == 2)
+      hipLaunchKernelGGL((kb_chalf<T, 2>), g, b, 0, st, cs, ctl, P.chalf[l].w, l, color);
+    else
+      hipLaunchKernelGGL((kb_chalf<T, 0>), g, b, 0, st, cs, ctl, P.chalf[l].w, l, color);
+  };
   for (int l = 1; l < P.Lmax; ++l) {
     auto coarse = [&](int in, int out, int add, int nsw, int res) {
       launch_coarse(P, cs, l, in, out, add, nsw, res, st);
     };
+    if (P.chalf_on[l]) {
+      ProfScope ps(pf, EBIT_KC_COARSE, st, 2 * nu1 + 1);
+      for (int sw = 0; sw < nu1; ++sw) {
+        chalf(l, 0, sw == 0 ? 1 : 0);
+        chalf(l, 1, 0);
+      }
+      hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                         P.crestrict[l].w, l, 0);
+      continue;
+    }
     {
       ProfScope ps(pf, EBIT_KC_COARSE, st, npre);
       sweep_run(nu1, 1, m, -1, 0, pairs, fuse, coarse);
@@ -3860,6 +3960,14 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
     auto coarse = [&](int in, int out, int add, int nsw, int res) {
       launch_coarse(P, cs, l, in, out, add, nsw, res, st);
     };
+    if (P.chalf_on[l]) {
+      ProfScope ps(pf, EBIT_KC_COARSE, st, 2 * nu2);
+      for (int sw = 0; sw < nu2; ++sw) {
+        chalf(l, 0, sw == 0 ? 2 : 0);
+        chalf(l, 1, 0);
+      }
+      continue;
+    }
     ProfScope ps(pf, EBIT_KC_COARSE, st, npost);
     sweep_run(nu2, npre + 1, m, preb, 1, pairs, 0, coarse);
   }
@@ -4020,7 +4128,16 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
   P->split = P->dim == 3;
   for (int c = 0; c < n; ++c)
     if (cases[c].lv[0].d.N * (long long)sizeof(double) >= (1LL << 31)) P->split = false;
-  std::vector<std::pair<int, int>> ecs[EBIT_MAX_LEVELS], ecr[EBIT_MAX_LEVELS];
+  std::vector<std::pair<int, int>> ecs[EBIT_MAX_LEVELS], ecr[EBIT_MAX_LEVELS], ech[EBIT_MAX_LEVELS];
+  for (int l = 1; l < P->Lmax; ++l) {
+    P->chalf_on[l] = P->split;
+    for (int c = 0; c < n; ++c) {
+      if (l >= lt[c]) continue;
+      const Dims& d = cases[c].lv[l].d;
+      for (int a = 0; a < 3; ++a)
+        if (d.per[a] && d.n[a] > 1 && (d.n[a] & 1)) P->chalf_on[l] = false;
+    }
+  }
   for (int sys = 0; sys < 2; ++sys)
     for (int c = 0; c < n; ++c) {
       const EbitPlanCase& pc = cases[c];
@@ -4111,6 +4228,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
           const Dims& d = pc.lv[l].d;
           ecs[l].push_back({c, C.lgx[l] * C.lgy[l] * ((d.n[2] + C.lzc[l] - 1) / C.lzc[l])});
           ecr[l].push_back({c, (int)nblk(pc.lv[l + 1].d.N)});
+          ech[l].push_back({c, P->chalf_on[l] ? (int)nblk((long long)((d.n[0] + 1) / 2) * d.n[1] * d.n[2]) : 0});
         }
       }
     }
@@ -4124,6 +4242,7 @@ hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const eb
   for (int l = 1; l < P->Lmax; ++l) {
     P->coarse[l] = make_list(ecs[l], host, d_wl);
     P->crestrict[l] = make_list(ecr[l], host, d_wl);
+    P->chalf[l] = make_list(ech[l], host, d_wl);
   }
   if ((e = hipMemcpyAsync(d_wl, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, P->ist)) != hipSuccess)
     return e;
