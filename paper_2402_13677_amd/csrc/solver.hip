@@ -520,19 +520,21 @@ __device__ inline void fine_store_rf(const T (&r)[FineTile<TX, TY>::NQ], const u
 template <typename T>
 struct RegularRow {
   T w0, w1, inv0, inv1;  // per phase (0 vapour, 1 liquid)
+  T dg0, dg1;            // the diagonal dg of each phase
 };
 
 template <typename T>
 __device__ inline RegularRow<T> regular_row(const FineOp& op) {
   const T ih2 = (T)op.ih2;
-  T w[2], inv[2];
+  T w[2], inv[2], dgs[2];
   for (int ph = 0; ph < 2; ++ph) {
     w[ph] = (T)op.coef[ph] * ih2;
     T dg = (op.sys == EBIT_SYS_HEAT) ? (T)op.mass[ph] : (T)0;
     for (int s = 0; s < 2 * op.d.dim; ++s) dg += w[ph];
+    dgs[ph] = dg;
     inv[ph] = (T)1 / dg;
   }
-  return RegularRow<T>{w[0], w[1], inv[0], inv[1]};
+  return RegularRow<T>{w[0], w[1], inv[0], inv[1], dgs[0], dgs[1]};
 }
 
 // Update this thread's cells of one colour of plane k (slots from
@@ -2476,56 +2478,101 @@ __global__ __launch_bounds__(EBIT_BLOCK) __attribute__((amdgpu_waves_per_eu(size
 
 // Residual + restriction of the 3D fine level in the colour-split order:
 // after a pre-smoothing that ends with the black half-sweep only the red
-// children carry a residual (even_child), r - A x as fine_residual_at forms
-// it; also clears the level-1 iterate.  One thread per coarse cell, in
-// tiles of the coarse grid.
+// children carry a residual (even_child), r - A x with A's row as
+// fine_row forms it; also clears the level-1 iterate.  One thread per
+// coarse cell, in tiles of the coarse grid: a red child (i, j, k) of coarse
+// cell ci is slot hw (j + n1 k) + ci of colour 0, so a wave's children are
+// consecutive slots, and its black neighbours are read as in kb_half3
+// (beyond a wall: 0).  The loads of the four children are issued together;
+// a regular child (no cut link, no wall side) takes the per-phase constant
+// row, the others fine_row in a second pass.
 template <typename T>
-__global__ void kb_fine_restrict_split(const SolveCase<T>* __restrict__ cs, const CaseCtl* __restrict__ ctl,
-                                       WorkList wl) {
+__global__ __launch_bounds__(EBIT_BLOCK) void kb_fine_restrict_split(const SolveCase<T>* __restrict__ cs,
+                                                                     const CaseCtl* __restrict__ ctl,
+                                                                     WorkList wl) {
   int lb, nb;
   const int c = wl_find(wl, lb, nb);
   if (!ctl[c].active) return;
   const SolveCase<T>& C = cs[c];
-  const FineOp op = C.op;
-  const Dims& d = op.d;
+  const FineOp& op = C.op;
+  const Dims d = op.d;
   const Dims cd = C.lev[1].d;
-  const int hw = (d.n[0] + 1) >> 1;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const int hw = (n0 + 1) >> 1;
+  const int plane = hw * n1;
   const long long H = split_half(d);
-  const T* z = C.z[0];
-  const T* rv = C.rv;
-  const uint8_t* fl = C.fs;
+  constexpr int TS = (int)sizeof(T);
+  const BufRsrc bz0 = buf_rsrc(C.z[0], H * TS);
+  const BufRsrc bz1 = buf_rsrc(C.z[0] + H, H * TS);
+  const BufRsrc brv = buf_rsrc(C.rv, H * TS);
+  const BufRsrc bfl = buf_rsrc(C.fs, H);
+  const int Hb = (int)(H * TS);
+  const bool p0 = d.per[0], p1 = d.per[1], p2 = d.per[2];
+  const RegularRow<T> rr = regular_row<T>(op);
   T* bc = C.lb[1];
   T* xcz = C.lx[1][0];
+  const bool tail = C.lt == 1;
   const int tiles = split_tiles(cd.n[0], cd.n[1], cd.n[2]);
   const int t0 = xcd_tile(lb, nb) * SP_TPB_R, t1 = min(t0 + SP_TPB_R, tiles);
   for (int t = t0; t < t1; ++t) {
     int ci, cj, ck;
     split_tile(t, cd.n[0], cd.n[1], ci, cj, ck);
     if (ci >= cd.n[0] || cj >= cd.n[1]) continue;
-    T sum = 0;
+    T r[4], v[4][6], zc[4];
+    uint8_t f[4];
+    bool ok[4];
+#pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
       int di, dj, dk;
       even_child(ch, di, dj, dk);
       const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
-      if (i < d.n[0] && j < d.n[1] && k < d.n[2]) {
-        const long long sc = split_index(d, H, i, j, k);  // colour 0
-        long long q[6];
-        int ni[6], nj[6], nk[6];
-        split_nbrs(d, hw, i, j, k, sc, q, ni, nj, nk);
-        T xn[6];
+      ok[ch] = i < n0 && j < n1 && k < n2;
+      // a child beyond an odd length reads whatever its offset names (the
+      // buffer bounds keep it inside) and is dropped
+      const int sl = hw * (j + n1 * k) + ci;
+      const int sb = sl * TS;
+      f[ch] = __builtin_amdgcn_raw_buffer_load_b8(bfl, sl, 0, 0);
+      r[ch] = buf_load<T>(brv, sb);
+      zc[ch] = buf_load<T>(bz0, sb);
+      half3_nbrs<T, 0>(bz1, Hb, n0, n1, n2, hw, plane, p0, p1, p2, i, j, k, (j + k) & 1, ci, sb, ok[ch], nullptr,
+                       0, 0, v[ch]);
+    }
+    int slow = 0;
 #pragma unroll
-        for (int e = 0; e < 6; ++e) xn[e] = q[e] >= 0 ? z[H + q[e]] : (T)0;
-        T diag, off[6], mass, rb = 0;
-        fine_row<T>(op, i, j, k, fl[sc], diag, off, mass, rb);
-        T r = rv[sc] - diag * z[sc];
-#pragma unroll
-        for (int e = 0; e < 6; ++e)
-          if (off[e] != (T)0) r -= off[e] * xn[e];
-        sum += r;
+    for (int ch = 0; ch < 4; ++ch) {
+      int di, dj, dk;
+      even_child(ch, di, dj, dk);
+      const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+      const bool wall = (!p0 && (i == 0 || i == n0 - 1)) || (!p1 && (j == 0 || j == n1 - 1)) ||
+                        (!p2 && (k == 0 || k == n2 - 1));
+      if (!ok[ch]) {
+        r[ch] = (T)0;
+      } else if ((f[ch] & F_CUT) || wall) {
+        slow |= 1 << ch;
+      } else {
+        const bool liq = (f[ch] & F_LIQ) != 0;
+        T xs = (v[ch][0] + v[ch][1]) + (v[ch][2] + v[ch][3]);
+        xs += v[ch][4] + v[ch][5];
+        r[ch] = r[ch] - (liq ? rr.dg1 : rr.dg0) * zc[ch] + (liq ? rr.w1 : rr.w0) * xs;
       }
     }
-    const long long I = ci + (long long)cd.n[0] * (cj + (long long)cd.n[1] * ck);
-    bc[C.lt == 1 ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = sum;
+    if (slow) {
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        if (!(slow & (1 << ch))) continue;
+        int di, dj, dk;
+        even_child(ch, di, dj, dk);
+        const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+        T diag, off[6], mass, rb = 0;
+        fine_row<T>(op, i, j, k, f[ch], diag, off, mass, rb);
+        T x = r[ch] - diag * zc[ch];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) x -= off[e] * v[ch][e];
+        r[ch] = x;
+      }
+    }
+    const int I = ci + cd.n[0] * (cj + cd.n[1] * ck);
+    bc[tail ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = (r[0] + r[1]) + (r[2] + r[3]);
     xcz[I] = (T)0;
   }
 }
@@ -2549,6 +2596,38 @@ __global__ void k_split_flags(Many<SplitArgs> m) {
     const int i = 2 * ih + ((color + j + k) & 1);
     fs[t] = i < d.n[0] ? flags[i + (long long)d.n[0] * jk] : (uint8_t)0;
   }
+}
+
+// The six sides -x +x -y +y -z +z of cell (i, j, k) (offset q) of a 3D
+// explicit level: the neighbour's coordinate along the side's axis (wrapped;
+// across a wall it names a cell whose value is not used), its offset,
+// whether the side couples (not across a wall, not along an axis of one
+// cell) and the coupling (the lower side's is stored at the neighbour).
+template <typename T>
+struct CoarseSides {
+  int nc[6], nq[6];
+  bool has[6];
+  T off[6];
+};
+
+template <typename T>
+__device__ inline void coarse_sides(const CoarseOp<T>& op, const Dims& d, int i, int j, int k, int q,
+                                    CoarseSides<T>& S) {
+  const int ia[3] = {i, j, k}, ln[3] = {d.n[0], d.n[1], d.n[2]};
+  const int st[3] = {1, d.n[0], d.n[0] * d.n[1]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const bool one = ln[a] < 2;
+    S.nc[2 * a] = ia[a] > 0 ? ia[a] - 1 : ln[a] - 1;
+    S.nc[2 * a + 1] = ia[a] + 1 < ln[a] ? ia[a] + 1 : 0;
+    S.nq[2 * a] = q + (S.nc[2 * a] - ia[a]) * st[a];
+    S.nq[2 * a + 1] = q + (S.nc[2 * a + 1] - ia[a]) * st[a];
+    S.has[2 * a] = !one && (ia[a] > 0 || d.per[a]);
+    S.has[2 * a + 1] = !one && (ia[a] + 1 < ln[a] || d.per[a]);
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e)
+    S.off[e] = S.has[e] ? ((e & 1) ? op.off[e >> 1][q] : op.off[e >> 1][S.nq[e]]) : (T)0;
 }
 
 // Half-sweep of an explicit 3D coarse level l in the natural order, in
@@ -2581,48 +2660,84 @@ __global__ __launch_bounds__(EBIT_BLOCK) void kb_chalf(const SolveCase<T>* __res
   T* __restrict__ x = C.lx[l][0];
   const T* __restrict__ xc = MODE == 2 ? (const T*)C.lx[l + 1][0] : nullptr;
   const Dims cd = C.lev[l + 1].d;
-  const int s1 = n0, s2 = n0 * n1;
   for (unsigned t = (unsigned)xcd_tile(lb, nb) * blockDim.x + threadIdx.x; t < slots;
        t += (unsigned)nb * blockDim.x) {
     const unsigned ih = t % hw, jk = t / hw;
     const int j = (int)(jk % (unsigned)n1), k = (int)(jk / (unsigned)n1);
     const int i = 2 * (int)ih + ((color + j + k) & 1);
     if (i >= n0) continue;
-    const int q = i + s1 * j + s2 * k;
-    // the six sides -x +x -y +y -z +z: the neighbour's coordinate (wrapped;
-    // across a wall it names a cell whose value is not used), whether the
-    // side couples (not across a wall, not along an axis of one cell) and
-    // its coefficient (the lower side's is stored at the neighbour)
-    const int ia[3] = {i, j, k}, st[3] = {1, s1, s2}, ln[3] = {n0, n1, n2};
-    int nc[6], nq[6];
-    bool has[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const bool one = ln[a] < 2;
-      nc[2 * a] = ia[a] > 0 ? ia[a] - 1 : ln[a] - 1;
-      nc[2 * a + 1] = ia[a] + 1 < ln[a] ? ia[a] + 1 : 0;
-      nq[2 * a] = q + (nc[2 * a] - ia[a]) * st[a];
-      nq[2 * a + 1] = q + (nc[2 * a + 1] - ia[a]) * st[a];
-      has[2 * a] = !one && (ia[a] > 0 || d.per[a]);
-      has[2 * a + 1] = !one && (ia[a] + 1 < ln[a] || d.per[a]);
-    }
-    T off[6], v[6];
+    const int q = i + n0 * (int)jk;
+    CoarseSides<T> S;
+    coarse_sides<T>(op, d, i, j, k, q, S);
+    T v[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-      off[e] = has[e] ? ((e & 1) ? op.off[e >> 1][q] : op.off[e >> 1][nq[e]]) : (T)0;
       v[e] = (T)0;
-      if (MODE != 1 && has[e]) {
-        v[e] = x[nq[e]];
+      if (MODE != 1 && S.has[e]) {
+        v[e] = x[S.nq[e]];
         if (MODE == 2) {
-          const int pi = (e >> 1) == 0 ? nc[e] : i, pj = (e >> 1) == 1 ? nc[e] : j, pk = (e >> 1) == 2 ? nc[e] : k;
+          const int a = e >> 1;
+          const int pi = a == 0 ? S.nc[e] : i, pj = a == 1 ? S.nc[e] : j, pk = a == 2 ? S.nc[e] : k;
           v[e] += xc[cell_index(cd, pi >> 1, pj >> 1, pk >> 1)];
         }
       }
     }
-    T sum = b[q] - off[0] * v[0] - off[1] * v[1];
-    sum -= off[2] * v[2] + off[3] * v[3];
-    sum -= off[4] * v[4] + off[5] * v[5];
+    T sum = b[q] - S.off[0] * v[0] - S.off[1] * v[1];
+    sum -= S.off[2] * v[2] + S.off[3] * v[3];
+    sum -= S.off[4] * v[4] + S.off[5] * v[5];
     x[q] = sum / op.diag[q];
+  }
+}
+
+// Restricted residual of a 3D level smoothed by kb_chalf (iterate in buffer
+// 0): after the black half-sweep only the red children carry a residual,
+// summed in the order of even_child; also clears the level l+1 iterate.
+// One thread per cell of level l+1, the loads of its four children issued
+// together.
+template <typename T>
+__global__ __launch_bounds__(EBIT_BLOCK) void kb_chalf_restrict(const SolveCase<T>* __restrict__ cs,
+                                                                const CaseCtl* __restrict__ ctl, WorkList wl,
+                                                                int l) {
+  int lb, nb;
+  const int c = wl_find(wl, lb, nb);
+  if (!ctl[c].active) return;
+  const SolveCase<T>& C = cs[c];
+  const CoarseOp<T>& op = C.lev[l];
+  const Dims d = op.d;
+  const Dims cd = C.lev[l + 1].d;
+  const T* __restrict__ b = C.lb[l];
+  const T* __restrict__ x = C.lx[l][0];
+  T* bc = C.lb[l + 1];
+  T* xcz = C.lx[l + 1][0];
+  const bool tail = C.lt == l + 1;
+  const unsigned cn0 = (unsigned)cd.n[0], cn1 = (unsigned)cd.n[1];
+  const unsigned ncell = cn0 * cn1 * (unsigned)cd.n[2];
+  for (unsigned I = (unsigned)xcd_tile(lb, nb) * blockDim.x + threadIdx.x; I < ncell;
+       I += (unsigned)nb * blockDim.x) {
+    const unsigned cjk = I / cn0;
+    const int ci = (int)(I - cjk * cn0), cj = (int)(cjk % cn1), ck = (int)(cjk / cn1);
+    T r[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      int di, dj, dk;
+      even_child(ch, di, dj, dk);
+      const int i = 2 * ci + di, j = 2 * cj + dj, k = 2 * ck + dk;
+      r[ch] = (T)0;
+      if (i < d.n[0] && j < d.n[1] && k < d.n[2]) {
+        const int q = i + d.n[0] * (j + d.n[1] * k);
+        CoarseSides<T> S;
+        coarse_sides<T>(op, d, i, j, k, q, S);
+        T v[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = S.has[e] ? x[S.nq[e]] : (T)0;
+        T sum = b[q] - op.diag[q] * x[q] - S.off[0] * v[0] - S.off[1] * v[1];
+        sum -= S.off[2] * v[2] + S.off[3] * v[3];
+        sum -= S.off[4] * v[4] + S.off[5] * v[5];
+        r[ch] = sum;
+      }
+    }
+    bc[tail ? tail_el(cd, tail_half(cd), ci, cj, ck) : I] = (r[0] + r[1]) + (r[2] + r[3]);
+    xcz[I] = (T)0;
   }
 }
 
@@ -3935,8 +4050,8 @@ void vcycle_b(const PlanT<T>& P, const SolveCase<T>* cs, hipStream_t st, EbitPro
         chalf(l, 0, sw == 0 ? 1 : 0);
         chalf(l, 1, 0);
       }
-      hipLaunchKernelGGL(kb_coarse_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
-                         P.crestrict[l].w, l, 0);
+      hipLaunchKernelGGL(kb_chalf_restrict<T>, dim3(P.crestrict[l].blocks), dim3(EBIT_BLOCK), 0, st, cs, ctl,
+                         P.crestrict[l].w, l);
       continue;
     }
     {
