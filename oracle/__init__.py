@@ -29,11 +29,14 @@ approach for phase change: the EBIT method") defines on a uniform grid:
   advect.py    interfacial velocity at cell centres (Eq. jump_interfacial_vel)
                and at markers (bilinear), EBIT marker motion in 1D passes
                with the circle-fit re-intersection (Sec. 2.1, 2D)
+  energy.py    the advection step of the energy equation: explicit Euler
+               with third-order WENO derivatives, per phase (Eq.
+               energy_advection)
   closed.py    closed forms used as pins (Stefan problem, Sec. 3.1)
 
 Parity unpinned: the 3D facet rule beyond planar exactness (the paper's EBIT
 is 2D only), saddle cells, and the first-order fallback of the mass-flux
 stencil.  Every other function is pinned by tests under tests/.
 """
-from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid, mg, advect  # noqa: F401
+from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid, mg, advect, energy  # noqa: F401
 from .geometry import GeometryError  # noqa: F401
