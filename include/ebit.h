@@ -20,6 +20,8 @@
  *   ebit_interface_velocity, ebit_advect_markers
  *                      the interfacial velocity (Eq. jump_interfacial_vel)
  *                      and the EBIT marker motion of one time step (Sec. 2.1)
+ *   ebit_advect_energy the advection step of the energy equation (Eq.
+ *                      energy_advection): explicit Euler, WENO3 derivatives
  *
  * Conventions (all calls):
  *   - Every array argument is a DEVICE pointer owned by the caller, contiguous,
@@ -294,6 +296,34 @@ ebit_status ebit_interface_velocity(ebit_ctx* ctx, const double* const u_l[3], c
  * colour arrays are unspecified. */
 ebit_status ebit_advect_markers(ebit_ctx* ctx, const double* const u_gamma[3], double* const marker[3],
                                 uint8_t* vertex_colour, uint8_t* cell_colour, double dt);
+
+/* Sec. 2.4, Eq. energy_advection: the intermediate temperature T* of one
+ * explicit Euler step of dT/dt + u . grad T = 0 in each phase (2D and 3D):
+ *   T*[c] = T_k[c] - dt * (u_0 D_0 + u_1 D_1 + u_2 D_2),
+ * with k the cell's colour (cell_colour 1: T_liq and u_l; 0: T_vap and u_v),
+ * u_a the mean of the cell's two a-faces in u_k, and D_a the third-order
+ * WENO derivative of Jiang & Shu (1996): the difference over h of the
+ * values at the cell's two a-faces, each reconstructed from the upwind side
+ * given by the sign of u_a (stencils (m, 0) and (0, p), linear weights 1/3
+ * and 2/3, smoothness (T_0 - T_m)^2 and (T_p - T_0)^2, weights
+ * d_r / (eps + beta_r)^2).  A zero component contributes nothing.  A
+ * stencil cell beyond a wall takes the value of the nearest cell inside;
+ * periodic axes wrap.  Every stencil reads one phase's field, so T_liq must
+ * hold liquid values two cells into the vapour near the interface and T_vap
+ * vapour values two cells into the liquid (Eq. extrapolation: ebit_extend
+ * with EBIT_EXT_LIQ_TO_VAP / EBIT_EXT_VAP_TO_LIQ).
+ * T_liq, T_vap, T_star: cells; u_l[a], u_v[a] (a < dim): axis-a face arrays;
+ * cell_colour: uint8 per cell.  All device, caller-owned; T_star must not be
+ * T_liq or T_vap (neighbours are read while cells are written).  eps: the
+ * WENO regulariser (Jiang & Shu: 1e-6).  No stability check: the caller
+ * keeps |u_a| dt / h small (the explicit step).  The call does not need
+ * ebit_build_coeffs and is asynchronous on the context stream.
+ * Errors: EBIT_EINVAL for a NULL pointer (among the first dim face arrays),
+ * T_star equal to an input, dt negative or not finite, eps not positive or
+ * not finite. */
+ebit_status ebit_advect_energy(ebit_ctx* ctx, const double* T_liq, const double* T_vap, const double* const u_l[3],
+                               const double* const u_v[3], const uint8_t* cell_colour, double dt, double eps,
+                               double* T_star);
 
 /* ---- inspection entry points (same conventions) --------------------------- */
 

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.hip", "geometry.hip", "solver.hip", "physics.hip", "extend.hip", "advect.hip"]
+SOURCES = ["api.hip", "geometry.hip", "solver.hip", "physics.hip", "extend.hip", "advect.hip", "energy.hip"]
 LIB = os.path.join(HERE, "libebit.so")
 
 HIPCC_FLAGS = [

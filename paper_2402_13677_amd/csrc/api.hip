@@ -953,6 +953,25 @@ ebit_status ebit_interface_velocity(ebit_ctx* c, const double* const u_l[3], con
   return EBIT_OK;
 }
 
+ebit_status ebit_advect_energy(ebit_ctx* c, const double* T_liq, const double* T_vap, const double* const u_l[3],
+                               const double* const u_v[3], const uint8_t* cell_colour, double dt, double eps,
+                               double* T_star) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  const int dim = c->fd.dim;
+  if (!T_liq || !T_vap || !u_l || !u_v || !cell_colour || !T_star) return fail(c, EBIT_EINVAL, "NULL argument");
+  for (int a = 0; a < dim; ++a)
+    if (!u_l[a] || !u_v[a]) return fail(c, EBIT_EINVAL, "NULL face field");
+  if (T_star == T_liq || T_star == T_vap) return fail(c, EBIT_EINVAL, "T_star must not be an input field");
+  if (!(dt >= 0.0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be finite and >= 0");
+  if (!(eps > 0.0) || !isfinite(eps)) return fail(c, EBIT_EINVAL, "eps must be finite and > 0");
+  const double* ul[3] = {u_l[0], u_l[1], dim == 3 ? u_l[2] : nullptr};
+  const double* uv[3] = {u_v[0], u_v[1], dim == 3 ? u_v[2] : nullptr};
+  HIPCK(c, ebit_launch_advect_energy(&c->fd, c->grid.h, T_liq, T_vap, ul, uv, cell_colour, dt, eps, T_star, c->st),
+        "energy advection");
+  return EBIT_OK;
+}
+
 ebit_status ebit_advect_markers(ebit_ctx* c, const double* const u_gamma[3], double* const marker[3],
                                 uint8_t* vertex_colour, uint8_t* cell_colour, double dt) {
   if (!c) return EBIT_EINVAL;

@@ -224,6 +224,18 @@ __device__ inline void cell_ijk(const Dims& d, long long c, int& i, int& j, int&
   k = (int)(c / ((long long)d.n[0] * d.n[1]));
 }
 
+// Tile (or first row block) taken by the lb-th of a case's nb blocks.  The
+// chip hands work-groups to its 8 XCDs round-robin by global index, and each
+// XCD has its own L2; the blocks of one XCD (equal lb mod 8, whatever the
+// case's first global block) take a contiguous range of tiles, so the halo
+// rows and planes that neighbouring tiles share are read once per XCD
+// rather than once per tile.  A bijection of [0, nb) that depends on lb and
+// nb alone, so a case maps the same way alone and in a batch.
+__device__ inline int xcd_tile(int lb, int nb) {
+  const int r = lb & 7, B = nb >> 3, R = nb & 7;
+  return r * B + (r < R ? r : R) + (lb >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // Arguments of the per-case kernels outside the solves, and their launch over
 // many cases: case e of a batch owns the blocks start[e] .. start[e+1]-1 of
@@ -570,6 +582,10 @@ hipError_t ebit_launch_scal_many(int n, const ebit::ScalArgs* tab, const int* st
 hipError_t ebit_launch_split_flags_many(int n, const ebit::SplitArgs* tab, const int* start, int blocks,
                                         hipStream_t st);
 // Interfacial velocity at the cell centres (out[a], a < dim).
+// Eq. energy_advection: T* of every cell from its own phase (energy.hip).
+hipError_t ebit_launch_advect_energy(const ebit::Dims* d, double h, const double* T_liq, const double* T_vap,
+                                     const double* const u_l[3], const double* const u_v[3], const uint8_t* ccol,
+                                     double dt, double eps, double* out, hipStream_t st);
 hipError_t ebit_launch_iface_velocity(const ebit::Dims* d, const uint8_t* flags, const double* nF,
                                       const double* const ul[3], const double* const uv[3], const double* mdot,
                                       double rho_l, double rho_v, double* const out[3], hipStream_t st);

@@ -1773,17 +1773,6 @@ __global__ __launch_bounds__(1024) void k_build_small(Many<BuildSmallArgs> m) {
 // ---------------------------------------------------------------------------
 // outer loop (FP64) with deterministic two-stage reductions
 // ---------------------------------------------------------------------------
-// Tile (or first row block) taken by the lb-th of a case's nb blocks.  The
-// chip hands work-groups to its 8 XCDs round-robin by global index, and each
-// XCD has its own L2; the blocks of one XCD (equal lb mod 8, whatever the
-// case's first global block) take a contiguous range of tiles, so the halo
-// rows and planes that neighbouring tiles share are read once per XCD
-// rather than once per tile.  A bijection of [0, nb) that depends on lb and
-// nb alone, so a case maps the same way alone and in a batch.
-__device__ inline int xcd_tile(int lb, int nb) {
-  const int r = lb & 7, B = nb >> 3, R = nb & 7;
-  return r * B + (r < R ? r : R) + (lb >> 3);
-}
 
 #define GRID_STRIDE(c, N) \
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < (N); c += (long long)gridDim.x * blockDim.x)

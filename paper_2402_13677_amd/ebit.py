@@ -99,6 +99,7 @@ def load():
         "ebit_cut_fractions_noalloc": (i, [ctypes.POINTER(Grid), _P3, vp, vp, _P3, vp, vp]),
         "ebit_interface_velocity": (i, [vp, _P3, _P3, vp, _P3]),
         "ebit_advect_markers": (i, [vp, _P3, _P3, vp, vp, d]),
+        "ebit_advect_energy": (i, [vp, vp, vp, _P3, _P3, vp, d, d, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -114,7 +115,7 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
             "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune",
-            "ebit_cut_fractions_noalloc", "ebit_interface_velocity", "ebit_advect_markers"]
+            "ebit_cut_fractions_noalloc", "ebit_interface_velocity", "ebit_advect_markers", "ebit_advect_energy"]
 NOALLOC_MAX_CELLS = 1 << 18
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ, EXT_IFACE_TO_BAND = range(3)
@@ -286,6 +287,17 @@ class Context:
                                           _ptr(ccol, torch.uint8), float(dt))
         if check:
             self._check(st, "ebit_advect_markers")
+        return st
+
+    def advect_energy(self, T_liq, T_vap, u_l, u_v, ccol, dt, T_star, eps=1e-6, check=True):
+        """Eq. energy_advection: T_star (cells, written) from each cell's
+        own phase field (T_liq / T_vap, extended across the interface) and
+        face velocities (u_l / u_v); returns the status code."""
+        st = self.lib.ebit_advect_energy(self.h, _ptr(T_liq, torch.float64), _ptr(T_vap, torch.float64), _p3(u_l),
+                                         _p3(u_v), _ptr(ccol, torch.uint8), float(dt), float(eps),
+                                         _ptr(T_star, torch.float64))
+        if check:
+            self._check(st, "ebit_advect_energy")
         return st
 
     def heat_rhs(self, T_star, b):

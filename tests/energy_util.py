@@ -9,7 +9,9 @@ import ebit_inputs as ei
 def energy_case(dim, n, periodic=(False, False, False), normal=(1.0, 0.4, 0.2), offset=0.5, h=None,
                 name="energy"):
     """n = (nx, ny, nz) cells (nz = 1 in 2D); liquid where
-    normal . (x - offset * extent) > 0; walls (T Neumann) or periodic axes."""
+    normal . (x - offset * extent) > 0; walls (T Neumann, p Dirichlet) or
+    periodic axes (a library context needs a power-of-two length there and
+    one wall axis)."""
     nn = (n[0], n[1], n[2] if dim == 3 else 1)
     h = h if h is not None else 1.0 / nn[0]
     m = np.array(normal, dtype=float)
@@ -19,13 +21,14 @@ def energy_case(dim, n, periodic=(False, False, False), normal=(1.0, 0.4, 0.2), 
     ext = np.array([nn[0] * h, nn[1] * h, nn[2] * h])
     ls = ei.Plane(m, tuple(offset * ext))
     vcol, ccol, markers = ei.colours_and_markers(dim, nn, h, ls)
-    T_bc = []
+    T_bc, p_bc = [], []
     for a in range(dim):
         for _ in range(2):
             T_bc.append((ei.PERIODIC, 0.0) if periodic[a] else (ei.NEUMANN, 0.0))
+            p_bc.append((ei.PERIODIC, 0.0) if periodic[a] else (ei.DIRICHLET, 0.0))
     z = [np.zeros(ei.face_shape(dim, nn, a)) for a in range(dim)]
     T0 = np.zeros(ei.cell_shape(dim, nn))
-    return ei.Case(name, dim, nn, h, ei.Props(), 1e-3, T_bc, list(T_bc), markers, vcol, ccol, T0, z,
+    return ei.Case(name, dim, nn, h, ei.Props(), 1e-3, T_bc, p_bc, markers, vcol, ccol, T0, z,
                    [x.copy() for x in z])
 
 
