@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -710,6 +711,90 @@ def marker_motion_cpu_baseline():
             "kind": "oracle", "sample": "one call each on bubble2d_256 (mdot = 1 in the band)"}
 
 
+def energy_bytes_per_cell(dim):
+    """Algorithmic bytes of one energy-advection call per cell: the colour
+    byte, the cell's own-phase T and its phase's face per axis (each face
+    read once), the T* write; the stencil neighbours come from the caches."""
+    return 1 + 8 + 8 * dim + 8
+
+
+def _energy_inputs(case, seed=41):
+    """Per-phase fields carried across the interface (Eq. extrapolation, 8
+    steps each way) from the workload's initial T, and smooth face
+    velocities of both signs (the workloads' own fields are zero or nearly
+    so): u_a = 1e-2 sin(2 pi (k . x) / L + phi_a) at the face centres, k and
+    phi seeded per axis and phase; dt for a CFL number of 0.5."""
+    import torch
+    from paper_2402_13677_amd import ebit
+    ctx, dc = ebit.context_for(case)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    Tl, Tv = dc.T0.clone(), dc.T0.clone()
+    ctx.extend(Tl, ebit.EXT_LIQ_TO_VAP, 8)
+    ctx.extend(Tv, ebit.EXT_VAP_TO_LIQ, 8)
+    import numpy as np
+    import ebit_inputs as ei
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = case.n[0] * case.h
+
+    def smooth(a):
+        shp = ei.face_shape(case.dim, case.n, a)             # (nz, ny, nx) order, one more along a
+        ax = [torch.arange(m, dtype=torch.float64, device="cuda") for m in reversed(shp[-case.dim:])]
+        xs = [(ax[b] + (0.0 if b == a else 0.5)) * case.h for b in range(case.dim)]
+        k = rng.integers(1, 4, case.dim)
+        arg = sum(float(k[b]) * xs[b].view([-1 if q == case.dim - 1 - b else 1 for q in range(case.dim)])
+                  for b in range(case.dim))
+        return (1e-2 * torch.sin(2 * math.pi * arg / L + float(rng.uniform(0, 2 * math.pi)))).reshape(-1)
+
+    ul = [smooth(a) for a in range(case.dim)]
+    uv = [smooth(a) for a in range(case.dim)]
+    torch.cuda.synchronize()
+    vmax = max(float(u.abs().max()) for u in ul + uv)
+    return ctx, dc, Tl, Tv, ul, uv, 0.5 * case.h / vmax
+
+
+def energy_bench(case, reps=20):
+    """ebit_advect_energy (Eq. energy_advection) on the workload's grid:
+    median of `reps` calls timed with events on the library's stream."""
+    import torch
+    ctx, dc, Tl, Tv, ul, uv, dt = _energy_inputs(case)
+    out = torch.empty_like(Tl)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ts = []
+    for _ in range(reps + 2):
+        ev[0].record()
+        ctx.advect_energy(Tl, Tv, ul, uv, dc.ccol, dt, out)
+        ev[1].record()
+        ev[1].synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    ms = statistics.median(ts[2:])
+    b = energy_bytes_per_cell(case.dim) * case.ncells
+    ctx.close()
+    return {"cells": case.ncells, "us": ms * 1e3, "algorithmic_bytes": b, "achieved_GBps": b / (ms * 1e-3) / 1e9,
+            "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "cell_updates_per_s": case.ncells / (ms * 1e-3),
+            "inputs": "per-phase T extended 8 steps across the interface, smooth face velocities "
+                      "1e-2 sin(2 pi k.x / L + phi) of both signs, CFL 0.5"}
+
+
+def energy_cpu_baseline(case, sample_cells=1 << 20):
+    """The oracle's energy advection (NumPy, one process) on a sample of
+    the workload's cells with the same inputs: cells per second."""
+    import numpy as np
+    import oracle
+    import torch
+    ctx, dc, Tl, Tv, ul, uv, dt = _energy_inputs(case)
+    h = lambda t: t.cpu().numpy()
+    Tl, Tv, ul, uv = h(Tl), h(Tv), [h(u) for u in ul], [h(u) for u in uv]
+    ctx.close()
+    rng = np.random.Generator(np.random.PCG64(42))
+    n = min(sample_cells, case.ncells)
+    cells = rng.choice(case.ncells, n, replace=False) if n < case.ncells else None
+    t0 = time.perf_counter()
+    oracle.energy.advect_energy(case, Tl, Tv, ul, uv, dt, cells=cells)
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} cells of {case.name} ({el:.1f} s, NumPy)"}
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters."""
@@ -771,12 +856,15 @@ def main():
                     help="fixed schedule nu,tail_cells,check_every (nu1 = nu2 = nu) instead of autotuning")
     ap.add_argument("--no-extension", action="store_true", help="skip the narrow-band extension timing")
     ap.add_argument("--no-one-fluid", action="store_true", help="skip the one-fluid projection timing")
+    ap.add_argument("--no-energy", action="store_true", help="skip the energy-advection timing")
     ap.add_argument("--no-marker-motion", action="store_true",
                     help="skip the interfacial-velocity and marker-motion timing")
     ap.add_argument("--marker-motion-only", action="store_true",
                     help="run only the interfacial-velocity and marker-motion timing (2D bubbles)")
+    ap.add_argument("--energy-only", action="store_true",
+                    help="run only the energy-advection timing on the workload (for profiling it)")
     ap.add_argument("--extras-only", action="store_true",
-                    help="time only the narrow-band extension and the one-fluid projection (for profiling them)")
+                    help="time only the narrow-band extension, the one-fluid projection and the energy advection")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -794,10 +882,14 @@ def main():
     case = make_case(args.workload)
     if isinstance(case, list):
         return main_batch(args, case)
+    if args.energy_only:
+        print(json.dumps({"workload": case.name, "energy_advection": energy_bench(case, reps=5)}))
+        return
     if args.extras_only:
         sched = parse_schedule(args.schedule) if args.schedule else None
         print(json.dumps({"workload": case.name, "extension": extension_bench(case),
                           "one_fluid": one_fluid_bench(case, args.precision, sched),
+                          "energy_advection": energy_bench(case),
                           "marker_motion": marker_motion_bench()}))
         return
     rtol = workload_rtol(case)
@@ -862,6 +954,11 @@ def main():
         extra["one_fluid"] = one_fluid_bench(case, args.precision, schedule)
         if not args.no_cpu_baseline and case.dim == 2:
             extra["one_fluid"]["cpu_oracle"] = one_fluid_cpu_baseline(case)
+    if not args.no_energy:
+        log("energy advection")
+        extra["energy_advection"] = energy_bench(case)
+        if not args.no_cpu_baseline:
+            extra["energy_advection"]["cpu_oracle"] = energy_cpu_baseline(case)
     if not args.no_marker_motion:
         log("interfacial velocity and marker motion (2D bubbles)")
         extra["marker_motion"] = marker_motion_bench()

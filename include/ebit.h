@@ -315,12 +315,13 @@ ebit_status ebit_advect_markers(ebit_ctx* ctx, const double* const u_gamma[3], d
  * T_liq, T_vap, T_star: cells; u_l[a], u_v[a] (a < dim): axis-a face arrays;
  * cell_colour: uint8 per cell.  All device, caller-owned; T_star must not be
  * T_liq or T_vap (neighbours are read while cells are written).  eps: the
- * WENO regulariser (Jiang & Shu: 1e-6).  No stability check: the caller
+ * WENO regulariser (Jiang & Shu: 1e-6), in [1e-60, 1e60] (the kernel forms
+ * products of four squared indicators).  No stability check: the caller
  * keeps |u_a| dt / h small (the explicit step).  The call does not need
  * ebit_build_coeffs and is asynchronous on the context stream.
  * Errors: EBIT_EINVAL for a NULL pointer (among the first dim face arrays),
- * T_star equal to an input, dt negative or not finite, eps not positive or
- * not finite. */
+ * T_star equal to an input, dt negative or not finite, eps outside
+ * [1e-60, 1e60] (or NaN). */
 ebit_status ebit_advect_energy(ebit_ctx* ctx, const double* T_liq, const double* T_vap, const double* const u_l[3],
                                const double* const u_v[3], const uint8_t* cell_colour, double dt, double eps,
                                double* T_star);

@@ -964,7 +964,7 @@ ebit_status ebit_advect_energy(ebit_ctx* c, const double* T_liq, const double* T
     if (!u_l[a] || !u_v[a]) return fail(c, EBIT_EINVAL, "NULL face field");
   if (T_star == T_liq || T_star == T_vap) return fail(c, EBIT_EINVAL, "T_star must not be an input field");
   if (!(dt >= 0.0) || !isfinite(dt)) return fail(c, EBIT_EINVAL, "dt must be finite and >= 0");
-  if (!(eps > 0.0) || !isfinite(eps)) return fail(c, EBIT_EINVAL, "eps must be finite and > 0");
+  if (!(eps >= 1e-60 && eps <= 1e60)) return fail(c, EBIT_EINVAL, "eps must lie in [1e-60, 1e60]");
   const double* ul[3] = {u_l[0], u_l[1], dim == 3 ? u_l[2] : nullptr};
   const double* uv[3] = {u_v[0], u_v[1], dim == 3 ? u_v[2] : nullptr};
   HIPCK(c, ebit_launch_advect_energy(&c->fd, c->grid.h, T_liq, T_vap, ul, uv, cell_colour, dt, eps, T_star, c->st),

@@ -6,18 +6,21 @@
 // each cell with its own phase's temperature field (the caller's fields
 // carry the values extended across the interface) and its own phase's
 // velocity at the centre (the mean of its two faces per axis).  D_a is the
-// third-order WENO derivative of Jiang & Shu: the difference over h of the
-// values at the cell's two a-faces, each reconstructed from the upwind side
+// third-order WENO derivative of Jiang & Shu: the difference of the values
+// at the cell's two a-faces times 1/h, each reconstructed from the upwind side
 // (the sign of u_a) from the two candidate stencils (m, 0) and (0, p) with
 // linear weights 1/3 and 2/3 and smoothness indicators (T_0 - T_m)^2 and
 // (T_p - T_0)^2.  A stencil cell beyond a wall takes the nearest cell's
 // value; periodic axes wrap.  A zero velocity component contributes
 // nothing.
 //
-// Layout and launch: one thread per cell in the natural order; each thread
-// reads its colour byte, its phase's 2 faces per axis, the centre and the 4
-// cells at distance 1 and 2 along each axis (the y and z neighbours come
-// from the L2: the blocks of one XCD take a contiguous range of rows).
+// Layout and launch: one thread per cell, a block per 16 x 16 tile of an
+// x-y plane, the tiles ordered column by column and bottom to top within a
+// column; each thread reads its colour byte, its phase's 2 faces per axis,
+// the centre and the 4 cells at distance 1 and 2 along each axis (the
+// neighbours come from the L2: an XCD's blocks climb a few columns at a
+// time, so the planes below were just read and the tile rims are shared
+// with the columns on either side).
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -28,27 +31,35 @@
 namespace ebit {
 namespace {
 
-constexpr int EN_BLOCK = 256;
+constexpr int EN_TX = 16, EN_TY = 16, EN_BLOCK = EN_TX * EN_TY;
 
 struct EnergyArgs {
   Dims d;
-  double h, dt, eps;
+  double inv_h, dt, eps;
   const uint8_t* ccol;
   const double* T[2];     // [0] vapour, [1] liquid
   const double* u[2][3];  // face fields per phase and axis
   double* out;
 };
 
-// Face value from the upwind cells (m, 0) and the downwind cell p.  The
-// weights alpha_r = d_r / (eps + beta_r)^2 enter only through their ratio,
-// so both are multiplied by (eps + beta0)^2 (eps + beta1)^2: one division.
-__device__ inline double weno3_face(double tm, double t0, double tp, double eps) {
-  const double q0 = 0.5 * (3.0 * t0 - tm);
-  const double q1 = 0.5 * (t0 + tp);
-  const double g0 = t0 - tm, g1 = tp - t0;
-  const double e0 = eps + g0 * g0, e1 = eps + g1 * g1;
-  const double w0 = (1.0 / 3.0) * (e1 * e1), w1 = (2.0 / 3.0) * (e0 * e0);
-  return (w0 * q0 + w1 * q1) / (w0 + w1);
+// The difference of the two face values a cell's derivative takes, seen
+// from the upwind side: with the stencil ordered upwind to downwind as
+// (a, b, c, e) (c the cell), the face c|e from (b, c | e) and the face b|c
+// from (a, b | c).  Each face value is written as its upwind cell plus half
+// the weighted mean of the two one-sided differences,
+//   face = t0 + (w0 (t0 - tm) + w1 (tp - t0)) / (2 (w0 + w1)),
+// the Jiang & Shu weights alpha_r = d_r / (eps + beta_r)^2 scaled by the
+// common factor (eps + beta0)^2 (eps + beta1)^2 (w0 = d0 (eps + beta1)^2,
+// w1 = d1 (eps + beta0)^2); both faces' quotients share one division.
+__device__ inline double weno3_diff(double a, double b, double c, double e, double eps) {
+  const double g_ab = b - a, g_bc = c - b, g_ce = e - c;
+  const double e_ab = eps + g_ab * g_ab, e_bc = eps + g_bc * g_bc, e_ce = eps + g_ce * g_ce;
+  // face c|e: (m, 0, p) = (b, c, e); face b|c: (a, b, c)
+  const double wu0 = (1.0 / 3.0) * (e_ce * e_ce), wu1 = (2.0 / 3.0) * (e_bc * e_bc);
+  const double wl0 = (1.0 / 3.0) * (e_bc * e_bc), wl1 = (2.0 / 3.0) * (e_ab * e_ab);
+  const double nu = wu0 * g_bc + wu1 * g_ce, du = wu0 + wu1;
+  const double nl = wl0 * g_ab + wl1 * g_bc, dl = wl0 + wl1;
+  return g_bc + 0.5 * ((nu * dl - nl * du) / (du * dl));
 }
 
 // index v (at most two steps outside [0, n)) wrapped or clamped
@@ -65,38 +76,51 @@ __device__ inline int wrap_clamp(int v, int n, bool per) {
 
 template <int DIM>
 __global__ __launch_bounds__(EN_BLOCK) void k_advect_energy(EnergyArgs g) {
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * EN_BLOCK + threadIdx.x;
+  // a context's grid has fewer than 2^31 cells (and fewer than 2^32 faces
+  // per axis): 32-bit offsets throughout.  Block t takes the EN_TX x EN_TY
+  // tile of column t / n2 at height t % n2, so the blocks of one XCD (a
+  // contiguous range of t) walk a few tile columns bottom to top and the
+  // z-neighbours a cell reads were fetched by the blocks just below.
   const Dims& d = g.d;
-  if (c >= d.N) return;
-  int ijk[3];
-  cell_ijk(d, c, ijk[0], ijk[1], ijk[2]);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int n2 = d.n[2];
+  const int col = t / n2, kz = t - col * n2;
+  const int gx = (d.n[0] + EN_TX - 1) / EN_TX;
+  const int ty = col / gx, tx = col - ty * gx;
+  const int ijk[3] = {tx * EN_TX + (int)(threadIdx.x % EN_TX), ty * EN_TY + (int)(threadIdx.x / EN_TX), kz};
+  if (ijk[0] >= d.n[0] || ijk[1] >= d.n[1]) return;
+  const unsigned n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
+  const unsigned c = (unsigned)ijk[0] + n0 * ((unsigned)ijk[1] + n1 * (unsigned)kz);
   const int ph = g.ccol[c] ? 1 : 0;
   const double* __restrict__ T = g.T[ph];
-  const long long st[3] = {1, d.n[0], (long long)d.n[0] * d.n[1]};
+  const unsigned st[3] = {1u, n0, n0 * n1};
   const double tc = T[c];
   double acc = 0.0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     // the cell's velocity component: the mean of its two a-faces
-    const long long fn0 = d.n[0] + (a == 0 ? 1 : 0), fn1 = d.n[1] + (a == 1 ? 1 : 0);
-    const long long lo = (long long)ijk[0] + fn0 * ((long long)ijk[1] + fn1 * ijk[2]);
-    const long long up = lo + (a == 0 ? 1LL : a == 1 ? (long long)d.n[0] : (long long)d.n[0] * d.n[1]);
+    const unsigned fn0 = n0 + (a == 0 ? 1u : 0u), fn1 = n1 + (a == 1 ? 1u : 0u);
+    const unsigned lo = (unsigned)ijk[0] + fn0 * ((unsigned)ijk[1] + fn1 * (unsigned)ijk[2]);
+    const unsigned up = lo + (a == 0 ? 1u : a == 1 ? n0 : n0 * n1);
     const double* __restrict__ f = g.u[ph][a];
     const double ua = 0.5 * (f[lo] + f[up]);
     // the four stencil cells along a (offsets -2, -1, +1, +2)
     const bool per = d.per[a] != 0;
     const int n = d.n[a], ia = ijk[a];
-    const long long base = c - (long long)ia * st[a];
-    const double tm2 = T[base + (long long)wrap_clamp(ia - 2, n, per) * st[a]];
-    const double tm1 = T[base + (long long)wrap_clamp(ia - 1, n, per) * st[a]];
-    const double tp1 = T[base + (long long)wrap_clamp(ia + 1, n, per) * st[a]];
-    const double tp2 = T[base + (long long)wrap_clamp(ia + 2, n, per) * st[a]];
-    double D = 0.0;
-    if (ua > 0.0)
-      D = (weno3_face(tm1, tc, tp1, g.eps) - weno3_face(tm2, tm1, tc, g.eps)) / g.h;
-    else if (ua < 0.0)
-      D = (weno3_face(tp2, tp1, tc, g.eps) - weno3_face(tp1, tc, tm1, g.eps)) / g.h;
-    acc = a == 0 ? ua * D : acc + ua * D;
+    const unsigned base = c - (unsigned)ia * st[a];
+    const double tm2 = T[base + (unsigned)wrap_clamp(ia - 2, n, per) * st[a]];
+    const double tm1 = T[base + (unsigned)wrap_clamp(ia - 1, n, per) * st[a]];
+    const double tp1 = T[base + (unsigned)wrap_clamp(ia + 1, n, per) * st[a]];
+    const double tp2 = T[base + (unsigned)wrap_clamp(ia + 2, n, per) * st[a]];
+    // the stencil ordered from the upwind side (u > 0: i-2, i-1, i, i+1;
+    // u < 0: i+2, i+1, i, i-1), selected rather than branched on; the
+    // downstream face minus the upstream one is then D_a h in the direction
+    // of the flow, so u_a D_a = |u_a| weno3_diff / h.  A zero component
+    // contributes exactly 0, whatever its stencil holds.
+    const bool pos = ua > 0.0;
+    const double df = weno3_diff(pos ? tm2 : tp2, pos ? tm1 : tp1, tc, pos ? tp1 : tm1, g.eps);
+    const double t = ua != 0.0 ? fabs(ua) * (df * g.inv_h) : 0.0;
+    acc = a == 0 ? t : acc + t;
   }
   g.out[c] = tc - g.dt * acc;
 }
@@ -112,7 +136,7 @@ extern "C" hipError_t ebit_launch_advect_energy(const Dims* d, double h, const d
                                                 hipStream_t st) {
   EnergyArgs g;
   g.d = *d;
-  g.h = h;
+  g.inv_h = 1.0 / h;
   g.dt = dt;
   g.eps = eps;
   g.ccol = ccol;
@@ -123,7 +147,8 @@ extern "C" hipError_t ebit_launch_advect_energy(const Dims* d, double h, const d
     g.u[0][a] = a < d->dim ? u_v[a] : nullptr;
   }
   g.out = out;
-  const long long blocks = (d->N + EN_BLOCK - 1) / EN_BLOCK;
+  const long long blocks =
+      (long long)((d->n[0] + EN_TX - 1) / EN_TX) * ((d->n[1] + EN_TY - 1) / EN_TY) * d->n[2];
   if (blocks == 0) return hipSuccess;
   if (d->dim == 3)
     hipLaunchKernelGGL(k_advect_energy<3>, dim3((unsigned)blocks), dim3(EN_BLOCK), 0, st, g);

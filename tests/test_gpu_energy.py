@@ -1,14 +1,15 @@
 """GPU parity of the energy advection step (ebit_advect_energy, Eq.
 energy_advection) with the oracle (oracle/energy.py), through the C ABI.
 
-Bar: element by element, |T*_gpu - T*_oracle| <= 8 ulp of max |T| (the
-observed worst is 2 ulp: 1.1e-13 at |T| ~ 380).  T* =
-T - dt sum_a u_a D_a; each face value is a weighted mean of values of size
-|T| (a few roundings, and the kernel clears the common denominator of the
-two weights, the oracle does not), so each D_a carries an error of a few
-ulp |T| / h, and |u_a| dt <= CFL h turns that into a few ulp |T| per axis
-(CFL <= 0.5 in these cases); the final subtraction adds one more.  The
-branch on the sign of u_a is taken on the same IEEE value on both sides.
+Bar: element by element, |T*_gpu - T*_oracle| <= 8 ulp of max |T|.  T* =
+T - dt sum_a u_a D_a.  The oracle forms each face value as a weighted mean
+of values of size |T| (a few roundings), so its D_a carries an error of a
+few ulp |T| / h; the kernel forms the face difference from one-sided
+differences (the upwind cell plus half a weighted mean of differences,
+both faces' quotients over one division), which is at least as accurate.
+|u_a| dt <= CFL h turns a few ulp |T| / h into a few ulp |T| per axis (CFL
+<= 0.5 in these cases); the final subtraction adds one more.  The choice
+of the upwind side is taken on the same IEEE value of u_a on both sides.
 
 Cases: 2D and 3D, walls and periodic axes, ragged sizes over several
 blocks, smooth and rough (step plus cell-scale noise) per-phase fields,
@@ -152,5 +153,7 @@ def test_errors():
     assert ctx.advect_energy(T, T, u, u, dc.ccol, -1.0, out, check=False) == ebit.EINVAL
     assert ctx.advect_energy(T, T, u, u, dc.ccol, float("nan"), out, check=False) == ebit.EINVAL
     assert ctx.advect_energy(T, T, u, u, dc.ccol, 0.1, out, eps=0.0, check=False) == ebit.EINVAL
+    assert ctx.advect_energy(T, T, u, u, dc.ccol, 0.1, out, eps=1e-70, check=False) == ebit.EINVAL
+    assert ctx.advect_energy(T, T, u, u, dc.ccol, 0.1, out, eps=float("inf"), check=False) == ebit.EINVAL
     assert ctx.advect_energy(T, T, u, u, dc.ccol, 0.1, T, check=False) == ebit.EINVAL
     assert ctx.advect_energy(T, T, u, u, dc.ccol, 0.1, out, check=False) == ebit.OK
