@@ -50,6 +50,9 @@
  *     created, makes the outer-loop kernels use 64-bit cell offsets at any
  *     grid size (the form they take from 2^30 cells on); results are the
  *     same bits.  It exists to test that form on small grids.
+ *     EBIT_TEST_FP32_STALL=1, read the same way, makes a mixed-precision
+ *     context or batch treat every solve still iterating after its first
+ *     block of iterations as stalled, to test the FP64 fallback.
  */
 #ifndef EBIT_H
 #define EBIT_H
@@ -104,7 +107,10 @@ typedef struct {
 /* Solver options; ebit_default_opts() fills the defaults in brackets. */
 typedef struct {
   int precision;      /* EBIT_FP64 [default] or EBIT_MIXED (FP32 V-cycles
-                         inside the FP64 outer loop)                          */
+                         inside the FP64 outer loop; a solve whose V-cycles
+                         stop contracting, above the rounding floor and
+                         before max_iters, continues in FP64 from its
+                         iterate: ebit_stats.fp64_fallback)                   */
   int outer;          /* EBIT_OUTER_PCG [default]: flexible CG preconditioned
                          by one V-cycle; EBIT_OUTER_DC: defect correction
                          x += alpha V(b - A x) with the energy-optimal step
@@ -140,6 +146,9 @@ typedef struct {
   double div_max;       /* ebit_project: max_c |div_c u_{k(c)}| after update  */
   int fallbacks;        /* ebit_mass_flux: first-order gradient fallbacks     */
   int status;           /* ebit_status of the call                            */
+  int fp64_fallback;    /* 1 if a mixed-precision solve stalled (its FP32
+                           V-cycles stopped contracting the FP64 residual)
+                           and was continued in FP64 from its iterate       */
 } ebit_stats;
 
 typedef struct ebit_ctx ebit_ctx;

@@ -326,7 +326,8 @@ size_t layout(const ebit_grid* g, const ebit_opts* o, char* base, ebit_ctx* ctx)
     }
     if (dl >= 0) lv[dl].inv_ok = cv.take<int>(2);
   }
-  const size_t plan_bytes = ebit_plan_device_bytes(1, o ? o->precision : EBIT_FP64);
+  // room for a plan of either precision (a mixed solve can fall back to FP64)
+  const size_t plan_bytes = std::max(ebit_plan_device_bytes(1, EBIT_FP64), ebit_plan_device_bytes(1, EBIT_MIXED));
   char* plan_mem = cv.take<char>(plan_bytes);
   char* build_tabs = cv.take<char>(ebit_build_table_bytes());
   // 2D marker motion: moved and fixed coordinates of every edge of both
@@ -429,12 +430,38 @@ ebit_status solve_status(const EbitSolveOut& r, ebit_stats* st) {
   return EBIT_OK;
 }
 
+hipError_t replan(EbitPlan** plan, ebit_ctx* const* ctx, int n, const ebit_opts* o, void* mem, size_t bytes);
+
+// The FP64 fallback of a mixed-precision solve whose FP32 inner cycle
+// stopped contracting: the same cases, re-planned in FP64 (the hierarchies
+// hold FP64 coefficients and tail images in either precision), continue
+// from the mixed iterate (a case already converged stops at once); the
+// mixed plan is restored afterwards.
+hipError_t solve_fp64_fallback(EbitPlan** plan, ebit_ctx* const* ctx, int n, const ebit_opts& mixed, void* mem,
+                               size_t bytes, int sys, double* const* x, hipStream_t st, EbitProfiler* pf,
+                               EbitSolveOut* r) {
+  ebit_opts o64 = mixed;
+  o64.precision = EBIT_FP64;
+  hipError_t e = replan(plan, ctx, n, &o64, mem, bytes);
+  if (e == hipSuccess) e = ebit_plan_solve(*plan, sys, x, 1, st, pf, r);
+  const hipError_t e2 = replan(plan, ctx, n, &mixed, mem, bytes);
+  return e != hipSuccess ? e : e2;
+}
+
 ebit_status run_solve(ebit_ctx* c, int sys, double* x, int use_guess, ebit_stats* st) {
   EbitSolveOut r;
   double* xs[1] = {x};
-  const hipError_t e = ebit_plan_solve(c->plan, sys, xs, use_guess, c->st, c->prof, &r);
+  hipError_t e = ebit_plan_solve(c->plan, sys, xs, use_guess, c->st, c->prof, &r);
   if (e != hipSuccess) return hip_fail(c, e, "solve");
+  int fell = 0;
+  if (r.status == 1 && r.stalled && c->opts.precision == EBIT_MIXED) {
+    ebit_ctx* cs[1] = {c};
+    e = solve_fp64_fallback(&c->plan, cs, 1, c->opts, c->plan_mem, c->plan_bytes, sys, xs, c->st, c->prof, &r);
+    if (e != hipSuccess) return hip_fail(c, e, "FP64 fallback solve");
+    fell = 1;
+  }
   const ebit_status s = solve_status(r, st);
+  if (st) st->fp64_fallback = fell;
   if (s == EBIT_ENOCONV) return fail(c, s, "no convergence within max_iters");
   if (s == EBIT_ENAN) return fail(c, s, "NaN or Inf in a residual norm");
   return s;
@@ -1059,7 +1086,7 @@ ebit_status ebit_levels(const ebit_ctx* c, int* nlevels, int* sizes) {
 
 size_t ebit_batch_workspace_bytes(int ncases, const ebit_opts* o) {
   if (ncases < 1) return 0;
-  const size_t b = ebit_plan_device_bytes(ncases, o ? o->precision : EBIT_FP64);
+  const size_t b = std::max(ebit_plan_device_bytes(ncases, EBIT_FP64), ebit_plan_device_bytes(ncases, EBIT_MIXED));
   return (b + ALIGN - 1) / ALIGN * ALIGN + batch_tabs_layout(ncases, nullptr, nullptr);
 }
 
@@ -1102,7 +1129,8 @@ ebit_status ebit_batch_create(ebit_batch** out, int ncases, ebit_ctx* const ctx[
     b->ctx[c] = ctx[c];
     pc[c] = EbitPlanCase{ctx[c]->lv, ctx[c]->nlev, ctx[c]->op, ctx[c]->B, ctx[c]->bvec};
   }
-  const size_t pb = (ebit_plan_device_bytes(ncases, b->opts.precision) + ALIGN - 1) / ALIGN * ALIGN;
+  const size_t pb = (std::max(ebit_plan_device_bytes(ncases, EBIT_FP64), ebit_plan_device_bytes(ncases, EBIT_MIXED)) +
+                     ALIGN - 1) / ALIGN * ALIGN;
   hipError_t e = hipEventCreate(&b->ev0);
   if (e == hipSuccess) e = hipEventCreate(&b->ev1);
   if (e == hipSuccess) e = ebit_plan_create(&b->plan, ncases, pc, &b->opts, ctx[0]->B.tail_lds, ws, pb);
@@ -1181,6 +1209,23 @@ ebit_status batch_ready(ebit_batch* b) {
     if (s != EBIT_OK) return bfail(b, s, c, b->ctx[c]->msg);
   }
   return EBIT_OK;
+}
+
+// A mixed batch solve in which some case's inner cycle stopped contracting
+// continues in FP64 for all cases from their current iterates (the cases
+// already converged stop at once); fell[c] marks the cases that stalled.
+hipError_t batch_fallback(ebit_batch* b, int sys, double* const* x, EbitSolveOut* r, std::vector<int>& fell) {
+  fell.assign(b->n, 0);
+  bool any = false;
+  for (int c = 0; c < b->n; ++c)
+    if (r[c].status == 1 && r[c].stalled) fell[c] = 1, any = true;
+  if (!any || b->opts.precision != EBIT_MIXED) {
+    fell.assign(b->n, 0);
+    return hipSuccess;
+  }
+  const size_t pb = (std::max(ebit_plan_device_bytes(b->n, EBIT_FP64), ebit_plan_device_bytes(b->n, EBIT_MIXED)) +
+                     ALIGN - 1) / ALIGN * ALIGN;
+  return solve_fp64_fallback(&b->plan, b->ctx, b->n, b->opts, b->ws, pb, sys, x, b->st, nullptr, r);
 }
 
 // per-case solve results into stats; the first failing status is returned
@@ -1301,7 +1346,9 @@ ebit_status ebit_batch_heat_solve(ebit_batch* b, const double* const T_star[], d
   }
   EbitSolveOut* r = new (std::nothrow) EbitSolveOut[b->n];
   if (!r) return EBIT_ENOMEM;
-  const hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_HEAT, T, use_guess, b->st, nullptr, r);
+  hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_HEAT, T, use_guess, b->st, nullptr, r);
+  std::vector<int> fell;
+  if (e == hipSuccess) e = batch_fallback(b, EBIT_SYS_HEAT, T, r, fell);
   if (e != hipSuccess) {
     delete[] r;
     return bhip(b, e, "solve");
@@ -1310,6 +1357,8 @@ ebit_status ebit_batch_heat_solve(ebit_batch* b, const double* const T_star[], d
   if (hipEventRecord(b->ev1, b->st) == hipSuccess && hipEventSynchronize(b->ev1) == hipSuccess)
     (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
   s = batch_results(b, r, stats, ms * 1e-3);
+  if (stats)
+    for (int c = 0; c < b->n; ++c) stats[c].fp64_fallback = fell[c];
   delete[] r;
   return s;
 }
@@ -1379,7 +1428,9 @@ ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const
   }
   EbitSolveOut* r = new (std::nothrow) EbitSolveOut[b->n];
   if (!r) return EBIT_ENOMEM;
-  const hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_PRESSURE, p, use_guess, b->st, nullptr, r);
+  hipError_t e = ebit_plan_solve(b->plan, EBIT_SYS_PRESSURE, p, use_guess, b->st, nullptr, r);
+  std::vector<int> fell;
+  if (e == hipSuccess) e = batch_fallback(b, EBIT_SYS_PRESSURE, p, r, fell);
   if (e != hipSuccess) {
     delete[] r;
     return bhip(b, e, "solve");
@@ -1416,7 +1467,10 @@ ebit_status ebit_batch_project(ebit_batch* b, double* const u_l[], double* const
   (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
   s = batch_results(b, r, stats, ms * 1e-3);
   if (stats)
-    for (int c = 0; c < b->n; ++c) stats[c].div_max = b->hsc[c].divmax;
+    for (int c = 0; c < b->n; ++c) {
+      stats[c].div_max = b->hsc[c].divmax;
+      stats[c].fp64_fallback = fell[c];
+    }
   delete[] r;
   return s;
 }

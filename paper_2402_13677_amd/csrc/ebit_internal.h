@@ -646,6 +646,7 @@ struct EbitPlanCase {
 // (max_iters, or stagnation above the rounding floor), 2 NaN/Inf.
 struct EbitSolveOut {
   int status;
+  int stalled;  // status 1 because the inner cycle stopped contracting
   int iters;
   double rel_res, bnorm, res_floor;
 };

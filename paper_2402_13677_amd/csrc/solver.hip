@@ -3444,7 +3444,7 @@ void ebit_build_tables(const EbitLevelHost* lv, int nlev, int want32, void* host
       t.mass[l] = lv[l].mass64[sys];
       t.d32[l] = want32 ? lv[l].diag32[sys] : nullptr;
       t.i32[l] = want32 ? lv[l].img32[sys] : nullptr;
-      t.i64[l] = want32 ? nullptr : lv[l].img64[sys];
+      t.i64[l] = lv[l].img64[sys];
       for (int a = 0; a < 3; ++a) {
         const bool on = a < lv[l].d.dim;
         t.off[l][a] = on ? lv[l].off64[sys][a] : nullptr;
@@ -3482,7 +3482,7 @@ int ebit_build_args(const FineOp* op, const EbitLevelHost* lv, int nlev, int wan
       o[sys].mass = lv[l].mass64[sys];
       o[sys].d32 = want32 ? lv[l].diag32[sys] : nullptr;
       o[sys].i32 = want32 ? lv[l].img32[sys] : nullptr;
-      o[sys].i64 = want32 ? nullptr : lv[l].img64[sys];
+      o[sys].i64 = lv[l].img64[sys];
       for (int a = 0; a < 3; ++a) {
         const bool on = a < o[sys].cd.dim;
         o[sys].off[a] = on ? lv[l].off64[sys][a] : nullptr;
@@ -3860,6 +3860,9 @@ struct PlanT {
   bool wide = false;
   // 3D: the fine level is smoothed in the colour-split order
   bool split = false;
+  // test switch: report the cases still running after the first block as
+  // stalled (EBIT_TEST_FP32_STALL)
+  bool force_stall = false;
 };
 
 template <typename T>
@@ -4193,11 +4196,20 @@ bool wide_offsets_env() {
   return e && e[0] == '1';
 }
 
+// EBIT_TEST_FP32_STALL=1 makes a mixed-precision plan report every case
+// that is still iterating after its first block as stalled (a test of the
+// FP64 fallback from the host side; the kernels run as always).
+bool force_stall_env() {
+  const char* e = std::getenv("EBIT_TEST_FP32_STALL");
+  return e && e[0] == '1';
+}
+
 template <typename T>
 hipError_t plan_create_t(PlanT<T>* P, int n, const EbitPlanCase* cases, const ebit_opts* o, int tail_lds, void* mem,
                          size_t bytes) {
   P->n = n;
   const bool wide_env = wide_offsets_env();
+  P->force_stall = std::is_same<T, float>::value && force_stall_env();
   P->o = *o;
   P->cases.assign(cases, cases + n);
   P->dim = cases[0].lv[0].d.dim;
@@ -4407,7 +4419,7 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
                        P.red.w, (int)MASK_ZERO);
   PK(hipGetLastError());
   const double fc = 2.220446049250313e-16;
-  std::vector<int> status(n, -1), restarts(n, 0), at_floor(n, 0);
+  std::vector<int> status(n, -1), restarts(n, 0), at_floor(n, 0), stalled(n, 0);
   std::vector<double> tol2(n, 0.0), floor2(n, 0.0), last_true(n, 0.0), bb(n, 0.0);
   const int check = o.check_every > 0 ? o.check_every : 1;
   for (bool first = true;; first = false) {
@@ -4441,6 +4453,11 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
       if (S.err & ERR_NAN) {
         status[c] = 2;
         cc.active = 0;
+      } else if (P.force_stall && S.bb != 0.0 && !(S.rr <= tol2[c])) {
+        status[c] = 1;
+        stalled[c] = 1;
+        cc.active = 0;
+        cc.recheck = 0;
       } else if (S.bb == 0.0) {
         status[c] = 0;  // b = 0: x = 0 (cleared on the device)
         cc.active = 0;
@@ -4460,6 +4477,8 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
           status[c] = 0;
         } else if (restarts[c] >= 8 || (stagnant && rr > floor2[c]) || S.iters >= o.max_iters) {
           status[c] = 1;
+          // the inner cycle stopped contracting (not the iteration limit)
+          stalled[c] = S.iters < o.max_iters ? 1 : 0;
         } else {
           // restart the recurrence from the recomputed residual
           ++restarts[c];
@@ -4485,6 +4504,7 @@ hipError_t plan_solve_t(PlanT<T>& P, int sys, double* const* x, int use_guess, h
     const Scal& S = P.h_sc[c];
     EbitSolveOut& r = out[c];
     r.status = status[c] < 0 ? 1 : status[c];
+    r.stalled = stalled[c];
     r.iters = S.iters;
     r.bnorm = sqrt(bb[c]);
     r.rel_res = bb[c] > 0 ? sqrt(S.rr / bb[c]) : 0.0;

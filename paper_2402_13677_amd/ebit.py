@@ -43,7 +43,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("vcycles", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("res_floor", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("div_max", ctypes.c_double),
-                ("fallbacks", ctypes.c_int), ("status", ctypes.c_int)]
+                ("fallbacks", ctypes.c_int), ("status", ctypes.c_int), ("fp64_fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

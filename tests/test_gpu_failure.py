@@ -1,0 +1,154 @@
+"""Failure paths of the solves, forced from the host (every kernel runs and
+exits normally):
+
+* a NaN in the heat right-hand side's input (T*) or in the projection's
+  face velocities (u*) gives EBIT_ENAN, for a context and for a batch;
+* a mixed-precision solve whose FP32 V-cycles stop contracting continues in
+  FP64 from its iterate: EBIT_TEST_FP32_STALL=1 (read when a context or a
+  batch is created) makes the mixed plan report every case still running
+  after its first block as stalled; the step then meets the oracle bar of
+  the parity tests (1e-12) with ebit_stats.fp64_fallback set, for a context
+  and for a batch, and a context created without the switch reports no
+  fallback.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import ebit_inputs as ei
+import oracle
+from parity_util import check_step, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _ebit():
+    from paper_2402_13677_amd import ebit
+    return ebit
+
+
+def _cases():
+    return [ei.random_case(2, 40, 1), ei.random_case(3, 17, 4, kind="plane", bc="mixed"), ei.config(0)]
+
+
+@pytest.mark.parametrize("which", ["heat", "projection"])
+def test_nan_input_gives_enan(which):
+    ebit = _ebit()
+    case = ei.random_case(2, 32, 5)
+    say(f"[gpu] failure: NaN in the {which} input")
+    ctx, dc = ebit.context_for(case, ebit.default_opts(precision=ebit.MIXED))
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    T = torch.zeros_like(dc.T0)
+    if which == "heat":
+        Ts = dc.T0.clone()
+        Ts.view(-1)[case.ncells // 2] = float("nan")
+        s = ctx.heat_solve(Ts, T, check=False)
+    else:
+        ctx.heat_solve(dc.T0, T)
+        m = torch.zeros_like(T)
+        ctx.mass_flux(T, m)
+        ul = [u.clone() for u in dc.u_l]
+        ul[0].view(-1)[ul[0].numel() // 2] = float("nan")
+        s = ctx.project(ul, [u.clone() for u in dc.u_v], m, torch.zeros_like(T), check=False)
+    assert s["status"] == ebit.ENAN, s
+    # the context stays usable: a clean solve afterwards succeeds
+    s2 = ctx.heat_solve(dc.T0, T, check=False)
+    assert s2["status"] == ebit.OK
+    ctx.close()
+
+
+def test_nan_input_in_a_batch_gives_enan():
+    ebit = _ebit()
+    cases = [ei.random_case(2, 24 + 8 * i, 10 + i) for i in range(3)]
+    ctxs = [ebit.context_for(c, ebit.default_opts(precision=ebit.MIXED)) for c in cases]
+    b = ebit.Batch([c for c, _ in ctxs])
+    dcs = [d for _, d in ctxs]
+    b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs], [c.dt for c in cases])
+    Ts = [d.T0.clone() for d in dcs]
+    Ts[1].view(-1)[5] = float("nan")
+    T = [torch.zeros_like(d.T0) for d in dcs]
+    s = b.heat_solve(Ts, T, check=False)
+    assert s[1]["status"] == ebit.ENAN
+    assert s[0]["status"] == ebit.OK and s[2]["status"] == ebit.OK
+    b.close()
+    for c, _ in ctxs:
+        c.close()
+
+
+def _step(ctx, dc, case):
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    T = torch.zeros_like(dc.T0)
+    sh = ctx.heat_solve(dc.T0, T)
+    m = torch.zeros_like(T)
+    mf = [torch.empty(ei.face_shape(case.dim, case.n, a), dtype=torch.float64, device="cuda")
+          for a in range(case.dim)]
+    ctx.mass_flux(T, m, mf)
+    p = torch.zeros_like(T)
+    sp = ctx.project(dc.u_l, dc.u_v, m, p)
+    torch.cuda.synchronize()
+    g = {"T": T.cpu().numpy().ravel(), "mdot": m.cpu().numpy().ravel(), "mface": [x.cpu().numpy() for x in mf],
+         "p": p.cpu().numpy().ravel(), "u_l": [u.cpu().numpy() for u in dc.u_l],
+         "u_v": [u.cpu().numpy() for u in dc.u_v]}
+    return g, sh, sp
+
+
+@pytest.fixture
+def stall_switch():
+    os.environ["EBIT_TEST_FP32_STALL"] = "1"
+    try:
+        yield
+    finally:
+        del os.environ["EBIT_TEST_FP32_STALL"]
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_stalled_mixed_solve_continues_in_fp64(idx, stall_switch):
+    ebit = _ebit()
+    case = _cases()[idx]
+    say(f"[gpu] failure: forced FP32 stall, {case.name}")
+    ref = oracle.pipeline.run_step(case, case.T0, case.u_l, case.u_v)
+    opts = ebit.default_opts(rtol=1e-15, precision=ebit.MIXED)
+    ctx, dc = ebit.context_for(case, opts)
+    g, sh, sp = _step(ctx, dc, case)
+    ctx.close()
+    say(f"   heat {sh['iters']} iters fallback {sh['fp64_fallback']}, projection {sp['iters']} iters "
+        f"fallback {sp['fp64_fallback']}")
+    assert sh["fp64_fallback"] == 1 and sp["fp64_fallback"] == 1
+    check_step(case, ref, g, log=say)
+
+
+def test_no_fallback_without_the_switch():
+    ebit = _ebit()
+    case = _cases()[0]
+    ctx, dc = ebit.context_for(case, ebit.default_opts(rtol=1e-12, precision=ebit.MIXED))
+    _, sh, sp = _step(ctx, dc, case)
+    ctx.close()
+    assert sh["fp64_fallback"] == 0 and sp["fp64_fallback"] == 0
+
+
+def test_stalled_mixed_batch_continues_in_fp64(stall_switch):
+    ebit = _ebit()
+    cases = _cases()[:1] + [ei.random_case(2, 33, 7, kind="plane", bc="mixed")]
+    refs = [oracle.pipeline.run_step(c, c.T0, c.u_l, c.u_v) for c in cases]
+    opts = ebit.default_opts(rtol=1e-15, precision=ebit.MIXED)
+    ctxs = [ebit.context_for(c, opts) for c in cases]
+    b = ebit.Batch([c for c, _ in ctxs])
+    dcs = [d for _, d in ctxs]
+    b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs], [c.dt for c in cases])
+    T = [torch.zeros_like(d.T0) for d in dcs]
+    sh = b.heat_solve([d.T0 for d in dcs], T)
+    m = [torch.zeros_like(t) for t in T]
+    b.mass_flux(T, m)
+    p = [torch.zeros_like(t) for t in T]
+    sp = b.project([d.u_l for d in dcs], [d.u_v for d in dcs], m, p)
+    torch.cuda.synchronize()
+    for i, (c, ref) in enumerate(zip(cases, refs)):
+        assert sh[i]["fp64_fallback"] == 1 and sp[i]["fp64_fallback"] == 1
+        g = {"T": T[i].cpu().numpy().ravel(), "mdot": m[i].cpu().numpy().ravel(), "p": p[i].cpu().numpy().ravel(),
+             "u_l": [u.cpu().numpy() for u in dcs[i].u_l], "u_v": [u.cpu().numpy() for u in dcs[i].u_v]}
+        check_step(c, ref, g, log=say)
+    b.close()
+    for c, _ in ctxs:
+        c.close()
