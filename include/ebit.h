@@ -75,7 +75,8 @@ typedef enum {
   EBIT_ENOCONV = -4,  /* max_iters reached; the best iterate is returned       */
   EBIT_ENAN = -5,     /* NaN/Inf met in a residual norm                        */
   EBIT_EHIP = -6,     /* a HIP call failed (sticky on the context)             */
-  EBIT_ESTATE = -7    /* call order violated (e.g. solve before build_coeffs)  */
+  EBIT_ESTATE = -7,   /* call order violated (e.g. solve before build_coeffs)  */
+  EBIT_EIO = -8       /* the schedule cache file could not be written          */
 } ebit_status;
 
 typedef enum { EBIT_BC_NEUMANN = 0, EBIT_BC_DIRICHLET = 1, EBIT_BC_PERIODIC = 2 } ebit_bc;
@@ -436,6 +437,38 @@ ebit_status ebit_autotune(ebit_ctx* ctx, const double* b_heat, const double* b_p
                           double* best_ms);
 ebit_status ebit_batch_autotune(ebit_batch* batch, const double* const b_heat[], const double* const b_press[],
                                 double* const x[], ebit_opts* chosen, double* best_ms);
+
+/* ---- the tuned-schedule cache ----------------------------------------------
+ * A text file of one schedule per line,
+ *   ebit-schedule <key> nu tail_cells check_every ms
+ * where the key of a context is "dim n0 n1 n2 precision outer" and that of a
+ * batch "batch dim ncases total_cells largest_case_cells precision outer".
+ * Lines are appended; the last line with a key wins; other lines are
+ * ignored.  Host code only (no device work).
+ *
+ * ebit_tune_lookup: *found = 1 and the schedule (nu1 = nu2, tail_cells,
+ * check_every) written into *chosen (its other fields copied from *base)
+ * when the file holds the key of (grid, base), else *found = 0 and *chosen =
+ * *base; a missing or unreadable file is not an error.  EBIT_EINVAL for a
+ * NULL argument or a bad grid.
+ * ebit_tune_store: appends the line of (grid, chosen, ms), creating the
+ * file.  EBIT_EINVAL for a NULL argument or a bad grid, EBIT_EIO when the
+ * file cannot be written. */
+ebit_status ebit_tune_lookup(const char* path, const ebit_grid* grid, const ebit_opts* base, ebit_opts* chosen,
+                             int* found);
+ebit_status ebit_tune_store(const char* path, const ebit_grid* grid, const ebit_opts* chosen, double ms);
+
+/* ebit_autotune / ebit_batch_autotune through the cache at path: a schedule
+ * stored for the key is applied without timing (*from_cache = 1, *best_ms
+ * the stored time); otherwise the candidates are timed as by
+ * ebit_autotune, the winner is applied and appended to the file
+ * (*from_cache = 0).  Errors as ebit_autotune, and EBIT_EIO when the file
+ * cannot be written. */
+ebit_status ebit_autotune_cached(ebit_ctx* ctx, const char* path, const double* b_heat, const double* b_press,
+                                 double* x, ebit_opts* chosen, double* best_ms, int* from_cache);
+ebit_status ebit_batch_autotune_cached(ebit_batch* batch, const char* path, const double* const b_heat[],
+                                       const double* const b_press[], double* const x[], ebit_opts* chosen,
+                                       double* best_ms, int* from_cache);
 
 /* ---- the geometry pass without allocation --------------------------------
  * For callers that cannot allocate device memory (code under HIP graph

@@ -4,7 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "ebit_internal.h"
@@ -678,6 +680,7 @@ const char* ebit_status_string(ebit_status s) {
     case EBIT_ENAN: return "NaN or Inf in the solver";
     case EBIT_EHIP: return "HIP runtime error";
     case EBIT_ESTATE: return "call order violated";
+    case EBIT_EIO: return "schedule cache file not writable";
   }
   return "unknown status";
 }
@@ -1598,6 +1601,150 @@ ebit_status ebit_batch_autotune(ebit_batch* b, const double* const b_heat[], con
   if (chosen) *chosen = best;
   if (best_ms) *best_ms = ms;
   if (!isfinite(ms)) return bfail(b, EBIT_ENOCONV, -1, "no candidate schedule converged");
+  return EBIT_OK;
+}
+
+/* ---- the tuned-schedule cache ------------------------------------------- */
+
+}  // extern "C"
+
+namespace {
+
+// "dim n0 n1 n2 precision outer" of a grid under options o
+std::string ctx_key(const ebit_grid* g, const ebit_opts* o) {
+  char k[128];
+  snprintf(k, sizeof(k), "%d %d %d %d %d %d", g->dim, g->n[0], g->n[1], g->n[2], o->precision, o->outer);
+  return k;
+}
+
+std::string batch_key(const ebit_batch* b, const ebit_opts* o) {
+  long long tot = 0, big = 0;
+  for (int c = 0; c < b->n; ++c) {
+    tot += b->ctx[c]->fd.N;
+    big = std::max(big, b->ctx[c]->fd.N);
+  }
+  char k[160];
+  snprintf(k, sizeof(k), "batch %d %d %lld %lld %d %d", b->ctx[0]->fd.dim, b->n, tot, big, o->precision, o->outer);
+  return k;
+}
+
+// the last line of the file with this key: nu, tail, check, ms
+bool cache_find(const char* path, const std::string& key, int* nu, int* tail, int* k, double* ms) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  bool hit = false;
+  char line[512];
+  const std::string head = "ebit-schedule " + key + " ";
+  while (fgets(line, sizeof(line), f)) {
+    if (strncmp(line, head.c_str(), head.size()) != 0) continue;
+    int a, t, c;
+    double m;
+    if (sscanf(line + head.size(), "%d %d %d %lf", &a, &t, &c, &m) == 4 && a >= 1 && a <= 8 && t >= 1 && c >= 1) {
+      *nu = a;
+      *tail = t;
+      *k = c;
+      *ms = m;
+      hit = true;
+    }
+  }
+  fclose(f);
+  return hit;
+}
+
+bool cache_put(const char* path, const std::string& key, const ebit_opts* o, double ms) {
+  FILE* f = fopen(path, "a");
+  if (!f) return false;
+  const int w = fprintf(f, "ebit-schedule %s %d %d %d %.6g\n", key.c_str(), o->nu1, o->tail_cells, o->check_every, ms);
+  const int cl = fclose(f);
+  return w > 0 && cl == 0;
+}
+
+void apply_schedule(ebit_opts* o, int nu, int tail, int k) {
+  o->nu1 = o->nu2 = nu;
+  o->tail_cells = tail;
+  o->check_every = k;
+}
+
+}  // namespace
+
+extern "C" {
+
+ebit_status ebit_tune_lookup(const char* path, const ebit_grid* grid, const ebit_opts* base, ebit_opts* chosen,
+                             int* found) {
+  char msg[256];
+  if (!path || !grid || !base || !chosen || !found) return EBIT_EINVAL;
+  if (!valid_grid(grid, msg, sizeof(msg))) return EBIT_EINVAL;
+  *chosen = *base;
+  *found = 0;
+  int nu, tail, k;
+  double ms;
+  if (cache_find(path, ctx_key(grid, base), &nu, &tail, &k, &ms)) {
+    apply_schedule(chosen, nu, tail, k);
+    *found = 1;
+  }
+  return EBIT_OK;
+}
+
+ebit_status ebit_tune_store(const char* path, const ebit_grid* grid, const ebit_opts* chosen, double ms) {
+  char msg[256];
+  if (!path || !grid || !chosen) return EBIT_EINVAL;
+  if (!valid_grid(grid, msg, sizeof(msg))) return EBIT_EINVAL;
+  return cache_put(path, ctx_key(grid, chosen), chosen, ms) ? EBIT_OK : EBIT_EIO;
+}
+
+ebit_status ebit_autotune_cached(ebit_ctx* c, const char* path, const double* b_heat, const double* b_press, double* x,
+                                 ebit_opts* chosen, double* best_ms, int* from_cache) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!path) return fail(c, EBIT_EINVAL, "NULL cache path");
+  int nu, tail, k;
+  double ms;
+  if (cache_find(path, ctx_key(&c->grid, &c->opts), &nu, &tail, &k, &ms)) {
+    ebit_opts o = c->opts;
+    apply_schedule(&o, nu, tail, k);
+    ebit_ctx* const cs[1] = {c};
+    const hipError_t e = replan(&c->plan, cs, 1, &o, c->plan_mem, c->plan_bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "re-plan with the cached schedule");
+    c->opts = o;
+    if (chosen) *chosen = o;
+    if (best_ms) *best_ms = ms;
+    if (from_cache) *from_cache = 1;
+    return EBIT_OK;
+  }
+  double m = 0;
+  s = ebit_autotune(c, b_heat, b_press, x, chosen, &m);
+  if (best_ms) *best_ms = m;
+  if (from_cache) *from_cache = 0;
+  if (s != EBIT_OK) return s;
+  if (!cache_put(path, ctx_key(&c->grid, &c->opts), &c->opts, m)) return fail(c, EBIT_EIO, "cannot write the cache");
+  return EBIT_OK;
+}
+
+ebit_status ebit_batch_autotune_cached(ebit_batch* b, const char* path, const double* const b_heat[],
+                                       const double* const b_press[], double* const x[], ebit_opts* chosen,
+                                       double* best_ms, int* from_cache) {
+  ebit_status s = batch_ready(b);
+  if (s != EBIT_OK) return s;
+  if (!path) return bfail(b, EBIT_EINVAL, -1, "NULL cache path");
+  int nu, tail, k;
+  double ms;
+  if (cache_find(path, batch_key(b, &b->opts), &nu, &tail, &k, &ms)) {
+    ebit_opts o = b->opts;
+    apply_schedule(&o, nu, tail, k);
+    const hipError_t e = replan(&b->plan, b->ctx, b->n, &o, b->ws, b->ws_bytes);
+    if (e != hipSuccess) return bhip(b, e, "re-plan with the cached schedule");
+    b->opts = o;
+    if (chosen) *chosen = o;
+    if (best_ms) *best_ms = ms;
+    if (from_cache) *from_cache = 1;
+    return EBIT_OK;
+  }
+  double m = 0;
+  s = ebit_batch_autotune(b, b_heat, b_press, x, chosen, &m);
+  if (best_ms) *best_ms = m;
+  if (from_cache) *from_cache = 0;
+  if (s != EBIT_OK) return s;
+  if (!cache_put(path, batch_key(b, &b->opts), &b->opts, m)) return bfail(b, EBIT_EIO, -1, "cannot write the cache");
   return EBIT_OK;
 }
 

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libebit.so")
 
-OK, EINVAL, ENOMEM, EGEOM, ENOCONV, ENAN, EHIP, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EGEOM, ENOCONV, ENAN, EHIP, ESTATE, EIO = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
 OUTER_PCG, OUTER_DC = 0, 1
 SYS_HEAT, SYS_PRESSURE = 0, 1
@@ -100,6 +100,14 @@ def load():
         "ebit_interface_velocity": (i, [vp, _P3, _P3, vp, _P3]),
         "ebit_advect_markers": (i, [vp, _P3, _P3, vp, vp, d]),
         "ebit_advect_energy": (i, [vp, vp, vp, _P3, _P3, vp, d, d, vp]),
+        "ebit_tune_lookup": (i, [ctypes.c_char_p, ctypes.POINTER(Grid), ctypes.POINTER(Opts), ctypes.POINTER(Opts),
+                                 ctypes.POINTER(i)]),
+        "ebit_tune_store": (i, [ctypes.c_char_p, ctypes.POINTER(Grid), ctypes.POINTER(Opts), d]),
+        "ebit_autotune_cached": (i, [vp, ctypes.c_char_p, vp, vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(d),
+                                     ctypes.POINTER(i)]),
+        "ebit_batch_autotune_cached": (i, [vp, ctypes.c_char_p, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), ctypes.POINTER(Opts), ctypes.POINTER(d),
+                                           ctypes.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -115,7 +123,8 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_profile", "ebit_profile_read", "ebit_batch_workspace_bytes", "ebit_batch_create",
             "ebit_batch_destroy", "ebit_batch_last_error", "ebit_batch_build_coeffs", "ebit_batch_heat_solve",
             "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune",
-            "ebit_cut_fractions_noalloc", "ebit_interface_velocity", "ebit_advect_markers", "ebit_advect_energy"]
+            "ebit_cut_fractions_noalloc", "ebit_interface_velocity", "ebit_advect_markers", "ebit_advect_energy",
+            "ebit_tune_lookup", "ebit_tune_store", "ebit_autotune_cached", "ebit_batch_autotune_cached"]
 NOALLOC_MAX_CELLS = 1 << 18
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ, EXT_IFACE_TO_BAND = range(3)
@@ -331,11 +340,43 @@ class Context:
         self.opts = o
         return {k: getattr(o, k) for k, _ in Opts._fields_}, ms.value
 
+    def autotune_cached(self, path, b_heat=None, b_press=None, x=None):
+        """autotune through the schedule cache file at path; returns
+        (chosen options dict, ms, from_cache)."""
+        o = Opts()
+        ms = ctypes.c_double()
+        hit = ctypes.c_int()
+        if x is None:
+            x = torch.empty_like(b_heat if b_heat is not None else b_press)
+        self._check(self.lib.ebit_autotune_cached(self.h, str(path).encode(), _ptr(b_heat, torch.float64),
+                                                  _ptr(b_press, torch.float64), _ptr(x, torch.float64),
+                                                  ctypes.byref(o), ctypes.byref(ms), ctypes.byref(hit)),
+                    "ebit_autotune_cached")
+        self.opts = o
+        return {k: getattr(o, k) for k, _ in Opts._fields_}, ms.value, bool(hit.value)
+
     def levels(self):
         n = ctypes.c_int()
         sizes = (ctypes.c_int * (3 * 32))()
         self._check(self.lib.ebit_levels(self.h, ctypes.byref(n), sizes), "ebit_levels")
         return [tuple(sizes[3 * l: 3 * l + 3]) for l in range(n.value)]
+
+
+def tune_lookup(path, grid, base):
+    """ebit_tune_lookup (host only): (found, Opts) for the grid's key."""
+    lib = load()
+    out = Opts()
+    found = ctypes.c_int()
+    st = lib.ebit_tune_lookup(str(path).encode(), ctypes.byref(grid), ctypes.byref(base), ctypes.byref(out),
+                              ctypes.byref(found))
+    if st != OK:
+        raise EbitError(st, "ebit_tune_lookup", "")
+    return bool(found.value), out
+
+
+def tune_store(path, grid, chosen, ms):
+    """ebit_tune_store (host only); returns the status code."""
+    return load().ebit_tune_store(str(path).encode(), ctypes.byref(grid), ctypes.byref(chosen), float(ms))
 
 
 def cut_fractions_noalloc(grid, markers, vcol, ccol, theta, flags, stream=None):
@@ -431,6 +472,21 @@ class Batch:
                                                  _ptrs(b_press) if b_press is not None else None, _ptrs(x),
                                                  ctypes.byref(o), ctypes.byref(ms)), "ebit_batch_autotune")
         return {k: getattr(o, k) for k, _ in Opts._fields_}, ms.value
+
+    def autotune_cached(self, path, b_heat=None, b_press=None, x=None):
+        """Batch counterpart of Context.autotune_cached."""
+        o = Opts()
+        ms = ctypes.c_double()
+        hit = ctypes.c_int()
+        ref = b_heat if b_heat is not None else b_press
+        if x is None:
+            x = [torch.empty_like(t) for t in ref]
+        self._check(self.lib.ebit_batch_autotune_cached(self.h, str(path).encode(),
+                                                        _ptrs(b_heat) if b_heat is not None else None,
+                                                        _ptrs(b_press) if b_press is not None else None, _ptrs(x),
+                                                        ctypes.byref(o), ctypes.byref(ms), ctypes.byref(hit)),
+                    "ebit_batch_autotune_cached")
+        return {k: getattr(o, k) for k, _ in Opts._fields_}, ms.value, bool(hit.value)
 
     def project(self, u_l, u_v, mdot, p, use_guess=False, check=True):
         s = self._stats()

@@ -31,7 +31,7 @@ def test_default_opts_and_status_strings():
     o = ebit.default_opts()
     assert o.precision == ebit.FP64 and o.outer == ebit.OUTER_PCG
     assert o.rtol == 1e-9 and o.nu1 == 2 and o.nu2 == 2 and o.theta_min == 1e-3
-    for s in (0, -1, -2, -3, -4, -5, -6, -7):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert ebit.status_string(s) != "unknown status"
 
 
@@ -83,3 +83,38 @@ def test_batch_workspace_bytes():
     assert b1 > 0 and b64 > 32 * b1
     om = ebit.default_opts(precision=ebit.MIXED)
     assert lib.ebit_batch_workspace_bytes(64, ctypes.byref(om)) > 0
+
+
+def test_schedule_cache_round_trip(tmp_path):
+    """ebit_tune_store / ebit_tune_lookup (host only): a stored schedule
+    comes back for its key (grid sizes, precision, outer loop) and only for
+    it; the last line of a key wins; foreign lines are ignored; a missing
+    file is no error; an unwritable path gives EBIT_EIO."""
+    path = tmp_path / "schedules.txt"
+    c = ei.config(0)
+    g = ebit.make_grid(c.dim, c.n, c.h, c.T_bc, c.p_bc)
+    base = ebit.default_opts(precision=ebit.MIXED)
+    found, o = ebit.tune_lookup(path, g, base)
+    assert not found and (o.nu1, o.tail_cells, o.check_every) == (base.nu1, base.tail_cells, base.check_every)
+    pick = ebit.default_opts(precision=ebit.MIXED)
+    pick.nu1 = pick.nu2 = 3
+    pick.tail_cells = 1024
+    pick.check_every = 4
+    assert ebit.tune_store(path, g, pick, 1.25) == ebit.OK
+    found, o = ebit.tune_lookup(path, g, base)
+    assert found and (o.nu1, o.nu2, o.tail_cells, o.check_every) == (3, 3, 1024, 4)
+    assert o.precision == ebit.MIXED and o.rtol == base.rtol
+    # another precision, another size: not found
+    assert not ebit.tune_lookup(path, g, ebit.default_opts(precision=ebit.FP64))[0]
+    g2 = ebit.make_grid(c.dim, (c.n[0], c.n[1] * 2, 1), c.h, c.T_bc, c.p_bc)
+    assert not ebit.tune_lookup(path, g2, base)[0]
+    # a later line of the same key wins; junk lines are skipped
+    with open(path, "a") as f:
+        f.write("something else entirely\nebit-schedule 2 64 64 1 1 0 not numbers\n")
+    pick.nu1 = pick.nu2 = 1
+    assert ebit.tune_store(path, g, pick, 0.5) == ebit.OK
+    found, o = ebit.tune_lookup(path, g, base)
+    assert found and (o.nu1, o.tail_cells, o.check_every) == (1, 1024, 4)
+    assert ebit.tune_store(tmp_path / "no" / "such" / "dir.txt", g, pick, 0.5) == ebit.EIO
+    bad = ebit.make_grid(2, (2, 64, 1), 1 / 64, c.T_bc, c.p_bc)
+    assert ebit.tune_store(path, bad, pick, 0.5) == ebit.EINVAL

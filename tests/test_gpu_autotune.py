@@ -95,3 +95,49 @@ def test_batch_autotune_then_parity():
     b.close()
     for x in ctxs:
         x.close()
+
+
+def test_schedule_cache_context_and_batch(tmp_path):
+    """ebit_autotune_cached: the first call times the candidates and appends
+    the winner to the file; a second context (batch) of the same key takes
+    it from the file without timing, gets the same schedule, and still
+    meets the parity bar."""
+    ebit = _ebit()
+    path = tmp_path / "schedules.txt"
+    c = ei.config(1, 48)
+    opts = ebit.default_opts(rtol=1e-15, max_iters=400, precision=ebit.MIXED)
+    say("[gpu] schedule cache: context")
+    chosen = []
+    for rep in range(2):
+        ctx, dc = ebit.context_for(c, opts)
+        ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, c.dt)
+        bh, bp = rhs_pair(ctx, dc)
+        ch, ms, hit = ctx.autotune_cached(path, bh, bp)
+        assert hit == (rep == 1), (rep, hit)
+        chosen.append((ch["nu1"], ch["tail_cells"], ch["check_every"]))
+        if rep == 1:
+            ref = oracle.pipeline.run_step(c, c.T0, c.u_l, c.u_v)
+            T = torch.zeros_like(dc.T0)
+            ctx.heat_solve(dc.T0, T)
+            assert rel(T.cpu().numpy(), ref["T"]) < 1e-12
+        ctx.close()
+    assert chosen[0] == chosen[1]
+    lines = [ln for ln in open(path) if ln.startswith("ebit-schedule")]
+    assert len(lines) == 1
+    say("[gpu] schedule cache: batch")
+    cases = ei.batch_cases(ncases=4, seed=4, sides=(16, 24, 32))
+    got = []
+    for rep in range(2):
+        ctxs, dcs = zip(*[ebit.context_for(x, opts) for x in cases])
+        b = ebit.Batch(list(ctxs))
+        b.build_coeffs([d.markers for d in dcs], [d.vcol for d in dcs], [d.ccol for d in dcs],
+                       [x.dt for x in cases])
+        pairs = [rhs_pair(cx, d) for cx, d in zip(ctxs, dcs)]
+        ch, ms, hit = b.autotune_cached(path, [p[0] for p in pairs], [p[1] for p in pairs])
+        assert hit == (rep == 1), (rep, hit)
+        got.append((ch["nu1"], ch["tail_cells"], ch["check_every"]))
+        b.close()
+        for cx in ctxs:
+            cx.close()
+    assert got[0] == got[1]
+    assert sum(1 for ln in open(path) if ln.startswith("ebit-schedule batch")) == 1
