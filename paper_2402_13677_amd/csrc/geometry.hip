@@ -85,6 +85,7 @@ __global__ void k_check_seam_vertices(Many<GeoArgs> m) {
 template <int M>
 __device__ inline void min_eigvec(double A[3][3], double v[3]) {
   double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  bool polish = false;
   for (int sweep = 0; sweep < 32; ++sweep) {
     double offn = 0.0, tot = 0.0;
 #pragma unroll
@@ -94,7 +95,13 @@ __device__ inline void min_eigvec(double A[3][3], double v[3]) {
         tot += A[p][q] * A[p][q];
         if (p != q) offn += A[p][q] * A[p][q];
       }
-    if (offn <= 1e-36 * tot) break;
+    // stop one sweep after the off-diagonal part reaches the matrix's
+    // rounding level (its Frobenius norm times 4 ulps; the last sweep
+    // polishes the eigenvectors): each rotation leaves a rounding residue of
+    // about that size, so a test much tighter never passes and runs every
+    // sweep
+    if (polish) break;
+    if (offn <= 7.888609052210118e-31 * tot) polish = true;
 #pragma unroll
     for (int p = 0; p < M - 1; ++p)
 #pragma unroll

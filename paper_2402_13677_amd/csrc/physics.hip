@@ -175,6 +175,77 @@ __device__ inline double fallback_grad(const FluxArgs& g, int kph, const double 
   return (best_T - g.Tsat) / best_p;
 }
 
+// The same per cell, with its four point values (two phases x two points
+// along the normal) taken by four lanes of one wave: each lane walks one
+// point's interpolation stencil, so the chain of dependent loads of an
+// interface cell is a quarter as long, and the lanes of the non-interface
+// cells of a wave are few (a wave holds 16 cells).  Lane 0 of the four
+// combines them exactly as k_mass_flux does (the same arithmetic on the
+// same values: the results are the same bits).
+template <int DIM>
+__global__ __launch_bounds__(EBIT_BLOCK) void k_mass_flux4(FluxArgs g) {
+  const Dims& d = g.d;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = t >> 2;
+  const int q = (int)(t & 3);
+  if (c >= d.N) return;
+  const uint8_t f = g.flags[c];
+  if (!(f & F_IF)) {
+    if (q == 0) g.mdot[c] = 0.0;
+    return;
+  }
+  // lane q: phase kph = 1 - (q >> 1) (liquid first), point q & 1
+  const int kph = (q >> 1) ? 0 : 1;
+  const int pt = q & 1;
+  const double h = g.h;
+  double cF[3], nF[3];
+  for (int r = 0; r < 3; ++r) {
+    cF[r] = g.cF[r * d.N + c];
+    nF[r] = g.nF[r * d.N + c];
+  }
+  const double d1 = h, d2 = 2.0 * h;
+  const double sg = kph ? 1.0 : -1.0;
+  double sd[3], P[3];
+  for (int r = 0; r < 3; ++r) {
+    sd[r] = sg * nF[r];
+    P[r] = cF[r] + (pt ? d2 : d1) * sd[r];
+  }
+  double T = 0.0;
+  const bool ok = point_value<DIM>(g, kph, P, sd, T);
+  // the group's four values and flags to its lane 0 (the four lanes of a
+  // cell are consecutive and all active here)
+  const int base = (int)(threadIdx.x & 63) & ~3;
+  double Tq[4];
+  int okq[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Tq[r] = __shfl(T, base + r, 64);
+    okq[r] = __shfl(ok ? 1 : 0, base + r, 64);
+  }
+  if (q != 0) return;
+  double D[2];
+  int fb = 0;
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int ph = kk == 0 ? 1 : 0;  // liquid first, as the oracle does
+    const int r0 = kk * 2;
+    if (okq[r0] && okq[r0 + 1]) {
+      D[ph] = (d2 / d1 * (Tq[r0] - g.Tsat) - d1 / d2 * (Tq[r0 + 1] - g.Tsat)) / (d2 - d1);
+    } else {
+      ++fb;
+      const double s2 = ph ? 1.0 : -1.0;
+      double sd2[3], P1[3];
+      for (int r = 0; r < 3; ++r) {
+        sd2[r] = s2 * nF[r];
+        P1[r] = cF[r] + d1 * sd2[r];
+      }
+      D[ph] = fallback_grad<DIM>(g, ph, cF, sd2, P1);
+    }
+  }
+  g.mdot[c] = (g.lam[1] * D[1] + g.lam[0] * D[0]) / g.h_lg;
+  if (fb) atomicAdd(&g.scal->fallbacks, fb);
+}
+
 template <int DIM, bool B>
 __global__ void k_mass_flux(Many<FluxArgs> m) {
   long long lb, nb;
@@ -555,7 +626,7 @@ extern "C" hipError_t ebit_launch_mass_flux(const Dims* d, double h, const doubl
   FluxArgs g;
   ebit_flux_args(&g, d, h, lam, h_lg, Tsat, theta_min, flags, th, cF, nF, T, mdot, mface, scal);
   if (d->dim == 3)
-    hipLaunchKernelGGL((k_mass_flux<3, false>), dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
+    hipLaunchKernelGGL(k_mass_flux4<3>, dim3(nblk(4 * d->N)), dim3(EBIT_BLOCK), 0, st, g);
   else
     hipLaunchKernelGGL((k_mass_flux<2, false>), dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, many_one(g));
   if (mface) hipLaunchKernelGGL(k_mass_flux_faces, dim3(nblk(d->N)), dim3(EBIT_BLOCK), 0, st, g);
