@@ -8,7 +8,7 @@ import math
 import numpy as np
 
 import ebit_inputs as ei
-from oracle import advect, closed, extend, flux, geometry, heat, project, solve
+from oracle import advect, closed, energy, extend, flux, geometry, heat, project, solve
 
 # Sec. 3.1: water at 1 bar, wall 10 K above saturation, 10 mm domain, the
 # layer 322.5 um thick at t = 0.282 s
@@ -54,9 +54,13 @@ def interface_x(case):
     return float(np.mean((ii + mx[jj, ii]) * case.h))
 
 
-def oracle_time_loop(case, t_end, t0=STEFAN_T0, on_step=None):
-    """Sec. 2.5 on the oracle, with T* = T^n (the vapour is at rest and the
-    liquid uniform, so the advection step leaves T unchanged):
+def oracle_time_loop(case, t_end, t0=STEFAN_T0, on_step=None, energy_advection=False):
+    """Sec. 2.5 on the oracle:
+      (with energy_advection) the advection step of the energy equation:
+      T* from each phase's field carried across the interface (Eq.
+      extrapolation) and that phase's velocity u^n (Eq. energy_advection),
+      then T* carried across again; without it T* = T^n (exact for the
+      Stefan problem, whose vapour is at rest and liquid uniform);
       the interfacial velocity from u^n and the band-extended mdot^n moves
       the markers; cells that change phase take the other phase's value
       carried across by Eq. extrapolation; the diffusion step on the new
@@ -74,6 +78,10 @@ def oracle_time_loop(case, t_end, t0=STEFAN_T0, on_step=None):
     for s in range(nsteps):
         Tl = extend.extend(case, geo, T, extend.LIQ_TO_VAP, EXT_ITERS)
         Tv = extend.extend(case, geo, T, extend.VAP_TO_LIQ, EXT_ITERS)
+        if energy_advection:
+            T = energy.advect_energy(case, Tl, Tv, ul, uv, dt)
+            Tl = extend.extend(case, geo, T, extend.LIQ_TO_VAP, EXT_ITERS)
+            Tv = extend.extend(case, geo, T, extend.VAP_TO_LIQ, EXT_ITERS)
         mk, vc, cc = advect.advect(case, geo, ul, uv, mb, dt)
         old = case.ccol.ravel()
         new = cc.ravel()
@@ -120,6 +128,31 @@ def _case_from(n, h, nn, vcol, ccol, markers, periodic, rho):
     T0 = np.zeros(ei.cell_shape(2, nn))
     return ei.Case(f"line{n}", 2, nn, h, pr, 1e-3, T_bc, p_bc, markers, vcol, ccol, T0, z,
                    [x.copy() for x in z])
+
+
+def translating_bubble_case(n, U, dt, dT=0.2):
+    """A vapour disc (R = 0.203, off the grid's symmetry lines) in a unit box
+    periodic in x with walls in y,
+    carried by a uniform flow U along x in both phases; the liquid holds
+    T_sat + dT (1 + sin 2 pi x) sin^2 pi y, the vapour T_sat, so the flow
+    carries a temperature field with gradients and the interface evaporates
+    where the liquid is warm.  Unit properties but for rho_v = lam_v = 0.5
+    and h_lg = 100 (the evaporation speed mdot / rho_v stays a fraction of
+    U)."""
+    h = 1.0 / n
+    nn = (n, n, 1)
+    ls = ei.Ball((0.513, 0.507, 0.0), 0.203, 1.0, 2)
+    vcol, ccol, markers = ei.colours_and_markers(2, nn, h, ls)
+    pr = ei.Props(rho_l=1.0, rho_v=0.5, lam_l=1.0, lam_v=0.5, cp_l=1.0, cp_v=1.0, h_lg=100.0, T_sat=0.0)
+    x, y = np.meshgrid((np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h)
+    Tl = dT * (1.0 + np.sin(2 * np.pi * x)) * np.sin(np.pi * y) ** 2
+    T0 = np.where(ccol[0] == 1, Tl, 0.0)[None].astype(np.float64)
+    T_bc = [(ei.PERIODIC, 0.0), (ei.PERIODIC, 0.0), (ei.NEUMANN, 0.0), (ei.NEUMANN, 0.0)]
+    p_bc = [(ei.PERIODIC, 0.0), (ei.PERIODIC, 0.0), (ei.DIRICHLET, 0.0), (ei.DIRICHLET, 0.0)]
+    ux = np.full(ei.face_shape(2, nn, 0), U)
+    uy = np.zeros(ei.face_shape(2, nn, 1))
+    return ei.Case(f"translating_bubble_{n}", 2, nn, h, pr, dt, T_bc, p_bc, markers, vcol, ccol, T0,
+                   [ux, uy], [ux.copy(), uy.copy()])
 
 
 def circle_case(n, centre, R, inside_vapour=True, rho=(1.0, 1.0)):
