@@ -78,6 +78,48 @@ def ghost_velocities(case, geo, mdot, u_l, u_v):
     return ul, uv
 
 
+def ghost_velocities_band(case, geo, mdot_band, u_l, u_v):
+    """Eq. ghost_velocity over the whole narrow band (Sec. 2.3, used only in
+    the band; Sec. 2.4, the mass flux carried to the band by Eq.
+    extrapolation for this purpose; step 4 of the time iteration of Sec.
+    2.5).  mdot_band: the mass flux after extension to the band.  Copies
+    returned.
+
+    Readings (the paper names the band and the jump, not the face rule):
+      * a face is in the band when both its cells are band cells (those of
+        extend.band); a cut link always is (its holder is an interface cell
+        and the other cell lies in that cell's block);
+      * a cut face takes the ghost of ghost_velocities (face owner, the
+        holder's mdot and facet normal); the holder is an interface cell,
+        whose extended value is its own mass flux;
+      * an uncut face belongs to the common phase of its two cells; mdot_f
+        and n_f are the means of the two cells' extended mdot and unit band
+        normals (a zero band normal counts as zero), and the other phase's
+        field takes the jump with the sign of ghost_velocities (u_v - u_l =
+        mdot_f [1/rho] n_f on every band face)."""
+    from .extend import band
+    pr = case.props
+    col = case.ccol.ravel().astype(int)
+    jump_coef = 1.0 / pr.rho_l - 1.0 / pr.rho_v      # [1/rho]
+    m = np.asarray(mdot_band, dtype=np.float64).ravel()
+    inb, nrm = band(case, geo)
+    ul, uv = ghost_velocities(case, geo, m, u_l, u_v)
+    for a in range(case.dim):
+        th = geo["theta"][a]
+        lo, up = _face_cells(case, a)
+        sel = (lo >= 0) & (up >= 0) & np.isnan(th)
+        sel[sel] = inb[lo[sel]] & inb[up[sel]]
+        c, n = lo[sel], up[sel]
+        mf = 0.5 * (m[c] + m[n])
+        nf = 0.5 * (nrm[c, a] + nrm[n, a])
+        jump = mf * jump_coef * nf
+        liq = col[c] == 1
+        ua, va = ul[a][sel], uv[a][sel]
+        uv[a][sel] = np.where(liq, ua + jump, va)
+        ul[a][sel] = np.where(liq, ua, va - jump)
+    return ul, uv
+
+
 def divergence(case, u_l, u_v):
     """div_c of the cell's own phase field (Eq. poisson_ghost_fluid RHS)."""
     col = case.ccol.astype(int)

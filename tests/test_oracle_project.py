@@ -240,3 +240,133 @@ def test_pressure_direct_matches_dense_lu(dim, n, seed):
     x1 = solve.direct(-L, -b, op)
     x2 = solve.dense(L, b)
     assert np.max(np.abs(x1 - x2)) <= 1e-12 * np.max(np.abs(x2))
+
+
+@pytest.mark.parametrize("dim,mvec,pt", [
+    (2, (0.8, 0.6, 0.0), (0.52, 0.47, 0.0)),
+    (2, (-0.28, 0.96, 0.0), (0.41, 0.55, 0.0)),
+    (3, (0.48, 0.6, 0.64), (0.49, 0.53, 0.51)),
+])
+def test_band_ghosts_planar_interface(dim, mvec, pt):
+    """Ghost velocities over the narrow band (Eq. ghost_velocity, the mass
+    flux carried to the band, step 4 of Sec. 2.5) on an exact straight
+    interface, worked out from the definitions rather than the oracle's code.
+
+    Every band normal of a plane is the plane's unit normal, and a mass flux
+    linear in position has, as the mean of two neighbouring cells, its value
+    at the face centre.  So on every face whose two cells are band cells
+    (a cell is in the band when its 3^d block holds an interface cell):
+      * a cut face follows the owner/holder rule (mdot of the cell holding
+        the crossing);
+      * an uncut face keeps the real field of its cells' common phase, and
+        the other field takes u_vap - u_liq = mdot(x_face) [1/rho] n_a;
+    every other face keeps both fields.  A flipped sign, a wrong axis of n,
+    the wrong field, one cell's mdot in place of the mean, or a face with
+    one cell outside the band taking a ghost fails here."""
+    n = 16 if dim == 2 else 9
+    nn = (n, n, n if dim == 3 else 1)
+    h = 1.0 / n
+    mv = np.asarray(mvec, float)
+    mv = mv / np.linalg.norm(mv)
+    ls = ei.Plane(mv, pt)
+    vcol, ccol, mk = ei.colours_and_markers(dim, nn, h, ls)
+    rng = np.random.default_rng(5)
+    props = ei.Props(rho_l=1.0, rho_v=0.02)
+    u = [rng.normal(0, 1.0, ei.face_shape(dim, nn, a)) for a in range(dim)]
+    uv = [rng.normal(0, 1.0, ei.face_shape(dim, nn, a)) for a in range(dim)]
+    case = ei.Case("tilted", dim, nn, h, props, 1e-4, [(0, 0.0)] * (2 * dim), [(1, 0.0)] * (2 * dim),
+                   mk, vcol, ccol, np.zeros(ei.cell_shape(dim, nn)), u, uv)
+    g = geometry.build(case)
+    N = case.ncells
+    nz = nn[2] if dim == 3 else 1
+    alpha, beta = 0.7, np.array([0.3, -0.45, 0.2])
+
+    def centre(i, j, kk):
+        return np.array([(i + .5) * h, (j + .5) * h, (kk + .5) * h if dim == 3 else 0.0])
+
+    mdot = np.zeros(N)
+    for kk in range(nz):
+        for j in range(n):
+            for i in range(n):
+                mdot[i + n * (j + n * kk)] = alpha + float(np.dot(beta, centre(i, j, kk)))
+    ul_o, uv_o = project.ghost_velocities_band(case, g, mdot, case.u_l, case.u_v)
+    # band membership from its definition
+    is_if = np.asarray(g["is_if"]).ravel().astype(bool)
+    inb = np.zeros(N, bool)
+    rz = 1 if dim == 3 else 0
+    for kk in range(nz):
+        for j in range(n):
+            for i in range(n):
+                for dk in range(-rz, rz + 1):
+                    for dj in (-1, 0, 1):
+                        for di in (-1, 0, 1):
+                            q = (i + di, j + dj, kk + dk)
+                            if all(0 <= q[b] < nn[b] for b in range(3)) and is_if[q[0] + n * (q[1] + n * q[2])]:
+                                inb[i + n * (j + n * kk)] = True
+    jump_coef = 1.0 / props.rho_l - 1.0 / props.rho_v
+    col = ccol.ravel()
+    seen = {"cut": 0, "liq": 0, "vap": 0, "half_band": 0}
+    for a in range(dim):
+        exp_ul, exp_uv = u[a].copy(), uv[a].copy()
+        for kk in range(nz):
+            for j in range(n):
+                for i in range(n):
+                    q = [i, j, kk]
+                    q[a] += 1
+                    if q[a] >= n:
+                        continue
+                    c = i + n * (j + n * kk)
+                    up = q[0] + n * (q[1] + n * q[2])
+                    fidx = (kk, j, i + 1) if a == 0 else ((kk, j + 1, i) if a == 1 else (kk + 1, j, i))
+                    if dim == 2:
+                        fidx = (0,) + fidx[1:]
+                    if not (inb[c] and inb[up]):
+                        seen["half_band"] += int(inb[c] or inb[up])
+                        continue
+                    if col[c] != col[up]:
+                        xc = centre(i, j, kk)
+                        t = -float(np.dot(mv, xc - np.asarray(pt))) / (mv[a] * h)
+                        holder = c if t < 0.5 else up
+                        owner = col[c] if t > 0.5 else col[up]
+                        jump = mdot[holder] * jump_coef * mv[a]
+                        seen["cut"] += 1
+                    else:
+                        xf = centre(i, j, kk)
+                        xf[a] += 0.5 * h
+                        jump = (alpha + float(np.dot(beta, xf))) * jump_coef * mv[a]
+                        owner = col[c]
+                        seen["liq" if owner == 1 else "vap"] += 1
+                    if owner == 1:
+                        exp_uv[fidx] = u[a][fidx] + jump
+                    else:
+                        exp_ul[fidx] = uv[a][fidx] - jump
+        scale = max(np.max(np.abs(exp_ul)), np.max(np.abs(exp_uv)))
+        assert np.max(np.abs(ul_o[a] - exp_ul)) <= 1e-12 * scale
+        assert np.max(np.abs(uv_o[a] - exp_uv)) <= 1e-12 * scale
+    assert all(v > 0 for v in seen.values()), seen
+
+
+def test_band_ghosts_reduce_to_cut_faces_off_the_band():
+    """On the 2D bubble with a mass flux only in the interface cells (not
+    extended): the cut faces take exactly the projection's ghosts, and an
+    uncut band face whose two cells carry no mass flux gets a ghost equal to
+    the real velocity of its phase (a zero jump)."""
+    case = ei.config(0)
+    g = geometry.build(case)
+    rng = np.random.default_rng(9)
+    mdot = rng.normal(0.0, 1.0, case.ncells) * np.asarray(g["is_if"]).ravel()
+    ul_b, uv_b = project.ghost_velocities_band(case, g, mdot, case.u_l, case.u_v)
+    ul_c, uv_c = project.ghost_velocities(case, g, mdot, case.u_l, case.u_v)
+    col = case.ccol.ravel().astype(int)
+    for a in range(case.dim):
+        th = g["theta"][a]
+        cut = ~np.isnan(th)
+        assert np.array_equal(ul_b[a][cut], ul_c[a][cut]) and np.array_equal(uv_b[a][cut], uv_c[a][cut])
+        # uncut faces: a zero mdot on both cells leaves u_v = u_l on liquid faces (ghost = real)
+        lo, up = flux._face_cells(case, a)
+        both = (lo >= 0) & (up >= 0) & ~cut
+        changed = both & ((ul_b[a] != case.u_l[a]) | (uv_b[a] != case.u_v[a]))
+        z = changed & (mdot[np.maximum(lo, 0)] == 0) & (mdot[np.maximum(up, 0)] == 0)
+        liq = col[np.maximum(lo, 0)] == 1
+        assert np.array_equal(uv_b[a][z & liq], ul_b[a][z & liq])
+        assert np.array_equal(ul_b[a][z & ~liq], uv_b[a][z & ~liq])
