@@ -541,8 +541,49 @@ def extension_bench(case, steps=40, reps=5):
         out[name] = {"changing_cells": moved, "call_ms": t_full, "setup_ms": t_set, "step_us": step_s * 1e6,
                      "algorithmic_bytes_per_step": byts, "achieved_GBps": byts / step_s / 1e9,
                      "frac": byts / step_s / 1e9 / HBM_PEAK_GBS}
+    out["ghost_band"] = ghost_band_bench(case, ctx, reps)
     ctx.close()
     return out
+
+
+def ghost_band_bench(case, ctx, reps):
+    """Eq. ghost_velocity over the narrow band (ebit_ghost_band) from a
+    band-extended mass flux, on the workload's geometry: median ms per call.
+    Algorithmic bytes per call: the band (dim dilation passes of one byte
+    read and one written per cell, then one byte read per cell), the facet
+    normals of the interface cells (8 B per axis), and per ghost face its
+    theta, the two cells' mass fluxes, the real value read and the ghost
+    written (40 B)."""
+    import numpy as np
+    import torch
+    from paper_2402_13677_amd import ebit
+
+    rng = np.random.default_rng(12)
+    m = torch.from_numpy(rng.uniform(0.5, 1.5, case.ncells)).to("cuda")
+    ctx.extend(m, ebit.EXT_IFACE_TO_BAND, 10)
+    shapes = [int(np.prod(case.u_l[a].shape)) for a in range(case.dim)]
+    l0 = [torch.from_numpy(rng.normal(0.0, 1.0, k)).to("cuda") for k in shapes]
+    v0 = [torch.from_numpy(rng.normal(0.0, 1.0, k)).to("cuda") for k in shapes]
+    ul, uv = [x.clone() for x in l0], [x.clone() for x in v0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(reps):
+        for a in range(case.dim):
+            ul[a].copy_(l0[a])
+            uv[a].copy_(v0[a])
+        ev[0].record()
+        ctx.ghost_band(ul, uv, m)
+        ev[1].record()
+        ev[1].synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    faces = sum(int((ul[a] != l0[a]).sum().item()) + int((uv[a] != v0[a]).sum().item()) for a in range(case.dim))
+    flags = torch.empty(case.ncells, dtype=torch.uint8, device="cuda")
+    ctx.get_geometry(flags=flags)
+    n_if = int(((flags >> 7) & 1).sum().item())
+    t = statistics.median(ms) * 1e-3
+    byts = case.ncells * (2.0 * case.dim + 1.0) + n_if * 8.0 * case.dim + faces * 40.0
+    return {"ghost_faces": faces, "interface_cells": n_if, "call_ms": t * 1e3, "algorithmic_bytes": byts,
+            "achieved_GBps": byts / t / 1e9, "frac": byts / t / 1e9 / HBM_PEAK_GBS}
 
 
 def extension_cpu_baseline(case, steps=40):
@@ -555,8 +596,12 @@ def extension_cpu_baseline(case, steps=40):
     for mode in (0, 1, 2):
         oracle.extend.extend(case, geo, q0, mode, steps)
     el = time.perf_counter() - t0
-    return {"ms_per_call": el / 3 * 1e3, "cores": 1, "kind": "oracle",
-            "sample": f"the three modes once each, {steps} steps, on the workload's geometry"}
+    t0 = time.perf_counter()
+    oracle.project.ghost_velocities_band(case, geo, q0, case.u_l, case.u_v)
+    gb = time.perf_counter() - t0
+    return {"ms_per_call": el / 3 * 1e3, "ghost_band_ms": gb * 1e3, "cores": 1, "kind": "oracle",
+            "sample": f"the three modes once each, {steps} steps, and the band ghost velocities once, "
+                      "on the workload's geometry"}
 
 
 def one_fluid_bench(case, precision, schedule, reps=10):

@@ -17,6 +17,8 @@
  *                      ghost_velocity), the variable-density Poisson problem
  *                      (Eqs. Poisson_equation, poisson_ghost_fluid) solved by
  *                      geometric multigrid, and the face-velocity update
+ *   ebit_ghost_band    the ghost velocities of Eq. ghost_velocity on every
+ *                      narrow-band face, from the band-extended mass flux
  *   ebit_interface_velocity, ebit_advect_markers
  *                      the interfacial velocity (Eq. jump_interfacial_vel)
  *                      and the EBIT marker motion of one time step (Sec. 2.1)
@@ -234,6 +236,30 @@ ebit_status ebit_project(ebit_ctx* ctx, double* const u_l[3], double* const u_v[
  * negative count; EBIT_ESTATE before ebit_build_coeffs. */
 typedef enum { EBIT_EXT_LIQ_TO_VAP = 0, EBIT_EXT_VAP_TO_LIQ = 1, EBIT_EXT_IFACE_TO_BAND = 2 } ebit_ext_mode;
 ebit_status ebit_extend(ebit_ctx* ctx, double* q, int mode, int iters);
+
+/* Secs. 2.3-2.5, Eq. ghost_velocity over the whole narrow band, from the mass
+ * flux carried to the band (step 4 of the time iteration: the mass flux, then
+ * the ghost velocities; Sec. 2.4 extends the mass flux to the band for this
+ * purpose).  A face gets a ghost when both its cells are band cells (those of
+ * ebit_extend), with the geometry of the last ebit_build_coeffs:
+ *   - a cut face as in ebit_project (its owner by theta, mdot and n of the
+ *     cell holding the crossing; that cell carries a facet, so its band value
+ *     is its own mass flux);
+ *   - an uncut face belongs to the common phase of its two cells and takes
+ *     mdot_f = (mdot_c + mdot_n) / 2 and n_f = (n_c + n_n)_a / 2, the means of
+ *     the two cells' band values and unit band normals (0 where the block's
+ *     facet normals sum to zero).
+ * The other phase's field takes u_vap = u_liq + mdot_f [1/rho] n_f on a
+ * liquid face and u_liq = u_vap - mdot_f [1/rho] n_f on a vapour face,
+ * [1/rho] = 1/rho_l - 1/rho_v.  Every other face entry is left as it is.
+ * u_l[a], u_v[a] (a < dim): axis-a face arrays, updated in place; mdot_band:
+ * cells (ebit_mass_flux, then ebit_extend with EBIT_EXT_IFACE_TO_BAND).  All
+ * device, caller-owned.  Asynchronous on the context stream; it reuses the
+ * context's solver scratch, so it is not to overlap a solve of the same
+ * context.  EBIT_EINVAL for a NULL argument; EBIT_ESTATE before
+ * ebit_build_coeffs.  ebit_project sets the cut faces again, to the same
+ * values when given the same mass flux. */
+ebit_status ebit_ghost_band(ebit_ctx* ctx, double* const u_l[3], double* const u_v[3], const double* mdot_band);
 
 /* Sec. 2.3, the one-fluid projection the paper sets against the ghost-fluid
  * one (Eqs. Poisson_equation and pc_source): one face velocity field u (a <

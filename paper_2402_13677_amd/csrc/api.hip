@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "ebit_internal.h"
+#include "ghost.h"
 
 using namespace ebit;
 
@@ -962,6 +963,22 @@ ebit_status ebit_extend(ebit_ctx* c, double* q, int mode, int iters) {
         ebit_launch_extend(&c->fd, mode, iters, c->flags, c->nF, q, c->bvec, (uint8_t*)c->B.z32,
                            (unsigned long long*)c->B.z64, w, (int*)c->B.partial, c->st),
         "extend");
+  return EBIT_OK;
+}
+
+ebit_status ebit_ghost_band(ebit_ctx* c, double* const u_l[3], double* const u_v[3], const double* mdot_band) {
+  ebit_status s = check_ready(c);
+  if (s != EBIT_OK) return s;
+  if (!u_l || !u_v || !mdot_band) return fail(c, EBIT_EINVAL, "NULL argument");
+  for (int a = 0; a < c->fd.dim; ++a)
+    if (!u_l[a] || !u_v[a]) return fail(c, EBIT_EINVAL, "NULL velocity array");
+  // scratch as in ebit_extend: the band bytes in the FP32 iterate, the
+  // dilation's counter in the reduction partials
+  const double jump = 1.0 / c->props.rho_l - 1.0 / c->props.rho_v;
+  HIPCK(c,
+        ebit_launch_ghost_band(&c->fd, jump, c->flags, c->th, c->nF, mdot_band, u_l, u_v, (uint8_t*)c->B.z32,
+                               (int*)c->B.partial, c->st),
+        "band ghost velocities");
   return EBIT_OK;
 }
 

@@ -27,11 +27,17 @@
 // alternates between q and a work array: a target reads targets from the
 // current source and every other cell from q, whose non-target entries
 // never change.
+//
+// The same band carries Eq. ghost_velocity from the extended mass flux to
+// every face whose two cells are band cells (k_ghost_band): cut faces by the
+// projection's rule, uncut faces with the means of the two cells' mass flux
+// and unit band normals.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "ebit_internal.h"
+#include "ghost.h"
 
 namespace ebit {
 namespace {
@@ -191,6 +197,78 @@ __global__ void k_ext_copy(const unsigned long long* __restrict__ list, const in
   }
 }
 
+// The unit band normal of band cell (i, j, k) (zero where the sum of its
+// block's facet normals vanishes).
+__device__ inline void unit_band_normal(const Dims& d, const uint8_t* flags, const double* nF, int i, int j, int k,
+                                        double n[3]) {
+  double s[3];
+  if (!band_normal_sum(d, flags, nF, i, j, k, s)) {
+    n[0] = n[1] = n[2] = 0.0;
+    return;
+  }
+  const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) n[r] = s[r] / L;
+}
+
+struct GhostBandArgs {
+  Dims d;
+  double jump;  // [1/rho] = 1/rho_l - 1/rho_v
+  const uint8_t* flags;
+  const uint8_t* band;
+  const double* th[3];
+  const double* nF;
+  const double* mdot;  // the mass flux carried to the band
+  double* ul[3];
+  double* uv[3];
+};
+
+// Eq. ghost_velocity on the band faces.  Each band cell handles its + faces
+// and, on the first layer, face 0 (the periodic copy of face n), as the
+// projection's ghost kernel does; every cut face has two band cells (its
+// holder carries a facet, the other cell lies in the holder's block), so the
+// cut faces handled here are exactly the projection's.
+__global__ __launch_bounds__(EXT_BLOCK) void k_ghost_band(GhostBandArgs g) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const Dims& d = g.d;
+  if (c >= d.N || !g.band[c]) return;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  const uint8_t f = g.flags[c];
+  double nc[3];
+  bool have_nc = false;
+  for (int s = 0; s < 2 * d.dim; ++s) {
+    const int a = s >> 1, up = s & 1;
+    const int ia = (a == 0) ? i : (a == 1) ? j : k;
+    if (!(up || ia == 0)) continue;
+    const int sd = up ? 1 : -1;
+    long long m;
+    if (!nbr_cell(d, i, j, k, a == 0 ? sd : 0, a == 1 ? sd : 0, a == 2 ? sd : 0, m)) continue;  // a wall
+    const long long fi = face_of_side(d, i, j, k, s);
+    if ((f >> s) & 1) {
+      const long long lo = up ? c : m, hi = up ? m : c;
+      cut_face_ghost(d, g.flags, g.nF, g.mdot, g.jump, a, lo, hi, g.th[a][fi], fi, g.ul[a], g.uv[a]);
+      continue;
+    }
+    if (!g.band[m]) continue;
+    if (!have_nc) {
+      unit_band_normal(d, g.flags, g.nF, i, j, k, nc);
+      have_nc = true;
+    }
+    int mi, mj, mk;
+    cell_ijk(d, m, mi, mj, mk);
+    double nm[3];
+    unit_band_normal(d, g.flags, g.nF, mi, mj, mk, nm);
+    const double mf = 0.5 * (g.mdot[c] + g.mdot[m]);
+    const double nf = 0.5 * (nc[a] + nm[a]);
+    const double jmp = mf * g.jump * nf;
+    if (f & F_LIQ)
+      g.uv[a][fi] = g.ul[a][fi] + jmp;
+    else
+      g.ul[a][fi] = g.uv[a][fi] - jmp;
+  }
+}
+
 }  // namespace
 }  // namespace ebit
 
@@ -243,5 +321,35 @@ extern "C" hipError_t ebit_launch_extend(const Dims* d, int mode, int iters, con
   if (src == work)
     hipLaunchKernelGGL(k_ext_copy, dim3(nl), dim3(EXT_BLOCK), 0, st, (const unsigned long long*)list,
                        (const int*)counter, (const double*)work, q);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t ebit_launch_ghost_band(const Dims* d, double jump, const uint8_t* flags,
+                                             const double* const th[3], const double* nF, const double* mdot,
+                                             double* const ul[3], double* const uv[3], uint8_t* bytes, int* counter,
+                                             hipStream_t st) {
+  const unsigned nb = (unsigned)((d->N + EXT_BLOCK - 1) / EXT_BLOCK);
+  uint8_t* A = bytes;
+  uint8_t* B = bytes + d->N;
+  const uint8_t* in = nullptr;
+  uint8_t* out = A;
+  for (int ax = 0; ax < d->dim; ++ax) {
+    hipLaunchKernelGGL(k_ext_dilate, dim3(nb), dim3(EXT_BLOCK), 0, st, *d, ax, flags, in, out, counter);
+    in = out;
+    out = (out == A) ? B : A;
+  }
+  GhostBandArgs g;
+  g.d = *d;
+  g.jump = jump;
+  g.flags = flags;
+  g.band = in;
+  g.nF = nF;
+  g.mdot = mdot;
+  for (int a = 0; a < 3; ++a) {
+    g.th[a] = a < d->dim ? th[a] : nullptr;
+    g.ul[a] = a < d->dim ? ul[a] : nullptr;
+    g.uv[a] = a < d->dim ? uv[a] : nullptr;
+  }
+  hipLaunchKernelGGL(k_ghost_band, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
   return hipGetLastError();
 }

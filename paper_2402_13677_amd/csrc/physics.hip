@@ -13,6 +13,7 @@
 #pragma clang fp contract(off)
 
 #include "ebit_internal.h"
+#include "ghost.h"
 
 namespace ebit {
 
@@ -440,8 +441,9 @@ __device__ inline double one_fluid_source(const ProjArgs& g, int i, int j, int k
   return g.mdot[c] * A * g.src;
 }
 
-// Ghost value on every cut face (Eq. ghost_velocity).  Each cell handles its
-// + faces and, on the first layer, face 0 (the periodic copy of face n).
+// Ghost value on every cut face (Eq. ghost_velocity, the rule of
+// cut_face_ghost).  Each cell handles its + faces and, on the first layer,
+// face 0 (the periodic copy of face n).
 template <bool B>
 __global__ void k_ghost_vel(Many<ProjArgs> m) {
   long long lb, nb;
@@ -462,16 +464,7 @@ __global__ void k_ghost_vel(Many<ProjArgs> m) {
     const long long nb = cell_index(d, ni, nj, nk);
     const long long lo = up ? c : nb, hi = up ? nb : c;
     const long long fi = face_of_side(d, i, j, k, s);
-    const double t = g.th[a][fi];
-    const int col_lo = (g.flags[lo] & F_LIQ) ? 1 : 0, col_hi = (g.flags[hi] & F_LIQ) ? 1 : 0;
-    const int kf = (t > 0.5) ? col_lo : ((t < 0.5) ? col_hi : 1);
-    long long hold = (t <= 0.5) ? lo : hi;
-    if (!(g.flags[hold] & F_IF)) hold = (hold == lo) ? hi : lo;
-    const double jmp = g.mdot[hold] * g.jump * g.nF[a * d.N + hold];
-    if (kf == 1)
-      g.uv[a][fi] = g.ul[a][fi] + jmp;
-    else
-      g.ul[a][fi] = g.uv[a][fi] - jmp;
+    cut_face_ghost(d, g.flags, g.nF, g.mdot, g.jump, a, lo, hi, g.th[a][fi], fi, g.ul[a], g.uv[a]);
   }
 }
 

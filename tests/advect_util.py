@@ -64,14 +64,17 @@ def oracle_time_loop(case, t_end, t0=STEFAN_T0, on_step=None, energy_advection=F
       the interfacial velocity from u^n and the band-extended mdot^n moves
       the markers; cells that change phase take the other phase's value
       carried across by Eq. extrapolation; the diffusion step on the new
-      geometry; mdot and its band extension; the projection.
+      geometry; mdot and its band extension; the ghost velocities on the
+      band faces from the extended mdot (Eq. ghost_velocity); the
+      projection.
     The first mdot and velocities come from the initial T."""
     dt = case.dt
     geo = geometry.build(case)
     T = case.T0.ravel().copy()
     mdot, _ = flux.mass_flux(case, geo, T)
     mb = extend.extend(case, geo, mdot, extend.IFACE_TO_BAND, EXT_ITERS)
-    pr = project.project(case, geo, mdot, case.u_l, case.u_v, solve.direct)
+    ul, uv = project.ghost_velocities_band(case, geo, mb, case.u_l, case.u_v)
+    pr = project.project(case, geo, mdot, ul, uv, solve.direct)
     ul, uv = pr["u_l"], pr["u_v"]
     nsteps = int(round((t_end - t0) / dt))
     t = t0
@@ -92,6 +95,7 @@ def oracle_time_loop(case, t_end, t0=STEFAN_T0, on_step=None, energy_advection=F
         T = solve.direct(A, b, heat.operator(case, geo))
         mdot, _ = flux.mass_flux(case, geo, T)
         mb = extend.extend(case, geo, mdot, extend.IFACE_TO_BAND, EXT_ITERS)
+        ul, uv = project.ghost_velocities_band(case, geo, mb, ul, uv)
         pr = project.project(case, geo, mdot, ul, uv, solve.direct)
         ul, uv = pr["u_l"], pr["u_v"]
         t += dt

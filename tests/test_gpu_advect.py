@@ -339,6 +339,7 @@ def test_stefan_time_loop_parity(nx, steps):
     ctx.mass_flux(T, mdot)
     mb = mdot.clone()
     ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, EXT_ITERS)
+    ctx.ghost_band(ul, uv, mb)
     ctx.project(ul, uv, mdot, p)
     worst = 0.0
     for s in range(steps):
@@ -357,6 +358,7 @@ def test_stefan_time_loop_parity(nx, steps):
         ctx.mass_flux(T, mdot)
         mb = mdot.clone()
         ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, EXT_ITERS)
+        ctx.ghost_band(ul, uv, mb)
         st = ctx.project(ul, uv, mdot, p)
         assert st["status"] == 0
         torch.cuda.synchronize()
@@ -405,6 +407,7 @@ def test_translating_bubble_loop_with_energy_advection():
     ctx.mass_flux(T, mdot)
     mb = mdot.clone()
     ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, EXT_ITERS)
+    ctx.ghost_band(ul, uv, mb)
     ctx.project(ul, uv, mdot, p)
     worst_T = 0.0
     for s in range(steps):
@@ -427,6 +430,7 @@ def test_translating_bubble_loop_with_energy_advection():
         ctx.mass_flux(T, mdot)
         mb = mdot.clone()
         ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, EXT_ITERS)
+        ctx.ghost_band(ul, uv, mb)
         assert ctx.project(ul, uv, mdot, p)["status"] == 0
         torch.cuda.synchronize()
         compare_markers([m.cpu().numpy() for m in mk], ref[s][0], 1e-8)
