@@ -972,11 +972,13 @@ ebit_status ebit_ghost_band(ebit_ctx* c, double* const u_l[3], double* const u_v
   if (!u_l || !u_v || !mdot_band) return fail(c, EBIT_EINVAL, "NULL argument");
   for (int a = 0; a < c->fd.dim; ++a)
     if (!u_l[a] || !u_v[a]) return fail(c, EBIT_EINVAL, "NULL velocity array");
-  // scratch as in ebit_extend: the band bytes in the FP32 iterate, the
-  // dilation's counter in the reduction partials
+  // scratch as in ebit_extend: the band bytes in the FP32 iterate, the band
+  // normals in the direction and product vectors, the dilation's counter in
+  // the reduction partials
   const double jump = 1.0 / c->props.rho_l - 1.0 / c->props.rho_v;
+  double* nb[3] = {c->B.p[0], c->B.p[1], c->B.q};
   HIPCK(c,
-        ebit_launch_ghost_band(&c->fd, jump, c->flags, c->th, c->nF, mdot_band, u_l, u_v, (uint8_t*)c->B.z32,
+        ebit_launch_ghost_band(&c->fd, jump, c->flags, c->th, c->nF, mdot_band, u_l, u_v, (uint8_t*)c->B.z32, nb,
                                (int*)c->B.partial, c->st),
         "band ghost velocities");
   return EBIT_OK;

@@ -59,22 +59,96 @@ __device__ inline bool ext_candidate(int mode, uint8_t fl) {
 
 // OR of the per-cell bit over the three cells c - e_AX, c, c + e_AX; the
 // first pass takes the interface bit of the flags (and clears the list
-// counter)
-__global__ void k_ext_dilate(Dims d, int ax, const uint8_t* __restrict__ flags, const uint8_t* __restrict__ in,
-                             uint8_t* __restrict__ out, int* counter) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= d.N) return;
+// counter).  Block b takes EXT_BLOCK cells of one x row (rows of more cells
+// take several blocks): the cell index comes from a row number and an
+// offset, with no per-thread division.
+__global__ __launch_bounds__(EXT_BLOCK) void k_ext_dilate(Dims d, int ax, const uint8_t* __restrict__ flags,
+                                                          const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                          int* counter) {
+  const unsigned n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
+  const unsigned per_row = (n0 + EXT_BLOCK - 1) / EXT_BLOCK;
+  const unsigned row = blockIdx.x / per_row;
+  const unsigned i = (blockIdx.x - row * per_row) * EXT_BLOCK + threadIdx.x;
+  if (i >= n0) return;
+  const unsigned c = row * n0 + i;
   if (!in && c == 0) *counter = 0;
-  int i, j, k;
-  cell_ijk(d, c, i, j, k);
-  uint8_t v = 0;
-#pragma unroll
-  for (int s = -1; s <= 1; ++s) {
-    long long m = c;
-    if (s != 0 && !nbr_cell(d, i, j, k, ax == 0 ? s : 0, ax == 1 ? s : 0, ax == 2 ? s : 0, m)) continue;
-    v |= in ? in[m] : (uint8_t)((flags[m] >> 7) & 1);
-  }
+  const unsigned j = row % n1, k = row / n1;
+  const unsigned ia = ax == 0 ? i : (ax == 1 ? j : k);
+  const unsigned na = (unsigned)d.n[ax];
+  const unsigned st = ax == 0 ? 1u : (ax == 1 ? n0 : n0 * n1);
+  const bool per = d.per[ax] != 0;
+  // the two neighbours along AX (the cell itself where there is none)
+  const unsigned lo = ia > 0 ? c - st : (per ? c + (na - 1) * st : c);
+  const unsigned hi = ia + 1 < na ? c + st : (per ? c - (na - 1) * st : c);
+  uint8_t v;
+  if (in)
+    v = in[lo] | in[c] | in[hi];
+  else
+    v = (uint8_t)(((flags[lo] | flags[c] | flags[hi]) >> 7) & 1);
   out[c] = v;
+}
+
+// The same pass four cells at a time, for rows of a multiple of 4 cells (so
+// every row starts on a 4-byte boundary): thread t takes the 32-bit word of
+// cells 4t .. 4t+3 (byte b of the word is cell 4t+b).  Along x the word is
+// ORed with itself shifted by one byte either way and with the bytes of the
+// cells just outside it; along y or z with the words of the rows either side.
+__global__ __launch_bounds__(EXT_BLOCK) void k_ext_dilate4(Dims d, int ax, const uint8_t* __restrict__ flags,
+                                                           const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                           int* counter) {
+  const unsigned t = blockIdx.x * EXT_BLOCK + threadIdx.x;
+  const unsigned N = (unsigned)d.N;
+  if (t >= N / 4) return;
+  const unsigned c = 4 * t;
+  if (!in && c == 0) *counter = 0;
+  const unsigned n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
+  const unsigned row = c / n0, i = c - row * n0;
+  const uint8_t* src = in ? in : flags;
+  // the interface bit of each byte on the first pass, the byte itself after
+  auto bits = [&](unsigned w) { return in ? w : (w >> 7) & 0x01010101u; };
+  const unsigned w = bits(*reinterpret_cast<const unsigned*>(src + c));
+  unsigned v;
+  if (ax == 0) {
+    const bool per = d.per[0] != 0;
+    unsigned left = 0, right = 0;
+    if (i > 0)
+      left = src[c - 1];
+    else if (per)
+      left = src[c + n0 - 1];
+    if (i + 4 < n0)
+      right = src[c + 4];
+    else if (per)
+      right = src[c + 4 - n0];
+    left = bits(left) & 0xffu;
+    right = bits(right) & 0xffu;
+    v = w | (w << 8) | (w >> 8) | left | (right << 24);
+  } else {
+    const unsigned j = row % n1, k = row / n1;
+    const unsigned ia = ax == 1 ? j : k;
+    const unsigned na = (unsigned)d.n[ax];
+    const unsigned st = ax == 1 ? n0 : n0 * n1;
+    const bool per = d.per[ax] != 0;
+    const unsigned lo = ia > 0 ? c - st : (per ? c + (na - 1) * st : c);
+    const unsigned hi = ia + 1 < na ? c + st : (per ? c - (na - 1) * st : c);
+    v = w | bits(*reinterpret_cast<const unsigned*>(src + lo)) | bits(*reinterpret_cast<const unsigned*>(src + hi));
+  }
+  *reinterpret_cast<unsigned*>(out + c) = v;
+}
+
+// blocks of k_ext_dilate (whole rows of EXT_BLOCK-cell chunks) or, for rows
+// of a multiple of 4 cells, of k_ext_dilate4
+inline bool dilate_by_words(const Dims* d) { return d->n[0] % 4 == 0; }
+inline unsigned dilate_blocks(const Dims* d) {
+  if (dilate_by_words(d)) return (unsigned)((d->N / 4 + EXT_BLOCK - 1) / EXT_BLOCK);
+  const unsigned per_row = ((unsigned)d->n[0] + EXT_BLOCK - 1) / EXT_BLOCK;
+  return per_row * (unsigned)d->n[1] * (unsigned)d->n[2];
+}
+inline void launch_dilate(const Dims* d, int ax, const uint8_t* flags, const uint8_t* in, uint8_t* out, int* counter,
+                          hipStream_t st) {
+  if (dilate_by_words(d))
+    hipLaunchKernelGGL(k_ext_dilate4, dim3(dilate_blocks(d)), dim3(EXT_BLOCK), 0, st, *d, ax, flags, in, out, counter);
+  else
+    hipLaunchKernelGGL(k_ext_dilate, dim3(dilate_blocks(d)), dim3(EXT_BLOCK), 0, st, *d, ax, flags, in, out, counter);
 }
 
 struct ExtArgs {
@@ -197,20 +271,6 @@ __global__ void k_ext_copy(const unsigned long long* __restrict__ list, const in
   }
 }
 
-// The unit band normal of band cell (i, j, k) (zero where the sum of its
-// block's facet normals vanishes).
-__device__ inline void unit_band_normal(const Dims& d, const uint8_t* flags, const double* nF, int i, int j, int k,
-                                        double n[3]) {
-  double s[3];
-  if (!band_normal_sum(d, flags, nF, i, j, k, s)) {
-    n[0] = n[1] = n[2] = 0.0;
-    return;
-  }
-  const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-#pragma unroll
-  for (int r = 0; r < 3; ++r) n[r] = s[r] / L;
-}
-
 struct GhostBandArgs {
   Dims d;
   double jump;  // [1/rho] = 1/rho_l - 1/rho_v
@@ -219,9 +279,25 @@ struct GhostBandArgs {
   const double* th[3];
   const double* nF;
   const double* mdot;  // the mass flux carried to the band
+  double* nb[3];       // the unit band normal of every band cell (scratch)
   double* ul[3];
   double* uv[3];
 };
+
+// The unit band normal of every band cell (zero where the sum of its
+// block's facet normals vanishes), for k_ghost_band to read for both cells
+// of a face.
+__global__ __launch_bounds__(EXT_BLOCK) void k_ghost_band_normal(GhostBandArgs g) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const Dims& d = g.d;
+  if (c >= d.N || !g.band[c]) return;
+  int i, j, k;
+  cell_ijk(d, c, i, j, k);
+  double s[3];
+  const bool on = band_normal_sum(d, g.flags, g.nF, i, j, k, s);
+  const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+  for (int a = 0; a < d.dim; ++a) g.nb[a][c] = on ? s[a] / L : 0.0;
+}
 
 // Eq. ghost_velocity on the band faces.  Each band cell handles its + faces
 // and, on the first layer, face 0 (the periodic copy of face n), as the
@@ -235,8 +311,6 @@ __global__ __launch_bounds__(EXT_BLOCK) void k_ghost_band(GhostBandArgs g) {
   int i, j, k;
   cell_ijk(d, c, i, j, k);
   const uint8_t f = g.flags[c];
-  double nc[3];
-  bool have_nc = false;
   for (int s = 0; s < 2 * d.dim; ++s) {
     const int a = s >> 1, up = s & 1;
     const int ia = (a == 0) ? i : (a == 1) ? j : k;
@@ -251,16 +325,8 @@ __global__ __launch_bounds__(EXT_BLOCK) void k_ghost_band(GhostBandArgs g) {
       continue;
     }
     if (!g.band[m]) continue;
-    if (!have_nc) {
-      unit_band_normal(d, g.flags, g.nF, i, j, k, nc);
-      have_nc = true;
-    }
-    int mi, mj, mk;
-    cell_ijk(d, m, mi, mj, mk);
-    double nm[3];
-    unit_band_normal(d, g.flags, g.nF, mi, mj, mk, nm);
     const double mf = 0.5 * (g.mdot[c] + g.mdot[m]);
-    const double nf = 0.5 * (nc[a] + nm[a]);
+    const double nf = 0.5 * (g.nb[a][c] + g.nb[a][m]);
     const double jmp = mf * g.jump * nf;
     if (f & F_LIQ)
       g.uv[a][fi] = g.ul[a][fi] + jmp;
@@ -285,7 +351,7 @@ extern "C" hipError_t ebit_launch_extend(const Dims* d, int mode, int iters, con
   const uint8_t* in = nullptr;
   uint8_t* out = A;
   for (int ax = 0; ax < d->dim; ++ax) {
-    hipLaunchKernelGGL(k_ext_dilate, dim3(nb), dim3(EXT_BLOCK), 0, st, *d, ax, flags, in, out, counter);
+    launch_dilate(d, ax, flags, in, out, counter, st);
     in = out;
     out = (out == A) ? B : A;
   }
@@ -326,15 +392,15 @@ extern "C" hipError_t ebit_launch_extend(const Dims* d, int mode, int iters, con
 
 extern "C" hipError_t ebit_launch_ghost_band(const Dims* d, double jump, const uint8_t* flags,
                                              const double* const th[3], const double* nF, const double* mdot,
-                                             double* const ul[3], double* const uv[3], uint8_t* bytes, int* counter,
-                                             hipStream_t st) {
-  const unsigned nb = (unsigned)((d->N + EXT_BLOCK - 1) / EXT_BLOCK);
+                                             double* const ul[3], double* const uv[3], uint8_t* bytes,
+                                             double* const nb[3], int* counter, hipStream_t st) {
+  const unsigned nblk = (unsigned)((d->N + EXT_BLOCK - 1) / EXT_BLOCK);
   uint8_t* A = bytes;
   uint8_t* B = bytes + d->N;
   const uint8_t* in = nullptr;
   uint8_t* out = A;
   for (int ax = 0; ax < d->dim; ++ax) {
-    hipLaunchKernelGGL(k_ext_dilate, dim3(nb), dim3(EXT_BLOCK), 0, st, *d, ax, flags, in, out, counter);
+    launch_dilate(d, ax, flags, in, out, counter, st);
     in = out;
     out = (out == A) ? B : A;
   }
@@ -347,9 +413,11 @@ extern "C" hipError_t ebit_launch_ghost_band(const Dims* d, double jump, const u
   g.mdot = mdot;
   for (int a = 0; a < 3; ++a) {
     g.th[a] = a < d->dim ? th[a] : nullptr;
+    g.nb[a] = a < d->dim ? nb[a] : nullptr;
     g.ul[a] = a < d->dim ? ul[a] : nullptr;
     g.uv[a] = a < d->dim ? uv[a] : nullptr;
   }
-  hipLaunchKernelGGL(k_ghost_band, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_ghost_band_normal, dim3(nblk), dim3(EXT_BLOCK), 0, st, g);
+  hipLaunchKernelGGL(k_ghost_band, dim3(nblk), dim3(EXT_BLOCK), 0, st, g);
   return hipGetLastError();
 }

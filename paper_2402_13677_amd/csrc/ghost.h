@@ -40,8 +40,9 @@ __device__ inline void cut_face_ghost(const Dims& d, const uint8_t* flags, const
 // cells), from a mass flux already carried to the band: cut faces as in the
 // projection; an uncut face belongs to the common phase of its cells and
 // takes the means of the two cells' mass flux and unit band normals.
-// bytes: 2 N bytes of scratch; counter: one int of scratch.
+// bytes: 2 N bytes of scratch; nb: dim arrays of N doubles of scratch (the
+// band cells' unit normals); counter: one int of scratch.
 extern "C" hipError_t ebit_launch_ghost_band(const ebit::Dims* d, double jump, const uint8_t* flags,
                                              const double* const th[3], const double* nF, const double* mdot,
-                                             double* const ul[3], double* const uv[3], uint8_t* bytes, int* counter,
-                                             hipStream_t st);
+                                             double* const ul[3], double* const uv[3], uint8_t* bytes,
+                                             double* const nb[3], int* counter, hipStream_t st);
