@@ -32,11 +32,13 @@ approach for phase change: the EBIT method") defines on a uniform grid:
   energy.py    the advection step of the energy equation: explicit Euler
                with third-order WENO derivatives, per phase (Eq.
                energy_advection)
+  volume.py    liquid volume fraction of each cell from the EBIT segments
+               (2D, Sec. 2.2 and Sec. 3.1)
   closed.py    closed forms used as pins (Stefan problem, Sec. 3.1)
 
 Parity unpinned: the 3D facet rule beyond planar exactness (the paper's EBIT
 is 2D only), saddle cells, and the first-order fallback of the mass-flux
 stencil.  Every other function is pinned by tests under tests/.
 """
-from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid, mg, advect, energy  # noqa: F401
+from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid, mg, advect, energy, volume  # noqa: F401
 from .geometry import GeometryError  # noqa: F401
