@@ -716,6 +716,18 @@ def marker_motion_bench(names=("bubble2d_256", "bubble2d_4096"), reps=20):
             ev[1].synchronize()
             t_mv.append(ev[0].elapsed_time(ev[1]))
         nmark = sum(int((~torch.isnan(m)).sum()) for m in dc.markers)
+        frac = torch.empty(N, dtype=torch.float64, device="cuda")
+        t_vf = []
+        for r in range(reps + 2):
+            ev[0].record()
+            ctx.volume_fraction(dc.markers, dc.vcol, frac)
+            ev[1].record()
+            ev[1].synchronize()
+            t_vf.append(ev[0].elapsed_time(ev[1]))
+        vf = statistics.median(t_vf[2:])
+        # per cell: its two own edges' markers (8 B each), its vertex byte,
+        # the fraction written (8 B)
+        b_vf = 25.0 * N
         iv = statistics.median(t_iv[2:])
         mv = statistics.median(t_mv[2:])
         b_iv = iface_velocity_bytes_per_cell(2) * N
@@ -728,7 +740,13 @@ def marker_motion_bench(names=("bubble2d_256", "bubble2d_4096"), reps=20):
                                         "achieved_GBps": b_mv / (mv * 1e-3) / 1e9,
                                         "frac": b_mv / (mv * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                         "launches": 10, "note": "whole call: ten launches and the status "
-                                        "read-back; the scan of the marker arrays is the only grid-sized part"}}
+                                        "read-back; the scan of the marker arrays is the only grid-sized part"},
+                     "volume_fraction": {"us": vf * 1e3, "algorithmic_bytes": b_vf,
+                                         "achieved_GBps": b_vf / (vf * 1e-3) / 1e9,
+                                         "frac": b_vf / (vf * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                         "liquid_area": float(frac.sum()) * case.h ** 2,
+                                         "note": "whole call: the error-word clear, the kernel and the status "
+                                         "read-back"}}
         ctx.close()
     return out
 
@@ -752,7 +770,10 @@ def marker_motion_cpu_baseline():
         mk, vc = oracle.advect.advect_pass(case, mk, vc, ug, dt, a)
     oracle.advect.cell_colours(case, mk, vc)
     t2 = time.perf_counter()
-    return {"interface_velocity_ms": (t1 - t0) * 1e3, "advect_markers_ms": (t2 - t1) * 1e3, "cores": 1,
+    oracle.volume.volume_fraction(case)
+    t3 = time.perf_counter()
+    return {"interface_velocity_ms": (t1 - t0) * 1e3, "advect_markers_ms": (t2 - t1) * 1e3,
+            "volume_fraction_ms": (t3 - t2) * 1e3, "cores": 1,
             "kind": "oracle", "sample": "one call each on bubble2d_256 (mdot = 1 in the band)"}
 
 

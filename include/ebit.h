@@ -19,6 +19,9 @@
  *                      geometric multigrid, and the face-velocity update
  *   ebit_ghost_band    the ghost velocities of Eq. ghost_velocity on every
  *                      narrow-band face, from the band-extended mass flux
+ *   ebit_volume_fraction
+ *                      the liquid volume fraction of every cell from the
+ *                      EBIT segments (2D)
  *   ebit_interface_velocity, ebit_advect_markers
  *                      the interfacial velocity (Eq. jump_interfacial_vel)
  *                      and the EBIT marker motion of one time step (Sec. 2.1)
@@ -260,6 +263,22 @@ ebit_status ebit_extend(ebit_ctx* ctx, double* q, int mode, int iters);
  * ebit_build_coeffs.  ebit_project sets the cut faces again, to the same
  * values when given the same mass flux. */
 ebit_status ebit_ghost_band(ebit_ctx* ctx, double* const u_l[3], double* const u_v[3], const double* mdot_band);
+
+/* Secs. 2.2 and 3.1, 2D: the liquid volume fraction of every cell (the
+ * integral of H over the cell divided by h^2) from the piecewise-linear EBIT
+ * reconstruction: in a cell with two markers, the area of the polygon of its
+ * liquid corners and its two markers (the cell on the liquid side of the
+ * segment joining them); a cell with no marker takes its corners' colour (1
+ * or 0).  marker[0], marker[1]: x- and y-edge arrays of s or NaN;
+ * vertex_colour: uint8 colours (the layouts of ebit_build_coeffs);
+ * frac: output, cells.  All device, caller-owned.  Needs no
+ * ebit_build_coeffs.  Synchronises the context stream to read the status.
+ * EBIT_EINVAL for a 3D context or a NULL argument; EBIT_EGEOM if a cell
+ * holds other than 0 or 2 markers or its corner colours do not change
+ * exactly at its markers (that cell's fraction is NaN, the others are
+ * written). */
+ebit_status ebit_volume_fraction(ebit_ctx* ctx, const double* const marker[3], const uint8_t* vertex_colour,
+                                 double* frac);
 
 /* Sec. 2.3, the one-fluid projection the paper sets against the ghost-fluid
  * one (Eqs. Poisson_equation and pc_source): one face velocity field u (a <

@@ -702,6 +702,74 @@ __global__ void k_adv_clear(int* err, int* count) {
 
 unsigned blocks_for(long long n) { return (unsigned)((n + ADV_BLOCK - 1) / ADV_BLOCK); }
 
+// Liquid volume fraction of every cell (2D; Secs. 2.2 and 3.1: the integral
+// of H over the cell, from the piecewise-linear EBIT reconstruction).  The
+// liquid part of a two-marker cell is the polygon of its liquid corners and
+// its two markers, taken counter-clockwise round the cell from (0, 0) in
+// cell units; its shoelace area is summed term by term in that order, from
+// 0.0, and halved.  A cell with no marker takes its corners' colour.  A
+// cell with other than 0 or 2 markers, or whose corner colours do not change
+// exactly at its markers, sets the geometry error bit and gets NaN.
+__global__ __launch_bounds__(ADV_BLOCK) void k_volume_fraction(int nx, int ny, const double* __restrict__ mx,
+                                                               const double* __restrict__ my,
+                                                               const uint8_t* __restrict__ vcol,
+                                                               double* __restrict__ frac, int* err) {
+  // fewer than 2^31 cells and edges: 32-bit offsets
+  const unsigned t = blockIdx.x * ADV_BLOCK + threadIdx.x;
+  const unsigned N = (unsigned)nx * (unsigned)ny;
+  if (t >= N) return;
+  const unsigned j = t / (unsigned)nx, i = t - j * (unsigned)nx;
+  const unsigned nx1 = (unsigned)nx + 1;
+  // corners (0,0), (1,0), (1,1), (0,1) and the edge after each: bottom,
+  // right, top, left (each marker s measured from the edge's lower vertex)
+  const int col[4] = {vcol[j * nx1 + i], vcol[j * nx1 + i + 1], vcol[(j + 1) * nx1 + i + 1], vcol[(j + 1) * nx1 + i]};
+  const double s[4] = {mx[j * (unsigned)nx + i], my[j * nx1 + i + 1], mx[(j + 1) * (unsigned)nx + i], my[j * nx1 + i]};
+  bool bad = false;
+  int nm = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bool has = !isnan(s[e]);
+    nm += has ? 1 : 0;
+    if ((col[e] != col[(e + 1) & 3]) != has) bad = true;
+  }
+  double f;
+  if (bad || (nm != 0 && nm != 2)) {
+    atomicOr(err, ADV_ERR_GEOM);
+    f = NAN;
+  } else if (nm == 0) {
+    f = col[0] ? 1.0 : 0.0;
+  } else {
+    const double cx[4] = {0.0, 1.0, 1.0, 0.0}, cy[4] = {0.0, 0.0, 1.0, 1.0};
+    const double px[4] = {s[0], 1.0, s[2], 0.0}, py[4] = {0.0, s[1], 1.0, s[3]};
+    double fx = 0.0, fy = 0.0, lx = 0.0, ly = 0.0, acc = 0.0;
+    bool first = true;
+    // append a vertex: the term of the previous one and this one
+    auto add = [&](double x, double y) {
+      if (first) {
+        fx = x;
+        fy = y;
+        first = false;
+      } else {
+        acc += lx * y - x * ly;
+      }
+      lx = x;
+      ly = y;
+    };
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (col[e]) add(cx[e], cy[e]);
+      if (!isnan(s[e])) add(px[e], py[e]);
+    }
+    acc += lx * fy - fx * ly;
+    f = 0.5 * acc;
+  }
+  frac[t] = f;
+}
+
+__global__ void k_vf_clear(int* err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *err = 0;
+}
+
 }  // namespace
 }  // namespace ebit
 
@@ -773,5 +841,14 @@ extern "C" hipError_t ebit_launch_advect(const Dims* d, double h, double dt, con
     hipLaunchKernelGGL(k_adv_reset, dim3(lb), dim3(ADV_BLOCK), 0, st, A, a);
   }
   hipLaunchKernelGGL(k_adv_colours, dim3(lb), dim3(ADV_BLOCK), 0, st, A);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t ebit_launch_volume_fraction(const Dims* d, const double* const mk[3], const uint8_t* vcol,
+                                                 double* frac, int* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_vf_clear, dim3(1), dim3(64), 0, st, err);
+  if (d->N > 0)
+    hipLaunchKernelGGL(k_volume_fraction, dim3(blocks_for(d->N)), dim3(ADV_BLOCK), 0, st, d->n[0], d->n[1], mk[0],
+                       mk[1], vcol, frac, err);
   return hipGetLastError();
 }

@@ -1046,6 +1046,23 @@ ebit_status ebit_advect_markers(ebit_ctx* c, const double* const u_gamma[3], dou
   return EBIT_OK;
 }
 
+ebit_status ebit_volume_fraction(ebit_ctx* c, const double* const marker[3], const uint8_t* vertex_colour,
+                                 double* frac) {
+  if (!c) return EBIT_EINVAL;
+  if (c->herr != hipSuccess) return EBIT_EHIP;
+  if (c->fd.dim != 2) return fail(c, EBIT_EINVAL, "the volume fraction is two-dimensional");
+  if ((long long)c->fd.n[0] * (c->fd.n[1] + 1) + (long long)(c->fd.n[0] + 1) * c->fd.n[1] >= (1LL << 31))
+    return fail(c, EBIT_EINVAL, "the volume fraction needs fewer than 2^31 edges");
+  if (!marker || !marker[0] || !marker[1] || !vertex_colour || !frac) return fail(c, EBIT_EINVAL, "NULL argument");
+  HIPCK(c, ebit_launch_volume_fraction(&c->fd, marker, vertex_colour, frac, c->adv_err, c->st), "volume fraction");
+  int herr = 0;
+  HIPCK(c, hipMemcpyAsync(&herr, c->adv_err, sizeof(int), hipMemcpyDeviceToHost, c->st), "volume fraction status");
+  HIPCK(c, hipStreamSynchronize(c->st), "volume fraction sync");
+  if (herr) return fail(c, EBIT_EGEOM, "a cell holds other than 0 or 2 markers, or its corner colours do not "
+                                       "change exactly at its markers");
+  return EBIT_OK;
+}
+
 ebit_status ebit_heat_rhs(ebit_ctx* c, const double* Ts, double* b) {
   ebit_status s = check_ready(c);
   if (s != EBIT_OK) return s;

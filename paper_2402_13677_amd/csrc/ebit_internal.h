@@ -596,6 +596,10 @@ size_t ebit_advect_scratch_bytes(const ebit::Dims* d);
 hipError_t ebit_launch_advect(const ebit::Dims* d, double h, double dt, const double* const ug[3],
                               double* const mk[3], uint8_t* vcol, uint8_t* ccol, void* scratch, int init,
                               int* err, hipStream_t st);
+// 2D liquid volume fraction of every cell from the markers and vertex
+// colours; err: one int, cleared here, geometry bit set for a bad cell.
+hipError_t ebit_launch_volume_fraction(const ebit::Dims* d, const double* const mk[3], const uint8_t* vcol,
+                                       double* frac, int* err, hipStream_t st);
 // Hierarchy builds: host tables of the one-work-group part (2 systems,
 // ebit_build_table_bytes() bytes) are filled once and uploaded by the
 // caller; ls is the first level that part builds.

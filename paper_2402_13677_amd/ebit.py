@@ -79,6 +79,7 @@ def load():
         "ebit_heat_rhs": (i, [vp, vp, vp]),
         "ebit_extend": (i, [vp, vp, i, i]),
         "ebit_ghost_band": (i, [vp, _P3, _P3, vp]),
+        "ebit_volume_fraction": (i, [vp, _P3, vp, vp]),
         "ebit_project_one_fluid": (i, [vp, _P3, vp, vp, i, ctypes.POINTER(Stats)]),
         "ebit_project_rhs": (i, [vp, _P3, _P3, vp, vp]),
         "ebit_levels": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
@@ -126,7 +127,7 @@ EXPORTED = ["ebit_default_opts", "ebit_status_string", "ebit_workspace_bytes", "
             "ebit_batch_mass_flux", "ebit_batch_project", "ebit_autotune", "ebit_batch_autotune",
             "ebit_cut_fractions_noalloc", "ebit_interface_velocity", "ebit_advect_markers", "ebit_advect_energy",
             "ebit_tune_lookup", "ebit_tune_store", "ebit_autotune_cached", "ebit_batch_autotune_cached",
-            "ebit_ghost_band"]
+            "ebit_ghost_band", "ebit_volume_fraction"]
 NOALLOC_MAX_CELLS = 1 << 18
 KC_FINE_SMOOTH, KC_FINE_RESTRICT, KC_COARSE, KC_OUTER_APPLY, KC_OUTER_UPDATE, KC_TAIL = range(6)
 EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ, EXT_IFACE_TO_BAND = range(3)
@@ -283,6 +284,14 @@ class Context:
         in place) into the narrow band; mode EXT_LIQ_TO_VAP, EXT_VAP_TO_LIQ
         or EXT_IFACE_TO_BAND."""
         self._check(self.lib.ebit_extend(self.h, _ptr(q, torch.float64), int(mode), int(iters)), "ebit_extend")
+
+    def volume_fraction(self, markers, vcol, frac, check=True):
+        """Liquid volume fraction of every cell (2D) into frac (cells) from
+        the markers and vertex colours; returns the status."""
+        st = self.lib.ebit_volume_fraction(self.h, _p3(markers), _ptr(vcol, torch.uint8), _ptr(frac, torch.float64))
+        if check:
+            self._check(st, "ebit_volume_fraction")
+        return st
 
     def ghost_band(self, u_l, u_v, mdot_band, check=True):
         """Eq. ghost_velocity on every narrow-band face (u_l, u_v: dim face
