@@ -53,6 +53,42 @@ __device__ inline long long face_index(const Dims& d, int a, int i, int j, int k
   return (long long)i + n0 * ((long long)j + n1 * k);
 }
 
+// Whether the 3^d block of (i, j, k) holds an interface cell: every flag of
+// the block is loaded at once with 32-bit offsets (walls stop, periodic axes
+// wrap), so the cells far from the interface (nearly all) need no ordered
+// sum of normals.
+template <int DIM>
+__device__ inline bool block_has_iface(const Dims& d, const uint8_t* __restrict__ flags, int i, int j, int k) {
+  const int p[3] = {i, j, k};
+  unsigned idx[3][3];
+  bool ok[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      int q = p[a] + o - 1;
+      bool v = a < DIM || o == 1;
+      if (a < DIM && (q < 0 || q >= d.n[a])) {
+        v = d.per[a] != 0;
+        q = q < 0 ? q + d.n[a] : q - d.n[a];
+      }
+      ok[a][o] = v;
+      idx[a][o] = v ? (unsigned)q : 0u;
+    }
+  const unsigned n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
+  uint8_t acc = 0;
+#pragma unroll
+  for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 3; ++ox) {
+        if (DIM == 2 && oz != 1) continue;
+        if (ok[0][ox] && ok[1][oy] && ok[2][oz]) acc |= flags[idx[0][ox] + n0 * (idx[1][oy] + n1 * idx[2][oz])];
+      }
+  return (acc >> 7) & 1;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(ADV_BLOCK) void k_iface_velocity(Dims d, const uint8_t* __restrict__ flags,
                                                               const double* __restrict__ nF, const double* ul0,
@@ -66,8 +102,8 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_iface_velocity(Dims d, const uint
   int i, j, k;
   cell_ijk(d, c, i, j, k);
   const bool liquid = (flags[c] >> 6) & 1;
-  double s[3];
-  const bool band = band_normal_sum(d, flags, nF, i, j, k, s);
+  double s[3] = {0.0, 0.0, 0.0};
+  const bool band = block_has_iface<DIM>(d, flags, i, j, k) && band_normal_sum(d, flags, nF, i, j, k, s);
   const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
   const double mr = mdot[c] / (liquid ? rho_l : rho_v);
   const double* ul[3] = {ul0, ul1, ul2};
