@@ -15,12 +15,15 @@
 // nothing.
 //
 // Layout and launch: one thread per cell, a block per 16 x 16 tile of an
-// x-y plane, the tiles ordered column by column and bottom to top within a
-// column; each thread reads its colour byte, its phase's 2 faces per axis,
-// the centre and the 4 cells at distance 1 and 2 along each axis (the
-// neighbours come from the L2: an XCD's blocks climb a few columns at a
-// time, so the planes below were just read and the tile rims are shared
-// with the columns on either side).
+// x-y plane.  The tile rows are grouped into eight strips (as many as there
+// are XCDs, each with its own L2); the blocks are ordered strip by strip,
+// within a strip plane by plane from the bottom, and within a plane tile by
+// tile, so the contiguous range of blocks an XCD takes is one strip climbed
+// plane by plane.  Each thread reads its colour byte, its phase's 2 faces
+// per axis, the centre and the 4 cells at distance 1 and 2 along each axis:
+// the x and y neighbours of a tile come from tiles of the same strip and
+// plane, just read into the same L2, and the z neighbours from the planes
+// just below; only the rows next to another strip are fetched twice.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -77,18 +80,19 @@ __device__ inline int wrap_clamp(int v, int n, bool per) {
 template <int DIM>
 __global__ __launch_bounds__(EN_BLOCK) void k_advect_energy(EnergyArgs g) {
   // a context's grid has fewer than 2^31 cells (and fewer than 2^32 faces
-  // per axis): 32-bit offsets throughout.  Block t takes the EN_TX x EN_TY
-  // tile of column t / n2 at height t % n2, so the blocks of one XCD (a
-  // contiguous range of t) walk a few tile columns bottom to top and the
-  // z-neighbours a cell reads were fetched by the blocks just below.
+  // per axis): 32-bit offsets throughout.  Block t: strip s = t / (n2 gx sh),
+  // then the plane and the tile within the strip's sh rows of gx tiles.
   const Dims& d = g.d;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int n2 = d.n[2];
-  const int col = t / n2, kz = t - col * n2;
-  const int gx = (d.n[0] + EN_TX - 1) / EN_TX;
-  const int ty = col / gx, tx = col - ty * gx;
+  const int gx = (d.n[0] + EN_TX - 1) / EN_TX, gy = (d.n[1] + EN_TY - 1) / EN_TY;
+  const int sh = (gy + 7) / 8;
+  const int per_plane = gx * sh, per_strip = per_plane * n2;
+  const int st_i = t / per_strip, r = t - st_i * per_strip;
+  const int kz = r / per_plane, q = r - kz * per_plane;
+  const int ty = st_i * sh + q / gx, tx = q % gx;
   const int ijk[3] = {tx * EN_TX + (int)(threadIdx.x % EN_TX), ty * EN_TY + (int)(threadIdx.x / EN_TX), kz};
-  if (ijk[0] >= d.n[0] || ijk[1] >= d.n[1]) return;
+  if (ty >= gy || ijk[0] >= d.n[0] || ijk[1] >= d.n[1]) return;
   const unsigned n0 = (unsigned)d.n[0], n1 = (unsigned)d.n[1];
   const unsigned c = (unsigned)ijk[0] + n0 * ((unsigned)ijk[1] + n1 * (unsigned)kz);
   const int ph = g.ccol[c] ? 1 : 0;
@@ -147,8 +151,9 @@ extern "C" hipError_t ebit_launch_advect_energy(const Dims* d, double h, const d
     g.u[0][a] = a < d->dim ? u_v[a] : nullptr;
   }
   g.out = out;
-  const long long blocks =
-      (long long)((d->n[0] + EN_TX - 1) / EN_TX) * ((d->n[1] + EN_TY - 1) / EN_TY) * d->n[2];
+  const long long gx = (d->n[0] + EN_TX - 1) / EN_TX, gy = (d->n[1] + EN_TY - 1) / EN_TY;
+  const long long sh = (gy + 7) / 8;
+  const long long blocks = ((gy + sh - 1) / sh) * sh * gx * d->n[2];
   if (blocks == 0) return hipSuccess;
   if (d->dim == 3)
     hipLaunchKernelGGL(k_advect_energy<3>, dim3((unsigned)blocks), dim3(EN_BLOCK), 0, st, g);
