@@ -751,6 +751,117 @@ def marker_motion_bench(names=("bubble2d_256", "bubble2d_4096"), reps=20):
     return out
 
 
+def time_loop_bench(n=256, steps=20, warmup=3, U=0.5):
+    """The whole time step of Sec. 2.5 on the GPU, on the translating vapour
+    disc of ebit_inputs at n^2 (periodic in x, walls in y, a uniform flow U
+    along x, CFL 0.1): per-phase extension of T, the energy advection and
+    the extension of T*, the interfacial velocity and the marker step, the
+    build, the heat solve, the mass flux and its band extension, the band
+    ghost velocities and the projection (u* = u^n: no momentum predictor).
+    Median of the steps timed with events on the library's stream, the torch
+    glue between the calls included."""
+    import torch
+    import ebit_inputs as ei
+    from paper_2402_13677_amd import ebit
+
+    dt = 0.1 / (n * U)
+    case = ei.translating_bubble(n, U, dt)
+    ctx, dc = ebit.context_for(case)
+    N = case.ncells
+    T = dc.T0.reshape(-1).clone()
+    mk, vc, cc = dc.markers, dc.vcol, dc.ccol
+    ul, uv = dc.u_l, dc.u_v
+    mdot = torch.zeros(N, dtype=torch.float64, device="cuda")
+    p = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ug = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(2)]
+    Tstar = torch.empty_like(T)
+    ext = 8
+    ctx.build_coeffs(mk, vc, cc, dt)
+    ctx.mass_flux(T, mdot)
+    mb = mdot.clone()
+    ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, ext)
+    ctx.ghost_band(ul, uv, mb)
+    ctx.project(ul, uv, mdot, p)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms, iters = [], []
+    for s in range(warmup + steps):
+        ev[0].record()
+        Tl = T.clone()
+        ctx.extend(Tl, ebit.EXT_LIQ_TO_VAP, ext)
+        Tv = T.clone()
+        ctx.extend(Tv, ebit.EXT_VAP_TO_LIQ, ext)
+        ctx.advect_energy(Tl, Tv, ul, uv, cc, dt, Tstar)
+        Tl = Tstar.clone()
+        ctx.extend(Tl, ebit.EXT_LIQ_TO_VAP, ext)
+        Tv = Tstar.clone()
+        ctx.extend(Tv, ebit.EXT_VAP_TO_LIQ, ext)
+        ctx.interface_velocity(ul, uv, mb, ug)
+        old = cc.reshape(-1).clone()
+        ctx.advect_markers(ug, mk, vc, cc, dt)
+        new = cc.reshape(-1)
+        Ts = torch.where(new == old, Tstar, torch.where(new == 1, Tl, Tv))
+        ctx.build_coeffs(mk, vc, cc, dt)
+        sh = ctx.heat_solve(Ts, T)
+        ctx.mass_flux(T, mdot)
+        mb = mdot.clone()
+        ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, ext)
+        ctx.ghost_band(ul, uv, mb)
+        sp = ctx.project(ul, uv, mdot, p)
+        ev[1].record()
+        ev[1].synchronize()
+        if s >= warmup:
+            ms.append(ev[0].elapsed_time(ev[1]))
+            iters.append((sh["iters"], sp["iters"]))
+    nmark = sum(int((~torch.isnan(m)).sum()) for m in mk)
+    ctx.close()
+    t = statistics.median(ms)
+    return {"workload": case.name, "cells": N, "steps": steps, "dt": dt, "ms_per_step": t,
+            "cell_steps_per_s": N / (t * 1e-3), "markers_after": nmark,
+            "outer_iters_heat_projection": [statistics.median([a for a, _ in iters]),
+                                            statistics.median([b for _, b in iters])],
+            "extension_steps": ext}
+
+
+def time_loop_cpu_baseline(n=256, U=0.5):
+    """The oracle's time step on the same case (1 thread, SuperLU solves):
+    one step."""
+    import dataclasses
+    import numpy as np
+    import ebit_inputs as ei
+    import oracle
+    from oracle import advect, energy, extend, flux, geometry, heat, project, solve
+    dt = 0.1 / (n * U)
+    case = ei.translating_bubble(n, U, dt)
+    ext = 8
+    geo = geometry.build(case)
+    T = case.T0.ravel().copy()
+    mdot, _ = flux.mass_flux(case, geo, T)
+    mb = extend.extend(case, geo, mdot, extend.IFACE_TO_BAND, ext)
+    ul, uv = project.ghost_velocities_band(case, geo, mb, case.u_l, case.u_v)
+    pr = project.project(case, geo, mdot, ul, uv, solve.direct)
+    ul, uv = pr["u_l"], pr["u_v"]
+    t0 = time.perf_counter()
+    Tl = extend.extend(case, geo, T, extend.LIQ_TO_VAP, ext)
+    Tv = extend.extend(case, geo, T, extend.VAP_TO_LIQ, ext)
+    T = energy.advect_energy(case, Tl, Tv, ul, uv, dt)
+    Tl = extend.extend(case, geo, T, extend.LIQ_TO_VAP, ext)
+    Tv = extend.extend(case, geo, T, extend.VAP_TO_LIQ, ext)
+    mk, vc, cc = advect.advect(case, geo, ul, uv, mb, dt)
+    old, new = case.ccol.ravel(), cc.ravel()
+    Ts = np.where(new == old, T, np.where(new == 1, Tl, Tv))
+    case = dataclasses.replace(case, markers=list(mk), vcol=vc, ccol=cc, T0=Ts.reshape(case.T0.shape))
+    geo = geometry.build(case)
+    A, b = heat.assemble(case, geo, Ts)
+    T = solve.direct(A, b, heat.operator(case, geo))
+    mdot, _ = flux.mass_flux(case, geo, T)
+    mb = extend.extend(case, geo, mdot, extend.IFACE_TO_BAND, ext)
+    ul, uv = project.ghost_velocities_band(case, geo, mb, ul, uv)
+    project.project(case, geo, mdot, ul, uv, solve.direct)
+    el = time.perf_counter() - t0
+    return {"ms_per_step": el * 1e3, "value": case.ncells / el, "unit": "cell-steps/s", "cores": 1,
+            "kind": "oracle", "sample": f"one step on {case.name} (direct solves)"}
+
+
 def marker_motion_cpu_baseline():
     """The oracle's interfacial velocity and marker step on bubble2d_256
     (1 thread): ms per call."""
@@ -923,6 +1034,7 @@ def main():
     ap.add_argument("--no-extension", action="store_true", help="skip the narrow-band extension timing")
     ap.add_argument("--no-one-fluid", action="store_true", help="skip the one-fluid projection timing")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-advection timing")
+    ap.add_argument("--no-time-loop", action="store_true", help="skip the whole-time-step timing (2D)")
     ap.add_argument("--no-marker-motion", action="store_true",
                     help="skip the interfacial-velocity and marker-motion timing")
     ap.add_argument("--marker-motion-only", action="store_true",
@@ -956,7 +1068,8 @@ def main():
         print(json.dumps({"workload": case.name, "extension": extension_bench(case),
                           "one_fluid": one_fluid_bench(case, args.precision, sched),
                           "energy_advection": energy_bench(case),
-                          "marker_motion": marker_motion_bench()}))
+                          "marker_motion": marker_motion_bench(),
+                          "time_loop": time_loop_bench()}))
         return
     rtol = workload_rtol(case)
     tune = parse_schedule(args.schedule) if args.schedule else (not args.no_autotune)
@@ -1030,6 +1143,11 @@ def main():
         extra["marker_motion"] = marker_motion_bench()
         if not args.no_cpu_baseline:
             extra["marker_motion"]["cpu_oracle"] = marker_motion_cpu_baseline()
+    if not args.no_time_loop:
+        log("the whole time step (2D translating bubble)")
+        extra["time_loop"] = time_loop_bench()
+        if not args.no_cpu_baseline:
+            extra["time_loop"]["cpu_oracle"] = time_loop_cpu_baseline()
     if not args.no_cpu_baseline:
         log("first step of each precision for the error against the oracle")
         gsteps = {"mixed": gpu_first_step(case, "mixed", schedule), "fp64": gpu_first_step(case, "fp64", schedule)}

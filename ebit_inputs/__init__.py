@@ -311,6 +311,30 @@ def bubble(dim, n, R, dT, delta, rho_ratio, lam_ratio, sigma_u=0.0, seed=None, d
                 vcol, ccol, T0.astype(np.float64), u_l, u_v)
 
 
+def translating_bubble(n, U, dt, dT=0.2):
+    """A vapour disc (R = 0.203, off the grid's symmetry lines) in a unit box
+    periodic in x with walls in y, carried by a uniform flow U along x in
+    both phases; the liquid holds T_sat + dT (1 + sin 2 pi x) sin^2 pi y,
+    the vapour T_sat, so the flow carries a temperature field with
+    gradients and the interface evaporates where the liquid is warm.  Unit
+    properties but for rho_v = lam_v = 0.5 and h_lg = 100 (the evaporation
+    speed mdot / rho_v stays a fraction of U)."""
+    h = 1.0 / n
+    nn = (n, n, 1)
+    ls = Ball((0.513, 0.507, 0.0), 0.203, 1.0, 2)
+    vcol, ccol, markers = colours_and_markers(2, nn, h, ls)
+    pr = Props(rho_l=1.0, rho_v=0.5, lam_l=1.0, lam_v=0.5, cp_l=1.0, cp_v=1.0, h_lg=100.0, T_sat=0.0)
+    x, y = np.meshgrid((np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h)
+    Tl = dT * (1.0 + np.sin(2 * np.pi * x)) * np.sin(np.pi * y) ** 2
+    T0 = np.where(ccol[0] == 1, Tl, 0.0)[None].astype(np.float64)
+    T_bc = [(PERIODIC, 0.0), (PERIODIC, 0.0), (NEUMANN, 0.0), (NEUMANN, 0.0)]
+    p_bc = [(PERIODIC, 0.0), (PERIODIC, 0.0), (DIRICHLET, 0.0), (DIRICHLET, 0.0)]
+    ux = np.full(face_shape(2, nn, 0), U)
+    uy = np.zeros(face_shape(2, nn, 1))
+    return Case(f"translating_bubble_{n}", 2, nn, h, pr, dt, T_bc, p_bc, markers, vcol, ccol, T0,
+                [ux, uy], [ux.copy(), uy.copy()])
+
+
 def film_3d(n=256, seed=5, rho_ratio=200.0, lam_ratio=0.2, T_wall=1.0, dt=1e-4, name=None):
     """Film-boiling-like layer: vapour below y = H(x, z), heated wall at y = 0.
 

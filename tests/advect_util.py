@@ -135,28 +135,9 @@ def _case_from(n, h, nn, vcol, ccol, markers, periodic, rho):
 
 
 def translating_bubble_case(n, U, dt, dT=0.2):
-    """A vapour disc (R = 0.203, off the grid's symmetry lines) in a unit box
-    periodic in x with walls in y,
-    carried by a uniform flow U along x in both phases; the liquid holds
-    T_sat + dT (1 + sin 2 pi x) sin^2 pi y, the vapour T_sat, so the flow
-    carries a temperature field with gradients and the interface evaporates
-    where the liquid is warm.  Unit properties but for rho_v = lam_v = 0.5
-    and h_lg = 100 (the evaporation speed mdot / rho_v stays a fraction of
-    U)."""
-    h = 1.0 / n
-    nn = (n, n, 1)
-    ls = ei.Ball((0.513, 0.507, 0.0), 0.203, 1.0, 2)
-    vcol, ccol, markers = ei.colours_and_markers(2, nn, h, ls)
-    pr = ei.Props(rho_l=1.0, rho_v=0.5, lam_l=1.0, lam_v=0.5, cp_l=1.0, cp_v=1.0, h_lg=100.0, T_sat=0.0)
-    x, y = np.meshgrid((np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h)
-    Tl = dT * (1.0 + np.sin(2 * np.pi * x)) * np.sin(np.pi * y) ** 2
-    T0 = np.where(ccol[0] == 1, Tl, 0.0)[None].astype(np.float64)
-    T_bc = [(ei.PERIODIC, 0.0), (ei.PERIODIC, 0.0), (ei.NEUMANN, 0.0), (ei.NEUMANN, 0.0)]
-    p_bc = [(ei.PERIODIC, 0.0), (ei.PERIODIC, 0.0), (ei.DIRICHLET, 0.0), (ei.DIRICHLET, 0.0)]
-    ux = np.full(ei.face_shape(2, nn, 0), U)
-    uy = np.zeros(ei.face_shape(2, nn, 1))
-    return ei.Case(f"translating_bubble_{n}", 2, nn, h, pr, dt, T_bc, p_bc, markers, vcol, ccol, T0,
-                   [ux, uy], [ux.copy(), uy.copy()])
+    """The translating vapour disc of ebit_inputs (a uniform flow U along x,
+    periodic in x, walls in y)."""
+    return ei.translating_bubble(n, U, dt, dT)
 
 
 def circle_case(n, centre, R, inside_vapour=True, rho=(1.0, 1.0)):
