@@ -311,6 +311,37 @@ def bubble(dim, n, R, dT, delta, rho_ratio, lam_ratio, sigma_u=0.0, seed=None, d
                 vcol, ccol, T0.astype(np.float64), u_l, u_v)
 
 
+class Slab(LevelSet):
+    """Liquid in |y - yc| < w / 2 (a horizontal slab in 2D)."""
+
+    def __init__(self, yc, w):
+        self.yc, self.w = yc, w
+
+    def phi(self, x, y, z):
+        return 0.5 * self.w - np.abs(y - self.yc)
+
+    def root(self, a, x0, y0, z0, h, start_liquid):
+        lo = (self.yc - 0.5 * self.w - y0) / h
+        hi = (self.yc + 0.5 * self.w - y0) / h
+        return np.where((lo >= 0.0) & (lo <= 1.0), lo, hi)
+
+
+def thin_slab_2d(nx=32, ny=20, yc_cells=9.63, w_cells=1.45, name="slab2d"):
+    """A liquid slab thinner than two cells across a 2D box periodic in x
+    with walls in y (T Neumann, p Dirichlet), h = 1/nx: a single row of
+    liquid centres, the interface cells in the rows either side.  T is zero
+    (the caller sets the liquid row's values)."""
+    dim, n = 2, (nx, ny, 1)
+    h = 1.0 / nx
+    ls = Slab(yc_cells * h, w_cells * h)
+    vcol, ccol, mk = colours_and_markers(dim, n, h, ls)
+    zero = _zero_faces(dim, n)
+    bc_T = [(PERIODIC, 0.0), (PERIODIC, 0.0), (NEUMANN, 0.0), (NEUMANN, 0.0)]
+    bc_p = [(PERIODIC, 0.0), (PERIODIC, 0.0), (DIRICHLET, 0.0), (DIRICHLET, 0.0)]
+    return Case(name, dim, n, h, Props(rho_l=1.0, rho_v=0.05), 1e-4, bc_T, bc_p, mk, vcol, ccol,
+                np.zeros(cell_shape(dim, n)), zero, [z.copy() for z in zero])
+
+
 def translating_bubble(n, U, dt, dT=0.2):
     """A vapour disc (R = 0.203, off the grid's symmetry lines) in a unit box
     periodic in x with walls in y, carried by a uniform flow U along x in

@@ -37,8 +37,9 @@ approach for phase change: the EBIT method") defines on a uniform grid:
   closed.py    closed forms used as pins (Stefan problem, Sec. 3.1)
 
 Parity unpinned: the 3D facet rule beyond planar exactness (the paper's EBIT
-is 2D only), saddle cells, and the first-order fallback of the mass-flux
-stencil.  Every other function is pinned by tests under tests/.
+is 2D only) and saddle cells.  Every other function is pinned by tests under
+tests/ (the first-order fallback of the mass-flux stencil by a thin slab
+worked out by hand).
 """
 from . import geometry, heat, flux, project, solve, closed, pipeline, extend, onefluid, mg, advect, energy, volume  # noqa: F401
 from .geometry import GeometryError  # noqa: F401

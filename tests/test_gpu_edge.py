@@ -173,3 +173,28 @@ def test_theta_min_clamp_small_cut_fractions():
     assert rel(T.cpu().numpy(), ref["T"]) < 1e-12
     assert rel(m.cpu().numpy(), ref["mdot"]) < 1e-11
     ctx.close()
+
+
+def test_mass_flux_first_order_fallback_thin_slab():
+    """A liquid slab thinner than two cells: on its liquid side every
+    interface cell falls back to the first-order difference (the oracle's
+    pinned values); the GPU gives the same mdot (element by element, 1e-12
+    of the largest) and the same fallback count."""
+    say("[gpu] edge mass-flux fallback on a thin slab")
+    ebit = _ebit()
+    case = ei.thin_slab_2d()
+    nx, ny = case.n[0], case.n[1]
+    x = (np.arange(nx) + 0.5) * case.h
+    T = np.zeros((ny, nx))
+    T[9] = 1.0 + 0.3 * np.sin(2 * np.pi * x)
+    geo = oracle.geometry.build(case)
+    ref, fb = oracle.flux.mass_flux(case, geo, T.ravel())
+    assert fb == 2 * nx
+    ctx, dc = ebit.context_for(case)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    m = torch.zeros(case.ncells, dtype=torch.float64, device="cuda")
+    st = ctx.mass_flux(torch.from_numpy(T.ravel()).to("cuda"), m)
+    got = m.cpu().numpy()
+    assert st["fallbacks"] == fb
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    ctx.close()

@@ -46,31 +46,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-class _Slab(ei.LevelSet):
-    """Liquid in |y - yc| < w / 2 (a horizontal slab in 2D)."""
-
-    def __init__(self, yc, w):
-        self.yc, self.w = yc, w
-
-    def phi(self, x, y, z):
-        return 0.5 * self.w - np.abs(y - self.yc)
-
-    def root(self, a, x0, y0, z0, h, start_liquid):
-        lo = (self.yc - 0.5 * self.w - y0) / h
-        hi = (self.yc + 0.5 * self.w - y0) / h
-        return np.where((lo >= 0.0) & (lo <= 1.0), lo, hi)
-
-
 def _slab_case():
-    dim, n = 2, (32, 20, 1)
-    h = 1.0 / 32
-    ls = _Slab(9.63 * h, 1.45 * h)
-    vcol, ccol, mk = ei.colours_and_markers(dim, n, h, ls)
-    zero = [np.zeros(ei.face_shape(dim, n, a)) for a in range(dim)]
-    bc_T = [(2, 0.0), (2, 0.0), (0, 0.0), (0, 0.0)]
-    bc_p = [(2, 0.0), (2, 0.0), (1, 0.0), (1, 0.0)]
-    return ei.Case("slab2d", dim, n, h, ei.Props(rho_l=1.0, rho_v=0.05), 1e-4, bc_T, bc_p, mk, vcol, ccol,
-                   np.zeros(ei.cell_shape(dim, n)), zero, [z.copy() for z in zero])
+    return ei.thin_slab_2d()
 
 
 def _aniso3d():

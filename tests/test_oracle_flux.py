@@ -99,3 +99,36 @@ def test_normal_gradient_quadratic_exact_away_from_ghosts(theta_cells):
     d1, d2 = 1.0 / n, 2.0 / n
     D = (d2 / d1 * vals[0] - d1 / d2 * vals[1]) / (d2 - d1)
     assert abs(D - gq) < 1e-10
+
+
+def test_first_order_fallback_on_a_thin_slab():
+    """A liquid slab 1.45 h thick (y in [8.905 h, 10.355 h]): one row of
+    liquid centres (row 9), the interface cells in rows 8 and 10 with flat
+    facets at y = 8.905 h (normal +y) and y = 10.355 h (normal -y).  On the
+    liquid side the second point (2h along the normal) lands two rows past
+    the slab, where neither a liquid cell nor a one-layer ghost exists, so
+    the gradient falls back to the first-order difference from the liquid
+    centre nearest the first point: the row-9 cell straight across, at 0.595 h
+    (row 8) or 0.855 h (row 10) from the facet along the normal.  The vapour
+    is at T_sat, so its side adds nothing.  Hence, worked out by hand,
+        mdot = lam_l (T_9 - T_sat) / (0.595 h) / h_lg   in row 8,
+        mdot = lam_l (T_9 - T_sat) / (0.855 h) / h_lg   in row 10,
+    with one fallback per interface cell."""
+    case = ei.thin_slab_2d()
+    nx, ny = case.n[0], case.n[1]
+    h = case.h
+    g = geometry.build(case)
+    x = (np.arange(nx) + 0.5) * h
+    T = np.zeros((ny, nx))
+    T[9] = 1.0 + 0.3 * np.sin(2 * np.pi * x)
+    m, fb = flux.mass_flux(case, g, T.ravel())
+    m = m.reshape(ny, nx)
+    pr = case.props
+    assert sorted(set(np.nonzero(g["is_if"])[0] // nx)) == [8, 10]
+    assert fb == 2 * nx
+    for row, dist in ((8, 0.595), (10, 0.855)):
+        expect = pr.lam_l * (T[9] - pr.T_sat) / (dist * h) / pr.h_lg
+        assert np.max(np.abs(m[row] - expect)) <= 1e-13 * np.max(np.abs(expect)), row
+    others = np.ones(ny, bool)
+    others[[8, 10]] = False
+    assert np.all(m[others] == 0.0)
