@@ -956,12 +956,14 @@ ebit_status ebit_extend(ebit_ctx* c, double* q, int mode, int iters) {
   if (iters < 0) return fail(c, EBIT_EINVAL, "negative step count");
   // solver scratch: the band and target bytes in the FP32 iterate (4 N
   // bytes), the target list in the FP64 iterate, the weights in the
-  // direction and product vectors, the list length in the reduction
-  // partials, the other iterate in b
+  // direction and product vectors, the targets' band normal sums in the
+  // residual, the second FP64 iterate and (3D) the colour-split residual,
+  // the list length in the reduction partials, the other iterate in b
   double* w[3] = {c->B.p[0], c->B.p[1], c->B.q};
+  double* ns[3] = {c->B.r, c->B.z64b, c->fd.dim == 3 ? c->B.r64s : nullptr};
   HIPCK(c,
         ebit_launch_extend(&c->fd, mode, iters, c->flags, c->nF, q, c->bvec, (uint8_t*)c->B.z32,
-                           (unsigned long long*)c->B.z64, w, (int*)c->B.partial, c->st),
+                           (unsigned long long*)c->B.z64, w, ns, (int*)c->B.partial, c->st),
         "extend");
   return EBIT_OK;
 }

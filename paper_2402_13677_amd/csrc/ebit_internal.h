@@ -540,11 +540,11 @@ hipError_t ebit_launch_geometry(const ebit::Dims* d, double h, const double* con
 hipError_t ebit_launch_fill_f64(long long n, double* x, double v, hipStream_t st);
 hipError_t ebit_launch_split_flags(const ebit::Dims* d, const uint8_t* flags, uint8_t* fsplit, hipStream_t st);
 // Narrow-band extension.  Scratch: bytes (2 N), list (N entries),
-// w[0..dim-1] (N doubles each), counter (one int); work (N doubles) holds
-// every other iterate.
+// w[0..dim-1] and ns[0..dim-1] (N doubles each), counter (one int); work (N
+// doubles) holds every other iterate.
 hipError_t ebit_launch_extend(const ebit::Dims* d, int mode, int iters, const uint8_t* flags, const double* nF,
                               double* q, double* work, uint8_t* bytes, unsigned long long* list,
-                              double* const w[3], int* counter, hipStream_t st);
+                              double* const w[3], double* const ns[3], int* counter, hipStream_t st);
 hipError_t ebit_launch_fill_f32(long long n, float* x, float v, hipStream_t st);
 // Batched (many-case) forms of the per-case kernels: a device table of
 // arguments and n + 1 block offsets (start) per launch.

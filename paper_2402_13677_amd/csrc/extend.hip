@@ -160,6 +160,7 @@ struct ExtArgs {
   uint8_t* tgt;
   unsigned long long* list;
   double* w[3];
+  double* ns[3];  // the band normal sum of every target (scratch, cells)
   int* counter;
 };
 
@@ -174,6 +175,9 @@ __global__ void k_ext_mark(ExtArgs g) {
     cell_ijk(d, c, i, j, k);
     double s[3];
     t = band_normal_sum(d, g.flags, g.nF, i, j, k, s) ? 1 : 0;
+    // kept for the list pass (read back for targets only)
+    if (t)
+      for (int a = 0; a < d.dim; ++a) g.ns[a][c] = s[a];
   }
   g.tgt[c] = t;
 }
@@ -189,8 +193,8 @@ __global__ __launch_bounds__(EXT_BLOCK) void k_ext_list(ExtArgs g) {
   if (act) {
     int i, j, k;
     cell_ijk(d, c, i, j, k);
-    double s[3];
-    band_normal_sum(d, g.flags, g.nF, i, j, k, s);
+    // the band normal sum the mark pass computed
+    const double s[3] = {g.ns[0][c], g.ns[1][c], d.dim == 3 ? g.ns[2][c] : 0.0};
     const double L = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
     const double sg = ((g.flags[c] >> 6) & 1) ? 1.0 : -1.0;
 #pragma unroll
@@ -342,7 +346,7 @@ using namespace ebit;
 
 extern "C" hipError_t ebit_launch_extend(const Dims* d, int mode, int iters, const uint8_t* flags, const double* nF,
                                          double* q, double* work, uint8_t* bytes, unsigned long long* list,
-                                         double* const w[3], int* counter, hipStream_t st) {
+                                         double* const w[3], double* const ns[3], int* counter, hipStream_t st) {
   const unsigned nb = (unsigned)((d->N + EXT_BLOCK - 1) / EXT_BLOCK);
   const unsigned nl = nb < 2048u ? nb : 2048u;
   uint8_t* A = bytes;
@@ -363,7 +367,10 @@ extern "C" hipError_t ebit_launch_extend(const Dims* d, int mode, int iters, con
   g.band = in;
   g.tgt = out;
   g.list = list;
-  for (int a = 0; a < 3; ++a) g.w[a] = w[a];
+  for (int a = 0; a < 3; ++a) {
+    g.w[a] = w[a];
+    g.ns[a] = a < d->dim ? ns[a] : nullptr;
+  }
   g.counter = counter;
   hipLaunchKernelGGL(k_ext_mark, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
   hipLaunchKernelGGL(k_ext_list, dim3(nb), dim3(EXT_BLOCK), 0, st, g);
