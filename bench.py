@@ -1047,8 +1047,8 @@ def main():
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "one GPU only: this build runs and measures the path on a single GPU; "
-                                   "how it would shard is a design note (DESIGN.md, section 11)",
+        print(json.dumps({"error": "one GPU only: the path runs and is measured on a single GPU; "
+                                   "sharding across GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
