@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Bars (see the tolerance statement in the design doc):
+Bars:
   * flags: bit-exact; cut pattern (NaN layout of theta): identical;
   * theta, facets, operator rows, right-hand sides, mass flux: FP64, same
     formulas in the same order, agreement to a few ulps (1e-13 relative);
