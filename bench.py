@@ -782,8 +782,11 @@ def time_loop_bench(n=256, steps=20, warmup=3, U=0.5):
     ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, ext)
     ctx.ghost_band(ul, uv, mb)
     ctx.project(ul, uv, mdot, p)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    names = ("energy_advection_and_extensions", "interface_velocity_and_markers", "build", "heat_solve",
+             "mass_flux_and_extension", "ghost_band", "projection")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
     ms, iters = [], []
+    parts = {k: [] for k in names}
     for s in range(warmup + steps):
         ev[0].record()
         Tl = T.clone()
@@ -795,23 +798,31 @@ def time_loop_bench(n=256, steps=20, warmup=3, U=0.5):
         ctx.extend(Tl, ebit.EXT_LIQ_TO_VAP, ext)
         Tv = Tstar.clone()
         ctx.extend(Tv, ebit.EXT_VAP_TO_LIQ, ext)
+        ev[1].record()
         ctx.interface_velocity(ul, uv, mb, ug)
         old = cc.reshape(-1).clone()
         ctx.advect_markers(ug, mk, vc, cc, dt)
         new = cc.reshape(-1)
         Ts = torch.where(new == old, Tstar, torch.where(new == 1, Tl, Tv))
+        ev[2].record()
         ctx.build_coeffs(mk, vc, cc, dt)
+        ev[3].record()
         sh = ctx.heat_solve(Ts, T)
+        ev[4].record()
         ctx.mass_flux(T, mdot)
         mb = mdot.clone()
         ctx.extend(mb, ebit.EXT_IFACE_TO_BAND, ext)
+        ev[5].record()
         ctx.ghost_band(ul, uv, mb)
+        ev[6].record()
         sp = ctx.project(ul, uv, mdot, p)
-        ev[1].record()
-        ev[1].synchronize()
+        ev[7].record()
+        ev[7].synchronize()
         if s >= warmup:
-            ms.append(ev[0].elapsed_time(ev[1]))
+            ms.append(ev[0].elapsed_time(ev[7]))
             iters.append((sh["iters"], sp["iters"]))
+            for q, k in enumerate(names):
+                parts[k].append(ev[q].elapsed_time(ev[q + 1]))
     nmark = sum(int((~torch.isnan(m)).sum()) for m in mk)
     ctx.close()
     t = statistics.median(ms)
@@ -819,7 +830,7 @@ def time_loop_bench(n=256, steps=20, warmup=3, U=0.5):
             "cell_steps_per_s": N / (t * 1e-3), "markers_after": nmark,
             "outer_iters_heat_projection": [statistics.median([a for a, _ in iters]),
                                             statistics.median([b for _, b in iters])],
-            "extension_steps": ext}
+            "extension_steps": ext, "ms_by_phase": {k: statistics.median(v) for k, v in parts.items()}}
 
 
 def time_loop_cpu_baseline(n=256, U=0.5):
