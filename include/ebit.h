@@ -58,6 +58,11 @@
  *     EBIT_TEST_FP32_STALL=1, read the same way, makes a mixed-precision
  *     context or batch treat every solve still iterating after its first
  *     block of iterations as stalled, to test the FP64 fallback.
+ *     EBIT_SOLVE_LOG=<path>, read when a context is created, appends one
+ *     JSON line per ebit_heat_solve, ebit_project and ebit_project_one_fluid
+ *     call of that context to the file (call, dim, n, precision, and the
+ *     fields of ebit_stats); those calls then always wait for the device,
+ *     as with a stats argument.  A file that cannot be opened is skipped.
  */
 #ifndef EBIT_H
 #define EBIT_H

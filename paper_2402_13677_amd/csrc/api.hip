@@ -15,6 +15,7 @@
 using namespace ebit;
 
 struct ebit_ctx {
+  char solve_log[512];  // EBIT_SOLVE_LOG at creation ("" = no log)
   ebit_grid grid;
   ebit_props props;
   ebit_opts opts;
@@ -705,6 +706,7 @@ ebit_status ebit_create(ebit_ctx** out, const ebit_grid* g, const ebit_props* p,
   ebit_ctx* c = new (std::nothrow) ebit_ctx;
   if (!c) return EBIT_ENOMEM;
   memset(c, 0, sizeof(*c));
+  if (const char* lp = getenv("EBIT_SOLVE_LOG")) snprintf(c->solve_log, sizeof(c->solve_log), "%s", lp);
   c->grid = *g;
   c->props = *p;
   if (o)
@@ -789,7 +791,26 @@ ebit_status ebit_build_coeffs(ebit_ctx* c, const double* const marker[3], const 
   return EBIT_OK;
 }
 
-ebit_status ebit_heat_solve(ebit_ctx* c, const double* Ts, double* T, int use_guess, ebit_stats* st) {
+// One JSON line per solve call, appended to the file EBIT_SOLVE_LOG named
+// when the context was created (nothing when it was unset); a file that
+// cannot be opened is skipped.
+static void log_solve(const ebit_ctx* c, const char* call, const ebit_stats* st) {
+  if (!c->solve_log[0] || !st) return;
+  FILE* f = fopen(c->solve_log, "a");
+  if (!f) return;
+  fprintf(f,
+          "{\"call\": \"%s\", \"dim\": %d, \"n\": [%d, %d, %d], \"precision\": %d, \"status\": %d, "
+          "\"iters\": %d, \"vcycles\": %d, \"rel_res\": %.17g, \"bnorm\": %.17g, \"res_floor\": %.17g, "
+          "\"seconds\": %.9g, \"div_max\": %.17g, \"fp64_fallback\": %d}\n",
+          call, c->grid.dim, c->grid.n[0], c->grid.n[1], c->grid.dim == 3 ? c->grid.n[2] : 1, c->opts.precision,
+          st->status, st->iters, st->vcycles, st->rel_res, st->bnorm, st->res_floor, st->seconds, st->div_max,
+          st->fp64_fallback);
+  fclose(f);
+}
+
+ebit_status ebit_heat_solve(ebit_ctx* c, const double* Ts, double* T, int use_guess, ebit_stats* st_in) {
+  ebit_stats st_loc;
+  ebit_stats* st = st_in ? st_in : (c && c->solve_log[0] ? &st_loc : nullptr);
   stats_init(st);
   ebit_status s = check_ready(c);
   if (s != EBIT_OK) return s;
@@ -806,6 +827,7 @@ ebit_status ebit_heat_solve(ebit_ctx* c, const double* Ts, double* T, int use_gu
     st->seconds = ms * 1e-3;
     st->status = s;
   }
+  log_solve(c, "heat_solve", st);
   return s;
 }
 
@@ -856,7 +878,9 @@ ebit_status ebit_project_rhs(ebit_ctx* c, double* const ul[3], double* const uv[
 }
 
 ebit_status ebit_project(ebit_ctx* c, double* const ul[3], double* const uv[3], const double* mdot, double* p,
-                         int use_guess, ebit_stats* st) {
+                         int use_guess, ebit_stats* st_in) {
+  ebit_stats st_loc;
+  ebit_stats* st = st_in ? st_in : (c && c->solve_log[0] ? &st_loc : nullptr);
   stats_init(st);
   ebit_status s = check_ready(c);
   if (s != EBIT_OK) return s;
@@ -882,11 +906,14 @@ ebit_status ebit_project(ebit_ctx* c, double* const ul[3], double* const uv[3], 
     st->div_max = hs.divmax;
     st->status = s;
   }
+  log_solve(c, "project", st);
   return s;
 }
 
 ebit_status ebit_project_one_fluid(ebit_ctx* c, double* const u[3], const double* mdot, double* p, int use_guess,
-                                   ebit_stats* st) {
+                                   ebit_stats* st_in) {
+  ebit_stats st_loc;
+  ebit_stats* st = st_in ? st_in : (c && c->solve_log[0] ? &st_loc : nullptr);
   stats_init(st);
   ebit_status s = check_ready(c);
   if (s != EBIT_OK) return s;
@@ -916,6 +943,7 @@ ebit_status ebit_project_one_fluid(ebit_ctx* c, double* const u[3], const double
     st->div_max = hs.divmax;
     st->status = s;
   }
+  log_solve(c, "project_one_fluid", st);
   return s;
 }
 

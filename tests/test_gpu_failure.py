@@ -152,3 +152,31 @@ def test_stalled_mixed_batch_continues_in_fp64(stall_switch):
     b.close()
     for c, _ in ctxs:
         c.close()
+
+
+def test_solve_log_jsonl(tmp_path, monkeypatch):
+    """EBIT_SOLVE_LOG: one JSON line per solve call of a context created
+    while it is set, with the fields the call's stats report (here without
+    a stats argument on the second pair of calls)."""
+    import json
+    ebit = _ebit()
+    path = tmp_path / "solves.jsonl"
+    monkeypatch.setenv("EBIT_SOLVE_LOG", str(path))
+    case = ei.config(0)
+    ctx, dc = ebit.context_for(case)
+    ctx.build_coeffs(dc.markers, dc.vcol, dc.ccol, case.dt)
+    T = torch.zeros_like(dc.T0)
+    sh = ctx.heat_solve(dc.T0, T)
+    m = torch.zeros_like(dc.T0)
+    ctx.mass_flux(T, m)
+    p = torch.zeros_like(dc.T0)
+    sp = ctx.project(dc.u_l, dc.u_v, m, p)
+    assert ctx.lib.ebit_heat_solve(ctx.h, ebit._ptr(dc.T0, torch.float64), ebit._ptr(T, torch.float64), 0,
+                                   None) == ebit.OK
+    ctx.close()
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert [x["call"] for x in lines] == ["heat_solve", "project", "heat_solve"]
+    assert lines[0]["iters"] == sh["iters"] and lines[0]["rel_res"] == sh["rel_res"]
+    assert lines[1]["iters"] == sp["iters"] and lines[1]["div_max"] == sp["div_max"]
+    assert lines[2]["status"] == ebit.OK and lines[2]["iters"] == sh["iters"]
+    assert lines[0]["n"] == [case.n[0], case.n[1], 1] and lines[0]["dim"] == 2
