@@ -1053,7 +1053,8 @@ def main():
     ap.add_argument("--energy-only", action="store_true",
                     help="run only the energy-advection timing on the workload (for profiling it)")
     ap.add_argument("--extras-only", action="store_true",
-                    help="time only the narrow-band extension, the one-fluid projection and the energy advection")
+                    help="time only the extras: the narrow-band extension with the band ghost velocities, the "
+                         "one-fluid projection, the energy advection, the marker motion and the whole 2D time step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
